@@ -1,0 +1,201 @@
+"""Model description and its flat binary form (the "model blob").
+
+A model is a tree of rigid bodies with joints, collision geoms, an explicit list of
+collision pairs and actuators, in the MJCF-like terms that the physics step of MuJoCo
+Playground consumes (the paper's physics knobs are MJCF options: Table
+``tab:dm_control_envs`` in the DM Control appendix, and the PD mapping of eq.
+``pd_mapping``).  This module only stores and serialises the description; it holds none
+of the step's arithmetic.  Both the FP64 reference and the GPU library parse the blob
+with their own code.
+
+Blob layout (little endian, version 1), every block 8-byte aligned:
+
+  header   int32[16]  : magic 0x4D484A4D ('MJHM'), version, nbody, njnt, ngeom, npair,
+                        nu, nq, nv, iterations, ls_iterations, nconmax, 0, 0, 0, 0
+           float64[16]: timestep, gravity[3], solref[2], solimp[5], tolerance, 0 x4
+  body     int32 [nbody][2] : parent, 0
+           f64   [nbody][19]: pos[3], quat[4] (w first), mass, ipos[3],
+                              inertia[6] (Ixx Iyy Izz Ixy Ixz Iyz, body frame, about ipos),
+                              0, 0
+  joint    int32 [njnt][2]  : type (0 free, 1 slide, 2 hinge), body
+           f64   [njnt][8]  : pos[3], axis[3], damping, armature
+  geom     int32 [ngeom][2] : type (0 plane, 1 sphere, 2 capsule, 3 box), body
+           f64   [ngeom][11]: size[3], pos[3], quat[4], friction
+  pair     int32 [npair][2] : geom1, geom2   (type(geom1) <= type(geom2))
+           f64   [npair][1] : friction coefficient mu
+  actuator int32 [nu][2]    : type (0 motor, 1 position PD), joint
+           f64   [nu][7]    : gear, kp, kd, ctrlrange[2], qdefault, 0
+  qpos0    f64   [nq]
+
+Geom sizes: sphere (r), capsule (r, half segment length; segment along local z),
+box (half extents).  Plane normal is the geom's local +z.
+"""
+from __future__ import annotations
+
+import struct
+from dataclasses import dataclass, field
+from typing import List, Tuple
+
+import numpy as np
+
+MAGIC = 0x4D484A4D
+VERSION = 1
+
+JNT_FREE, JNT_SLIDE, JNT_HINGE = 0, 1, 2
+GEOM_PLANE, GEOM_SPHERE, GEOM_CAPSULE, GEOM_BOX = 0, 1, 2, 3
+ACT_MOTOR, ACT_PD = 0, 1
+
+JNT_NQ = {JNT_FREE: 7, JNT_SLIDE: 1, JNT_HINGE: 1}
+JNT_NV = {JNT_FREE: 6, JNT_SLIDE: 1, JNT_HINGE: 1}
+
+
+@dataclass
+class Body:
+    parent: int
+    pos: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    quat: Tuple[float, float, float, float] = (1.0, 0.0, 0.0, 0.0)
+    mass: float = 0.0
+    ipos: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    inertia: Tuple[float, ...] = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)
+    name: str = ""
+
+
+@dataclass
+class Joint:
+    type: int
+    body: int
+    pos: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    axis: Tuple[float, float, float] = (0.0, 0.0, 1.0)
+    damping: float = 0.0
+    armature: float = 0.0
+    name: str = ""
+
+
+@dataclass
+class Geom:
+    type: int
+    body: int
+    size: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    pos: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    quat: Tuple[float, float, float, float] = (1.0, 0.0, 0.0, 0.0)
+    friction: float = 1.0
+    name: str = ""
+
+
+@dataclass
+class Actuator:
+    type: int
+    joint: int
+    gear: float = 1.0
+    kp: float = 0.0
+    kd: float = 0.0
+    ctrlrange: Tuple[float, float] = (-1.0, 1.0)
+    qdefault: float = 0.0
+
+
+@dataclass
+class Options:
+    timestep: float = 0.002
+    gravity: Tuple[float, float, float] = (0.0, 0.0, -9.81)
+    solref: Tuple[float, float] = (0.02, 1.0)
+    solimp: Tuple[float, float, float, float, float] = (0.9, 0.95, 0.001, 0.5, 2.0)
+    tolerance: float = 1e-8
+    iterations: int = 4
+    ls_iterations: int = 8
+    nconmax: int = 0
+
+
+@dataclass
+class Model:
+    name: str
+    bodies: List[Body] = field(default_factory=list)
+    joints: List[Joint] = field(default_factory=list)
+    geoms: List[Geom] = field(default_factory=list)
+    pairs: List[Tuple[int, int, float]] = field(default_factory=list)
+    actuators: List[Actuator] = field(default_factory=list)
+    opt: Options = field(default_factory=Options)
+    qpos0: np.ndarray = None
+
+    # ------------------------------------------------------------------ sizes
+    @property
+    def nbody(self) -> int:
+        return len(self.bodies)
+
+    @property
+    def nq(self) -> int:
+        return sum(JNT_NQ[j.type] for j in self.joints)
+
+    @property
+    def nv(self) -> int:
+        return sum(JNT_NV[j.type] for j in self.joints)
+
+    @property
+    def nu(self) -> int:
+        return len(self.actuators)
+
+    def jnt_qposadr(self) -> List[int]:
+        out, a = [], 0
+        for j in self.joints:
+            out.append(a)
+            a += JNT_NQ[j.type]
+        return out
+
+    def jnt_dofadr(self) -> List[int]:
+        out, a = [], 0
+        for j in self.joints:
+            out.append(a)
+            a += JNT_NV[j.type]
+        return out
+
+    def total_mass(self) -> float:
+        return float(sum(b.mass for b in self.bodies))
+
+    # -------------------------------------------------------------- validity
+    def validate(self) -> None:
+        assert self.bodies and self.bodies[0].parent == -1, "body 0 must be the world"
+        for i, b in enumerate(self.bodies[1:], start=1):
+            assert 0 <= b.parent < i, f"body {i}: parent must precede child"
+        last = 0
+        for j in self.joints:
+            assert j.body >= last, "joints must be grouped by body in body order"
+            last = j.body
+            if j.type == JNT_FREE:
+                assert self.bodies[j.body].parent == 0, "free joints attach to the world"
+                assert sum(1 for k in self.joints if k.body == j.body) == 1
+        for g1, g2, _ in self.pairs:
+            assert self.geoms[g1].type <= self.geoms[g2].type, "pair order by geom type"
+        assert self.qpos0 is not None and len(self.qpos0) == self.nq
+
+    # ---------------------------------------------------------------- to blob
+    def to_blob(self) -> bytes:
+        self.validate()
+        o = self.opt
+        hdr_i = [MAGIC, VERSION, self.nbody, len(self.joints), len(self.geoms),
+                 len(self.pairs), self.nu, self.nq, self.nv, o.iterations,
+                 o.ls_iterations, o.nconmax, 0, 0, 0, 0]
+        hdr_f = [o.timestep, *o.gravity, *o.solref, *o.solimp, o.tolerance, 0, 0, 0, 0]
+        assert len(hdr_f) == 16
+        parts = [struct.pack("<16i", *hdr_i), struct.pack("<16d", *hdr_f)]
+
+        def blk_i(rows):
+            a = np.asarray(rows, dtype="<i4").reshape(-1)
+            return a.tobytes()
+
+        def blk_f(rows):
+            a = np.asarray(rows, dtype="<f8").reshape(-1)
+            return a.tobytes()
+
+        parts.append(blk_i([[b.parent, 0] for b in self.bodies]))
+        parts.append(blk_f([[*b.pos, *b.quat, b.mass, *b.ipos, *b.inertia, 0, 0]
+                            for b in self.bodies]))
+        parts.append(blk_i([[j.type, j.body] for j in self.joints]))
+        parts.append(blk_f([[*j.pos, *j.axis, j.damping, j.armature] for j in self.joints]))
+        parts.append(blk_i([[g.type, g.body] for g in self.geoms]))
+        parts.append(blk_f([[*g.size, *g.pos, *g.quat, g.friction] for g in self.geoms]))
+        parts.append(blk_i([[p[0], p[1]] for p in self.pairs]))
+        parts.append(blk_f([[p[2]] for p in self.pairs]))
+        parts.append(blk_i([[a.type, a.joint] for a in self.actuators]))
+        parts.append(blk_f([[a.gear, a.kp, a.kd, *a.ctrlrange, a.qdefault, 0]
+                            for a in self.actuators]))
+        parts.append(blk_f(np.asarray(self.qpos0, dtype=np.float64)))
+        return b"".join(parts)

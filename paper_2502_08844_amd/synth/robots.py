@@ -1,0 +1,498 @@
+"""Synthetic robots shaped like the paper's workloads.
+
+The paper trains on MuJoCo Menagerie robots and DM Control tasks (its sections on DM
+Control, locomotion and manipulation environments).  Those asset files are not part of
+this project, so these generic models stand in for them, with the shapes the workloads
+need:
+
+* ``cartpole``  -- slider cart plus hinged capsule pole (DM Control CartpoleBalance).
+* ``quadruped`` -- free torso and 4 legs of 3 hinges with sphere feet; only the feet
+  collide with the floor, the reduced collision model the paper uses for joystick
+  policies (locomotion section, feet-only contacts).
+* ``humanoid``  -- free torso plus 21 hinges over 13 capsule bodies, floor contacts and
+  self-contacts between non-adjacent bodies, timestep 0.005 as in the DM Control
+  humanoid edits (Table ``tab:dm_control_envs``).
+* ``hand``      -- 4 fingers of 4 hinges above a palm (the floor) and a free cube; finger
+  joints carry the gearbox armature I_a = k_g^2 I_r of the LEAP-hand system
+  identification (manipulation appendix): k_g = 288.35, I_r = 1/2 m_r r_r^2 with
+  m_r = 2.0e-3 kg and r_r = 4.12e-3 m.
+
+Mass properties are uniform-density solids (standard closed forms; a capsule is a
+cylinder plus two hemispheres).  Nothing here is the physics step.
+"""
+from __future__ import annotations
+
+import math
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+from .model import (ACT_MOTOR, ACT_PD, GEOM_BOX, GEOM_CAPSULE, GEOM_PLANE, GEOM_SPHERE,
+                    JNT_FREE, JNT_HINGE, JNT_SLIDE, Actuator, Body, Geom, Joint, Model,
+                    Options)
+
+# ----------------------------------------------------------------------------------
+# closed-form mass properties (uniform density)
+
+
+def capsule_volume(r: float, half_len: float) -> float:
+    return math.pi * r * r * (2.0 * half_len) + 4.0 / 3.0 * math.pi * r ** 3
+
+
+def sphere_volume(r: float) -> float:
+    return 4.0 / 3.0 * math.pi * r ** 3
+
+
+def box_volume(half: Sequence[float]) -> float:
+    return 8.0 * half[0] * half[1] * half[2]
+
+
+def capsule_inertia(mass: float, r: float, half_len: float) -> np.ndarray:
+    """Principal inertia about the centre, segment along local z (cylinder + 2 caps)."""
+    L = 2.0 * half_len
+    vc = math.pi * r * r * L
+    vs = 4.0 / 3.0 * math.pi * r ** 3
+    mc = mass * vc / (vc + vs)
+    ms = mass * vs / (vc + vs)
+    h = half_len
+    i_axis = mc * r * r / 2.0 + ms * 2.0 * r * r / 5.0
+    i_perp = mc * (r * r / 4.0 + L * L / 12.0) + ms * (2.0 * r * r / 5.0 + h * h + 0.75 * h * r)
+    return np.diag([i_perp, i_perp, i_axis])
+
+
+def box_inertia(mass: float, half: Sequence[float]) -> np.ndarray:
+    a, b, c = (2.0 * x for x in half)
+    return np.diag([mass * (b * b + c * c) / 12.0, mass * (a * a + c * c) / 12.0,
+                    mass * (a * a + b * b) / 12.0])
+
+
+def sphere_inertia(mass: float, r: float) -> np.ndarray:
+    return np.eye(3) * (0.4 * mass * r * r)
+
+
+# ----------------------------------------------------------------------------------
+# small rotation helpers for building models
+
+
+def quat_to_mat(q: Sequence[float]) -> np.ndarray:
+    w, x, y, z = np.asarray(q, dtype=np.float64) / np.linalg.norm(q)
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+        [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+        [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def quat_z_to(u: Sequence[float]) -> Tuple[float, float, float, float]:
+    """Unit quaternion rotating local +z onto direction u."""
+    u = np.asarray(u, dtype=np.float64)
+    u = u / np.linalg.norm(u)
+    z = np.array([0.0, 0.0, 1.0])
+    c = float(np.dot(z, u))
+    if c > 1.0 - 1e-15:
+        return (1.0, 0.0, 0.0, 0.0)
+    if c < -1.0 + 1e-15:
+        return (0.0, 1.0, 0.0, 0.0)
+    ax = np.cross(z, u)
+    ax /= np.linalg.norm(ax)
+    ang = math.acos(c)
+    s = math.sin(ang / 2)
+    return (math.cos(ang / 2), ax[0] * s, ax[1] * s, ax[2] * s)
+
+
+def axis_angle_quat(axis: Sequence[float], ang: float) -> Tuple[float, float, float, float]:
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    s = math.sin(ang / 2)
+    return (math.cos(ang / 2), a[0] * s, a[1] * s, a[2] * s)
+
+
+class _Builder:
+    """Accumulates bodies/geoms and derives each body's mass properties from its geoms."""
+
+    def __init__(self, name: str):
+        self.m = Model(name=name)
+        self.m.bodies.append(Body(parent=-1, name="world"))
+        self._geom_mass: List[Tuple[int, float, np.ndarray, np.ndarray, np.ndarray]] = []
+
+    def body(self, parent: int, pos=(0, 0, 0), quat=(1, 0, 0, 0), name="") -> int:
+        self.m.bodies.append(Body(parent=parent, pos=tuple(map(float, pos)),
+                                  quat=tuple(map(float, quat)), name=name))
+        return len(self.m.bodies) - 1
+
+    def joint(self, body: int, type: int, axis=(0, 0, 1), pos=(0, 0, 0), damping=0.0,
+              armature=0.0, name="") -> int:
+        self.m.joints.append(Joint(type=type, body=body, pos=tuple(map(float, pos)),
+                                   axis=tuple(map(float, axis)), damping=float(damping),
+                                   armature=float(armature), name=name))
+        return len(self.m.joints) - 1
+
+    def geom(self, body: int, type: int, size, pos=(0, 0, 0), quat=(1, 0, 0, 0),
+             mass: float = 0.0, friction: float = 1.0, name="") -> int:
+        size = tuple(float(s) for s in size) + (0.0,) * (3 - len(size))
+        self.m.geoms.append(Geom(type=type, body=body, size=size,
+                                 pos=tuple(map(float, pos)), quat=tuple(map(float, quat)),
+                                 friction=float(friction), name=name))
+        gid = len(self.m.geoms) - 1
+        if mass > 0.0:
+            if type == GEOM_SPHERE:
+                ig = sphere_inertia(mass, size[0])
+            elif type == GEOM_CAPSULE:
+                ig = capsule_inertia(mass, size[0], size[1])
+            elif type == GEOM_BOX:
+                ig = box_inertia(mass, size)
+            else:
+                raise ValueError("massive plane")
+            R = quat_to_mat(quat)
+            self._geom_mass.append((body, mass, np.asarray(pos, float), R @ ig @ R.T, R))
+        return gid
+
+    def capsule_fromto(self, body, p0, p1, r, mass=0.0, friction=1.0, name="") -> int:
+        p0 = np.asarray(p0, float)
+        p1 = np.asarray(p1, float)
+        d = p1 - p0
+        return self.geom(body, GEOM_CAPSULE, (r, 0.5 * np.linalg.norm(d)),
+                         pos=0.5 * (p0 + p1), quat=quat_z_to(d), mass=mass,
+                         friction=friction, name=name)
+
+    def finish(self) -> Model:
+        # body mass, COM and inertia about the COM in the body frame
+        for bi, b in enumerate(self.m.bodies):
+            parts = [g for g in self._geom_mass if g[0] == bi]
+            if not parts:
+                continue
+            mass = sum(p[1] for p in parts)
+            com = sum(p[1] * p[2] for p in parts) / mass
+            I = np.zeros((3, 3))
+            for _, m_, c, Ic, _ in parts:
+                d = c - com
+                I += Ic + m_ * (np.dot(d, d) * np.eye(3) - np.outer(d, d))
+            b.mass = float(mass)
+            b.ipos = tuple(float(x) for x in com)
+            b.inertia = (I[0, 0], I[1, 1], I[2, 2], I[0, 1], I[0, 2], I[1, 2])
+        return self.m
+
+
+def _set_point_mass_props(m: Model, bi: int, mass: float, ipos, inertia_diag) -> None:
+    b = m.bodies[bi]
+    b.mass = float(mass)
+    b.ipos = tuple(map(float, ipos))
+    b.inertia = (float(inertia_diag[0]), float(inertia_diag[1]), float(inertia_diag[2]),
+                 0.0, 0.0, 0.0)
+
+
+# ----------------------------------------------------------------------------------
+# the four workload models
+
+
+def cartpole(hanging: bool = False, damping: float = 0.05, timestep: float = 0.01) -> Model:
+    """Slider cart (1 kg) + hinge pole (capsule r 0.045, length 0.6, 0.1 kg).
+
+    nq = nv = 2.  Motor on the slider with gear 10, ctrl in [-1, 1]; joint damping 0.05.
+    ``hanging`` points the pole down (for the small-angle pendulum check).
+    """
+    bld = _Builder("cartpole")
+    cart = bld.body(0, name="cart")
+    bld.joint(cart, JNT_SLIDE, axis=(1, 0, 0), damping=damping, name="slider")
+    # the cart only translates; its rotational inertia never enters the dynamics
+    bld.geom(cart, GEOM_BOX, (0.1, 0.075, 0.05), mass=1.0, name="cart")
+    pole = bld.body(cart, name="pole")
+    bld.joint(pole, JNT_HINGE, axis=(0, 1, 0), damping=damping, name="hinge")
+    tip = (0.0, 0.0, -0.6) if hanging else (0.0, 0.0, 0.6)
+    bld.capsule_fromto(pole, (0, 0, 0), tip, 0.045, mass=0.1, name="pole")
+    m = bld.finish()
+    m.actuators.append(Actuator(type=ACT_MOTOR, joint=0, gear=10.0, ctrlrange=(-1.0, 1.0)))
+    m.opt = Options(timestep=timestep, iterations=1, ls_iterations=4, nconmax=0)
+    m.qpos0 = np.zeros(2)
+    return m
+
+
+QUAD_Q_DEFAULT = (0.0, math.pi / 4, -math.pi / 2)
+QUAD_STAND_Z = 0.2 * math.sqrt(2.0) + 0.025
+
+
+def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4) -> Model:
+    """Free torso (box 0.3x0.1x0.05 m, 5 kg) + 4 legs x 3 hinges (capsules r 0.02,
+    length 0.2, 0.5 kg) with massless sphere feet (r 0.025).  nq 19, nv 18, nu 12.
+
+    Each leg: hip link (hinge about x, capsule lateral 0.2 m), thigh (hinge about y,
+    capsule down 0.2 m), shin (hinge about y, capsule down 0.2 m, foot sphere).
+    Position (PD) actuators kp 35, kd 0.5 on every hinge; ctrl is the target offset from
+    the default pose (0, pi/4, -pi/2) per leg.  Only the feet collide (plane x 4 feet).
+    """
+    bld = _Builder("quadruped")
+    plane = bld.geom(0, GEOM_PLANE, (0, 0, 0), friction=mu, name="floor")
+    torso = bld.body(0, pos=(0, 0, QUAD_STAND_Z), name="torso")
+    bld.joint(torso, JNT_FREE, name="root")
+    bld.geom(torso, GEOM_BOX, (0.15, 0.05, 0.025), mass=5.0, name="torso")
+    feet = []
+    hinge_ids = []
+    for i, (sx, sy) in enumerate(((1, 1), (1, -1), (-1, 1), (-1, -1))):
+        hip = bld.body(torso, pos=(0.15 * sx, 0.05 * sy, 0.0), name=f"hip{i}")
+        hinge_ids.append(bld.joint(hip, JNT_HINGE, axis=(1, 0, 0), name=f"abd{i}"))
+        bld.capsule_fromto(hip, (0, 0, 0), (0, 0.2 * sy, 0), 0.02, mass=0.5)
+        thigh = bld.body(hip, pos=(0, 0.2 * sy, 0), name=f"thigh{i}")
+        hinge_ids.append(bld.joint(thigh, JNT_HINGE, axis=(0, 1, 0), name=f"hip{i}"))
+        bld.capsule_fromto(thigh, (0, 0, 0), (0, 0, -0.2), 0.02, mass=0.5)
+        shin = bld.body(thigh, pos=(0, 0, -0.2), name=f"shin{i}")
+        hinge_ids.append(bld.joint(shin, JNT_HINGE, axis=(0, 1, 0), name=f"knee{i}"))
+        bld.capsule_fromto(shin, (0, 0, 0), (0, 0, -0.2), 0.02, mass=0.5)
+        feet.append(bld.geom(shin, GEOM_SPHERE, (0.025,), pos=(0, 0, -0.2), friction=mu,
+                             name=f"foot{i}"))
+    m = bld.finish()
+    for k, j in enumerate(hinge_ids):
+        m.actuators.append(Actuator(type=ACT_PD, joint=j, gear=1.0, kp=35.0, kd=0.5,
+                                    ctrlrange=(-1.0, 1.0), qdefault=QUAD_Q_DEFAULT[k % 3]))
+    m.pairs = [(plane, f, mu) for f in feet]
+    m.opt = Options(timestep=timestep, iterations=iterations, ls_iterations=8,
+                    nconmax=4)
+    q0 = np.zeros(m.nq)
+    q0[0:3] = (0, 0, QUAD_STAND_Z)
+    q0[3] = 1.0
+    m.qpos0 = q0
+    return m
+
+
+def quadruped_standing_qpos(m: Model) -> np.ndarray:
+    q = m.qpos0.copy()
+    q[7:] = np.tile(QUAD_Q_DEFAULT, 4)
+    return q
+
+
+HUMANOID_TOTAL_MASS = 35.0
+
+
+def humanoid(mu: float = 0.8, timestep: float = 0.005, iterations: int = 6,
+             nconmax: int = 32) -> Model:
+    """Free torso plus 21 hinges over 13 capsule/sphere bodies (nq 28, nv 27, nu 21).
+
+    Bodies: torso (free; capsule + head sphere), lower_waist (2 hinges), pelvis (1),
+    thigh x2 (3), shin x2 (1), foot x2 (2), upper_arm x2 (2), lower_arm x2 (1).
+    Radii 0.03-0.06 m, total mass 35 kg by uniform density.  Motors with gear 50 and
+    ctrl in [-1, 1]; hinge damping 0.2 and armature 0.02.  Collisions: the floor with
+    every geom, and every geom pair whose bodies are neither the same nor parent/child.
+    """
+    shapes = []  # (body, kind, args) collected first so density can be set for 35 kg
+    bld = _Builder("humanoid")
+    plane = bld.geom(0, GEOM_PLANE, (0, 0, 0), friction=mu, name="floor")
+    z0 = 1.25
+    torso = bld.body(0, pos=(0, 0, z0), name="torso")
+    bld.joint(torso, JNT_FREE, name="root")
+    shapes += [(torso, "cap", ((0, -0.07, 0), (0, 0.07, 0), 0.06)),
+               (torso, "sph", ((0, 0, 0.19), 0.06))]
+    hk = dict(damping=0.2, armature=0.02)
+    hinges = []
+    lw = bld.body(torso, pos=(0, 0, -0.26), name="lower_waist")
+    hinges.append(bld.joint(lw, JNT_HINGE, axis=(0, 0, 1), **hk))
+    hinges.append(bld.joint(lw, JNT_HINGE, axis=(0, 1, 0), **hk))
+    shapes.append((lw, "cap", ((0, -0.06, 0), (0, 0.06, 0), 0.05)))
+    pelvis = bld.body(lw, pos=(0, 0, -0.165), name="pelvis")
+    hinges.append(bld.joint(pelvis, JNT_HINGE, axis=(1, 0, 0), **hk))
+    shapes.append((pelvis, "cap", ((0, -0.07, 0), (0, 0.07, 0), 0.06)))
+    for side, sy in (("r", -1.0), ("l", 1.0)):
+        th = bld.body(pelvis, pos=(0, 0.1 * sy, -0.04), name=f"thigh_{side}")
+        for ax in ((1, 0, 0), (0, 0, 1), (0, 1, 0)):
+            hinges.append(bld.joint(th, JNT_HINGE, axis=ax, **hk))
+        shapes.append((th, "cap", ((0, 0, 0), (0, 0.0, -0.35), 0.05)))
+        sh = bld.body(th, pos=(0, 0, -0.4), name=f"shin_{side}")
+        hinges.append(bld.joint(sh, JNT_HINGE, axis=(0, -1, 0), **hk))
+        shapes.append((sh, "cap", ((0, 0, 0), (0, 0, -0.3), 0.04)))
+        ft = bld.body(sh, pos=(0, 0, -0.35), name=f"foot_{side}")
+        hinges.append(bld.joint(ft, JNT_HINGE, axis=(0, 1, 0), **hk))
+        hinges.append(bld.joint(ft, JNT_HINGE, axis=(1, 0, 0), **hk))
+        shapes.append((ft, "cap", ((-0.03, 0, 0), (0.12, 0, 0), 0.03)))
+    for side, sy in (("r", -1.0), ("l", 1.0)):
+        ua = bld.body(torso, pos=(0, 0.17 * sy, 0.06), name=f"upper_arm_{side}")
+        hinges.append(bld.joint(ua, JNT_HINGE, axis=(1, 0, 0), **hk))
+        hinges.append(bld.joint(ua, JNT_HINGE, axis=(0, 1, 0), **hk))
+        shapes.append((ua, "cap", ((0, 0, 0), (0, 0.05 * sy, -0.24), 0.04)))
+        la = bld.body(ua, pos=(0, 0.05 * sy, -0.26), name=f"lower_arm_{side}")
+        hinges.append(bld.joint(la, JNT_HINGE, axis=(0, -1, 0), **hk))
+        shapes.append((la, "cap", ((0, 0, 0), (0, 0.02 * sy, -0.23), 0.03)))
+
+    vol = 0.0
+    for _, kind, a in shapes:
+        if kind == "cap":
+            vol += capsule_volume(a[2], 0.5 * np.linalg.norm(np.subtract(a[1], a[0])))
+        else:
+            vol += sphere_volume(a[1])
+    rho = HUMANOID_TOTAL_MASS / vol
+    geom_ids = []
+    for bi, kind, a in shapes:
+        if kind == "cap":
+            hl = 0.5 * np.linalg.norm(np.subtract(a[1], a[0]))
+            geom_ids.append(bld.capsule_fromto(bi, a[0], a[1], a[2],
+                                               mass=rho * capsule_volume(a[2], hl),
+                                               friction=mu))
+        else:
+            geom_ids.append(bld.geom(bi, GEOM_SPHERE, (a[1],), pos=a[0],
+                                     mass=rho * sphere_volume(a[1]), friction=mu))
+    m = bld.finish()
+    for j in hinges:
+        m.actuators.append(Actuator(type=ACT_MOTOR, joint=j, gear=50.0,
+                                    ctrlrange=(-1.0, 1.0)))
+    pairs = [(plane, g, mu) for g in geom_ids]
+    for i, gi in enumerate(geom_ids):
+        for gj in geom_ids[i + 1:]:
+            bi, bj = m.geoms[gi].body, m.geoms[gj].body
+            if bi == bj or m.bodies[bi].parent == bj or m.bodies[bj].parent == bi:
+                continue
+            a, b = (gi, gj) if m.geoms[gi].type <= m.geoms[gj].type else (gj, gi)
+            pairs.append((a, b, mu))
+    m.pairs = pairs
+    m.opt = Options(timestep=timestep, iterations=iterations, ls_iterations=8,
+                    nconmax=nconmax)
+    q0 = np.zeros(m.nq)
+    q0[0:3] = (0, 0, z0)
+    q0[3] = 1.0
+    m.qpos0 = q0
+    return m
+
+
+LEAP_GEAR_RATIO = 288.35
+LEAP_ROTOR_MASS = 2.0e-3
+LEAP_ROTOR_RADIUS = 4.12e-3
+
+
+def leap_rotor_inertia() -> float:
+    """I_r = 1/2 m_r r_r^2 (uniform disc rotor)."""
+    return 0.5 * LEAP_ROTOR_MASS * LEAP_ROTOR_RADIUS ** 2
+
+
+def leap_armature() -> float:
+    """Reflected rotor inertia I_a = k_g^2 I_r; the paper rounds I_r to 1.7e-8."""
+    return LEAP_GEAR_RATIO ** 2 * 1.7e-8
+
+
+HAND_LINKS = (0.02, 0.045, 0.035, 0.03)
+
+
+def hand(mu: float = 1.0, timestep: float = 0.0025, iterations: int = 6) -> Model:
+    """4 fingers x 4 hinges over a palm (the floor plane) and a free 0.06 m cube.
+
+    Finger bases at x in {-0.045, -0.015, 0.015, 0.045}, y = -0.06, z = 0.075; links are
+    capsules (r 0.01, density 1000) along +y of lengths 0.02/0.045/0.035/0.03; the first
+    hinge abducts about z, the other three flex toward -z.  Armature k_g^2 I_r on every
+    finger joint; PD actuators kp 0.5, kd 0.01.  Cube: edge 0.06, 0.1 kg, resting on the
+    palm.  Collisions: cube x 16 capsules (capsule-box) and palm x cube (plane-box).
+    nq 23, nv 22, nu 16, nconmax 36.
+    """
+    bld = _Builder("hand")
+    plane = bld.geom(0, GEOM_PLANE, (0, 0, 0), friction=mu, name="palm")
+    arm = leap_armature()
+    rho = 1000.0
+    r = 0.01
+    caps = []
+    joints = []
+    for fx in (-0.045, -0.015, 0.015, 0.045):
+        parent, pos = 0, (fx, -0.06, 0.075)
+        for k, L in enumerate(HAND_LINKS):
+            b = bld.body(parent, pos=pos)
+            axis = (0, 0, 1) if k == 0 else (-1, 0, 0)
+            joints.append(bld.joint(b, JNT_HINGE, axis=axis, armature=arm))
+            caps.append(bld.capsule_fromto(b, (0, 0, 0), (0, L, 0), r,
+                                           mass=rho * capsule_volume(r, 0.5 * L),
+                                           friction=mu))
+            parent, pos = b, (0, L, 0)
+    cube = bld.body(0, pos=(0, 0, 0.03), name="cube")
+    bld.joint(cube, JNT_FREE)
+    cube_g = bld.geom(cube, GEOM_BOX, (0.03, 0.03, 0.03), mass=0.1, friction=mu)
+    m = bld.finish()
+    for j in joints:
+        m.actuators.append(Actuator(type=ACT_PD, joint=j, gear=1.0, kp=0.5, kd=0.01,
+                                    ctrlrange=(-1.0, 1.0), qdefault=0.0))
+    # pair order follows geom type: capsule (2) before box (3), plane (0) before box
+    m.pairs = [(c, cube_g, mu) for c in caps] + [(plane, cube_g, mu)]
+    m.opt = Options(timestep=timestep, iterations=iterations, ls_iterations=8,
+                    nconmax=36)
+    q0 = np.zeros(m.nq)
+    q0[16:19] = (0, 0, 0.03)
+    q0[19] = 1.0
+    m.qpos0 = q0
+    return m
+
+
+# ----------------------------------------------------------------------------------
+# small models used by the reference checks
+
+
+def hinge_chain(n: int = 4, link: float = 0.3, mass: float = 1.0, damping: float = 0.0,
+                axes=None, slide_root: bool = False) -> Model:
+    """Planar/spatial chain of capsule links hanging from the world (no contacts)."""
+    bld = _Builder(f"chain{n}")
+    parent, pos = 0, (0, 0, 0)
+    if slide_root:
+        cart = bld.body(0, name="cart")
+        bld.joint(cart, JNT_SLIDE, axis=(1, 0, 0), damping=damping)
+        bld.geom(cart, GEOM_BOX, (0.1, 0.1, 0.1), mass=2.0)
+        parent = cart
+    for i in range(n):
+        b = bld.body(parent, pos=pos)
+        ax = (0, 1, 0) if axes is None else axes[i % len(axes)]
+        bld.joint(b, JNT_HINGE, axis=ax, damping=damping)
+        bld.capsule_fromto(b, (0, 0, 0), (link, 0, 0), 0.03, mass=mass)
+        parent, pos = b, (link, 0, 0)
+    m = bld.finish()
+    m.opt = Options(timestep=1e-3, iterations=1, nconmax=0)
+    m.qpos0 = np.zeros(m.nq)
+    return m
+
+
+def free_body(shape: str = "box", mass: float = 1.0, gravity=(0.0, 0.0, -9.81),
+              half=(0.1, 0.2, 0.3), z0: float = 1.0, plane: bool = False,
+              mu: float = 1.0, timestep: float = 0.002, iterations: int = 50) -> Model:
+    """One free body (box or sphere), optionally resting on a plane."""
+    bld = _Builder(f"free_{shape}")
+    pl = bld.geom(0, GEOM_PLANE, (0, 0, 0), friction=mu) if plane else None
+    b = bld.body(0, pos=(0, 0, z0))
+    bld.joint(b, JNT_FREE)
+    if shape == "box":
+        g = bld.geom(b, GEOM_BOX, half, mass=mass, friction=mu)
+        nc = 4
+    elif shape == "sphere":
+        g = bld.geom(b, GEOM_SPHERE, (half[0],), mass=mass, friction=mu)
+        nc = 1
+    elif shape == "capsule":
+        g = bld.geom(b, GEOM_CAPSULE, (half[0], half[1]), mass=mass, friction=mu)
+        nc = 2
+    else:
+        raise ValueError(shape)
+    m = bld.finish()
+    if plane:
+        m.pairs = [(pl, g, mu)]
+    m.opt = Options(timestep=timestep, gravity=tuple(gravity), iterations=iterations,
+                    ls_iterations=50, nconmax=nc if plane else 0)
+    q0 = np.zeros(7)
+    q0[2] = z0
+    q0[3] = 1.0
+    m.qpos0 = q0
+    return m
+
+
+def two_bodies(t1: str, t2: str, size1, size2, gravity=(0.0, 0.0, 0.0)) -> Model:
+    """Two free bodies with one collision pair between them (collision unit checks)."""
+    bld = _Builder(f"{t1}_{t2}")
+    kinds = {"sphere": GEOM_SPHERE, "capsule": GEOM_CAPSULE, "box": GEOM_BOX}
+    gs = []
+    for t, s, z in ((t1, size1, 0.0), (t2, size2, 1.0)):
+        b = bld.body(0, pos=(0, 0, z))
+        bld.joint(b, JNT_FREE)
+        gs.append(bld.geom(b, kinds[t], s, mass=1.0))
+    m = bld.finish()
+    g1, g2 = gs
+    if m.geoms[g1].type > m.geoms[g2].type:
+        g1, g2 = g2, g1
+    m.pairs = [(g1, g2, 1.0)]
+    m.opt = Options(timestep=0.002, gravity=tuple(gravity), iterations=20, nconmax=4)
+    q0 = np.zeros(14)
+    q0[3] = q0[10] = 1.0
+    q0[9] = 1.0
+    m.qpos0 = q0
+    return m
+
+
+WORKLOADS = {
+    "cartpole": cartpole,
+    "quadruped": quadruped,
+    "humanoid": humanoid,
+    "hand": hand,
+}
