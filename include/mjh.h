@@ -1,0 +1,151 @@
+/*
+ * mjh -- batched rigid-body physics step for AMD MI355X (gfx950), C ABI.
+ *
+ * The library advances many independent simulated worlds in lockstep on one GPU: the
+ * physics step that MuJoCo Playground runs under its RL environments (the paper's
+ * raw-throughput appendix times this "env step" alone with random actions; its
+ * locomotion and manipulation PPO runs use 8192 parallel environments).  Each step
+ * of each world runs, in order:
+ *   actuation (motors, and the PD position mapping of eq. pd_mapping),
+ *   forward kinematics, composite-rigid-body joint-space inertia with a tree-sparse
+ *   L^T D L factorisation, recursive Newton-Euler bias forces, primitive collision
+ *   (plane / sphere / capsule / box), a convex soft-constraint contact solve by Newton
+ *   iterations with an exact line search over a pyramidal friction cone, and
+ *   semi-implicit Euler integration.
+ * The solver knobs are the MJCF options the paper edits per task (Table
+ * tab:dm_control_envs): timestep, iterations, contact budget.
+ *
+ * Conventions
+ *   - All device buffers are FP32 (state) or int32 (status), row-major [nworld][n],
+ *     each world's row contiguous.  Quaternions are w-first.  A free joint's qpos is
+ *     (x, y, z, qw, qx, qy, qz) and its qvel is (world linear velocity of the body
+ *     origin, body-frame angular velocity).
+ *   - Ownership: the library owns model arrays, scratch, checkpoint tapes and graphs
+ *     (freed by mjh_world_free / mjh_destroy).  The caller owns state, controls,
+ *     outputs and streams; a stream argument is a hipStream_t (NULL = default stream).
+ *   - Execution: launches are asynchronous and stream-ordered.  mjh_model_upload,
+ *     mjh_world_alloc, mjh_bind_* and mjh_autotune synchronise the device.
+ *   - Errors: every call validates its arguments before launching anything.  A
+ *     negative return is an error and mjh_last_error() describes it; nothing aborts
+ *     the process.  Numerical trouble inside a world is not a call error: it is
+ *     written to that world's status word and the other worlds continue.
+ *   - Thread safety: one context must not be used from two host threads at once.
+ */
+#ifndef MJH_H_
+#define MJH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mjh_ctx mjh_ctx;
+typedef struct mjh_batch mjh_batch;
+typedef int32_t mjh_status;
+
+enum {
+  MJH_OK = 0,
+  MJH_EINVAL = -1,       /* bad argument (NULL, size, range, unbound state)       */
+  MJH_ENOMEM = -2,       /* device or host allocation failed                      */
+  MJH_EHIP = -3,         /* a HIP runtime call failed (text in mjh_last_error)    */
+  MJH_EMODEL = -4,       /* malformed model blob                                  */
+  MJH_EUNSUPPORTED = -5, /* model feature outside what the kernels implement      */
+  MJH_ESTATE = -6        /* call out of order (e.g. rollout_bwd before _fwd)      */
+};
+
+/* per-world status bits (OR-ed over the steps of one call) */
+enum {
+  MJH_WORLD_NONFINITE = 1, /* non-finite qpos/qvel after a step                    */
+  MJH_WORLD_OVERFLOW = 2,  /* more penetrating candidates than nconmax; deepest kept*/
+  MJH_WORLD_NODESCENT = 4  /* Newton Hessian factorisation failed; step truncated   */
+};
+
+/* contact record written by mjh_bind_io's contact_out: MJH_CON_SIZE floats each:
+ * dist, pos[3], frame[9] (normal geom1->geom2, tangent1, tangent2),
+ * f_normal, f_tangent1, f_tangent2, pair index, candidate index, 0, 0            */
+#define MJH_CON_SIZE 20
+
+typedef struct mjh_dims {
+  int32_t nq, nv, nu, nbody, ngeom, npair;
+  int32_t ncand;      /* candidate contact slots over all pairs                   */
+  int32_t nconmax;    /* contact budget per world                                 */
+  int32_t iterations; /* Newton iterations per step                              */
+  int32_t lds_bytes;  /* on-chip working set of one world                        */
+  float timestep;
+} mjh_dims;
+
+/* One context per device.  device: HIP device ordinal.  *out receives the handle. */
+mjh_status mjh_create(int device, mjh_ctx** out);
+void mjh_destroy(mjh_ctx* ctx);
+/* Text of the last failing call on this context (never NULL; "" after success). */
+const char* mjh_last_error(const mjh_ctx* ctx);
+
+/* Parse a model blob (host memory, the layout written by the Python model module:
+ * header, bodies, joints, geoms, pairs, actuators, qpos0), derive the tree tables,
+ * upload FP32 constants and compute the bodies' translational inverse weights at
+ * qpos0 on the device.  *model_id receives a handle valid until mjh_destroy.
+ * MJH_EMODEL for a malformed blob, MJH_EUNSUPPORTED for nv > 64, box-box pairs,
+ * a free joint below the root or two actuators on one dof. */
+mjh_status mjh_model_upload(mjh_ctx* ctx, const void* blob, size_t nbytes,
+                            int32_t* model_id);
+mjh_status mjh_model_info(mjh_ctx* ctx, int32_t model_id, mjh_dims* out);
+/* Copy the model's body translational inverse weights (nbody floats, host memory).
+ * They scale the contact regulariser: R = (1-d)/d * (1+mu^2) * (w(body1) + w(body2)). */
+mjh_status mjh_model_invweight(mjh_ctx* ctx, int32_t model_id, float* out);
+
+/* A batch of worlds made of nmodel groups: counts[g] worlds of model model_ids[g].
+ * Groups are stepped together in one launch.  counts[g] >= 0. */
+mjh_status mjh_world_alloc(mjh_ctx* ctx, const int32_t* model_ids, const int32_t* counts,
+                           int32_t nmodel, mjh_batch** out);
+void mjh_world_free(mjh_batch* batch);
+
+/* Bind caller-owned device state of group g: qpos [n][nq], qvel [n][nv],
+ * qacc_ws [n][nv] (the Newton warm start; after a step it holds that step's
+ * acceleration), status [n] (may be NULL).  The library reads and writes them in
+ * every mjh_step.  Synchronous; must not overlap a step of this batch. */
+mjh_status mjh_bind_state(mjh_batch* b, int32_t group, float* qpos, float* qvel,
+                          float* qacc_ws, int32_t* status);
+/* Bind per-call inputs/outputs of group g: ctrl [ctrl_nstep][n][nu] (device; NULL =
+ * zero controls; step s of a call reads row s), contact_out [n][nconmax][MJH_CON_SIZE]
+ * and ncon_out [n] (device, may be NULL) receive the last step's contacts. */
+mjh_status mjh_bind_io(mjh_batch* b, int32_t group, const float* ctrl, int32_t ctrl_nstep,
+                       float* contact_out, int32_t* ncon_out);
+
+/* Advance every world of the batch by nstep steps (nstep <= bound ctrl_nstep unless
+ * ctrl is NULL).  State stays on chip across the nstep steps of one launch. */
+mjh_status mjh_step(mjh_batch* b, int32_t nstep, void* stream);
+
+/* Capture mjh_step(b, nstep) into a HIP graph (replayed by mjh_graph_launch).  The
+ * graph reads the bound pointers at replay time, so rebinding needs no recapture. */
+mjh_status mjh_graph_capture(mjh_batch* b, int32_t nstep, void* stream);
+mjh_status mjh_graph_launch(mjh_batch* b, void* stream);
+
+/* Time candidate launch shapes (lanes per world, worlds per work-group) for every
+ * group on the bound state with nstep_probe steps, keep the fastest, and restore the
+ * state afterwards.  cache_path (may be NULL) stores choices across processes. */
+mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_path);
+/* Force a launch shape for group g: team in {16, 32, 64} lanes, block in {64..1024}. */
+mjh_status mjh_set_launch(mjh_batch* b, int32_t group, int32_t team, int32_t block);
+mjh_status mjh_get_launch(mjh_batch* b, int32_t group, int32_t* team, int32_t* block);
+
+/* Differentiable rollout of group 0 (single-model batch).
+ * Loss: sum_{t=1..horizon} (qpos_t[zidx] - ztarget)^2 + wctrl * sum_t |ctrl_t|^2.
+ * mjh_rollout_fwd runs horizon steps from the bound state with ctrl [horizon][n][nu],
+ * keeps a checkpoint every ckpt_every steps, writes loss [n] and leaves the bound
+ * state at the final step.  mjh_rollout_bwd(dloss [n]) writes grad_qvel0 [n][nv] and
+ * grad_ctrl [horizon][n][nu] by the adjoint of the step: implicit differentiation at
+ * each Newton solution, reverse sweeps of RNE/kinematics and contact geometry,
+ * segments recomputed from the checkpoints.  Only plane-sphere and plane-capsule
+ * contacts are differentiated (MJH_EUNSUPPORTED otherwise). */
+mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every,
+                           const float* ctrl, int32_t zidx, float ztarget, float wctrl,
+                           float* loss, void* stream);
+mjh_status mjh_rollout_bwd(mjh_batch* b, const float* dloss, float* grad_qvel0,
+                           float* grad_ctrl, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MJH_H_ */

@@ -72,8 +72,41 @@ inline Dual pow(Dual a, double p) {
   return {std::pow(a.v, p), p * std::pow(a.v, p - 1.0) * a.d};
 }
 inline bool isfinite(Dual a) { return std::isfinite(a.v) && std::isfinite(a.d); }
+inline bool isfinite(double a) { return std::isfinite(a); }
 inline double val(double x) { return x; }
 inline double val(Dual x) { return x.v; }
+
+// ------------------------------------------------------- operation-counting scalar
+// Counts floating-point operations (+ - * / and elementary functions, one each) of the
+// reference algorithm; used to report the algorithmic work of one step.
+thread_local long long g_flops = 0;
+struct Cnt {
+  double v = 0.0;
+  Cnt() = default;
+  Cnt(double x) : v(x) {}  // NOLINT: implicit on purpose
+};
+inline Cnt operator+(Cnt a, Cnt b) { g_flops++; return Cnt(a.v + b.v); }
+inline Cnt operator-(Cnt a, Cnt b) { g_flops++; return Cnt(a.v - b.v); }
+inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
+inline Cnt operator*(Cnt a, Cnt b) { g_flops++; return Cnt(a.v * b.v); }
+inline Cnt operator/(Cnt a, Cnt b) { g_flops++; return Cnt(a.v / b.v); }
+inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
+inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
+inline Cnt& operator*=(Cnt& a, Cnt b) { a = a * b; return a; }
+inline Cnt& operator/=(Cnt& a, Cnt b) { a = a / b; return a; }
+inline bool operator<(Cnt a, Cnt b) { return a.v < b.v; }
+inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
+inline bool operator<=(Cnt a, Cnt b) { return a.v <= b.v; }
+inline bool operator>=(Cnt a, Cnt b) { return a.v >= b.v; }
+inline bool operator==(Cnt a, Cnt b) { return a.v == b.v; }
+inline bool operator!=(Cnt a, Cnt b) { return a.v != b.v; }
+inline Cnt sqrt(Cnt a) { g_flops++; return Cnt(std::sqrt(a.v)); }
+inline Cnt sin(Cnt a) { g_flops++; return Cnt(std::sin(a.v)); }
+inline Cnt cos(Cnt a) { g_flops++; return Cnt(std::cos(a.v)); }
+inline Cnt fabs(Cnt a) { return Cnt(std::fabs(a.v)); }
+inline Cnt pow(Cnt a, double p) { g_flops++; return Cnt(std::pow(a.v, p)); }
+inline bool isfinite(Cnt a) { return std::isfinite(a.v); }
+inline double val(Cnt x) { return x.v; }
 
 using std::cos;
 using std::fabs;
@@ -1537,5 +1570,27 @@ int mjo_trajectory(void* h, int nstep, const double* qpos, const double* qvel,
   }
   if (status) *status = st;
   return 0;
+}
+}  // extern "C"
+
+extern "C" {
+// Average floating-point operation count of one step (fixed mode) from each of nworld
+// states, counted by the operation-counting scalar.
+double mjo_count_flops(void* h, int nworld, const double* qpos, const double* qvel,
+                       const double* qacc_ws, const double* ctrl) {
+  Model& m = *static_cast<Model*>(h);
+  long long total = 0;
+  for (int w = 0; w < nworld; w++) {
+    Data<Cnt> d;
+    d.alloc(m);
+    for (int i = 0; i < m.nq; i++) d.qpos[i] = qpos[(size_t)w * m.nq + i];
+    for (int i = 0; i < m.nv; i++) d.qvel[i] = qvel[(size_t)w * m.nv + i];
+    if (qacc_ws) for (int i = 0; i < m.nv; i++) d.qacc_ws[i] = qacc_ws[(size_t)w * m.nv + i];
+    if (ctrl) for (int a = 0; a < m.nu; a++) d.ctrl[a] = ctrl[(size_t)w * m.nu + a];
+    g_flops = 0;
+    step(m, d, 0);
+    total += g_flops;
+  }
+  return nworld > 0 ? (double)total / nworld : 0.0;
 }
 }  // extern "C"

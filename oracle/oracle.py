@@ -64,6 +64,8 @@ def _load():
                                         C.c_double, C.c_int, C.c_int, C.c_int, D, D]
         lib.mjo_step_jvp.argtypes = [P, D, D, D, D, D, D, D, C.c_int, D, D, D, D]
         lib.mjo_trajectory.argtypes = [P, C.c_int, D, D, D, D, C.c_int, D, D, I]
+        lib.mjo_count_flops.argtypes = [P, C.c_int, D, D, D, D]
+        lib.mjo_count_flops.restype = C.c_double
         _lib = lib
     return _lib
 
@@ -235,3 +237,15 @@ class Oracle:
                                  _d(_arr(ctrl, nstep * self.nu) if ctrl is not None else None),
                                  mode, _d(tq), _d(tv), _i(st))
         return tq, tv, int(st[0])
+
+    def count_flops(self, qpos, qvel, qacc_ws=None, ctrl=None) -> float:
+        """Average floating-point operations of one reference step from each state.
+
+        ctrl is [nworld, nu] or [1, nworld, nu]."""
+        qpos = np.array(qpos, dtype=np.float64, order="C", ndmin=2)
+        qvel = np.array(qvel, dtype=np.float64, order="C", ndmin=2)
+        nw = qpos.shape[0]
+        ws = None if qacc_ws is None else np.ascontiguousarray(qacc_ws, dtype=np.float64)
+        u = None if ctrl is None else np.ascontiguousarray(ctrl, dtype=np.float64).reshape(
+            nw, self.nu)
+        return float(self._lib.mjo_count_flops(self._h, nw, _d(qpos), _d(qvel), _d(ws), _d(u)))

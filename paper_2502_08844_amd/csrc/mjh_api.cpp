@@ -1,0 +1,901 @@
+// Host side of the C ABI: model blob parsing and compilation into device tables,
+// world batches, launches, graph capture and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/mjh.h"
+#include "mjh_adjoint.h"
+#include "mjh_kernels.h"
+#include "mjh_model.h"
+
+using namespace mjh;
+
+// ===================================================================== host model
+namespace {
+
+struct HostModel {
+  // parsed blob (double precision as stored)
+  int nbody = 0, njnt = 0, ngeom = 0, npair = 0, nu = 0, nq = 0, nv = 0;
+  int iterations = 0, ls_iterations = 0, nconmax = 0;
+  double dt = 0, grav[3] = {0, 0, 0}, solref[2] = {0, 0}, solimp[5] = {0, 0, 0, 0, 0};
+  std::vector<int> body_parent, jnt_type, jnt_body, geom_type, geom_body, pair_g1, pair_g2,
+      act_type, act_jnt;
+  std::vector<double> body_pos, body_quat, body_mass, body_ipos, body_inertia, jnt_pos,
+      jnt_axis, jnt_damping, jnt_armature, geom_size, geom_pos, geom_quat, pair_mu, act_gear,
+      act_kp, act_kd, act_lo, act_hi, act_qdef, qpos0;
+};
+
+struct ModelRec {
+  HostModel h;
+  DevModel dm{};
+  void* dbuf = nullptr;  // one device allocation for all tables
+  size_t dbytes = 0;
+  double cost = 0.0;     // relative cost of one world-step (task ordering)
+};
+
+class Blob {
+ public:
+  Blob(const uint8_t* p, size_t n) : p_(p), n_(n) {}
+  template <class X> bool read(X* dst, size_t count) {
+    const size_t bytes = sizeof(X) * count;
+    if (off_ + bytes > n_) return false;
+    std::memcpy(dst, p_ + off_, bytes);
+    off_ += bytes;
+    return true;
+  }
+  size_t off() const { return off_; }
+
+ private:
+  const uint8_t* p_;
+  size_t n_, off_ = 0;
+};
+
+mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::string& err) {
+  Blob r(blob, nbytes);
+  int32_t hi[16];
+  double hf[16];
+  if (!r.read(hi, 16) || !r.read(hf, 16)) { err = "model blob: truncated header"; return MJH_EMODEL; }
+  if (hi[0] != 0x4D484A4D || hi[1] != 1) { err = "model blob: bad magic or version"; return MJH_EMODEL; }
+  m.nbody = hi[2]; m.njnt = hi[3]; m.ngeom = hi[4]; m.npair = hi[5]; m.nu = hi[6];
+  m.nq = hi[7]; m.nv = hi[8]; m.iterations = hi[9]; m.ls_iterations = hi[10]; m.nconmax = hi[11];
+  if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nq < 0 ||
+      m.nv < 0 || m.iterations < 0 || m.nconmax < 0 || m.nbody > 4096 || m.njnt > 4096 ||
+      m.ngeom > 4096 || m.npair > 65536 || m.nu > 4096 || m.nconmax > 4096) {
+    err = "model blob: size field out of range";
+    return MJH_EMODEL;
+  }
+  m.dt = hf[0];
+  for (int k = 0; k < 3; k++) m.grav[k] = hf[1 + k];
+  m.solref[0] = hf[4]; m.solref[1] = hf[5];
+  for (int k = 0; k < 5; k++) m.solimp[k] = hf[6 + k];
+  auto rd = [&](auto& vec, size_t count) {
+    vec.resize(count);
+    return r.read(vec.data(), count);
+  };
+  std::vector<int32_t> bi, ji, gi, pi, ai;
+  std::vector<double> bf, jf, gf, pf, af;
+  bool ok = rd(bi, 2 * m.nbody) && rd(bf, 19 * (size_t)m.nbody) && rd(ji, 2 * m.njnt) &&
+            rd(jf, 8 * (size_t)m.njnt) && rd(gi, 2 * m.ngeom) && rd(gf, 11 * (size_t)m.ngeom) &&
+            rd(pi, 2 * m.npair) && rd(pf, m.npair) && rd(ai, 2 * m.nu) &&
+            rd(af, 7 * (size_t)m.nu) && rd(m.qpos0, m.nq);
+  if (!ok || r.off() != nbytes) { err = "model blob: size mismatch"; return MJH_EMODEL; }
+  for (int b = 0; b < m.nbody; b++) {
+    m.body_parent.push_back(bi[2 * b]);
+    const double* f = &bf[19 * b];
+    m.body_pos.insert(m.body_pos.end(), f, f + 3);
+    m.body_quat.insert(m.body_quat.end(), f + 3, f + 7);
+    m.body_mass.push_back(f[7]);
+    m.body_ipos.insert(m.body_ipos.end(), f + 8, f + 11);
+    m.body_inertia.insert(m.body_inertia.end(), f + 11, f + 17);
+    if (b == 0 ? bi[0] != -1 : (bi[2 * b] < 0 || bi[2 * b] >= b)) {
+      err = "model blob: bodies must follow their parents (body 0 = world)";
+      return MJH_EMODEL;
+    }
+  }
+  for (int j = 0; j < m.njnt; j++) {
+    const int type = ji[2 * j], body = ji[2 * j + 1];
+    if (type < 0 || type > 2 || body <= 0 || body >= m.nbody || (j > 0 && body < ji[2 * j - 1])) {
+      err = "model blob: bad joint (type/body/order)";
+      return MJH_EMODEL;
+    }
+    m.jnt_type.push_back(type);
+    m.jnt_body.push_back(body);
+    const double* f = &jf[8 * j];
+    m.jnt_pos.insert(m.jnt_pos.end(), f, f + 3);
+    const double L = std::sqrt(f[3] * f[3] + f[4] * f[4] + f[5] * f[5]);
+    if (type != JNT_FREE && !(L > 0)) { err = "model blob: zero joint axis"; return MJH_EMODEL; }
+    for (int k = 0; k < 3; k++) m.jnt_axis.push_back(L > 0 ? f[3 + k] / L : 0.0);
+    m.jnt_damping.push_back(f[6]);
+    m.jnt_armature.push_back(f[7]);
+  }
+  for (int g = 0; g < m.ngeom; g++) {
+    const int type = gi[2 * g], body = gi[2 * g + 1];
+    if (type < 0 || type > 3 || body < 0 || body >= m.nbody) { err = "model blob: bad geom"; return MJH_EMODEL; }
+    m.geom_type.push_back(type);
+    m.geom_body.push_back(body);
+    const double* f = &gf[11 * g];
+    m.geom_size.insert(m.geom_size.end(), f, f + 3);
+    m.geom_pos.insert(m.geom_pos.end(), f + 3, f + 6);
+    m.geom_quat.insert(m.geom_quat.end(), f + 6, f + 10);
+  }
+  for (int p = 0; p < m.npair; p++) {
+    const int g1 = pi[2 * p], g2 = pi[2 * p + 1];
+    if (g1 < 0 || g1 >= m.ngeom || g2 < 0 || g2 >= m.ngeom) { err = "model blob: bad pair"; return MJH_EMODEL; }
+    const int t1 = m.geom_type[g1], t2 = m.geom_type[g2];
+    if (t1 > t2) { err = "model blob: pair geoms must be ordered by type"; return MJH_EMODEL; }
+    if (t1 == GEOM_PLANE && t2 == GEOM_PLANE) { err = "model blob: plane-plane pair"; return MJH_EMODEL; }
+    if (t1 == GEOM_BOX && t2 == GEOM_BOX) { err = "box-box pairs are not supported"; return MJH_EUNSUPPORTED; }
+    m.pair_g1.push_back(g1);
+    m.pair_g2.push_back(g2);
+    m.pair_mu.push_back(pf[p]);
+  }
+  for (int a = 0; a < m.nu; a++) {
+    const int type = ai[2 * a], jnt = ai[2 * a + 1];
+    if (type < 0 || type > 1 || jnt < 0 || jnt >= m.njnt) { err = "model blob: bad actuator"; return MJH_EMODEL; }
+    if (m.jnt_type[jnt] == JNT_FREE) { err = "actuators on free joints are not supported"; return MJH_EUNSUPPORTED; }
+    m.act_type.push_back(type);
+    m.act_jnt.push_back(jnt);
+    const double* f = &af[7 * a];
+    m.act_gear.push_back(f[0]); m.act_kp.push_back(f[1]); m.act_kd.push_back(f[2]);
+    m.act_lo.push_back(f[3]); m.act_hi.push_back(f[4]); m.act_qdef.push_back(f[5]);
+  }
+  return MJH_OK;
+}
+
+void quat_mat(const double* q, float* R) {
+  double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  double w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
+  double r[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                 2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                 2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+  for (int k = 0; k < 9; k++) R[k] = (float)r[k];
+}
+
+int pair_kind_of(int t1, int t2) {
+  if (t1 == GEOM_PLANE) return t2 == GEOM_SPHERE ? PK_PLANE_SPHERE : t2 == GEOM_CAPSULE ? PK_PLANE_CAPSULE : PK_PLANE_BOX;
+  if (t1 == GEOM_SPHERE) return t2 == GEOM_SPHERE ? PK_SPHERE_SPHERE : t2 == GEOM_CAPSULE ? PK_SPHERE_CAPSULE : PK_SPHERE_BOX;
+  return t2 == GEOM_CAPSULE ? PK_CAPSULE_CAPSULE : PK_CAPSULE_BOX;
+}
+int pair_slots(int kind) {
+  switch (kind) {
+    case PK_PLANE_CAPSULE: return 2;
+    case PK_PLANE_BOX: return 8;
+    case PK_CAPSULE_BOX: return 4;
+    default: return 1;
+  }
+}
+
+// Derive tree tables and the on-chip layout; pack every table into one host image
+// whose device copy DevModel points into.
+struct Packer {
+  std::vector<uint8_t> bytes;
+  std::vector<std::pair<size_t, const void**>> fix;  // offset -> DevModel pointer field
+  template <class X> void add(const std::vector<X>& v, const X** field) {
+    size_t off = (bytes.size() + 15) & ~size_t(15);
+    bytes.resize(off + std::max<size_t>(v.size(), 1) * sizeof(X), 0);
+    if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(X));
+    fix.push_back({off, reinterpret_cast<const void**>(field)});
+  }
+};
+
+mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::string& err) {
+  DevModel& d = rec.dm;
+  d = DevModel{};
+  d.nbody = h.nbody; d.njnt = h.njnt; d.nq = h.nq; d.nv = h.nv; d.nu = h.nu;
+  d.ngeom = h.ngeom; d.npair = h.npair; d.nconmax = h.nconmax; d.nrowmax = 4 * h.nconmax;
+  d.iterations = h.iterations;
+  if (h.nv > kMaxNv) { err = "nv > 64 is not supported"; return MJH_EUNSUPPORTED; }
+  // addresses
+  std::vector<int> body_jntadr(h.nbody, 0), body_jntnum(h.nbody, 0), body_dofadr(h.nbody, 0),
+      body_dofnum(h.nbody, 0), jnt_qposadr, jnt_dofadr, dof_body;
+  std::vector<float> dof_armature, dof_damping;
+  int qa = 0, da = 0;
+  for (int j = 0; j < h.njnt; j++) {
+    const int b = h.jnt_body[j];
+    if (body_jntnum[b] == 0) { body_jntadr[b] = j; body_dofadr[b] = da; }
+    body_jntnum[b]++;
+    const int nd = h.jnt_type[j] == JNT_FREE ? 6 : 1;
+    if (h.jnt_type[j] == JNT_FREE && h.body_parent[b] != 0) {
+      err = "a free joint must attach a child of the world"; return MJH_EUNSUPPORTED;
+    }
+    body_dofnum[b] += nd;
+    jnt_qposadr.push_back(qa);
+    jnt_dofadr.push_back(da);
+    for (int k = 0; k < nd; k++) {
+      dof_body.push_back(b);
+      dof_armature.push_back((float)h.jnt_armature[j]);
+      dof_damping.push_back((float)h.jnt_damping[j]);
+    }
+    qa += h.jnt_type[j] == JNT_FREE ? 7 : 1;
+    da += nd;
+  }
+  for (int b = 0; b < h.nbody; b++)
+    for (int j = body_jntadr[b]; j < body_jntadr[b] + body_jntnum[b]; j++)
+      if (h.jnt_type[j] == JNT_FREE && body_jntnum[b] != 1) {
+        err = "a free joint must be its body's only joint"; return MJH_EUNSUPPORTED;
+      }
+  if (qa != h.nq || da != h.nv) { err = "model blob: nq/nv disagree with the joints"; return MJH_EMODEL; }
+  // dof tree
+  std::vector<int> dof_parent(h.nv, -1);
+  for (int k = 0; k < h.nv; k++) {
+    const int b = dof_body[k];
+    if (k > body_dofadr[b]) { dof_parent[k] = k - 1; continue; }
+    for (int p = h.body_parent[b]; p > 0; p = h.body_parent[p])
+      if (body_dofnum[p] > 0) { dof_parent[k] = body_dofadr[p] + body_dofnum[p] - 1; break; }
+  }
+  std::vector<int> anc_start(h.nv + 1, 0), anc_list, mpair;
+  for (int k = 0; k < h.nv; k++) {
+    anc_start[k] = (int)anc_list.size();
+    for (int i = dof_parent[k]; i >= 0; i = dof_parent[i]) anc_list.push_back(i);
+    mpair.push_back((k << 16) | k);
+    for (int i = dof_parent[k]; i >= 0; i = dof_parent[i]) mpair.push_back((k << 16) | i);
+  }
+  anc_start[h.nv] = (int)anc_list.size();
+  std::vector<unsigned long long> body_dofmask(h.nbody, 0ull);
+  for (int b = 1; b < h.nbody; b++) {
+    unsigned long long mk = body_dofmask[h.body_parent[b]];
+    for (int k = body_dofadr[b]; k < body_dofadr[b] + body_dofnum[b]; k++) mk |= 1ull << k;
+    body_dofmask[b] = mk;
+  }
+  // tree levels and children
+  std::vector<int> level(h.nbody, 0);
+  int nlevel = 1;
+  for (int b = 1; b < h.nbody; b++) {
+    level[b] = level[h.body_parent[b]] + 1;
+    nlevel = std::max(nlevel, level[b] + 1);
+  }
+  std::vector<int> level_start(nlevel + 1, 0), level_body;
+  for (int lv = 0; lv < nlevel; lv++) {
+    level_start[lv] = (int)level_body.size();
+    for (int b = 0; b < h.nbody; b++)
+      if (level[b] == lv) level_body.push_back(b);
+  }
+  level_start[nlevel] = (int)level_body.size();
+  std::vector<int> child_start(h.nbody + 1, 0), child_list;
+  for (int b = 0; b < h.nbody; b++) {
+    child_start[b] = (int)child_list.size();
+    for (int c = 1; c < h.nbody; c++)
+      if (h.body_parent[c] == b) child_list.push_back(c);
+  }
+  child_start[h.nbody] = (int)child_list.size();
+  // actuators: one per dof at most
+  std::vector<int> dof_act(h.nv, -1), act_qadr, act_dadr;
+  for (int a = 0; a < h.nu; a++) {
+    const int j = h.act_jnt[a];
+    const int dof = jnt_dofadr[j];
+    if (dof_act[dof] >= 0) { err = "two actuators on one dof are not supported"; return MJH_EUNSUPPORTED; }
+    dof_act[dof] = a;
+    act_qadr.push_back(jnt_qposadr[j]);
+    act_dadr.push_back(dof);
+  }
+  // pairs and candidate slots
+  std::vector<int> pair_kind, pair_candadr, cand_pair;
+  int ncand = 0;
+  for (int p = 0; p < h.npair; p++) {
+    const int kind = pair_kind_of(h.geom_type[h.pair_g1[p]], h.geom_type[h.pair_g2[p]]);
+    pair_kind.push_back(kind);
+    pair_candadr.push_back(ncand);
+    for (int k = 0; k < pair_slots(kind); k++) cand_pair.push_back(p);
+    ncand += pair_slots(kind);
+  }
+  d.ncand = ncand;
+  d.nlevel = nlevel;
+  d.nmpair = (int)mpair.size();
+  d.ntri = h.nv * (h.nv + 1) / 2;
+  // constants (soft-constraint conventions: time constant at least 2 dt)
+  const double tc = std::max(h.solref[0], 2.0 * h.dt), zeta = h.solref[1], dmax = h.solimp[1];
+  d.dt = (float)h.dt;
+  d.K = (float)(1.0 / (dmax * dmax * tc * tc * zeta * zeta));
+  d.B = (float)(2.0 / (dmax * tc));
+  d.dmin = (float)h.solimp[0]; d.dmax = (float)h.solimp[1]; d.width = (float)h.solimp[2];
+  d.mid = (float)h.solimp[3]; d.power = (float)h.solimp[4];
+  for (int k = 0; k < 3; k++) d.grav[k] = (float)h.grav[k];
+  // float tables
+  auto fv = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+  std::vector<float> body_rot(9 * h.nbody), geom_rot(9 * h.ngeom);
+  for (int b = 0; b < h.nbody; b++) quat_mat(&h.body_quat[4 * b], &body_rot[9 * b]);
+  for (int g = 0; g < h.ngeom; g++) quat_mat(&h.geom_quat[4 * g], &geom_rot[9 * g]);
+  std::vector<float> invw(h.nbody, 0.f);
+  pk.add(h.body_parent, &d.body_parent);
+  pk.add(body_jntadr, &d.body_jntadr);
+  pk.add(body_jntnum, &d.body_jntnum);
+  pk.add(body_dofadr, &d.body_dofadr);
+  pk.add(body_dofnum, &d.body_dofnum);
+  pk.add(level_start, &d.level_start);
+  pk.add(level_body, &d.level_body);
+  pk.add(child_start, &d.child_start);
+  pk.add(child_list, &d.child_list);
+  pk.add(h.jnt_type, &d.jnt_type);
+  pk.add(jnt_qposadr, &d.jnt_qposadr);
+  pk.add(jnt_dofadr, &d.jnt_dofadr);
+  pk.add(dof_body, &d.dof_body);
+  pk.add(dof_act, &d.dof_act);
+  pk.add(anc_start, &d.anc_start);
+  pk.add(anc_list, &d.anc_list);
+  pk.add(mpair, &d.mpair);
+  pk.add(body_dofmask, &d.body_dofmask);
+  pk.add(h.geom_type, &d.geom_type);
+  pk.add(h.geom_body, &d.geom_body);
+  pk.add(h.pair_g1, &d.pair_g1);
+  pk.add(h.pair_g2, &d.pair_g2);
+  pk.add(pair_kind, &d.pair_kind);
+  pk.add(pair_candadr, &d.pair_candadr);
+  pk.add(cand_pair, &d.cand_pair);
+  pk.add(h.act_type, &d.act_type);
+  pk.add(act_qadr, &d.act_qadr);
+  pk.add(act_dadr, &d.act_dadr);
+  std::vector<float> bpos = fv(h.body_pos), bmass = fv(h.body_mass), bipos = fv(h.body_ipos),
+                     binert = fv(h.body_inertia), jpos = fv(h.jnt_pos), jaxis = fv(h.jnt_axis),
+                     gsize = fv(h.geom_size), gpos = fv(h.geom_pos), pmu = fv(h.pair_mu),
+                     agear = fv(h.act_gear), akp = fv(h.act_kp), akd = fv(h.act_kd),
+                     alo = fv(h.act_lo), ahi = fv(h.act_hi), aqd = fv(h.act_qdef),
+                     q0 = fv(h.qpos0);
+  pk.add(bpos, &d.body_pos);
+  pk.add(body_rot, &d.body_rot);
+  pk.add(bmass, &d.body_mass);
+  pk.add(bipos, &d.body_ipos);
+  pk.add(binert, &d.body_inertia);
+  pk.add(jpos, &d.jnt_pos);
+  pk.add(jaxis, &d.jnt_axis);
+  pk.add(dof_armature, &d.dof_armature);
+  pk.add(dof_damping, &d.dof_damping);
+  pk.add(gsize, &d.geom_size);
+  pk.add(gpos, &d.geom_pos);
+  pk.add(geom_rot, &d.geom_rot);
+  pk.add(pmu, &d.pair_mu);
+  pk.add(agear, &d.act_gear);
+  pk.add(akp, &d.act_kp);
+  pk.add(akd, &d.act_kd);
+  pk.add(alo, &d.act_lo);
+  pk.add(ahi, &d.act_hi);
+  pk.add(aqd, &d.act_qdef);
+  pk.add(q0, &d.qpos0);
+  pk.add(invw, const_cast<const float**>(&d.body_invweight));
+  // on-chip layout (4-byte words, every block 16-byte aligned)
+  int off = 0;
+  auto take = [&](int words) {
+    const int o = off;
+    off += (words + 3) & ~3;
+    return o;
+  };
+  const int nb = h.nbody, nv = h.nv, nr = d.nrowmax;
+  // persistent across the whole step
+  d.o_qpos = take(h.nq);
+  d.o_qvel = take(nv);
+  d.o_qacc = take(nv);
+  d.o_xpos = take(3 * nb);
+  d.o_xmat = take(9 * nb);
+  d.o_cdof = take(6 * nv);
+  d.o_M = take(d.ntri);
+  d.o_frc = take(nv);
+  d.o_a0 = take(nv);
+  d.o_scal = take(SC_COUNT);
+  // the sweeps' scratch (velocities, bias accelerations, forces, inertias) is dead once
+  // the mass matrix is built; the contact and Newton scratch reuses the same words
+  const int shared = off;
+  d.o_cvel = take(6 * nb);
+  d.o_cacc = take(6 * nb);
+  d.o_cfrc = take(6 * nb);
+  d.o_cinert = take(kCinert * nb);
+  d.o_F = take(6 * nv);
+  const int sweep_end = off;
+  off = shared;
+  d.o_H = take(d.ntri);
+  d.o_Mr = take(nv);
+  d.o_g = take(nv);
+  d.o_d = take(nv);
+  d.o_Md = take(nv);
+  d.o_tmp = take(nv);
+  d.o_cand = take(2 * ncand);
+  d.o_con = take(kConRec * h.nconmax);
+  d.o_J = take(nr * nv);
+  d.o_aref = take(nr);
+  d.o_D = take(nr);
+  d.o_e = take(nr);
+  d.o_s = take(nr);
+  off = std::max(off, sweep_end);
+  d.lds_words = off;
+  rec.cost = (double)nv * nv * (nv + 4.0 * nr) + 50.0 * nb + 30.0 * ncand;
+  return MJH_OK;
+}
+
+}  // namespace
+
+// ===================================================================== contexts
+struct mjh_ctx {
+  int device = 0;
+  std::string err;
+  std::vector<std::unique_ptr<ModelRec>> models;
+  size_t lds_limit = 65536;  // dynamic LDS per work-group the device allows
+  int num_cu = 0;
+};
+
+struct GroupRec {
+  int model = 0;
+  int nworld = 0;
+  float* qpos = nullptr;
+  float* qvel = nullptr;
+  float* qacc = nullptr;
+  int* status = nullptr;
+  const float* ctrl = nullptr;
+  int ctrl_nstep = 0;
+  float* con_out = nullptr;
+  int* ncon_out = nullptr;
+  int team = 32;
+  int block = 128;
+};
+
+struct mjh_batch {
+  mjh_ctx* ctx = nullptr;
+  std::vector<GroupRec> groups;
+  DevGroup* d_groups = nullptr;
+  DevTask* d_tasks = nullptr;
+  int ntask = 0;
+  int block = 64;
+  size_t lds_bytes = 0;
+  bool dirty = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_nstep = 0;
+  AdjointState* adj = nullptr;
+};
+
+#define MJH_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);                    \
+      return MJH_EHIP;                                                                 \
+    }                                                                                  \
+  } while (0)
+
+static mjh_status fail(mjh_ctx* ctx, mjh_status code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+// worlds per work-group for a group's launch shape, bounded by the LDS budget
+static int worlds_per_block(const mjh_ctx* ctx, const ModelRec& mr, int team, int block) {
+  int wpb = std::max(1, block / team);
+  const size_t per = (size_t)mr.dm.lds_words * sizeof(float);
+  while (wpb > 1 && (size_t)wpb * per > ctx->lds_limit) wpb--;
+  return wpb;
+}
+
+// rebuild the device group/task tables (synchronous)
+static mjh_status sync_tables(mjh_batch* b) {
+  mjh_ctx* ctx = b->ctx;
+  if (!b->dirty) return MJH_OK;
+  std::vector<DevGroup> dg(b->groups.size());
+  struct Tk { DevTask t; double cost; };
+  std::vector<Tk> tasks;
+  int block = 0;
+  size_t lds = 0;
+  for (size_t g = 0; g < b->groups.size(); g++) {
+    const GroupRec& gr = b->groups[g];
+    const ModelRec& mr = *ctx->models[gr.model];
+    DevGroup& x = dg[g];
+    x.m = mr.dm;
+    x.qpos = gr.qpos; x.qvel = gr.qvel; x.qacc = gr.qacc; x.status = gr.status;
+    x.ctrl = gr.ctrl; x.con_out = gr.con_out; x.ncon_out = gr.ncon_out;
+    x.nworld = gr.nworld; x.ctrl_nstep = gr.ctrl_nstep; x.team = gr.team;
+    if (gr.nworld == 0) continue;
+    const int wpb = worlds_per_block(ctx, mr, gr.team, gr.block);
+    const size_t per = (size_t)mr.dm.lds_words * sizeof(float);
+    if (per > ctx->lds_limit)
+      return fail(ctx, MJH_EUNSUPPORTED, "one world's working set exceeds the LDS limit");
+    block = std::max(block, wpb * gr.team);
+    lds = std::max(lds, (size_t)wpb * per);
+    for (int w0 = 0; w0 < gr.nworld; w0 += wpb) {
+      Tk t;
+      t.t.group = (int)g; t.t.w0 = w0; t.t.nw = std::min(wpb, gr.nworld - w0); t.t.pad_ = 0;
+      t.cost = mr.cost * t.t.nw;
+      tasks.push_back(t);
+    }
+  }
+  // expensive work-groups first: the dispatcher then fills the device longest-first
+  std::stable_sort(tasks.begin(), tasks.end(), [](const Tk& a, const Tk& c) { return a.cost > c.cost; });
+  std::vector<DevTask> dt(tasks.size());
+  for (size_t i = 0; i < tasks.size(); i++) dt[i] = tasks[i].t;
+  if (b->d_groups) { (void)hipFree(b->d_groups); b->d_groups = nullptr; }
+  if (b->d_tasks) { (void)hipFree(b->d_tasks); b->d_tasks = nullptr; }
+  MJH_HIP(hipMalloc(&b->d_groups, std::max<size_t>(dg.size(), 1) * sizeof(DevGroup)));
+  MJH_HIP(hipMalloc(&b->d_tasks, std::max<size_t>(dt.size(), 1) * sizeof(DevTask)));
+  if (!dg.empty()) MJH_HIP(hipMemcpy(b->d_groups, dg.data(), dg.size() * sizeof(DevGroup), hipMemcpyHostToDevice));
+  if (!dt.empty()) MJH_HIP(hipMemcpy(b->d_tasks, dt.data(), dt.size() * sizeof(DevTask), hipMemcpyHostToDevice));
+  b->ntask = (int)dt.size();
+  b->block = std::max(block, 16);
+  b->lds_bytes = lds;
+  b->dirty = false;
+  if (b->graph_exec) { (void)hipGraphExecDestroy(b->graph_exec); b->graph_exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  return MJH_OK;
+}
+
+// ===================================================================== C ABI
+extern "C" {
+
+mjh_status mjh_create(int device, mjh_ctx** out) {
+  if (!out) return MJH_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MJH_EINVAL;
+  auto* ctx = new (std::nothrow) mjh_ctx();
+  if (!ctx) return MJH_ENOMEM;
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess) { delete ctx; return MJH_EHIP; }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ctx; return MJH_EHIP; }
+  int lim = 0;
+  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lim > 0)
+    ctx->lds_limit = (size_t)lim;
+  ctx->num_cu = prop.multiProcessorCount;
+  if (set_step_lds_limit(ctx->lds_limit) != hipSuccess) ctx->lds_limit = 65536;
+  *out = ctx;
+  return MJH_OK;
+}
+
+void mjh_destroy(mjh_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  for (auto& m : ctx->models)
+    if (m && m->dbuf) (void)hipFree(m->dbuf);
+  delete ctx;
+}
+
+const char* mjh_last_error(const mjh_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+mjh_status mjh_model_upload(mjh_ctx* ctx, const void* blob, size_t nbytes, int32_t* model_id) {
+  if (!ctx) return MJH_EINVAL;
+  if (!blob || !model_id) return fail(ctx, MJH_EINVAL, "model_upload: NULL argument");
+  ctx->err.clear();
+  auto rec = std::make_unique<ModelRec>();
+  std::string err;
+  mjh_status st = parse_blob(static_cast<const uint8_t*>(blob), nbytes, rec->h, err);
+  if (st != MJH_OK) return fail(ctx, st, err);
+  Packer pk;
+  st = compile_model(rec->h, *rec, pk, err);
+  if (st != MJH_OK) return fail(ctx, st, err);
+  if ((size_t)rec->dm.lds_words * 4 > ctx->lds_limit)
+    return fail(ctx, MJH_EUNSUPPORTED, "model working set exceeds the device's LDS per work-group");
+  MJH_HIP(hipSetDevice(ctx->device));
+  MJH_HIP(hipMalloc(&rec->dbuf, pk.bytes.size()));
+  rec->dbytes = pk.bytes.size();
+  MJH_HIP(hipMemcpy(rec->dbuf, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice));
+  uint8_t* base = static_cast<uint8_t*>(rec->dbuf);
+  for (auto& f : pk.fix) *f.second = base + f.first;
+  // translational inverse weights at qpos0, computed on the device
+  MJH_HIP(launch_invweight(rec->dm, nullptr));
+  MJH_HIP(hipDeviceSynchronize());
+  *model_id = (int32_t)ctx->models.size();
+  ctx->models.push_back(std::move(rec));
+  return MJH_OK;
+}
+
+mjh_status mjh_model_info(mjh_ctx* ctx, int32_t model_id, mjh_dims* out) {
+  if (!ctx) return MJH_EINVAL;
+  if (!out || model_id < 0 || model_id >= (int)ctx->models.size())
+    return fail(ctx, MJH_EINVAL, "model_info: bad model id or NULL output");
+  const DevModel& d = ctx->models[model_id]->dm;
+  out->nq = d.nq; out->nv = d.nv; out->nu = d.nu; out->nbody = d.nbody; out->ngeom = d.ngeom;
+  out->npair = d.npair; out->ncand = d.ncand; out->nconmax = d.nconmax;
+  out->iterations = d.iterations; out->lds_bytes = d.lds_words * 4; out->timestep = d.dt;
+  return MJH_OK;
+}
+
+mjh_status mjh_model_invweight(mjh_ctx* ctx, int32_t model_id, float* out) {
+  if (!ctx) return MJH_EINVAL;
+  if (!out || model_id < 0 || model_id >= (int)ctx->models.size())
+    return fail(ctx, MJH_EINVAL, "model_invweight: bad model id or NULL output");
+  const DevModel& d = ctx->models[model_id]->dm;
+  MJH_HIP(hipMemcpy(out, d.body_invweight, d.nbody * sizeof(float), hipMemcpyDeviceToHost));
+  return MJH_OK;
+}
+
+mjh_status mjh_world_alloc(mjh_ctx* ctx, const int32_t* model_ids, const int32_t* counts,
+                           int32_t nmodel, mjh_batch** out) {
+  if (!ctx) return MJH_EINVAL;
+  if (!model_ids || !counts || !out || nmodel <= 0)
+    return fail(ctx, MJH_EINVAL, "world_alloc: NULL argument or nmodel <= 0");
+  *out = nullptr;
+  auto* b = new (std::nothrow) mjh_batch();
+  if (!b) return fail(ctx, MJH_ENOMEM, "world_alloc: out of host memory");
+  b->ctx = ctx;
+  for (int g = 0; g < nmodel; g++) {
+    if (model_ids[g] < 0 || model_ids[g] >= (int)ctx->models.size() || counts[g] < 0) {
+      delete b;
+      return fail(ctx, MJH_EINVAL, "world_alloc: bad model id or negative count");
+    }
+    GroupRec gr;
+    gr.model = model_ids[g];
+    gr.nworld = counts[g];
+    const DevModel& d = ctx->models[gr.model]->dm;
+    // default launch shape: small trees take half a wavefront, large ones a whole one
+    gr.team = d.nv <= 8 ? 16 : (d.nrowmax <= 32 ? 32 : 64);
+    gr.block = 128;
+    b->groups.push_back(gr);
+  }
+  *out = b;
+  return MJH_OK;
+}
+
+void mjh_world_free(mjh_batch* b) {
+  if (!b) return;
+  if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_groups) (void)hipFree(b->d_groups);
+  if (b->d_tasks) (void)hipFree(b->d_tasks);
+  adjoint_free(b->adj);
+  delete b;
+}
+
+mjh_status mjh_bind_state(mjh_batch* b, int32_t group, float* qpos, float* qvel, float* qacc_ws,
+                          int32_t* status) {
+  if (!b) return MJH_EINVAL;
+  mjh_ctx* ctx = b->ctx;
+  if (group < 0 || group >= (int)b->groups.size())
+    return fail(ctx, MJH_EINVAL, "bind_state: bad group");
+  GroupRec& g = b->groups[group];
+  if (g.nworld > 0 && (!qpos || !qvel || !qacc_ws))
+    return fail(ctx, MJH_EINVAL, "bind_state: qpos, qvel and qacc_ws are required");
+  g.qpos = qpos; g.qvel = qvel; g.qacc = qacc_ws; g.status = status;
+  b->dirty = true;
+  return sync_tables(b);
+}
+
+mjh_status mjh_bind_io(mjh_batch* b, int32_t group, const float* ctrl, int32_t ctrl_nstep,
+                       float* contact_out, int32_t* ncon_out) {
+  if (!b) return MJH_EINVAL;
+  mjh_ctx* ctx = b->ctx;
+  if (group < 0 || group >= (int)b->groups.size())
+    return fail(ctx, MJH_EINVAL, "bind_io: bad group");
+  if (ctrl && ctrl_nstep <= 0) return fail(ctx, MJH_EINVAL, "bind_io: ctrl_nstep must be > 0");
+  if (ncon_out && !contact_out) return fail(ctx, MJH_EINVAL, "bind_io: ncon_out needs contact_out");
+  GroupRec& g = b->groups[group];
+  g.ctrl = ctrl; g.ctrl_nstep = ctrl ? ctrl_nstep : 0;
+  g.con_out = contact_out; g.ncon_out = ncon_out;
+  b->dirty = true;
+  return sync_tables(b);
+}
+
+static mjh_status check_ready(mjh_batch* b, int32_t nstep) {
+  mjh_ctx* ctx = b->ctx;
+  if (nstep < 0) return fail(ctx, MJH_EINVAL, "step: nstep < 0");
+  for (auto& g : b->groups) {
+    if (g.nworld == 0) continue;
+    if (!g.qpos || !g.qvel || !g.qacc) return fail(ctx, MJH_ESTATE, "step: state not bound");
+    if (g.ctrl && nstep > g.ctrl_nstep)
+      return fail(ctx, MJH_EINVAL, "step: nstep exceeds the bound control rows");
+  }
+  return MJH_OK;
+}
+
+mjh_status mjh_step(mjh_batch* b, int32_t nstep, void* stream) {
+  if (!b) return MJH_EINVAL;
+  mjh_ctx* ctx = b->ctx;
+  mjh_status st = check_ready(b, nstep);
+  if (st != MJH_OK) return st;
+  st = sync_tables(b);
+  if (st != MJH_OK) return st;
+  if (nstep == 0 || b->ntask == 0) return MJH_OK;
+  MJH_HIP(launch_step(b->d_groups, b->d_tasks, b->ntask, nstep, b->block, b->lds_bytes,
+                      static_cast<hipStream_t>(stream)));
+  return MJH_OK;
+}
+
+mjh_status mjh_graph_capture(mjh_batch* b, int32_t nstep, void* stream) {
+  if (!b) return MJH_EINVAL;
+  mjh_ctx* ctx = b->ctx;
+  if (!stream) return fail(ctx, MJH_EINVAL, "graph_capture: needs a non-default stream");
+  mjh_status st = check_ready(b, nstep);
+  if (st != MJH_OK) return st;
+  st = sync_tables(b);
+  if (st != MJH_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (b->graph_exec) { (void)hipGraphExecDestroy(b->graph_exec); b->graph_exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  MJH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipError_t le = launch_step(b->d_groups, b->d_tasks, b->ntask, nstep, b->block, b->lds_bytes, s);
+  hipGraph_t g = nullptr;
+  hipError_t ce = hipStreamEndCapture(s, &g);
+  if (le != hipSuccess || ce != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(ctx, MJH_EHIP, std::string("graph capture failed: ") +
+                                   hipGetErrorString(le != hipSuccess ? le : ce));
+  }
+  b->graph = g;
+  MJH_HIP(hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
+  b->graph_nstep = nstep;
+  return MJH_OK;
+}
+
+mjh_status mjh_graph_launch(mjh_batch* b, void* stream) {
+  if (!b) return MJH_EINVAL;
+  mjh_ctx* ctx = b->ctx;
+  if (!b->graph_exec) return fail(ctx, MJH_ESTATE, "graph_launch: no captured graph");
+  if (b->dirty) return fail(ctx, MJH_ESTATE, "graph_launch: launch shape changed; capture again");
+  mjh_status st = check_ready(b, b->graph_nstep);
+  if (st != MJH_OK) return st;
+  MJH_HIP(hipGraphLaunch(b->graph_exec, static_cast<hipStream_t>(stream)));
+  return MJH_OK;
+}
+
+mjh_status mjh_set_launch(mjh_batch* b, int32_t group, int32_t team, int32_t block) {
+  if (!b) return MJH_EINVAL;
+  mjh_ctx* ctx = b->ctx;
+  if (group < 0 || group >= (int)b->groups.size())
+    return fail(ctx, MJH_EINVAL, "set_launch: bad group");
+  if (!(team == 16 || team == 32 || team == 64) || block < team || block > kMaxBlock ||
+      block % team != 0)
+    return fail(ctx, MJH_EINVAL, "set_launch: team in {16,32,64}, block a multiple of team <= 256");
+  b->groups[group].team = team;
+  b->groups[group].block = block;
+  b->dirty = true;
+  return sync_tables(b);
+}
+
+mjh_status mjh_get_launch(mjh_batch* b, int32_t group, int32_t* team, int32_t* block) {
+  if (!b) return MJH_EINVAL;
+  if (group < 0 || group >= (int)b->groups.size() || !team || !block)
+    return fail(b->ctx, MJH_EINVAL, "get_launch: bad group or NULL output");
+  *team = b->groups[group].team;
+  *block = b->groups[group].block;
+  return MJH_OK;
+}
+
+// Time every candidate shape per group (other groups keep their shape), keep the
+// fastest.  The bound state is saved before and restored after the probes.
+mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_path) {
+  if (!b) return MJH_EINVAL;
+  mjh_ctx* ctx = b->ctx;
+  if (nstep_probe <= 0) return fail(ctx, MJH_EINVAL, "autotune: nstep_probe must be > 0");
+  mjh_status st = check_ready(b, nstep_probe);
+  if (st != MJH_OK) return st;
+  // cache: lines "nq nv nbody npair nconmax nworld team block"
+  std::map<std::string, std::pair<int, int>> cache;
+  auto key_of = [&](const GroupRec& g) {
+    const DevModel& d = ctx->models[g.model]->dm;
+    std::ostringstream k;
+    k << d.nq << ' ' << d.nv << ' ' << d.nbody << ' ' << d.npair << ' ' << d.nconmax << ' '
+      << d.iterations << ' ' << g.nworld;
+    return k.str();
+  };
+  if (cache_path) {
+    std::ifstream f(cache_path);
+    std::string line;
+    while (std::getline(f, line)) {
+      std::istringstream is(line);
+      int v[7], t, bl;
+      bool ok = true;
+      for (int& x : v) ok = ok && (bool)(is >> x);
+      if (ok && (is >> t >> bl)) {
+        std::ostringstream k;
+        k << v[0] << ' ' << v[1] << ' ' << v[2] << ' ' << v[3] << ' ' << v[4] << ' ' << v[5] << ' ' << v[6];
+        cache[k.str()] = {t, bl};
+      }
+    }
+  }
+  // save state
+  struct Saved { std::vector<float> q, v, a; };
+  std::vector<Saved> saved(b->groups.size());
+  for (size_t g = 0; g < b->groups.size(); g++) {
+    GroupRec& gr = b->groups[g];
+    const DevModel& d = ctx->models[gr.model]->dm;
+    saved[g].q.resize((size_t)gr.nworld * d.nq);
+    saved[g].v.resize((size_t)gr.nworld * d.nv);
+    saved[g].a.resize((size_t)gr.nworld * d.nv);
+    if (gr.nworld == 0) continue;
+    MJH_HIP(hipMemcpy(saved[g].q.data(), gr.qpos, saved[g].q.size() * 4, hipMemcpyDeviceToHost));
+    MJH_HIP(hipMemcpy(saved[g].v.data(), gr.qvel, saved[g].v.size() * 4, hipMemcpyDeviceToHost));
+    MJH_HIP(hipMemcpy(saved[g].a.data(), gr.qacc, saved[g].a.size() * 4, hipMemcpyDeviceToHost));
+  }
+  auto restore = [&]() -> mjh_status {
+    for (size_t g = 0; g < b->groups.size(); g++) {
+      GroupRec& gr = b->groups[g];
+      if (gr.nworld == 0) continue;
+      MJH_HIP(hipMemcpy(gr.qpos, saved[g].q.data(), saved[g].q.size() * 4, hipMemcpyHostToDevice));
+      MJH_HIP(hipMemcpy(gr.qvel, saved[g].v.data(), saved[g].v.size() * 4, hipMemcpyHostToDevice));
+      MJH_HIP(hipMemcpy(gr.qacc, saved[g].a.data(), saved[g].a.size() * 4, hipMemcpyHostToDevice));
+    }
+    return MJH_OK;
+  };
+  hipEvent_t e0, e1;
+  MJH_HIP(hipEventCreate(&e0));
+  MJH_HIP(hipEventCreate(&e1));
+  const int teams[3] = {16, 32, 64};
+  const int blocks[3] = {64, 128, 256};
+  for (size_t g = 0; g < b->groups.size(); g++) {
+    GroupRec& gr = b->groups[g];
+    if (gr.nworld == 0) continue;
+    const std::string key = key_of(gr);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      gr.team = it->second.first;
+      gr.block = it->second.second;
+      b->dirty = true;
+      continue;
+    }
+    // time this group alone: other groups are switched off during its probes
+    std::vector<int> counts;
+    for (auto& o : b->groups) counts.push_back(o.nworld);
+    for (size_t o = 0; o < b->groups.size(); o++)
+      if (o != g) b->groups[o].nworld = 0;
+    float best = INFINITY;
+    int bt = gr.team, bb = gr.block;
+    for (int t : teams)
+      for (int bl : blocks) {
+        if (bl < t) continue;
+        gr.team = t;
+        gr.block = bl;
+        b->dirty = true;
+        st = sync_tables(b);
+        if (st != MJH_OK) break;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; rep++) {  // first run warms caches
+          if (restore() != MJH_OK) { st = MJH_EHIP; break; }
+          MJH_HIP(hipEventRecord(e0, nullptr));
+          MJH_HIP(launch_step(b->d_groups, b->d_tasks, b->ntask, nstep_probe, b->block, b->lds_bytes, nullptr));
+          MJH_HIP(hipEventRecord(e1, nullptr));
+          MJH_HIP(hipEventSynchronize(e1));
+          MJH_HIP(hipEventElapsedTime(&ms, e0, e1));
+        }
+        if (st != MJH_OK) break;
+        if (ms < best) { best = ms; bt = t; bb = bl; }
+      }
+    for (size_t o = 0; o < b->groups.size(); o++) b->groups[o].nworld = counts[o];
+    gr.team = bt;
+    gr.block = bb;
+    b->dirty = true;
+    if (st != MJH_OK) break;
+    cache[key] = {bt, bb};
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  mjh_status rs = restore();
+  if (st == MJH_OK) st = rs;
+  if (st == MJH_OK) st = sync_tables(b);
+  if (st == MJH_OK && cache_path) {
+    std::ofstream f(cache_path);
+    for (auto& kv : cache) f << kv.first << ' ' << kv.second.first << ' ' << kv.second.second << '\n';
+  }
+  return st;
+}
+
+mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every, const float* ctrl,
+                           int32_t zidx, float ztarget, float wctrl, float* loss, void* stream) {
+  if (!b) return MJH_EINVAL;
+  mjh_ctx* ctx = b->ctx;
+  if (b->groups.size() != 1) return fail(ctx, MJH_EINVAL, "rollout: single-model batches only");
+  GroupRec& g = b->groups[0];
+  const ModelRec& mr = *ctx->models[g.model];
+  std::string err;
+  mjh_status st = adjoint_forward(&b->adj, mr.dm, g.nworld, g.qpos, g.qvel, g.qacc, horizon,
+                                  ckpt_every, ctrl, zidx, ztarget, wctrl, loss,
+                                  static_cast<hipStream_t>(stream), err);
+  if (st != MJH_OK) return fail(ctx, st, err);
+  return MJH_OK;
+}
+
+mjh_status mjh_rollout_bwd(mjh_batch* b, const float* dloss, float* grad_qvel0, float* grad_ctrl,
+                           void* stream) {
+  if (!b) return MJH_EINVAL;
+  mjh_ctx* ctx = b->ctx;
+  std::string err;
+  mjh_status st = adjoint_backward(b->adj, dloss, grad_qvel0, grad_ctrl,
+                                   static_cast<hipStream_t>(stream), err);
+  if (st != MJH_OK) return fail(ctx, st, err);
+  return MJH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1081 @@
+// Device phases of one physics step for one world, executed by a team of T lanes
+// (T in {16, 32, 64}, always inside one wavefront).  The world's working set lives in
+// LDS at `W` (layout in DevModel); loops are strided over the team's lanes and phases
+// are separated by wavefront-level barriers.
+//
+// Phase order per step (the MuJoCo pipeline that the paper's environments step):
+//   actuation -> kinematics + velocities + RNE forward sweep (by tree level)
+//   -> backward sweep (composite inertia, RNE forces) -> mass matrix (CRBA)
+//   -> sparse L^T D L factorisation and unconstrained acceleration
+//   -> collision candidates, selection, contact records -> pyramidal constraint rows
+//   -> Newton solve with exact line search -> semi-implicit Euler.
+// The mathematics follows Featherstone, Rigid Body Dynamics Algorithms (spatial
+// algebra ch. 2, RNEA Table 5.1, CRBA Table 6.2, LTDL sec. 6.5), Todorov (ICRA 2014)
+// for the soft-constraint cost, and Ericson ch. 5 for closest points.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mjh_model.h"
+
+namespace mjh {
+
+#define DEV __device__ __forceinline__
+
+
+// ------------------------------------------------------------------- team helpers
+struct Team {
+  int lane;  // 0 .. T-1
+  int T;     // lanes per world: 16, 32 or 64
+  // wavefront-level barrier: orders LDS traffic of all lanes of the wave
+  DEV void sync() const {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  DEV float sum(float v) const {
+    for (int o = T >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, T);
+    return v;
+  }
+  DEV float max(float v) const {
+    for (int o = T >> 1; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, T));
+    return v;
+  }
+  DEV float min(float v) const {
+    for (int o = T >> 1; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, T));
+    return v;
+  }
+  DEV int isum(int v) const {
+    for (int o = T >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, T);
+    return v;
+  }
+  DEV int ior(int v) const {
+    for (int o = T >> 1; o > 0; o >>= 1) v |= __shfl_xor(v, o, T);
+    return v;
+  }
+  // exclusive prefix sum over the team's lanes
+  DEV int exscan(int v) const {
+    int x = v;
+    for (int o = 1; o < T; o <<= 1) {
+      int y = __shfl_up(x, o, T);
+      if (lane >= o) x += y;
+    }
+    return x - v;
+  }
+};
+
+// ------------------------------------------------------------------ small algebra
+DEV float dot3(const float* a, const float* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+DEV void cross3(const float* a, const float* b, float* r) {
+  float x = a[1] * b[2] - a[2] * b[1];
+  float y = a[2] * b[0] - a[0] * b[2];
+  float z = a[0] * b[1] - a[1] * b[0];
+  r[0] = x; r[1] = y; r[2] = z;
+}
+DEV void mv3(const float* R, const float* v, float* r) {  // r = R v (row-major R)
+  float x = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
+  float y = R[3] * v[0] + R[4] * v[1] + R[5] * v[2];
+  float z = R[6] * v[0] + R[7] * v[1] + R[8] * v[2];
+  r[0] = x; r[1] = y; r[2] = z;
+}
+DEV void mtv3(const float* R, const float* v, float* r) {  // r = R^T v
+  float x = R[0] * v[0] + R[3] * v[1] + R[6] * v[2];
+  float y = R[1] * v[0] + R[4] * v[1] + R[7] * v[2];
+  float z = R[2] * v[0] + R[5] * v[1] + R[8] * v[2];
+  r[0] = x; r[1] = y; r[2] = z;
+}
+DEV void mm3(const float* A, const float* B, float* C) {  // C = A B (C may alias)
+  float o[9];
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+      o[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+#pragma unroll
+  for (int k = 0; k < 9; k++) C[k] = o[k];
+}
+DEV void quat_to_mat(const float* q, float* R) {
+  float w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z); R[2] = 2.f * (x * z + w * y);
+  R[3] = 2.f * (x * y + w * z); R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+  R[6] = 2.f * (x * z - w * y); R[7] = 2.f * (y * z + w * x); R[8] = 1.f - 2.f * (x * x + y * y);
+}
+// rotation by angle about unit axis a
+DEV void axis_rot(const float* a, float ang, float* R) {
+  float s, c;
+  sincosf(ang, &s, &c);
+  float t = 1.f - c;
+  R[0] = c + t * a[0] * a[0];        R[1] = t * a[0] * a[1] - s * a[2]; R[2] = t * a[0] * a[2] + s * a[1];
+  R[3] = t * a[0] * a[1] + s * a[2]; R[4] = c + t * a[1] * a[1];        R[5] = t * a[1] * a[2] - s * a[0];
+  R[6] = t * a[0] * a[2] - s * a[1]; R[7] = t * a[1] * a[2] + s * a[0]; R[8] = c + t * a[2] * a[2];
+}
+// spatial motion cross product [w1; v1] x [w2; v2]
+DEV void crossm(const float* m1, const float* m2, float* r) {
+  float a[3], b[3], c[3];
+  cross3(m1, m2, a);
+  cross3(m1, m2 + 3, b);
+  cross3(m1 + 3, m2, c);
+  r[0] = a[0]; r[1] = a[1]; r[2] = a[2];
+  r[3] = b[0] + c[0]; r[4] = b[1] + c[1]; r[5] = b[2] + c[2];
+}
+// spatial force cross product [w; v] x* [n; f]
+DEV void crossf(const float* m, const float* f, float* r) {
+  float a[3], b[3], c[3];
+  cross3(m, f, a);
+  cross3(m + 3, f + 3, b);
+  cross3(m, f + 3, c);
+  r[0] = a[0] + b[0]; r[1] = a[1] + b[1]; r[2] = a[2] + b[2];
+  r[3] = c[0]; r[4] = c[1]; r[5] = c[2];
+}
+// spatial inertia (m, h = m c, I_O) applied to motion [w; v]
+DEV void inertia_mul(const float* I, const float* mv, float* f) {
+  const float* w = mv;
+  const float* v = mv + 3;
+  float hv[3], hw[3];
+  cross3(I + 1, v, hv);
+  cross3(I + 1, w, hw);
+  f[0] = I[4] * w[0] + I[7] * w[1] + I[8] * w[2] + hv[0];
+  f[1] = I[7] * w[0] + I[5] * w[1] + I[9] * w[2] + hv[1];
+  f[2] = I[8] * w[0] + I[9] * w[1] + I[6] * w[2] + hv[2];
+  f[3] = I[0] * v[0] - hw[0];
+  f[4] = I[0] * v[1] - hw[1];
+  f[5] = I[0] * v[2] - hw[2];
+}
+DEV float dot6(const float* a, const float* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3] + a[4] * b[4] + a[5] * b[5];
+}
+// packed lower-triangular index of a symmetric matrix
+DEV int sym(int i, int j) { return i >= j ? (i * (i + 1) >> 1) + j : (j * (j + 1) >> 1) + i; }
+DEV int tri(int i, int j) { return (i * (i + 1) >> 1) + j; }  // requires i >= j
+// triangular pair index p -> (b, a) with 0 <= a <= b, p = b (b + 1) / 2 + a
+DEV void tri_unrank(int p, int& b, int& a) {
+  int r = (int)((sqrtf(8.f * (float)p + 1.f) - 1.f) * 0.5f);
+  while ((r + 1) * (r + 2) / 2 <= p) r++;
+  while (r * (r + 1) / 2 > p) r--;
+  b = r;
+  a = p - r * (r + 1) / 2;
+}
+
+// ------------------------------------------------------------ A0: actuation
+// per dof: motor tau = gear u; position actuator (eq. pd_mapping)
+// tau = kp (q_default + gear u - q) - kd qdot; joint damping -b qdot.  Controls are
+// clamped to their range.  Result: frc = act + passive (bias subtracted later).
+DEV void actuation(const DevModel& m, float* W, const Team& t, const float* ctrl) {
+  const float* qpos = W + m.o_qpos;
+  const float* qvel = W + m.o_qvel;
+  float* frc = W + m.o_frc;
+  for (int i = t.lane; i < m.nv; i += t.T) {
+    float f = -m.dof_damping[i] * qvel[i];
+    int a = m.dof_act[i];
+    if (a >= 0) {
+      const float c = ctrl ? ctrl[a] : 0.f;
+      float u = fminf(fmaxf(c, m.act_lo[a]), m.act_hi[a]);
+      if (m.act_type[a] == ACT_MOTOR) {
+        f += m.act_gear[a] * u;
+      } else {
+        f += m.act_kp[a] * (m.act_qdef[a] + m.act_gear[a] * u - qpos[m.act_qadr[a]]) -
+             m.act_kd[a] * qvel[i];
+      }
+    }
+    frc[i] = f;
+  }
+}
+
+// ----------------------------------- A1/A2/A5 forward sweep by tree level (RBDA 4, 5)
+// For each body: place its frame on the parent, apply its joints in order (hinge:
+// rotation about the world axis through the world anchor; slide: translation; free:
+// absolute pose), record motion subspaces S (world origin) and their rates, the
+// body velocity V, bias acceleration A (qacc = 0, world at -gravity), spatial
+// inertia and the body force f = I A + V x* I V.
+DEV void forward_sweep(const DevModel& m, float* W, const Team& t) {
+  const float* qpos = W + m.o_qpos;
+  const float* qvel = W + m.o_qvel;
+  float* xpos = W + m.o_xpos;
+  float* xmat = W + m.o_xmat;
+  float* cvel = W + m.o_cvel;
+  float* cacc = W + m.o_cacc;
+  float* cfrc = W + m.o_cfrc;
+  float* cinert = W + m.o_cinert;
+  float* cdof = W + m.o_cdof;
+  // the world body: at rest, accelerating at -gravity (this scratch is shared with the
+  // contact phases, so it is set again every step)
+  if (t.lane < 6) {
+    cvel[t.lane] = 0.f;
+    cacc[t.lane] = t.lane < 3 ? 0.f : -m.grav[t.lane - 3];
+  }
+  t.sync();
+  for (int lv = 1; lv < m.nlevel; lv++) {
+    const int e = m.level_start[lv + 1];
+    for (int ib = m.level_start[lv] + t.lane; ib < e; ib += t.T) {
+      const int b = m.level_body[ib];
+      const int p = m.body_parent[b];
+      float pos[3], R[9], V[6], A[6];
+      mv3(xmat + 9 * p, m.body_pos + 3 * b, pos);
+      for (int k = 0; k < 3; k++) pos[k] += xpos[3 * p + k];
+      mm3(xmat + 9 * p, m.body_rot + 9 * b, R);
+      for (int k = 0; k < 6; k++) { V[k] = cvel[6 * p + k]; A[k] = cacc[6 * p + k]; }
+      const int j0 = m.body_jntadr[b], nj = m.body_jntnum[b];
+      for (int j = j0; j < j0 + nj; j++) {
+        const int qa = m.jnt_qposadr[j], da = m.jnt_dofadr[j];
+        float* S = cdof + 6 * da;
+        float Sd[6];
+        const int type = m.jnt_type[j];
+        if (type == JNT_FREE) {
+          float q[4] = {qpos[qa + 3], qpos[qa + 4], qpos[qa + 5], qpos[qa + 6]};
+          float inv = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+          for (int k = 0; k < 4; k++) q[k] *= inv;
+          quat_to_mat(q, R);
+          for (int k = 0; k < 3; k++) pos[k] = qpos[qa + k];
+          for (int i = 0; i < 3; i++) {
+            float* s = S + 6 * i;
+            s[0] = s[1] = s[2] = 0.f;
+            s[3] = (i == 0) ? 1.f : 0.f; s[4] = (i == 1) ? 1.f : 0.f; s[5] = (i == 2) ? 1.f : 0.f;
+            float* r = S + 6 * (3 + i);
+            float col[3] = {R[i], R[3 + i], R[6 + i]};
+            r[0] = col[0]; r[1] = col[1]; r[2] = col[2];
+            cross3(pos, col, r + 3);
+          }
+          for (int i = 0; i < 6; i++)
+            for (int k = 0; k < 6; k++) V[k] += S[6 * i + k] * qvel[da + i];
+          // translation subspaces are fixed in the world (zero rate), rotation ones turn
+          // with the body: rate V_body x S
+          for (int i = 3; i < 6; i++) {
+            crossm(V, S + 6 * i, Sd);
+            for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel[da + i];
+          }
+        } else if (type == JNT_SLIDE) {
+          float ax[3];
+          mv3(R, m.jnt_axis + 3 * j, ax);
+          const float q = qpos[qa];
+          for (int k = 0; k < 3; k++) pos[k] += ax[k] * q;
+          S[0] = S[1] = S[2] = 0.f;
+          S[3] = ax[0]; S[4] = ax[1]; S[5] = ax[2];
+          for (int k = 0; k < 6; k++) V[k] += S[k] * qvel[da];
+          crossm(V, S, Sd);
+          for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel[da];
+        } else {  // hinge
+          float ax[3], off[3], anc[3], Rj[9];
+          mv3(R, m.jnt_axis + 3 * j, ax);
+          mv3(R, m.jnt_pos + 3 * j, off);
+          for (int k = 0; k < 3; k++) anc[k] = pos[k] + off[k];
+          axis_rot(ax, qpos[qa], Rj);
+          mm3(Rj, R, R);
+          mv3(R, m.jnt_pos + 3 * j, off);
+          for (int k = 0; k < 3; k++) pos[k] = anc[k] - off[k];
+          S[0] = ax[0]; S[1] = ax[1]; S[2] = ax[2];
+          cross3(anc, ax, S + 3);
+          for (int k = 0; k < 6; k++) V[k] += S[k] * qvel[da];
+          crossm(V, S, Sd);
+          for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel[da];
+        }
+      }
+      for (int k = 0; k < 3; k++) xpos[3 * b + k] = pos[k];
+      for (int k = 0; k < 9; k++) xmat[9 * b + k] = R[k];
+      for (int k = 0; k < 6; k++) { cvel[6 * b + k] = V[k]; cacc[6 * b + k] = A[k]; }
+      // spatial inertia at the world origin: m, h = m c, I_O = R I R^T + m (|c|^2 1 - c c^T)
+      float c[3], Rt[9], RI[9], Iw[9];
+      mv3(R, m.body_ipos + 3 * b, c);
+      for (int k = 0; k < 3; k++) c[k] += pos[k];
+      const float* bi = m.body_inertia + 6 * b;
+      float Il[9] = {bi[0], bi[3], bi[4], bi[3], bi[1], bi[5], bi[4], bi[5], bi[2]};
+      for (int i = 0; i < 3; i++)
+        for (int k = 0; k < 3; k++) Rt[3 * i + k] = R[3 * k + i];
+      mm3(R, Il, RI);
+      mm3(RI, Rt, Iw);
+      const float mass = m.body_mass[b];
+      const float cc = dot3(c, c);
+      float* ci = cinert + kCinert * b;
+      ci[0] = mass;
+      ci[1] = mass * c[0]; ci[2] = mass * c[1]; ci[3] = mass * c[2];
+      ci[4] = Iw[0] + mass * (cc - c[0] * c[0]);
+      ci[5] = Iw[4] + mass * (cc - c[1] * c[1]);
+      ci[6] = Iw[8] + mass * (cc - c[2] * c[2]);
+      ci[7] = Iw[1] - mass * c[0] * c[1];
+      ci[8] = Iw[2] - mass * c[0] * c[2];
+      ci[9] = Iw[5] - mass * c[1] * c[2];
+      float IA[6], IV[6], VIV[6];
+      inertia_mul(ci, A, IA);
+      inertia_mul(ci, V, IV);
+      crossf(V, IV, VIV);
+      for (int k = 0; k < 6; k++) cfrc[6 * b + k] = IA[k] + VIV[k];
+    }
+    t.sync();
+  }
+}
+
+// ------------------------------- A3/A5 backward sweep, bias forces and CRBA (RBDA 6)
+DEV void backward_and_mass(const DevModel& m, float* W, const Team& t) {
+  float* cfrc = W + m.o_cfrc;
+  float* Ic = W + m.o_cinert;  // body inertias become subtree (composite) inertias
+  const float* cdof = W + m.o_cdof;
+  float* F = W + m.o_F;
+  float* M = W + m.o_M;
+  float* frc = W + m.o_frc;
+  for (int lv = m.nlevel - 1; lv >= 1; lv--) {
+    const int e = m.level_start[lv + 1];
+    for (int ib = m.level_start[lv] + t.lane; ib < e; ib += t.T) {
+      const int b = m.level_body[ib];
+      float ic[kCinert], f[6];
+      for (int k = 0; k < kCinert; k++) ic[k] = Ic[kCinert * b + k];
+      for (int k = 0; k < 6; k++) f[k] = cfrc[6 * b + k];
+      for (int c = m.child_start[b]; c < m.child_start[b + 1]; c++) {
+        const int ch = m.child_list[c];
+        for (int k = 0; k < kCinert; k++) ic[k] += Ic[kCinert * ch + k];
+        for (int k = 0; k < 6; k++) f[k] += cfrc[6 * ch + k];
+      }
+      for (int k = 0; k < kCinert; k++) Ic[kCinert * b + k] = ic[k];
+      for (int k = 0; k < 6; k++) cfrc[6 * b + k] = f[k];
+    }
+    t.sync();
+  }
+  // bias force c_i = S_i . f_subtree; F_i = Ic S_i
+  for (int i = t.lane; i < m.nv; i += t.T) {
+    const int b = m.dof_body[i];
+    frc[i] -= dot6(cdof + 6 * i, cfrc + 6 * b);
+    inertia_mul(Ic + kCinert * b, cdof + 6 * i, F + 6 * i);
+  }
+  t.sync();
+  // M_ij = S_j . F_i for j ancestor-or-self of i (other entries stay zero)
+  for (int k = t.lane; k < m.nmpair; k += t.T) {
+    const int pr = m.mpair[k];
+    const int i = pr >> 16, j = pr & 0xffff;
+    float v = dot6(cdof + 6 * j, F + 6 * i);
+    if (i == j) v += m.dof_armature[i];
+    M[tri(i, j)] = v;
+  }
+  t.sync();
+}
+
+// ------------------------------------------ A4/A6 sparse L^T D L and a0 = M^-1 frc
+// Factor a copy of M in H (no fill-in outside the dof-ancestor pattern).
+DEV void ltdl_factor(const DevModel& m, float* W, const Team& t) {
+  const float* M = W + m.o_M;
+  float* H = W + m.o_H;
+  for (int k = t.lane; k < m.ntri; k += t.T) H[k] = M[k];
+  t.sync();
+  for (int k = m.nv - 1; k >= 0; k--) {
+    const int a0 = m.anc_start[k], na = m.anc_start[k + 1] - a0;
+    const float inv = 1.f / H[tri(k, k)];
+    const int npr = na * (na + 1) / 2;
+    for (int p = t.lane; p < npr; p += t.T) {
+      int bi, ai;
+      tri_unrank(p, bi, ai);
+      const int i = m.anc_list[a0 + ai];  // nearer ancestor (larger index)
+      const int j = m.anc_list[a0 + bi];  // j ancestor-or-self of i
+      H[tri(i, j)] -= H[tri(k, i)] * H[tri(k, j)] * inv;
+    }
+    t.sync();
+    for (int q = t.lane; q < na; q += t.T) {
+      const int i = m.anc_list[a0 + q];
+      H[tri(k, i)] *= inv;
+    }
+    t.sync();
+  }
+}
+// x = M^-1 rhs with the factors in H: L^T y = rhs, y /= D, L x = y (one lane; the
+// other lanes wait at the barrier).  rhs and x may alias.
+DEV void ltdl_solve(const DevModel& m, float* W, const Team& t, const float* rhs, float* x) {
+  const float* H = W + m.o_H;
+  if (t.lane == 0) {
+    for (int i = 0; i < m.nv; i++) x[i] = rhs[i];
+    for (int k = m.nv - 1; k >= 0; k--) {
+      const float yk = x[k];
+      for (int q = m.anc_start[k]; q < m.anc_start[k + 1]; q++) {
+        const int i = m.anc_list[q];
+        x[i] -= H[tri(k, i)] * yk;
+      }
+    }
+    for (int k = 0; k < m.nv; k++) x[k] /= H[tri(k, k)];
+    for (int k = 0; k < m.nv; k++) {
+      float s = x[k];
+      for (int q = m.anc_start[k]; q < m.anc_start[k + 1]; q++) {
+        const int i = m.anc_list[q];
+        s -= H[tri(k, i)] * x[i];
+      }
+      x[k] = s;
+    }
+  }
+  t.sync();
+}
+
+// ------------------------------------------------------------------ A7: collision
+// geom pose from its body's pose
+DEV void geom_pose(const DevModel& m, const float* W, int g, float* pos, float* R) {
+  const int b = m.geom_body[g];
+  const float* xp = W + m.o_xpos + 3 * b;
+  const float* xr = W + m.o_xmat + 9 * b;
+  mv3(xr, m.geom_pos + 3 * g, pos);
+  pos[0] += xp[0]; pos[1] += xp[1]; pos[2] += xp[2];
+  mm3(xr, m.geom_rot + 9 * g, R);
+}
+
+// signed distance of a box-frame point to a box (half extents h) and the outward
+// gradient (box frame)
+DEV float box_sdf(const float* p, const float* h, float* grad) {
+  float q[3], o[3];
+  bool outside = false;
+  for (int k = 0; k < 3; k++) {
+    q[k] = fabsf(p[k]) - h[k];
+    o[k] = fmaxf(q[k], 0.f);
+    outside |= q[k] > 0.f;
+  }
+  if (outside) {
+    float L = sqrtf(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+    for (int k = 0; k < 3; k++) grad[k] = (p[k] < 0.f ? -1.f : 1.f) * o[k] / L;
+    return L;
+  }
+  int ax = 0;
+  if (q[1] > q[ax]) ax = 1;
+  if (q[2] > q[ax]) ax = 2;
+  grad[0] = grad[1] = grad[2] = 0.f;
+  grad[ax] = p[ax] < 0.f ? -1.f : 1.f;
+  return q[ax];
+}
+// box (centre c, rotation R, half extents h) at world point p: sdf and outward
+// world normal
+DEV float box_point(const float* c, const float* R, const float* h, const float* p, float* n) {
+  float rel[3] = {p[0] - c[0], p[1] - c[1], p[2] - c[2]}, pl[3], g[3];
+  mtv3(R, rel, pl);
+  float s = box_sdf(pl, h, g);
+  mv3(R, g, n);
+  return s;
+}
+DEV float box_sdf_only(const float* c, const float* R, const float* h, const float* p) {
+  float n[3];
+  return box_point(c, R, h, p, n);
+}
+
+// capsule segment a + t u (radius r) against a box: the box SDF is convex along the
+// segment; golden-section search for its minimum, then the ends of the eps-sublevel
+// interval of the minimum by bisection.  Candidates (t = 0, t = 1, t_lo, t_hi) after
+// de-duplication; the two deepest penetrating ones are kept (others get +inf).
+constexpr float kCapBoxEps = 1e-7f;
+constexpr float kCapBoxDup = 1e-6f;
+DEV void capsule_box_cands(const float* a, const float* u, float r, const float* c,
+                           const float* R, const float* h, float* dist, float* tpar) {
+  auto f = [&](float t) {
+    float p[3] = {a[0] + t * u[0], a[1] + t * u[1], a[2] + t * u[2]};
+    return box_sdf_only(c, R, h, p);
+  };
+  const float gr = 0.6180339887498949f;
+  float lo = 0.f, hi = 1.f;
+  float x1 = hi - gr * (hi - lo), x2 = lo + gr * (hi - lo);
+  float f1 = f(x1), f2 = f(x2);
+  for (int it = 0; it < 40; it++) {
+    if (f1 < f2) { hi = x2; x2 = x1; f2 = f1; x1 = hi - gr * (hi - lo); f1 = f(x1); }
+    else { lo = x1; x1 = x2; f1 = f2; x2 = lo + gr * (hi - lo); f2 = f(x2); }
+  }
+  const float tm = 0.5f * (lo + hi);
+  const float fa = f(0.f), fb = f(1.f);
+  const float fm = fminf(f(tm), fminf(fa, fb));
+  const float thr = fm + kCapBoxEps;
+  float tlo, thi;
+  if (fa <= thr) tlo = 0.f;
+  else {
+    float l = 0.f, g = tm;
+    for (int it = 0; it < 30; it++) { float md = 0.5f * (l + g); if (f(md) <= thr) g = md; else l = md; }
+    tlo = g;
+  }
+  if (fb <= thr) thi = 1.f;
+  else {
+    float l = tm, g = 1.f;
+    for (int it = 0; it < 30; it++) { float md = 0.5f * (l + g); if (f(md) <= thr) l = md; else g = md; }
+    thi = l;
+  }
+  float ts[4] = {0.f, 1.f, tlo, thi};
+  bool keep[4] = {true, true, true, true};
+  if (fabsf(tlo) < kCapBoxDup || fabsf(tlo - 1.f) < kCapBoxDup) keep[2] = false;
+  if (fabsf(thi) < kCapBoxDup || fabsf(thi - 1.f) < kCapBoxDup || fabsf(thi - tlo) < kCapBoxDup)
+    keep[3] = false;
+  float dep[4];
+  for (int k = 0; k < 4; k++) {
+    dep[k] = f(ts[k]) - r;
+    if (!(dep[k] < 0.f)) keep[k] = false;
+  }
+  int s0 = -1, s1 = -1;
+  for (int k = 0; k < 4; k++)
+    if (keep[k] && (s0 < 0 || dep[k] < dep[s0])) s0 = k;
+  for (int k = 0; k < 4; k++)
+    if (keep[k] && k != s0 && (s1 < 0 || dep[k] < dep[s1])) s1 = k;
+  for (int k = 0; k < 4; k++) {
+    dist[k] = (k == s0 || k == s1) ? dep[k] : INFINITY;
+    tpar[k] = ts[k];
+  }
+}
+
+// closest points of segments p0 + s d1 and q0 + t d2; parallel ones take the middle
+// of the overlap (same rule as the reference)
+DEV void seg_seg(const float* p0, const float* d1, const float* q0, const float* d2, float& s,
+                 float& t) {
+  float r[3] = {p0[0] - q0[0], p0[1] - q0[1], p0[2] - q0[2]};
+  float a = dot3(d1, d1), e = dot3(d2, d2), f = dot3(d2, r), c = dot3(d1, r), b = dot3(d1, d2);
+  float den = a * e - b * b;
+  if (den > 1e-6f * a * e) {
+    s = fminf(fmaxf((b * f - c * e) / den, 0.f), 1.f);
+    t = (b * s + f) / e;
+    if (t < 0.f) { t = 0.f; s = fminf(fmaxf(-c / a, 0.f), 1.f); }
+    else if (t > 1.f) { t = 1.f; s = fminf(fmaxf((b - c) / a, 0.f), 1.f); }
+  } else {
+    float s0 = fminf(fmaxf(-c / a, 0.f), 1.f);
+    float s1 = fminf(fmaxf((b - c) / a, 0.f), 1.f);
+    s = 0.5f * (s0 + s1);
+    t = fminf(fmaxf((b * s + f) / e, 0.f), 1.f);
+  }
+}
+
+// full contact of two spheres (centres c1, c2): dist, midpoint, normal 1 -> 2
+DEV float sphere_sphere(const float* c1, float r1, const float* c2, float r2, float* pos, float* n) {
+  float d[3] = {c2[0] - c1[0], c2[1] - c1[1], c2[2] - c1[2]};
+  float L = sqrtf(dot3(d, d));
+  if (L > 1e-12f) { n[0] = d[0] / L; n[1] = d[1] / L; n[2] = d[2] / L; }
+  else { n[0] = 0.f; n[1] = 0.f; n[2] = 1.f; }
+  float dist = L - r1 - r2;
+  for (int k = 0; k < 3; k++) pos[k] = c1[k] + n[k] * (r1 + 0.5f * dist);
+  return dist;
+}
+
+// Evaluate candidate `sub` of pair `p` (kind-specific); returns dist and fills pos and
+// normal.  For capsule-box the parameter t selects the segment point.
+DEV float pair_contact(const DevModel& m, const float* W, int p, int sub, float tpar, float* pos,
+                       float* n) {
+  const int g1 = m.pair_g1[p], g2 = m.pair_g2[p];
+  float x1[3], R1[9], x2[3], R2[9];
+  geom_pose(m, W, g1, x1, R1);
+  geom_pose(m, W, g2, x2, R2);
+  const float* s1 = m.geom_size + 3 * g1;
+  const float* s2 = m.geom_size + 3 * g2;
+  const float z1[3] = {R1[2], R1[5], R1[8]};
+  const float z2[3] = {R2[2], R2[5], R2[8]};
+  switch (m.pair_kind[p]) {
+    case PK_PLANE_SPHERE:
+    case PK_PLANE_CAPSULE: {
+      float c[3] = {x2[0], x2[1], x2[2]};
+      if (m.pair_kind[p] == PK_PLANE_CAPSULE) {
+        const float sg = sub == 0 ? -s2[1] : s2[1];
+        for (int k = 0; k < 3; k++) c[k] += sg * z2[k];
+      }
+      float rel[3] = {c[0] - x1[0], c[1] - x1[1], c[2] - x1[2]};
+      float dist = dot3(z1, rel) - s2[0];
+      for (int k = 0; k < 3; k++) { n[k] = z1[k]; pos[k] = c[k] - z1[k] * (s2[0] + 0.5f * dist); }
+      return dist;
+    }
+    case PK_PLANE_BOX: {
+      float loc[3] = {(sub & 1) ? s2[0] : -s2[0], (sub & 2) ? s2[1] : -s2[1],
+                      (sub & 4) ? s2[2] : -s2[2]}, w[3], cor[3];
+      mv3(R2, loc, w);
+      for (int k = 0; k < 3; k++) cor[k] = x2[k] + w[k];
+      float rel[3] = {cor[0] - x1[0], cor[1] - x1[1], cor[2] - x1[2]};
+      float dist = dot3(z1, rel);
+      for (int k = 0; k < 3; k++) { n[k] = z1[k]; pos[k] = cor[k] - 0.5f * dist * z1[k]; }
+      return dist;
+    }
+    case PK_SPHERE_SPHERE:
+      return sphere_sphere(x1, s1[0], x2, s2[0], pos, n);
+    case PK_SPHERE_CAPSULE: {
+      float a[3], u[3];
+      for (int k = 0; k < 3; k++) { a[k] = x2[k] - s2[1] * z2[k]; u[k] = 2.f * s2[1] * z2[k]; }
+      float uu = dot3(u, u);
+      float ap[3] = {x1[0] - a[0], x1[1] - a[1], x1[2] - a[2]};
+      float t = uu < 1e-30f ? 0.f : fminf(fmaxf(dot3(ap, u) / uu, 0.f), 1.f);
+      float q[3] = {a[0] + t * u[0], a[1] + t * u[1], a[2] + t * u[2]};
+      return sphere_sphere(x1, s1[0], q, s2[0], pos, n);
+    }
+    case PK_SPHERE_BOX: {
+      float nb[3];
+      float sd = box_point(x2, R2, s2, x1, nb);
+      for (int k = 0; k < 3; k++) { n[k] = -nb[k]; pos[k] = x1[k] - 0.5f * (s1[0] + sd) * nb[k]; }
+      return sd - s1[0];
+    }
+    case PK_CAPSULE_CAPSULE: {
+      float a[3], u[3], b[3], w[3];
+      for (int k = 0; k < 3; k++) {
+        a[k] = x1[k] - s1[1] * z1[k]; u[k] = 2.f * s1[1] * z1[k];
+        b[k] = x2[k] - s2[1] * z2[k]; w[k] = 2.f * s2[1] * z2[k];
+      }
+      float s, t;
+      seg_seg(a, u, b, w, s, t);
+      float pp[3] = {a[0] + s * u[0], a[1] + s * u[1], a[2] + s * u[2]};
+      float qq[3] = {b[0] + t * w[0], b[1] + t * w[1], b[2] + t * w[2]};
+      return sphere_sphere(pp, s1[0], qq, s2[0], pos, n);
+    }
+    case PK_CAPSULE_BOX: {
+      float pt[3], nb[3];
+      for (int k = 0; k < 3; k++) pt[k] = x1[k] + (2.f * tpar - 1.f) * s1[1] * z1[k];
+      float sd = box_point(x2, R2, s2, pt, nb);
+      for (int k = 0; k < 3; k++) { n[k] = -nb[k]; pos[k] = pt[k] - 0.5f * (s1[0] + sd) * nb[k]; }
+      return sd - s1[0];
+    }
+  }
+  return INFINITY;
+}
+
+// Phase 1: every pair writes its candidates' distances (and parameters) into the
+// candidate slots; non-penetrating / not-kept candidates get +inf.
+DEV void collide_candidates(const DevModel& m, float* W, const Team& t) {
+  float* cd = W + m.o_cand;
+  float* cp = cd + m.ncand;
+  for (int p = t.lane; p < m.npair; p += t.T) {
+    const int base = m.pair_candadr[p];
+    const int kind = m.pair_kind[p];
+    if (kind == PK_CAPSULE_BOX) {
+      const int g1 = m.pair_g1[p], g2 = m.pair_g2[p];
+      float x1[3], R1[9], x2[3], R2[9];
+      geom_pose(m, W, g1, x1, R1);
+      geom_pose(m, W, g2, x2, R2);
+      const float* s1 = m.geom_size + 3 * g1;
+      const float* h = m.geom_size + 3 * g2;
+      // bounding spheres reject far pairs without changing any result
+      float dc[3] = {x2[0] - x1[0], x2[1] - x1[1], x2[2] - x1[2]};
+      float rb = sqrtf(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+      if (sqrtf(dot3(dc, dc)) > rb + s1[1] + s1[0]) {
+        for (int k = 0; k < 4; k++) { cd[base + k] = INFINITY; cp[base + k] = 0.f; }
+        continue;
+      }
+      float a[3], u[3];
+      for (int k = 0; k < 3; k++) { a[k] = x1[k] - s1[1] * R1[3 * k + 2]; u[k] = 2.f * s1[1] * R1[3 * k + 2]; }
+      float dist[4], tp[4];
+      capsule_box_cands(a, u, s1[0], x2, R2, h, dist, tp);
+      for (int k = 0; k < 4; k++) { cd[base + k] = dist[k]; cp[base + k] = tp[k]; }
+    } else if (kind == PK_PLANE_BOX) {
+      float dist[8];
+      float pos[3], n[3];
+      for (int k = 0; k < 8; k++) {
+        float d = pair_contact(m, W, p, k, 0.f, pos, n);
+        dist[k] = d < 0.f ? d : INFINITY;
+      }
+      // keep the 4 deepest (ties to the lower corner)
+      unsigned used = 0;
+      for (int s = 0; s < 4; s++) {
+        int best = -1;
+        for (int k = 0; k < 8; k++)
+          if (!(used >> k & 1) && dist[k] < INFINITY && (best < 0 || dist[k] < dist[best])) best = k;
+        if (best < 0) break;
+        used |= 1u << best;
+      }
+      for (int k = 0; k < 8; k++) { cd[base + k] = (used >> k & 1) ? dist[k] : INFINITY; cp[base + k] = 0.f; }
+    } else {
+      const int nc = kind == PK_PLANE_CAPSULE ? 2 : 1;
+      float pos[3], n[3];
+      for (int k = 0; k < nc; k++) {
+        float d = pair_contact(m, W, p, k, 0.f, pos, n);
+        cd[base + k] = d < 0.f ? d : INFINITY;
+        cp[base + k] = 0.f;
+      }
+    }
+  }
+  t.sync();
+}
+
+// contact frame: tangent 1 from the world axis least aligned with the normal (lowest
+// index on ties), tangent 2 = n x t1
+DEV void contact_frame(const float* n, float* fr) {
+  int ax = 0;
+  if (fabsf(n[1]) < fabsf(n[ax])) ax = 1;
+  if (fabsf(n[2]) < fabsf(n[ax])) ax = 2;
+  float en = n[ax];
+  float t1[3] = {-en * n[0], -en * n[1], -en * n[2]};
+  t1[ax] += 1.f;
+  float inv = 1.f / sqrtf(dot3(t1, t1));
+  for (int k = 0; k < 3; k++) t1[k] *= inv;
+  float t2[3];
+  cross3(n, t1, t2);
+  for (int k = 0; k < 3; k++) { fr[k] = n[k]; fr[3 + k] = t1[k]; fr[6 + k] = t2[k]; }
+}
+
+// Phase 2: select the contacts (all penetrating candidates in slot order, or on
+// overflow the nconmax deepest, ties to the lower slot) and build their records.
+DEV void select_contacts(const DevModel& m, float* W, const Team& t, int& status) {
+  const float* cd = W + m.o_cand;
+  const float* cp = cd + m.ncand;
+  float* con = W + m.o_con;
+  int* scal = (int*)(W + m.o_scal);
+  // count penetrating candidates
+  int cnt = 0;
+  for (int c = t.lane; c < m.ncand; c += t.T) cnt += cd[c] < INFINITY;
+  const int total = t.isum(cnt);
+  const bool overflow = total > m.nconmax;
+  if (overflow) status |= 2;
+  int base = 0;
+  for (int c0 = 0; c0 < m.ncand; c0 += t.T) {
+    const int c = c0 + t.lane;
+    bool sel = false;
+    if (c < m.ncand && cd[c] < INFINITY) {
+      sel = true;
+      if (overflow) {
+        int rank = 0;
+        const float dc = cd[c];
+        for (int q = 0; q < m.ncand; q++) {
+          const float dq = cd[q];
+          rank += (dq < dc) || (dq == dc && q < c);
+        }
+        sel = rank < m.nconmax;
+      }
+    }
+    const int slot = base + t.exscan(sel ? 1 : 0);
+    if (sel) {
+      const int p = m.cand_pair[c];
+      const int sub = c - m.pair_candadr[p];
+      float pos[3], n[3];
+      const float dist = pair_contact(m, W, p, sub, cp[c], pos, n);
+      float* r = con + kConRec * slot;
+      r[0] = dist;
+      r[1] = pos[0]; r[2] = pos[1]; r[3] = pos[2];
+      contact_frame(n, r + 4);
+      r[13] = m.pair_mu[p];
+      r[14] = __int_as_float(m.geom_body[m.pair_g1[p]]);
+      r[15] = __int_as_float(m.geom_body[m.pair_g2[p]]);
+      r[16] = __int_as_float(p);
+      r[17] = __int_as_float(sub);
+    }
+    base += t.isum(sel ? 1 : 0);
+  }
+  if (t.lane == 0) scal[SC_NCON] = base;
+  t.sync();
+}
+
+// ------------------------------------------------------------- A8: constraint rows
+// Pyramid rows J_e = J_n +- mu J_tk (order +t1, -t1, +t2, -t2) from the point
+// Jacobians of the two bodies at the contact point; impedance d(r), reference
+// acceleration aref = -B (J_e qvel) - K d(r) r, regulariser R = (1-d)/d (1+mu^2)
+// (w1 + w2), D = 1/R.
+DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
+  const int* scal = (const int*)(W + m.o_scal);
+  const int ncon = scal[SC_NCON];
+  const int nv = m.nv, nrow = 4 * ncon;
+  const float* con = W + m.o_con;
+  const float* cdof = W + m.o_cdof;
+  float* J = W + m.o_J;
+  for (int idx = t.lane; idx < ncon * nv; idx += t.T) {
+    const int c = idx / nv, i = idx - c * nv;
+    const float* r = con + kConRec * c;
+    const int b1 = __float_as_int(r[14]), b2 = __float_as_int(r[15]);
+    const unsigned long long bit = 1ull << i;
+    float jd[3] = {0.f, 0.f, 0.f};
+    const bool in2 = (m.body_dofmask[b2] & bit) != 0;
+    const bool in1 = (m.body_dofmask[b1] & bit) != 0;
+    if (in1 != in2) {
+      const float* S = cdof + 6 * i;
+      float wx[3];
+      cross3(S, r + 1, wx);
+      const float sg = in2 ? 1.f : -1.f;
+      for (int k = 0; k < 3; k++) jd[k] = sg * (S[3 + k] + wx[k]);
+    }
+    const float jn = dot3(r + 4, jd), j1 = dot3(r + 7, jd), j2 = dot3(r + 10, jd);
+    const float mu = r[13];
+    J[(4 * c + 0) * nv + i] = jn + mu * j1;
+    J[(4 * c + 1) * nv + i] = jn - mu * j1;
+    J[(4 * c + 2) * nv + i] = jn + mu * j2;
+    J[(4 * c + 3) * nv + i] = jn - mu * j2;
+  }
+  t.sync();
+  const float* qvel = W + m.o_qvel;
+  float* aref = W + m.o_aref;
+  float* D = W + m.o_D;
+  for (int row = t.lane; row < nrow; row += t.T) {
+    const int c = row >> 2;
+    const float* r = con + kConRec * c;
+    const float dist = r[0];
+    float jv = 0.f;
+    for (int i = 0; i < nv; i++) jv += J[row * nv + i] * qvel[i];
+    const float x = fminf(fabsf(dist) / m.width, 1.f);
+    float y;
+    if (x <= m.mid) y = powf(x, m.power) / powf(m.mid, m.power - 1.f);
+    else y = 1.f - powf(1.f - x, m.power) / powf(1.f - m.mid, m.power - 1.f);
+    const float imp = m.dmin + y * (m.dmax - m.dmin);
+    aref[row] = -m.B * jv - m.K * imp * dist;
+    const int b1 = __float_as_int(r[14]), b2 = __float_as_int(r[15]);
+    const float mu = r[13];
+    const float A = fmaxf((1.f + mu * mu) * (m.body_invweight[b1] + m.body_invweight[b2]), 1e-15f);
+    D[row] = imp / ((1.f - imp) * A);
+  }
+  t.sync();
+}
+
+// --------------------------------------------------- A9: Newton solve (NW ch. 3, 6)
+// F(a) = 1/2 (a - a0)^T M (a - a0) + sum_r 1/2 D_r min(0, J_r a - aref_r)^2.
+// Start from the cheaper of the warm start and a0; each iteration: gradient and
+// Hessian on the active set, dense Cholesky of H, Newton direction, exact line
+// search (phi' evaluated at every breakpoint in parallel), update.
+DEV void newton(const DevModel& m, float* W, const Team& t, int& status) {
+  const int* scal = (const int*)(W + m.o_scal);
+  const int nv = m.nv, nrow = 4 * scal[SC_NCON];
+  const float* M = W + m.o_M;
+  float* H = W + m.o_H;
+  const float* J = W + m.o_J;
+  const float* aref = W + m.o_aref;
+  const float* D = W + m.o_D;
+  float* e = W + m.o_e;     // J a - aref
+  float* s = W + m.o_s;     // J delta
+  const float* a0 = W + m.o_a0;
+  float* a = W + m.o_qacc;  // iterate (warm start on entry)
+  float* Mr = W + m.o_Mr;   // M (a - a0)
+  float* g = W + m.o_g;
+  float* d = W + m.o_d;
+  float* Md = W + m.o_Md;
+  float* tmp = W + m.o_tmp;
+  if (nrow == 0) {
+    for (int i = t.lane; i < nv; i += t.T) a[i] = a0[i];
+    t.sync();
+    return;
+  }
+  // ---- start point: cost of the warm start vs cost of a0
+  for (int i = t.lane; i < nv; i += t.T) tmp[i] = a[i] - a0[i];
+  t.sync();
+  float qw = 0.f;
+  for (int i = t.lane; i < nv; i += t.T) {
+    float v = 0.f;
+    for (int k = 0; k < nv; k++) v += M[sym(i, k)] * tmp[k];
+    Mr[i] = v;
+    qw += 0.5f * tmp[i] * v;
+  }
+  float cw = 0.f, c0 = 0.f;
+  for (int r = t.lane; r < nrow; r += t.T) {
+    float jw = 0.f, j0 = 0.f;
+    for (int i = 0; i < nv; i++) { jw += J[r * nv + i] * a[i]; j0 += J[r * nv + i] * a0[i]; }
+    const float ew = jw - aref[r], e0 = j0 - aref[r];
+    if (ew < 0.f) cw += 0.5f * D[r] * ew * ew;
+    if (e0 < 0.f) c0 += 0.5f * D[r] * e0 * e0;
+    e[r] = ew;
+    s[r] = e0;  // stash
+  }
+  cw = t.sum(cw + qw);
+  c0 = t.sum(c0);
+  t.sync();
+  if (!(cw <= c0)) {
+    for (int i = t.lane; i < nv; i += t.T) { a[i] = a0[i]; Mr[i] = 0.f; }
+    for (int r = t.lane; r < nrow; r += t.T) e[r] = s[r];
+    t.sync();
+  }
+  for (int it = 0; it < m.iterations; it++) {
+    // ---- gradient g = M (a - a0) + sum_active D e J
+    for (int i = t.lane; i < nv; i += t.T) {
+      float v = Mr[i];
+      for (int r = 0; r < nrow; r++) {
+        const float er = e[r];
+        if (er < 0.f) v += D[r] * er * J[r * nv + i];
+      }
+      g[i] = v;
+    }
+    // ---- Hessian H = M + sum_active D J^T J (packed lower)
+    for (int k = t.lane; k < m.ntri; k += t.T) {
+      int i, j;
+      tri_unrank(k, i, j);
+      float v = M[k];
+      for (int r = 0; r < nrow; r++) {
+        if (e[r] < 0.f) v += D[r] * J[r * nv + i] * J[r * nv + j];
+      }
+      H[k] = v;
+    }
+    t.sync();
+    // ---- dense Cholesky H = L L^T (right-looking, packed lower)
+    bool ok = true;
+    for (int j = 0; j < nv; j++) {
+      const float piv = H[tri(j, j)];
+      ok = ok && (piv > 0.f);
+      const float dj = sqrtf(fmaxf(piv, 1e-30f));
+      const float inv = 1.f / dj;
+      for (int i = j + 1 + t.lane; i < nv; i += t.T) H[tri(i, j)] *= inv;
+      t.sync();
+      if (t.lane == 0) H[tri(j, j)] = dj;
+      const int n2 = nv - j - 1;
+      const int npr = n2 * (n2 + 1) / 2;
+      for (int p = t.lane; p < npr; p += t.T) {
+        int bi, ai;
+        tri_unrank(p, bi, ai);
+        const int i = j + 1 + bi, k = j + 1 + ai;
+        H[tri(i, k)] -= H[tri(i, j)] * H[tri(k, j)];
+      }
+      t.sync();
+    }
+    if (!ok) { status |= 4; break; }
+    // ---- delta = -H^-1 g (serial substitutions in one lane)
+    if (t.lane == 0) {
+      for (int i = 0; i < nv; i++) {
+        float v = -g[i];
+        for (int k = 0; k < i; k++) v -= H[tri(i, k)] * d[k];
+        d[i] = v / H[tri(i, i)];
+      }
+      for (int i = nv - 1; i >= 0; i--) {
+        float v = d[i];
+        for (int k = i + 1; k < nv; k++) v -= H[tri(k, i)] * d[k];
+        d[i] = v / H[tri(i, i)];
+      }
+    }
+    t.sync();
+    // ---- line search quantities
+    float gd = 0.f, dMd = 0.f, dMr = 0.f;
+    for (int i = t.lane; i < nv; i += t.T) {
+      float v = 0.f;
+      for (int k = 0; k < nv; k++) v += M[sym(i, k)] * d[k];
+      Md[i] = v;
+      gd += g[i] * d[i];
+      dMd += d[i] * v;
+      dMr += d[i] * Mr[i];
+    }
+    for (int r = t.lane; r < nrow; r += t.T) {
+      float v = 0.f;
+      for (int i = 0; i < nv; i++) v += J[r * nv + i] * d[i];
+      s[r] = v;
+    }
+    gd = t.sum(gd);
+    dMd = t.sum(dMd);
+    dMr = t.sum(dMr);
+    t.sync();
+    if (!(gd < 0.f)) break;  // gradient already zero to working precision
+    // phi'(al) = dMr + al dMd + sum_r D_r s_r min(0, e_r + al s_r), nondecreasing.
+    // Evaluate it at every positive breakpoint; the root lies between the largest
+    // breakpoint with phi' <= 0 and the smallest with phi' > 0, where phi' is linear.
+    float lo = 0.f, hi = INFINITY;
+    for (int r = t.lane; r < nrow; r += t.T) {
+      const float sr = s[r];
+      if (sr == 0.f) continue;
+      const float br = -e[r] / sr;
+      if (!(br > 0.f)) continue;
+      float dp = dMr + br * dMd;
+      for (int q = 0; q < nrow; q++) {
+        const float v = e[q] + br * s[q];
+        if (v < 0.f) dp += D[q] * s[q] * v;
+      }
+      if (dp <= 0.f) lo = fmaxf(lo, br);
+      else hi = fminf(hi, br);
+    }
+    lo = t.max(lo);
+    hi = t.min(hi);
+    const float probe = (hi < INFINITY) ? 0.5f * (lo + hi) : lo + 1.f;
+    float Ac = 0.f, Bc = 0.f;
+    for (int r = t.lane; r < nrow; r += t.T) {
+      if (e[r] + probe * s[r] < 0.f) { Ac += D[r] * s[r] * e[r]; Bc += D[r] * s[r] * s[r]; }
+    }
+    Ac = t.sum(Ac) + dMr;
+    Bc = t.sum(Bc) + dMd;
+    float al = -Ac / Bc;
+    al = fminf(fmaxf(al, lo), hi);
+    // ---- update
+    for (int i = t.lane; i < nv; i += t.T) { a[i] += al * d[i]; Mr[i] += al * Md[i]; }
+    for (int r = t.lane; r < nrow; r += t.T) e[r] += al * s[r];
+    t.sync();
+  }
+}
+
+// ------------------------------------------------- A10: forces, A11: integration
+DEV void export_contacts(const DevModel& m, float* W, const Team& t, float* out, int* nout) {
+  const int* scal = (const int*)(W + m.o_scal);
+  const int ncon = scal[SC_NCON], nv = m.nv;
+  const float* con = W + m.o_con;
+  const float* J = W + m.o_J;
+  const float* aref = W + m.o_aref;
+  const float* D = W + m.o_D;
+  const float* a = W + m.o_qacc;
+  for (int idx = ncon * kConOut + t.lane; idx < m.nconmax * kConOut; idx += t.T) out[idx] = 0.f;
+  for (int c = t.lane; c < ncon; c += t.T) {
+    const float* r = con + kConRec * c;
+    float f[4];
+    for (int e = 0; e < 4; e++) {
+      const int row = 4 * c + e;
+      float ja = 0.f;
+      for (int i = 0; i < nv; i++) ja += J[row * nv + i] * a[i];
+      f[e] = fmaxf(D[row] * (aref[row] - ja), 0.f);
+    }
+    float* o = out + kConOut * c;
+    for (int k = 0; k < 13; k++) o[k] = r[k];
+    o[13] = f[0] + f[1] + f[2] + f[3];
+    o[14] = r[13] * (f[0] - f[1]);
+    o[15] = r[13] * (f[2] - f[3]);
+    o[16] = (float)__float_as_int(r[16]);
+    o[17] = (float)__float_as_int(r[17]);
+  }
+  if (t.lane == 0 && nout) *nout = ncon;
+}
+
+DEV void integrate(const DevModel& m, float* W, const Team& t, int& status) {
+  float* qpos = W + m.o_qpos;
+  float* qvel = W + m.o_qvel;
+  const float* a = W + m.o_qacc;
+  const float h = m.dt;
+  for (int i = t.lane; i < m.nv; i += t.T) qvel[i] += h * a[i];
+  t.sync();
+  bool bad = false;
+  for (int j = t.lane; j < m.njnt; j += t.T) {
+    const int qa = m.jnt_qposadr[j], da = m.jnt_dofadr[j];
+    if (m.jnt_type[j] == JNT_FREE) {
+      for (int k = 0; k < 3; k++) qpos[qa + k] += h * qvel[da + k];
+      float w[3] = {h * qvel[da + 3], h * qvel[da + 4], h * qvel[da + 5]};
+      float ang = sqrtf(dot3(w, w));
+      float dq[4];
+      if (ang > 1e-15f) {
+        float sn, cs;
+        sincosf(0.5f * ang, &sn, &cs);
+        float sc = sn / ang;
+        dq[0] = cs; dq[1] = w[0] * sc; dq[2] = w[1] * sc; dq[3] = w[2] * sc;
+      } else {
+        dq[0] = 1.f; dq[1] = 0.5f * w[0]; dq[2] = 0.5f * w[1]; dq[3] = 0.5f * w[2];
+      }
+      const float q0 = qpos[qa + 3], q1 = qpos[qa + 4], q2 = qpos[qa + 5], q3 = qpos[qa + 6];
+      float r0 = q0 * dq[0] - q1 * dq[1] - q2 * dq[2] - q3 * dq[3];
+      float r1 = q0 * dq[1] + q1 * dq[0] + q2 * dq[3] - q3 * dq[2];
+      float r2 = q0 * dq[2] - q1 * dq[3] + q2 * dq[0] + q3 * dq[1];
+      float r3 = q0 * dq[3] + q1 * dq[2] - q2 * dq[1] + q3 * dq[0];
+      float inv = 1.f / sqrtf(r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3);
+      qpos[qa + 3] = r0 * inv; qpos[qa + 4] = r1 * inv;
+      qpos[qa + 5] = r2 * inv; qpos[qa + 6] = r3 * inv;
+      for (int k = 0; k < 7; k++) bad |= !isfinite(qpos[qa + k]);
+      for (int k = 0; k < 6; k++) bad |= !isfinite(qvel[da + k]);
+    } else {
+      qpos[qa] += h * qvel[da];
+      bad |= !isfinite(qpos[qa]) || !isfinite(qvel[da]);
+    }
+  }
+  if (bad) status |= 1;
+  t.sync();
+}
+
+// ------------------------------------------------------------- one full step
+// Phase timing for profiling builds only (-DMJH_PHASE_TIMING): every lane accumulates
+// cycle counts per phase; release builds compile the marks away.
+#ifdef MJH_PHASE_TIMING
+#define MJH_MARK(k)                                           \
+  do {                                                        \
+    t.sync();                                                 \
+    long long now_ = (long long)__builtin_readcyclecounter(); \
+    if (ph) ph[k] += now_ - *last;                            \
+    *last = now_;                                             \
+  } while (0)
+#else
+#define MJH_MARK(k) \
+  do {              \
+  } while (0)
+#endif
+
+DEV void world_step(const DevModel& m, float* W, const Team& t, const float* ctrl,
+                    int& status, long long* ph = nullptr, long long* last = nullptr) {
+  actuation(m, W, t, ctrl);
+  MJH_MARK(0);
+  forward_sweep(m, W, t);
+  MJH_MARK(1);
+  backward_and_mass(m, W, t);
+  MJH_MARK(2);
+  ltdl_factor(m, W, t);
+  ltdl_solve(m, W, t, W + m.o_frc, W + m.o_a0);
+  MJH_MARK(3);
+  collide_candidates(m, W, t);
+  select_contacts(m, W, t, status);
+  MJH_MARK(4);
+  constraint_rows(m, W, t);
+  MJH_MARK(5);
+  newton(m, W, t, status);
+  MJH_MARK(6);
+}
+
+// initialise the world's constant LDS slots (world body, zero pattern of M)
+DEV void world_init(const DevModel& m, float* W, const Team& t) {
+  for (int k = t.lane; k < m.lds_words; k += t.T) W[k] = 0.f;
+  t.sync();
+  if (t.lane == 0) {
+    float* xmat = W + m.o_xmat;
+    xmat[0] = xmat[4] = xmat[8] = 1.f;
+    float* cacc = W + m.o_cacc;
+    cacc[3] = -m.grav[0]; cacc[4] = -m.grav[1]; cacc[5] = -m.grav[2];
+  }
+  t.sync();
+}
+
+}  // namespace mjh

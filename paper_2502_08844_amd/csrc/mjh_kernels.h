@@ -1,0 +1,19 @@
+// Kernel entry points shared between the kernel and host translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mjh_model.h"
+
+namespace mjh {
+
+constexpr int kMaxBlock = 256;  // threads per work-group of the step kernel
+
+// Launch the step kernel: one work-group of `block` threads per task.
+hipError_t launch_step(const DevGroup* groups, const DevTask* tasks, int ntask, int nstep,
+                       int block, size_t lds_bytes, hipStream_t stream);
+// Allow the step kernel `bytes` of dynamic LDS per work-group.
+hipError_t set_step_lds_limit(size_t bytes);
+// Compute body_invweight of a freshly uploaded model (one work-group).
+hipError_t launch_invweight(const DevModel& m, hipStream_t stream);
+
+}  // namespace mjh

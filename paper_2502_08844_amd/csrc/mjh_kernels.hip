@@ -1,0 +1,161 @@
+// Kernels of the batched physics step.
+//
+// mjh_step_kernel: one work-group per task (a run of worlds of one model); inside it a
+// team of T lanes (16, 32 or 64, chosen per model) owns one world.  The world's state
+// is loaded from HBM into LDS once, advanced `nstep` steps on chip (only the controls
+// are read per step), and written back once.  The same kernel serves a batch of
+// several models: each work-group reads its task and its group's model descriptor.
+// No work-group barrier is used, so teams beyond a task's world count simply exit.
+#include <hip/hip_runtime.h>
+
+#include "mjh_device.h"
+#include "mjh_kernels.h"
+
+namespace mjh {
+
+#ifdef MJH_PHASE_TIMING
+// per-world phase cycle totals of the last launch (profiling builds only)
+constexpr int kPhaseWorlds = 8192;
+__device__ long long g_phase_cycles[kPhaseWorlds * 8];
+#endif
+
+__device__ void run_worlds(const DevGroup& G, float* W, int world, int nstep, int lane, int T) {
+  const DevModel& m = G.m;
+  const Team t{lane, T};
+  world_init(m, W, t);
+  const int nq = m.nq, nv = m.nv, nu = m.nu;
+  const size_t w = (size_t)world;
+  for (int i = lane; i < nq; i += T) W[m.o_qpos + i] = G.qpos[w * nq + i];
+  for (int i = lane; i < nv; i += T) {
+    W[m.o_qvel + i] = G.qvel[w * nv + i];
+    W[m.o_qacc + i] = G.qacc[w * nv + i];
+  }
+  t.sync();
+  int status = 0;
+#ifdef MJH_PHASE_TIMING
+  long long ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  long long last = (long long)__builtin_readcyclecounter();
+#endif
+  for (int s = 0; s < nstep; s++) {
+    const float* u = G.ctrl ? G.ctrl + ((size_t)s * G.nworld + w) * nu : nullptr;
+#ifdef MJH_PHASE_TIMING
+    world_step(m, W, t, u, status, ph, &last);
+#else
+    world_step(m, W, t, u, status);
+#endif
+    if (s == nstep - 1 && G.con_out)
+      export_contacts(m, W, t, G.con_out + w * m.nconmax * kConOut,
+                      G.ncon_out ? G.ncon_out + w : nullptr);
+    integrate(m, W, t, status);
+#ifdef MJH_PHASE_TIMING
+    t.sync();
+    const long long now_ = (long long)__builtin_readcyclecounter();
+    ph[7] += now_ - last;
+    last = now_;
+#endif
+  }
+#ifdef MJH_PHASE_TIMING
+  if (lane == 0 && world < kPhaseWorlds)
+    for (int k = 0; k < 8; k++) g_phase_cycles[world * 8 + k] = ph[k];
+#endif
+  for (int i = lane; i < nq; i += T) G.qpos[w * nq + i] = W[m.o_qpos + i];
+  for (int i = lane; i < nv; i += T) {
+    G.qvel[w * nv + i] = W[m.o_qvel + i];
+    G.qacc[w * nv + i] = W[m.o_qacc + i];
+  }
+  status = t.ior(status);
+  if (lane == 0 && G.status) G.status[w] = status;
+}
+
+__global__ void __launch_bounds__(kMaxBlock, 4)
+mjh_step_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__ tasks,
+                int nstep) {
+  extern __shared__ float lds[];
+  const DevTask tk = tasks[blockIdx.x];
+  const DevGroup& G = groups[tk.group];
+  const int T = G.team;
+  const int team = threadIdx.x / T;
+  if (team >= tk.nw) return;
+  float* W = lds + (size_t)team * G.m.lds_words;
+  const int lane = threadIdx.x - team * T;
+  const int world = tk.w0 + team;
+  run_worlds(G, W, world, nstep, lane, T);
+}
+
+// Translational inverse weight of every body at qpos0:
+//   w(b) = trace(J_com(b) M^-1 J_com(b)^T) / 3,
+// one work-group of 64 lanes evaluating the model once.
+__global__ void __launch_bounds__(64) mjh_invweight_kernel(DevModel m) {
+  extern __shared__ float lds[];
+  float* W = lds;
+  const Team t{(int)threadIdx.x, 64};
+  world_init(m, W, t);
+  for (int i = t.lane; i < m.nq; i += t.T) W[m.o_qpos + i] = m.qpos0[i];
+  t.sync();
+  forward_sweep(m, W, t);
+  backward_and_mass(m, W, t);
+  ltdl_factor(m, W, t);
+  float* jr = W + m.o_tmp;
+  float* x = W + m.o_d;
+  const float* cdof = W + m.o_cdof;
+  for (int b = 0; b < m.nbody; b++) {
+    if (b == 0) {
+      if (t.lane == 0) m.body_invweight[0] = 0.f;
+      continue;
+    }
+    float c[3];
+    mv3(W + m.o_xmat + 9 * b, m.body_ipos + 3 * b, c);
+    for (int k = 0; k < 3; k++) c[k] += W[m.o_xpos + 3 * b + k];
+    float tr = 0.f;
+    for (int r = 0; r < 3; r++) {
+      for (int i = t.lane; i < m.nv; i += t.T) {
+        float v = 0.f;
+        if (m.body_dofmask[b] >> i & 1ull) {
+          float wx[3];
+          cross3(cdof + 6 * i, c, wx);
+          v = cdof[6 * i + 3 + r] + wx[r];
+        }
+        jr[i] = v;
+      }
+      t.sync();
+      ltdl_solve(m, W, t, jr, x);
+      float part = 0.f;
+      for (int i = t.lane; i < m.nv; i += t.T) part += jr[i] * x[i];
+      tr += t.sum(part);
+      t.sync();
+    }
+    if (t.lane == 0) m.body_invweight[b] = tr / 3.f;
+  }
+}
+
+// ------------------------------------------------------------- host-side launchers
+hipError_t launch_step(const DevGroup* groups, const DevTask* tasks, int ntask, int nstep,
+                       int block, size_t lds_bytes, hipStream_t stream) {
+  if (ntask <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mjh_step_kernel, dim3(ntask), dim3(block), lds_bytes, stream, groups,
+                     tasks, nstep);
+  return hipGetLastError();
+}
+
+hipError_t set_step_lds_limit(size_t bytes) {
+  return hipFuncSetAttribute((const void*)mjh_step_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_invweight(const DevModel& m, hipStream_t stream) {
+  const size_t lds = (size_t)m.lds_words * sizeof(float);
+  hipError_t e = hipFuncSetAttribute((const void*)mjh_invweight_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mjh_invweight_kernel, dim3(1), dim3(64), lds, stream, m);
+  return hipGetLastError();
+}
+
+#ifdef MJH_PHASE_TIMING
+hipError_t read_phase_cycles(long long* host, int nworld) {
+  const int n = nworld < kPhaseWorlds ? nworld : kPhaseWorlds;
+  return hipMemcpyFromSymbol(host, HIP_SYMBOL(g_phase_cycles), sizeof(long long) * 8 * (size_t)n);
+}
+#endif
+
+}  // namespace mjh

@@ -1,0 +1,126 @@
+// Device-side model description and per-world on-chip layout.
+//
+// A model is uploaded once as a single device allocation of FP32 and int32 tables;
+// DevModel holds the sizes, the derived constants and pointers into that allocation.
+// Every kernel reads model tables through these pointers (they are identical for all
+// worlds of a model, so they stay resident in L2 / the scalar cache).
+#pragma once
+#include <cstdint>
+
+namespace mjh {
+
+enum JointType : int { JNT_FREE = 0, JNT_SLIDE = 1, JNT_HINGE = 2 };
+enum GeomType : int { GEOM_PLANE = 0, GEOM_SPHERE = 1, GEOM_CAPSULE = 2, GEOM_BOX = 3 };
+enum ActType : int { ACT_MOTOR = 0, ACT_PD = 1 };
+// pair kinds (type(geom1) <= type(geom2)) and their candidate contact slots
+enum PairKind : int {
+  PK_PLANE_SPHERE = 0,   // 1 candidate
+  PK_PLANE_CAPSULE = 1,  // 2: the two segment ends
+  PK_PLANE_BOX = 2,      // 8 corners, at most 4 kept
+  PK_SPHERE_SPHERE = 3,  // 1
+  PK_SPHERE_CAPSULE = 4, // 1
+  PK_SPHERE_BOX = 5,     // 1
+  PK_CAPSULE_CAPSULE = 6,// 1
+  PK_CAPSULE_BOX = 7     // 4: ends + ends of the minimiser interval, at most 2 kept
+};
+
+constexpr int kMaxNv = 64;      // ancestor masks are 64-bit
+constexpr int kConRec = 18;     // on-chip contact record (floats)
+constexpr int kConOut = 20;     // exported contact record (MJH_CON_SIZE)
+constexpr int kCinert = 10;     // spatial inertia: m, m c (3), I at origin (6)
+
+struct DevModel {
+  // ---- sizes
+  int nbody, njnt, nq, nv, nu, ngeom, npair, ncand, nconmax, nrowmax;
+  int iterations, nlevel, nmpair, ntri;
+  // ---- constants
+  float dt, K, B;                       // soft-constraint stiffness/damping
+  float dmin, dmax, width, mid, power;  // impedance (solimp)
+  float grav[3];
+  // ---- int tables
+  const int* body_parent;
+  const int* body_jntadr;
+  const int* body_jntnum;
+  const int* body_dofadr;
+  const int* body_dofnum;
+  const int* level_start;   // [nlevel + 1] into level_body
+  const int* level_body;    // bodies sorted by tree depth (level 0 = world)
+  const int* child_start;   // [nbody + 1] CSR of children
+  const int* child_list;
+  const int* jnt_type;
+  const int* jnt_qposadr;
+  const int* jnt_dofadr;
+  const int* dof_body;
+  const int* dof_act;       // actuator driving the dof, or -1
+  const int* anc_start;     // [nv + 1] strict dof ancestors, nearest first
+  const int* anc_list;
+  const int* mpair;         // [nmpair] (i << 16) | j, j ancestor-or-self of i
+  const unsigned long long* body_dofmask;  // dofs on the path body -> root
+  const int* geom_type;
+  const int* geom_body;
+  const int* pair_g1;
+  const int* pair_g2;
+  const int* pair_kind;
+  const int* pair_candadr;  // first candidate slot of each pair
+  const int* cand_pair;     // [ncand] owning pair
+  const int* act_type;
+  const int* act_qadr;
+  const int* act_dadr;
+  // ---- float tables
+  const float* body_pos;      // [nbody][3] in parent frame
+  const float* body_rot;      // [nbody][9] in parent frame
+  const float* body_mass;
+  const float* body_ipos;     // [nbody][3]
+  const float* body_inertia;  // [nbody][6] xx yy zz xy xz yz (body frame, about COM)
+  const float* jnt_pos;       // [njnt][3]
+  const float* jnt_axis;      // [njnt][3] unit
+  const float* dof_armature;
+  const float* dof_damping;
+  const float* geom_size;     // [ngeom][3]
+  const float* geom_pos;      // [ngeom][3]
+  const float* geom_rot;      // [ngeom][9]
+  const float* pair_mu;
+  const float* act_gear;
+  const float* act_kp;
+  const float* act_kd;
+  const float* act_lo;
+  const float* act_hi;
+  const float* act_qdef;
+  const float* qpos0;
+  float* body_invweight;      // filled on the device at upload
+  // ---- per-world on-chip layout (offsets in 4-byte words)
+  int lds_words;
+  int o_qpos, o_qvel, o_qacc;
+  int o_xpos, o_xmat, o_cvel, o_cacc, o_cfrc, o_cinert, o_cdof, o_F;
+  int o_M, o_H;
+  int o_frc, o_a0, o_Mr, o_g, o_d, o_Md, o_tmp;
+  int o_cand, o_con, o_J, o_aref, o_D, o_e, o_s, o_scal;
+};
+
+// scalar slots inside o_scal
+enum ScalSlot : int {
+  SC_NCON = 0, SC_COUNT = 4
+};
+
+// one group of worlds of the same model inside a batch, as the kernel sees it
+struct DevGroup {
+  DevModel m;
+  float* qpos;
+  float* qvel;
+  float* qacc;
+  int* status;
+  const float* ctrl;
+  float* con_out;
+  int* ncon_out;
+  int nworld;
+  int ctrl_nstep;
+  int team;       // lanes per world
+  int pad_;
+};
+
+// a work item: one work-group advances worlds [w0, w0 + nw) of group g
+struct DevTask {
+  int group, w0, nw, pad_;
+};
+
+}  // namespace mjh

@@ -372,8 +372,8 @@ def hand(mu: float = 1.0, timestep: float = 0.0025, iterations: int = 6) -> Mode
     Finger bases at x in {-0.045, -0.015, 0.015, 0.045}, y = -0.06, z = 0.075; links are
     capsules (r 0.01, density 1000) along +y of lengths 0.02/0.045/0.035/0.03; the first
     hinge abducts about z, the other three flex toward -z.  Armature k_g^2 I_r on every
-    finger joint; PD actuators kp 0.5, kd 0.01.  Cube: edge 0.06, 0.1 kg, resting on the
-    palm.  Collisions: cube x 16 capsules (capsule-box) and palm x cube (plane-box).
+    finger joint; PD actuators kp 0.5, kd 0.01.  Cube: edge 0.06, 0.1 kg, released 1 mm
+    above the palm.  Collisions: cube x 16 capsules (capsule-box) and palm x cube (plane-box).
     nq 23, nv 22, nu 16, nconmax 36.
     """
     bld = _Builder("hand")
@@ -393,7 +393,7 @@ def hand(mu: float = 1.0, timestep: float = 0.0025, iterations: int = 6) -> Mode
                                            mass=rho * capsule_volume(r, 0.5 * L),
                                            friction=mu))
             parent, pos = b, (0, L, 0)
-    cube = bld.body(0, pos=(0, 0, 0.03), name="cube")
+    cube = bld.body(0, pos=(0, 0, 0.031), name="cube")
     bld.joint(cube, JNT_FREE)
     cube_g = bld.geom(cube, GEOM_BOX, (0.03, 0.03, 0.03), mass=0.1, friction=mu)
     m = bld.finish()
@@ -405,7 +405,7 @@ def hand(mu: float = 1.0, timestep: float = 0.0025, iterations: int = 6) -> Mode
     m.opt = Options(timestep=timestep, iterations=iterations, ls_iterations=8,
                     nconmax=36)
     q0 = np.zeros(m.nq)
-    q0[16:19] = (0, 0, 0.03)
+    q0[16:19] = (0, 0, 0.031)  # 1 mm above the palm: no contact exactly at distance 0
     q0[19] = 1.0
     m.qpos0 = q0
     return m

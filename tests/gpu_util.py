@@ -1,0 +1,122 @@
+"""Helpers of the GPU parity tests: run the HIP path and the FP64 reference from the
+same states and measure the differences (error metric: per world,
+||x_gpu - x_ref||_inf / max(||x_ref||_inf, s), with s = 9.81 for accelerations and
+s = total mass * 9.81 for contact forces)."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2502_08844_amd.synth import inputs, robots
+
+G = 9.81
+
+
+def gpu_ctx():
+    from paper_2502_08844_amd import mjh
+    return mjh, mjh.Context(0)
+
+
+def run_gpu(ctx, mjh, m, qpos, qvel, qacc_ws, ctrl, nstep, team=None, block=None,
+            contacts=True):
+    """Advance worlds nstep steps on the GPU from float64 arrays (rounded to float32)."""
+    nw = qpos.shape[0]
+    w = mjh.World(ctx, m, nw, qpos=qpos, qvel=qvel)
+    if qacc_ws is not None:
+        w.qacc_ws.copy_(torch.as_tensor(qacc_ws, dtype=torch.float32))
+    if team is not None:
+        w.batch.set_launch(0, team, block)
+    u = None if ctrl is None else torch.as_tensor(ctrl, dtype=torch.float32, device="cuda")
+    out = w.step(u, nstep=nstep, contacts=contacts)
+    torch.cuda.synchronize()
+    res = dict(qpos=w.qpos.cpu().double().numpy(), qvel=w.qvel.cpu().double().numpy(),
+               qacc=w.qacc_ws.cpu().double().numpy(), status=w.status.cpu().numpy())
+    if contacts:
+        con, ncon = out
+        res["contacts"] = con.cpu().double().numpy()
+        res["ncon"] = ncon.cpu().numpy()
+    return res
+
+
+def compare_step(m, o, state, ctrl1, gpu1, mode=oracle.MODE_FIXED, near=1e-5):
+    """Compare one GPU step (gpu1) with the reference step from the same float32 state.
+
+    Returns per-world qacc and contact-force relative errors and a flag per world for
+    states near a switch (contact emission |dist| < near, a candidate set change, or a
+    constraint row at its activation threshold), which are reported, not gated."""
+    qpos, qvel, ws = state
+    nw = qpos.shape[0]
+    ref = o.step(qpos.copy(), qvel.copy(), ws.copy(), ctrl1, nstep=1, mode=mode, nthreads=8)
+    mass = sum(b.mass for b in m.bodies)
+    err_a = np.zeros(nw)
+    err_f = np.zeros(nw)
+    flag = np.zeros(nw, dtype=bool)
+    for w in range(nw):
+        a_r, a_g = ref["qacc"][w], gpu1["qacc"][w]
+        err_a[w] = np.abs(a_g - a_r).max() / max(np.abs(a_r).max(), G)
+        nc_r, nc_g = ref["ncon"][w], gpu1["ncon"][w] if "ncon" in gpu1 else -1
+        if nc_r == 0 and nc_g <= 0:
+            continue
+        cr = ref["contacts"][w, :nc_r]
+        if nc_g != nc_r:
+            flag[w] = True
+            continue
+        cg = gpu1["contacts"][w, :nc_g]
+        if not np.array_equal(cr[:, 16:18], cg[:, 16:18]):
+            flag[w] = True
+            continue
+        if np.any(np.abs(cr[:, 0]) < near):
+            flag[w] = True
+        # rows at their activation threshold in the reference solution
+        f = o.forward(qpos[w], qvel[w], ws[w], ctrl1[0, w] if ctrl1 is not None else None,
+                      mode=mode)
+        e = f["J"] @ f["qacc"] - f["aref"]
+        if np.any(np.abs(e) < 1e-6 * (1 + np.abs(f["aref"]).max())):
+            flag[w] = True
+        err_f[w] = np.abs(cg[:, 13:16] - cr[:, 13:16]).max() / (mass * G)
+    return dict(err_a=err_a, err_f=err_f, flag=flag, ref=ref)
+
+
+def workload(kind, nw, nstep, seed=0):
+    m = robots.WORKLOADS[kind]()
+    qp, qv = inputs.initial_state(kind, m, nw, seed=seed)
+    u = inputs.controls(kind, m, nw, nstep, seed=seed)
+    return m, qp, qv, u
+
+
+def teacher_forced(ctx, mjh, kind, nw, checkpoints, seed=0, team=None, block=None,
+                   mode=oracle.MODE_FIXED):
+    """Run the GPU along its own trajectory; at each checkpoint step t compare the GPU
+    step t -> t+1 with the reference step from the GPU's float32 state at t."""
+    m, qp, qv, u = workload(kind, nw, max(checkpoints) + 1, seed)
+    o = oracle.Oracle(m)
+    ws = np.zeros((nw, m.nv))
+    t = 0
+    stats = []
+    for c in sorted(checkpoints):
+        if c > t:
+            r = run_gpu(ctx, mjh, m, qp, qv, ws, u[t:c], c - t, team, block, contacts=False)
+            qp, qv, ws = r["qpos"], r["qvel"], r["qacc"]
+            t = c
+        g1 = run_gpu(ctx, mjh, m, qp, qv, ws, u[t:t + 1], 1, team, block)
+        cmp = compare_step(m, o, (qp, qv, ws), u[t:t + 1], g1, mode=mode)
+        cmp["t"] = t
+        cmp["ncon"] = g1["ncon"]
+        cmp["status"] = g1["status"]
+        stats.append(cmp)
+    return m, stats
+
+
+def summarize(kind, stats):
+    ea = np.concatenate([s["err_a"][~s["flag"]] for s in stats])
+    ef = np.concatenate([s["err_f"][~s["flag"]] for s in stats])
+    nflag = int(sum(s["flag"].sum() for s in stats))
+    ntot = int(sum(len(s["flag"]) for s in stats))
+    fa = np.concatenate([s["err_a"][s["flag"]] for s in stats])
+    line = (f"[parity] {kind}: qacc rel err max {ea.max():.2e} p99 "
+            f"{np.percentile(ea, 99):.2e}; contact force rel err max "
+            f"{(ef.max() if ef.size else 0):.2e}; near-switch states {nflag}/{ntot}"
+            + (f" (their qacc err max {fa.max():.2e})" if fa.size else ""))
+    print(line, flush=True)
+    return ea, ef, nflag, ntot

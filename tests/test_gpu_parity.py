@@ -1,0 +1,138 @@
+"""GPU parity: the HIP step against the FP64 reference from identical float32 states.
+
+Tolerances (per world, relative as defined in gpu_util): single-step qacc <= 1e-4 and
+contact forces <= 1e-3, on worlds that are not at a contact/activation switch; the
+switch states are counted and printed.
+"""
+import numpy as np
+import pytest
+import torch
+
+from tests.gpu_util import (G, compare_step, gpu_ctx, run_gpu, summarize, teacher_forced,
+                            workload)
+
+pytestmark = pytest.mark.gpu
+
+QACC_TOL = 1e-4
+FORCE_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def lib():
+    mjh, ctx = gpu_ctx()
+    return mjh, ctx
+
+
+@pytest.mark.parametrize("kind", ["cartpole", "quadruped", "humanoid", "hand"])
+def test_invweight_matches_reference(lib, kind):
+    import oracle
+    from paper_2502_08844_amd.synth import robots
+    mjh, ctx = lib
+    m = robots.WORKLOADS[kind]()
+    gm = ctx.model_upload(m)
+    w_ref = oracle.Oracle(m).body_invweight()
+    w_gpu = gm.invweight()
+    assert np.allclose(w_gpu, w_ref, rtol=2e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("kind,nw,ckpts", [
+    ("cartpole", 64, [0, 10, 100, 500]),
+    ("quadruped", 203, [0, 5, 50, 150]),
+    ("humanoid", 67, [0, 20, 100]),
+    ("hand", 67, [0, 20, 100]),
+])
+def test_single_step_parity(lib, kind, nw, ckpts):
+    mjh, ctx = lib
+    print(f"[gpu] parity {kind} nw={nw} ckpts={ckpts}", flush=True)
+    m, stats = teacher_forced(ctx, mjh, kind, nw, ckpts)
+    ea, ef, nflag, ntot = summarize(kind, stats)
+    assert ea.max() <= QACC_TOL
+    if ef.size:
+        assert ef.max() <= FORCE_TOL
+    assert nflag <= 0.25 * ntot
+
+
+def test_trajectory_and_status_and_determinism(lib):
+    mjh, ctx = lib
+    m, qp, qv, u = workload("quadruped", 130, 40, seed=3)
+    a = run_gpu(ctx, mjh, m, qp, qv, None, u, 40)
+    b = run_gpu(ctx, mjh, m, qp, qv, None, u, 40)
+    for k in ("qpos", "qvel", "qacc", "contacts", "ncon", "status"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.all(a["status"] & 1 == 0)
+    # quaternion stays unit
+    assert np.allclose(np.linalg.norm(a["qpos"][:, 3:7], axis=1), 1.0, atol=1e-6)
+
+
+@pytest.mark.parametrize("team,block", [(16, 64), (32, 128), (64, 256), (64, 64)])
+def test_launch_shapes_agree(lib, team, block):
+    mjh, ctx = lib
+    m, qp, qv, u = workload("quadruped", 77, 10, seed=5)
+    ref = run_gpu(ctx, mjh, m, qp, qv, None, u, 10, team=32, block=128)
+    r = run_gpu(ctx, mjh, m, qp, qv, None, u, 10, team=team, block=block)
+    err = np.abs(r["qpos"] - ref["qpos"]).max()
+    assert err < 1e-4, err
+
+
+def test_edge_cases(lib):
+    mjh, ctx = lib
+    from paper_2502_08844_amd.synth import robots
+    m = robots.quadruped()
+    gm = ctx.model_upload(m)
+    # zero worlds and zero steps are no-ops
+    w0 = mjh.World(ctx, gm, 0)
+    w0.step(None, nstep=3)
+    w1 = mjh.World(ctx, gm, 5, qpos=np.tile(m.qpos0, (5, 1)))
+    before = w1.qpos.clone()
+    w1.step(None, nstep=0)
+    assert torch.equal(before, w1.qpos)
+    # non-finite input only flags its own world
+    qp = np.tile(m.qpos0, (4, 1))
+    qp[2, 8] = np.nan
+    w = mjh.World(ctx, gm, 4, qpos=qp)
+    w.step(None, nstep=2)
+    st = w.status.cpu().numpy()
+    assert st[2] & 1 and not np.any(st[[0, 1, 3]] & 1)
+    assert np.isfinite(w.qpos.cpu().numpy()[[0, 1, 3]]).all()
+    # bad arguments are errors, not crashes
+    with pytest.raises(mjh.MjhError):
+        w.batch.set_launch(0, 48, 96)
+    with pytest.raises(mjh.MjhError):
+        ctx.model_upload(b"not a model")
+    u = torch.zeros(2, 4, m.nu, device="cuda")
+    w.batch.bind_io(0, u)
+    with pytest.raises(mjh.MjhError):
+        w.batch.step(5)
+
+
+def test_contact_overflow_status(lib):
+    """More penetrating candidates than the budget: the deepest 16 are kept, in list
+    order, and the overflow bit is set.  Poses are chosen so that the 16th and 17th
+    deepest candidates differ clearly (no tie for the two precisions to break)."""
+    mjh, ctx = lib
+    import math
+    import oracle
+    from paper_2502_08844_amd.synth import robots
+    small = robots.humanoid(nconmax=16)
+    big = robots.humanoid(nconmax=400)
+    ob, os_ = oracle.Oracle(big), oracle.Oracle(small)
+    rng = np.random.default_rng(0)
+    poses = []
+    while len(poses) < 3:
+        q = small.qpos0.copy()
+        q[2] = 0.03 + rng.uniform(-0.01, 0.01)
+        rot = robots.axis_angle_quat(rng.normal(size=3), rng.uniform(0.0, 0.15))
+        base = robots.axis_angle_quat((0, 1, 0), math.pi / 2)
+        from tests.test_oracle_dynamics import quat_mul
+        q[3:7] = quat_mul(np.array(rot), np.array(base))
+        q[7:] = rng.uniform(-0.2, 0.2, size=small.nq - 7)
+        q = q.astype(np.float32).astype(np.float64)
+        d = np.sort(ob.forward(q)["contacts"][:, 0])
+        if len(d) > 17 and d[16] - d[15] > 1e-4:
+            poses.append(q)
+    qp = np.array(poses)
+    r = run_gpu(ctx, mjh, small, qp, np.zeros((3, small.nv)), None, None, 1)
+    ref = os_.step(qp, np.zeros((3, small.nv)), nstep=1)
+    assert np.all(r["status"] & 2) and np.all(ref["status"] & 2)
+    assert np.all(r["ncon"] == 16)
+    assert np.array_equal(r["contacts"][:, :, 16:18], ref["contacts"][:, :16, 16:18])
