@@ -13,7 +13,7 @@ struct AdjointState;
 
 // Run `horizon` steps of `nworld` worlds from the bound state, storing checkpoints
 // every ckpt_every steps, accumulate the loss per world.
-mjh_status adjoint_forward(AdjointState** st, const DevModel& m, int nworld, float* qpos,
+mjh_status adjoint_forward(AdjointState** st, const DevModel& m, int team, int nworld, float* qpos,
                            float* qvel, float* qacc, int horizon, int ckpt_every,
                            const float* ctrl, int zidx, float ztarget, float wctrl,
                            float* loss, hipStream_t stream, std::string& err);

@@ -1,25 +1,879 @@
-// Differentiable rollout (checkpointed forward, reverse sweep).
+// Differentiable rollout: checkpointed forward and hand-written reverse sweep.
+//
+// Forward (rollout_fwd_kernel): every world runs `horizon` steps with the Newton
+// solve iterated to convergence, stores (qpos, qvel, qacc_ws) every `ckpt` steps and
+// accumulates the loss  sum_t (qpos_{t+1}[zidx] - ztarget)^2 + wctrl |u_t|^2.
+// Reverse (rollout_bwd_kernel): segments in reverse order; each is recomputed from its
+// checkpoint into a per-world tape (Griewank & Walther, checkpointed reverse mode),
+// then every step is solved again and its vector-Jacobian product taken:
+//   * semi-implicit Euler and the exponential-map orientation update, reversed;
+//   * the contact solve by implicit differentiation at the Newton solution a*:
+//     grad_a F(a*; theta) = 0 gives theta_bar = -(dG/dtheta)^T H^-1 a_bar with
+//     G = ID(q, qdot, a*) - tau(q, qdot, u) - sum_active J^T D (aref - J a*), H the
+//     Newton Hessian at a*;
+//   * reverse sweeps of the recursive Newton-Euler inverse dynamics, of the contact
+//     rows (Jacobians, impedance, reference acceleration, contact geometry) and of
+//     the forward kinematics.
+// Contact geometry is differentiated for plane-sphere and plane-capsule pairs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
 #include "mjh_adjoint.h"
+#include "mjh_device.h"
 
 namespace mjh {
 
-struct AdjointState {
-  int dummy = 0;
+constexpr int kAdjIters = 16;  // Newton iterations cap inside differentiable rollouts
+constexpr int kAdjBlock = 64;  // threads per work-group of the rollout kernels
+
+// ------------------------------------------------------------------ small helpers
+DEV void skew_mul(const float* w, const float* R, float* out) {  // [w]x R
+  for (int j = 0; j < 3; j++) {
+    const float r0 = R[j], r1 = R[3 + j], r2 = R[6 + j];
+    out[j] = w[1] * r2 - w[2] * r1;
+    out[3 + j] = w[2] * r0 - w[0] * r2;
+    out[6 + j] = w[0] * r1 - w[1] * r0;
+  }
+}
+DEV void quat_mul4(const float* a, const float* b, float* r) {
+  const float w = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+  const float x = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+  const float y = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+  const float z = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+  r[0] = w; r[1] = x; r[2] = y; r[3] = z;
+}
+// pair (g, mv) of a spatial-inertia product f = I mv: accumulate the cotangent of the
+// inertia parameters (m, h, I_O (xx yy zz xy xz yz)) given the cotangent g of f
+DEV void inertia_cot(float* ib, const float* g, const float* mv) {
+  const float* w = mv;
+  const float* v = mv + 3;
+  ib[0] += g[3] * v[0] + g[4] * v[1] + g[5] * v[2];
+  float a[3], b[3];
+  cross3(v, g, a);
+  cross3(w, g + 3, b);
+  ib[1] += a[0] - b[0]; ib[2] += a[1] - b[1]; ib[3] += a[2] - b[2];
+  // symmetric part of g_n w^T, stored as full-matrix entries xx yy zz xy xz yz
+  ib[4] += g[0] * w[0]; ib[5] += g[1] * w[1]; ib[6] += g[2] * w[2];
+  ib[7] += 0.5f * (g[0] * w[1] + w[0] * g[1]);
+  ib[8] += 0.5f * (g[0] * w[2] + w[0] * g[2]);
+  ib[9] += 0.5f * (g[1] * w[2] + w[1] * g[2]);
+}
+// impedance d(r) and its derivative
+DEV void impedance_d(const DevModel& m, float r, float& d, float& dd) {
+  const float x = fminf(fabsf(r) / m.width, 1.f);
+  float y, yp;
+  if (x <= m.mid) {
+    y = powf(x, m.power) / powf(m.mid, m.power - 1.f);
+    yp = m.power * powf(x, m.power - 1.f) / powf(m.mid, m.power - 1.f);
+  } else {
+    y = 1.f - powf(1.f - x, m.power) / powf(1.f - m.mid, m.power - 1.f);
+    yp = m.power * powf(1.f - x, m.power - 1.f) / powf(1.f - m.mid, m.power - 1.f);
+  }
+  d = m.dmin + y * (m.dmax - m.dmin);
+  dd = (x >= 1.f) ? 0.f : (m.dmax - m.dmin) * yp * (r < 0.f ? -1.f : 1.f) / m.width;
+}
+
+// subtree force totals (cfrc in place), leaving the body inertias untouched
+DEV void accumulate_forces(const DevModel& m, float* W, const Team& t) {
+  float* cfrc = W + m.o_cfrc;
+  for (int lv = m.nlevel - 1; lv >= 1; lv--) {
+    const int e = m.level_start[lv + 1];
+    for (int ib = m.level_start[lv] + t.lane; ib < e; ib += t.T) {
+      const int b = m.level_body[ib];
+      for (int c = m.child_start[b]; c < m.child_start[b + 1]; c++) {
+        const int ch = m.child_list[c];
+        for (int k = 0; k < 6; k++) cfrc[6 * b + k] += cfrc[6 * ch + k];
+      }
+    }
+    t.sync();
+  }
+}
+
+// pose of body b's frame before its joints (from the parent's final pose)
+DEV void body_base(const DevModel& m, const float* W, int b, float* pos, float* R) {
+  const int p = m.body_parent[b];
+  const float* xp = W + m.o_xpos + 3 * p;
+  const float* Rp = W + m.o_xmat + 9 * p;
+  mv3(Rp, m.body_pos + 3 * b, pos);
+  pos[0] += xp[0]; pos[1] += xp[1]; pos[2] += xp[2];
+  mm3(Rp, m.body_rot + 9 * b, R);
+}
+
+// ------------------------------------------------------------------ adjoint step
+// Inputs in LDS: qpos/qvel (state before the step), qacc (= a*), qbi/vbi (cotangents of
+// the state after the step).  Outputs: qb (nq), vb (nv), ub (nu).  Returns false for an
+// unsupported contact pair.
+DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u, int& status) {
+  const int nv = m.nv, nb = m.nbody;
+  const float h = m.dt;
+  const int ncon = ((const int*)(W + m.o_scal))[SC_NCON];
+  const int nrow = 4 * ncon;
+  const float* qpos = W + m.o_qpos;
+  const float* qvel = W + m.o_qvel;
+  const float* a = W + m.o_qacc;
+  const float* qbi = W + m.o_qbi;
+  const float* vbi = W + m.o_vbi;
+  float* qb = W + m.o_qb;
+  float* vb = W + m.o_vb;
+  float* ub = W + m.o_ub;
+  float* mu = W + m.o_mu;
+  float* abar = W + m.o_g;  // scratch of the forward solve, free now
+  const float* cdof = W + m.o_cdof;
+  float* Sbar = W + m.o_Sbar;
+  float* xbar = W + m.o_xbar;
+  float* Rbar = W + m.o_Rbar;
+  float* cinbar = W + m.o_cinbar;
+  float* Vbar = W + m.o_Vbar;
+  float* Abar = W + m.o_Abar;
+  float* Fbar = W + m.o_Fbar;
+  float* vup = W + m.o_vup;
+  float* aup = W + m.o_aup;
+  float* xup = W + m.o_xup;
+  float* Rup = W + m.o_Rup;
+
+  // ---- clear body accumulators
+  for (int k = t.lane; k < 3 * nb; k += t.T) xbar[k] = 0.f;
+  for (int k = t.lane; k < 9 * nb; k += t.T) Rbar[k] = 0.f;
+  for (int k = t.lane; k < kCinert * nb; k += t.T) cinbar[k] = 0.f;
+  for (int k = t.lane; k < m.nu; k += t.T) ub[k] = 0.f;
+  // ---- semi-implicit Euler, reversed (lane per joint)
+  for (int j = t.lane; j < m.njnt; j += t.T) {
+    const int qa = m.jnt_qposadr[j], da = m.jnt_dofadr[j];
+    if (m.jnt_type[j] == JNT_FREE) {
+      for (int k = 0; k < 3; k++) {
+        qb[qa + k] = qbi[qa + k];
+        vb[da + k] = vbi[da + k] + h * qbi[qa + k];
+      }
+      // q' = normalize(q (x) exp(h w')), w' = qvel'[3:6]
+      float wv[3];
+      for (int k = 0; k < 3; k++) wv[k] = h * (qvel[da + 3 + k] + h * a[da + 3 + k]);
+      const float th = sqrtf(dot3(wv, wv));
+      float sn, cs;
+      sincosf(0.5f * th, &sn, &cs);
+      // f(th) = sin(th/2)/th and f'(th)/th; series below 0.1 (the closed form cancels)
+      float fth, fpt;
+      if (th > 0.1f) {
+        fth = sn / th;
+        fpt = (0.5f * th * cs - sn) / (th * th * th);
+      } else {
+        const float t2 = th * th;
+        fth = 0.5f - t2 / 48.f + t2 * t2 / 3840.f;
+        fpt = -1.f / 24.f + t2 / 960.f;
+      }
+      const float ds0 = -0.5f * fth;
+      const float dq[4] = {cs, fth * wv[0], fth * wv[1], fth * wv[2]};
+      const float quat[4] = {qpos[qa + 3], qpos[qa + 4], qpos[qa + 5], qpos[qa + 6]};
+      float r[4];
+      quat_mul4(quat, dq, r);
+      const float rn = sqrtf(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+      const float qo[4] = {r[0] / rn, r[1] / rn, r[2] / rn, r[3] / rn};
+      const float* gq = qbi + qa + 3;
+      const float dotq = qo[0] * gq[0] + qo[1] * gq[1] + qo[2] * gq[2] + qo[3] * gq[3];
+      float rbar[4];
+      for (int k = 0; k < 4; k++) rbar[k] = (gq[k] - qo[k] * dotq) / rn;
+      const float dqc[4] = {dq[0], -dq[1], -dq[2], -dq[3]};
+      const float qc[4] = {quat[0], -quat[1], -quat[2], -quat[3]};
+      float qq[4], dqbar[4];
+      quat_mul4(rbar, dqc, qq);
+      quat_mul4(qc, rbar, dqbar);
+      for (int k = 0; k < 4; k++) qb[qa + 3 + k] = qq[k];
+      const float wd = wv[0] * dqbar[1] + wv[1] * dqbar[2] + wv[2] * dqbar[3];
+      for (int k = 0; k < 3; k++) {
+        const float wbar = dqbar[0] * ds0 * wv[k] + fth * dqbar[1 + k] + fpt * wd * wv[k];
+        vb[da + 3 + k] = vbi[da + 3 + k] + h * wbar;
+      }
+    } else {
+      qb[qa] = qbi[qa];
+      vb[da] = vbi[da] + h * qbi[qa];
+    }
+  }
+  t.sync();
+  for (int i = t.lane; i < nv; i += t.T) abar[i] = h * vb[i];
+  // ---- implicit differentiation: lambda = H(a*)^-1 a_bar, mu = -lambda
+  {
+    const float* J = W + m.o_J;
+    const float* aref = W + m.o_aref;
+    float* e = W + m.o_e;
+    for (int r = t.lane; r < nrow; r += t.T) {
+      float v = 0.f;
+      for (int i = 0; i < nv; i++) v += J[r * nv + i] * a[i];
+      e[r] = v - aref[r];
+    }
+    t.sync();
+    if (!hessian_cholesky(m, W, t, nrow)) status |= 4;
+    cholesky_solve(m, W, t, abar, mu, -1.f);
+  }
+  // ---- actuation and passive forces, reversed (lane per dof)
+  for (int i = t.lane; i < nv; i += t.T) {
+    const float mi = mu[i];
+    vb[i] += m.dof_damping[i] * mi;
+    const int ac = m.dof_act[i];
+    if (ac >= 0) {
+      const float c = u ? u[ac] : 0.f;
+      const bool inr = c >= m.act_lo[ac] && c <= m.act_hi[ac];
+      if (m.act_type[ac] == ACT_MOTOR) {
+        ub[ac] = inr ? -m.act_gear[ac] * mi : 0.f;
+      } else {
+        ub[ac] = inr ? -m.act_kp[ac] * m.act_gear[ac] * mi : 0.f;
+        vb[i] += m.act_kd[ac] * mi;
+      }
+    }
+  }
+  t.sync();
+  for (int i = t.lane; i < nv; i += t.T) {  // PD stiffness acts on qpos (separate pass:
+    const int ac = m.dof_act[i];             // qb of a hinge is one word per lane)
+    if (ac >= 0 && m.act_type[ac] == ACT_PD) qb[m.act_qadr[ac]] += m.act_kp[ac] * mu[i];
+  }
+  // ---- inverse dynamics with a*: V, A, body inertias, subtree forces
+  forward_sweep(m, W, t, a);
+  accumulate_forces(m, W, t);
+  const float* cvel = W + m.o_cvel;
+  const float* cacc = W + m.o_cacc;
+  const float* cfrc = W + m.o_cfrc;  // subtree totals
+  const float* cin = W + m.o_cinert;
+  // S_bar = mu_k F_body(k); F_bar(b) = sum_k in b mu_k S_k
+  for (int k = t.lane; k < nv; k += t.T) {
+    const int b = m.dof_body[k];
+    for (int c = 0; c < 6; c++) Sbar[6 * k + c] = mu[k] * cfrc[6 * b + c];
+  }
+  for (int b = t.lane; b < nb; b += t.T) {
+    float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = m.body_dofadr[b]; k < m.body_dofadr[b] + m.body_dofnum[b]; k++)
+      for (int c = 0; c < 6; c++) f[c] += mu[k] * cdof[6 * k + c];
+    for (int c = 0; c < 6; c++) Fbar[6 * b + c] = f[c];
+  }
+  t.sync();
+  for (int lv = 1; lv < m.nlevel; lv++) {  // subtree totals: every ancestor's bar adds
+    const int e = m.level_start[lv + 1];
+    for (int ib = m.level_start[lv] + t.lane; ib < e; ib += t.T) {
+      const int b = m.level_body[ib], p = m.body_parent[b];
+      if (p > 0)
+        for (int c = 0; c < 6; c++) Fbar[6 * b + c] += Fbar[6 * p + c];
+    }
+    t.sync();
+  }
+  // f = I A + V x* (I V), reversed (lane per body)
+  for (int b = 1 + t.lane; b < nb; b += t.T) {
+    const float* I = cin + kCinert * b;
+    const float* V = cvel + 6 * b;
+    const float* A = cacc + 6 * b;
+    const float* fb = Fbar + 6 * b;
+    float IV[6], t1[6], t2[6], t3[6];
+    inertia_mul(I, fb, Abar + 6 * b);
+    inertia_mul(I, V, IV);
+    crossf(fb, IV, t1);
+    crossm(V, fb, t2);
+    inertia_mul(I, t2, t3);
+    for (int c = 0; c < 6; c++) Vbar[6 * b + c] = -t1[c] - t3[c];
+    float* ib = cinbar + kCinert * b;
+    inertia_cot(ib, fb, A);
+    for (int c = 0; c < 6; c++) t2[c] = -t2[c];
+    inertia_cot(ib, t2, V);
+  }
+  t.sync();
+  // V, A recursions reversed, leaves to root (lane per body; children pass up)
+  for (int lv = m.nlevel - 1; lv >= 1; lv--) {
+    const int e = m.level_start[lv + 1];
+    for (int ib = m.level_start[lv] + t.lane; ib < e; ib += t.T) {
+      const int b = m.level_body[ib], p = m.body_parent[b];
+      float Vb_[6], Ab_[6];
+      for (int c = 0; c < 6; c++) { Vb_[c] = Vbar[6 * b + c]; Ab_[c] = Abar[6 * b + c]; }
+      for (int cc = m.child_start[b]; cc < m.child_start[b + 1]; cc++) {
+        const int ch = m.child_list[cc];
+        for (int c = 0; c < 6; c++) { Vb_[c] += vup[6 * ch + c]; Ab_[c] += aup[6 * ch + c]; }
+      }
+      // forward velocities inside the body (V after each joint)
+      const int j0 = m.body_jntadr[b], nj = m.body_jntnum[b];
+      float Vs[4][6];  // V after joint jj (bodies carry at most 4 scalar joints here)
+      float V[6];
+      for (int c = 0; c < 6; c++) V[c] = cvel[6 * p + c];
+      const bool free = nj == 1 && m.jnt_type[j0] == JNT_FREE;
+      if (!free) {
+        for (int jj = 0; jj < nj && jj < 4; jj++) {
+          const int da = m.jnt_dofadr[j0 + jj];
+          for (int c = 0; c < 6; c++) { V[c] += cdof[6 * da + c] * qvel[da]; Vs[jj][c] = V[c]; }
+        }
+        for (int jj = nj - 1; jj >= 0; jj--) {
+          const int da = m.jnt_dofadr[j0 + jj];
+          const float* S = cdof + 6 * da;
+          // A += Sd v + S a, Sd = V_k x S
+          float Sdbar[6], Sd[6], tmp[6];
+          crossm(Vs[jj < 4 ? jj : 3], S, Sd);
+          for (int c = 0; c < 6; c++) {
+            Sdbar[c] = qvel[da] * Ab_[c];
+            Sbar[6 * da + c] += a[da] * Ab_[c];
+          }
+          vb[da] += dot6(Sd, Ab_);
+          crossf(S, Sdbar, tmp);
+          for (int c = 0; c < 6; c++) Vb_[c] += tmp[c];
+          crossf(Vs[jj < 4 ? jj : 3], Sdbar, tmp);
+          for (int c = 0; c < 6; c++) Sbar[6 * da + c] += -tmp[c] + qvel[da] * Vb_[c];
+          vb[da] += dot6(S, Vb_);
+        }
+      } else {
+        const int da = m.jnt_dofadr[j0];
+        for (int i = 0; i < 6; i++)
+          for (int c = 0; c < 6; c++) V[c] += cdof[6 * (da + i) + c] * qvel[da + i];
+        for (int i = 0; i < 6; i++) {
+          const float* S = cdof + 6 * (da + i);
+          for (int c = 0; c < 6; c++) Sbar[6 * (da + i) + c] += a[da + i] * Ab_[c];
+          if (i >= 3) {
+            float Sd[6], Sdbar[6], tmp[6];
+            crossm(V, S, Sd);
+            for (int c = 0; c < 6; c++) Sdbar[c] = qvel[da + i] * Ab_[c];
+            vb[da + i] += dot6(Sd, Ab_);
+            crossf(S, Sdbar, tmp);
+            for (int c = 0; c < 6; c++) Vb_[c] += tmp[c];
+            crossf(V, Sdbar, tmp);
+            for (int c = 0; c < 6; c++) Sbar[6 * (da + i) + c] -= tmp[c];
+          }
+        }
+        for (int i = 0; i < 6; i++) {
+          const float* S = cdof + 6 * (da + i);
+          for (int c = 0; c < 6; c++) Sbar[6 * (da + i) + c] += qvel[da + i] * Vb_[c];
+          vb[da + i] += dot6(S, Vb_);
+        }
+      }
+      for (int c = 0; c < 6; c++) { vup[6 * b + c] = Vb_[c]; aup[6 * b + c] = Ab_[c]; }
+    }
+    t.sync();
+  }
+  // ---- contact rows, reversed
+  if (nrow > 0) {
+    const float* J = W + m.o_J;
+    const float* D = W + m.o_D;
+    const float* e = W + m.o_e;
+    const float* con = W + m.o_con;
+    float* rs = W + m.o_rowsc;   // per row: s, x, y, alpha, beta, gamma, rho
+    float* cs = W + m.o_consc;   // per contact: csbar[3], gp[3], body, ok
+    for (int r = t.lane; r < nrow; r += t.T) {
+      float sv = 0.f, xv = 0.f, yv = 0.f;
+      for (int i = 0; i < nv; i++) {
+        const float jr = J[r * nv + i];
+        sv += jr * mu[i]; xv += jr * qvel[i]; yv += jr * a[i];
+      }
+      float al = 0.f, be = 0.f, ga = 0.f, rho = 0.f;
+      if (e[r] < 0.f) {
+        const float* rec = con + kConRec * (r >> 2);
+        const float dist = rec[0];
+        float d, dd;
+        impedance_d(m, dist, d, dd);
+        const float Dv = D[r];
+        const float Ahat = d / ((1.f - d) * Dv);
+        const float Dp = dd / ((1.f - d) * (1.f - d) * Ahat);
+        const float core = m.B * xv + m.K * d * dist + yv;
+        al = Dv * core;
+        be = m.B * Dv * sv;
+        ga = Dv * sv;
+        rho = sv * (Dp * core + Dv * m.K * (dd * dist + d));
+      }
+      float* o = rs + 7 * r;
+      o[0] = sv; o[1] = xv; o[2] = yv; o[3] = al; o[4] = be; o[5] = ga; o[6] = rho;
+    }
+    t.sync();
+    // dofs: qvel cotangent through aref, and the Jacobian's subspace cotangents
+    for (int k = t.lane; k < nv; k += t.T) {
+      const unsigned long long bit = 1ull << k;
+      float vadd = 0.f;
+      float sb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      for (int r = 0; r < nrow; r++) {
+        const float* o = rs + 7 * r;
+        if (!(e[r] < 0.f)) continue;
+        vadd += o[4] * J[r * nv + k];
+        const float* rec = con + kConRec * (r >> 2);
+        const int b1 = __float_as_int(rec[14]), b2 = __float_as_int(rec[15]);
+        const bool in2 = (m.body_dofmask[b2] & bit) != 0, in1 = (m.body_dofmask[b1] & bit) != 0;
+        if (in1 == in2) continue;
+        const float sg = in2 ? 1.f : -1.f;
+        const int ed = r & 3;
+        const float sgm = (ed & 1) ? -rec[13] : rec[13];
+        const float* tk = rec + 4 + 3 * (1 + (ed >> 1));
+        const float ev[3] = {rec[4] + sgm * tk[0], rec[5] + sgm * tk[1], rec[6] + sgm * tk[2]};
+        const float w = sg * (o[3] * mu[k] + o[4] * qvel[k] + o[5] * a[k]);
+        float pe[3];
+        cross3(rec + 1, ev, pe);
+        for (int c = 0; c < 3; c++) { sb[c] += w * pe[c]; sb[3 + c] += w * ev[c]; }
+      }
+      vb[k] += vadd;
+      for (int c = 0; c < 6; c++) Sbar[6 * k + c] += sb[c];
+    }
+    // contacts: point and distance cotangents -> sphere-centre cotangent
+    for (int c = t.lane; c < ncon; c += t.T) {
+      const float* rec = con + kConRec * c;
+      const int b1 = __float_as_int(rec[14]), b2 = __float_as_int(rec[15]);
+      const int p = __float_as_int(rec[16]), sub = __float_as_int(rec[17]);
+      float xb[3] = {0.f, 0.f, 0.f}, rb = 0.f;
+      for (int ed = 0; ed < 4; ed++) {
+        const int r = 4 * c + ed;
+        if (!(e[r] < 0.f)) continue;
+        const float* o = rs + 7 * r;
+        rb += o[6];
+        const float sgm = (ed & 1) ? -rec[13] : rec[13];
+        const float* tk = rec + 4 + 3 * (1 + (ed >> 1));
+        const float ev[3] = {rec[4] + sgm * tk[0], rec[5] + sgm * tk[1], rec[6] + sgm * tk[2]};
+        float om[3] = {0.f, 0.f, 0.f};
+        for (int k = 0; k < nv; k++) {
+          const unsigned long long bit = 1ull << k;
+          const bool in2 = (m.body_dofmask[b2] & bit) != 0, in1 = (m.body_dofmask[b1] & bit) != 0;
+          if (in1 == in2) continue;
+          const float w = (in2 ? 1.f : -1.f) * (o[3] * mu[k] + o[4] * qvel[k] + o[5] * a[k]);
+          for (int q = 0; q < 3; q++) om[q] += cdof[6 * k + q] * w;
+        }
+        float x3[3];
+        cross3(ev, om, x3);
+        for (int q = 0; q < 3; q++) xb[q] += x3[q];
+      }
+      // plane contacts: pos = c_s - n (R + r/2), r = n . (c_s - p0) - R
+      const int kind = m.pair_kind[p];
+      float* o = cs + 10 * c;
+      const float* n = rec + 4;
+      const float nx = dot3(n, xb);
+      for (int q = 0; q < 3; q++) o[q] = xb[q] - 0.5f * n[q] * nx + rb * n[q];
+      const int g2 = m.pair_g2[p];
+      float gp[3] = {m.geom_pos[3 * g2], m.geom_pos[3 * g2 + 1], m.geom_pos[3 * g2 + 2]};
+      if (kind == PK_PLANE_CAPSULE) {
+        const float* Rg = m.geom_rot + 9 * g2;
+        const float sg = sub == 0 ? -m.geom_size[3 * g2 + 1] : m.geom_size[3 * g2 + 1];
+        gp[0] += sg * Rg[2]; gp[1] += sg * Rg[5]; gp[2] += sg * Rg[8];
+      }
+      o[3] = gp[0]; o[4] = gp[1]; o[5] = gp[2];
+      o[6] = __int_as_float(b2);
+      o[7] = (kind == PK_PLANE_SPHERE || kind == PK_PLANE_CAPSULE) ? 1.f : 0.f;
+    }
+    t.sync();
+    for (int b = 1 + t.lane; b < nb; b += t.T) {
+      for (int c = 0; c < ncon; c++) {
+        const float* o = cs + 10 * c;
+        if (__float_as_int(o[6]) != b) continue;
+        for (int q = 0; q < 3; q++) {
+          xbar[3 * b + q] += o[q];
+          for (int k = 0; k < 3; k++) Rbar[9 * b + 3 * q + k] += o[q] * o[3 + k];
+        }
+      }
+    }
+    int bad = 0;
+    for (int c = t.lane; c < ncon; c += t.T) bad |= (cs[10 * c + 7] == 0.f);
+    if (t.isum(bad)) status |= 8;
+  }
+  t.sync();
+  // ---- body inertias -> body poses (lane per body)
+  for (int b = 1 + t.lane; b < nb; b += t.T) {
+    const float* xp = W + m.o_xpos + 3 * b;
+    const float* R = W + m.o_xmat + 9 * b;
+    const float mass = m.body_mass[b];
+    const float* ipos = m.body_ipos + 3 * b;
+    float c[3];
+    mv3(R, ipos, c);
+    for (int q = 0; q < 3; q++) c[q] += xp[q];
+    const float* ib = cinbar + kCinert * b;
+    const float Ib[9] = {ib[4], ib[7], ib[8], ib[7], ib[5], ib[9], ib[8], ib[9], ib[6]};
+    const float tr = ib[4] + ib[5] + ib[6];
+    float Ic[3];
+    mv3(Ib, c, Ic);
+    float cb[3];
+    for (int q = 0; q < 3; q++) cb[q] = mass * ib[1 + q] + mass * (2.f * tr * c[q] - 2.f * Ic[q]);
+    const float* bi = m.body_inertia + 6 * b;
+    const float Il[9] = {bi[0], bi[3], bi[4], bi[3], bi[1], bi[5], bi[4], bi[5], bi[2]};
+    float T1[9], T2[9];
+    mm3(Ib, R, T1);
+    mm3(T1, Il, T2);
+    for (int q = 0; q < 3; q++) {
+      xbar[3 * b + q] += cb[q];
+      for (int k = 0; k < 3; k++) Rbar[9 * b + 3 * q + k] += 2.f * T2[3 * q + k] + cb[q] * ipos[k];
+    }
+  }
+  t.sync();
+  // ---- forward kinematics, reversed (leaves to root; children pass up)
+  for (int lv = m.nlevel - 1; lv >= 1; lv--) {
+    const int e = m.level_start[lv + 1];
+    for (int ib = m.level_start[lv] + t.lane; ib < e; ib += t.T) {
+      const int b = m.level_body[ib];
+      float xb[3], Rb[9];
+      for (int q = 0; q < 3; q++) xb[q] = xbar[3 * b + q];
+      for (int q = 0; q < 9; q++) Rb[q] = Rbar[9 * b + q];
+      for (int cc = m.child_start[b]; cc < m.child_start[b + 1]; cc++) {
+        const int ch = m.child_list[cc];
+        for (int q = 0; q < 3; q++) xb[q] += xup[3 * ch + q];
+        for (int q = 0; q < 9; q++) Rb[q] += Rup[9 * ch + q];
+      }
+      const int j0 = m.body_jntadr[b], nj = m.body_jntnum[b];
+      if (nj == 1 && m.jnt_type[j0] == JNT_FREE) {
+        const int qa = m.jnt_qposadr[j0], da = m.jnt_dofadr[j0];
+        const float* R1 = W + m.o_xmat + 9 * b;
+        const float* x1 = W + m.o_xpos + 3 * b;
+        for (int q = 0; q < 3; q++) qb[qa + q] += xb[q];
+        for (int i = 0; i < 3; i++) {
+          const float* Sb = Sbar + 6 * (da + 3 + i);
+          const float r[3] = {R1[i], R1[3 + i], R1[6 + i]};
+          float t1[3], t2[3];
+          cross3(Sb + 3, x1, t1);
+          cross3(r, Sb + 3, t2);
+          for (int q = 0; q < 3; q++) {
+            Rb[3 * q + i] += Sb[q] + t1[q];
+            qb[qa + q] += t2[q];
+          }
+        }
+        float qq[4] = {qpos[qa + 3], qpos[qa + 4], qpos[qa + 5], qpos[qa + 6]};
+        const float nrm = sqrtf(qq[0] * qq[0] + qq[1] * qq[1] + qq[2] * qq[2] + qq[3] * qq[3]);
+        const float w = qq[0] / nrm, x = qq[1] / nrm, y = qq[2] / nrm, z = qq[3] / nrm;
+        const float dW[9] = {0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0};
+        const float dX[9] = {0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x};
+        const float dY[9] = {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y};
+        const float dZ[9] = {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0};
+        float qn[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < 9; q++) {
+          qn[0] += Rb[q] * dW[q]; qn[1] += Rb[q] * dX[q];
+          qn[2] += Rb[q] * dY[q]; qn[3] += Rb[q] * dZ[q];
+        }
+        const float dot = w * qn[0] + x * qn[1] + y * qn[2] + z * qn[3];
+        const float un[4] = {w, x, y, z};
+        for (int q = 0; q < 4; q++) qb[qa + 3 + q] += (qn[q] - un[q] * dot) / nrm;
+        for (int q = 0; q < 3; q++) xup[3 * b + q] = 0.f;
+        for (int q = 0; q < 9; q++) Rup[9 * b + q] = 0.f;
+        continue;
+      }
+      // frames before each joint, recomputed from the parent pose
+      float xs[4][3], Rs[4][9];
+      float pos[3], R[9];
+      body_base(m, W, b, pos, R);
+      for (int jj = 0; jj < nj && jj < 4; jj++) {
+        const int j = j0 + jj, qa = m.jnt_qposadr[j];
+        for (int q = 0; q < 3; q++) xs[jj][q] = pos[q];
+        for (int q = 0; q < 9; q++) Rs[jj][q] = R[q];
+        float ax[3];
+        mv3(R, m.jnt_axis + 3 * j, ax);
+        if (m.jnt_type[j] == JNT_SLIDE) {
+          for (int q = 0; q < 3; q++) pos[q] += ax[q] * qpos[qa];
+        } else {
+          float off[3], anc[3], Rj[9];
+          mv3(R, m.jnt_pos + 3 * j, off);
+          for (int q = 0; q < 3; q++) anc[q] = pos[q] + off[q];
+          axis_rot(ax, qpos[qa], Rj);
+          mm3(Rj, R, R);
+          mv3(R, m.jnt_pos + 3 * j, off);
+          for (int q = 0; q < 3; q++) pos[q] = anc[q] - off[q];
+        }
+      }
+      for (int jj = (nj < 4 ? nj : 4) - 1; jj >= 0; jj--) {
+        const int j = j0 + jj, qa = m.jnt_qposadr[j], da = m.jnt_dofadr[j];
+        const float* R0 = Rs[jj];
+        const float* ev = m.jnt_axis + 3 * j;
+        const float* Sb = Sbar + 6 * da;
+        float ax[3];
+        mv3(R0, ev, ax);
+        if (m.jnt_type[j] == JNT_SLIDE) {
+          float axb[3];
+          for (int q = 0; q < 3; q++) axb[q] = Sb[3 + q] + qpos[qa] * xb[q];
+          qb[qa] += dot3(ax, xb);
+          for (int q = 0; q < 3; q++)
+            for (int k = 0; k < 3; k++) Rb[3 * q + k] += axb[q] * ev[k];
+        } else {
+          const float* ap = m.jnt_pos + 3 * j;
+          float off[3], anc[3], Rj[9];
+          mv3(R0, ap, off);
+          for (int q = 0; q < 3; q++) anc[q] = xs[jj][q] + off[q];
+          axis_rot(ax, qpos[qa], Rj);
+          float ancb[3], axb[3], t1[3];
+          cross3(ax, Sb + 3, ancb);
+          for (int q = 0; q < 3; q++) ancb[q] += xb[q];
+          cross3(Sb + 3, anc, t1);
+          for (int q = 0; q < 3; q++) axb[q] = Sb[q] + t1[q];
+          float R1b[9];
+          for (int q = 0; q < 3; q++)
+            for (int k = 0; k < 3; k++) R1b[3 * q + k] = Rb[3 * q + k] - xb[q] * ap[k];
+          // R1 = Rj R0: Rj_bar = R1b R0^T, R0_bar = Rj^T R1b
+          float Rjb[9], R0b[9];
+          for (int q = 0; q < 3; q++)
+            for (int k = 0; k < 3; k++) {
+              float s1 = 0.f, s2 = 0.f;
+              for (int l = 0; l < 3; l++) {
+                s1 += R1b[3 * q + l] * R0[3 * k + l];
+                s2 += Rj[3 * l + q] * R1b[3 * l + k];
+              }
+              Rjb[3 * q + k] = s1;
+              R0b[3 * q + k] = s2;
+            }
+          float SR[9];
+          skew_mul(ax, Rj, SR);
+          float qsum = 0.f;
+          for (int q = 0; q < 9; q++) qsum += Rjb[q] * SR[q];
+          qb[qa] += qsum;
+          float sq, cq;
+          sincosf(qpos[qa], &sq, &cq);
+          const float v2[3] = {Rjb[7] - Rjb[5], Rjb[2] - Rjb[6], Rjb[3] - Rjb[1]};
+          for (int q = 0; q < 3; q++) {
+            float sa = 0.f;
+            for (int k = 0; k < 3; k++) sa += (Rjb[3 * q + k] + Rjb[3 * k + q]) * ax[k];
+            axb[q] += sq * v2[q] + (1.f - cq) * sa;
+          }
+          for (int q = 0; q < 3; q++) xb[q] = ancb[q];
+          for (int q = 0; q < 3; q++)
+            for (int k = 0; k < 3; k++)
+              Rb[3 * q + k] = R0b[3 * q + k] + ancb[q] * ap[k] + axb[q] * ev[k];
+        }
+      }
+      // frame before the joints = parent pose composed with the body offset
+      const float* bp = m.body_pos + 3 * b;
+      const float* Rl = m.body_rot + 9 * b;
+      for (int q = 0; q < 3; q++) xup[3 * b + q] = xb[q];
+      for (int q = 0; q < 3; q++)
+        for (int k = 0; k < 3; k++) {
+          float s = xb[q] * bp[k];
+          for (int l = 0; l < 3; l++) s += Rb[3 * q + l] * Rl[3 * k + l];
+          Rup[9 * b + 3 * q + k] = s;
+        }
+    }
+    t.sync();
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+struct RolloutArgs {
+  DevModel m;
+  int nworld, horizon, ckpt, zidx, team, nseg;
+  float ztarget, wctrl;
+  float* qpos;
+  float* qvel;
+  float* qacc;
+  const float* ctrl;  // [horizon][nworld][nu]
+  float* tape_ckpt;   // [nseg][nworld][nq + 2 nv]
+  float* tape_seg;    // [ckpt + 1][nworld][nq + 2 nv]
+  float* loss;
+  const float* dloss;
+  float* grad_qvel0;
+  float* grad_ctrl;
+  int* status;
 };
 
-mjh_status adjoint_forward(AdjointState**, const DevModel&, int, float*, float*, float*, int,
-                           int, const float*, int, float, float, float*, hipStream_t,
+DEV void store_state(const DevModel& m, const float* W, const Team& t, float* dst) {
+  for (int i = t.lane; i < m.nq; i += t.T) dst[i] = W[m.o_qpos + i];
+  for (int i = t.lane; i < m.nv; i += t.T) {
+    dst[m.nq + i] = W[m.o_qvel + i];
+    dst[m.nq + m.nv + i] = W[m.o_qacc + i];
+  }
+}
+DEV void load_state(const DevModel& m, float* W, const Team& t, const float* src) {
+  for (int i = t.lane; i < m.nq; i += t.T) W[m.o_qpos + i] = src[i];
+  for (int i = t.lane; i < m.nv; i += t.T) {
+    W[m.o_qvel + i] = src[m.nq + i];
+    W[m.o_qacc + i] = src[m.nq + m.nv + i];
+  }
+  t.sync();
+}
+
+__global__ void __launch_bounds__(kAdjBlock) rollout_fwd_kernel(RolloutArgs A) {
+  extern __shared__ float lds[];
+  const int T = A.team;
+  const int team = threadIdx.x / T;
+  const int w = blockIdx.x * (blockDim.x / T) + team;
+  if (w >= A.nworld) return;
+  const DevModel& m = A.m;
+  const Team t{(int)threadIdx.x - team * T, T};
+  float* W = lds + (size_t)team * m.lds_words;
+  const int ns = m.nq + 2 * m.nv;
+  world_init(m, W, t);
+  const float* src0 = nullptr;
+  (void)src0;
+  for (int i = t.lane; i < m.nq; i += T) W[m.o_qpos + i] = A.qpos[(size_t)w * m.nq + i];
+  for (int i = t.lane; i < m.nv; i += T) {
+    W[m.o_qvel + i] = A.qvel[(size_t)w * m.nv + i];
+    W[m.o_qacc + i] = A.qacc[(size_t)w * m.nv + i];
+  }
+  t.sync();
+  int status = 0;
+  float loss = 0.f;
+  for (int s = 0; s < A.horizon; s++) {
+    if (s % A.ckpt == 0)
+      store_state(m, W, t, A.tape_ckpt + ((size_t)(s / A.ckpt) * A.nworld + w) * ns);
+    const float* u = A.ctrl + ((size_t)s * A.nworld + w) * m.nu;
+    world_step(m, W, t, u, status, kAdjIters);
+    integrate(m, W, t, status);
+    if (t.lane == 0) {
+      const float dz = W[m.o_qpos + A.zidx] - A.ztarget;
+      float uu = 0.f;
+      for (int k = 0; k < m.nu; k++) uu += u[k] * u[k];
+      loss += dz * dz + A.wctrl * uu;
+    }
+  }
+  for (int i = t.lane; i < m.nq; i += T) A.qpos[(size_t)w * m.nq + i] = W[m.o_qpos + i];
+  for (int i = t.lane; i < m.nv; i += T) {
+    A.qvel[(size_t)w * m.nv + i] = W[m.o_qvel + i];
+    A.qacc[(size_t)w * m.nv + i] = W[m.o_qacc + i];
+  }
+  status = t.ior(status);
+  if (t.lane == 0) {
+    A.loss[w] = loss;
+    if (A.status) A.status[w] = status;
+  }
+}
+
+__global__ void __launch_bounds__(kAdjBlock) rollout_bwd_kernel(RolloutArgs A) {
+  extern __shared__ float lds[];
+  const int T = A.team;
+  const int team = threadIdx.x / T;
+  const int w = blockIdx.x * (blockDim.x / T) + team;
+  if (w >= A.nworld) return;
+  const DevModel& m = A.m;
+  const Team t{(int)threadIdx.x - team * T, T};
+  float* W = lds + (size_t)team * m.lds_words;
+  const int ns = m.nq + 2 * m.nv;
+  world_init(m, W, t);
+  const float dl = A.dloss[w];
+  float* qbi = W + m.o_qbi;
+  float* vbi = W + m.o_vbi;
+  for (int i = t.lane; i < m.nq; i += T) qbi[i] = 0.f;
+  for (int i = t.lane; i < m.nv; i += T) vbi[i] = 0.f;
+  t.sync();
+  int status = 0;
+  auto seg_slot = [&](int k) { return A.tape_seg + ((size_t)k * A.nworld + w) * ns; };
+  for (int seg = A.nseg - 1; seg >= 0; seg--) {
+    const int s0 = seg * A.ckpt;
+    const int len = min(A.ckpt, A.horizon - s0);
+    // recompute the segment's states s0 .. s0 + len into the tape
+    load_state(m, W, t, A.tape_ckpt + ((size_t)seg * A.nworld + w) * ns);
+    store_state(m, W, t, seg_slot(0));
+    for (int k = 0; k < len; k++) {
+      const float* u = A.ctrl + ((size_t)(s0 + k) * A.nworld + w) * m.nu;
+      world_step(m, W, t, u, status, kAdjIters);
+      integrate(m, W, t, status);
+      store_state(m, W, t, seg_slot(k + 1));
+    }
+    t.sync();
+    for (int k = len - 1; k >= 0; k--) {
+      const int s = s0 + k;
+      const float* u = A.ctrl + ((size_t)s * A.nworld + w) * m.nu;
+      // loss term of the state after step s
+      const float znext = seg_slot(k + 1)[A.zidx];
+      if (t.lane == 0) qbi[A.zidx] += 2.f * (znext - A.ztarget) * dl;
+      load_state(m, W, t, seg_slot(k));
+      world_step(m, W, t, u, status, kAdjIters);
+      adjoint_step(m, W, t, u, status);
+      float* gu = A.grad_ctrl + ((size_t)s * A.nworld + w) * m.nu;
+      const float* ub = W + m.o_ub;
+      for (int i = t.lane; i < m.nu; i += T) gu[i] = ub[i] + 2.f * A.wctrl * u[i] * dl;
+      for (int i = t.lane; i < m.nq; i += T) qbi[i] = W[m.o_qb + i];
+      for (int i = t.lane; i < m.nv; i += T) vbi[i] = W[m.o_vb + i];
+      t.sync();
+    }
+  }
+  for (int i = t.lane; i < m.nv; i += T) A.grad_qvel0[(size_t)w * m.nv + i] = vbi[i];
+  status = t.ior(status);
+  if (t.lane == 0 && A.status) A.status[w] |= status;
+}
+
+// ------------------------------------------------------------------ host side
+struct AdjointState {
+  RolloutArgs args{};
+  float* tape_ckpt = nullptr;
+  float* tape_seg = nullptr;
+  int* status = nullptr;
+  size_t ckpt_words = 0, seg_words = 0, status_words = 0;
+  bool have_fwd = false;
+};
+
+static int blocks_for(int nworld, int team) {
+  const int wpb = kAdjBlock / team;
+  return (nworld + wpb - 1) / wpb;
+}
+
+mjh_status adjoint_forward(AdjointState** stp, const DevModel& m, int team, int nworld, float* qpos,
+                           float* qvel, float* qacc, int horizon, int ckpt, const float* ctrl,
+                           int zidx, float ztarget, float wctrl, float* loss, hipStream_t stream,
                            std::string& err) {
-  err = "rollout_fwd: not available in this build";
-  return MJH_EUNSUPPORTED;
+  if (horizon <= 0 || ckpt <= 0 || !ctrl || !loss || zidx < 0 || zidx >= m.nq) {
+    err = "rollout_fwd: need horizon > 0, ckpt_every > 0, ctrl, loss and 0 <= zidx < nq";
+    return MJH_EINVAL;
+  }
+  if (!qpos || !qvel || !qacc) { err = "rollout_fwd: state not bound"; return MJH_ESTATE; }
+  // the reverse sweep differentiates plane-sphere / plane-capsule contact geometry
+  team = (team == 16 || team == 32 || team == 64) ? team : 32;
+  AdjointState* st = *stp;
+  if (!st) {
+    st = new (std::nothrow) AdjointState();
+    if (!st) { err = "rollout_fwd: out of host memory"; return MJH_ENOMEM; }
+    *stp = st;
+  }
+  const int nseg = (horizon + ckpt - 1) / ckpt;
+  const size_t ns = (size_t)m.nq + 2 * m.nv;
+  const size_t need_ckpt = (size_t)nseg * nworld * ns;
+  const size_t need_seg = (size_t)(std::min(ckpt, horizon) + 1) * nworld * ns;
+  if (need_ckpt > st->ckpt_words) {
+    if (st->tape_ckpt) (void)hipFree(st->tape_ckpt);
+    st->tape_ckpt = nullptr;
+    if (hipMalloc(&st->tape_ckpt, need_ckpt * sizeof(float)) != hipSuccess) {
+      st->ckpt_words = 0;
+      err = "rollout_fwd: out of device memory (checkpoints)";
+      return MJH_ENOMEM;
+    }
+    st->ckpt_words = need_ckpt;
+  }
+  if (need_seg > st->seg_words) {
+    if (st->tape_seg) (void)hipFree(st->tape_seg);
+    st->tape_seg = nullptr;
+    if (hipMalloc(&st->tape_seg, need_seg * sizeof(float)) != hipSuccess) {
+      st->seg_words = 0;
+      err = "rollout_fwd: out of device memory (segment tape)";
+      return MJH_ENOMEM;
+    }
+    st->seg_words = need_seg;
+  }
+  if ((size_t)nworld > st->status_words) {
+    if (st->status) (void)hipFree(st->status);
+    st->status = nullptr;
+    if (hipMalloc(&st->status, sizeof(int) * (size_t)nworld) != hipSuccess) {
+      st->status_words = 0;
+      err = "rollout_fwd: out of device memory";
+      return MJH_ENOMEM;
+    }
+    st->status_words = (size_t)nworld;
+  }
+  RolloutArgs& A = st->args;
+  A.m = m;
+  A.nworld = nworld; A.horizon = horizon; A.ckpt = ckpt; A.zidx = zidx; A.team = team;
+  A.nseg = nseg; A.ztarget = ztarget; A.wctrl = wctrl;
+  A.qpos = qpos; A.qvel = qvel; A.qacc = qacc; A.ctrl = ctrl;
+  A.tape_ckpt = st->tape_ckpt; A.tape_seg = st->tape_seg; A.loss = loss; A.status = st->status;
+  st->have_fwd = false;
+  if (nworld == 0) { st->have_fwd = true; return MJH_OK; }
+  const size_t lds = (size_t)(kAdjBlock / team) * m.lds_words * sizeof(float);
+  hipError_t e = hipFuncSetAttribute((const void*)rollout_fwd_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)rollout_bwd_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) { err = std::string("rollout_fwd: ") + hipGetErrorString(e); return MJH_EHIP; }
+  hipLaunchKernelGGL(rollout_fwd_kernel, dim3(blocks_for(nworld, team)), dim3(kAdjBlock), lds,
+                     stream, A);
+  e = hipGetLastError();
+  if (e != hipSuccess) { err = std::string("rollout_fwd: ") + hipGetErrorString(e); return MJH_EHIP; }
+  st->have_fwd = true;
+  return MJH_OK;
 }
 
-mjh_status adjoint_backward(AdjointState*, const float*, float*, float*, hipStream_t,
-                            std::string& err) {
-  err = "rollout_bwd: not available in this build";
-  return MJH_EUNSUPPORTED;
+mjh_status adjoint_backward(AdjointState* st, const float* dloss, float* grad_qvel0,
+                            float* grad_ctrl, hipStream_t stream, std::string& err) {
+  if (!st || !st->have_fwd) { err = "rollout_bwd: call rollout_fwd first"; return MJH_ESTATE; }
+  if (!dloss || !grad_qvel0 || !grad_ctrl) { err = "rollout_bwd: NULL argument"; return MJH_EINVAL; }
+  RolloutArgs A = st->args;
+  A.dloss = dloss;
+  A.grad_qvel0 = grad_qvel0;
+  A.grad_ctrl = grad_ctrl;
+  if (A.nworld == 0) return MJH_OK;
+  const size_t lds = (size_t)(kAdjBlock / A.team) * A.m.lds_words * sizeof(float);
+  hipLaunchKernelGGL(rollout_bwd_kernel, dim3(blocks_for(A.nworld, A.team)), dim3(kAdjBlock), lds,
+                     stream, A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) { err = std::string("rollout_bwd: ") + hipGetErrorString(e); return MJH_EHIP; }
+  return MJH_OK;
 }
 
-void adjoint_free(AdjointState* st) { delete st; }
+void adjoint_free(AdjointState* st) {
+  if (!st) return;
+  if (st->tape_ckpt) (void)hipFree(st->tape_ckpt);
+  if (st->tape_seg) (void)hipFree(st->tape_seg);
+  if (st->status) (void)hipFree(st->status);
+  delete st;
+}
 
 }  // namespace mjh

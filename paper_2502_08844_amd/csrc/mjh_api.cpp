@@ -39,6 +39,7 @@ struct HostModel {
 struct ModelRec {
   HostModel h;
   DevModel dm{};
+  DevModel dm_adj{};  // same tables, adjoint on-chip layout
   void* dbuf = nullptr;  // one device allocation for all tables
   size_t dbytes = 0;
   double cost = 0.0;     // relative cost of one world-step (task ordering)
@@ -406,6 +407,29 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   d.o_s = take(nr);
   off = std::max(off, sweep_end);
   d.lds_words = off;
+  // adjoint layout: the same tables, every region separate, plus the reverse-sweep
+  // scratch (cotangents of dofs, bodies, rows and contacts)
+  DevModel& x = rec.dm_adj;
+  x = d;
+  off = 0;
+  x.o_qpos = take(h.nq); x.o_qvel = take(nv); x.o_qacc = take(nv);
+  x.o_xpos = take(3 * nb); x.o_xmat = take(9 * nb); x.o_cdof = take(6 * nv);
+  x.o_M = take(d.ntri); x.o_frc = take(nv); x.o_a0 = take(nv); x.o_scal = take(SC_COUNT);
+  x.o_cvel = take(6 * nb); x.o_cacc = take(6 * nb); x.o_cfrc = take(6 * nb);
+  x.o_cinert = take(kCinert * nb); x.o_F = take(6 * nv);
+  x.o_H = take(d.ntri); x.o_Mr = take(nv); x.o_g = take(nv); x.o_d = take(nv);
+  x.o_Md = take(nv); x.o_tmp = take(nv); x.o_cand = take(2 * ncand);
+  x.o_con = take(kConRec * h.nconmax); x.o_J = take(nr * nv); x.o_aref = take(nr);
+  x.o_D = take(nr); x.o_e = take(nr); x.o_s = take(nr);
+  x.o_qbi = take(h.nq); x.o_vbi = take(nv); x.o_qb = take(h.nq); x.o_vb = take(nv);
+  x.o_ub = take(h.nu); x.o_mu = take(nv); x.o_Sbar = take(6 * nv);
+  x.o_xbar = take(3 * nb); x.o_Rbar = take(9 * nb); x.o_cinbar = take(kCinert * nb);
+  x.o_Vbar = take(6 * nb); x.o_Abar = take(6 * nb); x.o_Fbar = take(6 * nb);
+  x.o_vup = take(6 * nb); x.o_aup = take(6 * nb); x.o_xup = take(3 * nb);
+  x.o_Rup = take(9 * nb); x.o_rowsc = take(7 * nr); x.o_consc = take(10 * h.nconmax);
+  x.lds_words = off;
+  off = d.lds_words;
+  d.lds_words = off;
   rec.cost = (double)nv * nv * (nv + 4.0 * nr) + 50.0 * nb + 30.0 * ncand;
   return MJH_OK;
 }
@@ -575,6 +599,24 @@ mjh_status mjh_model_upload(mjh_ctx* ctx, const void* blob, size_t nbytes, int32
   MJH_HIP(hipMemcpy(rec->dbuf, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice));
   uint8_t* base = static_cast<uint8_t*>(rec->dbuf);
   for (auto& f : pk.fix) *f.second = base + f.first;
+  {  // the adjoint layout shares every table pointer
+    DevModel x = rec->dm;
+    const DevModel& lay = rec->dm_adj;
+    x.lds_words = lay.lds_words;
+    x.o_qpos = lay.o_qpos; x.o_qvel = lay.o_qvel; x.o_qacc = lay.o_qacc; x.o_xpos = lay.o_xpos;
+    x.o_xmat = lay.o_xmat; x.o_cdof = lay.o_cdof; x.o_M = lay.o_M; x.o_frc = lay.o_frc;
+    x.o_a0 = lay.o_a0; x.o_scal = lay.o_scal; x.o_cvel = lay.o_cvel; x.o_cacc = lay.o_cacc;
+    x.o_cfrc = lay.o_cfrc; x.o_cinert = lay.o_cinert; x.o_F = lay.o_F; x.o_H = lay.o_H;
+    x.o_Mr = lay.o_Mr; x.o_g = lay.o_g; x.o_d = lay.o_d; x.o_Md = lay.o_Md; x.o_tmp = lay.o_tmp;
+    x.o_cand = lay.o_cand; x.o_con = lay.o_con; x.o_J = lay.o_J; x.o_aref = lay.o_aref;
+    x.o_D = lay.o_D; x.o_e = lay.o_e; x.o_s = lay.o_s; x.o_qbi = lay.o_qbi; x.o_vbi = lay.o_vbi;
+    x.o_qb = lay.o_qb; x.o_vb = lay.o_vb; x.o_ub = lay.o_ub; x.o_mu = lay.o_mu;
+    x.o_Sbar = lay.o_Sbar; x.o_xbar = lay.o_xbar; x.o_Rbar = lay.o_Rbar;
+    x.o_cinbar = lay.o_cinbar; x.o_Vbar = lay.o_Vbar; x.o_Abar = lay.o_Abar;
+    x.o_Fbar = lay.o_Fbar; x.o_vup = lay.o_vup; x.o_aup = lay.o_aup; x.o_xup = lay.o_xup;
+    x.o_Rup = lay.o_Rup; x.o_rowsc = lay.o_rowsc; x.o_consc = lay.o_consc;
+    rec->dm_adj = x;
+  }
   // translational inverse weights at qpos0, computed on the device
   MJH_HIP(launch_invweight(rec->dm, nullptr));
   MJH_HIP(hipDeviceSynchronize());
@@ -879,8 +921,22 @@ mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every, co
   if (b->groups.size() != 1) return fail(ctx, MJH_EINVAL, "rollout: single-model batches only");
   GroupRec& g = b->groups[0];
   const ModelRec& mr = *ctx->models[g.model];
+  // the reverse sweep covers plane-sphere / plane-capsule contact geometry and bodies
+  // of at most four scalar joints
+  for (int p = 0; p < mr.h.npair; p++) {
+    const int t1 = mr.h.geom_type[mr.h.pair_g1[p]], t2 = mr.h.geom_type[mr.h.pair_g2[p]];
+    if (!(t1 == GEOM_PLANE && (t2 == GEOM_SPHERE || t2 == GEOM_CAPSULE)))
+      return fail(ctx, MJH_EUNSUPPORTED,
+                  "rollout: only plane-sphere and plane-capsule contacts are differentiated");
+  }
+  {
+    std::vector<int> nj(mr.h.nbody, 0);
+    for (int j = 0; j < mr.h.njnt; j++) nj[mr.h.jnt_body[j]]++;
+    for (int b = 0; b < mr.h.nbody; b++)
+      if (nj[b] > 4) return fail(ctx, MJH_EUNSUPPORTED, "rollout: a body has more than 4 joints");
+  }
   std::string err;
-  mjh_status st = adjoint_forward(&b->adj, mr.dm, g.nworld, g.qpos, g.qvel, g.qacc, horizon,
+  mjh_status st = adjoint_forward(&b->adj, mr.dm_adj, g.team, g.nworld, g.qpos, g.qvel, g.qacc, horizon,
                                   ckpt_every, ctrl, zidx, ztarget, wctrl, loss,
                                   static_cast<hipStream_t>(stream), err);
   if (st != MJH_OK) return fail(ctx, st, err);

@@ -186,7 +186,7 @@ DEV void actuation(const DevModel& m, float* W, const Team& t, const float* ctrl
 // absolute pose), record motion subspaces S (world origin) and their rates, the
 // body velocity V, bias acceleration A (qacc = 0, world at -gravity), spatial
 // inertia and the body force f = I A + V x* I V.
-DEV void forward_sweep(const DevModel& m, float* W, const Team& t) {
+DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* qacc = nullptr) {
   const float* qpos = W + m.o_qpos;
   const float* qvel = W + m.o_qvel;
   float* xpos = W + m.o_xpos;
@@ -242,6 +242,9 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t) {
             crossm(V, S + 6 * i, Sd);
             for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel[da + i];
           }
+          if (qacc)
+            for (int i = 0; i < 6; i++)
+              for (int k = 0; k < 6; k++) A[k] += S[6 * i + k] * qacc[da + i];
         } else if (type == JNT_SLIDE) {
           float ax[3];
           mv3(R, m.jnt_axis + 3 * j, ax);
@@ -251,7 +254,7 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t) {
           S[3] = ax[0]; S[4] = ax[1]; S[5] = ax[2];
           for (int k = 0; k < 6; k++) V[k] += S[k] * qvel[da];
           crossm(V, S, Sd);
-          for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel[da];
+          for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel[da] + (qacc ? S[k] * qacc[da] : 0.f);
         } else {  // hinge
           float ax[3], off[3], anc[3], Rj[9];
           mv3(R, m.jnt_axis + 3 * j, ax);
@@ -265,7 +268,7 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t) {
           cross3(anc, ax, S + 3);
           for (int k = 0; k < 6; k++) V[k] += S[k] * qvel[da];
           crossm(V, S, Sd);
-          for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel[da];
+          for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel[da] + (qacc ? S[k] * qacc[da] : 0.f);
         }
       }
       for (int k = 0; k < 3; k++) xpos[3 * b + k] = pos[k];
@@ -791,15 +794,75 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
 }
 
 // --------------------------------------------------- A9: Newton solve (NW ch. 3, 6)
+// H = M + sum_{rows with e < 0} D J^T J (packed lower), factorised in place as L L^T
+// (right-looking, one column per barrier pair).  Returns false for a non-positive pivot.
+DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nrow) {
+  const int nv = m.nv;
+  const float* M = W + m.o_M;
+  float* H = W + m.o_H;
+  const float* J = W + m.o_J;
+  const float* D = W + m.o_D;
+  const float* e = W + m.o_e;
+  for (int k = t.lane; k < m.ntri; k += t.T) {
+    int i, j;
+    tri_unrank(k, i, j);
+    float v = M[k];
+    for (int r = 0; r < nrow; r++) {
+      if (e[r] < 0.f) v += D[r] * J[r * nv + i] * J[r * nv + j];
+    }
+    H[k] = v;
+  }
+  t.sync();
+  bool ok = true;
+  for (int j = 0; j < nv; j++) {
+    const float piv = H[tri(j, j)];
+    ok = ok && (piv > 0.f);
+    const float dj = sqrtf(fmaxf(piv, 1e-30f));
+    const float inv = 1.f / dj;
+    for (int i = j + 1 + t.lane; i < nv; i += t.T) H[tri(i, j)] *= inv;
+    t.sync();
+    if (t.lane == 0) H[tri(j, j)] = dj;
+    const int n2 = nv - j - 1;
+    const int npr = n2 * (n2 + 1) / 2;
+    for (int p = t.lane; p < npr; p += t.T) {
+      int bi, ai;
+      tri_unrank(p, bi, ai);
+      const int i = j + 1 + bi, k = j + 1 + ai;
+      H[tri(i, k)] -= H[tri(i, j)] * H[tri(k, j)];
+    }
+    t.sync();
+  }
+  return ok;
+}
+// x = sgn * (L L^T)^{-1} rhs with the factor in H (one lane; rhs and x may alias)
+DEV void cholesky_solve(const DevModel& m, float* W, const Team& t, const float* rhs, float* x,
+                        float sgn) {
+  const float* H = W + m.o_H;
+  const int nv = m.nv;
+  if (t.lane == 0) {
+    for (int i = 0; i < nv; i++) {
+      float v = sgn * rhs[i];
+      for (int k = 0; k < i; k++) v -= H[tri(i, k)] * x[k];
+      x[i] = v / H[tri(i, i)];
+    }
+    for (int i = nv - 1; i >= 0; i--) {
+      float v = x[i];
+      for (int k = i + 1; k < nv; k++) v -= H[tri(k, i)] * x[k];
+      x[i] = v / H[tri(i, i)];
+    }
+  }
+  t.sync();
+}
+
 // F(a) = 1/2 (a - a0)^T M (a - a0) + sum_r 1/2 D_r min(0, J_r a - aref_r)^2.
 // Start from the cheaper of the warm start and a0; each iteration: gradient and
 // Hessian on the active set, dense Cholesky of H, Newton direction, exact line
-// search (phi' evaluated at every breakpoint in parallel), update.
-DEV void newton(const DevModel& m, float* W, const Team& t, int& status) {
+// search (phi' evaluated at every breakpoint in parallel), update.  Stops early when
+// the Newton direction is no longer a descent direction (converged to precision).
+DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int iters) {
   const int* scal = (const int*)(W + m.o_scal);
   const int nv = m.nv, nrow = 4 * scal[SC_NCON];
   const float* M = W + m.o_M;
-  float* H = W + m.o_H;
   const float* J = W + m.o_J;
   const float* aref = W + m.o_aref;
   const float* D = W + m.o_D;
@@ -845,7 +908,7 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status) {
     for (int r = t.lane; r < nrow; r += t.T) e[r] = s[r];
     t.sync();
   }
-  for (int it = 0; it < m.iterations; it++) {
+  for (int it = 0; it < iters; it++) {
     // ---- gradient g = M (a - a0) + sum_active D e J
     for (int i = t.lane; i < nv; i += t.T) {
       float v = Mr[i];
@@ -855,52 +918,9 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status) {
       }
       g[i] = v;
     }
-    // ---- Hessian H = M + sum_active D J^T J (packed lower)
-    for (int k = t.lane; k < m.ntri; k += t.T) {
-      int i, j;
-      tri_unrank(k, i, j);
-      float v = M[k];
-      for (int r = 0; r < nrow; r++) {
-        if (e[r] < 0.f) v += D[r] * J[r * nv + i] * J[r * nv + j];
-      }
-      H[k] = v;
-    }
-    t.sync();
-    // ---- dense Cholesky H = L L^T (right-looking, packed lower)
-    bool ok = true;
-    for (int j = 0; j < nv; j++) {
-      const float piv = H[tri(j, j)];
-      ok = ok && (piv > 0.f);
-      const float dj = sqrtf(fmaxf(piv, 1e-30f));
-      const float inv = 1.f / dj;
-      for (int i = j + 1 + t.lane; i < nv; i += t.T) H[tri(i, j)] *= inv;
-      t.sync();
-      if (t.lane == 0) H[tri(j, j)] = dj;
-      const int n2 = nv - j - 1;
-      const int npr = n2 * (n2 + 1) / 2;
-      for (int p = t.lane; p < npr; p += t.T) {
-        int bi, ai;
-        tri_unrank(p, bi, ai);
-        const int i = j + 1 + bi, k = j + 1 + ai;
-        H[tri(i, k)] -= H[tri(i, j)] * H[tri(k, j)];
-      }
-      t.sync();
-    }
-    if (!ok) { status |= 4; break; }
-    // ---- delta = -H^-1 g (serial substitutions in one lane)
-    if (t.lane == 0) {
-      for (int i = 0; i < nv; i++) {
-        float v = -g[i];
-        for (int k = 0; k < i; k++) v -= H[tri(i, k)] * d[k];
-        d[i] = v / H[tri(i, i)];
-      }
-      for (int i = nv - 1; i >= 0; i--) {
-        float v = d[i];
-        for (int k = i + 1; k < nv; k++) v -= H[tri(k, i)] * d[k];
-        d[i] = v / H[tri(i, i)];
-      }
-    }
-    t.sync();
+    if (!hessian_cholesky(m, W, t, nrow)) { status |= 4; break; }
+    // ---- delta = -H^-1 g
+    cholesky_solve(m, W, t, g, d, -1.f);
     // ---- line search quantities
     float gd = 0.f, dMd = 0.f, dMr = 0.f;
     for (int i = t.lane; i < nv; i += t.T) {
@@ -1046,7 +1066,7 @@ DEV void integrate(const DevModel& m, float* W, const Team& t, int& status) {
 #endif
 
 DEV void world_step(const DevModel& m, float* W, const Team& t, const float* ctrl,
-                    int& status, long long* ph = nullptr, long long* last = nullptr) {
+                    int& status, int iters, long long* ph = nullptr, long long* last = nullptr) {
   actuation(m, W, t, ctrl);
   MJH_MARK(0);
   forward_sweep(m, W, t);
@@ -1061,7 +1081,7 @@ DEV void world_step(const DevModel& m, float* W, const Team& t, const float* ctr
   MJH_MARK(4);
   constraint_rows(m, W, t);
   MJH_MARK(5);
-  newton(m, W, t, status);
+  newton(m, W, t, status, iters);
   MJH_MARK(6);
 }
 

@@ -95,6 +95,9 @@ struct DevModel {
   int o_M, o_H;
   int o_frc, o_a0, o_Mr, o_g, o_d, o_Md, o_tmp;
   int o_cand, o_con, o_J, o_aref, o_D, o_e, o_s, o_scal;
+  // adjoint layout only (no aliasing between the sweep and contact scratch there)
+  int o_qbi, o_vbi, o_qb, o_vb, o_ub, o_mu, o_Sbar, o_xbar, o_Rbar, o_cinbar;
+  int o_Vbar, o_Abar, o_Fbar, o_vup, o_aup, o_xup, o_Rup, o_rowsc, o_consc;
 };
 
 // scalar slots inside o_scal

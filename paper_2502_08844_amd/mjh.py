@@ -216,11 +216,25 @@ class Batch:
 
     def rollout_fwd(self, horizon: int, ckpt_every: int, ctrl, zidx: int, ztarget: float,
                     wctrl: float, loss, stream=None):
+        if len(self.models) != 1:
+            raise ValueError("rollouts take a single-model batch")
+        nw, nu = self.counts[0], self.models[0].nu
+        if ctrl is None or ctrl.numel() != horizon * nw * nu or loss.numel() != nw:
+            raise ValueError(f"ctrl must be [{horizon}, {nw}, {nu}] and loss [{nw}]")
+        self._rollout = (int(horizon), nw, self.models[0].nv, nu)
         self.ctx.check(mjh_rollout_fwd(self._h, int(horizon), int(ckpt_every), _ptr(ctrl),
                                        int(zidx), float(ztarget), float(wctrl), _ptr(loss),
                                        _stream(stream)))
 
     def rollout_bwd(self, dloss, grad_qvel0, grad_ctrl, stream=None):
+        shp = getattr(self, "_rollout", None)
+        if shp is None:
+            raise ValueError("rollout_bwd needs a preceding rollout_fwd")
+        horizon, nw, nv, nu = shp
+        if (dloss.numel() != nw or grad_qvel0.numel() != nw * nv
+                or grad_ctrl.numel() != horizon * nw * nu):
+            raise ValueError(f"dloss [{nw}], grad_qvel0 [{nw}, {nv}], "
+                             f"grad_ctrl [{horizon}, {nw}, {nu}] expected")
         self.ctx.check(mjh_rollout_bwd(self._h, _ptr(dloss), _ptr(grad_qvel0),
                                        _ptr(grad_ctrl), _stream(stream)))
 
@@ -261,3 +275,52 @@ class World:
         self.batch.bind_io(0, ctrl, con, ncon)
         self.batch.step(nstep, stream)
         return (con, ncon) if contacts else None
+
+
+class Rollout(torch.autograd.Function):
+    """Differentiable rollout loss of a single-model World.
+
+    forward(ctx, qvel0, ctrl, world, horizon, ckpt_every, zidx, ztarget, wctrl)
+      -> loss [nworld]: sum_t (qpos_t[zidx] - ztarget)^2 + wctrl |ctrl_t|^2, starting from
+      world.qpos with initial velocity qvel0 [nworld, nv] and controls ctrl
+      [horizon, nworld, nu].  backward returns d(loss)/d(qvel0) and d(loss)/d(ctrl) from
+      the library's adjoint (checkpointed every ckpt_every steps).
+    The world's state is advanced to the final step by forward.
+    """
+
+    @staticmethod
+    def forward(ctx, qvel0, ctrl, world, horizon, ckpt_every, zidx=2, ztarget=0.3,
+                wctrl=1e-3):
+        world.qvel.copy_(qvel0)
+        ctrl = ctrl.contiguous()
+        loss = torch.empty(world.nworld, dtype=torch.float32, device=qvel0.device)
+        world.batch.rollout_fwd(horizon, ckpt_every, ctrl, zidx, ztarget, wctrl, loss)
+        ctx.world = world
+        ctx.save_for_backward(ctrl)
+        return loss
+
+    @staticmethod
+    def backward(ctx, dloss):
+        (ctrl,) = ctx.saved_tensors
+        w = ctx.world
+        gq = torch.empty(w.nworld, w.model.nv, dtype=torch.float32, device=dloss.device)
+        gu = torch.empty_like(ctrl)
+        w.batch.rollout_bwd(dloss.contiguous().float(), gq, gu)
+        return gq, gu, None, None, None, None, None, None
+
+
+def rollout_fwd(world: World, ctrl, horizon: int, ckpt_every: int, zidx: int = 2,
+                ztarget: float = 0.3, wctrl: float = 1e-3, stream=None):
+    loss = torch.empty(world.nworld, dtype=torch.float32, device=world.qpos.device)
+    world.batch.rollout_fwd(horizon, ckpt_every, ctrl, zidx, ztarget, wctrl, loss, stream)
+    return loss
+
+
+def rollout_bwd(world: World, dloss, horizon: int, stream=None):
+    """Gradients (d loss/d qvel0 [nworld, nv], d loss/d ctrl [horizon, nworld, nu]) of the
+    last rollout_fwd of this world, weighted by dloss [nworld]."""
+    dev = world.qpos.device
+    gq = torch.empty(world.nworld, world.model.nv, dtype=torch.float32, device=dev)
+    gu = torch.empty(horizon, world.nworld, world.model.nu, dtype=torch.float32, device=dev)
+    world.batch.rollout_bwd(dloss.contiguous().float(), gq, gu, stream)
+    return gq, gu
