@@ -34,6 +34,9 @@ def parse():
     ap.add_argument("--cpu-sample-worlds", type=int, default=8192)
     ap.add_argument("--cpu-sample-steps", type=int, default=40)
     ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (a reference "
+                         "kernel for calibrating hardware byte counters)")
     return ap.parse_args()
 
 
@@ -67,6 +70,13 @@ def main():
     from paper_2502_08844_amd import mjh
     from paper_2502_08844_amd.synth import inputs, robots
 
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     kind = "quadruped"
     m = robots.quadruped()
     nw, ns = args.nworld, args.nstep

@@ -640,62 +640,56 @@ T box_point(const T* c, const T* R, const double* h, const T* p, T* nworld) {
   return s;
 }
 
-// capsule segment against a box: minimise the box SDF along the segment (it is convex),
-// then take the endpoints and the two ends of the minimiser's eps-sublevel interval as
-// candidates; keep the two deepest penetrating ones.  Normal from capsule to box.
+// capsule segment a + t u against a box.  The box SDF f(t) along the segment is convex,
+// so its derivative f'(t) = grad sdf(p(t)) . u is nondecreasing.  The minimiser set is
+// bracketed by t_lo = sup{t : f'(t) < -tau} and t_hi = inf{t : f'(t) > tau}
+// (tau = 1e-5 |u|), found by bisection on the sign of f' (well conditioned where the
+// values of f are not).  A bracket longer than 1e-3 is a flat stretch: both ends are
+// candidates; otherwise its midpoint is.  With the two segment ends this gives up to
+// four candidates (t = 0, t = 1, then the interior ones), de-duplicated within 1e-6;
+// the two deepest penetrating ones are kept.  Normal from capsule to box.
 template <class T>
 void capsule_box(const T* a, const T* u, T r, const T* c, const T* R, const double* h,
                  std::vector<Cand<T>>& out) {
-  auto f = [&](T t) {
+  // f'(t) from the box-frame SDF gradient at p(t)
+  auto fprime = [&](T t) {
     T p[3] = {a[0] + t * u[0], a[1] + t * u[1], a[2] + t * u[2]};
     T nw[3];
-    return box_point(c, R, h, p, nw);
+    box_point(c, R, h, p, nw);
+    return dot3(nw, u);
   };
-  const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
-  T lo = 0.0, hi = 1.0;
-  T x1 = hi - gr * (hi - lo), x2 = lo + gr * (hi - lo);
-  T f1 = f(x1), f2 = f(x2);
-  for (int it = 0; it < 80; it++) {
-    if (f1 < f2) {
-      hi = x2; x2 = x1; f2 = f1;
-      x1 = hi - gr * (hi - lo); f1 = f(x1);
-    } else {
-      lo = x1; x1 = x2; f1 = f2;
-      x2 = lo + gr * (hi - lo); f2 = f(x2);
-    }
-  }
-  T tm = 0.5 * (lo + hi);
-  T fm = tmin(f(tm), tmin(f(T(0.0)), f(T(1.0))));
-  const double eps = 1e-7;
-  T thr = fm + eps;
-  // ends of the sublevel interval {t : f(t) <= fm + eps} by bisection
+  const T tau = 1e-5 * norm3(u);
   T tlo, thi;
-  if (f(T(0.0)) <= thr) {
-    tlo = 0.0;
-  } else {
-    T l = 0.0, g = tm;
+  if (!(fprime(T(0.0)) < -tau)) tlo = 0.0;
+  else if (fprime(T(1.0)) < -tau) tlo = 1.0;
+  else {
+    T l = 0.0, g = 1.0;  // fprime(l) < -tau <= fprime(g)
     for (int it = 0; it < 60; it++) {
       T mid = 0.5 * (l + g);
-      if (f(mid) <= thr) g = mid; else l = mid;
+      if (fprime(mid) < -tau) l = mid; else g = mid;
     }
-    tlo = g;
+    tlo = 0.5 * (l + g);
   }
-  if (f(T(1.0)) <= thr) {
-    thi = 1.0;
-  } else {
-    T l = tm, g = 1.0;
+  if (!(fprime(T(1.0)) > tau)) thi = 1.0;
+  else if (fprime(T(0.0)) > tau) thi = 0.0;
+  else {
+    T l = 0.0, g = 1.0;  // fprime(l) <= tau < fprime(g)
     for (int it = 0; it < 60; it++) {
       T mid = 0.5 * (l + g);
-      if (f(mid) <= thr) l = mid; else g = mid;
+      if (fprime(mid) > tau) g = mid; else l = mid;
     }
-    thi = l;
+    thi = 0.5 * (l + g);
   }
   T ts[4] = {T(0.0), T(1.0), tlo, thi};
   bool keep[4] = {true, true, true, true};
-  const double tdup = 1e-6;
-  if (fabs(tlo - 0.0) < tdup || fabs(tlo - 1.0) < tdup) keep[2] = false;
-  if (fabs(thi - 0.0) < tdup || fabs(thi - 1.0) < tdup || fabs(thi - tlo) < tdup)
+  if (thi - tlo < 1e-3) {  // not a flat stretch: one interior candidate at the middle
+    ts[2] = 0.5 * (tlo + thi);
     keep[3] = false;
+  }
+  const double tdup = 1e-6;
+  for (int k = 2; k < 4; k++)
+    if (fabs(ts[k] - 0.0) < tdup || fabs(ts[k] - 1.0) < tdup) keep[k] = false;
+  if (keep[2] && keep[3] && fabs(ts[3] - ts[2]) < tdup) keep[3] = false;
   T depth[4];
   T nrm[4][3];
   T pts[4][3];

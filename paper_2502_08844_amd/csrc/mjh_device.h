@@ -349,47 +349,63 @@ DEV void backward_and_mass(const DevModel& m, float* W, const Team& t) {
 }
 
 // ------------------------------------------ A4/A6 sparse L^T D L and a0 = M^-1 frc
-// Factor a copy of M in H (no fill-in outside the dof-ancestor pattern).
-DEV void ltdl_factor(const DevModel& m, float* W, const Team& t) {
+// Factor a copy of M in H (no fill-in outside the dof-ancestor pattern), leaves first.
+// Eliminating dof k updates the entries among its ancestors with row k unscaled; the
+// scaling of row k by 1/D_k waits one elimination (nothing reads it meanwhile), so each
+// elimination costs one barrier.  When `rhs` is given, the first triangular solve
+// L^T y = rhs rides along: once row k is final, y_i -= L_ki y_k for its ancestors.
+DEV void ltdl_factor(const DevModel& m, float* W, const Team& t, float* y = nullptr) {
   const float* M = W + m.o_M;
   float* H = W + m.o_H;
   for (int k = t.lane; k < m.ntri; k += t.T) H[k] = M[k];
   t.sync();
-  for (int k = m.nv - 1; k >= 0; k--) {
-    const int a0 = m.anc_start[k], na = m.anc_start[k + 1] - a0;
-    const float inv = 1.f / H[tri(k, k)];
-    const int npr = na * (na + 1) / 2;
-    for (int p = t.lane; p < npr; p += t.T) {
-      int bi, ai;
-      tri_unrank(p, bi, ai);
-      const int i = m.anc_list[a0 + ai];  // nearer ancestor (larger index)
-      const int j = m.anc_list[a0 + bi];  // j ancestor-or-self of i
-      H[tri(i, j)] -= H[tri(k, i)] * H[tri(k, j)] * inv;
+  for (int k = m.nv - 1; k >= -1; k--) {
+    if (k >= 0) {
+      const int a0 = m.anc_start[k], na = m.anc_start[k + 1] - a0;
+      const float inv = 1.f / H[tri(k, k)];
+      const int npr = na * (na + 1) / 2;
+      for (int p = t.lane; p < npr; p += t.T) {
+        int bi, ai;
+        tri_unrank(p, bi, ai);
+        const int i = m.anc_list[a0 + ai];  // nearer ancestor (larger index)
+        const int j = m.anc_list[a0 + bi];  // j ancestor-or-self of i
+        H[tri(i, j)] -= H[tri(k, i)] * H[tri(k, j)] * inv;
+      }
     }
-    t.sync();
-    for (int q = t.lane; q < na; q += t.T) {
-      const int i = m.anc_list[a0 + q];
-      H[tri(k, i)] *= inv;
+    const int k1 = k + 1;  // deferred: scale row k1, then propagate y_k1
+    if (k1 < m.nv) {
+      const int a1 = m.anc_start[k1], n1 = m.anc_start[k1 + 1] - a1;
+      const float inv1 = 1.f / H[tri(k1, k1)];
+      const float yk = y ? y[k1] : 0.f;
+      for (int q = t.lane; q < n1; q += t.T) {
+        const int i = m.anc_list[a1 + q];
+        const float l = H[tri(k1, i)] * inv1;
+        H[tri(k1, i)] = l;
+        if (y) y[i] -= l * yk;
+      }
     }
     t.sync();
   }
 }
 // x = M^-1 rhs with the factors in H: L^T y = rhs, y /= D, L x = y (one lane; the
-// other lanes wait at the barrier).  rhs and x may alias.
-DEV void ltdl_solve(const DevModel& m, float* W, const Team& t, const float* rhs, float* x) {
+// other lanes wait at the barrier).  rhs and x may alias.  With `half` the first solve
+// has already been done by ltdl_factor and x holds y.
+DEV void ltdl_solve(const DevModel& m, float* W, const Team& t, const float* rhs, float* x,
+                    bool half = false) {
   const float* H = W + m.o_H;
   if (t.lane == 0) {
-    for (int i = 0; i < m.nv; i++) x[i] = rhs[i];
-    for (int k = m.nv - 1; k >= 0; k--) {
-      const float yk = x[k];
-      for (int q = m.anc_start[k]; q < m.anc_start[k + 1]; q++) {
-        const int i = m.anc_list[q];
-        x[i] -= H[tri(k, i)] * yk;
+    if (!half) {
+      for (int i = 0; i < m.nv; i++) x[i] = rhs[i];
+      for (int k = m.nv - 1; k >= 0; k--) {
+        const float yk = x[k];
+        for (int q = m.anc_start[k]; q < m.anc_start[k + 1]; q++) {
+          const int i = m.anc_list[q];
+          x[i] -= H[tri(k, i)] * yk;
+        }
       }
     }
-    for (int k = 0; k < m.nv; k++) x[k] /= H[tri(k, k)];
     for (int k = 0; k < m.nv; k++) {
-      float s = x[k];
+      float s = x[k] / H[tri(k, k)];
       for (int q = m.anc_start[k]; q < m.anc_start[k + 1]; q++) {
         const int i = m.anc_list[q];
         s -= H[tri(k, i)] * x[i];
@@ -447,51 +463,59 @@ DEV float box_sdf_only(const float* c, const float* R, const float* h, const flo
   return box_point(c, R, h, p, n);
 }
 
-// capsule segment a + t u (radius r) against a box: the box SDF is convex along the
-// segment; golden-section search for its minimum, then the ends of the eps-sublevel
-// interval of the minimum by bisection.  Candidates (t = 0, t = 1, t_lo, t_hi) after
-// de-duplication; the two deepest penetrating ones are kept (others get +inf).
-constexpr float kCapBoxEps = 1e-7f;
+// capsule segment a + t u (radius r) against a box.  The box SDF f(t) along the
+// segment is convex, so f'(t) = grad sdf(p(t)) . u is nondecreasing; the minimiser set
+// is bracketed by t_lo = sup{f' < -tau} and t_hi = inf{f' > tau} (tau = 1e-5 |u|),
+// found by bisection on the sign of f' -- derivative signs stay reliable in FP32 where
+// differences of SDF values do not.  A bracket of length >= 1e-3 is a flat stretch
+// (both ends are candidates), otherwise its midpoint is.  Candidates t = 0, t = 1 and
+// the interior ones, de-duplicated within 1e-6; the two deepest penetrating ones are
+// kept (others get +inf).
+constexpr float kCapBoxTau = 1e-5f;
+constexpr float kCapBoxFlat = 1e-3f;
 constexpr float kCapBoxDup = 1e-6f;
 DEV void capsule_box_cands(const float* a, const float* u, float r, const float* c,
                            const float* R, const float* h, float* dist, float* tpar) {
-  auto f = [&](float t) {
-    float p[3] = {a[0] + t * u[0], a[1] + t * u[1], a[2] + t * u[2]};
-    return box_sdf_only(c, R, h, p);
+  auto fprime = [&](float t) {
+    float p[3] = {a[0] + t * u[0], a[1] + t * u[1], a[2] + t * u[2]}, n[3];
+    box_point(c, R, h, p, n);
+    return dot3(n, u);
   };
-  const float gr = 0.6180339887498949f;
-  float lo = 0.f, hi = 1.f;
-  float x1 = hi - gr * (hi - lo), x2 = lo + gr * (hi - lo);
-  float f1 = f(x1), f2 = f(x2);
-  for (int it = 0; it < 40; it++) {
-    if (f1 < f2) { hi = x2; x2 = x1; f2 = f1; x1 = hi - gr * (hi - lo); f1 = f(x1); }
-    else { lo = x1; x1 = x2; f1 = f2; x2 = lo + gr * (hi - lo); f2 = f(x2); }
-  }
-  const float tm = 0.5f * (lo + hi);
-  const float fa = f(0.f), fb = f(1.f);
-  const float fm = fminf(f(tm), fminf(fa, fb));
-  const float thr = fm + kCapBoxEps;
+  const float tau = kCapBoxTau * sqrtf(dot3(u, u));
   float tlo, thi;
-  if (fa <= thr) tlo = 0.f;
+  if (!(fprime(0.f) < -tau)) tlo = 0.f;
+  else if (fprime(1.f) < -tau) tlo = 1.f;
   else {
-    float l = 0.f, g = tm;
-    for (int it = 0; it < 30; it++) { float md = 0.5f * (l + g); if (f(md) <= thr) g = md; else l = md; }
-    tlo = g;
+    float l = 0.f, g = 1.f;
+    for (int it = 0; it < 32; it++) {
+      const float md = 0.5f * (l + g);
+      if (fprime(md) < -tau) l = md; else g = md;
+    }
+    tlo = 0.5f * (l + g);
   }
-  if (fb <= thr) thi = 1.f;
+  if (!(fprime(1.f) > tau)) thi = 1.f;
+  else if (fprime(0.f) > tau) thi = 0.f;
   else {
-    float l = tm, g = 1.f;
-    for (int it = 0; it < 30; it++) { float md = 0.5f * (l + g); if (f(md) <= thr) l = md; else g = md; }
-    thi = l;
+    float l = 0.f, g = 1.f;
+    for (int it = 0; it < 32; it++) {
+      const float md = 0.5f * (l + g);
+      if (fprime(md) > tau) g = md; else l = md;
+    }
+    thi = 0.5f * (l + g);
   }
   float ts[4] = {0.f, 1.f, tlo, thi};
   bool keep[4] = {true, true, true, true};
-  if (fabsf(tlo) < kCapBoxDup || fabsf(tlo - 1.f) < kCapBoxDup) keep[2] = false;
-  if (fabsf(thi) < kCapBoxDup || fabsf(thi - 1.f) < kCapBoxDup || fabsf(thi - tlo) < kCapBoxDup)
+  if (thi - tlo < kCapBoxFlat) {
+    ts[2] = 0.5f * (tlo + thi);
     keep[3] = false;
+  }
+  for (int k = 2; k < 4; k++)
+    if (fabsf(ts[k]) < kCapBoxDup || fabsf(ts[k] - 1.f) < kCapBoxDup) keep[k] = false;
+  if (keep[2] && keep[3] && fabsf(ts[3] - ts[2]) < kCapBoxDup) keep[3] = false;
   float dep[4];
   for (int k = 0; k < 4; k++) {
-    dep[k] = f(ts[k]) - r;
+    float p[3] = {a[0] + ts[k] * u[0], a[1] + ts[k] * u[1], a[2] + ts[k] * u[2]};
+    dep[k] = box_sdf_only(c, R, h, p) - r;
     if (!(dep[k] < 0.f)) keep[k] = false;
   }
   int s0 = -1, s1 = -1;
@@ -794,42 +818,61 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
 }
 
 // --------------------------------------------------- A9: Newton solve (NW ch. 3, 6)
-// H = M + sum_{rows with e < 0} D J^T J (packed lower), factorised in place as L L^T
-// (right-looking, one column per barrier pair).  Returns false for a non-positive pivot.
-DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nrow) {
+// H = M + sum_{rows with e < 0} D J^T J (packed lower), factorised in place as L L^T.
+// Right-looking by columns; column j is used unscaled by its own trailing update and
+// scaled one column later, so each column costs one barrier.  When `y` is given the
+// forward solve L y = b (b overwritten) rides along.  Returns false for a non-positive
+// pivot.  `w` (nrow words) receives the active rows' weights D (0 when inactive).
+DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nrow,
+                          float* b = nullptr, float* y = nullptr) {
   const int nv = m.nv;
   const float* M = W + m.o_M;
   float* H = W + m.o_H;
   const float* J = W + m.o_J;
   const float* D = W + m.o_D;
   const float* e = W + m.o_e;
+  float* w = W + m.o_s;  // row weights; the line search rewrites this scratch later
+  for (int r = t.lane; r < nrow; r += t.T) w[r] = e[r] < 0.f ? D[r] : 0.f;
+  t.sync();
   for (int k = t.lane; k < m.ntri; k += t.T) {
     int i, j;
     tri_unrank(k, i, j);
     float v = M[k];
-    for (int r = 0; r < nrow; r++) {
-      if (e[r] < 0.f) v += D[r] * J[r * nv + i] * J[r * nv + j];
-    }
+    for (int r = 0; r < nrow; r++) v += w[r] * J[r * nv + i] * J[r * nv + j];
     H[k] = v;
   }
   t.sync();
   bool ok = true;
-  for (int j = 0; j < nv; j++) {
-    const float piv = H[tri(j, j)];
-    ok = ok && (piv > 0.f);
-    const float dj = sqrtf(fmaxf(piv, 1e-30f));
-    const float inv = 1.f / dj;
-    for (int i = j + 1 + t.lane; i < nv; i += t.T) H[tri(i, j)] *= inv;
-    t.sync();
-    if (t.lane == 0) H[tri(j, j)] = dj;
-    const int n2 = nv - j - 1;
-    const int npr = n2 * (n2 + 1) / 2;
-    for (int p = t.lane; p < npr; p += t.T) {
-      int bi, ai;
-      tri_unrank(p, bi, ai);
-      const int i = j + 1 + bi, k = j + 1 + ai;
-      H[tri(i, k)] -= H[tri(i, j)] * H[tri(k, j)];
+  float dlast = 1.f, invlast = 1.f;  // column j - 1, scaled during column j
+  for (int j = 0; j <= nv; j++) {
+    float dj = 1.f, inv = 1.f;
+    if (j < nv) {
+      const float piv = H[tri(j, j)];
+      ok = ok && (piv > 0.f);
+      dj = sqrtf(fmaxf(piv, 1e-30f));
+      inv = 1.f / dj;
+      const float inv2 = inv * inv;
+      const int n2 = nv - j - 1;
+      const int npr = n2 * (n2 + 1) / 2;
+      for (int p = t.lane; p < npr; p += t.T) {
+        int bi, ai;
+        tri_unrank(p, bi, ai);
+        const int i = j + 1 + bi, k = j + 1 + ai;
+        H[tri(i, k)] -= H[tri(i, j)] * H[tri(k, j)] * inv2;
+      }
+      if (y) {
+        const float yj = b[j] * inv;
+        for (int i = j + 1 + t.lane; i < nv; i += t.T) b[i] -= H[tri(i, j)] * inv * yj;
+        if (t.lane == 0) y[j] = yj;
+      }
     }
+    if (j >= 1) {
+      const int c = j - 1;
+      for (int i = c + 1 + t.lane; i < nv; i += t.T) H[tri(i, c)] *= invlast;
+      if (t.lane == 0) H[tri(c, c)] = dlast;
+    }
+    dlast = dj;
+    invlast = inv;
     t.sync();
   }
   return ok;
@@ -847,6 +890,19 @@ DEV void cholesky_solve(const DevModel& m, float* W, const Team& t, const float*
     }
     for (int i = nv - 1; i >= 0; i--) {
       float v = x[i];
+      for (int k = i + 1; k < nv; k++) v -= H[tri(k, i)] * x[k];
+      x[i] = v / H[tri(i, i)];
+    }
+  }
+  t.sync();
+}
+// back substitution L^T x = y (one lane; x and y may alias)
+DEV void cholesky_back(const DevModel& m, float* W, const Team& t, const float* y, float* x) {
+  const float* H = W + m.o_H;
+  const int nv = m.nv;
+  if (t.lane == 0) {
+    for (int i = nv - 1; i >= 0; i--) {
+      float v = y[i];
       for (int k = i + 1; k < nv; k++) v -= H[tri(k, i)] * x[k];
       x[i] = v / H[tri(i, i)];
     }
@@ -918,9 +974,10 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int ite
       }
       g[i] = v;
     }
-    if (!hessian_cholesky(m, W, t, nrow)) { status |= 4; break; }
-    // ---- delta = -H^-1 g
-    cholesky_solve(m, W, t, g, d, -1.f);
+    for (int i = t.lane; i < nv; i += t.T) d[i] = -g[i];
+    // ---- delta = -H^-1 g: forward solve fused into the factorisation, then back
+    if (!hessian_cholesky(m, W, t, nrow, d, tmp)) { status |= 4; break; }
+    cholesky_back(m, W, t, tmp, d);
     // ---- line search quantities
     float gd = 0.f, dMd = 0.f, dMr = 0.f;
     for (int i = t.lane; i < nv; i += t.T) {
@@ -1073,8 +1130,13 @@ DEV void world_step(const DevModel& m, float* W, const Team& t, const float* ctr
   MJH_MARK(1);
   backward_and_mass(m, W, t);
   MJH_MARK(2);
-  ltdl_factor(m, W, t);
-  ltdl_solve(m, W, t, W + m.o_frc, W + m.o_a0);
+  {
+    float* a0 = W + m.o_a0;
+    const float* frc = W + m.o_frc;
+    for (int i = t.lane; i < m.nv; i += t.T) a0[i] = frc[i];
+  }
+  ltdl_factor(m, W, t, W + m.o_a0);  // also solves L^T y = frc in place
+  ltdl_solve(m, W, t, nullptr, W + m.o_a0, true);
   MJH_MARK(3);
   collide_candidates(m, W, t);
   select_contacts(m, W, t, status);

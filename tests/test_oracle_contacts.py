@@ -212,9 +212,44 @@ def test_capsule_lying_on_box_gives_two_end_contacts():
     qp = two_body_qpos([0.1, 0.0, 0.039], q, [0, 0, 0], [1, 0, 0, 0])
     c = _contacts(m, qp)
     assert len(c) == 2
-    # outside the face the SDF is smooth at the edge, so the crossing is only
-    # located to about sqrt(2 * 0.009 * eps) along the segment
-    assert np.allclose(sorted(c[:, 1]), [0.06, 0.1], atol=1e-4)
+    # the flat stretch over the face ends where the distance starts to grow at the edge
+    assert np.allclose(sorted(c[:, 1]), [0.06, 0.1], atol=1e-6)
+
+
+def test_capsule_box_rounded_edge_gives_one_closest_point():
+    """A capsule passing at an angle beside a box edge touches it once, at the closest
+    point of the segment to the box (checked by a refined dense search)."""
+    half = (0.05, 0.05, 0.05)
+    m = robots.two_bodies("capsule", "box", (0.01, 0.04), half)
+    rng = np.random.default_rng(9)
+    done = 0
+    for _ in range(50):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        q = np.array(robots.quat_z_to(d))
+        corner = np.array([0.05, 0.05, rng.uniform(-0.03, 0.03)])  # on the +x+y edge
+        off = np.array([1.0, 1.0, 0.0]) / np.sqrt(2) * 0.008
+        center = corner + off + d * rng.uniform(-0.02, 0.02)
+        qp = two_body_qpos(center, q, [0, 0, 0], [1, 0, 0, 0])
+        c = _contacts(m, qp)
+        a = center - 0.04 * d
+        u = 0.08 * d
+        ts = np.linspace(0, 1, 20001)
+        P = a[None] + ts[:, None] * u[None]
+        o = np.maximum(np.abs(P) - np.array(half), 0)
+        dist = np.linalg.norm(o, axis=1)
+        k = int(np.argmin(dist))
+        if k in (0, len(ts) - 1) or np.all(np.abs(P[k]) <= half) or dist[k] - 0.01 > -1e-4:
+            continue  # want an interior, outside-the-box, penetrating closest point
+        interior = [row for row in c if row[17] >= 2]
+        assert len(interior) == 1
+        pt = P[k]
+        nb = o[k] * np.sign(pt) / dist[k]
+        expect = pt - 0.5 * (0.01 + dist[k]) * nb
+        assert np.allclose(interior[0][1:4], expect, atol=2e-6)
+        assert np.allclose(interior[0][4:7], -nb, atol=1e-3)
+        done += 1
+    assert done >= 5
 
 
 # ------------------------------------------------------------------ frame C10
