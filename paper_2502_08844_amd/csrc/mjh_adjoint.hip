@@ -21,6 +21,7 @@
 
 #include "mjh_adjoint.h"
 #include "mjh_device.h"
+#include "mjh_kernels.h"
 
 namespace mjh {
 
@@ -664,13 +665,14 @@ DEV void load_state(const DevModel& m, float* W, const Team& t, const float* src
 
 __global__ void __launch_bounds__(kAdjBlock) rollout_fwd_kernel(RolloutArgs A) {
   extern __shared__ float lds[];
+  const DevModel& m = A.m;
+  load_pair_table(m, (unsigned*)lds);
   const int T = A.team;
   const int team = threadIdx.x / T;
   const int w = blockIdx.x * (blockDim.x / T) + team;
   if (w >= A.nworld) return;
-  const DevModel& m = A.m;
-  const Team t{(int)threadIdx.x - team * T, T};
-  float* W = lds + (size_t)team * m.lds_words;
+  const Team t{(int)threadIdx.x - team * T, T, (const unsigned short*)lds};
+  float* W = lds + table_words(m.ntri) + (size_t)team * m.lds_words;
   const int ns = m.nq + 2 * m.nv;
   world_init(m, W, t);
   const float* src0 = nullptr;
@@ -710,13 +712,14 @@ __global__ void __launch_bounds__(kAdjBlock) rollout_fwd_kernel(RolloutArgs A) {
 
 __global__ void __launch_bounds__(kAdjBlock) rollout_bwd_kernel(RolloutArgs A) {
   extern __shared__ float lds[];
+  const DevModel& m = A.m;
+  load_pair_table(m, (unsigned*)lds);
   const int T = A.team;
   const int team = threadIdx.x / T;
   const int w = blockIdx.x * (blockDim.x / T) + team;
   if (w >= A.nworld) return;
-  const DevModel& m = A.m;
-  const Team t{(int)threadIdx.x - team * T, T};
-  float* W = lds + (size_t)team * m.lds_words;
+  const Team t{(int)threadIdx.x - team * T, T, (const unsigned short*)lds};
+  float* W = lds + table_words(m.ntri) + (size_t)team * m.lds_words;
   const int ns = m.nq + 2 * m.nv;
   world_init(m, W, t);
   const float dl = A.dloss[w];
@@ -836,7 +839,8 @@ mjh_status adjoint_forward(AdjointState** stp, const DevModel& m, int team, int 
   A.tape_ckpt = st->tape_ckpt; A.tape_seg = st->tape_seg; A.loss = loss; A.status = st->status;
   st->have_fwd = false;
   if (nworld == 0) { st->have_fwd = true; return MJH_OK; }
-  const size_t lds = (size_t)(kAdjBlock / team) * m.lds_words * sizeof(float);
+  const size_t lds =
+      ((size_t)table_words(m.ntri) + (size_t)(kAdjBlock / team) * m.lds_words) * sizeof(float);
   hipError_t e = hipFuncSetAttribute((const void*)rollout_fwd_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e == hipSuccess)
@@ -860,7 +864,8 @@ mjh_status adjoint_backward(AdjointState* st, const float* dloss, float* grad_qv
   A.grad_qvel0 = grad_qvel0;
   A.grad_ctrl = grad_ctrl;
   if (A.nworld == 0) return MJH_OK;
-  const size_t lds = (size_t)(kAdjBlock / A.team) * A.m.lds_words * sizeof(float);
+  const size_t lds =
+      ((size_t)table_words(A.m.ntri) + (size_t)(kAdjBlock / A.team) * A.m.lds_words) * sizeof(float);
   hipLaunchKernelGGL(rollout_bwd_kernel, dim3(blocks_for(A.nworld, A.team)), dim3(kAdjBlock), lds,
                      stream, A);
   hipError_t e = hipGetLastError();

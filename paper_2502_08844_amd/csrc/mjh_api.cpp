@@ -235,6 +235,15 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
     for (int p = h.body_parent[b]; p > 0; p = h.body_parent[p])
       if (body_dofnum[p] > 0) { dof_parent[k] = body_dofadr[p] + body_dofnum[p] - 1; break; }
   }
+  // packed lower-triangle index p = b (b + 1) / 2 + a -> 16-bit entry (b << 8) | a, two
+  // entries per 32-bit word (entry 2k in the low half)
+  std::vector<uint16_t> tri_entry;
+  for (int b = 0; b < h.nv; b++)
+    for (int a = 0; a <= b; a++) tri_entry.push_back((uint16_t)((b << 8) | a));
+  if (tri_entry.size() & 1) tri_entry.push_back(0);
+  std::vector<uint32_t> tri_pair(tri_entry.size() / 2);
+  for (size_t k = 0; k < tri_pair.size(); k++)
+    tri_pair[k] = (uint32_t)tri_entry[2 * k] | ((uint32_t)tri_entry[2 * k + 1] << 16);
   std::vector<int> anc_start(h.nv + 1, 0), anc_list, mpair;
   for (int k = 0; k < h.nv; k++) {
     anc_start[k] = (int)anc_list.size();
@@ -326,6 +335,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   pk.add(anc_list, &d.anc_list);
   pk.add(mpair, &d.mpair);
   pk.add(body_dofmask, &d.body_dofmask);
+  pk.add(tri_pair, &d.tri_pair);
   pk.add(h.geom_type, &d.geom_type);
   pk.add(h.geom_body, &d.geom_body);
   pk.add(h.pair_g1, &d.pair_g1);
@@ -363,11 +373,12 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   pk.add(aqd, &d.act_qdef);
   pk.add(q0, &d.qpos0);
   pk.add(invw, const_cast<const float**>(&d.body_invweight));
-  // on-chip layout (4-byte words, every block 16-byte aligned)
+  // on-chip layout in 4-byte words, regions packed back to back (every LDS access is a
+  // scalar 32-bit one, so no region needs more alignment)
   int off = 0;
   auto take = [&](int words) {
     const int o = off;
-    off += (words + 3) & ~3;
+    off += words;
     return o;
   };
   const int nb = h.nbody, nv = h.nv, nr = d.nrowmax;
@@ -467,6 +478,7 @@ struct mjh_batch {
   DevTask* d_tasks = nullptr;
   int ntask = 0;
   int block = 64;
+  int tab_words = 0;
   size_t lds_bytes = 0;
   bool dirty = true;
   hipGraph_t graph = nullptr;
@@ -489,11 +501,14 @@ static mjh_status fail(mjh_ctx* ctx, mjh_status code, const std::string& msg) {
   return code;
 }
 
-// worlds per work-group for a group's launch shape, bounded by the LDS budget
-static int worlds_per_block(const mjh_ctx* ctx, const ModelRec& mr, int team, int block) {
+// worlds per work-group for a group's launch shape, bounded by the LDS budget (the
+// work-group also holds a triangular pair table of tab_words words)
+static int worlds_per_block(const mjh_ctx* ctx, const ModelRec& mr, int team, int block,
+                            int tab_words) {
   int wpb = std::max(1, block / team);
   const size_t per = (size_t)mr.dm.lds_words * sizeof(float);
-  while (wpb > 1 && (size_t)wpb * per > ctx->lds_limit) wpb--;
+  const size_t tab = (size_t)tab_words * sizeof(float);
+  while (wpb > 1 && tab + (size_t)wpb * per > ctx->lds_limit) wpb--;
   return wpb;
 }
 
@@ -506,6 +521,9 @@ static mjh_status sync_tables(mjh_batch* b) {
   std::vector<Tk> tasks;
   int block = 0;
   size_t lds = 0;
+  int tab_words = 0;
+  for (const GroupRec& gr : b->groups)
+    if (gr.nworld > 0) tab_words = std::max(tab_words, table_words(ctx->models[gr.model]->dm.ntri));
   for (size_t g = 0; g < b->groups.size(); g++) {
     const GroupRec& gr = b->groups[g];
     const ModelRec& mr = *ctx->models[gr.model];
@@ -515,12 +533,13 @@ static mjh_status sync_tables(mjh_batch* b) {
     x.ctrl = gr.ctrl; x.con_out = gr.con_out; x.ncon_out = gr.ncon_out;
     x.nworld = gr.nworld; x.ctrl_nstep = gr.ctrl_nstep; x.team = gr.team;
     if (gr.nworld == 0) continue;
-    const int wpb = worlds_per_block(ctx, mr, gr.team, gr.block);
+    const int wpb = worlds_per_block(ctx, mr, gr.team, gr.block, tab_words);
     const size_t per = (size_t)mr.dm.lds_words * sizeof(float);
-    if (per > ctx->lds_limit)
+    const size_t tab = (size_t)tab_words * sizeof(float);
+    if (tab + per > ctx->lds_limit)
       return fail(ctx, MJH_EUNSUPPORTED, "one world's working set exceeds the LDS limit");
     block = std::max(block, wpb * gr.team);
-    lds = std::max(lds, (size_t)wpb * per);
+    lds = std::max(lds, tab + (size_t)wpb * per);
     for (int w0 = 0; w0 < gr.nworld; w0 += wpb) {
       Tk t;
       t.t.group = (int)g; t.t.w0 = w0; t.t.nw = std::min(wpb, gr.nworld - w0); t.t.pad_ = 0;
@@ -539,6 +558,7 @@ static mjh_status sync_tables(mjh_batch* b) {
   if (!dg.empty()) MJH_HIP(hipMemcpy(b->d_groups, dg.data(), dg.size() * sizeof(DevGroup), hipMemcpyHostToDevice));
   if (!dt.empty()) MJH_HIP(hipMemcpy(b->d_tasks, dt.data(), dt.size() * sizeof(DevTask), hipMemcpyHostToDevice));
   b->ntask = (int)dt.size();
+  b->tab_words = tab_words;
   b->block = std::max(block, 16);
   b->lds_bytes = lds;
   b->dirty = false;
@@ -591,7 +611,7 @@ mjh_status mjh_model_upload(mjh_ctx* ctx, const void* blob, size_t nbytes, int32
   Packer pk;
   st = compile_model(rec->h, *rec, pk, err);
   if (st != MJH_OK) return fail(ctx, st, err);
-  if ((size_t)rec->dm.lds_words * 4 > ctx->lds_limit)
+  if ((size_t)(rec->dm.lds_words + table_words(rec->dm.ntri)) * 4 > ctx->lds_limit)
     return fail(ctx, MJH_EUNSUPPORTED, "model working set exceeds the device's LDS per work-group");
   MJH_HIP(hipSetDevice(ctx->device));
   MJH_HIP(hipMalloc(&rec->dbuf, pk.bytes.size()));
@@ -732,7 +752,7 @@ mjh_status mjh_step(mjh_batch* b, int32_t nstep, void* stream) {
   if (st != MJH_OK) return st;
   if (nstep == 0 || b->ntask == 0) return MJH_OK;
   MJH_HIP(launch_step(b->d_groups, b->d_tasks, b->ntask, nstep, b->block, b->lds_bytes,
-                      static_cast<hipStream_t>(stream)));
+                      b->tab_words, static_cast<hipStream_t>(stream)));
   return MJH_OK;
 }
 
@@ -748,7 +768,8 @@ mjh_status mjh_graph_capture(mjh_batch* b, int32_t nstep, void* stream) {
   if (b->graph_exec) { (void)hipGraphExecDestroy(b->graph_exec); b->graph_exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   MJH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  hipError_t le = launch_step(b->d_groups, b->d_tasks, b->ntask, nstep, b->block, b->lds_bytes, s);
+  hipError_t le = launch_step(b->d_groups, b->d_tasks, b->ntask, nstep, b->block, b->lds_bytes,
+                              b->tab_words, s);
   hipGraph_t g = nullptr;
   hipError_t ce = hipStreamEndCapture(s, &g);
   if (le != hipSuccess || ce != hipSuccess) {
@@ -887,7 +908,8 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
         for (int rep = 0; rep < 2; rep++) {  // first run warms caches
           if (restore() != MJH_OK) { st = MJH_EHIP; break; }
           MJH_HIP(hipEventRecord(e0, nullptr));
-          MJH_HIP(launch_step(b->d_groups, b->d_tasks, b->ntask, nstep_probe, b->block, b->lds_bytes, nullptr));
+          MJH_HIP(launch_step(b->d_groups, b->d_tasks, b->ntask, nstep_probe, b->block, b->lds_bytes,
+                              b->tab_words, nullptr));
           MJH_HIP(hipEventRecord(e1, nullptr));
           MJH_HIP(hipEventSynchronize(e1));
           MJH_HIP(hipEventElapsedTime(&ms, e0, e1));

@@ -24,8 +24,15 @@ namespace mjh {
 
 // ------------------------------------------------------------------- team helpers
 struct Team {
-  int lane;  // 0 .. T-1
-  int T;     // lanes per world: 16, 32 or 64
+  int lane;       // 0 .. T-1
+  int T;          // lanes per world: 16, 32 or 64
+  const unsigned short* tp;  // triangular pair table in LDS: tp[p] = (b << 8) | a, p = b(b+1)/2 + a
+  // p -> (b, a) with 0 <= a <= b
+  DEV void unrank(int p, int& b, int& a) const {
+    const int v = tp[p];
+    b = v >> 8;
+    a = v & 0xff;
+  }
   // wavefront-level barrier: orders LDS traffic of all lanes of the wave
   DEV void sync() const {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -146,15 +153,6 @@ DEV float dot6(const float* a, const float* b) {
 // packed lower-triangular index of a symmetric matrix
 DEV int sym(int i, int j) { return i >= j ? (i * (i + 1) >> 1) + j : (j * (j + 1) >> 1) + i; }
 DEV int tri(int i, int j) { return (i * (i + 1) >> 1) + j; }  // requires i >= j
-// triangular pair index p -> (b, a) with 0 <= a <= b, p = b (b + 1) / 2 + a
-DEV void tri_unrank(int p, int& b, int& a) {
-  int r = (int)((sqrtf(8.f * (float)p + 1.f) - 1.f) * 0.5f);
-  while ((r + 1) * (r + 2) / 2 <= p) r++;
-  while (r * (r + 1) / 2 > p) r--;
-  b = r;
-  a = p - r * (r + 1) / 2;
-}
-
 // ------------------------------------------------------------ A0: actuation
 // per dof: motor tau = gear u; position actuator (eq. pd_mapping)
 // tau = kp (q_default + gear u - q) - kd qdot; joint damping -b qdot.  Controls are
@@ -366,7 +364,7 @@ DEV void ltdl_factor(const DevModel& m, float* W, const Team& t, float* y = null
       const int npr = na * (na + 1) / 2;
       for (int p = t.lane; p < npr; p += t.T) {
         int bi, ai;
-        tri_unrank(p, bi, ai);
+        t.unrank(p, bi, ai);
         const int i = m.anc_list[a0 + ai];  // nearer ancestor (larger index)
         const int j = m.anc_list[a0 + bi];  // j ancestor-or-self of i
         H[tri(i, j)] -= H[tri(k, i)] * H[tri(k, j)] * inv;
@@ -836,7 +834,7 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nrow,
   t.sync();
   for (int k = t.lane; k < m.ntri; k += t.T) {
     int i, j;
-    tri_unrank(k, i, j);
+    t.unrank(k, i, j);
     float v = M[k];
     for (int r = 0; r < nrow; r++) v += w[r] * J[r * nv + i] * J[r * nv + j];
     H[k] = v;
@@ -856,7 +854,7 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nrow,
       const int npr = n2 * (n2 + 1) / 2;
       for (int p = t.lane; p < npr; p += t.T) {
         int bi, ai;
-        tri_unrank(p, bi, ai);
+        t.unrank(p, bi, ai);
         const int i = j + 1 + bi, k = j + 1 + ai;
         H[tri(i, k)] -= H[tri(i, j)] * H[tri(k, j)] * inv2;
       }
@@ -1145,6 +1143,13 @@ DEV void world_step(const DevModel& m, float* W, const Team& t, const float* ctr
   MJH_MARK(5);
   newton(m, W, t, status, iters);
   MJH_MARK(6);
+}
+
+// copy a model's triangular pair table to the head of the work-group's LDS (all
+// threads of the work-group take part; call before any team leaves)
+DEV void load_pair_table(const DevModel& m, unsigned* tab) {
+  for (int k = threadIdx.x; k < (m.ntri + 1) / 2; k += blockDim.x) tab[k] = m.tri_pair[k];
+  __syncthreads();
 }
 
 // initialise the world's constant LDS slots (world body, zero pattern of M)

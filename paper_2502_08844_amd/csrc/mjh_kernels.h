@@ -8,9 +8,12 @@ namespace mjh {
 
 constexpr int kMaxBlock = 256;  // threads per work-group of the step kernel
 
+// LDS words of a work-group's triangular pair table (16-byte aligned)
+__host__ __device__ inline int table_words(int ntri) { return ((ntri + 1) / 2 + 3) & ~3; }
+
 // Launch the step kernel: one work-group of `block` threads per task.
 hipError_t launch_step(const DevGroup* groups, const DevTask* tasks, int ntask, int nstep,
-                       int block, size_t lds_bytes, hipStream_t stream);
+                       int block, size_t lds_bytes, int tab_words, hipStream_t stream);
 // Allow the step kernel `bytes` of dynamic LDS per work-group.
 hipError_t set_step_lds_limit(size_t bytes);
 // Compute body_invweight of a freshly uploaded model (one work-group).

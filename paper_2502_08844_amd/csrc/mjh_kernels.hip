@@ -19,9 +19,10 @@ constexpr int kPhaseWorlds = 8192;
 __device__ long long g_phase_cycles[kPhaseWorlds * 8];
 #endif
 
-__device__ void run_worlds(const DevGroup& G, float* W, int world, int nstep, int lane, int T) {
+__device__ void run_worlds(const DevGroup& G, float* W, int world, int nstep, int lane, int T,
+                           const unsigned short* tab) {
   const DevModel& m = G.m;
-  const Team t{lane, T};
+  const Team t{lane, T, tab};
   world_init(m, W, t);
   const int nq = m.nq, nv = m.nv, nu = m.nu;
   const size_t w = (size_t)world;
@@ -69,26 +70,28 @@ __device__ void run_worlds(const DevGroup& G, float* W, int world, int nstep, in
 
 __global__ void __launch_bounds__(kMaxBlock, 4)
 mjh_step_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__ tasks,
-                int nstep) {
+                int nstep, int tab_words) {
   extern __shared__ float lds[];
   const DevTask tk = tasks[blockIdx.x];
   const DevGroup& G = groups[tk.group];
+  load_pair_table(G.m, (unsigned*)lds);
   const int T = G.team;
   const int team = threadIdx.x / T;
   if (team >= tk.nw) return;
-  float* W = lds + (size_t)team * G.m.lds_words;
+  float* W = lds + tab_words + (size_t)team * G.m.lds_words;
   const int lane = threadIdx.x - team * T;
   const int world = tk.w0 + team;
-  run_worlds(G, W, world, nstep, lane, T);
+  run_worlds(G, W, world, nstep, lane, T, (const unsigned short*)lds);
 }
 
 // Translational inverse weight of every body at qpos0:
 //   w(b) = trace(J_com(b) M^-1 J_com(b)^T) / 3,
 // one work-group of 64 lanes evaluating the model once.
-__global__ void __launch_bounds__(64) mjh_invweight_kernel(DevModel m) {
+__global__ void __launch_bounds__(64) mjh_invweight_kernel(DevModel m, int tab_words) {
   extern __shared__ float lds[];
-  float* W = lds;
-  const Team t{(int)threadIdx.x, 64};
+  load_pair_table(m, (unsigned*)lds);
+  float* W = lds + tab_words;
+  const Team t{(int)threadIdx.x, 64, (const unsigned short*)lds};
   world_init(m, W, t);
   for (int i = t.lane; i < m.nq; i += t.T) W[m.o_qpos + i] = m.qpos0[i];
   t.sync();
@@ -130,10 +133,10 @@ __global__ void __launch_bounds__(64) mjh_invweight_kernel(DevModel m) {
 
 // ------------------------------------------------------------- host-side launchers
 hipError_t launch_step(const DevGroup* groups, const DevTask* tasks, int ntask, int nstep,
-                       int block, size_t lds_bytes, hipStream_t stream) {
+                       int block, size_t lds_bytes, int tab_words, hipStream_t stream) {
   if (ntask <= 0) return hipSuccess;
   hipLaunchKernelGGL(mjh_step_kernel, dim3(ntask), dim3(block), lds_bytes, stream, groups,
-                     tasks, nstep);
+                     tasks, nstep, tab_words);
   return hipGetLastError();
 }
 
@@ -143,11 +146,12 @@ hipError_t set_step_lds_limit(size_t bytes) {
 }
 
 hipError_t launch_invweight(const DevModel& m, hipStream_t stream) {
-  const size_t lds = (size_t)m.lds_words * sizeof(float);
+  const int tab = table_words(m.ntri);
+  const size_t lds = (size_t)(tab + m.lds_words) * sizeof(float);
   hipError_t e = hipFuncSetAttribute((const void*)mjh_invweight_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(mjh_invweight_kernel, dim3(1), dim3(64), lds, stream, m);
+  hipLaunchKernelGGL(mjh_invweight_kernel, dim3(1), dim3(64), lds, stream, m, tab);
   return hipGetLastError();
 }
 

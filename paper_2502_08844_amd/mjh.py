@@ -98,6 +98,7 @@ class Context:
         if rc != OK:
             raise MjhError(rc, f"mjh_create({device}) failed")
         self._h = h
+        self._free = _lib.mjh_destroy
         self.device = device
 
     def check(self, rc: int):
@@ -105,8 +106,10 @@ class Context:
             raise MjhError(rc, _lib.mjh_last_error(self._h).decode())
 
     def close(self):
+        # the library handle is held by the instance: module globals may already be
+        # cleared when this runs at interpreter exit
         if getattr(self, "_h", None):
-            _lib.mjh_destroy(self._h)
+            self._free(self._h)
             self._h = None
 
     def __del__(self):
@@ -163,12 +166,13 @@ class Batch:
         self.models = models
         self.counts = counts
         self._h = handle
+        self._free = _lib.mjh_world_free
         self._state = [None] * len(models)
         self._io = [None] * len(models)
 
     def close(self):
         if getattr(self, "_h", None):
-            _lib.mjh_world_free(self._h)
+            self._free(self._h)
             self._h = None
 
     def __del__(self):
