@@ -32,7 +32,13 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-worlds", type=int, default=8192)
-    ap.add_argument("--cpu-sample-steps", type=int, default=40)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="run the reference on the host in chunks of 40 steps until this "
+                         "much time has been spent")
+    ap.add_argument("--no-rollout", action="store_true",
+                    help="skip the adjoint-rollout comparison (1024 worlds, horizon 64)")
+    ap.add_argument("--no-hetero", action="store_true",
+                    help="skip the heterogeneous-batch comparison")
     ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a reference "
@@ -48,14 +54,142 @@ def algorithmic_flops_per_world_step(model, qpos, qvel, ctrl):
     return o.count_flops(qpos, qvel, None, ctrl)
 
 
-def cpu_baseline(model, qpos, qvel, ctrl, nthreads):
+def cpu_baseline(kind, model, qpos, qvel, nthreads, seconds, seed, chunk=40, max_chunks=200):
+    """The FP64 reference stepping the same kind of worlds on the host: chunks of `chunk`
+    steps with fresh controls, state carried over, until `seconds` have been spent."""
     import oracle
+    from paper_2502_08844_amd.synth import inputs
     o = oracle.Oracle(model)
-    nw, ns = qpos.shape[0], ctrl.shape[0]
+    nw = qpos.shape[0]
+    q, v, ws = qpos.copy(), qvel.copy(), None
+    spent, steps = 0.0, 0
+    for c in range(max_chunks):
+        u = inputs.controls(kind, model, nw, chunk, seed=seed + 1000 + c)
+        t0 = time.perf_counter()
+        out = o.step(q, v, ws, u, nstep=chunk, nthreads=nthreads)
+        spent += time.perf_counter() - t0
+        steps += chunk
+        q, v, ws = out["qpos"], out["qvel"], out["qacc_ws"]
+        if spent >= seconds:
+            break
+    return nw * steps / spent, spent, steps
+
+
+def timed(fn, stream, reps):
+    """Median event-timed duration (ms) of fn() on `stream` over reps runs."""
+    import torch
+    ms = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    return sorted(ms)[len(ms) // 2]
+
+
+def rollout_compare(ctx, seed, nw=1024, horizon=64, ckpt=8, reps=3):
+    """Adjoint rollout (forward with checkpoints + reverse sweep) against the plain step
+    on the same worlds: 1024 quadrupeds, horizon 64, checkpoints every 8 steps."""
+    import torch
+    from paper_2502_08844_amd import mjh
+    from paper_2502_08844_amd.synth import inputs, robots
+    m = robots.quadruped()
+    gm = ctx.model_upload(m)
+    qp, qv = inputs.initial_state("quadruped", m, nw, seed=seed)
+    rng = inputs.rng(seed, 7)
+    u = torch.tensor(inputs.f32(rng.uniform(-0.5, 0.5, size=(horizon, nw, m.nu))),
+                     device="cuda").contiguous()
+    stream = torch.cuda.current_stream()
+    plain = mjh.World(ctx, gm, nw, qpos=qp, qvel=qv)
+    q0, v0 = plain.qpos.clone(), plain.qvel.clone()
+    plain.batch.bind_io(0, u)
+
+    def run_plain():
+        plain.qpos.copy_(q0); plain.qvel.copy_(v0); plain.qacc_ws.zero_()
+        plain.batch.step(horizon, stream)
+    run_plain()
+    t_plain = timed(run_plain, stream, reps)
+    w = mjh.World(ctx, gm, nw, qpos=qp, qvel=qv)
+    loss = torch.empty(nw, device="cuda")
+    dloss = torch.ones(nw, device="cuda")
+    gq = torch.empty(nw, m.nv, device="cuda")
+    gu = torch.empty_like(u)
+
+    def run_fwd():
+        w.qpos.copy_(q0); w.qvel.copy_(v0); w.qacc_ws.zero_()
+        w.batch.rollout_fwd(horizon, ckpt, u, 2, 0.3, 1e-3, loss, stream)
+
+    def run_bwd():
+        w.batch.rollout_bwd(dloss, gq, gu, stream)
+    run_fwd(); run_bwd()
+    t_fwd = timed(run_fwd, stream, reps)
+    t_bwd = timed(run_bwd, stream, reps)
+    ws = nw * horizon
+    return {"workload": f"quadruped {nw} worlds, horizon {horizon}, checkpoints every {ckpt}",
+            "plain_world_steps_per_s": round(ws / (t_plain * 1e-3), 1),
+            "fwd_bwd_rollout_steps_per_s": round(ws / ((t_fwd + t_bwd) * 1e-3), 1),
+            "fwd_ms": round(t_fwd, 3), "bwd_ms": round(t_bwd, 3), "plain_ms": round(t_plain, 3),
+            "fwd_bwd_over_plain_time": round((t_fwd + t_bwd) / t_plain, 2)}
+
+
+def hetero_compare(ctx, seed, nstep=500, reps=3):
+    """4096 quadruped + 2048 humanoid + 2048 hand worlds in one autotuned launch replayed
+    from a HIP graph, against the three models stepped by their own default launches."""
+    import torch
+    from paper_2502_08844_amd import mjh
+    from paper_2502_08844_amd.synth import inputs, robots
+    spec = [("quadruped", 4096), ("humanoid", 2048), ("hand", 2048)]
+    stream = torch.cuda.current_stream()
+    worlds, ctrls, init = [], [], []
+    for k, (kind, nw) in enumerate(spec):
+        m = robots.WORKLOADS[kind]()
+        qp, qv = inputs.initial_state(kind, m, nw, seed=seed + k)
+        u = torch.tensor(inputs.controls(kind, m, nw, nstep, seed=seed + k), device="cuda")
+        w = mjh.World(ctx, ctx.model_upload(m), nw, qpos=qp, qvel=qv)
+        w.batch.bind_io(0, u.contiguous())
+        worlds.append(w); ctrls.append(u.contiguous()); init.append((w.qpos.clone(), w.qvel.clone()))
+    total = sum(nw for _, nw in spec) * nstep
+
+    def reset(ws):
+        for w, (q, v) in zip(ws, init):
+            w.qpos.copy_(q); w.qvel.copy_(v); w.qacc_ws.zero_()
+
+    def run_plain():
+        reset(worlds)
+        for w in worlds:
+            w.batch.step(nstep, stream)
+    run_plain()
+    t_plain = timed(run_plain, stream, reps)
+    het = ctx.world_alloc([w.model for w in worlds], [nw for _, nw in spec])
+    states = []
+    for g, w in enumerate(worlds):
+        st = (w.qpos.clone(), w.qvel.clone(), torch.zeros_like(w.qvel),
+              torch.zeros(w.nworld, dtype=torch.int32, device="cuda"))
+        het.bind_state(g, *st)
+        het.bind_io(g, ctrls[g])
+        states.append(st)
     t0 = time.perf_counter()
-    o.step(qpos.copy(), qvel.copy(), None, ctrl, nstep=ns, nthreads=nthreads)
-    dt = time.perf_counter() - t0
-    return nw * ns / dt, dt
+    het.autotune(20)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    gs = torch.cuda.Stream()
+    het.graph_capture(nstep, gs)
+
+    def run_graph():
+        for (q, v, a, _), (q0, v0) in zip(states, init):
+            q.copy_(q0); v.copy_(v0); a.zero_()
+        het.graph_launch(stream)
+    run_graph()
+    t_graph = timed(run_graph, stream, reps)
+    return {"workload": "4096 quadruped + 2048 humanoid + 2048 hand worlds x "
+                        f"{nstep} steps",
+            "graph_autotuned_world_steps_per_s": round(total / (t_graph * 1e-3), 1),
+            "per_model_default_world_steps_per_s": round(total / (t_plain * 1e-3), 1),
+            "speedup": round(t_plain / t_graph, 3),
+            "launch": {kind: list(het.get_launch(g)) for g, (kind, _) in enumerate(spec)},
+            "autotune_s": round(t_tune, 2)}
 
 
 def main():
@@ -144,7 +278,8 @@ def main():
             "flops_per_world_step": round(flops_ws, 1),
             "hbm_bytes_per_world_step": round(bytes_ws, 2),
             "hbm_frac": round(bytes_ws * nw * ns / (kavg * 1e-3) / 1e9 / HBM_PEAK_GBS, 8)}
-    out = {"metric": "world-steps/sec at 8192 quadruped worlds", "value": round(value, 1),
+    out = {"metric": "world-steps/sec at 8192 quadruped worlds; fwd+bwd rollout steps/sec vs plain",
+           "value": round(value, 1),
            "unit": "world-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -155,15 +290,20 @@ def main():
                       "launch": list(world.batch.get_launch(0)),
                       "status_nonzero_worlds": int(np.count_nonzero(status))},
            "roofline": roof}
+    del world, ctrl
+    if not args.no_rollout:
+        out["rollout"] = rollout_compare(ctx, args.seed)
+    if not args.no_hetero:
+        out["hetero"] = hetero_compare(ctx, args.seed)
     if not args.no_cpu_baseline:
         nthreads = min(os.cpu_count() or 1, 16)
-        cw, cs = args.cpu_sample_worlds, args.cpu_sample_steps
-        u = inputs.controls(kind, m, cw, cs, seed=args.seed)
-        rate, secs = cpu_baseline(m, qp[:cw], qv[:cw], u, nthreads)
+        cw = min(args.cpu_sample_worlds, nw)
+        rate, secs, cs = cpu_baseline(kind, m, qp[:cw], qv[:cw], nthreads, args.cpu_seconds,
+                                      args.seed)
         out["cpu_baseline"] = {"value": round(rate, 1), "unit": "world-steps/s",
                                "cores": nthreads, "kind": "oracle",
-                               "sample": f"{cw} quadruped worlds x {cs} steps, FP64, "
-                                         f"{secs:.1f} s"}
+                               "sample": f"{cw} quadruped worlds x {cs} steps (chunks of 40, "
+                                         f"fresh random PD targets), FP64, {secs:.1f} s"}
     print(json.dumps(out), flush=True)
 
 

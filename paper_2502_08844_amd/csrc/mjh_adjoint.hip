@@ -550,8 +550,8 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
           float off[3], anc[3], Rj[9];
           mv3(R, m.jnt_pos + 3 * j, off);
           for (int q = 0; q < 3; q++) anc[q] = pos[q] + off[q];
-          axis_rot(ax, qpos[qa], Rj);
-          mm3(Rj, R, R);
+          axis_rot(m.jnt_axis + 3 * j, qpos[qa], Rj);  // R Rot(a, q) = Rot(R a, q) R
+          mm3(R, Rj, R);
           mv3(R, m.jnt_pos + 3 * j, off);
           for (int q = 0; q < 3; q++) pos[q] = anc[q] - off[q];
         }

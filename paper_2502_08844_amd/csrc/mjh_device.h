@@ -21,6 +21,8 @@ namespace mjh {
 
 #define DEV __device__ __forceinline__
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
 
 // ------------------------------------------------------------------- team helpers
 struct Team {
@@ -39,25 +41,55 @@ struct Team {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  DEV float sum(float v) const {
-    for (int o = T >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, T);
+  // All-reductions over the team's lanes.  Within a 16-lane row they use DPP lane
+  // permutations (xor 1 and xor 2 by quad permutes, then the half-row and row mirrors);
+  // wider teams then combine row pairs and wave halves with the gfx950 permlane swaps.
+  // Every step combines a lane's value with its partner's by a commutative operation,
+  // so all lanes of the team end with bitwise the same result.  Every lane of the team
+  // must be active.
+  template <class Op>
+  DEV int allreduce(int v, Op op) const {
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false));  // row_mirror
+    if (T >= 32) {
+      const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+      v = op((int)r[0], (int)r[1]);
+    }
+    if (T == 64) {
+      const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+      v = op((int)r[0], (int)r[1]);
+    }
     return v;
   }
-  DEV float max(float v) const {
-    for (int o = T >> 1; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, T));
-    return v;
+  template <class Op>
+  DEV float allreducef(float v, Op op) const {
+    return __int_as_float(allreduce(__float_as_int(v), [&](int a, int b) {
+      return __float_as_int(op(__int_as_float(a), __int_as_float(b)));
+    }));
   }
-  DEV float min(float v) const {
-    for (int o = T >> 1; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, T));
-    return v;
-  }
-  DEV int isum(int v) const {
-    for (int o = T >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, T);
-    return v;
-  }
-  DEV int ior(int v) const {
-    for (int o = T >> 1; o > 0; o >>= 1) v |= __shfl_xor(v, o, T);
-    return v;
+  DEV float sum(float v) const { return allreducef(v, [](float a, float b) { return a + b; }); }
+  DEV float max(float v) const { return allreducef(v, [](float a, float b) { return fmaxf(a, b); }); }
+  DEV float min(float v) const { return allreducef(v, [](float a, float b) { return fminf(a, b); }); }
+  DEV int isum(int v) const { return allreduce(v, [](int a, int b) { return a + b; }); }
+  DEV int ior(int v) const { return allreduce(v, [](int a, int b) { return a | b; }); }
+  // the value of `v` held by lane `i` of this team (i uniform), read with v_readlane:
+  // one read per team of the wavefront, then each lane keeps its own team's
+  DEV float bcast(float v, int i) const {
+    const int base = (int)(threadIdx.x & 63) - lane;  // the team's first lane in the wave
+    const int iv = __float_as_int(v);
+    int r = __builtin_amdgcn_readlane(iv, i);
+    if (T == 32) {
+      const int r1 = __builtin_amdgcn_readlane(iv, i + 32);
+      r = base ? r1 : r;
+    } else if (T == 16) {
+      const int r1 = __builtin_amdgcn_readlane(iv, i + 16);
+      const int r2 = __builtin_amdgcn_readlane(iv, i + 32);
+      const int r3 = __builtin_amdgcn_readlane(iv, i + 48);
+      r = base == 0 ? r : base == 16 ? r1 : base == 32 ? r2 : r3;
+    }
+    return __int_as_float(r);
   }
   // exclusive prefix sum over the team's lanes
   DEV int exscan(int v) const {
@@ -150,9 +182,10 @@ DEV void inertia_mul(const float* I, const float* mv, float* f) {
 DEV float dot6(const float* a, const float* b) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3] + a[4] * b[4] + a[5] * b[5];
 }
-// packed lower-triangular index of a symmetric matrix
-DEV int sym(int i, int j) { return i >= j ? (i * (i + 1) >> 1) + j : (j * (j + 1) >> 1) + i; }
-DEV int tri(int i, int j) { return (i * (i + 1) >> 1) + j; }  // requires i >= j
+// packed lower-triangular index of a symmetric matrix (indices < 2^12, so the product
+// fits the full-rate 24-bit multiplier)
+DEV int tri(int i, int j) { return (__mul24(i, i + 1) >> 1) + j; }  // requires i >= j
+DEV int sym(int i, int j) { return i >= j ? tri(i, j) : tri(j, i); }
 // ------------------------------------------------------------ A0: actuation
 // per dof: motor tau = gear u; position actuator (eq. pd_mapping)
 // tau = kp (q_default + gear u - q) - kd qdot; joint damping -b qdot.  Controls are
@@ -254,12 +287,16 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* 
           crossm(V, S, Sd);
           for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel[da] + (qacc ? S[k] * qacc[da] : 0.f);
         } else {  // hinge
+          // Rotation about the world axis R a equals R Rot(a, q) with the body-frame
+          // axis a.  The second form builds the joint rotation from exact model data,
+          // so FP32 rounding only adds along a chain; rotating about the rounded world
+          // axis amplifies the frame error at every large-angle hinge.
           float ax[3], off[3], anc[3], Rj[9];
-          mv3(R, m.jnt_axis + 3 * j, ax);
           mv3(R, m.jnt_pos + 3 * j, off);
           for (int k = 0; k < 3; k++) anc[k] = pos[k] + off[k];
-          axis_rot(ax, qpos[qa], Rj);
-          mm3(Rj, R, R);
+          axis_rot(m.jnt_axis + 3 * j, qpos[qa], Rj);
+          mm3(R, Rj, R);
+          mv3(R, m.jnt_axis + 3 * j, ax);
           mv3(R, m.jnt_pos + 3 * j, off);
           for (int k = 0; k < 3; k++) pos[k] = anc[k] - off[k];
           S[0] = ax[0]; S[1] = ax[1]; S[2] = ax[2];
@@ -391,6 +428,28 @@ DEV void ltdl_factor(const DevModel& m, float* W, const Team& t, float* y = null
 DEV void ltdl_solve(const DevModel& m, float* W, const Team& t, const float* rhs, float* x,
                     bool half = false) {
   const float* H = W + m.o_H;
+  const int nv = m.nv;
+  if (nv <= t.T) {
+    // lane k holds entry k; each column's finished entry is broadcast from its lane and
+    // applied to the others.  Entries of H off the tree pattern are exact zeros, so
+    // the dense column updates equal the ancestor-list ones.
+    const int k = t.lane;
+    float acc = k < nv ? (half ? x[k] : rhs[k]) : 0.f;
+    if (!half) {
+      for (int j = nv - 1; j > 0; j--) {  // L^T y = rhs
+        const float yj = t.bcast(acc, j);
+        if (k < j) acc -= H[tri(j, k)] * yj;
+      }
+    }
+    if (k < nv) acc /= H[tri(k, k)];
+    for (int j = 0; j < nv - 1; j++) {  // L x = y / D
+      const float xj = t.bcast(acc, j);
+      if (k > j && k < nv) acc -= H[tri(k, j)] * xj;
+    }
+    if (k < nv) x[k] = acc;
+    t.sync();
+    return;
+  }
   if (t.lane == 0) {
     if (!half) {
       for (int i = 0; i < m.nv; i++) x[i] = rhs[i];
@@ -832,12 +891,42 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nrow,
   float* w = W + m.o_s;  // row weights; the line search rewrites this scratch later
   for (int r = t.lane; r < nrow; r += t.T) w[r] = e[r] < 0.f ? D[r] : 0.f;
   t.sync();
-  for (int k = t.lane; k < m.ntri; k += t.T) {
-    int i, j;
-    t.unrank(k, i, j);
-    float v = M[k];
-    for (int r = 0; r < nrow; r++) v += w[r] * J[r * nv + i] * J[r * nv + j];
-    H[k] = v;
+  if (t.T == 64 && nv <= 32) {
+    // One world per wavefront: H = M + sum_r w_r J_r^T J_r as a dense contraction on
+    // the matrix cores, two rows per v_mfma_f32_32x32x2_f32 (A = w J, B = J, the
+    // 32 x 32 accumulator padded beyond nv).  Operand layout: lane l holds column
+    // l % 32 of row r + l / 32.  Accumulator element v of lane l is entry
+    // (8 (v / 4) + 4 (l / 32) + v % 4, l % 32).
+    const int j = t.lane & 31, kh = t.lane >> 5;
+    const int nr = __builtin_amdgcn_readfirstlane(nrow);  // one world per wave: uniform
+    f32x16 C;
+#pragma unroll
+    for (int v = 0; v < 16; v++) {
+      const int i = 8 * (v >> 2) + 4 * kh + (v & 3);
+      C[v] = (i < nv && j <= i) ? M[tri(i, j)] : 0.f;
+    }
+    for (int r = 0; r < nr; r += 2) {
+      const int rr = r + kh;
+      float a = 0.f, b = 0.f;
+      if (rr < nr && j < nv) {
+        b = J[rr * nv + j];
+        a = w[rr] * b;
+      }
+      C = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, C, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; v++) {
+      const int i = 8 * (v >> 2) + 4 * kh + (v & 3);
+      if (i < nv && j <= i) H[tri(i, j)] = C[v];
+    }
+  } else {
+    for (int k = t.lane; k < m.ntri; k += t.T) {
+      int i, j;
+      t.unrank(k, i, j);
+      float v = M[k];
+      for (int r = 0; r < nrow; r++) v += w[r] * J[r * nv + i] * J[r * nv + j];
+      H[k] = v;
+    }
   }
   t.sync();
   bool ok = true;
@@ -894,10 +983,23 @@ DEV void cholesky_solve(const DevModel& m, float* W, const Team& t, const float*
   }
   t.sync();
 }
-// back substitution L^T x = y (one lane; x and y may alias)
+// back substitution L^T x = y (x and y may alias)
 DEV void cholesky_back(const DevModel& m, float* W, const Team& t, const float* y, float* x) {
   const float* H = W + m.o_H;
   const int nv = m.nv;
+  if (nv <= t.T) {
+    // lane i holds entry i; x_j is broadcast from lane j once its column is finished
+    const int i = t.lane;
+    float acc = i < nv ? y[i] : 0.f;
+    const float rinv = i < nv ? 1.f / H[tri(i, i)] : 0.f;
+    for (int j = nv - 1; j > 0; j--) {
+      const float xj = t.bcast(acc * rinv, j);
+      if (i < j) acc -= H[tri(j, i)] * xj;
+    }
+    if (i < nv) x[i] = acc * rinv;
+    t.sync();
+    return;
+  }
   if (t.lane == 0) {
     for (int i = nv - 1; i >= 0; i--) {
       float v = y[i];

@@ -4,6 +4,8 @@ same states and measure the differences (error metric: per world,
 s = total mass * 9.81 for contact forces)."""
 from __future__ import annotations
 
+import os
+
 import numpy as np
 import torch
 
@@ -51,6 +53,7 @@ def compare_step(m, o, state, ctrl1, gpu1, mode=oracle.MODE_FIXED, near=1e-5):
     mass = sum(b.mass for b in m.bodies)
     err_a = np.zeros(nw)
     err_f = np.zeros(nw)
+    err_geo = np.zeros((nw, 3))  # contact depth, point and normal deviations
     flag = np.zeros(nw, dtype=bool)
     for w in range(nw):
         a_r, a_g = ref["qacc"][w], gpu1["qacc"][w]
@@ -75,7 +78,10 @@ def compare_step(m, o, state, ctrl1, gpu1, mode=oracle.MODE_FIXED, near=1e-5):
         if np.any(np.abs(e) < 1e-6 * (1 + np.abs(f["aref"]).max())):
             flag[w] = True
         err_f[w] = np.abs(cg[:, 13:16] - cr[:, 13:16]).max() / (mass * G)
-    return dict(err_a=err_a, err_f=err_f, flag=flag, ref=ref)
+        err_geo[w] = (np.abs(cg[:, 0] - cr[:, 0]).max(), np.abs(cg[:, 1:4] - cr[:, 1:4]).max(),
+                      np.abs(cg[:, 4:7] - cr[:, 4:7]).max())
+    return dict(err_a=err_a, err_f=err_f, err_geo=err_geo, flag=flag, ref=ref,
+                state=state, ctrl=ctrl1, gpu_qacc=gpu1["qacc"], gpu_contacts=gpu1.get("contacts"))
 
 
 def workload(kind, nw, nstep, seed=0):
@@ -119,4 +125,28 @@ def summarize(kind, stats):
             f"{(ef.max() if ef.size else 0):.2e}; near-switch states {nflag}/{ntot}"
             + (f" (their qacc err max {fa.max():.2e})" if fa.size else ""))
     print(line, flush=True)
+    # the worst unflagged world: its contacts, and optionally its state for offline study
+    best = None
+    for s in stats:
+        ok = np.flatnonzero(~s["flag"])
+        if ok.size:
+            w = ok[np.argmax(s["err_a"][ok])]
+            if best is None or s["err_a"][w] > best[0]["err_a"][best[1]]:
+                best = (s, w)
+    if best is not None:
+        s, w = best
+        nc = int(s["ncon"][w])
+        pairs = s["ref"]["contacts"][w, :nc, 16].astype(int).tolist() if nc else []
+        print(f"[parity] {kind} worst world: step {s['t']} world {w} err {s['err_a'][w]:.2e} "
+              f"ncon {nc} pairs {pairs} |d dist| {s['err_geo'][w][0]:.1e} "
+              f"|d pos| {s['err_geo'][w][1]:.1e} |d normal| {s['err_geo'][w][2]:.1e}", flush=True)
+        out = os.environ.get("MJH_PARITY_DUMP")
+        if out:
+            os.makedirs(out, exist_ok=True)
+            q, v, ws = s["state"]
+            np.savez(os.path.join(out, f"worst_{kind}.npz"), qpos=q[w], qvel=v[w], ws=ws[w],
+                     ctrl=s["ctrl"][0, w] if s["ctrl"] is not None else np.zeros(0),
+                     gpu_qacc=s["gpu_qacc"][w],
+                     gpu_contacts=s["gpu_contacts"][w] if s["gpu_contacts"] is not None
+                     else np.zeros(0))
     return ea, ef, nflag, ntot
