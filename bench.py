@@ -100,7 +100,7 @@ def rollout_compare(ctx, seed, nw=1024, horizon=64, ckpt=8, reps=3):
     qp, qv = inputs.initial_state("quadruped", m, nw, seed=seed)
     rng = inputs.rng(seed, 7)
     u = torch.tensor(inputs.f32(rng.uniform(-0.5, 0.5, size=(horizon, nw, m.nu))),
-                     device="cuda").contiguous()
+                     dtype=torch.float32, device="cuda").contiguous()
     stream = torch.cuda.current_stream()
     plain = mjh.World(ctx, gm, nw, qpos=qp, qvel=qv)
     q0, v0 = plain.qpos.clone(), plain.qvel.clone()
@@ -146,7 +146,8 @@ def hetero_compare(ctx, seed, nstep=500, reps=3):
     for k, (kind, nw) in enumerate(spec):
         m = robots.WORKLOADS[kind]()
         qp, qv = inputs.initial_state(kind, m, nw, seed=seed + k)
-        u = torch.tensor(inputs.controls(kind, m, nw, nstep, seed=seed + k), device="cuda")
+        u = torch.tensor(inputs.controls(kind, m, nw, nstep, seed=seed + k),
+                         dtype=torch.float32, device="cuda")
         w = mjh.World(ctx, ctx.model_upload(m), nw, qpos=qp, qvel=qv)
         w.batch.bind_io(0, u.contiguous())
         worlds.append(w); ctrls.append(u.contiguous()); init.append((w.qpos.clone(), w.qvel.clone()))

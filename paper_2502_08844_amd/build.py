@@ -10,9 +10,13 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmjh.so")
 SOURCES = ["mjh_api.cpp", "mjh_kernels.hip", "mjh_adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-# -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions
+# -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions.
+# -fno-hip-fp32-correctly-rounded-divide-sqrt: FP32 division and square root within a
+# few ulp (v_rcp/v_sqrt based) instead of the correctly rounded ~10-instruction
+# sequences; pivots and line-search ratios sit on per-column dependency chains.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-fno-hip-fp32-correctly-rounded-divide-sqrt",
          "-Wall", "-Wno-unused-function"]
 
 

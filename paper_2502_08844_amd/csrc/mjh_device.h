@@ -23,6 +23,16 @@ namespace mjh {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// A zero the compiler cannot see through.  Adding it to the LDS base pointer and the
+// lane index at the start of a phase keeps values derived from them (region pointers,
+// lane masks) from being hoisted out of the step loop and held, or spilled, across
+// phases; each phase recomputes them with a few adds.
+DEV int opaque_zero() {
+  int z = 0;
+  asm volatile("" : "+v"(z));
+  return z;
+}
+
 
 // ------------------------------------------------------------------- team helpers
 struct Team {
@@ -876,8 +886,9 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
 
 // --------------------------------------------------- A9: Newton solve (NW ch. 3, 6)
 // H = M + sum_{rows with e < 0} D J^T J (packed lower), factorised in place as L L^T.
-// Right-looking by columns; column j is used unscaled by its own trailing update and
-// scaled one column later, so each column costs one barrier.  When `y` is given the
+// Right-looking; a column is used unscaled by its own trailing update and scaled in
+// the next barrier interval.  With nv <= T two columns share a barrier, otherwise each
+// column costs one.  When `y` is given the
 // forward solve L y = b (b overwritten) rides along.  Returns false for a non-positive
 // pivot.  `w` (nrow words) receives the active rows' weights D (0 when inactive).
 DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nrow,
@@ -930,6 +941,81 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nrow,
   }
   t.sync();
   bool ok = true;
+  if (nv <= t.T) {
+    // Two columns (j, j + 1) per barrier.  With p0 = H_jj and l = H_{j+1,j}, the
+    // second column after the first one's update is u_i = H_{i,j+1} - H_ij l / p0 and
+    // its pivot p1 = H_{j+1,j+1} - l^2 / p0; every trailing entry then takes both
+    // rank-1 updates, H_ik -= H_ij H_kj / p0 + u_i u_k / p1, recomputing u_i and u_k
+    // from the entries as they were at the block's start, so the two columns need no
+    // barrier between them.  Lane r keeps u for row j + 2 + r in a register; both
+    // columns are scaled to L in the next block, which does not read them.
+    float u_own = 0.f;
+    int pc = -1;
+    bool ptwo = false;
+    float pd0 = 1.f, pi0 = 1.f, pd1 = 1.f, pi1 = 1.f;
+    for (int j = 0;; j += 2) {
+      if (pc >= 0) {
+        const int r0w = pc + 1 + t.lane;
+        if (r0w < nv) H[tri(r0w, pc)] *= pi0;
+        if (ptwo) {
+          const int r1w = pc + 2 + t.lane;
+          if (r1w < nv) H[tri(r1w, pc + 1)] = u_own * pi1;
+          if (t.lane == 0) H[tri(pc + 1, pc + 1)] = pd1;
+        }
+        if (t.lane == 0) H[tri(pc, pc)] = pd0;
+      }
+      if (j >= nv) {
+        t.sync();
+        break;
+      }
+      const bool two = j + 1 < nv;
+      const float p0 = H[tri(j, j)];
+      ok = ok && (p0 > 0.f);
+      const float d0 = sqrtf(fmaxf(p0, 1e-30f)), i0 = 1.f / d0, r0 = i0 * i0;
+      float l10 = 0.f, d1 = 1.f, i1 = 1.f, r1 = 0.f;
+      if (two) {
+        l10 = H[tri(j + 1, j)];
+        const float p1 = H[tri(j + 1, j + 1)] - l10 * l10 * r0;
+        ok = ok && (p1 > 0.f);
+        d1 = sqrtf(fmaxf(p1, 1e-30f));
+        i1 = 1.f / d1;
+        r1 = i1 * i1;
+      }
+      const float lr = l10 * r0;
+      const int c = j + (two ? 2 : 1);  // first trailing row and column
+      const int n2 = nv - c, npr = n2 * (n2 + 1) / 2;
+      for (int p = t.lane; p < npr; p += t.T) {
+        int bi, ai;
+        t.unrank(p, bi, ai);
+        const int i = c + bi, k = c + ai;
+        const int ri = tri(i, 0), rk = tri(k, 0);
+        const float hij = H[ri + j], hkj = H[rk + j];
+        float v = H[ri + k] - hij * hkj * r0;
+        if (two) {
+          const float ui = H[ri + j + 1] - hij * lr;
+          const float uk = H[rk + j + 1] - hkj * lr;
+          v -= ui * uk * r1;
+        }
+        H[ri + k] = v;
+      }
+      const int ir = c + t.lane;
+      u_own = (two && ir < nv) ? H[tri(ir, j + 1)] - H[tri(ir, j)] * lr : 0.f;
+      if (y) {  // L y = b for the two columns; rows below take both updates
+        const float y0 = b[j] * i0;
+        const float y1 = two ? (b[j + 1] - l10 * i0 * y0) * i1 : 0.f;
+        if (ir < nv) b[ir] -= H[tri(ir, j)] * i0 * y0 + u_own * i1 * y1;
+        if (t.lane == 0) {
+          y[j] = y0;
+          if (two) y[j + 1] = y1;
+        }
+      }
+      pc = j;
+      ptwo = two;
+      pd0 = d0; pi0 = i0; pd1 = d1; pi1 = i1;
+      t.sync();
+    }
+    return ok;
+  }
   float dlast = 1.f, invlast = 1.f;  // column j - 1, scaled during column j
   for (int j = 0; j <= nv; j++) {
     float dj = 1.f, inv = 1.f;
@@ -1222,29 +1308,52 @@ DEV void integrate(const DevModel& m, float* W, const Team& t, int& status) {
   } while (0)
 #endif
 
-DEV void world_step(const DevModel& m, float* W, const Team& t, const float* ctrl,
+DEV void world_step(const DevModel& m, float* W0, const Team& t0, const float* ctrl,
                     int& status, int iters, long long* ph = nullptr, long long* last = nullptr) {
-  actuation(m, W, t, ctrl);
-  MJH_MARK(0);
-  forward_sweep(m, W, t);
-  MJH_MARK(1);
-  backward_and_mass(m, W, t);
-  MJH_MARK(2);
+#define MJH_PHASE_CTX                                   \
+  float* W = W0 + opaque_zero();                        \
+  const Team t{t0.lane + opaque_zero(), t0.T, t0.tp};
   {
+    MJH_PHASE_CTX
+    actuation(m, W, t, ctrl);
+    MJH_MARK(0);
+  }
+  {
+    MJH_PHASE_CTX
+    forward_sweep(m, W, t);
+    MJH_MARK(1);
+  }
+  {
+    MJH_PHASE_CTX
+    backward_and_mass(m, W, t);
+    MJH_MARK(2);
+  }
+  {
+    MJH_PHASE_CTX
     float* a0 = W + m.o_a0;
     const float* frc = W + m.o_frc;
     for (int i = t.lane; i < m.nv; i += t.T) a0[i] = frc[i];
+    ltdl_factor(m, W, t, W + m.o_a0);  // also solves L^T y = frc in place
+    ltdl_solve(m, W, t, nullptr, W + m.o_a0, true);
+    MJH_MARK(3);
   }
-  ltdl_factor(m, W, t, W + m.o_a0);  // also solves L^T y = frc in place
-  ltdl_solve(m, W, t, nullptr, W + m.o_a0, true);
-  MJH_MARK(3);
-  collide_candidates(m, W, t);
-  select_contacts(m, W, t, status);
-  MJH_MARK(4);
-  constraint_rows(m, W, t);
-  MJH_MARK(5);
-  newton(m, W, t, status, iters);
-  MJH_MARK(6);
+  {
+    MJH_PHASE_CTX
+    collide_candidates(m, W, t);
+    select_contacts(m, W, t, status);
+    MJH_MARK(4);
+  }
+  {
+    MJH_PHASE_CTX
+    constraint_rows(m, W, t);
+    MJH_MARK(5);
+  }
+  {
+    MJH_PHASE_CTX
+    newton(m, W, t, status, iters);
+    MJH_MARK(6);
+  }
+#undef MJH_PHASE_CTX
 }
 
 // copy a model's triangular pair table to the head of the work-group's LDS (all
