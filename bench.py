@@ -18,8 +18,52 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+# FP32 vector ceiling of this code: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+# The published 157.3 TFLOP/s counts packed FP32 (two FMAs per lane), which this build
+# disables.
+FP32_VECTOR_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6
+FP32_PUBLISHED_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0             # MI355X published HBM3E bandwidth
+PROFILE = os.path.join(ROOT, "profiles", "mjh_step_kernel_quadruped_8192x1000.txt")
+PROFILED = (8192, 1000)           # nworld, nstep of the committed counter profile
+
+
+def quadruped_algo_bytes(nu, nq, nv, nstep):
+    """Algorithmic HBM bytes per world-step: the controls of the step, plus qpos, qvel
+    and the warm start read and written once per launch."""
+    return 4.0 * nu + 4.0 * 2 * (nq + 2 * nv) / nstep
+
+
+ALGO_BYTES_PER_WORLD_STEP_AT_1000 = quadruped_algo_bytes(12, 19, 18, 1000)
+
+
+def kernel_source_digest():
+    """Digest of the step kernel's sources and build flags: a counter profile applies
+    to the current kernel only if it was taken with the same digest."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2502_08844_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    from paper_2502_08844_amd import build as _build
+    h.update(" ".join(_build.FLAGS).encode())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(nw, ns):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE profile,
+    when it was taken on this kernel and this workload; otherwise None."""
+    if (nw, ns) != PROFILED or not os.path.exists(PROFILE):
+        return None
+    digest, traffic = None, None
+    with open(PROFILE) as f:
+        for line in f:
+            if line.startswith("kernel source digest:"):
+                digest = line.split(":", 1)[1].strip()
+            elif line.strip().startswith("traffic_bytes_per_launch:"):
+                traffic = float(line.split(":", 1)[1])
+    return traffic if digest == kernel_source_digest() else None
 
 
 def parse():
@@ -271,10 +315,12 @@ def main():
     flops_ws = algorithmic_flops_per_world_step(m, qp[:sample], qv[:sample],
                                                 inputs.controls(kind, m, sample, 1, seed=1))
     achieved_tf = flops_ws * nw * ns / (kavg * 1e-3) / 1e12
-    bytes_ws = 4.0 * m.nu + 4.0 * 2 * (m.nq + 2 * m.nv) / ns
-    roof = {"bound": "alu", "achieved": round(achieved_tf, 4), "peak": FP32_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved_tf / FP32_VECTOR_PEAK_TFLOPS, 6),
-            "traffic": None,
+    bytes_ws = quadruped_algo_bytes(m.nu, m.nq, m.nv, ns)
+    roof = {"bound": "alu", "achieved": round(achieved_tf, 4),
+            "peak": round(FP32_VECTOR_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+            "frac": round(achieved_tf / FP32_VECTOR_PEAK_TFLOPS, 6),
+            "traffic": profiled_traffic(nw, ns),
+            "published_fp32_peak_packed": FP32_PUBLISHED_PEAK_TFLOPS,
             "kernel": "mjh_step_kernel", "kernel_ms": round(kavg, 3),
             "flops_per_world_step": round(flops_ws, 1),
             "hbm_bytes_per_world_step": round(bytes_ws, 2),
