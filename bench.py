@@ -28,42 +28,38 @@ PROFILE = os.path.join(ROOT, "profiles", "mjh_step_kernel_quadruped_8192x1000.tx
 PROFILED = (8192, 1000)           # nworld, nstep of the committed counter profile
 
 
-def quadruped_algo_bytes(nu, nq, nv, nstep):
+def algo_bytes(nu, nq, nv, nstep):
     """Algorithmic HBM bytes per world-step: the controls of the step, plus qpos, qvel
     and the warm start read and written once per launch."""
     return 4.0 * nu + 4.0 * 2 * (nq + 2 * nv) / nstep
 
 
-ALGO_BYTES_PER_WORLD_STEP_AT_1000 = quadruped_algo_bytes(12, 19, 18, 1000)
+ALGO_BYTES_PER_WORLD_STEP_AT_1000 = algo_bytes(12, 19, 18, 1000)  # quadruped
 
 
-def kernel_source_digest():
-    """Digest of the step kernel's sources and build flags: a counter profile applies
-    to the current kernel only if it was taken with the same digest."""
+def kernel_digest():
+    """Digest of the built library (the build is reproducible, and comments do not
+    change it): a counter profile applies to the current kernel only if it was taken
+    with the same digest."""
     import hashlib
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2502_08844_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
-    from paper_2502_08844_amd import build as _build
-    h.update(" ".join(_build.FLAGS).encode())
-    return h.hexdigest()[:16]
+    from paper_2502_08844_amd import mjh
+    with open(mjh.LIB_PATH, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def profiled_traffic(nw, ns):
+def profiled_traffic(kind, nw, ns):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE profile,
     when it was taken on this kernel and this workload; otherwise None."""
-    if (nw, ns) != PROFILED or not os.path.exists(PROFILE):
+    if kind != "quadruped" or (nw, ns) != PROFILED or not os.path.exists(PROFILE):
         return None
     digest, traffic = None, None
     with open(PROFILE) as f:
         for line in f:
-            if line.startswith("kernel source digest:"):
+            if line.startswith("library digest:"):
                 digest = line.split(":", 1)[1].strip()
             elif line.strip().startswith("traffic_bytes_per_launch:"):
                 traffic = float(line.split(":", 1)[1])
-    return traffic if digest == kernel_source_digest() else None
+    return traffic if digest == kernel_digest() else None
 
 
 def parse():
@@ -71,6 +67,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--model", default="quadruped",
+                    choices=["quadruped", "humanoid", "hand", "cartpole"],
+                    help="robot of the timed batch (the headline metric is the quadruped)")
     ap.add_argument("--nworld", type=int, default=8192)
     ap.add_argument("--nstep", type=int, default=1000)
     ap.add_argument("--seed", type=int, default=0)
@@ -135,7 +134,8 @@ def timed(fn, stream, reps):
 
 def rollout_compare(ctx, seed, nw=1024, horizon=64, ckpt=8, reps=3):
     """Adjoint rollout (forward with checkpoints + reverse sweep) against the plain step
-    on the same worlds: 1024 quadrupeds, horizon 64, checkpoints every 8 steps."""
+    on the same worlds: 1024 quadrupeds, horizon 64, checkpoints every 8 steps.  Both
+    use the launch shape the autotuner picks for the plain step at this world count."""
     import torch
     from paper_2502_08844_amd import mjh
     from paper_2502_08844_amd.synth import inputs, robots
@@ -149,6 +149,8 @@ def rollout_compare(ctx, seed, nw=1024, horizon=64, ckpt=8, reps=3):
     plain = mjh.World(ctx, gm, nw, qpos=qp, qvel=qv)
     q0, v0 = plain.qpos.clone(), plain.qvel.clone()
     plain.batch.bind_io(0, u)
+    plain.batch.autotune(8)
+    team, block = plain.batch.get_launch(0)
 
     def run_plain():
         plain.qpos.copy_(q0); plain.qvel.copy_(v0); plain.qacc_ws.zero_()
@@ -156,6 +158,7 @@ def rollout_compare(ctx, seed, nw=1024, horizon=64, ckpt=8, reps=3):
     run_plain()
     t_plain = timed(run_plain, stream, reps)
     w = mjh.World(ctx, gm, nw, qpos=qp, qvel=qv)
+    w.batch.set_launch(0, team, block)
     loss = torch.empty(nw, device="cuda")
     dloss = torch.ones(nw, device="cuda")
     gq = torch.empty(nw, m.nv, device="cuda")
@@ -175,7 +178,8 @@ def rollout_compare(ctx, seed, nw=1024, horizon=64, ckpt=8, reps=3):
             "plain_world_steps_per_s": round(ws / (t_plain * 1e-3), 1),
             "fwd_bwd_rollout_steps_per_s": round(ws / ((t_fwd + t_bwd) * 1e-3), 1),
             "fwd_ms": round(t_fwd, 3), "bwd_ms": round(t_bwd, 3), "plain_ms": round(t_plain, 3),
-            "fwd_bwd_over_plain_time": round((t_fwd + t_bwd) / t_plain, 2)}
+            "fwd_bwd_over_plain_time": round((t_fwd + t_bwd) / t_plain, 2),
+            "launch": [team, block]}
 
 
 def hetero_compare(ctx, seed, nstep=500, reps=3):
@@ -256,8 +260,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    kind = "quadruped"
-    m = robots.quadruped()
+    kind = args.model
+    m = robots.WORKLOADS[kind]()
     nw, ns = args.nworld, args.nstep
     ctx = mjh.Context(0)
     gm = ctx.model_upload(m)
@@ -267,8 +271,18 @@ def main():
     q0, v0 = world.qpos.clone(), world.qvel.clone()
     gen = torch.Generator(device=dev)
     gen.manual_seed(args.seed)
-    # PD target offsets U(-0.5, 0.5), resampled every step, resident in HBM
-    ctrl = (torch.rand(ns, nw, m.nu, device=dev, generator=gen) - 0.5).contiguous()
+    # controls resampled every step, resident in HBM, drawn on the device with the
+    # distributions of the synthetic workloads
+    shape = (ns, nw, m.nu)
+    if kind == "quadruped":    # PD target offsets U(-0.5, 0.5)
+        ctrl = torch.rand(shape, device=dev, generator=gen) - 0.5
+    elif kind == "humanoid":   # torques N(0, 0.3) clipped to [-1, 1]
+        ctrl = (0.3 * torch.randn(shape, device=dev, generator=gen)).clamp_(-1.0, 1.0)
+    elif kind == "hand":       # PD target offsets U(-0.3, 0.3)
+        ctrl = 0.6 * torch.rand(shape, device=dev, generator=gen) - 0.3
+    else:                      # cart force U(-1, 1)
+        ctrl = 2.0 * torch.rand(shape, device=dev, generator=gen) - 1.0
+    ctrl = ctrl.contiguous()
     world.batch.bind_io(0, ctrl)
     stream = torch.cuda.current_stream()
 
@@ -315,23 +329,25 @@ def main():
     flops_ws = algorithmic_flops_per_world_step(m, qp[:sample], qv[:sample],
                                                 inputs.controls(kind, m, sample, 1, seed=1))
     achieved_tf = flops_ws * nw * ns / (kavg * 1e-3) / 1e12
-    bytes_ws = quadruped_algo_bytes(m.nu, m.nq, m.nv, ns)
+    bytes_ws = algo_bytes(m.nu, m.nq, m.nv, ns)
     roof = {"bound": "alu", "achieved": round(achieved_tf, 4),
             "peak": round(FP32_VECTOR_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
             "frac": round(achieved_tf / FP32_VECTOR_PEAK_TFLOPS, 6),
-            "traffic": profiled_traffic(nw, ns),
+            "traffic": profiled_traffic(kind, nw, ns),
             "published_fp32_peak_packed": FP32_PUBLISHED_PEAK_TFLOPS,
             "kernel": "mjh_step_kernel", "kernel_ms": round(kavg, 3),
             "flops_per_world_step": round(flops_ws, 1),
             "hbm_bytes_per_world_step": round(bytes_ws, 2),
             "hbm_frac": round(bytes_ws * nw * ns / (kavg * 1e-3) / 1e9 / HBM_PEAK_GBS, 8)}
-    out = {"metric": "world-steps/sec at 8192 quadruped worlds; fwd+bwd rollout steps/sec vs plain",
+    metric = ("world-steps/sec at 8192 quadruped worlds; fwd+bwd rollout steps/sec vs plain"
+              if kind == "quadruped" else f"world-steps/sec at {nw} {kind} worlds")
+    out = {"metric": metric,
            "value": round(value, 1),
            "unit": "world-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-           "data": "synthetic (seeded quadruped states, uniform random PD targets)",
-           "config": {"workload": f"quadruped {nw} worlds x {ns} physics steps per launch",
+           "data": f"synthetic (seeded {kind} states, random controls every step)",
+           "config": {"workload": f"{kind} {nw} worlds x {ns} physics steps per launch",
                       "nworld": nw, "nstep_per_launch": ns, "dt": m.opt.timestep,
                       "newton_iterations": m.opt.iterations, "graph": bool(args.graph),
                       "launch": list(world.batch.get_launch(0)),
@@ -349,8 +365,8 @@ def main():
                                       args.seed)
         out["cpu_baseline"] = {"value": round(rate, 1), "unit": "world-steps/s",
                                "cores": nthreads, "kind": "oracle",
-                               "sample": f"{cw} quadruped worlds x {cs} steps (chunks of 40, "
-                                         f"fresh random PD targets), FP64, {secs:.1f} s"}
+                               "sample": f"{cw} {kind} worlds x {cs} steps (chunks of 40, "
+                                         f"fresh random controls), FP64, {secs:.1f} s"}
     print(json.dumps(out), flush=True)
 
 

@@ -137,7 +137,8 @@ mjh_status mjh_get_launch(mjh_batch* b, int32_t group, int32_t* team, int32_t* b
  * state at the final step.  mjh_rollout_bwd(dloss [n]) writes grad_qvel0 [n][nv] and
  * grad_ctrl [horizon][n][nu] by the adjoint of the step: implicit differentiation at
  * each Newton solution, reverse sweeps of RNE/kinematics and contact geometry,
- * segments recomputed from the checkpoints.  Only plane-sphere and plane-capsule
+ * segments recomputed from the checkpoints.  Inside rollouts Newton iterates until
+ * max|grad| <= 1e-5 * max(1, max|smooth force|), at most 16 iterations.  Only plane-sphere and plane-capsule
  * contacts are differentiated (MJH_EUNSUPPORTED otherwise). */
 mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every,
                            const float* ctrl, int32_t zidx, float ztarget, float wctrl,

@@ -1,7 +1,8 @@
 // Differentiable rollout: checkpointed forward and hand-written reverse sweep.
 //
 // Forward (rollout_fwd_kernel): every world runs `horizon` steps with the Newton
-// solve iterated to convergence, stores (qpos, qvel, qacc_ws) every `ckpt` steps and
+// solve iterated to convergence (max |g| <= kAdjGtol * max(1, max |qfrc_smooth|), at
+// most kAdjIters iterations), stores (qpos, qvel, qacc_ws) every `ckpt` steps and
 // accumulates the loss  sum_t (qpos_{t+1}[zidx] - ztarget)^2 + wctrl |u_t|^2.
 // Reverse (rollout_bwd_kernel): segments in reverse order; each is recomputed from its
 // checkpoint into a per-world tape (Griewank & Walther, checkpointed reverse mode),
@@ -26,6 +27,8 @@
 namespace mjh {
 
 constexpr int kAdjIters = 16;  // Newton iterations cap inside differentiable rollouts
+// inside rollouts Newton runs to convergence: max |g| <= kAdjGtol * max(1, max |qfrc_smooth|)
+constexpr float kAdjGtol = 1e-5f;
 constexpr int kAdjBlock = 64;  // threads per work-group of the rollout kernels
 
 // ------------------------------------------------------------------ small helpers
@@ -689,7 +692,7 @@ __global__ void __launch_bounds__(kAdjBlock) rollout_fwd_kernel(RolloutArgs A) {
     if (s % A.ckpt == 0)
       store_state(m, W, t, A.tape_ckpt + ((size_t)(s / A.ckpt) * A.nworld + w) * ns);
     const float* u = A.ctrl + ((size_t)s * A.nworld + w) * m.nu;
-    world_step(m, W, t, u, status, kAdjIters);
+    world_step(m, W, t, u, status, kAdjIters, kAdjGtol);
     integrate(m, W, t, status);
     if (t.lane == 0) {
       const float dz = W[m.o_qpos + A.zidx] - A.ztarget;
@@ -738,7 +741,7 @@ __global__ void __launch_bounds__(kAdjBlock) rollout_bwd_kernel(RolloutArgs A) {
     store_state(m, W, t, seg_slot(0));
     for (int k = 0; k < len; k++) {
       const float* u = A.ctrl + ((size_t)(s0 + k) * A.nworld + w) * m.nu;
-      world_step(m, W, t, u, status, kAdjIters);
+      world_step(m, W, t, u, status, kAdjIters, kAdjGtol);
       integrate(m, W, t, status);
       store_state(m, W, t, seg_slot(k + 1));
     }
@@ -750,7 +753,7 @@ __global__ void __launch_bounds__(kAdjBlock) rollout_bwd_kernel(RolloutArgs A) {
       const float znext = seg_slot(k + 1)[A.zidx];
       if (t.lane == 0) qbi[A.zidx] += 2.f * (znext - A.ztarget) * dl;
       load_state(m, W, t, seg_slot(k));
-      world_step(m, W, t, u, status, kAdjIters);
+      world_step(m, W, t, u, status, kAdjIters, kAdjGtol);
       adjoint_step(m, W, t, u, status);
       float* gu = A.grad_ctrl + ((size_t)s * A.nworld + w) * m.nu;
       const float* ub = W + m.o_ub;

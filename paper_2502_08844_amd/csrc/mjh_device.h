@@ -1050,11 +1050,29 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nrow,
   }
   return ok;
 }
-// x = sgn * (L L^T)^{-1} rhs with the factor in H (one lane; rhs and x may alias)
+// x = sgn * (L L^T)^{-1} rhs with the factor in H (rhs and x may alias)
 DEV void cholesky_solve(const DevModel& m, float* W, const Team& t, const float* rhs, float* x,
                         float sgn) {
   const float* H = W + m.o_H;
   const int nv = m.nv;
+  if (nv <= t.T) {
+    // lane i holds entry i; each finished entry is broadcast from its lane
+    const int i = t.lane;
+    const float rinv = i < nv ? 1.f / H[tri(i, i)] : 0.f;
+    float acc = i < nv ? sgn * rhs[i] : 0.f;
+    for (int j = 0; j < nv - 1; j++) {  // L y = sgn rhs
+      const float yj = t.bcast(acc * rinv, j);
+      if (i > j && i < nv) acc -= H[tri(i, j)] * yj;
+    }
+    acc *= rinv;
+    for (int j = nv - 1; j > 0; j--) {  // L^T x = y
+      const float xj = t.bcast(acc * rinv, j);
+      if (i < j) acc -= H[tri(j, i)] * xj;
+    }
+    if (i < nv) x[i] = acc * rinv;
+    t.sync();
+    return;
+  }
   if (t.lane == 0) {
     for (int i = 0; i < nv; i++) {
       float v = sgn * rhs[i];
@@ -1100,8 +1118,10 @@ DEV void cholesky_back(const DevModel& m, float* W, const Team& t, const float* 
 // Start from the cheaper of the warm start and a0; each iteration: gradient and
 // Hessian on the active set, dense Cholesky of H, Newton direction, exact line
 // search (phi' evaluated at every breakpoint in parallel), update.  Stops early when
-// the Newton direction is no longer a descent direction (converged to precision).
-DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int iters) {
+// the Newton direction is no longer a descent direction (converged to precision) or,
+// with gtol > 0, when max |g| <= gtol * max(1, max |qfrc_smooth|).
+DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int iters,
+                float gtol = 0.f) {
   const int* scal = (const int*)(W + m.o_scal);
   const int nv = m.nv, nrow = 4 * scal[SC_NCON];
   const float* M = W + m.o_M;
@@ -1150,8 +1170,16 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int ite
     for (int r = t.lane; r < nrow; r += t.T) e[r] = s[r];
     t.sync();
   }
+  float gstop = 0.f;
+  if (gtol > 0.f) {
+    const float* frc = W + m.o_frc;
+    float fm = 1.f;
+    for (int i = t.lane; i < nv; i += t.T) fm = fmaxf(fm, fabsf(frc[i]));
+    gstop = gtol * t.max(fm);
+  }
   for (int it = 0; it < iters; it++) {
     // ---- gradient g = M (a - a0) + sum_active D e J
+    float gmax = 0.f;
     for (int i = t.lane; i < nv; i += t.T) {
       float v = Mr[i];
       for (int r = 0; r < nrow; r++) {
@@ -1159,7 +1187,9 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int ite
         if (er < 0.f) v += D[r] * er * J[r * nv + i];
       }
       g[i] = v;
+      gmax = fmaxf(gmax, fabsf(v));
     }
+    if (gtol > 0.f && t.max(gmax) <= gstop) break;  // converged to FP32 precision
     for (int i = t.lane; i < nv; i += t.T) d[i] = -g[i];
     // ---- delta = -H^-1 g: forward solve fused into the factorisation, then back
     if (!hessian_cholesky(m, W, t, nrow, d, tmp)) { status |= 4; break; }
@@ -1309,7 +1339,8 @@ DEV void integrate(const DevModel& m, float* W, const Team& t, int& status) {
 #endif
 
 DEV void world_step(const DevModel& m, float* W0, const Team& t0, const float* ctrl,
-                    int& status, int iters, long long* ph = nullptr, long long* last = nullptr) {
+                    int& status, int iters, float gtol = 0.f, long long* ph = nullptr,
+                    long long* last = nullptr) {
 #define MJH_PHASE_CTX                                   \
   float* W = W0 + opaque_zero();                        \
   const Team t{t0.lane + opaque_zero(), t0.T, t0.tp};
@@ -1350,7 +1381,7 @@ DEV void world_step(const DevModel& m, float* W0, const Team& t0, const float* c
   }
   {
     MJH_PHASE_CTX
-    newton(m, W, t, status, iters);
+    newton(m, W, t, status, iters, gtol);
     MJH_MARK(6);
   }
 #undef MJH_PHASE_CTX

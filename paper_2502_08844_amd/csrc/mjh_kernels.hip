@@ -40,7 +40,7 @@ __device__ void run_worlds(const DevGroup& G, float* W, int world, int nstep, in
   for (int s = 0; s < nstep; s++) {
     const float* u = G.ctrl ? G.ctrl + ((size_t)s * G.nworld + w) * nu : nullptr;
 #ifdef MJH_PHASE_TIMING
-    world_step(m, W, t, u, status, m.iterations, ph, &last);
+    world_step(m, W, t, u, status, m.iterations, 0.f, ph, &last);
 #else
     world_step(m, W, t, u, status, m.iterations);
 #endif
