@@ -199,13 +199,14 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
     const float* J = W + m.o_J;
     const float* aref = W + m.o_aref;
     float* e = W + m.o_e;
+    const int nru = pad_rows(m, W, t, nrow);
     for (int r = t.lane; r < nrow; r += t.T) {
       float v = 0.f;
       for (int i = 0; i < nv; i++) v += J[r * nv + i] * a[i];
       e[r] = v - aref[r];
     }
     t.sync();
-    if (!hessian_cholesky(m, W, t, nrow)) status |= 4;
+    if (!hessian_cholesky(m, W, t, nru)) status |= 4;
     cholesky_solve(m, W, t, abar, mu, -1.f);
   }
   // ---- actuation and passive forces, reversed (lane per dof)

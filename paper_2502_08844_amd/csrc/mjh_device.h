@@ -885,13 +885,43 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
 }
 
 // --------------------------------------------------- A9: Newton solve (NW ch. 3, 6)
+// Loops over all constraint rows run to a wave-uniform bound (the largest row count
+// among the wavefront's worlds), which keeps them off the EXEC mask.  Every lane reads
+// the contact counts that the wavefront's teams stored in their own LDS (slot SC_NCON,
+// written by select_contacts before the last barrier), clamped to [0, nconmax]: teams
+// that left the kernel never wrote theirs, and cross-lane operations are not used here
+// because teams may be inactive.  A world's rows from its own count up to the bound are
+// zeroed (J, D, e, s), so they add nothing to gradients, Hessian or line search.
+// Returns the bound.
+DEV int pad_rows(const DevModel& m, float* W, const Team& t, int nrow) {
+  const int tw = 64 / t.T;                              // teams per wavefront
+  const int my = (int)((threadIdx.x & 63) / t.T);      // this team's place in it
+  int mx = 0;
+  for (int k = 0; k < tw; k++) {
+    const int* sk = (const int*)(W + (k - my) * m.lds_words + m.o_scal);
+    const int nc = sk[SC_NCON];
+    mx = max(mx, min(max(nc, 0), m.nconmax));
+  }
+  // every active lane computed the same mx, and this team's own count is among them
+  const int nru = __builtin_amdgcn_readfirstlane(4 * mx);
+  float* J = W + m.o_J;
+  for (int k = nrow * m.nv + t.lane; k < nru * m.nv; k += t.T) J[k] = 0.f;
+  float* D = W + m.o_D;
+  float* e = W + m.o_e;
+  float* s = W + m.o_s;
+  for (int r = nrow + t.lane; r < nru; r += t.T) { D[r] = 0.f; e[r] = 0.f; s[r] = 0.f; }
+  t.sync();
+  return nru;
+}
+
 // H = M + sum_{rows with e < 0} D J^T J (packed lower), factorised in place as L L^T.
+// nru is the padded row bound of pad_rows.
 // Right-looking; a column is used unscaled by its own trailing update and scaled in
 // the next barrier interval.  With nv <= T two columns share a barrier, otherwise each
 // column costs one.  When `y` is given the
 // forward solve L y = b (b overwritten) rides along.  Returns false for a non-positive
 // pivot.  `w` (nrow words) receives the active rows' weights D (0 when inactive).
-DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nrow,
+DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
                           float* b = nullptr, float* y = nullptr) {
   const int nv = m.nv;
   const float* M = W + m.o_M;
@@ -900,7 +930,7 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nrow,
   const float* D = W + m.o_D;
   const float* e = W + m.o_e;
   float* w = W + m.o_s;  // row weights; the line search rewrites this scratch later
-  for (int r = t.lane; r < nrow; r += t.T) w[r] = e[r] < 0.f ? D[r] : 0.f;
+  for (int r = t.lane; r < nru; r += t.T) w[r] = e[r] < 0.f ? D[r] : 0.f;
   t.sync();
   if (t.T == 64 && nv <= 32) {
     // One world per wavefront: H = M + sum_r w_r J_r^T J_r as a dense contraction on
@@ -909,7 +939,7 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nrow,
     // l % 32 of row r + l / 32.  Accumulator element v of lane l is entry
     // (8 (v / 4) + 4 (l / 32) + v % 4, l % 32).
     const int j = t.lane & 31, kh = t.lane >> 5;
-    const int nr = __builtin_amdgcn_readfirstlane(nrow);  // one world per wave: uniform
+    const int nr = nru;
     f32x16 C;
 #pragma unroll
     for (int v = 0; v < 16; v++) {
@@ -935,7 +965,7 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nrow,
       int i, j;
       t.unrank(k, i, j);
       float v = M[k];
-      for (int r = 0; r < nrow; r++) v += w[r] * J[r * nv + i] * J[r * nv + j];
+      for (int r = 0; r < nru; r++) v += w[r] * J[r * nv + i] * J[r * nv + j];
       H[k] = v;
     }
   }
@@ -1142,6 +1172,7 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int ite
     t.sync();
     return;
   }
+  const int nru = pad_rows(m, W, t, nrow);
   // ---- start point: cost of the warm start vs cost of a0
   for (int i = t.lane; i < nv; i += t.T) tmp[i] = a[i] - a0[i];
   t.sync();
@@ -1182,9 +1213,9 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int ite
     float gmax = 0.f;
     for (int i = t.lane; i < nv; i += t.T) {
       float v = Mr[i];
-      for (int r = 0; r < nrow; r++) {
+      for (int r = 0; r < nru; r++) {
         const float er = e[r];
-        if (er < 0.f) v += D[r] * er * J[r * nv + i];
+        v += (er < 0.f ? D[r] * er : 0.f) * J[r * nv + i];
       }
       g[i] = v;
       gmax = fmaxf(gmax, fabsf(v));
@@ -1192,7 +1223,7 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int ite
     if (gtol > 0.f && t.max(gmax) <= gstop) break;  // converged to FP32 precision
     for (int i = t.lane; i < nv; i += t.T) d[i] = -g[i];
     // ---- delta = -H^-1 g: forward solve fused into the factorisation, then back
-    if (!hessian_cholesky(m, W, t, nrow, d, tmp)) { status |= 4; break; }
+    if (!hessian_cholesky(m, W, t, nru, d, tmp)) { status |= 4; break; }
     cholesky_back(m, W, t, tmp, d);
     // ---- line search quantities
     float gd = 0.f, dMd = 0.f, dMr = 0.f;
@@ -1224,9 +1255,9 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int ite
       const float br = -e[r] / sr;
       if (!(br > 0.f)) continue;
       float dp = dMr + br * dMd;
-      for (int q = 0; q < nrow; q++) {
-        const float v = e[q] + br * s[q];
-        if (v < 0.f) dp += D[q] * s[q] * v;
+      for (int q = 0; q < nru; q++) {
+        const float sq = s[q], v = e[q] + br * sq;
+        dp += (v < 0.f ? D[q] * sq : 0.f) * v;
       }
       if (dp <= 0.f) lo = fmaxf(lo, br);
       else hi = fminf(hi, br);

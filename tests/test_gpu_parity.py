@@ -64,6 +64,21 @@ def test_trajectory_and_status_and_determinism(lib):
     assert np.allclose(np.linalg.norm(a["qpos"][:, 3:7], axis=1), 1.0, atol=1e-6)
 
 
+@pytest.mark.parametrize("team,block", [(16, 64), (64, 64)])
+def test_single_step_parity_other_launch_shapes(lib, team, block):
+    """Single steps against the reference for team sizes other than the default. With
+    16 lanes per world the quadruped (nv 18) takes the fallback paths for nv > T. Four
+    worlds share a wavefront, and some of them return from the solve early."""
+    mjh, ctx = lib
+    print(f"[gpu] parity quadruped team={team} block={block}", flush=True)
+    m, stats = teacher_forced(ctx, mjh, "quadruped", 77, [0, 2, 3, 20], seed=5, team=team,
+                              block=block)
+    ea, ef, nflag, ntot = summarize(f"quadruped-T{team}", stats)
+    assert ea.max() <= QACC_TOL
+    if ef.size:
+        assert ef.max() <= FORCE_TOL
+
+
 @pytest.mark.parametrize("team,block", [(16, 64), (32, 128), (64, 256), (64, 64)])
 def test_launch_shapes_agree(lib, team, block):
     mjh, ctx = lib
