@@ -675,8 +675,8 @@ __global__ void __launch_bounds__(kAdjBlock) rollout_fwd_kernel(RolloutArgs A) {
   const int team = threadIdx.x / T;
   const int w = blockIdx.x * (blockDim.x / T) + team;
   if (w >= A.nworld) return;
-  const Team t{(int)threadIdx.x - team * T, T, (const unsigned short*)lds};
-  float* W = lds + table_words(m.ntri) + (size_t)team * m.lds_words;
+  const Team t{(int)threadIdx.x - team * T, T, (const unsigned char*)lds};
+  float* W = lds + table_words(m) + (size_t)team * m.lds_words;
   const int ns = m.nq + 2 * m.nv;
   world_init(m, W, t);
   const float* src0 = nullptr;
@@ -722,8 +722,8 @@ __global__ void __launch_bounds__(kAdjBlock) rollout_bwd_kernel(RolloutArgs A) {
   const int team = threadIdx.x / T;
   const int w = blockIdx.x * (blockDim.x / T) + team;
   if (w >= A.nworld) return;
-  const Team t{(int)threadIdx.x - team * T, T, (const unsigned short*)lds};
-  float* W = lds + table_words(m.ntri) + (size_t)team * m.lds_words;
+  const Team t{(int)threadIdx.x - team * T, T, (const unsigned char*)lds};
+  float* W = lds + table_words(m) + (size_t)team * m.lds_words;
   const int ns = m.nq + 2 * m.nv;
   world_init(m, W, t);
   const float dl = A.dloss[w];
@@ -844,7 +844,7 @@ mjh_status adjoint_forward(AdjointState** stp, const DevModel& m, int team, int 
   st->have_fwd = false;
   if (nworld == 0) { st->have_fwd = true; return MJH_OK; }
   const size_t lds =
-      ((size_t)table_words(m.ntri) + (size_t)(kAdjBlock / team) * m.lds_words) * sizeof(float);
+      ((size_t)table_words(m) + (size_t)(kAdjBlock / team) * m.lds_words) * sizeof(float);
   hipError_t e = hipFuncSetAttribute((const void*)rollout_fwd_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e == hipSuccess)
@@ -869,7 +869,7 @@ mjh_status adjoint_backward(AdjointState* st, const float* dloss, float* grad_qv
   A.grad_ctrl = grad_ctrl;
   if (A.nworld == 0) return MJH_OK;
   const size_t lds =
-      ((size_t)table_words(A.m.ntri) + (size_t)(kAdjBlock / A.team) * A.m.lds_words) * sizeof(float);
+      ((size_t)table_words(A.m) + (size_t)(kAdjBlock / A.team) * A.m.lds_words) * sizeof(float);
   hipLaunchKernelGGL(rollout_bwd_kernel, dim3(blocks_for(A.nworld, A.team)), dim3(kAdjBlock), lds,
                      stream, A);
   hipError_t e = hipGetLastError();

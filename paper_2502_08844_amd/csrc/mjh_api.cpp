@@ -235,15 +235,6 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
     for (int p = h.body_parent[b]; p > 0; p = h.body_parent[p])
       if (body_dofnum[p] > 0) { dof_parent[k] = body_dofadr[p] + body_dofnum[p] - 1; break; }
   }
-  // packed lower-triangle index p = b (b + 1) / 2 + a -> 16-bit entry (b << 8) | a, two
-  // entries per 32-bit word (entry 2k in the low half)
-  std::vector<uint16_t> tri_entry;
-  for (int b = 0; b < h.nv; b++)
-    for (int a = 0; a <= b; a++) tri_entry.push_back((uint16_t)((b << 8) | a));
-  if (tri_entry.size() & 1) tri_entry.push_back(0);
-  std::vector<uint32_t> tri_pair(tri_entry.size() / 2);
-  for (size_t k = 0; k < tri_pair.size(); k++)
-    tri_pair[k] = (uint32_t)tri_entry[2 * k] | ((uint32_t)tri_entry[2 * k + 1] << 16);
   std::vector<int> anc_start(h.nv + 1, 0), anc_list, mpair;
   for (int k = 0; k < h.nv; k++) {
     anc_start[k] = (int)anc_list.size();
@@ -335,7 +326,6 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   pk.add(anc_list, &d.anc_list);
   pk.add(mpair, &d.mpair);
   pk.add(body_dofmask, &d.body_dofmask);
-  pk.add(tri_pair, &d.tri_pair);
   pk.add(h.geom_type, &d.geom_type);
   pk.add(h.geom_body, &d.geom_body);
   pk.add(h.pair_g1, &d.pair_g1);
@@ -404,20 +394,43 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   const int sweep_end = off;
   off = shared;
   d.o_H = take(d.ntri);
-  d.o_Mr = take(nv);
-  d.o_g = take(nv);
-  d.o_d = take(nv);
-  d.o_Md = take(nv);
-  d.o_tmp = take(nv);
-  d.o_cand = take(2 * ncand);
+  // Newton's vectors are born after the constraint rows, when the body poses and motion
+  // subspaces are dead until the next step's kinematics: they live in xmat/cdof past
+  // the world body's rotation (constant, set once per launch).
+  d.o_Mr = d.o_xmat + 9;
+  d.o_g = d.o_Mr + nv;
+  d.o_d = d.o_g + nv;
+  d.o_Md = d.o_d + nv;
+  d.o_tmp = d.o_Md + nv;  // 5 nv words <= 9 (nbody - 1) + 6 nv, always
+  // Candidates live from collision to contact selection, while the LTDL factor held in
+  // H is already consumed and the Newton Hessian not yet built: they share H's words.
+  if (2 * ncand <= d.ntri) d.o_cand = d.o_H;
+  else d.o_cand = take(2 * ncand);
   d.o_con = take(kConRec * h.nconmax);
   d.o_J = take(nr * nv);
-  d.o_aref = take(nr);
+  // the reference accelerations are read once, when Newton forms its residuals, before
+  // the first Hessian is built: they too share H's words
+  d.o_aref = nr <= d.ntri ? d.o_H : take(nr);
   d.o_D = take(nr);
   d.o_e = take(nr);
   d.o_s = take(nr);
   off = std::max(off, sweep_end);
   d.lds_words = off;
+  // Table of the packed lower triangle at the head of a work-group's LDS: index
+  // p = b (b + 1) / 2 + a -> row b, one byte (nv <= 64), four per word; a is recomputed.
+  // One byte rather than two keeps a 64-lane world's work-group small enough for a
+  // seventh humanoid world per CU.
+  {
+    std::vector<uint8_t> entry;
+    for (int b = 0; b < h.nv; b++)
+      for (int a = 0; a <= b; a++) entry.push_back((uint8_t)b);
+    while (entry.size() & 3) entry.push_back(0);
+    std::vector<uint32_t> tri_pair(entry.size() / 4);  // little-endian bytes
+    for (size_t k = 0; k < tri_pair.size(); k++)
+      tri_pair[k] = (uint32_t)entry[4 * k] | ((uint32_t)entry[4 * k + 1] << 8) |
+                    ((uint32_t)entry[4 * k + 2] << 16) | ((uint32_t)entry[4 * k + 3] << 24);
+    pk.add(tri_pair, &d.tri_pair);
+  }
   // adjoint layout: the same tables, every region separate, plus the reverse-sweep
   // scratch (cotangents of dofs, bodies, rows and contacts)
   DevModel& x = rec.dm_adj;
@@ -523,7 +536,7 @@ static mjh_status sync_tables(mjh_batch* b) {
   size_t lds = 0;
   int tab_words = 0;
   for (const GroupRec& gr : b->groups)
-    if (gr.nworld > 0) tab_words = std::max(tab_words, table_words(ctx->models[gr.model]->dm.ntri));
+    if (gr.nworld > 0) tab_words = std::max(tab_words, table_words(ctx->models[gr.model]->dm));
   for (size_t g = 0; g < b->groups.size(); g++) {
     const GroupRec& gr = b->groups[g];
     const ModelRec& mr = *ctx->models[gr.model];
@@ -611,7 +624,7 @@ mjh_status mjh_model_upload(mjh_ctx* ctx, const void* blob, size_t nbytes, int32
   Packer pk;
   st = compile_model(rec->h, *rec, pk, err);
   if (st != MJH_OK) return fail(ctx, st, err);
-  if ((size_t)(rec->dm.lds_words + table_words(rec->dm.ntri)) * 4 > ctx->lds_limit)
+  if ((size_t)(rec->dm.lds_words + table_words(rec->dm)) * 4 > ctx->lds_limit)
     return fail(ctx, MJH_EUNSUPPORTED, "model working set exceeds the device's LDS per work-group");
   MJH_HIP(hipSetDevice(ctx->device));
   MJH_HIP(hipMalloc(&rec->dbuf, pk.bytes.size()));
@@ -683,9 +696,11 @@ mjh_status mjh_world_alloc(mjh_ctx* ctx, const int32_t* model_ids, const int32_t
     gr.model = model_ids[g];
     gr.nworld = counts[g];
     const DevModel& d = ctx->models[gr.model]->dm;
-    // default launch shape: small trees take half a wavefront, large ones a whole one
+    // default launch shape: small trees take a quarter or half of a wavefront, large
+    // ones a whole one.  A whole-wavefront world is its own work-group, so the LDS of a
+    // CU can be filled one world at a time.
     gr.team = d.nv <= 8 ? 16 : (d.nrowmax <= 32 ? 32 : 64);
-    gr.block = 128;
+    gr.block = gr.team == 64 ? 64 : 128;
     b->groups.push_back(gr);
   }
   *out = b;

@@ -38,12 +38,11 @@ DEV int opaque_zero() {
 struct Team {
   int lane;       // 0 .. T-1
   int T;          // lanes per world: 16, 32 or 64
-  const unsigned short* tp;  // triangular pair table in LDS: tp[p] = (b << 8) | a, p = b(b+1)/2 + a
-  // p -> (b, a) with 0 <= a <= b
+  const unsigned char* tp;  // triangle table in LDS: tp[p] = b for p = b(b+1)/2 + a
+  // packed index p -> (b, a) with 0 <= a <= b
   DEV void unrank(int p, int& b, int& a) const {
-    const int v = tp[p];
-    b = v >> 8;
-    a = v & 0xff;
+    b = tp[p];
+    a = p - (__mul24(b, b + 1) >> 1);
   }
   // wavefront-level barrier: orders LDS traffic of all lanes of the wave
   DEV void sync() const {
@@ -1283,22 +1282,15 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int ite
 // ------------------------------------------------- A10: forces, A11: integration
 DEV void export_contacts(const DevModel& m, float* W, const Team& t, float* out, int* nout) {
   const int* scal = (const int*)(W + m.o_scal);
-  const int ncon = scal[SC_NCON], nv = m.nv;
+  const int ncon = scal[SC_NCON];
   const float* con = W + m.o_con;
-  const float* J = W + m.o_J;
-  const float* aref = W + m.o_aref;
   const float* D = W + m.o_D;
-  const float* a = W + m.o_qacc;
+  const float* er = W + m.o_e;  // J qacc - aref, kept current by the Newton updates
   for (int idx = ncon * kConOut + t.lane; idx < m.nconmax * kConOut; idx += t.T) out[idx] = 0.f;
   for (int c = t.lane; c < ncon; c += t.T) {
     const float* r = con + kConRec * c;
     float f[4];
-    for (int e = 0; e < 4; e++) {
-      const int row = 4 * c + e;
-      float ja = 0.f;
-      for (int i = 0; i < nv; i++) ja += J[row * nv + i] * a[i];
-      f[e] = fmaxf(D[row] * (aref[row] - ja), 0.f);
-    }
+    for (int e = 0; e < 4; e++) f[e] = fmaxf(-D[4 * c + e] * er[4 * c + e], 0.f);
     float* o = out + kConOut * c;
     for (int k = 0; k < 13; k++) o[k] = r[k];
     o[13] = f[0] + f[1] + f[2] + f[3];
@@ -1421,7 +1413,7 @@ DEV void world_step(const DevModel& m, float* W0, const Team& t0, const float* c
 // copy a model's triangular pair table to the head of the work-group's LDS (all
 // threads of the work-group take part; call before any team leaves)
 DEV void load_pair_table(const DevModel& m, unsigned* tab) {
-  for (int k = threadIdx.x; k < (m.ntri + 1) / 2; k += blockDim.x) tab[k] = m.tri_pair[k];
+  for (int k = threadIdx.x; k < (m.ntri + 3) / 4; k += blockDim.x) tab[k] = m.tri_pair[k];
   __syncthreads();
 }
 

@@ -9,7 +9,9 @@ namespace mjh {
 constexpr int kMaxBlock = 256;  // threads per work-group of the step kernel
 
 // LDS words of a work-group's triangular pair table (16-byte aligned)
-__host__ __device__ inline int table_words(int ntri) { return ((ntri + 1) / 2 + 3) & ~3; }
+__host__ __device__ inline int table_words(const DevModel& m) {
+  return ((m.ntri + 3) / 4 + 3) & ~3;
+}
 
 // Launch the step kernel: one work-group of `block` threads per task.
 hipError_t launch_step(const DevGroup* groups, const DevTask* tasks, int ntask, int nstep,

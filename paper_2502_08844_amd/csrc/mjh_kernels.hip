@@ -20,7 +20,7 @@ __device__ long long g_phase_cycles[kPhaseWorlds * 8];
 #endif
 
 __device__ void run_worlds(const DevGroup& G, float* W, int world, int nstep, int lane, int T,
-                           const unsigned short* tab) {
+                           const unsigned char* tab) {
   const DevModel& m = G.m;
   const Team t{lane, T, tab};
   world_init(m, W, t);
@@ -81,7 +81,7 @@ mjh_step_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__
   float* W = lds + tab_words + (size_t)team * G.m.lds_words;
   const int lane = threadIdx.x - team * T;
   const int world = tk.w0 + team;
-  run_worlds(G, W, world, nstep, lane, T, (const unsigned short*)lds);
+  run_worlds(G, W, world, nstep, lane, T, (const unsigned char*)lds);
 }
 
 // Translational inverse weight of every body at qpos0:
@@ -91,15 +91,18 @@ __global__ void __launch_bounds__(64) mjh_invweight_kernel(DevModel m, int tab_w
   extern __shared__ float lds[];
   load_pair_table(m, (unsigned*)lds);
   float* W = lds + tab_words;
-  const Team t{(int)threadIdx.x, 64, (const unsigned short*)lds};
+  const Team t{(int)threadIdx.x, 64, (const unsigned char*)lds};
   world_init(m, W, t);
   for (int i = t.lane; i < m.nq; i += t.T) W[m.o_qpos + i] = m.qpos0[i];
   t.sync();
   forward_sweep(m, W, t);
   backward_and_mass(m, W, t);
   ltdl_factor(m, W, t);
-  float* jr = W + m.o_tmp;
-  float* x = W + m.o_d;
+  // scratch: the smooth-force and unconstrained-acceleration vectors, unused here (the
+  // Newton vectors share words with the poses read below, and the sweep scratch with
+  // the factor in H)
+  float* jr = W + m.o_frc;
+  float* x = W + m.o_a0;
   const float* cdof = W + m.o_cdof;
   for (int b = 0; b < m.nbody; b++) {
     if (b == 0) {
@@ -146,7 +149,7 @@ hipError_t set_step_lds_limit(size_t bytes) {
 }
 
 hipError_t launch_invweight(const DevModel& m, hipStream_t stream) {
-  const int tab = table_words(m.ntri);
+  const int tab = table_words(m);
   const size_t lds = (size_t)(tab + m.lds_words) * sizeof(float);
   hipError_t e = hipFuncSetAttribute((const void*)mjh_invweight_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -56,8 +56,8 @@ struct DevModel {
   const int* anc_list;
   const int* mpair;         // [nmpair] (i << 16) | j, j ancestor-or-self of i
   const unsigned long long* body_dofmask;  // dofs on the path body -> root
-  const unsigned* tri_pair;  // [(ntri + 1) / 2] 16-bit entries (b << 8) | a for packed
-                             // index p = b (b + 1) / 2 + a, two per word (p even: low half)
+  const unsigned* tri_pair;  // [(ntri + 3) / 4] row b of packed index p = b (b + 1) / 2 + a,
+                             // one byte each, four per word (p % 4 == 0: low byte)
   const int* geom_type;
   const int* geom_body;
   const int* pair_g1;
