@@ -915,9 +915,9 @@ DEV int pad_rows(const DevModel& m, float* W, const Team& t, int nrow) {
 
 // H = M + sum_{rows with e < 0} D J^T J (packed lower), factorised in place as L L^T.
 // nru is the padded row bound of pad_rows.
-// Right-looking; a column is used unscaled by its own trailing update and scaled in
-// the next barrier interval.  With nv <= T two columns share a barrier, otherwise each
-// column costs one.  When `y` is given the
+// Right-looking.  With nv <= T four columns share two barriers; otherwise each column
+// costs one, used unscaled by its own trailing update and scaled in the next barrier
+// interval.  When `y` is given the
 // forward solve L y = b (b overwritten) rides along.  Returns false for a non-positive
 // pivot.  `w` (nrow words) receives the active rows' weights D (0 when inactive).
 DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
@@ -971,76 +971,90 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
   t.sync();
   bool ok = true;
   if (nv <= t.T) {
-    // Two columns (j, j + 1) per barrier.  With p0 = H_jj and l = H_{j+1,j}, the
-    // second column after the first one's update is u_i = H_{i,j+1} - H_ij l / p0 and
-    // its pivot p1 = H_{j+1,j+1} - l^2 / p0; every trailing entry then takes both
-    // rank-1 updates, H_ik -= H_ij H_kj / p0 + u_i u_k / p1, recomputing u_i and u_k
-    // from the entries as they were at the block's start, so the two columns need no
-    // barrier between them.  Lane r keeps u for row j + 2 + r in a register; both
-    // columns are scaled to L in the next block, which does not read them.
-    float u_own = 0.f;
-    int pc = -1;
-    bool ptwo = false;
-    float pd0 = 1.f, pi0 = 1.f, pd1 = 1.f, pi1 = 1.f;
-    for (int j = 0;; j += 2) {
-      if (pc >= 0) {
-        const int r0w = pc + 1 + t.lane;
-        if (r0w < nv) H[tri(r0w, pc)] *= pi0;
-        if (ptwo) {
-          const int r1w = pc + 2 + t.lane;
-          if (r1w < nv) H[tri(r1w, pc + 1)] = u_own * pi1;
-          if (t.lane == 0) H[tri(pc + 1, pc + 1)] = pd1;
+    // Blocks of four columns, two barriers each; lane r owns row r.
+    //  A: every lane eliminates the 4 x 4 diagonal block in registers (the same values
+    //     in all lanes; lane a stores row a of the factor after the barrier).  Lane i
+    //     of a row below the block applies the block's columns, in order, to its four
+    //     entries and stores them as L.  The forward solve takes the same columns.
+    //  B: every trailing entry takes the block's four rank-1 updates in one pass.
+    const int i = t.lane;
+    for (int j = 0; j < nv; j += 4) {
+      const int bw = min(4, nv - j);
+      float P[4][4], in[4];
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c <= a; c++) P[a][c] = (a < bw) ? H[tri(j + a, j + c)] : 0.f;
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        const float pc = c < bw ? P[c][c] : 1.f;
+        ok = ok && (pc > 0.f);
+        in[c] = 1.f / sqrtf(fmaxf(pc, 1e-30f));
+        const float rc = in[c] * in[c];
+#pragma unroll
+        for (int a = c + 1; a < 4; a++)
+#pragma unroll
+          for (int a2 = c + 1; a2 <= a; a2++) P[a][a2] -= P[a][c] * P[a2][c] * rc;
+      }
+      float dr[4];  // row i of the block's factor, for lane i < bw (sqrt(p) = p / sqrt(p))
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        float v = 0.f;
+#pragma unroll
+        for (int a = c; a < 4; a++) v = (i == a) ? P[a][c] * in[c] : v;
+        dr[c] = v;
+      }
+      const bool prow = i >= j + bw && i < nv;
+      float u[4] = {0.f, 0.f, 0.f, 0.f};  // this row's L entries of the block
+      if (prow) {
+        const int ri = tri(i, j);
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+          float v = c < bw ? H[ri + c] : 0.f;
+#pragma unroll
+          for (int c2 = 0; c2 < c; c2++) v -= u[c2] * P[c][c2] * in[c2];
+          u[c] = v * in[c];
+          if (c < bw) H[ri + c] = u[c];
         }
-        if (t.lane == 0) H[tri(pc, pc)] = pd0;
       }
-      if (j >= nv) {
-        t.sync();
-        break;
+      if (y) {  // L y = b for the block's columns; rows below take their updates
+        float yv[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+          float v = c < bw ? b[j + c] : 0.f;
+#pragma unroll
+          for (int c2 = 0; c2 < c; c2++) v -= P[c][c2] * in[c2] * yv[c2];
+          yv[c] = v * in[c];
+        }
+        if (prow) {
+          float v = b[i];
+#pragma unroll
+          for (int c = 0; c < 4; c++) v -= u[c] * yv[c];
+          b[i] = v;
+        }
+        if (t.lane == 0) {
+#pragma unroll
+          for (int c = 0; c < 4; c++)
+            if (c < bw) y[j + c] = yv[c];
+        }
       }
-      const bool two = j + 1 < nv;
-      const float p0 = H[tri(j, j)];
-      ok = ok && (p0 > 0.f);
-      const float d0 = sqrtf(fmaxf(p0, 1e-30f)), i0 = 1.f / d0, r0 = i0 * i0;
-      float l10 = 0.f, d1 = 1.f, i1 = 1.f, r1 = 0.f;
-      if (two) {
-        l10 = H[tri(j + 1, j)];
-        const float p1 = H[tri(j + 1, j + 1)] - l10 * l10 * r0;
-        ok = ok && (p1 > 0.f);
-        d1 = sqrtf(fmaxf(p1, 1e-30f));
-        i1 = 1.f / d1;
-        r1 = i1 * i1;
+      t.sync();
+      if (i < bw) {  // every lane has read the block: store row j + i of its factor
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+          if (c <= i) H[tri(j + i, j + c)] = dr[c];
       }
-      const float lr = l10 * r0;
-      const int c = j + (two ? 2 : 1);  // first trailing row and column
-      const int n2 = nv - c, npr = n2 * (n2 + 1) / 2;
+      const int c0 = j + bw, n2 = nv - c0, npr = n2 * (n2 + 1) / 2;
       for (int p = t.lane; p < npr; p += t.T) {
         int bi, ai;
         t.unrank(p, bi, ai);
-        const int i = c + bi, k = c + ai;
-        const int ri = tri(i, 0), rk = tri(k, 0);
-        const float hij = H[ri + j], hkj = H[rk + j];
-        float v = H[ri + k] - hij * hkj * r0;
-        if (two) {
-          const float ui = H[ri + j + 1] - hij * lr;
-          const float uk = H[rk + j + 1] - hkj * lr;
-          v -= ui * uk * r1;
-        }
-        H[ri + k] = v;
+        const int ri = tri(c0 + bi, 0), rk = tri(c0 + ai, 0);
+        float v = H[ri + c0 + ai];
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+          if (c < bw) v -= H[ri + j + c] * H[rk + j + c];
+        H[ri + c0 + ai] = v;
       }
-      const int ir = c + t.lane;
-      u_own = (two && ir < nv) ? H[tri(ir, j + 1)] - H[tri(ir, j)] * lr : 0.f;
-      if (y) {  // L y = b for the two columns; rows below take both updates
-        const float y0 = b[j] * i0;
-        const float y1 = two ? (b[j + 1] - l10 * i0 * y0) * i1 : 0.f;
-        if (ir < nv) b[ir] -= H[tri(ir, j)] * i0 * y0 + u_own * i1 * y1;
-        if (t.lane == 0) {
-          y[j] = y0;
-          if (two) y[j + 1] = y1;
-        }
-      }
-      pc = j;
-      ptwo = two;
-      pd0 = d0; pi0 = i0; pd1 = d1; pi1 = i1;
       t.sync();
     }
     return ok;
