@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--model", default="quadruped",
-                    choices=["quadruped", "humanoid", "hand", "cartpole"],
+                    choices=["quadruped", "quadruped_limits", "humanoid", "hand", "cartpole"],
                     help="robot of the timed batch (the headline metric is the quadruped)")
     ap.add_argument("--nworld", type=int, default=8192)
     ap.add_argument("--nstep", type=int, default=1000)
@@ -82,6 +82,8 @@ def parse():
                     help="skip the adjoint-rollout comparison (1024 worlds, horizon 64)")
     ap.add_argument("--no-hetero", action="store_true",
                     help="skip the heterogeneous-batch comparison")
+    ap.add_argument("--no-limits", action="store_true",
+                    help="skip the joint-limit workload (quadruped with limited hinges)")
     ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a reference "
@@ -182,6 +184,37 @@ def rollout_compare(ctx, seed, nw=1024, horizon=64, ckpt=8, reps=3):
             "launch": [team, block]}
 
 
+def limits_compare(ctx, seed, nw=8192, nstep=1000, reps=3):
+    """The quadruped with every hinge limited (joint-limit rows beside the contacts),
+    8192 worlds x 1000 steps in its default launch, next to the plain quadruped."""
+    import torch
+    from paper_2502_08844_amd import mjh
+    from paper_2502_08844_amd.synth import inputs, robots
+    stream = torch.cuda.current_stream()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    kind = "quadruped_limits"
+    m = robots.WORKLOADS[kind]()
+    qp, qv = inputs.initial_state(kind, m, nw, seed=seed)
+    w = mjh.World(ctx, ctx.model_upload(m), nw, qpos=qp, qvel=qv)
+    u = (torch.rand((nstep, nw, m.nu), device="cuda", generator=gen) - 0.5).contiguous()
+    w.batch.bind_io(0, u)
+    q0, v0 = w.qpos.clone(), w.qvel.clone()
+
+    def run():
+        w.qpos.copy_(q0); w.qvel.copy_(v0); w.qacc_ws.zero_()
+        w.batch.step(nstep, stream)
+    run()
+    ms = timed(run, stream, reps)
+    status = w.status.cpu()
+    return {"workload": f"quadruped with limited hinges (default angle +- 0.15 rad), {nw} "
+                        f"worlds x {nstep} steps",
+            "world_steps_per_s": round(nw * nstep / (ms * 1e-3), 1),
+            "nrowmax": 4 * m.opt.nconmax + m.nlimit,
+            "launch": list(w.batch.get_launch(0)),
+            "status_nonzero_worlds": int((status != 0).sum())}
+
+
 def hetero_compare(ctx, seed, nstep=500, reps=3):
     """4096 quadruped + 2048 humanoid + 2048 hand worlds in one autotuned launch replayed
     from a HIP graph, against the three models stepped by their own default launches."""
@@ -274,7 +307,7 @@ def main():
     # controls resampled every step, resident in HBM, drawn on the device with the
     # distributions of the synthetic workloads
     shape = (ns, nw, m.nu)
-    if kind == "quadruped":    # PD target offsets U(-0.5, 0.5)
+    if kind in ("quadruped", "quadruped_limits"):  # PD target offsets U(-0.5, 0.5)
         ctrl = torch.rand(shape, device=dev, generator=gen) - 0.5
     elif kind == "humanoid":   # torques N(0, 0.3) clipped to [-1, 1]
         ctrl = (0.3 * torch.randn(shape, device=dev, generator=gen)).clamp_(-1.0, 1.0)
@@ -358,6 +391,8 @@ def main():
         out["rollout"] = rollout_compare(ctx, args.seed)
     if not args.no_hetero:
         out["hetero"] = hetero_compare(ctx, args.seed)
+    if not args.no_limits:
+        out["limits"] = limits_compare(ctx, args.seed)
     if not args.no_cpu_baseline:
         nthreads = min(os.cpu_count() or 1, 16)
         cw = min(args.cpu_sample_worlds, nw)

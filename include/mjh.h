@@ -74,6 +74,8 @@ typedef struct mjh_dims {
   int32_t iterations; /* Newton iterations per step                              */
   int32_t lds_bytes;  /* on-chip working set of one world                        */
   float timestep;
+  int32_t nlimit;     /* limited hinge/slide joints (at most one row each)        */
+  int32_t nrowmax;    /* constraint rows per world: 4 nconmax + nlimit            */
 } mjh_dims;
 
 /* One context per device.  device: HIP device ordinal.  *out receives the handle. */
@@ -84,8 +86,15 @@ const char* mjh_last_error(const mjh_ctx* ctx);
 
 /* Parse a model blob (host memory, the layout written by the Python model module:
  * header, bodies, joints, geoms, pairs, actuators, qpos0), derive the tree tables,
- * upload FP32 constants and compute the bodies' translational inverse weights at
- * qpos0 on the device.  *model_id receives a handle valid until mjh_destroy.
+ * upload FP32 constants and compute the bodies' translational inverse weights and the
+ * limited dofs' inverse weights at qpos0 on the device.  *model_id receives a handle
+ * valid until mjh_destroy.
+ * Joint limits (a hinge or slide joint with range lo < hi) are one-sided soft
+ * constraints of the same convex model as the contacts (Todorov 2014, which the paper's
+ * MJX physics uses): a joint whose coordinate q lies outside its range adds one row
+ * after the contact rows, in joint order, with distance r = q - lo and J = e_dof below
+ * the range, r = hi - q and J = -e_dof above it, and the regulariser's A = (M^-1)_kk
+ * at qpos0.
  * MJH_EMODEL for a malformed blob, MJH_EUNSUPPORTED for nv > 64, box-box pairs,
  * a free joint below the root or two actuators on one dof. */
 mjh_status mjh_model_upload(mjh_ctx* ctx, const void* blob, size_t nbytes,
@@ -94,6 +103,9 @@ mjh_status mjh_model_info(mjh_ctx* ctx, int32_t model_id, mjh_dims* out);
 /* Copy the model's body translational inverse weights (nbody floats, host memory).
  * They scale the contact regulariser: R = (1-d)/d * (1+mu^2) * (w(body1) + w(body2)). */
 mjh_status mjh_model_invweight(mjh_ctx* ctx, int32_t model_id, float* out);
+/* Copy the limited joints' dof inverse weights (M^-1)_kk at qpos0 (nlimit floats, host
+ * memory, joint order): the A of a joint-limit row, R = (1-d)/d * A. */
+mjh_status mjh_model_limit_invweight(mjh_ctx* ctx, int32_t model_id, float* out);
 
 /* A batch of worlds made of nmodel groups: counts[g] worlds of model model_ids[g].
  * Groups are stepped together in one launch.  counts[g] >= 0. */

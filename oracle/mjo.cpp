@@ -227,8 +227,8 @@ struct Model {
   double tolerance = 0;
   std::vector<int> body_parent;
   std::vector<double> body_pos, body_quat, body_mass, body_ipos, body_inertia;
-  std::vector<int> jnt_type, jnt_body;
-  std::vector<double> jnt_pos, jnt_axis, jnt_damping, jnt_armature;
+  std::vector<int> jnt_type, jnt_body, jnt_limited;
+  std::vector<double> jnt_pos, jnt_axis, jnt_damping, jnt_armature, jnt_range;
   std::vector<int> geom_type, geom_body;
   std::vector<double> geom_size, geom_pos, geom_quat, geom_friction;
   std::vector<int> pair_g1, pair_g2;
@@ -241,6 +241,8 @@ struct Model {
   std::vector<int> dof_body, dof_jnt, dof_parent;
   std::vector<double> dof_damping, dof_armature;
   std::vector<double> body_invweight;
+  std::vector<double> dof_invweight;  // (M^-1)_kk at qpos0
+  int nlimit = 0;                     // limited joints
 };
 
 struct Reader {
@@ -882,9 +884,24 @@ template <class T> T impedance(const Model& m, T r) {
 //   J_e = J_n +- mu J_t;  aref = -b (J_e qvel) - k d(r) r;  R = (1-d)/d * A, D = 1/R,
 //   k = 1/(dmax^2 tc^2 zeta^2), b = 2/(dmax tc) with (tc, zeta) = solref, tc >= 2 dt,
 //   A = (1 + mu^2)(w(b1) + w(b2)) with w the bodies' translational inverse weights.
+//
+// Joint limits follow the contacts, one row per limited hinge or slide joint whose
+// coordinate lies outside its range, in joint order: distance r = q - lo (row J = e_k)
+// or r = hi - q (J = -e_k), the same aref, impedance and R with A = (M^-1)_kk at qpos0.
 template <class T> void constraint_rows(const Model& m, Data<T>& d) {
   const int nc = (int)d.con.size(), n = m.nv;
-  d.nrow = 4 * nc;
+  std::vector<int> lim_dof;
+  std::vector<double> lim_sign;
+  std::vector<T> lim_dist;
+  for (int j = 0; j < m.njnt; j++) {
+    if (!m.jnt_limited[j]) continue;
+    const T q = d.qpos[m.jnt_qposadr[j]];
+    const T rlo = q - m.jnt_range[2 * j], rhi = m.jnt_range[2 * j + 1] - q;
+    if (rlo < 0.0) { lim_dof.push_back(m.jnt_dofadr[j]); lim_sign.push_back(1.0); lim_dist.push_back(rlo); }
+    else if (rhi < 0.0) { lim_dof.push_back(m.jnt_dofadr[j]); lim_sign.push_back(-1.0); lim_dist.push_back(rhi); }
+  }
+  const int nl = (int)lim_dof.size();
+  d.nrow = 4 * nc + nl;
   d.J.assign(d.nrow * n, 0.0);
   d.aref.assign(d.nrow, 0.0);
   d.D.assign(d.nrow, 0.0);
@@ -920,6 +937,15 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
       d.aref[row] = -B * jv - K * imp * k.dist;
       d.D[row] = 1.0 / R;
     }
+  }
+  for (int l = 0; l < nl; l++) {
+    const int row = 4 * nc + l, k = lim_dof[l];
+    d.J[row * n + k] = lim_sign[l];
+    const T imp = impedance(m, lim_dist[l]);
+    const double A = std::max(m.dof_invweight[k], 1e-15);
+    const T R = (1.0 - imp) / imp * A;
+    d.aref[row] = -B * (lim_sign[l] * d.qvel[k]) - K * imp * lim_dist[l];
+    d.D[row] = 1.0 / R;
   }
 }
 
@@ -1146,7 +1172,7 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   r.read(hi, 16);
   r.read(hf, 16);
   if (!r.ok) { err = "blob too short"; return false; }
-  if (hi[0] != 0x4D484A4D || hi[1] != 1) { err = "bad magic/version"; return false; }
+  if (hi[0] != 0x4D484A4D || hi[1] != 2) { err = "bad magic/version"; return false; }
   m.nbody = hi[2]; m.njnt = hi[3]; m.ngeom = hi[4]; m.npair = hi[5]; m.nu = hi[6];
   m.nq = hi[7]; m.nv = hi[8]; m.iterations = hi[9]; m.ls_iterations = hi[10];
   m.nconmax = hi[11];
@@ -1161,8 +1187,8 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   std::vector<int32_t> bi(2 * m.nbody);
   std::vector<double> bf(19 * m.nbody);
   r.read(bi.data(), bi.size()); r.read(bf.data(), bf.size());
-  std::vector<int32_t> ji(2 * m.njnt);
-  std::vector<double> jf(8 * m.njnt);
+  std::vector<int32_t> ji(4 * m.njnt);
+  std::vector<double> jf(10 * m.njnt);
   r.read(ji.data(), ji.size()); r.read(jf.data(), jf.size());
   std::vector<int32_t> gi(2 * m.ngeom);
   std::vector<double> gf(11 * m.ngeom);
@@ -1187,19 +1213,27 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
     if (b > 0 && (bi[2 * b] < 0 || bi[2 * b] >= b)) { err = "body order"; return false; }
   }
   for (int j = 0; j < m.njnt; j++) {
-    m.jnt_type.push_back(ji[2 * j]);
-    m.jnt_body.push_back(ji[2 * j + 1]);
-    const double* f = &jf[8 * j];
+    const int* jj = &ji[4 * j];
+    m.jnt_type.push_back(jj[0]);
+    m.jnt_body.push_back(jj[1]);
+    m.jnt_limited.push_back(jj[2] != 0);
+    const double* f = &jf[10 * j];
     m.jnt_pos.insert(m.jnt_pos.end(), f, f + 3);
     double ax[3] = {f[3], f[4], f[5]};
     double L = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
     for (int k = 0; k < 3; k++) m.jnt_axis.push_back(L > 0 ? ax[k] / L : 0.0);
     m.jnt_damping.push_back(f[6]);
     m.jnt_armature.push_back(f[7]);
-    if (ji[2 * j] < 0 || ji[2 * j] > 2 || ji[2 * j + 1] <= 0 || ji[2 * j + 1] >= m.nbody) {
+    m.jnt_range.push_back(f[8]);
+    m.jnt_range.push_back(f[9]);
+    if (jj[0] < 0 || jj[0] > 2 || jj[1] <= 0 || jj[1] >= m.nbody) {
       err = "bad joint"; return false;
     }
-    if (j > 0 && ji[2 * j + 1] < ji[2 * j - 1]) { err = "joints not grouped by body"; return false; }
+    if (j > 0 && jj[1] < ji[4 * (j - 1) + 1]) { err = "joints not grouped by body"; return false; }
+    if (jj[2] != 0) {
+      if (jj[0] == JFREE || !(f[8] < f[9])) { err = "bad joint limit"; return false; }
+      m.nlimit++;
+    }
   }
   for (int g = 0; g < m.ngeom; g++) {
     m.geom_type.push_back(gi[2 * g]);
@@ -1284,6 +1318,15 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
       }
       m.body_invweight[b] = tr / 3.0;
     }
+    // joint-limit rows: the dof's own inverse weight (M^-1)_kk at qpos0
+    m.dof_invweight.assign(m.nv, 0.0);
+    std::vector<double> e(m.nv);
+    for (int k = 0; k < m.nv; k++) {
+      std::fill(e.begin(), e.end(), 0.0);
+      e[k] = 1.0;
+      solve_ltdl(m, d.qLD, e.data(), x.data());
+      m.dof_invweight[k] = x[k];
+    }
   }
   return true;
 }
@@ -1340,11 +1383,11 @@ void* mjo_load(const unsigned char* blob, long nbytes, char* err, int errlen) {
 
 void mjo_free(void* h) { delete static_cast<Model*>(h); }
 
-// out[0..11] = nq nv nu nbody njnt ngeom npair nconmax iterations ls_iterations
+// out[0..10] = nq nv nu nbody njnt ngeom npair nconmax iterations ls_iterations nlimit
 int mjo_dims(void* h, int* out) {
   Model& m = *static_cast<Model*>(h);
-  int v[10] = {m.nq, m.nv, m.nu, m.nbody, m.njnt, m.ngeom, m.npair, m.nconmax,
-               m.iterations, m.ls_iterations};
+  int v[11] = {m.nq, m.nv, m.nu, m.nbody, m.njnt, m.ngeom, m.npair, m.nconmax,
+               m.iterations, m.ls_iterations, m.nlimit};
   std::memcpy(out, v, sizeof(v));
   return 0;
 }
@@ -1352,6 +1395,12 @@ int mjo_dims(void* h, int* out) {
 int mjo_body_invweight(void* h, double* out) {
   Model& m = *static_cast<Model*>(h);
   for (int b = 0; b < m.nbody; b++) out[b] = m.body_invweight[b];
+  return 0;
+}
+
+int mjo_dof_invweight(void* h, double* out) {
+  Model& m = *static_cast<Model*>(h);
+  for (int k = 0; k < m.nv; k++) out[k] = m.dof_invweight[k];
   return 0;
 }
 
@@ -1420,8 +1469,9 @@ int mjo_step(void* h, int nworld, int nstep, double* qpos, double* qvel, double*
 // Intermediates of one forward evaluation (no integration) of a single world.
 // Output sizes: xpos [nbody*3], xmat [nbody*9], xipos [nbody*3], cdof [nv*6],
 // cvel [nbody*6], M [nv*nv], bias [nv], act [nv], pass [nv], qacc_smooth [nv],
-// qacc [nv], qfrc_con [nv], ncon, contacts [nconmax*20], nrow, J [4 nconmax * nv],
-// aref [4 nconmax], D [4 nconmax], efc_force [4 nconmax].  NULL skips an output.
+// qacc [nv], qfrc_con [nv], ncon, contacts [nconmax*20], nrow, J [nrowmax * nv],
+// aref, D, efc_force [nrowmax] with nrowmax = 4 nconmax + nlimit (contact rows first,
+// then the active limit rows).  NULL skips an output.
 int mjo_forward(void* h, const double* qpos, const double* qvel, const double* qacc_ws,
                 const double* ctrl, int mode, double* xpos, double* xmat, double* xipos,
                 double* cdof, double* cvel, double* M, double* bias, double* act,

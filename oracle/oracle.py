@@ -50,6 +50,7 @@ def _load():
         lib.mjo_free.argtypes = [P]
         lib.mjo_dims.argtypes = [P, I]
         lib.mjo_body_invweight.argtypes = [P, D]
+        lib.mjo_dof_invweight.argtypes = [P, D]
         lib.mjo_dof_parent.argtypes = [P, I]
         lib.mjo_step.argtypes = [P, C.c_int, C.c_int, D, D, D, D, C.c_int, C.c_int, D, D, I,
                                  I, D]
@@ -98,10 +99,12 @@ class Oracle:
         self._h = self._lib.mjo_load(bytes(blob), len(blob), err, 256)
         if not self._h:
             raise ValueError("oracle rejected model: " + err.value.decode())
-        dims = np.zeros(10, dtype=np.int32)
+        dims = np.zeros(11, dtype=np.int32)
         self._lib.mjo_dims(self._h, _i(dims))
         (self.nq, self.nv, self.nu, self.nbody, self.njnt, self.ngeom, self.npair,
-         self.nconmax, self.iterations, self.ls_iterations) = (int(x) for x in dims)
+         self.nconmax, self.iterations, self.ls_iterations, self.nlimit) = \
+            (int(x) for x in dims)
+        self.nrowmax = 4 * self.nconmax + self.nlimit
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -112,6 +115,12 @@ class Oracle:
     def body_invweight(self) -> np.ndarray:
         out = np.zeros(self.nbody)
         self._lib.mjo_body_invweight(self._h, _d(out))
+        return out
+
+    def dof_invweight(self) -> np.ndarray:
+        """(M^-1)_kk at qpos0, the A of a joint-limit row on dof k."""
+        out = np.zeros(self.nv)
+        self._lib.mjo_dof_invweight(self._h, _d(out))
         return out
 
     def dof_parent(self) -> np.ndarray:
@@ -141,6 +150,7 @@ class Oracle:
     def forward(self, qpos, qvel=None, qacc_ws=None, ctrl=None, mode=MODE_FIXED):
         """All intermediates of one forward evaluation of a single world."""
         nv, nb, nc = self.nv, self.nbody, max(self.nconmax, 1)
+        nr = max(self.nrowmax, 1)
         qpos = _arr(qpos, self.nq)
         qvel = _arr(qvel, nv) if qvel is not None else np.zeros(nv)
         ws = _arr(qacc_ws, nv) if qacc_ws is not None else np.zeros(nv)
@@ -149,8 +159,8 @@ class Oracle:
                  cdof=np.zeros((nv, 6)), cvel=np.zeros((nb, 6)), M=np.zeros((nv, nv)),
                  bias=np.zeros(nv), act=np.zeros(nv), passive=np.zeros(nv),
                  qacc_smooth=np.zeros(nv), qacc=np.zeros(nv), qfrc_con=np.zeros(nv),
-                 contacts=np.zeros((nc, CON_SIZE)), J=np.zeros((4 * nc, nv)),
-                 aref=np.zeros(4 * nc), D=np.zeros(4 * nc), efc_force=np.zeros(4 * nc))
+                 contacts=np.zeros((nc, CON_SIZE)), J=np.zeros((nr, nv)),
+                 aref=np.zeros(nr), D=np.zeros(nr), efc_force=np.zeros(nr))
         ncon = np.zeros(1, dtype=np.int32)
         nrow = np.zeros(1, dtype=np.int32)
         status = np.zeros(1, dtype=np.int32)

@@ -112,7 +112,9 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
   const int nv = m.nv, nb = m.nbody;
   const float h = m.dt;
   const int ncon = ((const int*)(W + m.o_scal))[SC_NCON];
-  const int nrow = 4 * ncon;
+  const int nrow = ((const int*)(W + m.o_scal))[SC_NROW];
+  const int nrc = 4 * ncon;  // contact rows; joint-limit rows follow
+  const int* lim = (const int*)(W + m.o_lim);
   const float* qpos = W + m.o_qpos;
   const float* qvel = W + m.o_qvel;
   const float* a = W + m.o_qacc;
@@ -360,8 +362,14 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
       }
       float al = 0.f, be = 0.f, ga = 0.f, rho = 0.f;
       if (e[r] < 0.f) {
-        const float* rec = con + kConRec * (r >> 2);
-        const float dist = rec[0];
+        float dist;
+        if (r < nrc) {
+          dist = con[kConRec * (r >> 2)];
+        } else {
+          int dof;
+          float sg;
+          limit_row(m, W, lim[r - nrc], dof, sg, dist);
+        }
         float d, dd;
         impedance_d(m, dist, d, dd);
         const float Dv = D[r];
@@ -386,6 +394,7 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
         const float* o = rs + 7 * r;
         if (!(e[r] < 0.f)) continue;
         vadd += o[4] * J[r * nv + k];
+        if (r >= nrc) continue;  // a limit row's Jacobian is constant
         const float* rec = con + kConRec * (r >> 2);
         const int b1 = __float_as_int(rec[14]), b2 = __float_as_int(rec[15]);
         const bool in2 = (m.body_dofmask[b2] & bit) != 0, in1 = (m.body_dofmask[b1] & bit) != 0;
@@ -445,6 +454,13 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
       o[3] = gp[0]; o[4] = gp[1]; o[5] = gp[2];
       o[6] = __int_as_float(b2);
       o[7] = (kind == PK_PLANE_SPHERE || kind == PK_PLANE_CAPSULE) ? 1.f : 0.f;
+    }
+    // joint limits: the distance cotangent goes to the joint coordinate, r = +-(q - end)
+    for (int k = t.lane; k < nrow - nrc; k += t.T) {
+      int dof;
+      float sg, dist;
+      limit_row(m, W, lim[k], dof, sg, dist);
+      qb[m.lim_qadr[lim[k] & 0xffff]] += sg * rs[7 * (nrc + k) + 6];
     }
     t.sync();
     for (int b = 1 + t.lane; b < nb; b += t.T) {

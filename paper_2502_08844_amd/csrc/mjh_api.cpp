@@ -29,11 +29,11 @@ struct HostModel {
   int nbody = 0, njnt = 0, ngeom = 0, npair = 0, nu = 0, nq = 0, nv = 0;
   int iterations = 0, ls_iterations = 0, nconmax = 0;
   double dt = 0, grav[3] = {0, 0, 0}, solref[2] = {0, 0}, solimp[5] = {0, 0, 0, 0, 0};
-  std::vector<int> body_parent, jnt_type, jnt_body, geom_type, geom_body, pair_g1, pair_g2,
-      act_type, act_jnt;
+  std::vector<int> body_parent, jnt_type, jnt_body, jnt_limited, geom_type, geom_body,
+      pair_g1, pair_g2, act_type, act_jnt;
   std::vector<double> body_pos, body_quat, body_mass, body_ipos, body_inertia, jnt_pos,
-      jnt_axis, jnt_damping, jnt_armature, geom_size, geom_pos, geom_quat, pair_mu, act_gear,
-      act_kp, act_kd, act_lo, act_hi, act_qdef, qpos0;
+      jnt_axis, jnt_damping, jnt_armature, jnt_range, geom_size, geom_pos, geom_quat, pair_mu,
+      act_gear, act_kp, act_kd, act_lo, act_hi, act_qdef, qpos0;
 };
 
 struct ModelRec {
@@ -67,7 +67,7 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   int32_t hi[16];
   double hf[16];
   if (!r.read(hi, 16) || !r.read(hf, 16)) { err = "model blob: truncated header"; return MJH_EMODEL; }
-  if (hi[0] != 0x4D484A4D || hi[1] != 1) { err = "model blob: bad magic or version"; return MJH_EMODEL; }
+  if (hi[0] != 0x4D484A4D || hi[1] != 2) { err = "model blob: bad magic or version"; return MJH_EMODEL; }
   m.nbody = hi[2]; m.njnt = hi[3]; m.ngeom = hi[4]; m.npair = hi[5]; m.nu = hi[6];
   m.nq = hi[7]; m.nv = hi[8]; m.iterations = hi[9]; m.ls_iterations = hi[10]; m.nconmax = hi[11];
   if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nq < 0 ||
@@ -86,8 +86,8 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   };
   std::vector<int32_t> bi, ji, gi, pi, ai;
   std::vector<double> bf, jf, gf, pf, af;
-  bool ok = rd(bi, 2 * m.nbody) && rd(bf, 19 * (size_t)m.nbody) && rd(ji, 2 * m.njnt) &&
-            rd(jf, 8 * (size_t)m.njnt) && rd(gi, 2 * m.ngeom) && rd(gf, 11 * (size_t)m.ngeom) &&
+  bool ok = rd(bi, 2 * m.nbody) && rd(bf, 19 * (size_t)m.nbody) && rd(ji, 4 * m.njnt) &&
+            rd(jf, 10 * (size_t)m.njnt) && rd(gi, 2 * m.ngeom) && rd(gf, 11 * (size_t)m.ngeom) &&
             rd(pi, 2 * m.npair) && rd(pf, m.npair) && rd(ai, 2 * m.nu) &&
             rd(af, 7 * (size_t)m.nu) && rd(m.qpos0, m.nq);
   if (!ok || r.off() != nbytes) { err = "model blob: size mismatch"; return MJH_EMODEL; }
@@ -105,14 +105,22 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
     }
   }
   for (int j = 0; j < m.njnt; j++) {
-    const int type = ji[2 * j], body = ji[2 * j + 1];
-    if (type < 0 || type > 2 || body <= 0 || body >= m.nbody || (j > 0 && body < ji[2 * j - 1])) {
+    const int type = ji[4 * j], body = ji[4 * j + 1], limited = ji[4 * j + 2] != 0;
+    if (type < 0 || type > 2 || body <= 0 || body >= m.nbody ||
+        (j > 0 && body < ji[4 * (j - 1) + 1])) {
       err = "model blob: bad joint (type/body/order)";
+      return MJH_EMODEL;
+    }
+    const double* f = &jf[10 * j];
+    if (limited && (type == JNT_FREE || !(f[8] < f[9]))) {
+      err = "model blob: a limit needs a hinge or slide joint and range[0] < range[1]";
       return MJH_EMODEL;
     }
     m.jnt_type.push_back(type);
     m.jnt_body.push_back(body);
-    const double* f = &jf[8 * j];
+    m.jnt_limited.push_back(limited);
+    m.jnt_range.push_back(f[8]);
+    m.jnt_range.push_back(f[9]);
     m.jnt_pos.insert(m.jnt_pos.end(), f, f + 3);
     const double L = std::sqrt(f[3] * f[3] + f[4] * f[4] + f[5] * f[5]);
     if (type != JNT_FREE && !(L > 0)) { err = "model blob: zero joint axis"; return MJH_EMODEL; }
@@ -194,7 +202,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   DevModel& d = rec.dm;
   d = DevModel{};
   d.nbody = h.nbody; d.njnt = h.njnt; d.nq = h.nq; d.nv = h.nv; d.nu = h.nu;
-  d.ngeom = h.ngeom; d.npair = h.npair; d.nconmax = h.nconmax; d.nrowmax = 4 * h.nconmax;
+  d.ngeom = h.ngeom; d.npair = h.npair; d.nconmax = h.nconmax;
   d.iterations = h.iterations;
   if (h.nv > kMaxNv) { err = "nv > 64 is not supported"; return MJH_EUNSUPPORTED; }
   // addresses
@@ -280,6 +288,18 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
     act_qadr.push_back(jnt_qposadr[j]);
     act_dadr.push_back(dof);
   }
+  // joint limits, in joint order
+  std::vector<int> lim_qadr, lim_dadr;
+  std::vector<float> lim_lo, lim_hi;
+  for (int j = 0; j < h.njnt; j++)
+    if (h.jnt_limited[j]) {
+      lim_qadr.push_back(jnt_qposadr[j]);
+      lim_dadr.push_back(jnt_dofadr[j]);
+      lim_lo.push_back((float)h.jnt_range[2 * j]);
+      lim_hi.push_back((float)h.jnt_range[2 * j + 1]);
+    }
+  d.nlim = (int)lim_qadr.size();
+  d.nrowmax = 4 * h.nconmax + d.nlim;
   // pairs and candidate slots
   std::vector<int> pair_kind, pair_candadr, cand_pair;
   int ncand = 0;
@@ -336,6 +356,10 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   pk.add(h.act_type, &d.act_type);
   pk.add(act_qadr, &d.act_qadr);
   pk.add(act_dadr, &d.act_dadr);
+  pk.add(lim_qadr, &d.lim_qadr);
+  pk.add(lim_dadr, &d.lim_dadr);
+  pk.add(lim_lo, &d.lim_lo);
+  pk.add(lim_hi, &d.lim_hi);
   std::vector<float> bpos = fv(h.body_pos), bmass = fv(h.body_mass), bipos = fv(h.body_ipos),
                      binert = fv(h.body_inertia), jpos = fv(h.jnt_pos), jaxis = fv(h.jnt_axis),
                      gsize = fv(h.geom_size), gpos = fv(h.geom_pos), pmu = fv(h.pair_mu),
@@ -363,6 +387,8 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   pk.add(aqd, &d.act_qdef);
   pk.add(q0, &d.qpos0);
   pk.add(invw, const_cast<const float**>(&d.body_invweight));
+  std::vector<float> lim_invw(d.nlim, 0.f);
+  pk.add(lim_invw, const_cast<const float**>(&d.lim_invweight));
   // on-chip layout in 4-byte words, regions packed back to back (every LDS access is a
   // scalar 32-bit one, so no region needs more alignment)
   int off = 0;
@@ -407,6 +433,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   if (2 * ncand <= d.ntri) d.o_cand = d.o_H;
   else d.o_cand = take(2 * ncand);
   d.o_con = take(kConRec * h.nconmax);
+  d.o_lim = take(d.nlim);  // violated limits: joint-limit index | 0x10000 for the upper end
   d.o_J = take(nr * nv);
   // the reference accelerations are read once, when Newton forms its residuals, before
   // the first Hessian is built: they too share H's words
@@ -443,7 +470,8 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   x.o_cinert = take(kCinert * nb); x.o_F = take(6 * nv);
   x.o_H = take(d.ntri); x.o_Mr = take(nv); x.o_g = take(nv); x.o_d = take(nv);
   x.o_Md = take(nv); x.o_tmp = take(nv); x.o_cand = take(2 * ncand);
-  x.o_con = take(kConRec * h.nconmax); x.o_J = take(nr * nv); x.o_aref = take(nr);
+  x.o_con = take(kConRec * h.nconmax); x.o_lim = take(d.nlim); x.o_J = take(nr * nv);
+  x.o_aref = take(nr);
   x.o_D = take(nr); x.o_e = take(nr); x.o_s = take(nr);
   x.o_qbi = take(h.nq); x.o_vbi = take(nv); x.o_qb = take(h.nq); x.o_vb = take(nv);
   x.o_ub = take(h.nu); x.o_mu = take(nv); x.o_Sbar = take(6 * nv);
@@ -631,24 +659,14 @@ mjh_status mjh_model_upload(mjh_ctx* ctx, const void* blob, size_t nbytes, int32
   rec->dbytes = pk.bytes.size();
   MJH_HIP(hipMemcpy(rec->dbuf, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice));
   uint8_t* base = static_cast<uint8_t*>(rec->dbuf);
-  for (auto& f : pk.fix) *f.second = base + f.first;
-  {  // the adjoint layout shares every table pointer
-    DevModel x = rec->dm;
-    const DevModel& lay = rec->dm_adj;
-    x.lds_words = lay.lds_words;
-    x.o_qpos = lay.o_qpos; x.o_qvel = lay.o_qvel; x.o_qacc = lay.o_qacc; x.o_xpos = lay.o_xpos;
-    x.o_xmat = lay.o_xmat; x.o_cdof = lay.o_cdof; x.o_M = lay.o_M; x.o_frc = lay.o_frc;
-    x.o_a0 = lay.o_a0; x.o_scal = lay.o_scal; x.o_cvel = lay.o_cvel; x.o_cacc = lay.o_cacc;
-    x.o_cfrc = lay.o_cfrc; x.o_cinert = lay.o_cinert; x.o_F = lay.o_F; x.o_H = lay.o_H;
-    x.o_Mr = lay.o_Mr; x.o_g = lay.o_g; x.o_d = lay.o_d; x.o_Md = lay.o_Md; x.o_tmp = lay.o_tmp;
-    x.o_cand = lay.o_cand; x.o_con = lay.o_con; x.o_J = lay.o_J; x.o_aref = lay.o_aref;
-    x.o_D = lay.o_D; x.o_e = lay.o_e; x.o_s = lay.o_s; x.o_qbi = lay.o_qbi; x.o_vbi = lay.o_vbi;
-    x.o_qb = lay.o_qb; x.o_vb = lay.o_vb; x.o_ub = lay.o_ub; x.o_mu = lay.o_mu;
-    x.o_Sbar = lay.o_Sbar; x.o_xbar = lay.o_xbar; x.o_Rbar = lay.o_Rbar;
-    x.o_cinbar = lay.o_cinbar; x.o_Vbar = lay.o_Vbar; x.o_Abar = lay.o_Abar;
-    x.o_Fbar = lay.o_Fbar; x.o_vup = lay.o_vup; x.o_aup = lay.o_aup; x.o_xup = lay.o_xup;
-    x.o_Rup = lay.o_Rup; x.o_rowsc = lay.o_rowsc; x.o_consc = lay.o_consc;
-    rec->dm_adj = x;
+  // every table pointer, in both layouts (the adjoint layout differs only in its
+  // on-chip offsets, which compile_model set)
+  for (auto& f : pk.fix) {
+    const size_t field = reinterpret_cast<const uint8_t*>(f.second) -
+                         reinterpret_cast<const uint8_t*>(&rec->dm);
+    *f.second = base + f.first;
+    *reinterpret_cast<const void**>(reinterpret_cast<uint8_t*>(&rec->dm_adj) + field) =
+        base + f.first;
   }
   // translational inverse weights at qpos0, computed on the device
   MJH_HIP(launch_invweight(rec->dm, nullptr));
@@ -666,6 +684,18 @@ mjh_status mjh_model_info(mjh_ctx* ctx, int32_t model_id, mjh_dims* out) {
   out->nq = d.nq; out->nv = d.nv; out->nu = d.nu; out->nbody = d.nbody; out->ngeom = d.ngeom;
   out->npair = d.npair; out->ncand = d.ncand; out->nconmax = d.nconmax;
   out->iterations = d.iterations; out->lds_bytes = d.lds_words * 4; out->timestep = d.dt;
+  out->nlimit = d.nlim; out->nrowmax = d.nrowmax;
+  return MJH_OK;
+}
+
+mjh_status mjh_model_limit_invweight(mjh_ctx* ctx, int32_t model_id, float* out) {
+  if (!ctx) return MJH_EINVAL;
+  if (model_id < 0 || model_id >= (int)ctx->models.size() ||
+      (!out && ctx->models[model_id]->dm.nlim > 0))
+    return fail(ctx, MJH_EINVAL, "model_limit_invweight: bad model id or NULL output");
+  const DevModel& d = ctx->models[model_id]->dm;
+  if (d.nlim > 0)
+    MJH_HIP(hipMemcpy(out, d.lim_invweight, d.nlim * sizeof(float), hipMemcpyDeviceToHost));
   return MJH_OK;
 }
 
@@ -846,7 +876,7 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
     const DevModel& d = ctx->models[g.model]->dm;
     std::ostringstream k;
     k << d.nq << ' ' << d.nv << ' ' << d.nbody << ' ' << d.npair << ' ' << d.nconmax << ' '
-      << d.iterations << ' ' << g.nworld;
+      << d.nlim << ' ' << d.iterations << ' ' << g.nworld;
     return k.str();
   };
   if (cache_path) {

@@ -826,17 +826,57 @@ DEV void select_contacts(const DevModel& m, float* W, const Team& t, int& status
 }
 
 // ------------------------------------------------------------- A8: constraint rows
+// impedance d(r) of the soft-constraint model from solimp (dmin, dmax, width, mid, power)
+DEV float impedance(const DevModel& m, float dist) {
+  const float x = fminf(fabsf(dist) / m.width, 1.f);
+  float y;
+  if (x <= m.mid) y = powf(x, m.power) / powf(m.mid, m.power - 1.f);
+  else y = 1.f - powf(1.f - x, m.power) / powf(1.f - m.mid, m.power - 1.f);
+  return m.dmin + y * (m.dmax - m.dmin);
+}
+
+// violated joint limit k of a world (its o_lim entry): dof, sign of its row and distance
+DEV void limit_row(const DevModel& m, const float* W, int code, int& dof, float& sg,
+                   float& dist) {
+  const int l = code & 0xffff;
+  const bool upper = code >> 16;
+  const float q = W[m.o_qpos + m.lim_qadr[l]];
+  dof = m.lim_dadr[l];
+  sg = upper ? -1.f : 1.f;
+  dist = upper ? m.lim_hi[l] - q : q - m.lim_lo[l];
+}
+
 // Pyramid rows J_e = J_n +- mu J_tk (order +t1, -t1, +t2, -t2) from the point
 // Jacobians of the two bodies at the contact point; impedance d(r), reference
 // acceleration aref = -B (J_e qvel) - K d(r) r, regulariser R = (1-d)/d (1+mu^2)
-// (w1 + w2), D = 1/R.
+// (w1 + w2), D = 1/R.  Then one row per joint outside its range, in joint order:
+// J = +-e_dof, r the distance past the range end, R = (1-d)/d (M^-1)_kk at qpos0.
+// Writes the row count to the SC_NROW slot.
 DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
-  const int* scal = (const int*)(W + m.o_scal);
+  int* scal = (int*)(W + m.o_scal);
   const int ncon = scal[SC_NCON];
-  const int nv = m.nv, nrow = 4 * ncon;
+  const int nv = m.nv, nrc = 4 * ncon;
   const float* con = W + m.o_con;
   const float* cdof = W + m.o_cdof;
   float* J = W + m.o_J;
+  // violated limits, compacted in joint order
+  int nl = 0;
+  int* lim = (int*)(W + m.o_lim);
+  for (int l0 = 0; l0 < m.nlim; l0 += t.T) {
+    const int l = l0 + t.lane;
+    int code = -1;
+    if (l < m.nlim) {
+      const float q = W[m.o_qpos + m.lim_qadr[l]];
+      if (q < m.lim_lo[l]) code = l;
+      else if (q > m.lim_hi[l]) code = l | 0x10000;
+    }
+    const int act = code >= 0 ? 1 : 0;
+    const int slot = nl + t.exscan(act);
+    if (act) lim[slot] = code;
+    nl += t.isum(act);
+  }
+  const int nrow = nrc + nl;
+  if (t.lane == 0) scal[SC_NROW] = nrow;
   for (int idx = t.lane; idx < ncon * nv; idx += t.T) {
     const int c = idx / nv, i = idx - c * nv;
     const float* r = con + kConRec * c;
@@ -859,26 +899,37 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
     J[(4 * c + 2) * nv + i] = jn + mu * j2;
     J[(4 * c + 3) * nv + i] = jn - mu * j2;
   }
+  for (int idx = t.lane; idx < nl * nv; idx += t.T) {
+    const int k = idx / nv, i = idx - k * nv;
+    int dof;
+    float sg, dist;
+    limit_row(m, W, lim[k], dof, sg, dist);
+    J[(nrc + k) * nv + i] = i == dof ? sg : 0.f;
+  }
   t.sync();
   const float* qvel = W + m.o_qvel;
   float* aref = W + m.o_aref;
   float* D = W + m.o_D;
   for (int row = t.lane; row < nrow; row += t.T) {
-    const int c = row >> 2;
-    const float* r = con + kConRec * c;
-    const float dist = r[0];
-    float jv = 0.f;
-    for (int i = 0; i < nv; i++) jv += J[row * nv + i] * qvel[i];
-    const float x = fminf(fabsf(dist) / m.width, 1.f);
-    float y;
-    if (x <= m.mid) y = powf(x, m.power) / powf(m.mid, m.power - 1.f);
-    else y = 1.f - powf(1.f - x, m.power) / powf(1.f - m.mid, m.power - 1.f);
-    const float imp = m.dmin + y * (m.dmax - m.dmin);
+    float dist, jv = 0.f, A;
+    if (row < nrc) {
+      const float* r = con + kConRec * (row >> 2);
+      dist = r[0];
+      for (int i = 0; i < nv; i++) jv += J[row * nv + i] * qvel[i];
+      const int b1 = __float_as_int(r[14]), b2 = __float_as_int(r[15]);
+      const float mu = r[13];
+      A = (1.f + mu * mu) * (m.body_invweight[b1] + m.body_invweight[b2]);
+    } else {
+      const int code = lim[row - nrc];
+      int dof;
+      float sg;
+      limit_row(m, W, code, dof, sg, dist);
+      jv = sg * qvel[dof];
+      A = m.lim_invweight[code & 0xffff];
+    }
+    const float imp = impedance(m, dist);
     aref[row] = -m.B * jv - m.K * imp * dist;
-    const int b1 = __float_as_int(r[14]), b2 = __float_as_int(r[15]);
-    const float mu = r[13];
-    const float A = fmaxf((1.f + mu * mu) * (m.body_invweight[b1] + m.body_invweight[b2]), 1e-15f);
-    D[row] = imp / ((1.f - imp) * A);
+    D[row] = imp / ((1.f - imp) * fmaxf(A, 1e-15f));
   }
   t.sync();
 }
@@ -886,8 +937,8 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
 // --------------------------------------------------- A9: Newton solve (NW ch. 3, 6)
 // Loops over all constraint rows run to a wave-uniform bound (the largest row count
 // among the wavefront's worlds), which keeps them off the EXEC mask.  Every lane reads
-// the contact counts that the wavefront's teams stored in their own LDS (slot SC_NCON,
-// written by select_contacts before the last barrier), clamped to [0, nconmax]: teams
+// the row counts that the wavefront's teams stored in their own LDS (slot SC_NROW,
+// written by constraint_rows before its last barrier), clamped to [0, nrowmax]: teams
 // that left the kernel never wrote theirs, and cross-lane operations are not used here
 // because teams may be inactive.  A world's rows from its own count up to the bound are
 // zeroed (J, D, e, s), so they add nothing to gradients, Hessian or line search.
@@ -898,11 +949,11 @@ DEV int pad_rows(const DevModel& m, float* W, const Team& t, int nrow) {
   int mx = 0;
   for (int k = 0; k < tw; k++) {
     const int* sk = (const int*)(W + (k - my) * m.lds_words + m.o_scal);
-    const int nc = sk[SC_NCON];
-    mx = max(mx, min(max(nc, 0), m.nconmax));
+    const int nr = sk[SC_NROW];
+    mx = max(mx, min(max(nr, 0), m.nrowmax));
   }
   // every active lane computed the same mx, and this team's own count is among them
-  const int nru = __builtin_amdgcn_readfirstlane(4 * mx);
+  const int nru = __builtin_amdgcn_readfirstlane(mx);
   float* J = W + m.o_J;
   for (int k = nrow * m.nv + t.lane; k < nru * m.nv; k += t.T) J[k] = 0.f;
   float* D = W + m.o_D;
@@ -1166,7 +1217,7 @@ DEV void cholesky_back(const DevModel& m, float* W, const Team& t, const float* 
 DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int iters,
                 float gtol = 0.f) {
   const int* scal = (const int*)(W + m.o_scal);
-  const int nv = m.nv, nrow = 4 * scal[SC_NCON];
+  const int nv = m.nv, nrow = scal[SC_NROW];
   const float* M = W + m.o_M;
   const float* J = W + m.o_J;
   const float* aref = W + m.o_aref;

@@ -35,7 +35,7 @@ F = C.c_float
 class Dims(C.Structure):
     _fields_ = [("nq", I32), ("nv", I32), ("nu", I32), ("nbody", I32), ("ngeom", I32),
                 ("npair", I32), ("ncand", I32), ("nconmax", I32), ("iterations", I32),
-                ("lds_bytes", I32), ("timestep", F)]
+                ("lds_bytes", I32), ("timestep", F), ("nlimit", I32), ("nrowmax", I32)]
 
 
 def _sig(name, *args):
@@ -53,6 +53,7 @@ _lib.mjh_last_error.restype = C.c_char_p
 mjh_model_upload = _sig("mjh_model_upload", P, C.c_char_p, C.c_size_t, C.POINTER(I32))
 mjh_model_info = _sig("mjh_model_info", P, I32, C.POINTER(Dims))
 mjh_model_invweight = _sig("mjh_model_invweight", P, I32, C.POINTER(F))
+mjh_model_limit_invweight = _sig("mjh_model_limit_invweight", P, I32, C.POINTER(F))
 mjh_world_alloc = _sig("mjh_world_alloc", P, C.POINTER(I32), C.POINTER(I32), I32, C.POINTER(P))
 _lib.mjh_world_free.argtypes = [P]
 _lib.mjh_world_free.restype = None
@@ -141,6 +142,7 @@ class Model:
         self.dims = d
         self.nq, self.nv, self.nu = d.nq, d.nv, d.nu
         self.nconmax = d.nconmax
+        self.nlimit, self.nrowmax = d.nlimit, d.nrowmax
         self.timestep = d.timestep
 
     def invweight(self):
@@ -148,6 +150,13 @@ class Model:
         out = (F * self.dims.nbody)()
         self.ctx.check(mjh_model_invweight(self.ctx._h, self.id, out))
         return np.array(out[:], dtype=np.float64)
+
+    def limit_invweight(self):
+        """(M^-1)_kk at qpos0 of each limited joint's dof, in joint order."""
+        import numpy as np
+        out = (F * max(self.dims.nlimit, 1))()
+        self.ctx.check(mjh_model_limit_invweight(self.ctx._h, self.id, out))
+        return np.array(out[:self.dims.nlimit], dtype=np.float64)
 
 
 @dataclass

@@ -8,7 +8,7 @@ Playground consumes (the paper's physics knobs are MJCF options: Table
 of the step's arithmetic.  Both the FP64 reference and the GPU library parse the blob
 with their own code.
 
-Blob layout (little endian, version 1), every block 8-byte aligned:
+Blob layout (little endian, version 2), every block 8-byte aligned:
 
   header   int32[16]  : magic 0x4D484A4D ('MJHM'), version, nbody, njnt, ngeom, npair,
                         nu, nq, nv, iterations, ls_iterations, nconmax, 0, 0, 0, 0
@@ -17,8 +17,8 @@ Blob layout (little endian, version 1), every block 8-byte aligned:
            f64   [nbody][19]: pos[3], quat[4] (w first), mass, ipos[3],
                               inertia[6] (Ixx Iyy Izz Ixy Ixz Iyz, body frame, about ipos),
                               0, 0
-  joint    int32 [njnt][2]  : type (0 free, 1 slide, 2 hinge), body
-           f64   [njnt][8]  : pos[3], axis[3], damping, armature
+  joint    int32 [njnt][4]  : type (0 free, 1 slide, 2 hinge), body, limited (0/1), 0
+           f64   [njnt][10] : pos[3], axis[3], damping, armature, range[2]
   geom     int32 [ngeom][2] : type (0 plane, 1 sphere, 2 capsule, 3 box), body
            f64   [ngeom][11]: size[3], pos[3], quat[4], friction
   pair     int32 [npair][2] : geom1, geom2   (type(geom1) <= type(geom2))
@@ -26,6 +26,9 @@ Blob layout (little endian, version 1), every block 8-byte aligned:
   actuator int32 [nu][2]    : type (0 motor, 1 position PD), joint
            f64   [nu][7]    : gear, kp, kd, ctrlrange[2], qdefault, 0
   qpos0    f64   [nq]
+
+A limited hinge or slide joint keeps its coordinate inside range[0] < q < range[1]
+through a soft one-sided constraint (the joint-limit rows of the constraint set).
 
 Geom sizes: sphere (r), capsule (r, half segment length; segment along local z),
 box (half extents).  Plane normal is the geom's local +z.
@@ -39,7 +42,7 @@ from typing import List, Tuple
 import numpy as np
 
 MAGIC = 0x4D484A4D
-VERSION = 1
+VERSION = 2
 
 JNT_FREE, JNT_SLIDE, JNT_HINGE = 0, 1, 2
 GEOM_PLANE, GEOM_SPHERE, GEOM_CAPSULE, GEOM_BOX = 0, 1, 2, 3
@@ -68,6 +71,8 @@ class Joint:
     axis: Tuple[float, float, float] = (0.0, 0.0, 1.0)
     damping: float = 0.0
     armature: float = 0.0
+    limited: bool = False
+    range: Tuple[float, float] = (0.0, 0.0)
     name: str = ""
 
 
@@ -133,6 +138,11 @@ class Model:
     def nu(self) -> int:
         return len(self.actuators)
 
+    @property
+    def nlimit(self) -> int:
+        """Limited joints: each adds at most one constraint row (one side at a time)."""
+        return sum(1 for j in self.joints if j.limited)
+
     def jnt_qposadr(self) -> List[int]:
         out, a = [], 0
         for j in self.joints:
@@ -162,6 +172,9 @@ class Model:
             if j.type == JNT_FREE:
                 assert self.bodies[j.body].parent == 0, "free joints attach to the world"
                 assert sum(1 for k in self.joints if k.body == j.body) == 1
+                assert not j.limited, "free joints have no limits"
+            if j.limited:
+                assert j.range[0] < j.range[1], "limited joint needs range[0] < range[1]"
         for g1, g2, _ in self.pairs:
             assert self.geoms[g1].type <= self.geoms[g2].type, "pair order by geom type"
         assert self.qpos0 is not None and len(self.qpos0) == self.nq
@@ -188,8 +201,9 @@ class Model:
         parts.append(blk_i([[b.parent, 0] for b in self.bodies]))
         parts.append(blk_f([[*b.pos, *b.quat, b.mass, *b.ipos, *b.inertia, 0, 0]
                             for b in self.bodies]))
-        parts.append(blk_i([[j.type, j.body] for j in self.joints]))
-        parts.append(blk_f([[*j.pos, *j.axis, j.damping, j.armature] for j in self.joints]))
+        parts.append(blk_i([[j.type, j.body, int(bool(j.limited)), 0] for j in self.joints]))
+        parts.append(blk_f([[*j.pos, *j.axis, j.damping, j.armature, *j.range]
+                            for j in self.joints]))
         parts.append(blk_i([[g.type, g.body] for g in self.geoms]))
         parts.append(blk_f([[*g.size, *g.pos, *g.quat, g.friction] for g in self.geoms]))
         parts.append(blk_i([[p[0], p[1]] for p in self.pairs]))

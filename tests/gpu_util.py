@@ -45,8 +45,9 @@ def compare_step(m, o, state, ctrl1, gpu1, mode=oracle.MODE_FIXED, near=1e-5):
     """Compare one GPU step (gpu1) with the reference step from the same float32 state.
 
     Returns per-world qacc and contact-force relative errors and a flag per world for
-    states near a switch (contact emission |dist| < near, a candidate set change, or a
-    constraint row at its activation threshold), which are reported, not gated."""
+    states near a switch (contact emission |dist| < near, a limited joint within near
+    of its range end, a candidate set change, or a constraint row at its activation
+    threshold), which are reported, not gated."""
     qpos, qvel, ws = state
     nw = qpos.shape[0]
     ref = o.step(qpos.copy(), qvel.copy(), ws.copy(), ctrl1, nstep=1, mode=mode, nthreads=8)
@@ -55,11 +56,26 @@ def compare_step(m, o, state, ctrl1, gpu1, mode=oracle.MODE_FIXED, near=1e-5):
     err_f = np.zeros(nw)
     err_geo = np.zeros((nw, 3))  # contact depth, point and normal deviations
     flag = np.zeros(nw, dtype=bool)
+    qadr = m.jnt_qposadr()
+    lims = [(qadr[j], jt.range[0], jt.range[1]) for j, jt in enumerate(m.joints) if jt.limited]
+
+    def at_threshold(w):  # a row at its activation threshold in the reference solution
+        f = o.forward(qpos[w], qvel[w], ws[w], ctrl1[0, w] if ctrl1 is not None else None,
+                      mode=mode)
+        if f["nrow"] == 0:
+            return False
+        e = f["J"] @ f["qacc"] - f["aref"]
+        return bool(np.any(np.abs(e) < 1e-6 * (1 + np.abs(f["aref"]).max())))
+
     for w in range(nw):
         a_r, a_g = ref["qacc"][w], gpu1["qacc"][w]
         err_a[w] = np.abs(a_g - a_r).max() / max(np.abs(a_r).max(), G)
+        if any(min(abs(qpos[w, k] - lo), abs(qpos[w, k] - hi)) < near for k, lo, hi in lims):
+            flag[w] = True
         nc_r, nc_g = ref["ncon"][w], gpu1["ncon"][w] if "ncon" in gpu1 else -1
         if nc_r == 0 and nc_g <= 0:
+            if lims and at_threshold(w):
+                flag[w] = True
             continue
         cr = ref["contacts"][w, :nc_r]
         if nc_g != nc_r:
@@ -71,11 +87,7 @@ def compare_step(m, o, state, ctrl1, gpu1, mode=oracle.MODE_FIXED, near=1e-5):
             continue
         if np.any(np.abs(cr[:, 0]) < near):
             flag[w] = True
-        # rows at their activation threshold in the reference solution
-        f = o.forward(qpos[w], qvel[w], ws[w], ctrl1[0, w] if ctrl1 is not None else None,
-                      mode=mode)
-        e = f["J"] @ f["qacc"] - f["aref"]
-        if np.any(np.abs(e) < 1e-6 * (1 + np.abs(f["aref"]).max())):
+        if at_threshold(w):
             flag[w] = True
         err_f[w] = np.abs(cg[:, 13:16] - cr[:, 13:16]).max() / (mass * G)
         err_geo[w] = (np.abs(cg[:, 0] - cr[:, 0]).max(), np.abs(cg[:, 1:4] - cr[:, 1:4]).max(),
