@@ -228,7 +228,8 @@ struct Model {
   std::vector<int> body_parent;
   std::vector<double> body_pos, body_quat, body_mass, body_ipos, body_inertia;
   std::vector<int> jnt_type, jnt_body, jnt_limited;
-  std::vector<double> jnt_pos, jnt_axis, jnt_damping, jnt_armature, jnt_range;
+  std::vector<double> jnt_pos, jnt_axis, jnt_damping, jnt_armature, jnt_range,
+      jnt_frictionloss;
   std::vector<int> geom_type, geom_body;
   std::vector<double> geom_size, geom_pos, geom_quat, geom_friction;
   std::vector<int> pair_g1, pair_g2;
@@ -239,10 +240,11 @@ struct Model {
   // derived
   std::vector<int> jnt_qposadr, jnt_dofadr, body_jntadr, body_jntnum, body_dofadr, body_dofnum;
   std::vector<int> dof_body, dof_jnt, dof_parent;
-  std::vector<double> dof_damping, dof_armature;
+  std::vector<double> dof_damping, dof_armature, dof_frictionloss;
   std::vector<double> body_invweight;
   std::vector<double> dof_invweight;  // (M^-1)_kk at qpos0
   int nlimit = 0;                     // limited joints
+  int nfric = 0;                      // dofs with friction loss (one row each, always)
 };
 
 struct Reader {
@@ -275,6 +277,7 @@ template <class T> struct Data {
   std::vector<Contact<T>> con;
   int nrow = 0;
   std::vector<T> J, aref, D, efc_force, qfrc_con;
+  std::vector<double> fl;  // per row: friction-loss bound, 0 for a one-sided row
   std::vector<T> qacc;
   std::vector<T> H;  // dense Cholesky factor of the last Newton Hessian
   int status = 0;
@@ -888,6 +891,9 @@ template <class T> T impedance(const Model& m, T r) {
 // Joint limits follow the contacts, one row per limited hinge or slide joint whose
 // coordinate lies outside its range, in joint order: distance r = q - lo (row J = e_k)
 // or r = hi - q (J = -e_k), the same aref, impedance and R with A = (M^-1)_kk at qpos0.
+// Then one friction-loss row per dof k with a bound F_k > 0, always present: J = e_k,
+// r = 0 (so d = d(0) and aref = -b qvel_k), the same A; its force is limited to
+// [-F_k, F_k] (dry joint friction, Todorov 2014's box-constrained rows).
 template <class T> void constraint_rows(const Model& m, Data<T>& d) {
   const int nc = (int)d.con.size(), n = m.nv;
   std::vector<int> lim_dof;
@@ -901,10 +907,11 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
     else if (rhi < 0.0) { lim_dof.push_back(m.jnt_dofadr[j]); lim_sign.push_back(-1.0); lim_dist.push_back(rhi); }
   }
   const int nl = (int)lim_dof.size();
-  d.nrow = 4 * nc + nl;
+  d.nrow = 4 * nc + nl + m.nfric;
   d.J.assign(d.nrow * n, 0.0);
   d.aref.assign(d.nrow, 0.0);
   d.D.assign(d.nrow, 0.0);
+  d.fl.assign(d.nrow, 0.0);
   const double tc = std::max(m.solref[0], 2.0 * m.dt), zeta = m.solref[1];
   const double dmax = m.solimp[1];
   const double K = 1.0 / (dmax * dmax * tc * tc * zeta * zeta);
@@ -947,11 +954,26 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
     d.aref[row] = -B * (lim_sign[l] * d.qvel[k]) - K * imp * lim_dist[l];
     d.D[row] = 1.0 / R;
   }
+  int row = 4 * nc + nl;
+  for (int k = 0; k < n; k++) {
+    if (!(m.dof_frictionloss[k] > 0.0)) continue;
+    d.J[row * n + k] = 1.0;
+    const T imp = impedance(m, T(0.0));
+    const double A = std::max(m.dof_invweight[k], 1e-15);
+    d.aref[row] = -B * d.qvel[k];
+    d.D[row] = 1.0 / ((1.0 - imp) / imp * A);
+    d.fl[row] = m.dof_frictionloss[k];
+    row++;
+  }
 }
 
 // ---------------------------------------------------------- A9: Newton contact solve
-// Minimise F(a) = 1/2 (a - a0)^T M (a - a0) + sum_i 1/2 D_i min(0, J_i a - aref_i)^2,
-// a strictly convex piecewise quadratic (M is SPD).
+// Minimise F(a) = 1/2 (a - a0)^T M (a - a0) + sum_i s_i(J_i a - aref_i), with
+//   s_i(e) = 1/2 D_i min(0, e)^2                       for a one-sided row,
+//   s_i(e) = 1/2 D_i e^2 if |D_i e| <= F_i, else F_i |e| - F_i^2 / (2 D_i)
+//                                                      for a friction-loss row (bound F_i),
+// the largest of -f e - f^2 / (2 D) over the row's admissible forces f (f >= 0, or
+// |f| <= F).  F is strictly convex and piecewise quadratic (M is SPD).
 template <class T> struct Solver {
   const Model& m;
   Data<T>& d;
@@ -963,6 +985,23 @@ template <class T> struct Solver {
     for (int k = 0; k < n; k++) s += d.J[i * n + k] * a[k];
     return s;
   }
+  // s_i(e), its derivative, and whether e lies on the row's quadratic piece
+  T srow(int i, T e) const {
+    const double F = d.fl[i];
+    if (F == 0.0) return e < 0.0 ? T(0.5 * d.D[i] * e * e) : T(0.0);
+    if (fabs(d.D[i] * e) <= F) return 0.5 * d.D[i] * e * e;
+    return F * fabs(e) - F * F / (2.0 * d.D[i]);
+  }
+  T dsrow(int i, T e) const {
+    const double F = d.fl[i];
+    if (F == 0.0) return e < 0.0 ? T(d.D[i] * e) : T(0.0);
+    const T v = d.D[i] * e;
+    return v > F ? T(F) : (v < -F ? T(-F) : v);
+  }
+  bool quad(int i, T e) const {
+    const double F = d.fl[i];
+    return F == 0.0 ? e < 0.0 : fabs(d.D[i] * e) < F;
+  }
   T cost(const T* a) const {
     std::vector<T> da(n), Mda(n);
     for (int k = 0; k < n; k++) da[k] = a[k] - d.qacc_smooth[k];
@@ -972,10 +1011,7 @@ template <class T> struct Solver {
       for (int k = 0; k < n; k++) s += d.M[i * n + k] * da[k];
       c += 0.5 * da[i] * s;
     }
-    for (int i = 0; i < nr; i++) {
-      T e = jrow(i, a) - d.aref[i];
-      if (e < 0.0) c += 0.5 * d.D[i] * e * e;
-    }
+    for (int i = 0; i < nr; i++) c += srow(i, jrow(i, a) - d.aref[i]);
     return c;
   }
   // gradient and Hessian with the active set at a
@@ -988,12 +1024,12 @@ template <class T> struct Solver {
     }
     for (int r = 0; r < nr; r++) {
       T e = jrow(r, a) - d.aref[r];
-      if (!(e < 0.0)) continue;
       const T* Jr = &d.J[r * n];
-      for (int i = 0; i < n; i++) {
-        g[i] += d.D[r] * e * Jr[i];
+      const T ds = dsrow(r, e);
+      for (int i = 0; i < n; i++) g[i] += ds * Jr[i];
+      if (!quad(r, e)) continue;
+      for (int i = 0; i < n; i++)
         for (int k = 0; k < n; k++) H[i * n + k] += d.D[r] * Jr[i] * Jr[k];
-      }
     }
   }
   // exact minimiser of phi(alpha) = F(a + alpha delta) over alpha >= 0: phi' is piecewise
@@ -1008,17 +1044,27 @@ template <class T> struct Solver {
       dMd += delta[i] * t;
       dMa += t * (a[i] - d.qacc_smooth[i]);
     }
-    // phi'(alpha) = dMa + alpha dMd + sum_{rows active at alpha} D_i s_i (e_i + alpha s_i)
+    // phi'(alpha) = dMa + alpha dMd + sum_i s_i s_i'(e_i + alpha s_i), linear in alpha
+    // between breakpoints: A + alpha Bc with the pieces that hold at `probe`
     auto dphi_lin = [&](T probe, T& A, T& Bc) {
       A = dMa; Bc = dMd;
-      for (int i = 0; i < nr; i++)
-        if (e[i] + probe * s[i] < 0.0) { A += d.D[i] * s[i] * e[i]; Bc += d.D[i] * s[i] * s[i]; }
+      for (int i = 0; i < nr; i++) {
+        const T ep = e[i] + probe * s[i];
+        if (quad(i, ep)) { A += d.D[i] * s[i] * e[i]; Bc += d.D[i] * s[i] * s[i]; }
+        else A += s[i] * dsrow(i, ep);  // 0, or the friction bound +-F
+      }
     };
+    // breakpoints: where a row's e crosses 0 (one-sided) or +-F/D (friction loss)
     std::vector<T> bps;
     for (int i = 0; i < nr; i++)
       if (s[i] != 0.0) {
-        T al = -e[i] / s[i];
-        if (al > 0.0) bps.push_back(al);
+        const double F = d.fl[i];
+        const int nb = F == 0.0 ? 1 : 2;
+        for (int k = 0; k < nb; k++) {
+          const T at = F == 0.0 ? T(0.0) : T((k == 0 ? F : -F) / d.D[i]);
+          T al = (at - e[i]) / s[i];
+          if (al > 0.0) bps.push_back(al);
+        }
       }
     std::sort(bps.begin(), bps.end(), [](const T& x, const T& y) { return x < y; });
     T lo = 0.0;
@@ -1121,7 +1167,9 @@ template <class T> void forward(const Model& m, Data<T>& d, int mode) {
     T jar = 0.0;
     for (int i = 0; i < m.nv; i++) jar += d.J[r * m.nv + i] * d.qacc[i];
     T f = d.D[r] * (d.aref[r] - jar);
-    d.efc_force[r] = f > 0.0 ? f : T(0.0);
+    const double F = d.fl[r];
+    if (F == 0.0) d.efc_force[r] = f > 0.0 ? f : T(0.0);
+    else d.efc_force[r] = f > F ? T(F) : (f < -F ? T(-F) : f);
     for (int i = 0; i < m.nv; i++) d.qfrc_con[i] += d.J[r * m.nv + i] * d.efc_force[r];
   }
 }
@@ -1188,7 +1236,7 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   std::vector<double> bf(19 * m.nbody);
   r.read(bi.data(), bi.size()); r.read(bf.data(), bf.size());
   std::vector<int32_t> ji(4 * m.njnt);
-  std::vector<double> jf(10 * m.njnt);
+  std::vector<double> jf(11 * m.njnt);
   r.read(ji.data(), ji.size()); r.read(jf.data(), jf.size());
   std::vector<int32_t> gi(2 * m.ngeom);
   std::vector<double> gf(11 * m.ngeom);
@@ -1217,7 +1265,7 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
     m.jnt_type.push_back(jj[0]);
     m.jnt_body.push_back(jj[1]);
     m.jnt_limited.push_back(jj[2] != 0);
-    const double* f = &jf[10 * j];
+    const double* f = &jf[11 * j];
     m.jnt_pos.insert(m.jnt_pos.end(), f, f + 3);
     double ax[3] = {f[3], f[4], f[5]};
     double L = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
@@ -1234,6 +1282,10 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
       if (jj[0] == JFREE || !(f[8] < f[9])) { err = "bad joint limit"; return false; }
       m.nlimit++;
     }
+    if (!(f[10] >= 0.0) || (jj[0] == JFREE && f[10] != 0.0)) {
+      err = "bad friction loss"; return false;
+    }
+    m.jnt_frictionloss.push_back(f[10]);
   }
   for (int g = 0; g < m.ngeom; g++) {
     m.geom_type.push_back(gi[2 * g]);
@@ -1281,6 +1333,8 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
       m.dof_jnt.push_back(j);
       m.dof_damping.push_back(m.jnt_damping[j]);
       m.dof_armature.push_back(m.jnt_armature[j]);
+      m.dof_frictionloss.push_back(m.jnt_frictionloss[j]);
+      if (m.jnt_frictionloss[j] > 0.0) m.nfric++;
     }
     qa += m.jnt_type[j] == JFREE ? 7 : 1;
     da += nd;
@@ -1383,11 +1437,12 @@ void* mjo_load(const unsigned char* blob, long nbytes, char* err, int errlen) {
 
 void mjo_free(void* h) { delete static_cast<Model*>(h); }
 
-// out[0..10] = nq nv nu nbody njnt ngeom npair nconmax iterations ls_iterations nlimit
+// out[0..11] = nq nv nu nbody njnt ngeom npair nconmax iterations ls_iterations nlimit
+// nfric
 int mjo_dims(void* h, int* out) {
   Model& m = *static_cast<Model*>(h);
-  int v[11] = {m.nq, m.nv, m.nu, m.nbody, m.njnt, m.ngeom, m.npair, m.nconmax,
-               m.iterations, m.ls_iterations, m.nlimit};
+  int v[12] = {m.nq, m.nv, m.nu, m.nbody, m.njnt, m.ngeom, m.npair, m.nconmax,
+               m.iterations, m.ls_iterations, m.nlimit, m.nfric};
   std::memcpy(out, v, sizeof(v));
   return 0;
 }
@@ -1470,8 +1525,8 @@ int mjo_step(void* h, int nworld, int nstep, double* qpos, double* qvel, double*
 // Output sizes: xpos [nbody*3], xmat [nbody*9], xipos [nbody*3], cdof [nv*6],
 // cvel [nbody*6], M [nv*nv], bias [nv], act [nv], pass [nv], qacc_smooth [nv],
 // qacc [nv], qfrc_con [nv], ncon, contacts [nconmax*20], nrow, J [nrowmax * nv],
-// aref, D, efc_force [nrowmax] with nrowmax = 4 nconmax + nlimit (contact rows first,
-// then the active limit rows).  NULL skips an output.
+// aref, D, efc_force [nrowmax] with nrowmax = 4 nconmax + nlimit + nfric (contact rows
+// first, then the violated limits, then the friction-loss rows).  NULL skips an output.
 int mjo_forward(void* h, const double* qpos, const double* qvel, const double* qacc_ws,
                 const double* ctrl, int mode, double* xpos, double* xmat, double* xipos,
                 double* cdof, double* cvel, double* M, double* bias, double* act,
@@ -1494,6 +1549,17 @@ int mjo_forward(void* h, const double* qpos, const double* qvel, const double* q
   cp(d.J, J); cp(d.aref, aref); cp(d.D, D); cp(d.efc_force, efc_force);
   if (status) *status = d.status;
   return 0;
+}
+
+// the Newton cost F(a) of one world's step (state, ctrl) at the acceleration a
+double mjo_cost(void* h, const double* qpos, const double* qvel, const double* ctrl,
+                const double* a) {
+  Model& m = *static_cast<Model*>(h);
+  Data<double> d;
+  set_state(m, d, qpos, qvel, nullptr, ctrl);
+  forward(m, d, 0);
+  Solver<double> s(m, d);
+  return s.cost(a);
 }
 
 // inverse dynamics tau = M(q) qacc + c(q, qvel) (gravity included)

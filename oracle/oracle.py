@@ -57,6 +57,8 @@ def _load():
         lib.mjo_forward.argtypes = [P, D, D, D, D, C.c_int] + [D] * 12 + [I, D, I, D, D, D,
                                                                          D, I]
         lib.mjo_inverse.argtypes = [P, D, D, D, D]
+        lib.mjo_cost.argtypes = [P, D, D, D, D]
+        lib.mjo_cost.restype = C.c_double
         lib.mjo_ltdl_solve.argtypes = [P, D, D, D, D]
         lib.mjo_point_jac.argtypes = [P, D, C.c_int, D, D]
         lib.mjo_rollout_loss.argtypes = [P, C.c_int, C.c_int, D, D, D, D, C.c_double,
@@ -99,12 +101,12 @@ class Oracle:
         self._h = self._lib.mjo_load(bytes(blob), len(blob), err, 256)
         if not self._h:
             raise ValueError("oracle rejected model: " + err.value.decode())
-        dims = np.zeros(11, dtype=np.int32)
+        dims = np.zeros(12, dtype=np.int32)
         self._lib.mjo_dims(self._h, _i(dims))
         (self.nq, self.nv, self.nu, self.nbody, self.njnt, self.ngeom, self.npair,
-         self.nconmax, self.iterations, self.ls_iterations, self.nlimit) = \
+         self.nconmax, self.iterations, self.ls_iterations, self.nlimit, self.nfric) = \
             (int(x) for x in dims)
-        self.nrowmax = 4 * self.nconmax + self.nlimit
+        self.nrowmax = 4 * self.nconmax + self.nlimit + self.nfric
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -177,6 +179,12 @@ class Oracle:
         for key in ("J", "aref", "D", "efc_force"):
             o[key] = o[key][:r]
         return o
+
+    def cost(self, qpos, qvel, ctrl, a) -> float:
+        """The Newton cost F(a) of one world's step from (qpos, qvel) under ctrl."""
+        u = _arr(ctrl, self.nu) if ctrl is not None else np.zeros(max(self.nu, 1))
+        return float(self._lib.mjo_cost(self._h, _d(_arr(qpos, self.nq)),
+                                        _d(_arr(qvel, self.nv)), _d(u), _d(_arr(a, self.nv))))
 
     def inverse(self, qpos, qvel, qacc) -> np.ndarray:
         tau = np.zeros(self.nv)

@@ -18,7 +18,7 @@ Blob layout (little endian, version 2), every block 8-byte aligned:
                               inertia[6] (Ixx Iyy Izz Ixy Ixz Iyz, body frame, about ipos),
                               0, 0
   joint    int32 [njnt][4]  : type (0 free, 1 slide, 2 hinge), body, limited (0/1), 0
-           f64   [njnt][10] : pos[3], axis[3], damping, armature, range[2]
+           f64   [njnt][11] : pos[3], axis[3], damping, armature, range[2], frictionloss
   geom     int32 [ngeom][2] : type (0 plane, 1 sphere, 2 capsule, 3 box), body
            f64   [ngeom][11]: size[3], pos[3], quat[4], friction
   pair     int32 [npair][2] : geom1, geom2   (type(geom1) <= type(geom2))
@@ -28,7 +28,9 @@ Blob layout (little endian, version 2), every block 8-byte aligned:
   qpos0    f64   [nq]
 
 A limited hinge or slide joint keeps its coordinate inside range[0] < q < range[1]
-through a soft one-sided constraint (the joint-limit rows of the constraint set).
+through a soft one-sided constraint (the joint-limit rows of the constraint set).  A
+hinge or slide joint with frictionloss F > 0 gets a dry-friction row whose force is
+bounded by F.
 
 Geom sizes: sphere (r), capsule (r, half segment length; segment along local z),
 box (half extents).  Plane normal is the geom's local +z.
@@ -73,6 +75,7 @@ class Joint:
     armature: float = 0.0
     limited: bool = False
     range: Tuple[float, float] = (0.0, 0.0)
+    frictionloss: float = 0.0
     name: str = ""
 
 
@@ -139,6 +142,15 @@ class Model:
         return len(self.actuators)
 
     @property
+    def nfric(self) -> int:
+        """Dofs with friction loss: one constraint row each, always present."""
+        return sum(1 for j in self.joints if j.frictionloss > 0)
+
+    @property
+    def nrowmax(self) -> int:
+        return 4 * self.opt.nconmax + self.nlimit + self.nfric
+
+    @property
     def nlimit(self) -> int:
         """Limited joints: each adds at most one constraint row (one side at a time)."""
         return sum(1 for j in self.joints if j.limited)
@@ -175,6 +187,8 @@ class Model:
                 assert not j.limited, "free joints have no limits"
             if j.limited:
                 assert j.range[0] < j.range[1], "limited joint needs range[0] < range[1]"
+            assert j.frictionloss >= 0 and (j.type != JNT_FREE or j.frictionloss == 0), \
+                "friction loss needs a hinge or slide joint"
         for g1, g2, _ in self.pairs:
             assert self.geoms[g1].type <= self.geoms[g2].type, "pair order by geom type"
         assert self.qpos0 is not None and len(self.qpos0) == self.nq
@@ -202,8 +216,8 @@ class Model:
         parts.append(blk_f([[*b.pos, *b.quat, b.mass, *b.ipos, *b.inertia, 0, 0]
                             for b in self.bodies]))
         parts.append(blk_i([[j.type, j.body, int(bool(j.limited)), 0] for j in self.joints]))
-        parts.append(blk_f([[*j.pos, *j.axis, j.damping, j.armature, *j.range]
-                            for j in self.joints]))
+        parts.append(blk_f([[*j.pos, *j.axis, j.damping, j.armature, *j.range,
+                             j.frictionloss] for j in self.joints]))
         parts.append(blk_i([[g.type, g.body] for g in self.geoms]))
         parts.append(blk_f([[*g.size, *g.pos, *g.quat, g.friction] for g in self.geoms]))
         parts.append(blk_i([[p[0], p[1]] for p in self.pairs]))

@@ -120,12 +120,13 @@ class _Builder:
         return len(self.m.bodies) - 1
 
     def joint(self, body: int, type: int, axis=(0, 0, 1), pos=(0, 0, 0), damping=0.0,
-              armature=0.0, range=None, name="") -> int:
+              armature=0.0, range=None, frictionloss=0.0, name="") -> int:
         self.m.joints.append(Joint(type=type, body=body, pos=tuple(map(float, pos)),
                                    axis=tuple(map(float, axis)), damping=float(damping),
                                    armature=float(armature), limited=range is not None,
                                    range=(0.0, 0.0) if range is None else
-                                   (float(range[0]), float(range[1])), name=name))
+                                   (float(range[0]), float(range[1])),
+                                   frictionloss=float(frictionloss), name=name))
         return len(self.m.joints) - 1
 
     def geom(self, body: int, type: int, size, pos=(0, 0, 0), quat=(1, 0, 0, 0),
@@ -216,22 +217,29 @@ QUAD_STAND_Z = 0.2 * math.sqrt(2.0) + 0.025
 QUAD_RANGE_HALF = (0.15, 0.15, 0.15)
 
 
+# dry joint friction of the quadruped_friction workload (N m): large enough that with
+# the random PD targets about a fifth of the hinges stick at a time, the rest slip
+QUAD_FRICTIONLOSS = 3.0
+
+
 def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
-              limits: bool = False) -> Model:
+              limits: bool = False, frictionloss: float = 0.0) -> Model:
     """Free torso (box 0.3x0.1x0.05 m, 5 kg) + 4 legs x 3 hinges (capsules r 0.02,
     length 0.2, 0.5 kg) with massless sphere feet (r 0.025).  nq 19, nv 18, nu 12.
 
     With ``limits`` every hinge is limited to its default angle +- 0.15 rad, narrower
     than the initial noise and the reach of the random PD targets, so that limit rows
     switch on and off all through a rollout (with the benchmark inputs about 2.3 of
-    the 12 are active on average, up to 7).
+    the 12 are active on average, up to 7).  With ``frictionloss`` every hinge carries
+    that dry friction (one friction-loss row each).
 
     Each leg: hip link (hinge about x, capsule lateral 0.2 m), thigh (hinge about y,
     capsule down 0.2 m), shin (hinge about y, capsule down 0.2 m, foot sphere).
     Position (PD) actuators kp 35, kd 0.5 on every hinge; ctrl is the target offset from
     the default pose (0, pi/4, -pi/2) per leg.  Only the feet collide (plane x 4 feet).
     """
-    bld = _Builder("quadruped_limits" if limits else "quadruped")
+    bld = _Builder("quadruped" + ("_limits" if limits else "") +
+                   ("_friction" if frictionloss > 0 else ""))
 
     def rng(k):
         if not limits:
@@ -247,15 +255,15 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     for i, (sx, sy) in enumerate(((1, 1), (1, -1), (-1, 1), (-1, -1))):
         hip = bld.body(torso, pos=(0.15 * sx, 0.05 * sy, 0.0), name=f"hip{i}")
         hinge_ids.append(bld.joint(hip, JNT_HINGE, axis=(1, 0, 0), range=rng(0),
-                                   name=f"abd{i}"))
+                                   frictionloss=frictionloss, name=f"abd{i}"))
         bld.capsule_fromto(hip, (0, 0, 0), (0, 0.2 * sy, 0), 0.02, mass=0.5)
         thigh = bld.body(hip, pos=(0, 0.2 * sy, 0), name=f"thigh{i}")
         hinge_ids.append(bld.joint(thigh, JNT_HINGE, axis=(0, 1, 0), range=rng(1),
-                                   name=f"hip{i}"))
+                                   frictionloss=frictionloss, name=f"hip{i}"))
         bld.capsule_fromto(thigh, (0, 0, 0), (0, 0, -0.2), 0.02, mass=0.5)
         shin = bld.body(thigh, pos=(0, 0, -0.2), name=f"shin{i}")
         hinge_ids.append(bld.joint(shin, JNT_HINGE, axis=(0, 1, 0), range=rng(2),
-                                   name=f"knee{i}"))
+                                   frictionloss=frictionloss, name=f"knee{i}"))
         bld.capsule_fromto(shin, (0, 0, 0), (0, 0, -0.2), 0.02, mass=0.5)
         feet.append(bld.geom(shin, GEOM_SPHERE, (0.025,), pos=(0, 0, -0.2), friction=mu,
                              name=f"foot{i}"))
@@ -441,12 +449,20 @@ def quadruped_limits() -> Model:
     return quadruped(limits=True)
 
 
+def quadruped_friction() -> Model:
+    """The quadruped with dry friction QUAD_FRICTIONLOSS on every hinge."""
+    return quadruped(frictionloss=QUAD_FRICTIONLOSS)
+
+
 def slider(mass: float = 2.0, armature: float = 0.0, range=(0.0, 1.0), axis=(0, 0, 1),
-           gravity=(0.0, 0.0, -9.81), timestep: float = 0.002) -> Model:
-    """One sphere on a limited slide joint (nv 1): the one-dof limit problem."""
+           gravity=(0.0, 0.0, -9.81), timestep: float = 0.002,
+           frictionloss: float = 0.0) -> Model:
+    """One sphere on a slide joint (nv 1), limited to ``range`` unless it is None: the
+    one-dof limit and friction-loss problems."""
     bld = _Builder("slider")
     b = bld.body(0, name="slider")
-    bld.joint(b, JNT_SLIDE, axis=axis, armature=armature, range=range)
+    bld.joint(b, JNT_SLIDE, axis=axis, armature=armature, range=range,
+              frictionloss=frictionloss)
     bld.geom(b, GEOM_SPHERE, (0.05,), mass=mass)
     m = bld.finish()
     m.opt = Options(timestep=timestep, gravity=tuple(gravity), iterations=8, nconmax=0)
@@ -455,23 +471,26 @@ def slider(mass: float = 2.0, armature: float = 0.0, range=(0.0, 1.0), axis=(0, 
 
 
 def hinge_chain(n: int = 4, link: float = 0.3, mass: float = 1.0, damping: float = 0.0,
-                axes=None, slide_root: bool = False, limit: float = None) -> Model:
+                axes=None, slide_root: bool = False, limit: float = None,
+                frictionloss: float = 0.0) -> Model:
     """Planar/spatial chain of capsule links hanging from the world (no contacts).
     With ``limit`` every hinge is limited to [-limit, limit] (and the slide root to
-    [-2 limit, 2 limit])."""
+    [-2 limit, 2 limit]).  Every joint gets dry friction ``frictionloss``."""
     bld = _Builder(f"chain{n}")
     parent, pos = 0, (0, 0, 0)
     if slide_root:
         cart = bld.body(0, name="cart")
         bld.joint(cart, JNT_SLIDE, axis=(1, 0, 0), damping=damping,
-                  range=None if limit is None else (-2 * limit, 2 * limit))
+                  range=None if limit is None else (-2 * limit, 2 * limit),
+                  frictionloss=frictionloss)
         bld.geom(cart, GEOM_BOX, (0.1, 0.1, 0.1), mass=2.0)
         parent = cart
     for i in range(n):
         b = bld.body(parent, pos=pos)
         ax = (0, 1, 0) if axes is None else axes[i % len(axes)]
         bld.joint(b, JNT_HINGE, axis=ax, damping=damping,
-                  range=None if limit is None else (-limit, limit))
+                  range=None if limit is None else (-limit, limit),
+                  frictionloss=frictionloss)
         bld.capsule_fromto(b, (0, 0, 0), (link, 0, 0), 0.03, mass=mass)
         parent, pos = b, (link, 0, 0)
     m = bld.finish()
@@ -537,6 +556,7 @@ WORKLOADS = {
     "cartpole": cartpole,
     "quadruped": quadruped,
     "quadruped_limits": quadruped_limits,
+    "quadruped_friction": quadruped_friction,
     "humanoid": humanoid,
     "hand": hand,
 }
