@@ -68,7 +68,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--model", default="quadruped",
-                    choices=["quadruped", "quadruped_limits", "humanoid", "hand", "cartpole"],
+                    choices=["quadruped", "quadruped_limits", "quadruped_friction", "humanoid",
+                             "hand", "cartpole"],
                     help="robot of the timed batch (the headline metric is the quadruped)")
     ap.add_argument("--nworld", type=int, default=8192)
     ap.add_argument("--nstep", type=int, default=1000)
@@ -83,7 +84,8 @@ def parse():
     ap.add_argument("--no-hetero", action="store_true",
                     help="skip the heterogeneous-batch comparison")
     ap.add_argument("--no-limits", action="store_true",
-                    help="skip the joint-limit workload (quadruped with limited hinges)")
+                    help="skip the joint-limit and friction-loss workloads (quadruped with "
+                         "limited hinges, quadruped with dry joint friction)")
     ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a reference "
@@ -184,16 +186,15 @@ def rollout_compare(ctx, seed, nw=1024, horizon=64, ckpt=8, reps=3):
             "launch": [team, block]}
 
 
-def limits_compare(ctx, seed, nw=8192, nstep=1000, reps=3):
-    """The quadruped with every hinge limited (joint-limit rows beside the contacts),
-    8192 worlds x 1000 steps in its default launch, next to the plain quadruped."""
+def constraint_compare(ctx, seed, kind, what, nw=8192, nstep=1000, reps=3):
+    """A quadruped variant with more constraint rows beside the contacts (limited
+    hinges, or dry joint friction), 8192 worlds x 1000 steps in its default launch."""
     import torch
     from paper_2502_08844_amd import mjh
     from paper_2502_08844_amd.synth import inputs, robots
     stream = torch.cuda.current_stream()
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
-    kind = "quadruped_limits"
     m = robots.WORKLOADS[kind]()
     qp, qv = inputs.initial_state(kind, m, nw, seed=seed)
     w = mjh.World(ctx, ctx.model_upload(m), nw, qpos=qp, qvel=qv)
@@ -207,10 +208,9 @@ def limits_compare(ctx, seed, nw=8192, nstep=1000, reps=3):
     run()
     ms = timed(run, stream, reps)
     status = w.status.cpu()
-    return {"workload": f"quadruped with limited hinges (default angle +- 0.15 rad), {nw} "
-                        f"worlds x {nstep} steps",
+    return {"workload": f"quadruped with {what}, {nw} worlds x {nstep} steps",
             "world_steps_per_s": round(nw * nstep / (ms * 1e-3), 1),
-            "nrowmax": 4 * m.opt.nconmax + m.nlimit,
+            "nrowmax": m.nrowmax,
             "launch": list(w.batch.get_launch(0)),
             "status_nonzero_worlds": int((status != 0).sum())}
 
@@ -307,7 +307,7 @@ def main():
     # controls resampled every step, resident in HBM, drawn on the device with the
     # distributions of the synthetic workloads
     shape = (ns, nw, m.nu)
-    if kind in ("quadruped", "quadruped_limits"):  # PD target offsets U(-0.5, 0.5)
+    if kind.startswith("quadruped"):  # PD target offsets U(-0.5, 0.5)
         ctrl = torch.rand(shape, device=dev, generator=gen) - 0.5
     elif kind == "humanoid":   # torques N(0, 0.3) clipped to [-1, 1]
         ctrl = (0.3 * torch.randn(shape, device=dev, generator=gen)).clamp_(-1.0, 1.0)
@@ -392,7 +392,11 @@ def main():
     if not args.no_hetero:
         out["hetero"] = hetero_compare(ctx, args.seed)
     if not args.no_limits:
-        out["limits"] = limits_compare(ctx, args.seed)
+        out["limits"] = constraint_compare(ctx, args.seed, "quadruped_limits",
+                                           "limited hinges (default angle +- 0.15 rad)")
+        out["friction_loss"] = constraint_compare(
+            ctx, args.seed, "quadruped_friction",
+            f"dry joint friction {robots.QUAD_FRICTIONLOSS} N m on every hinge")
     if not args.no_cpu_baseline:
         nthreads = min(os.cpu_count() or 1, 16)
         cw = min(args.cpu_sample_worlds, nw)

@@ -75,7 +75,8 @@ typedef struct mjh_dims {
   int32_t lds_bytes;  /* on-chip working set of one world                        */
   float timestep;
   int32_t nlimit;     /* limited hinge/slide joints (at most one row each)        */
-  int32_t nrowmax;    /* constraint rows per world: 4 nconmax + nlimit            */
+  int32_t nrowmax;    /* constraint rows per world: 4 nconmax + nlimit + nfric    */
+  int32_t nfric;      /* dofs with friction loss (one row each, always present)   */
 } mjh_dims;
 
 /* One context per device.  device: HIP device ordinal.  *out receives the handle. */
@@ -94,7 +95,9 @@ const char* mjh_last_error(const mjh_ctx* ctx);
  * MJX physics uses): a joint whose coordinate q lies outside its range adds one row
  * after the contact rows, in joint order, with distance r = q - lo and J = e_dof below
  * the range, r = hi - q and J = -e_dof above it, and the regulariser's A = (M^-1)_kk
- * at qpos0.
+ * at qpos0.  A hinge or slide joint with friction loss F > 0 (dry joint friction)
+ * adds one row after those, in dof order, always present: J = e_dof, r = 0, the same
+ * A, and a force confined to [-F, F] (a Huber term in the solver's cost).
  * MJH_EMODEL for a malformed blob, MJH_EUNSUPPORTED for nv > 64, box-box pairs,
  * a free joint below the root or two actuators on one dof. */
 mjh_status mjh_model_upload(mjh_ctx* ctx, const void* blob, size_t nbytes,

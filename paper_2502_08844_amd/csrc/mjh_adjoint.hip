@@ -113,8 +113,11 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
   const float h = m.dt;
   const int ncon = ((const int*)(W + m.o_scal))[SC_NCON];
   const int nrow = ((const int*)(W + m.o_scal))[SC_NROW];
-  const int nrc = 4 * ncon;  // contact rows; joint-limit rows follow
+  const int nrc = 4 * ncon;  // contact rows; joint-limit rows follow, then friction loss
+  const int nrf = nrow - m.nfric;
+  const int nl = nrf - nrc;
   const int* lim = (const int*)(W + m.o_lim);
+  const float* fl = W + m.o_fl;
   const float* qpos = W + m.o_qpos;
   const float* qvel = W + m.o_qvel;
   const float* a = W + m.o_qacc;
@@ -361,11 +364,13 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
         sv += jr * mu[i]; xv += jr * qvel[i]; yv += jr * a[i];
       }
       float al = 0.f, be = 0.f, ga = 0.f, rho = 0.f;
-      if (e[r] < 0.f) {
-        float dist;
+      // rows on their quadratic piece; a friction row on a linear piece has the constant
+      // slope +-F and carries no cotangent
+      if (row_quad(D[r], r < nrf ? 0.f : fl[r], e[r])) {
+        float dist = 0.f;  // friction loss: r = 0, not a function of the state
         if (r < nrc) {
           dist = con[kConRec * (r >> 2)];
-        } else {
+        } else if (r < nrf) {
           int dof;
           float sg;
           limit_row(m, W, lim[r - nrc], dof, sg, dist);
@@ -379,7 +384,7 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
         al = Dv * core;
         be = m.B * Dv * sv;
         ga = Dv * sv;
-        rho = sv * (Dp * core + Dv * m.K * (dd * dist + d));
+        rho = r < nrf ? sv * (Dp * core + Dv * m.K * (dd * dist + d)) : 0.f;
       }
       float* o = rs + 7 * r;
       o[0] = sv; o[1] = xv; o[2] = yv; o[3] = al; o[4] = be; o[5] = ga; o[6] = rho;
@@ -392,9 +397,9 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
       float sb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       for (int r = 0; r < nrow; r++) {
         const float* o = rs + 7 * r;
-        if (!(e[r] < 0.f)) continue;
+        if (!row_quad(D[r], r < nrf ? 0.f : fl[r], e[r])) continue;
         vadd += o[4] * J[r * nv + k];
-        if (r >= nrc) continue;  // a limit row's Jacobian is constant
+        if (r >= nrc) continue;  // limit and friction rows: constant Jacobians
         const float* rec = con + kConRec * (r >> 2);
         const int b1 = __float_as_int(rec[14]), b2 = __float_as_int(rec[15]);
         const bool in2 = (m.body_dofmask[b2] & bit) != 0, in1 = (m.body_dofmask[b1] & bit) != 0;
@@ -456,7 +461,7 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
       o[7] = (kind == PK_PLANE_SPHERE || kind == PK_PLANE_CAPSULE) ? 1.f : 0.f;
     }
     // joint limits: the distance cotangent goes to the joint coordinate, r = +-(q - end)
-    for (int k = t.lane; k < nrow - nrc; k += t.T) {
+    for (int k = t.lane; k < nl; k += t.T) {
       int dof;
       float sg, dist;
       limit_row(m, W, lim[k], dof, sg, dist);

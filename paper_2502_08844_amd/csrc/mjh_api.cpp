@@ -32,7 +32,8 @@ struct HostModel {
   std::vector<int> body_parent, jnt_type, jnt_body, jnt_limited, geom_type, geom_body,
       pair_g1, pair_g2, act_type, act_jnt;
   std::vector<double> body_pos, body_quat, body_mass, body_ipos, body_inertia, jnt_pos,
-      jnt_axis, jnt_damping, jnt_armature, jnt_range, geom_size, geom_pos, geom_quat, pair_mu,
+      jnt_axis, jnt_damping, jnt_armature, jnt_range, jnt_frictionloss, geom_size, geom_pos,
+      geom_quat, pair_mu,
       act_gear, act_kp, act_kd, act_lo, act_hi, act_qdef, qpos0;
 };
 
@@ -87,7 +88,7 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   std::vector<int32_t> bi, ji, gi, pi, ai;
   std::vector<double> bf, jf, gf, pf, af;
   bool ok = rd(bi, 2 * m.nbody) && rd(bf, 19 * (size_t)m.nbody) && rd(ji, 4 * m.njnt) &&
-            rd(jf, 10 * (size_t)m.njnt) && rd(gi, 2 * m.ngeom) && rd(gf, 11 * (size_t)m.ngeom) &&
+            rd(jf, 11 * (size_t)m.njnt) && rd(gi, 2 * m.ngeom) && rd(gf, 11 * (size_t)m.ngeom) &&
             rd(pi, 2 * m.npair) && rd(pf, m.npair) && rd(ai, 2 * m.nu) &&
             rd(af, 7 * (size_t)m.nu) && rd(m.qpos0, m.nq);
   if (!ok || r.off() != nbytes) { err = "model blob: size mismatch"; return MJH_EMODEL; }
@@ -111,11 +112,16 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
       err = "model blob: bad joint (type/body/order)";
       return MJH_EMODEL;
     }
-    const double* f = &jf[10 * j];
+    const double* f = &jf[11 * j];
     if (limited && (type == JNT_FREE || !(f[8] < f[9]))) {
       err = "model blob: a limit needs a hinge or slide joint and range[0] < range[1]";
       return MJH_EMODEL;
     }
+    if (!(f[10] >= 0.0) || (type == JNT_FREE && f[10] != 0.0)) {
+      err = "model blob: friction loss needs a hinge or slide joint and a bound >= 0";
+      return MJH_EMODEL;
+    }
+    m.jnt_frictionloss.push_back(f[10]);
     m.jnt_type.push_back(type);
     m.jnt_body.push_back(body);
     m.jnt_limited.push_back(limited);
@@ -299,7 +305,16 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
       lim_hi.push_back((float)h.jnt_range[2 * j + 1]);
     }
   d.nlim = (int)lim_qadr.size();
-  d.nrowmax = 4 * h.nconmax + d.nlim;
+  // friction loss, in dof order (hinge and slide joints: one dof each)
+  std::vector<int> fric_dadr;
+  std::vector<float> fric_loss;
+  for (int j = 0; j < h.njnt; j++)
+    if (h.jnt_frictionloss[j] > 0.0) {
+      fric_dadr.push_back(jnt_dofadr[j]);
+      fric_loss.push_back((float)h.jnt_frictionloss[j]);
+    }
+  d.nfric = (int)fric_dadr.size();
+  d.nrowmax = 4 * h.nconmax + d.nlim + d.nfric;
   // pairs and candidate slots
   std::vector<int> pair_kind, pair_candadr, cand_pair;
   int ncand = 0;
@@ -360,6 +375,8 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   pk.add(lim_dadr, &d.lim_dadr);
   pk.add(lim_lo, &d.lim_lo);
   pk.add(lim_hi, &d.lim_hi);
+  pk.add(fric_dadr, &d.fric_dadr);
+  pk.add(fric_loss, &d.fric_loss);
   std::vector<float> bpos = fv(h.body_pos), bmass = fv(h.body_mass), bipos = fv(h.body_ipos),
                      binert = fv(h.body_inertia), jpos = fv(h.jnt_pos), jaxis = fv(h.jnt_axis),
                      gsize = fv(h.geom_size), gpos = fv(h.geom_pos), pmu = fv(h.pair_mu),
@@ -387,8 +404,8 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   pk.add(aqd, &d.act_qdef);
   pk.add(q0, &d.qpos0);
   pk.add(invw, const_cast<const float**>(&d.body_invweight));
-  std::vector<float> lim_invw(d.nlim, 0.f);
-  pk.add(lim_invw, const_cast<const float**>(&d.lim_invweight));
+  std::vector<float> dof_invw(h.nv, 0.f);
+  pk.add(dof_invw, const_cast<const float**>(&d.dof_invweight));
   // on-chip layout in 4-byte words, regions packed back to back (every LDS access is a
   // scalar 32-bit one, so no region needs more alignment)
   int off = 0;
@@ -441,6 +458,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   d.o_D = take(nr);
   d.o_e = take(nr);
   d.o_s = take(nr);
+  d.o_fl = take(d.nfric > 0 ? nr : 0);  // per-row friction bound (0: one-sided row)
   off = std::max(off, sweep_end);
   d.lds_words = off;
   // Table of the packed lower triangle at the head of a work-group's LDS: index
@@ -472,7 +490,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   x.o_Md = take(nv); x.o_tmp = take(nv); x.o_cand = take(2 * ncand);
   x.o_con = take(kConRec * h.nconmax); x.o_lim = take(d.nlim); x.o_J = take(nr * nv);
   x.o_aref = take(nr);
-  x.o_D = take(nr); x.o_e = take(nr); x.o_s = take(nr);
+  x.o_D = take(nr); x.o_e = take(nr); x.o_s = take(nr); x.o_fl = take(d.nfric > 0 ? nr : 0);
   x.o_qbi = take(h.nq); x.o_vbi = take(nv); x.o_qb = take(h.nq); x.o_vb = take(nv);
   x.o_ub = take(h.nu); x.o_mu = take(nv); x.o_Sbar = take(6 * nv);
   x.o_xbar = take(3 * nb); x.o_Rbar = take(9 * nb); x.o_cinbar = take(kCinert * nb);
@@ -684,7 +702,7 @@ mjh_status mjh_model_info(mjh_ctx* ctx, int32_t model_id, mjh_dims* out) {
   out->nq = d.nq; out->nv = d.nv; out->nu = d.nu; out->nbody = d.nbody; out->ngeom = d.ngeom;
   out->npair = d.npair; out->ncand = d.ncand; out->nconmax = d.nconmax;
   out->iterations = d.iterations; out->lds_bytes = d.lds_words * 4; out->timestep = d.dt;
-  out->nlimit = d.nlim; out->nrowmax = d.nrowmax;
+  out->nlimit = d.nlim; out->nrowmax = d.nrowmax; out->nfric = d.nfric;
   return MJH_OK;
 }
 
@@ -694,8 +712,16 @@ mjh_status mjh_model_limit_invweight(mjh_ctx* ctx, int32_t model_id, float* out)
       (!out && ctx->models[model_id]->dm.nlim > 0))
     return fail(ctx, MJH_EINVAL, "model_limit_invweight: bad model id or NULL output");
   const DevModel& d = ctx->models[model_id]->dm;
-  if (d.nlim > 0)
-    MJH_HIP(hipMemcpy(out, d.lim_invweight, d.nlim * sizeof(float), hipMemcpyDeviceToHost));
+  if (d.nlim > 0) {
+    std::vector<float> all(d.nv);
+    MJH_HIP(hipMemcpy(all.data(), d.dof_invweight, d.nv * sizeof(float), hipMemcpyDeviceToHost));
+    const ModelRec& rec = *ctx->models[model_id];
+    int l = 0, da = 0;
+    for (int j = 0; j < rec.h.njnt; j++) {
+      if (rec.h.jnt_limited[j]) out[l++] = all[da];
+      da += rec.h.jnt_type[j] == JNT_FREE ? 6 : 1;
+    }
+  }
   return MJH_OK;
 }
 
@@ -876,7 +902,7 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
     const DevModel& d = ctx->models[g.model]->dm;
     std::ostringstream k;
     k << d.nq << ' ' << d.nv << ' ' << d.nbody << ' ' << d.npair << ' ' << d.nconmax << ' '
-      << d.nlim << ' ' << d.iterations << ' ' << g.nworld;
+      << d.nlim << ' ' << d.nfric << ' ' << d.iterations << ' ' << g.nworld;
     return k.str();
   };
   if (cache_path) {

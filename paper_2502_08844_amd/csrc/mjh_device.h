@@ -851,6 +851,8 @@ DEV void limit_row(const DevModel& m, const float* W, int code, int& dof, float&
 // acceleration aref = -B (J_e qvel) - K d(r) r, regulariser R = (1-d)/d (1+mu^2)
 // (w1 + w2), D = 1/R.  Then one row per joint outside its range, in joint order:
 // J = +-e_dof, r the distance past the range end, R = (1-d)/d (M^-1)_kk at qpos0.
+// Then one friction-loss row per dof with a bound F > 0, always: J = e_dof, r = 0,
+// the same R, and the bound stored per row (0 marks a one-sided row).
 // Writes the row count to the SC_NROW slot.
 DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
   int* scal = (int*)(W + m.o_scal);
@@ -875,7 +877,8 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
     if (act) lim[slot] = code;
     nl += t.isum(act);
   }
-  const int nrow = nrc + nl;
+  const int nrf = nrc + nl;  // first friction-loss row
+  const int nrow = nrf + m.nfric;
   if (t.lane == 0) scal[SC_NROW] = nrow;
   for (int idx = t.lane; idx < ncon * nv; idx += t.T) {
     const int c = idx / nv, i = idx - c * nv;
@@ -906,6 +909,10 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
     limit_row(m, W, lim[k], dof, sg, dist);
     J[(nrc + k) * nv + i] = i == dof ? sg : 0.f;
   }
+  for (int idx = t.lane; idx < m.nfric * nv; idx += t.T) {
+    const int k = idx / nv, i = idx - k * nv;
+    J[(nrf + k) * nv + i] = i == m.fric_dadr[k] ? 1.f : 0.f;
+  }
   t.sync();
   const float* qvel = W + m.o_qvel;
   float* aref = W + m.o_aref;
@@ -919,19 +926,40 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
       const int b1 = __float_as_int(r[14]), b2 = __float_as_int(r[15]);
       const float mu = r[13];
       A = (1.f + mu * mu) * (m.body_invweight[b1] + m.body_invweight[b2]);
-    } else {
+    } else if (row < nrf) {
       const int code = lim[row - nrc];
       int dof;
       float sg;
       limit_row(m, W, code, dof, sg, dist);
       jv = sg * qvel[dof];
-      A = m.lim_invweight[code & 0xffff];
+      A = m.dof_invweight[dof];
+    } else {
+      const int dof = m.fric_dadr[row - nrf];
+      dist = 0.f;
+      jv = qvel[dof];
+      A = m.dof_invweight[dof];
     }
     const float imp = impedance(m, dist);
     aref[row] = -m.B * jv - m.K * imp * dist;
     D[row] = imp / ((1.f - imp) * fmaxf(A, 1e-15f));
+    if (m.nfric > 0) W[m.o_fl + row] = row < nrf ? 0.f : m.fric_loss[row - nrf];
   }
   t.sync();
+}
+
+// Pieces of a row's cost s(e) in the Newton solve: one-sided rows (bound F = 0)
+// s = 1/2 D min(0, e)^2; friction-loss rows (F > 0) the Huber term, 1/2 D e^2 while
+// |D e| <= F, else F |e| - F^2 / (2 D).
+DEV float row_cost(float D, float F, float e) {
+  if (F == 0.f) return e < 0.f ? 0.5f * D * e * e : 0.f;
+  return fabsf(D * e) <= F ? 0.5f * D * e * e : F * fabsf(e) - 0.5f * F * F / D;
+}
+DEV float row_slope(float D, float F, float e) {  // s'(e), D min(0, e) or clamp(D e, +-F)
+  const float v = D * e;
+  return F == 0.f ? fminf(v, 0.f) : fminf(fmaxf(v, -F), F);
+}
+DEV bool row_quad(float D, float F, float e) {  // on the quadratic piece: curvature D
+  return F == 0.f ? e < 0.f : fabsf(D * e) < F;
 }
 
 // --------------------------------------------------- A9: Newton solve (NW ch. 3, 6)
@@ -960,6 +988,8 @@ DEV int pad_rows(const DevModel& m, float* W, const Team& t, int nrow) {
   float* e = W + m.o_e;
   float* s = W + m.o_s;
   for (int r = nrow + t.lane; r < nru; r += t.T) { D[r] = 0.f; e[r] = 0.f; s[r] = 0.f; }
+  if (m.nfric > 0)
+    for (int r = nrow + t.lane; r < nru; r += t.T) W[m.o_fl + r] = 0.f;
   t.sync();
   return nru;
 }
@@ -970,7 +1000,7 @@ DEV int pad_rows(const DevModel& m, float* W, const Team& t, int nrow) {
 // costs one, used unscaled by its own trailing update and scaled in the next barrier
 // interval.  When `y` is given the
 // forward solve L y = b (b overwritten) rides along.  Returns false for a non-positive
-// pivot.  `w` (nrow words) receives the active rows' weights D (0 when inactive).
+// pivot.  `w` (nrow words) receives the rows' curvatures: D on the quadratic piece, else 0.
 DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
                           float* b = nullptr, float* y = nullptr) {
   const int nv = m.nv;
@@ -980,7 +1010,12 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
   const float* D = W + m.o_D;
   const float* e = W + m.o_e;
   float* w = W + m.o_s;  // row weights; the line search rewrites this scratch later
-  for (int r = t.lane; r < nru; r += t.T) w[r] = e[r] < 0.f ? D[r] : 0.f;
+  if (m.nfric > 0) {
+    const float* fl = W + m.o_fl;
+    for (int r = t.lane; r < nru; r += t.T) w[r] = row_quad(D[r], fl[r], e[r]) ? D[r] : 0.f;
+  } else {
+    for (int r = t.lane; r < nru; r += t.T) w[r] = e[r] < 0.f ? D[r] : 0.f;
+  }
   t.sync();
   if (t.T == 64 && nv <= 32) {
     // One world per wavefront: H = M + sum_r w_r J_r^T J_r as a dense contraction on
@@ -1208,14 +1243,19 @@ DEV void cholesky_back(const DevModel& m, float* W, const Team& t, const float* 
   t.sync();
 }
 
-// F(a) = 1/2 (a - a0)^T M (a - a0) + sum_r 1/2 D_r min(0, J_r a - aref_r)^2.
+// F(a) = 1/2 (a - a0)^T M (a - a0) + sum_r s_r(J_r a - aref_r), with the row pieces of
+// row_cost (1/2 D min(0, e)^2 for one-sided rows, the Huber term for friction loss).
 // Start from the cheaper of the warm start and a0; each iteration: gradient and
 // Hessian on the active set, dense Cholesky of H, Newton direction, exact line
 // search (phi' evaluated at every breakpoint in parallel), update.  Stops early when
 // the Newton direction is no longer a descent direction (converged to precision) or,
-// with gtol > 0, when max |g| <= gtol * max(1, max |qfrc_smooth|).
-DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int iters,
-                float gtol = 0.f) {
+// with gtol > 0, when max |g| <= gtol * max(1, max |qfrc_smooth|).  FR: the model has
+// friction-loss rows (two breakpoints each, Huber pieces); without them every row is
+// one-sided and the loops keep their shorter form.
+template <bool FR>
+DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, int iters,
+                     float gtol) {
+  const float* fl = W + m.o_fl;  // per-row friction bound (FR only)
   const int* scal = (const int*)(W + m.o_scal);
   const int nv = m.nv, nrow = scal[SC_NROW];
   const float* M = W + m.o_M;
@@ -1252,8 +1292,13 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int ite
     float jw = 0.f, j0 = 0.f;
     for (int i = 0; i < nv; i++) { jw += J[r * nv + i] * a[i]; j0 += J[r * nv + i] * a0[i]; }
     const float ew = jw - aref[r], e0 = j0 - aref[r];
-    if (ew < 0.f) cw += 0.5f * D[r] * ew * ew;
-    if (e0 < 0.f) c0 += 0.5f * D[r] * e0 * e0;
+    if (FR) {
+      cw += row_cost(D[r], fl[r], ew);
+      c0 += row_cost(D[r], fl[r], e0);
+    } else {
+      if (ew < 0.f) cw += 0.5f * D[r] * ew * ew;
+      if (e0 < 0.f) c0 += 0.5f * D[r] * e0 * e0;
+    }
     e[r] = ew;
     s[r] = e0;  // stash
   }
@@ -1279,7 +1324,7 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int ite
       float v = Mr[i];
       for (int r = 0; r < nru; r++) {
         const float er = e[r];
-        v += (er < 0.f ? D[r] * er : 0.f) * J[r * nv + i];
+        v += (FR ? row_slope(D[r], fl[r], er) : (er < 0.f ? D[r] * er : 0.f)) * J[r * nv + i];
       }
       g[i] = v;
       gmax = fmaxf(gmax, fabsf(v));
@@ -1312,16 +1357,22 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int ite
     // phi'(al) = dMr + al dMd + sum_r D_r s_r min(0, e_r + al s_r), nondecreasing.
     // Evaluate it at every positive breakpoint; the root lies between the largest
     // breakpoint with phi' <= 0 and the smallest with phi' > 0, where phi' is linear.
+    // Breakpoints: a one-sided row's e crosses 0; a friction row's D e crosses +F
+    // (candidate r) and -F (candidate nrow + its index among the friction rows).
     float lo = 0.f, hi = INFINITY;
-    for (int r = t.lane; r < nrow; r += t.T) {
+    const int nbp = FR ? nrow + m.nfric : nrow;
+    for (int c = t.lane; c < nbp; c += t.T) {
+      const int r = c < nrow ? c : nrow - m.nfric + (c - nrow);
       const float sr = s[r];
       if (sr == 0.f) continue;
-      const float br = -e[r] / sr;
+      float at = 0.f;
+      if (FR && fl[r] > 0.f) at = (c < nrow ? fl[r] : -fl[r]) / D[r];
+      const float br = (at - e[r]) / sr;
       if (!(br > 0.f)) continue;
       float dp = dMr + br * dMd;
       for (int q = 0; q < nru; q++) {
         const float sq = s[q], v = e[q] + br * sq;
-        dp += (v < 0.f ? D[q] * sq : 0.f) * v;
+        dp += FR ? sq * row_slope(D[q], fl[q], v) : (v < 0.f ? D[q] * sq : 0.f) * v;
       }
       if (dp <= 0.f) lo = fmaxf(lo, br);
       else hi = fminf(hi, br);
@@ -1331,7 +1382,13 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int ite
     const float probe = (hi < INFINITY) ? 0.5f * (lo + hi) : lo + 1.f;
     float Ac = 0.f, Bc = 0.f;
     for (int r = t.lane; r < nrow; r += t.T) {
-      if (e[r] + probe * s[r] < 0.f) { Ac += D[r] * s[r] * e[r]; Bc += D[r] * s[r] * s[r]; }
+      const float ep = e[r] + probe * s[r];
+      if (FR ? row_quad(D[r], fl[r], ep) : ep < 0.f) {
+        Ac += D[r] * s[r] * e[r];
+        Bc += D[r] * s[r] * s[r];
+      } else if (FR) {
+        Ac += s[r] * row_slope(D[r], fl[r], ep);  // +-F on a friction row's linear piece
+      }
     }
     Ac = t.sum(Ac) + dMr;
     Bc = t.sum(Bc) + dMd;
@@ -1342,6 +1399,11 @@ DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int ite
     for (int r = t.lane; r < nrow; r += t.T) e[r] += al * s[r];
     t.sync();
   }
+}
+DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int iters,
+                float gtol = 0.f) {
+  if (m.nfric > 0) newton_impl<true>(m, W, t, status, iters, gtol);
+  else newton_impl<false>(m, W, t, status, iters, gtol);
 }
 
 // ------------------------------------------------- A10: forces, A11: integration

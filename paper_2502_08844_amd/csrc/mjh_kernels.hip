@@ -86,8 +86,7 @@ mjh_step_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__
 
 // Translational inverse weight of every body at qpos0:
 //   w(b) = trace(J_com(b) M^-1 J_com(b)^T) / 3,
-// and (M^-1)_kk of every limited dof k, one work-group of 64 lanes evaluating the model
-// once.
+// and (M^-1)_kk of every dof k, one work-group of 64 lanes evaluating the model once.
 __global__ void __launch_bounds__(64) mjh_invweight_kernel(DevModel m, int tab_words) {
   extern __shared__ float lds[];
   load_pair_table(m, (unsigned*)lds);
@@ -133,13 +132,12 @@ __global__ void __launch_bounds__(64) mjh_invweight_kernel(DevModel m, int tab_w
     }
     if (t.lane == 0) m.body_invweight[b] = tr / 3.f;
   }
-  // joint-limit rows: (M^-1)_kk of each limited dof
-  for (int l = 0; l < m.nlim; l++) {
-    const int k = m.lim_dadr[l];
+  // joint-limit and friction-loss rows: (M^-1)_kk of every dof
+  for (int k = 0; k < m.nv; k++) {
     for (int i = t.lane; i < m.nv; i += t.T) jr[i] = i == k ? 1.f : 0.f;
     t.sync();
     ltdl_solve(m, W, t, jr, x);
-    if (t.lane == 0) m.lim_invweight[l] = x[k];
+    if (t.lane == 0) m.dof_invweight[k] = x[k];
     t.sync();
   }
 }

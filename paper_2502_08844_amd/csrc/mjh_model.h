@@ -31,7 +31,7 @@ constexpr int kCinert = 10;     // spatial inertia: m, m c (3), I at origin (6)
 
 struct DevModel {
   // ---- sizes
-  int nbody, njnt, nq, nv, nu, ngeom, npair, ncand, nconmax, nlim, nrowmax;
+  int nbody, njnt, nq, nv, nu, ngeom, npair, ncand, nconmax, nlim, nfric, nrowmax;
   int iterations, nlevel, nmpair, ntri;
   // ---- constants
   float dt, K, B;                       // soft-constraint stiffness/damping
@@ -70,6 +70,7 @@ struct DevModel {
   const int* act_dadr;
   const int* lim_qadr;      // [nlim] qpos address of each limited joint (joint order)
   const int* lim_dadr;      // [nlim] its dof
+  const int* fric_dadr;     // [nfric] dofs with friction loss (dof order)
   // ---- float tables
   const float* body_pos;      // [nbody][3] in parent frame
   const float* body_rot;      // [nbody][9] in parent frame
@@ -93,22 +94,23 @@ struct DevModel {
   const float* qpos0;
   const float* lim_lo;        // [nlim] range of each limited joint
   const float* lim_hi;
+  const float* fric_loss;     // [nfric] friction-loss bound of each such dof
   float* body_invweight;      // filled on the device at upload
-  float* lim_invweight;       // [nlim] (M^-1)_kk of the limit's dof at qpos0, likewise
+  float* dof_invweight;       // [nv] (M^-1)_kk at qpos0 (limit and friction rows), likewise
   // ---- per-world on-chip layout (offsets in 4-byte words)
   int lds_words;
   int o_qpos, o_qvel, o_qacc;
   int o_xpos, o_xmat, o_cvel, o_cacc, o_cfrc, o_cinert, o_cdof, o_F;
   int o_M, o_H;
   int o_frc, o_a0, o_Mr, o_g, o_d, o_Md, o_tmp;
-  int o_cand, o_con, o_lim, o_J, o_aref, o_D, o_e, o_s, o_scal;
+  int o_cand, o_con, o_lim, o_J, o_aref, o_D, o_e, o_s, o_fl, o_scal;
   // adjoint layout only (no aliasing between the sweep and contact scratch there)
   int o_qbi, o_vbi, o_qb, o_vb, o_ub, o_mu, o_Sbar, o_xbar, o_Rbar, o_cinbar;
   int o_Vbar, o_Abar, o_Fbar, o_vup, o_aup, o_xup, o_Rup, o_rowsc, o_consc;
 };
 
-// scalar slots inside o_scal: the contact count and the row count (4 per contact,
-// then one per violated joint limit)
+// scalar slots inside o_scal: the contact count and the row count (4 per contact, then
+// one per violated joint limit, then one per friction-loss dof)
 enum ScalSlot : int {
   SC_NCON = 0, SC_NROW = 1, SC_COUNT = 4
 };
