@@ -236,6 +236,9 @@ struct Model {
   std::vector<double> pair_mu;
   std::vector<int> act_type, act_jnt;
   std::vector<double> act_gear, act_kp, act_kd, act_range, act_qdef;
+  int neq = 0;
+  std::vector<int> eq_type, eq_b1, eq_b2;
+  std::vector<double> eq_a1, eq_a2;  // anchor in body1's / body2's frame
   std::vector<double> qpos0;
   // derived
   std::vector<int> jnt_qposadr, jnt_dofadr, body_jntadr, body_jntnum, body_dofadr, body_dofnum;
@@ -894,6 +897,9 @@ template <class T> T impedance(const Model& m, T r) {
 // Then one friction-loss row per dof k with a bound F_k > 0, always present: J = e_k,
 // r = 0 (so d = d(0) and aref = -b qvel_k), the same A; its force is limited to
 // [-F_k, F_k] (dry joint friction, Todorov 2014's box-constrained rows).
+// Then three two-sided rows per connect equality, always present: with p1, p2 the
+// anchor's world positions through body1 and body2, row k has J = e_k^T (J_p(b1, p1) -
+// J_p(b2, p2)), r = (p1 - p2)_k, and A = w(b1) + w(b2); its force is unbounded.
 template <class T> void constraint_rows(const Model& m, Data<T>& d) {
   const int nc = (int)d.con.size(), n = m.nv;
   std::vector<int> lim_dof;
@@ -907,7 +913,7 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
     else if (rhi < 0.0) { lim_dof.push_back(m.jnt_dofadr[j]); lim_sign.push_back(-1.0); lim_dist.push_back(rhi); }
   }
   const int nl = (int)lim_dof.size();
-  d.nrow = 4 * nc + nl + m.nfric;
+  d.nrow = 4 * nc + nl + m.nfric + 3 * m.neq;
   d.J.assign(d.nrow * n, 0.0);
   d.aref.assign(d.nrow, 0.0);
   d.D.assign(d.nrow, 0.0);
@@ -965,6 +971,28 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
     d.fl[row] = m.dof_frictionloss[k];
     row++;
   }
+  for (int q = 0; q < m.neq; q++) {
+    const int b1 = m.eq_b1[q], b2 = m.eq_b2[q];
+    T p1[3], p2[3];
+    matvec(&d.xmat[9 * b1], &m.eq_a1[3 * q], p1);
+    matvec(&d.xmat[9 * b2], &m.eq_a2[3 * q], p2);
+    for (int k = 0; k < 3; k++) { p1[k] += d.xpos[3 * b1 + k]; p2[k] += d.xpos[3 * b2 + k]; }
+    point_jac(m, d, b1, p1, J1.data());
+    point_jac(m, d, b2, p2, J2.data());
+    const double A = std::max(m.body_invweight[b1] + m.body_invweight[b2], 1e-15);
+    for (int k = 0; k < 3; k++, row++) {
+      T jv = 0.0;
+      for (int i = 0; i < n; i++) {
+        d.J[row * n + i] = J1[k * n + i] - J2[k * n + i];
+        jv += d.J[row * n + i] * d.qvel[i];
+      }
+      const T r = p1[k] - p2[k];
+      const T imp = impedance(m, r);
+      d.aref[row] = -B * jv - K * imp * r;
+      d.D[row] = 1.0 / ((1.0 - imp) / imp * A);
+      d.fl[row] = INFINITY;  // two-sided: the quadratic piece everywhere
+    }
+  }
 }
 
 // ---------------------------------------------------------- A9: Newton contact solve
@@ -972,6 +1000,7 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
 //   s_i(e) = 1/2 D_i min(0, e)^2                       for a one-sided row,
 //   s_i(e) = 1/2 D_i e^2 if |D_i e| <= F_i, else F_i |e| - F_i^2 / (2 D_i)
 //                                                      for a friction-loss row (bound F_i),
+//   s_i(e) = 1/2 D_i e^2                               for an equality row (F_i = inf),
 // the largest of -f e - f^2 / (2 D) over the row's admissible forces f (f >= 0, or
 // |f| <= F).  F is strictly convex and piecewise quadratic (M is SPD).
 template <class T> struct Solver {
@@ -989,7 +1018,7 @@ template <class T> struct Solver {
   T srow(int i, T e) const {
     const double F = d.fl[i];
     if (F == 0.0) return e < 0.0 ? T(0.5 * d.D[i] * e * e) : T(0.0);
-    if (fabs(d.D[i] * e) <= F) return 0.5 * d.D[i] * e * e;
+    if (std::isinf(F) || fabs(d.D[i] * e) <= F) return 0.5 * d.D[i] * e * e;
     return F * fabs(e) - F * F / (2.0 * d.D[i]);
   }
   T dsrow(int i, T e) const {
@@ -1000,7 +1029,7 @@ template <class T> struct Solver {
   }
   bool quad(int i, T e) const {
     const double F = d.fl[i];
-    return F == 0.0 ? e < 0.0 : fabs(d.D[i] * e) < F;
+    return F == 0.0 ? e < 0.0 : (std::isinf(F) || fabs(d.D[i] * e) < F);
   }
   T cost(const T* a) const {
     std::vector<T> da(n), Mda(n);
@@ -1059,6 +1088,7 @@ template <class T> struct Solver {
     for (int i = 0; i < nr; i++)
       if (s[i] != 0.0) {
         const double F = d.fl[i];
+        if (std::isinf(F)) continue;  // two-sided rows have no breakpoint
         const int nb = F == 0.0 ? 1 : 2;
         for (int k = 0; k < nb; k++) {
           const T at = F == 0.0 ? T(0.0) : T((k == 0 ? F : -F) / d.D[i]);
@@ -1224,12 +1254,14 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   m.nbody = hi[2]; m.njnt = hi[3]; m.ngeom = hi[4]; m.npair = hi[5]; m.nu = hi[6];
   m.nq = hi[7]; m.nv = hi[8]; m.iterations = hi[9]; m.ls_iterations = hi[10];
   m.nconmax = hi[11];
+  m.neq = hi[12];
   m.dt = hf[0];
   for (int k = 0; k < 3; k++) m.grav[k] = hf[1 + k];
   m.solref[0] = hf[4]; m.solref[1] = hf[5];
   for (int k = 0; k < 5; k++) m.solimp[k] = hf[6 + k];
   m.tolerance = hf[11];
-  if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nconmax < 0) {
+  if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nconmax < 0 ||
+      m.neq < 0) {
     err = "negative size"; return false;
   }
   std::vector<int32_t> bi(2 * m.nbody);
@@ -1247,6 +1279,9 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   std::vector<int32_t> ai(2 * m.nu);
   std::vector<double> af(7 * m.nu);
   r.read(ai.data(), ai.size()); r.read(af.data(), af.size());
+  std::vector<int32_t> ei(4 * m.neq);
+  std::vector<double> ef(6 * m.neq);
+  r.read(ei.data(), ei.size()); r.read(ef.data(), ef.size());
   m.qpos0.resize(m.nq);
   r.read(m.qpos0.data(), m.nq);
   if (!r.ok || r.off != nbytes) { err = "blob size mismatch"; return false; }
@@ -1315,6 +1350,15 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
     m.act_range.push_back(f[3]); m.act_range.push_back(f[4]);
     m.act_qdef.push_back(f[5]);
     if (ai[2 * a + 1] < 0 || ai[2 * a + 1] >= m.njnt) { err = "bad actuator"; return false; }
+  }
+  for (int e = 0; e < m.neq; e++) {
+    const int* q = &ei[4 * e];
+    if (q[0] != 0 || q[1] <= 0 || q[1] >= m.nbody || q[2] < 0 || q[2] >= m.nbody || q[1] == q[2]) {
+      err = "bad equality"; return false;
+    }
+    m.eq_type.push_back(q[0]); m.eq_b1.push_back(q[1]); m.eq_b2.push_back(q[2]);
+    m.eq_a1.insert(m.eq_a1.end(), &ef[6 * e], &ef[6 * e] + 3);
+    m.eq_a2.insert(m.eq_a2.end(), &ef[6 * e] + 3, &ef[6 * e] + 6);
   }
   // derived addresses
   m.body_jntadr.assign(m.nbody, 0); m.body_jntnum.assign(m.nbody, 0);
@@ -1437,12 +1481,12 @@ void* mjo_load(const unsigned char* blob, long nbytes, char* err, int errlen) {
 
 void mjo_free(void* h) { delete static_cast<Model*>(h); }
 
-// out[0..11] = nq nv nu nbody njnt ngeom npair nconmax iterations ls_iterations nlimit
-// nfric
+// out[0..12] = nq nv nu nbody njnt ngeom npair nconmax iterations ls_iterations nlimit
+// nfric neq
 int mjo_dims(void* h, int* out) {
   Model& m = *static_cast<Model*>(h);
-  int v[12] = {m.nq, m.nv, m.nu, m.nbody, m.njnt, m.ngeom, m.npair, m.nconmax,
-               m.iterations, m.ls_iterations, m.nlimit, m.nfric};
+  int v[13] = {m.nq, m.nv, m.nu, m.nbody, m.njnt, m.ngeom, m.npair, m.nconmax,
+               m.iterations, m.ls_iterations, m.nlimit, m.nfric, m.neq};
   std::memcpy(out, v, sizeof(v));
   return 0;
 }
@@ -1525,8 +1569,9 @@ int mjo_step(void* h, int nworld, int nstep, double* qpos, double* qvel, double*
 // Output sizes: xpos [nbody*3], xmat [nbody*9], xipos [nbody*3], cdof [nv*6],
 // cvel [nbody*6], M [nv*nv], bias [nv], act [nv], pass [nv], qacc_smooth [nv],
 // qacc [nv], qfrc_con [nv], ncon, contacts [nconmax*20], nrow, J [nrowmax * nv],
-// aref, D, efc_force [nrowmax] with nrowmax = 4 nconmax + nlimit + nfric (contact rows
-// first, then the violated limits, then the friction-loss rows).  NULL skips an output.
+// aref, D, efc_force [nrowmax] with nrowmax = 4 nconmax + nlimit + nfric + 3 neq (contact
+// rows first, then the violated limits, the friction-loss rows and the equality rows).
+// NULL skips an output.
 int mjo_forward(void* h, const double* qpos, const double* qvel, const double* qacc_ws,
                 const double* ctrl, int mode, double* xpos, double* xmat, double* xipos,
                 double* cdof, double* cvel, double* M, double* bias, double* act,

@@ -11,7 +11,7 @@ with their own code.
 Blob layout (little endian, version 2), every block 8-byte aligned:
 
   header   int32[16]  : magic 0x4D484A4D ('MJHM'), version, nbody, njnt, ngeom, npair,
-                        nu, nq, nv, iterations, ls_iterations, nconmax, 0, 0, 0, 0
+                        nu, nq, nv, iterations, ls_iterations, nconmax, neq, 0, 0, 0
            float64[16]: timestep, gravity[3], solref[2], solimp[5], tolerance, 0 x4
   body     int32 [nbody][2] : parent, 0
            f64   [nbody][19]: pos[3], quat[4] (w first), mass, ipos[3],
@@ -25,12 +25,18 @@ Blob layout (little endian, version 2), every block 8-byte aligned:
            f64   [npair][1] : friction coefficient mu
   actuator int32 [nu][2]    : type (0 motor, 1 position PD), joint
            f64   [nu][7]    : gear, kp, kd, ctrlrange[2], qdefault, 0
+  equality int32 [neq][4]   : type (0 connect), body1, body2, 0
+           f64   [neq][6]   : anchor in body1's frame[3], the same point in body2's frame[3]
   qpos0    f64   [nq]
 
 A limited hinge or slide joint keeps its coordinate inside range[0] < q < range[1]
 through a soft one-sided constraint (the joint-limit rows of the constraint set).  A
 hinge or slide joint with frictionloss F > 0 gets a dry-friction row whose force is
 bounded by F.
+
+A connect equality holds a point of body1 on a point of body2 (a ball joint closing a
+loop, or pinning a body to the world when body2 = 0): three always-present two-sided
+rows.
 
 Geom sizes: sphere (r), capsule (r, half segment length; segment along local z),
 box (half extents).  Plane normal is the geom's local +z.
@@ -49,6 +55,7 @@ VERSION = 2
 JNT_FREE, JNT_SLIDE, JNT_HINGE = 0, 1, 2
 GEOM_PLANE, GEOM_SPHERE, GEOM_CAPSULE, GEOM_BOX = 0, 1, 2, 3
 ACT_MOTOR, ACT_PD = 0, 1
+EQ_CONNECT = 0
 
 JNT_NQ = {JNT_FREE: 7, JNT_SLIDE: 1, JNT_HINGE: 1}
 JNT_NV = {JNT_FREE: 6, JNT_SLIDE: 1, JNT_HINGE: 1}
@@ -102,6 +109,15 @@ class Actuator:
 
 
 @dataclass
+class Equality:
+    type: int
+    body1: int
+    body2: int
+    anchor1: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    anchor2: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+
+
+@dataclass
 class Options:
     timestep: float = 0.002
     gravity: Tuple[float, float, float] = (0.0, 0.0, -9.81)
@@ -121,6 +137,7 @@ class Model:
     geoms: List[Geom] = field(default_factory=list)
     pairs: List[Tuple[int, int, float]] = field(default_factory=list)
     actuators: List[Actuator] = field(default_factory=list)
+    equalities: List[Equality] = field(default_factory=list)
     opt: Options = field(default_factory=Options)
     qpos0: np.ndarray = None
 
@@ -147,8 +164,12 @@ class Model:
         return sum(1 for j in self.joints if j.frictionloss > 0)
 
     @property
+    def neq(self) -> int:
+        return len(self.equalities)
+
+    @property
     def nrowmax(self) -> int:
-        return 4 * self.opt.nconmax + self.nlimit + self.nfric
+        return 4 * self.opt.nconmax + self.nlimit + self.nfric + 3 * self.neq
 
     @property
     def nlimit(self) -> int:
@@ -189,6 +210,10 @@ class Model:
                 assert j.range[0] < j.range[1], "limited joint needs range[0] < range[1]"
             assert j.frictionloss >= 0 and (j.type != JNT_FREE or j.frictionloss == 0), \
                 "friction loss needs a hinge or slide joint"
+        for e in self.equalities:
+            assert e.type == EQ_CONNECT, "only connect equalities"
+            assert 0 < e.body1 < self.nbody and 0 <= e.body2 < self.nbody
+            assert e.body1 != e.body2
         for g1, g2, _ in self.pairs:
             assert self.geoms[g1].type <= self.geoms[g2].type, "pair order by geom type"
         assert self.qpos0 is not None and len(self.qpos0) == self.nq
@@ -199,7 +224,7 @@ class Model:
         o = self.opt
         hdr_i = [MAGIC, VERSION, self.nbody, len(self.joints), len(self.geoms),
                  len(self.pairs), self.nu, self.nq, self.nv, o.iterations,
-                 o.ls_iterations, o.nconmax, 0, 0, 0, 0]
+                 o.ls_iterations, o.nconmax, self.neq, 0, 0, 0]
         hdr_f = [o.timestep, *o.gravity, *o.solref, *o.solimp, o.tolerance, 0, 0, 0, 0]
         assert len(hdr_f) == 16
         parts = [struct.pack("<16i", *hdr_i), struct.pack("<16d", *hdr_f)]
@@ -225,5 +250,7 @@ class Model:
         parts.append(blk_i([[a.type, a.joint] for a in self.actuators]))
         parts.append(blk_f([[a.gear, a.kp, a.kd, *a.ctrlrange, a.qdefault, 0]
                             for a in self.actuators]))
+        parts.append(blk_i([[e.type, e.body1, e.body2, 0] for e in self.equalities]))
+        parts.append(blk_f([[*e.anchor1, *e.anchor2] for e in self.equalities]))
         parts.append(blk_f(np.asarray(self.qpos0, dtype=np.float64)))
         return b"".join(parts)

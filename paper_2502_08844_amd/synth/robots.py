@@ -27,9 +27,9 @@ from typing import List, Sequence, Tuple
 
 import numpy as np
 
-from .model import (ACT_MOTOR, ACT_PD, GEOM_BOX, GEOM_CAPSULE, GEOM_PLANE, GEOM_SPHERE,
-                    JNT_FREE, JNT_HINGE, JNT_SLIDE, Actuator, Body, Geom, Joint, Model,
-                    Options)
+from .model import (ACT_MOTOR, ACT_PD, EQ_CONNECT, GEOM_BOX, GEOM_CAPSULE, GEOM_PLANE,
+                    GEOM_SPHERE, JNT_FREE, JNT_HINGE, JNT_SLIDE, Actuator, Body, Equality,
+                    Geom, Joint, Model, Options)
 
 # ----------------------------------------------------------------------------------
 # closed-form mass properties (uniform density)
@@ -148,6 +148,13 @@ class _Builder:
             R = quat_to_mat(quat)
             self._geom_mass.append((body, mass, np.asarray(pos, float), R @ ig @ R.T, R))
         return gid
+
+    def connect(self, body1: int, body2: int, anchor1, anchor2) -> int:
+        """Hold anchor1 (body1's frame) on anchor2 (body2's frame; the world if 0)."""
+        self.m.equalities.append(Equality(type=EQ_CONNECT, body1=body1, body2=body2,
+                                          anchor1=tuple(map(float, anchor1)),
+                                          anchor2=tuple(map(float, anchor2))))
+        return len(self.m.equalities) - 1
 
     def capsule_fromto(self, body, p0, p1, r, mass=0.0, friction=1.0, name="") -> int:
         p0 = np.asarray(p0, float)
@@ -467,6 +474,71 @@ def slider(mass: float = 2.0, armature: float = 0.0, range=(0.0, 1.0), axis=(0, 
     m = bld.finish()
     m.opt = Options(timestep=timestep, gravity=tuple(gravity), iterations=8, nconmax=0)
     m.qpos0 = np.zeros(1)
+    return m
+
+
+def pinned_body(shape: str = "sphere", mass: float = 1.0, anchor=(0.0, 0.0, 0.0),
+                z0: float = 1.0, timestep: float = 0.002) -> Model:
+    """A free sphere or capsule (half length 0.2 along z) whose point ``anchor`` (body
+    frame) is pinned by a connect equality to where it sits at qpos0."""
+    bld = _Builder(f"pinned_{shape}")
+    b = bld.body(0, pos=(0, 0, z0))
+    bld.joint(b, JNT_FREE)
+    if shape == "sphere":
+        bld.geom(b, GEOM_SPHERE, (0.1,), mass=mass)
+    else:
+        bld.geom(b, GEOM_CAPSULE, (0.03, 0.2), mass=mass)
+    m = bld.finish()
+    bld.connect(b, 0, anchor, (anchor[0], anchor[1], anchor[2] + z0))
+    m.opt = Options(timestep=timestep, iterations=4, nconmax=0)
+    q0 = np.zeros(7)
+    q0[2] = z0
+    q0[3] = 1.0
+    m.qpos0 = q0
+    return m
+
+
+def connected_spheres(m1: float = 1.0, m2: float = 3.0, gap: float = 0.0,
+                      gravity=(0.0, 0.0, -9.81), timestep: float = 0.002) -> Model:
+    """Two free spheres whose centres are held together by a connect equality (the
+    second sphere starts ``gap`` above the first)."""
+    bld = _Builder("connected_spheres")
+    b1 = bld.body(0, pos=(0, 0, 1.0))
+    bld.joint(b1, JNT_FREE)
+    bld.geom(b1, GEOM_SPHERE, (0.1,), mass=m1)
+    b2 = bld.body(0, pos=(0, 0, 1.0 + gap))
+    bld.joint(b2, JNT_FREE)
+    bld.geom(b2, GEOM_SPHERE, (0.1,), mass=m2)
+    m = bld.finish()
+    bld.connect(b1, b2, (0, 0, 0), (0, 0, 0))
+    m.opt = Options(timestep=timestep, gravity=tuple(gravity), iterations=4, nconmax=0)
+    q0 = np.zeros(14)
+    q0[2], q0[3], q0[9], q0[10] = 1.0, 1.0, 1.0 + gap, 1.0
+    m.qpos0 = q0
+    return m
+
+
+def four_bar(link: float = 0.3, span: float = 0.4, mass: float = 0.5, damping: float = 0.0,
+             frictionloss: float = 0.0, timestep: float = 0.002) -> Model:
+    """A planar parallelogram linkage closed by a connect equality: two cranks of length
+    ``link`` hang from world pivots ``span`` apart (hinges about y); a coupler rides on
+    the first crank's tip and its far end is connected to the second crank's tip.  One
+    degree of freedom: the coupler translates without turning (q_coupler = -q_crank1,
+    q_crank2 = q_crank1)."""
+    bld = _Builder("four_bar")
+    c1 = bld.body(0, pos=(0, 0, 0), name="crank1")
+    bld.joint(c1, JNT_HINGE, axis=(0, 1, 0), damping=damping, frictionloss=frictionloss)
+    bld.capsule_fromto(c1, (0, 0, 0), (0, 0, -link), 0.02, mass=mass)
+    cp = bld.body(c1, pos=(0, 0, -link), name="coupler")
+    bld.joint(cp, JNT_HINGE, axis=(0, 1, 0), damping=damping, frictionloss=frictionloss)
+    bld.capsule_fromto(cp, (0, 0, 0), (span, 0, 0), 0.02, mass=mass)
+    c2 = bld.body(0, pos=(span, 0, 0), name="crank2")
+    bld.joint(c2, JNT_HINGE, axis=(0, 1, 0), damping=damping, frictionloss=frictionloss)
+    bld.capsule_fromto(c2, (0, 0, 0), (0, 0, -link), 0.02, mass=mass)
+    m = bld.finish()
+    bld.connect(cp, c2, (span, 0, 0), (0, 0, -link))
+    m.opt = Options(timestep=timestep, iterations=4, nconmax=0)
+    m.qpos0 = np.zeros(3)
     return m
 
 
