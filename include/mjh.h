@@ -76,7 +76,9 @@ typedef struct mjh_dims {
   float timestep;
   int32_t nlimit;     /* limited hinge/slide joints (at most one row each)        */
   int32_t nrowmax;    /* constraint rows per world: 4 nconmax + nlimit + nfric    */
+                      /*   + 3 neq                                                 */
   int32_t nfric;      /* dofs with friction loss (one row each, always present)   */
+  int32_t neq;        /* connect equalities (three rows each, always present)     */
 } mjh_dims;
 
 /* One context per device.  device: HIP device ordinal.  *out receives the handle. */
@@ -97,7 +99,11 @@ const char* mjh_last_error(const mjh_ctx* ctx);
  * the range, r = hi - q and J = -e_dof above it, and the regulariser's A = (M^-1)_kk
  * at qpos0.  A hinge or slide joint with friction loss F > 0 (dry joint friction)
  * adds one row after those, in dof order, always present: J = e_dof, r = 0, the same
- * A, and a force confined to [-F, F] (a Huber term in the solver's cost).
+ * A, and a force confined to [-F, F] (a Huber term in the solver's cost).  A connect
+ * equality (a point fixed in body1 held on a point fixed in body2, or in the world)
+ * adds three two-sided rows last, one per world axis: J = J_p(b1, p1) - J_p(b2, p2),
+ * r = p1 - p2, A = w(b1) + w(b2).  mjh_rollout_fwd rejects models with equalities
+ * (MJH_EUNSUPPORTED).
  * MJH_EMODEL for a malformed blob, MJH_EUNSUPPORTED for nv > 64, box-box pairs,
  * a free joint below the root or two actuators on one dof. */
 mjh_status mjh_model_upload(mjh_ctx* ctx, const void* blob, size_t nbytes,

@@ -27,7 +27,9 @@ namespace {
 struct HostModel {
   // parsed blob (double precision as stored)
   int nbody = 0, njnt = 0, ngeom = 0, npair = 0, nu = 0, nq = 0, nv = 0;
-  int iterations = 0, ls_iterations = 0, nconmax = 0;
+  int iterations = 0, ls_iterations = 0, nconmax = 0, neq = 0;
+  std::vector<int> eq_body;        // [neq][2]
+  std::vector<double> eq_anchor;   // [neq][6]
   double dt = 0, grav[3] = {0, 0, 0}, solref[2] = {0, 0}, solimp[5] = {0, 0, 0, 0, 0};
   std::vector<int> body_parent, jnt_type, jnt_body, jnt_limited, geom_type, geom_body,
       pair_g1, pair_g2, act_type, act_jnt;
@@ -71,9 +73,11 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   if (hi[0] != 0x4D484A4D || hi[1] != 2) { err = "model blob: bad magic or version"; return MJH_EMODEL; }
   m.nbody = hi[2]; m.njnt = hi[3]; m.ngeom = hi[4]; m.npair = hi[5]; m.nu = hi[6];
   m.nq = hi[7]; m.nv = hi[8]; m.iterations = hi[9]; m.ls_iterations = hi[10]; m.nconmax = hi[11];
+  m.neq = hi[12];
   if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nq < 0 ||
       m.nv < 0 || m.iterations < 0 || m.nconmax < 0 || m.nbody > 4096 || m.njnt > 4096 ||
-      m.ngeom > 4096 || m.npair > 65536 || m.nu > 4096 || m.nconmax > 4096) {
+      m.ngeom > 4096 || m.npair > 65536 || m.nu > 4096 || m.nconmax > 4096 || m.neq < 0 ||
+      m.neq > 1024) {
     err = "model blob: size field out of range";
     return MJH_EMODEL;
   }
@@ -85,12 +89,13 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
     vec.resize(count);
     return r.read(vec.data(), count);
   };
-  std::vector<int32_t> bi, ji, gi, pi, ai;
-  std::vector<double> bf, jf, gf, pf, af;
+  std::vector<int32_t> bi, ji, gi, pi, ai, ei;
+  std::vector<double> bf, jf, gf, pf, af, ef;
   bool ok = rd(bi, 2 * m.nbody) && rd(bf, 19 * (size_t)m.nbody) && rd(ji, 4 * m.njnt) &&
             rd(jf, 11 * (size_t)m.njnt) && rd(gi, 2 * m.ngeom) && rd(gf, 11 * (size_t)m.ngeom) &&
             rd(pi, 2 * m.npair) && rd(pf, m.npair) && rd(ai, 2 * m.nu) &&
-            rd(af, 7 * (size_t)m.nu) && rd(m.qpos0, m.nq);
+            rd(af, 7 * (size_t)m.nu) && rd(ei, 4 * (size_t)m.neq) && rd(ef, 6 * (size_t)m.neq) &&
+            rd(m.qpos0, m.nq);
   if (!ok || r.off() != nbytes) { err = "model blob: size mismatch"; return MJH_EMODEL; }
   for (int b = 0; b < m.nbody; b++) {
     m.body_parent.push_back(bi[2 * b]);
@@ -164,6 +169,16 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
     const double* f = &af[7 * a];
     m.act_gear.push_back(f[0]); m.act_kp.push_back(f[1]); m.act_kd.push_back(f[2]);
     m.act_lo.push_back(f[3]); m.act_hi.push_back(f[4]); m.act_qdef.push_back(f[5]);
+  }
+  for (int e = 0; e < m.neq; e++) {
+    const int type = ei[4 * e], b1 = ei[4 * e + 1], b2 = ei[4 * e + 2];
+    if (type != 0) { err = "only connect equalities are supported"; return MJH_EUNSUPPORTED; }
+    if (b1 <= 0 || b1 >= m.nbody || b2 < 0 || b2 >= m.nbody || b1 == b2) {
+      err = "model blob: bad equality bodies"; return MJH_EMODEL;
+    }
+    m.eq_body.push_back(b1);
+    m.eq_body.push_back(b2);
+    m.eq_anchor.insert(m.eq_anchor.end(), &ef[6 * e], &ef[6 * e] + 6);
   }
   return MJH_OK;
 }
@@ -314,7 +329,8 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
       fric_loss.push_back((float)h.jnt_frictionloss[j]);
     }
   d.nfric = (int)fric_dadr.size();
-  d.nrowmax = 4 * h.nconmax + d.nlim + d.nfric;
+  d.neq = h.neq;
+  d.nrowmax = 4 * h.nconmax + d.nlim + d.nfric + 3 * d.neq;
   // pairs and candidate slots
   std::vector<int> pair_kind, pair_candadr, cand_pair;
   int ncand = 0;
@@ -377,6 +393,9 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   pk.add(lim_hi, &d.lim_hi);
   pk.add(fric_dadr, &d.fric_dadr);
   pk.add(fric_loss, &d.fric_loss);
+  pk.add(h.eq_body, &d.eq_body);
+  std::vector<float> eq_anchor = fv(h.eq_anchor);
+  pk.add(eq_anchor, &d.eq_anchor);
   std::vector<float> bpos = fv(h.body_pos), bmass = fv(h.body_mass), bipos = fv(h.body_ipos),
                      binert = fv(h.body_inertia), jpos = fv(h.jnt_pos), jaxis = fv(h.jnt_axis),
                      gsize = fv(h.geom_size), gpos = fv(h.geom_pos), pmu = fv(h.pair_mu),
@@ -458,7 +477,8 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   d.o_D = take(nr);
   d.o_e = take(nr);
   d.o_s = take(nr);
-  d.o_fl = take(d.nfric > 0 ? nr : 0);  // per-row friction bound (0: one-sided row)
+  // per-row force bound (0: one-sided row, F: friction loss, +inf: two-sided equality)
+  d.o_fl = take(d.nfric + d.neq > 0 ? nr : 0);
   off = std::max(off, sweep_end);
   d.lds_words = off;
   // Table of the packed lower triangle at the head of a work-group's LDS: index
@@ -490,7 +510,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   x.o_Md = take(nv); x.o_tmp = take(nv); x.o_cand = take(2 * ncand);
   x.o_con = take(kConRec * h.nconmax); x.o_lim = take(d.nlim); x.o_J = take(nr * nv);
   x.o_aref = take(nr);
-  x.o_D = take(nr); x.o_e = take(nr); x.o_s = take(nr); x.o_fl = take(d.nfric > 0 ? nr : 0);
+  x.o_D = take(nr); x.o_e = take(nr); x.o_s = take(nr); x.o_fl = take(d.nfric + d.neq > 0 ? nr : 0);
   x.o_qbi = take(h.nq); x.o_vbi = take(nv); x.o_qb = take(h.nq); x.o_vb = take(nv);
   x.o_ub = take(h.nu); x.o_mu = take(nv); x.o_Sbar = take(6 * nv);
   x.o_xbar = take(3 * nb); x.o_Rbar = take(9 * nb); x.o_cinbar = take(kCinert * nb);
@@ -702,7 +722,7 @@ mjh_status mjh_model_info(mjh_ctx* ctx, int32_t model_id, mjh_dims* out) {
   out->nq = d.nq; out->nv = d.nv; out->nu = d.nu; out->nbody = d.nbody; out->ngeom = d.ngeom;
   out->npair = d.npair; out->ncand = d.ncand; out->nconmax = d.nconmax;
   out->iterations = d.iterations; out->lds_bytes = d.lds_words * 4; out->timestep = d.dt;
-  out->nlimit = d.nlim; out->nrowmax = d.nrowmax; out->nfric = d.nfric;
+  out->nlimit = d.nlim; out->nrowmax = d.nrowmax; out->nfric = d.nfric; out->neq = d.neq;
   return MJH_OK;
 }
 
@@ -902,7 +922,7 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
     const DevModel& d = ctx->models[g.model]->dm;
     std::ostringstream k;
     k << d.nq << ' ' << d.nv << ' ' << d.nbody << ' ' << d.npair << ' ' << d.nconmax << ' '
-      << d.nlim << ' ' << d.nfric << ' ' << d.iterations << ' ' << g.nworld;
+      << d.nlim << ' ' << d.nfric << ' ' << d.neq << ' ' << d.iterations << ' ' << g.nworld;
     return k.str();
   };
   if (cache_path) {
@@ -1022,6 +1042,8 @@ mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every, co
       return fail(ctx, MJH_EUNSUPPORTED,
                   "rollout: only plane-sphere and plane-capsule contacts are differentiated");
   }
+  if (mr.h.neq > 0)
+    return fail(ctx, MJH_EUNSUPPORTED, "rollout: equality constraints are not differentiated");
   {
     std::vector<int> nj(mr.h.nbody, 0);
     for (int j = 0; j < mr.h.njnt; j++) nj[mr.h.jnt_body[j]]++;

@@ -835,6 +835,21 @@ DEV float impedance(const DevModel& m, float dist) {
   return m.dmin + y * (m.dmax - m.dmin);
 }
 
+// rows with a per-row force bound (friction loss, equalities): the bound array exists
+DEV bool has_bounds(const DevModel& m) { return m.nfric + m.neq > 0; }
+
+// world positions of connect equality q's point through body1 (p1) and body2 (p2)
+DEV void eq_points(const DevModel& m, const float* W, int q, float* p1, float* p2) {
+  const int b1 = m.eq_body[2 * q], b2 = m.eq_body[2 * q + 1];
+  const float* a = m.eq_anchor + 6 * q;
+  mv3(W + m.o_xmat + 9 * b1, a, p1);
+  mv3(W + m.o_xmat + 9 * b2, a + 3, p2);
+  for (int k = 0; k < 3; k++) {
+    p1[k] += W[m.o_xpos + 3 * b1 + k];
+    p2[k] += W[m.o_xpos + 3 * b2 + k];
+  }
+}
+
 // violated joint limit k of a world (its o_lim entry): dof, sign of its row and distance
 DEV void limit_row(const DevModel& m, const float* W, int code, int& dof, float& sg,
                    float& dist) {
@@ -852,8 +867,10 @@ DEV void limit_row(const DevModel& m, const float* W, int code, int& dof, float&
 // (w1 + w2), D = 1/R.  Then one row per joint outside its range, in joint order:
 // J = +-e_dof, r the distance past the range end, R = (1-d)/d (M^-1)_kk at qpos0.
 // Then one friction-loss row per dof with a bound F > 0, always: J = e_dof, r = 0,
-// the same R, and the bound stored per row (0 marks a one-sided row).
-// Writes the row count to the SC_NROW slot.
+// the same R, and the bound stored per row (0 marks a one-sided row).  Then three
+// two-sided rows per connect equality (bound +inf): with p1, p2 the held point through
+// body1 and body2, J = J_p(b1, p1) - J_p(b2, p2) per world axis, r = p1 - p2,
+// R = (1-d)/d (w1 + w2).  Writes the row count to the SC_NROW slot.
 DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
   int* scal = (int*)(W + m.o_scal);
   const int ncon = scal[SC_NCON];
@@ -878,7 +895,8 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
     nl += t.isum(act);
   }
   const int nrf = nrc + nl;  // first friction-loss row
-  const int nrow = nrf + m.nfric;
+  const int nre = nrf + m.nfric;  // first equality row
+  const int nrow = nre + 3 * m.neq;
   if (t.lane == 0) scal[SC_NROW] = nrow;
   for (int idx = t.lane; idx < ncon * nv; idx += t.T) {
     const int c = idx / nv, i = idx - c * nv;
@@ -913,6 +931,25 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
     const int k = idx / nv, i = idx - k * nv;
     J[(nrf + k) * nv + i] = i == m.fric_dadr[k] ? 1.f : 0.f;
   }
+  for (int idx = t.lane; idx < m.neq * nv; idx += t.T) {
+    const int q = idx / nv, i = idx - q * nv;
+    float p1[3], p2[3];
+    eq_points(m, W, q, p1, p2);
+    const unsigned long long bit = 1ull << i;
+    float jd[3] = {0.f, 0.f, 0.f};
+    const float* S = cdof + 6 * i;
+    if (m.body_dofmask[m.eq_body[2 * q]] & bit) {
+      float wx[3];
+      cross3(S, p1, wx);
+      for (int k = 0; k < 3; k++) jd[k] += S[3 + k] + wx[k];
+    }
+    if (m.body_dofmask[m.eq_body[2 * q + 1]] & bit) {
+      float wx[3];
+      cross3(S, p2, wx);
+      for (int k = 0; k < 3; k++) jd[k] -= S[3 + k] + wx[k];
+    }
+    for (int k = 0; k < 3; k++) J[(nre + 3 * q + k) * nv + i] = jd[k];
+  }
   t.sync();
   const float* qvel = W + m.o_qvel;
   float* aref = W + m.o_aref;
@@ -933,23 +970,31 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
       limit_row(m, W, code, dof, sg, dist);
       jv = sg * qvel[dof];
       A = m.dof_invweight[dof];
-    } else {
+    } else if (row < nre) {
       const int dof = m.fric_dadr[row - nrf];
       dist = 0.f;
       jv = qvel[dof];
       A = m.dof_invweight[dof];
+    } else {
+      const int q = (row - nre) / 3, k = row - nre - 3 * q;
+      float p1[3], p2[3];
+      eq_points(m, W, q, p1, p2);
+      dist = p1[k] - p2[k];
+      for (int i = 0; i < nv; i++) jv += J[row * nv + i] * qvel[i];
+      A = m.body_invweight[m.eq_body[2 * q]] + m.body_invweight[m.eq_body[2 * q + 1]];
     }
     const float imp = impedance(m, dist);
     aref[row] = -m.B * jv - m.K * imp * dist;
     D[row] = imp / ((1.f - imp) * fmaxf(A, 1e-15f));
-    if (m.nfric > 0) W[m.o_fl + row] = row < nrf ? 0.f : m.fric_loss[row - nrf];
+    if (has_bounds(m))
+      W[m.o_fl + row] = row < nrf ? 0.f : (row < nre ? m.fric_loss[row - nrf] : INFINITY);
   }
   t.sync();
 }
 
 // Pieces of a row's cost s(e) in the Newton solve: one-sided rows (bound F = 0)
 // s = 1/2 D min(0, e)^2; friction-loss rows (F > 0) the Huber term, 1/2 D e^2 while
-// |D e| <= F, else F |e| - F^2 / (2 D).
+// |D e| <= F, else F |e| - F^2 / (2 D); two-sided rows (F = +inf) 1/2 D e^2.
 DEV float row_cost(float D, float F, float e) {
   if (F == 0.f) return e < 0.f ? 0.5f * D * e * e : 0.f;
   return fabsf(D * e) <= F ? 0.5f * D * e * e : F * fabsf(e) - 0.5f * F * F / D;
@@ -988,7 +1033,7 @@ DEV int pad_rows(const DevModel& m, float* W, const Team& t, int nrow) {
   float* e = W + m.o_e;
   float* s = W + m.o_s;
   for (int r = nrow + t.lane; r < nru; r += t.T) { D[r] = 0.f; e[r] = 0.f; s[r] = 0.f; }
-  if (m.nfric > 0)
+  if (has_bounds(m))
     for (int r = nrow + t.lane; r < nru; r += t.T) W[m.o_fl + r] = 0.f;
   t.sync();
   return nru;
@@ -1010,7 +1055,7 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
   const float* D = W + m.o_D;
   const float* e = W + m.o_e;
   float* w = W + m.o_s;  // row weights; the line search rewrites this scratch later
-  if (m.nfric > 0) {
+  if (has_bounds(m)) {
     const float* fl = W + m.o_fl;
     for (int r = t.lane; r < nru; r += t.T) w[r] = row_quad(D[r], fl[r], e[r]) ? D[r] : 0.f;
   } else {
@@ -1250,8 +1295,9 @@ DEV void cholesky_back(const DevModel& m, float* W, const Team& t, const float* 
 // search (phi' evaluated at every breakpoint in parallel), update.  Stops early when
 // the Newton direction is no longer a descent direction (converged to precision) or,
 // with gtol > 0, when max |g| <= gtol * max(1, max |qfrc_smooth|).  FR: the model has
-// friction-loss rows (two breakpoints each, Huber pieces); without them every row is
-// one-sided and the loops keep their shorter form.
+// friction-loss rows (two breakpoints each, Huber pieces) or two-sided equality rows
+// (quadratic everywhere, no breakpoint); without them every row is one-sided and the
+// loops keep their shorter form.
 template <bool FR>
 DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, int iters,
                      float gtol) {
@@ -1358,15 +1404,20 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
     // Evaluate it at every positive breakpoint; the root lies between the largest
     // breakpoint with phi' <= 0 and the smallest with phi' > 0, where phi' is linear.
     // Breakpoints: a one-sided row's e crosses 0; a friction row's D e crosses +F
-    // (candidate r) and -F (candidate nrow + its index among the friction rows).
+    // (candidate r) and -F (candidate nrow + its index among the friction rows); a
+    // two-sided row (bound +inf) has none.
     float lo = 0.f, hi = INFINITY;
     const int nbp = FR ? nrow + m.nfric : nrow;
+    const int nfr0 = nrow - m.nfric - 3 * m.neq;  // first friction-loss row
     for (int c = t.lane; c < nbp; c += t.T) {
-      const int r = c < nrow ? c : nrow - m.nfric + (c - nrow);
+      const int r = c < nrow ? c : nfr0 + (c - nrow);
       const float sr = s[r];
       if (sr == 0.f) continue;
       float at = 0.f;
-      if (FR && fl[r] > 0.f) at = (c < nrow ? fl[r] : -fl[r]) / D[r];
+      if (FR && fl[r] > 0.f) {
+        if (fl[r] == INFINITY) continue;
+        at = (c < nrow ? fl[r] : -fl[r]) / D[r];
+      }
       const float br = (at - e[r]) / sr;
       if (!(br > 0.f)) continue;
       float dp = dMr + br * dMd;
@@ -1402,7 +1453,7 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
 }
 DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int iters,
                 float gtol = 0.f) {
-  if (m.nfric > 0) newton_impl<true>(m, W, t, status, iters, gtol);
+  if (has_bounds(m)) newton_impl<true>(m, W, t, status, iters, gtol);
   else newton_impl<false>(m, W, t, status, iters, gtol);
 }
 

@@ -36,7 +36,7 @@ class Dims(C.Structure):
     _fields_ = [("nq", I32), ("nv", I32), ("nu", I32), ("nbody", I32), ("ngeom", I32),
                 ("npair", I32), ("ncand", I32), ("nconmax", I32), ("iterations", I32),
                 ("lds_bytes", I32), ("timestep", F), ("nlimit", I32), ("nrowmax", I32),
-                ("nfric", I32)]
+                ("nfric", I32), ("neq", I32)]
 
 
 def _sig(name, *args):
@@ -143,7 +143,7 @@ class Model:
         self.dims = d
         self.nq, self.nv, self.nu = d.nq, d.nv, d.nu
         self.nconmax = d.nconmax
-        self.nlimit, self.nrowmax, self.nfric = d.nlimit, d.nrowmax, d.nfric
+        self.nlimit, self.nrowmax, self.nfric, self.neq = d.nlimit, d.nrowmax, d.nfric, d.neq
         self.timestep = d.timestep
 
     def invweight(self):

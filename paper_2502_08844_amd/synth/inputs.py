@@ -36,7 +36,7 @@ def initial_state(kind: str, m: Model, nworld: int, seed: int = 0):
     if kind == "cartpole":
         qpos[:] = r_q.uniform(-0.1, 0.1, size=(nworld, nq))
         qvel[:] = r_v.uniform(-0.05, 0.05, size=(nworld, nv))
-    elif kind in ("quadruped", "quadruped_limits", "quadruped_friction"):
+    elif kind.startswith("quadruped"):
         qpos[:, 7:] = np.tile(robots.QUAD_Q_DEFAULT, 4) + r_q.uniform(-0.2, 0.2,
                                                                         size=(nworld, 12))
     elif kind == "humanoid":
@@ -54,7 +54,7 @@ def controls(kind: str, m: Model, nworld: int, nstep: int, seed: int = 0) -> np.
     shape = (nstep, nworld, m.nu)
     if kind == "cartpole":
         u = r.uniform(-1.0, 1.0, size=shape)
-    elif kind in ("quadruped", "quadruped_limits", "quadruped_friction"):
+    elif kind.startswith("quadruped"):
         u = r.uniform(-0.5, 0.5, size=shape)
     elif kind == "humanoid":
         u = np.clip(r.normal(0.0, 0.3, size=shape), -1.0, 1.0)

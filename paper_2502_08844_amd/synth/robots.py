@@ -230,7 +230,7 @@ QUAD_FRICTIONLOSS = 3.0
 
 
 def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
-              limits: bool = False, frictionloss: float = 0.0) -> Model:
+              limits: bool = False, frictionloss: float = 0.0, tether: bool = False) -> Model:
     """Free torso (box 0.3x0.1x0.05 m, 5 kg) + 4 legs x 3 hinges (capsules r 0.02,
     length 0.2, 0.5 kg) with massless sphere feet (r 0.025).  nq 19, nv 18, nu 12.
 
@@ -238,7 +238,9 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     than the initial noise and the reach of the random PD targets, so that limit rows
     switch on and off all through a rollout (with the benchmark inputs about 2.3 of
     the 12 are active on average, up to 7).  With ``frictionloss`` every hinge carries
-    that dry friction (one friction-loss row each).
+    that dry friction (one friction-loss row each).  With ``tether`` the torso's centre
+    is held by a connect equality on its standing position (a gantry tether: three
+    two-sided rows).
 
     Each leg: hip link (hinge about x, capsule lateral 0.2 m), thigh (hinge about y,
     capsule down 0.2 m), shin (hinge about y, capsule down 0.2 m, foot sphere).
@@ -246,7 +248,7 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     the default pose (0, pi/4, -pi/2) per leg.  Only the feet collide (plane x 4 feet).
     """
     bld = _Builder("quadruped" + ("_limits" if limits else "") +
-                   ("_friction" if frictionloss > 0 else ""))
+                   ("_friction" if frictionloss > 0 else "") + ("_tethered" if tether else ""))
 
     def rng(k):
         if not limits:
@@ -279,6 +281,8 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
         m.actuators.append(Actuator(type=ACT_PD, joint=j, gear=1.0, kp=35.0, kd=0.5,
                                     ctrlrange=(-1.0, 1.0), qdefault=QUAD_Q_DEFAULT[k % 3]))
     m.pairs = [(plane, f, mu) for f in feet]
+    if tether:
+        bld.connect(torso, 0, (0, 0, 0), (0, 0, QUAD_STAND_Z))
     m.opt = Options(timestep=timestep, iterations=iterations, ls_iterations=8,
                     nconmax=4)
     q0 = np.zeros(m.nq)
@@ -456,6 +460,11 @@ def quadruped_limits() -> Model:
     return quadruped(limits=True)
 
 
+def quadruped_tethered() -> Model:
+    """The quadruped with its torso centre tethered to its standing position."""
+    return quadruped(tether=True)
+
+
 def quadruped_friction() -> Model:
     """The quadruped with dry friction QUAD_FRICTIONLOSS on every hinge."""
     return quadruped(frictionloss=QUAD_FRICTIONLOSS)
@@ -629,6 +638,7 @@ WORKLOADS = {
     "quadruped": quadruped,
     "quadruped_limits": quadruped_limits,
     "quadruped_friction": quadruped_friction,
+    "quadruped_tethered": quadruped_tethered,
     "humanoid": humanoid,
     "hand": hand,
 }

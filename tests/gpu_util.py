@@ -46,8 +46,9 @@ def compare_step(m, o, state, ctrl1, gpu1, mode=oracle.MODE_FIXED, near=1e-5):
 
     Returns per-world qacc and contact-force relative errors and a flag per world for
     states near a switch (contact emission |dist| < near, a limited joint within near
-    of its range end, a candidate set change, or a constraint row at its activation
-    threshold), which are reported, not gated."""
+    of its range end, a candidate set change, a one-sided row at its activation
+    threshold, or a friction-loss row where |D e| meets its bound), which are
+    reported, not gated."""
     qpos, qvel, ws = state
     nw = qpos.shape[0]
     ref = o.step(qpos.copy(), qvel.copy(), ws.copy(), ctrl1, nstep=1, mode=mode, nthreads=8)
@@ -59,13 +60,23 @@ def compare_step(m, o, state, ctrl1, gpu1, mode=oracle.MODE_FIXED, near=1e-5):
     qadr = m.jnt_qposadr()
     lims = [(qadr[j], jt.range[0], jt.range[1]) for j, jt in enumerate(m.joints) if jt.limited]
 
-    def at_threshold(w):  # a row at its activation threshold in the reference solution
+    fric = np.array([j.frictionloss for j in m.joints if j.frictionloss > 0])
+    neqr = 3 * len(m.equalities)
+
+    def at_threshold(w):  # a row at a switch of its cost's pieces in the reference solution
         f = o.forward(qpos[w], qvel[w], ws[w], ctrl1[0, w] if ctrl1 is not None else None,
                       mode=mode)
         if f["nrow"] == 0:
             return False
         e = f["J"] @ f["qacc"] - f["aref"]
-        return bool(np.any(np.abs(e) < 1e-6 * (1 + np.abs(f["aref"]).max())))
+        tol = 1e-6 * (1 + np.abs(f["aref"]).max())
+        one = f["nrow"] - len(fric) - neqr  # one-sided rows: switch at e = 0
+        if np.any(np.abs(e[:one]) < tol):
+            return True
+        if len(fric):  # friction loss: switch where |D e| = F
+            De = np.abs(f["D"][one:one + len(fric)] * e[one:one + len(fric)])
+            return bool(np.any(np.abs(De - fric) < 1e-5 * fric))
+        return False
 
     for w in range(nw):
         a_r, a_g = ref["qacc"][w], gpu1["qacc"][w]
