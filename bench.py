@@ -68,8 +68,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--model", default="quadruped",
-                    choices=["quadruped", "quadruped_limits", "quadruped_friction", "humanoid",
-                             "hand", "cartpole"],
+                    choices=["quadruped", "quadruped_limits", "quadruped_friction",
+                             "quadruped_tethered", "humanoid", "hand", "cartpole"],
                     help="robot of the timed batch (the headline metric is the quadruped)")
     ap.add_argument("--nworld", type=int, default=8192)
     ap.add_argument("--nstep", type=int, default=1000)
@@ -84,8 +84,8 @@ def parse():
     ap.add_argument("--no-hetero", action="store_true",
                     help="skip the heterogeneous-batch comparison")
     ap.add_argument("--no-limits", action="store_true",
-                    help="skip the joint-limit and friction-loss workloads (quadruped with "
-                         "limited hinges, quadruped with dry joint friction)")
+                    help="skip the joint-limit, friction-loss and equality workloads "
+                         "(quadruped variants)")
     ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a reference "
@@ -188,7 +188,8 @@ def rollout_compare(ctx, seed, nw=1024, horizon=64, ckpt=8, reps=3):
 
 def constraint_compare(ctx, seed, kind, what, nw=8192, nstep=1000, reps=3):
     """A quadruped variant with more constraint rows beside the contacts (limited
-    hinges, or dry joint friction), 8192 worlds x 1000 steps in its default launch."""
+    hinges, dry joint friction, or a tether equality), 8192 worlds x 1000 steps in its
+    default launch."""
     import torch
     from paper_2502_08844_amd import mjh
     from paper_2502_08844_amd.synth import inputs, robots
@@ -397,6 +398,9 @@ def main():
         out["friction_loss"] = constraint_compare(
             ctx, args.seed, "quadruped_friction",
             f"dry joint friction {robots.QUAD_FRICTIONLOSS} N m on every hinge")
+        out["equality"] = constraint_compare(
+            ctx, args.seed, "quadruped_tethered",
+            "its torso centre held on its standing position by a connect equality")
     if not args.no_cpu_baseline:
         nthreads = min(os.cpu_count() or 1, 16)
         cw = min(args.cpu_sample_worlds, nw)
