@@ -6,7 +6,10 @@
 // accumulates the loss  sum_t (qpos_{t+1}[zidx] - ztarget)^2 + wctrl |u_t|^2.
 // Reverse (rollout_bwd_kernel): segments in reverse order; each is recomputed from its
 // checkpoint into a per-world tape (Griewank & Walther, checkpointed reverse mode),
-// then every step is solved again and its vector-Jacobian product taken:
+// which keeps, for every step of the segment, the on-chip image right after its solve
+// (the forward regions of the adjoint layout, a few KB per world-step in HBM). Each
+// step's image is then reloaded, not solved again, and its vector-Jacobian product
+// taken:
 //   * semi-implicit Euler and the exponential-map orientation update, reversed;
 //   * the contact solve by implicit differentiation at the Newton solution a*:
 //     grad_a F(a*; theta) = 0 gives theta_bar = -(dG/dtheta)^T H^-1 a_bar with
@@ -665,6 +668,8 @@ struct RolloutArgs {
   const float* ctrl;  // [horizon][nworld][nu]
   float* tape_ckpt;   // [nseg][nworld][nq + 2 nv]
   float* tape_seg;    // [ckpt + 1][nworld][nq + 2 nv]
+  unsigned* tape_snap;  // [ckpt][nworld][snap_words]: on-chip image after each step's solve
+  int snap_words;       // the forward regions of the adjoint layout, [0, o_qbi)
   float* loss;
   const float* dloss;
   float* grad_qvel0;
@@ -758,12 +763,17 @@ __global__ void __launch_bounds__(kAdjBlock) rollout_bwd_kernel(RolloutArgs A) {
   for (int seg = A.nseg - 1; seg >= 0; seg--) {
     const int s0 = seg * A.ckpt;
     const int len = min(A.ckpt, A.horizon - s0);
-    // recompute the segment's states s0 .. s0 + len into the tape
+    // recompute the segment's states s0 .. s0 + len into the tape, and after each
+    // step's solve the on-chip image the reverse step needs (kinematics, mass matrix,
+    // rows, solution), so that the reverse sweep does not solve the step again
     load_state(m, W, t, A.tape_ckpt + ((size_t)seg * A.nworld + w) * ns);
     store_state(m, W, t, seg_slot(0));
     for (int k = 0; k < len; k++) {
       const float* u = A.ctrl + ((size_t)(s0 + k) * A.nworld + w) * m.nu;
       world_step(m, W, t, u, status, kAdjIters, kAdjGtol);
+      unsigned* snap = A.tape_snap + ((size_t)k * A.nworld + w) * A.snap_words;
+      const unsigned* Wu = (const unsigned*)W;
+      for (int i = t.lane; i < A.snap_words; i += T) snap[i] = Wu[i];
       integrate(m, W, t, status);
       store_state(m, W, t, seg_slot(k + 1));
     }
@@ -774,8 +784,12 @@ __global__ void __launch_bounds__(kAdjBlock) rollout_bwd_kernel(RolloutArgs A) {
       // loss term of the state after step s
       const float znext = seg_slot(k + 1)[A.zidx];
       if (t.lane == 0) qbi[A.zidx] += 2.f * (znext - A.ztarget) * dl;
-      load_state(m, W, t, seg_slot(k));
-      world_step(m, W, t, u, status, kAdjIters, kAdjGtol);
+      {
+        const unsigned* snap = A.tape_snap + ((size_t)k * A.nworld + w) * A.snap_words;
+        unsigned* Wu = (unsigned*)W;
+        for (int i = t.lane; i < A.snap_words; i += T) Wu[i] = snap[i];
+      }
+      t.sync();
       adjoint_step(m, W, t, u, status);
       float* gu = A.grad_ctrl + ((size_t)s * A.nworld + w) * m.nu;
       const float* ub = W + m.o_ub;
@@ -795,6 +809,8 @@ struct AdjointState {
   RolloutArgs args{};
   float* tape_ckpt = nullptr;
   float* tape_seg = nullptr;
+  unsigned* tape_snap = nullptr;
+  size_t snap_alloc = 0;  // words
   int* status = nullptr;
   size_t ckpt_words = 0, seg_words = 0, status_words = 0;
   bool have_fwd = false;
@@ -846,6 +862,17 @@ mjh_status adjoint_forward(AdjointState** stp, const DevModel& m, int team, int 
     }
     st->seg_words = need_seg;
   }
+  const size_t need_snap = (size_t)std::min(ckpt, horizon) * nworld * (size_t)m.o_qbi;
+  if (need_snap > st->snap_alloc) {
+    if (st->tape_snap) (void)hipFree(st->tape_snap);
+    st->tape_snap = nullptr;
+    if (hipMalloc(&st->tape_snap, need_snap * sizeof(unsigned)) != hipSuccess) {
+      st->snap_alloc = 0;
+      err = "rollout_fwd: out of device memory (on-chip images of a segment)";
+      return MJH_ENOMEM;
+    }
+    st->snap_alloc = need_snap;
+  }
   if ((size_t)nworld > st->status_words) {
     if (st->status) (void)hipFree(st->status);
     st->status = nullptr;
@@ -862,6 +889,7 @@ mjh_status adjoint_forward(AdjointState** stp, const DevModel& m, int team, int 
   A.nseg = nseg; A.ztarget = ztarget; A.wctrl = wctrl;
   A.qpos = qpos; A.qvel = qvel; A.qacc = qacc; A.ctrl = ctrl;
   A.tape_ckpt = st->tape_ckpt; A.tape_seg = st->tape_seg; A.loss = loss; A.status = st->status;
+  A.tape_snap = st->tape_snap; A.snap_words = m.o_qbi;
   st->have_fwd = false;
   if (nworld == 0) { st->have_fwd = true; return MJH_OK; }
   const size_t lds =
@@ -902,6 +930,7 @@ void adjoint_free(AdjointState* st) {
   if (!st) return;
   if (st->tape_ckpt) (void)hipFree(st->tape_ckpt);
   if (st->tape_seg) (void)hipFree(st->tape_seg);
+  if (st->tape_snap) (void)hipFree(st->tape_snap);
   if (st->status) (void)hipFree(st->status);
   delete st;
 }
