@@ -237,6 +237,7 @@ struct Model {
   std::vector<int> act_type, act_jnt;
   std::vector<double> act_gear, act_kp, act_kd, act_range, act_qdef;
   int neq = 0;
+  int integrator = 0;  // 0: semi-implicit Euler; 1: the same with implicit damping
   std::vector<int> eq_type, eq_b1, eq_b2;
   std::vector<double> eq_a1, eq_a2;  // anchor in body1's / body2's frame
   std::vector<double> qpos0;
@@ -282,6 +283,7 @@ template <class T> struct Data {
   std::vector<T> J, aref, D, efc_force, qfrc_con;
   std::vector<double> fl;  // per row: friction-loss bound, 0 for a one-sided row
   std::vector<T> qacc;
+  std::vector<T> qacc_int;  // acceleration the integrator applies (differs with implicit damping)
   std::vector<T> H;  // dense Cholesky factor of the last Newton Hessian
   int status = 0;
   int newton_iters = 0;
@@ -295,7 +297,7 @@ template <class T> struct Data {
     M.assign(m.nv * m.nv, 0.0); qLD.assign(m.nv * m.nv, 0.0);
     qfrc_bias.assign(m.nv, 0.0); qfrc_act.assign(m.nv, 0.0); qfrc_pass.assign(m.nv, 0.0);
     qfrc_smooth.assign(m.nv, 0.0); qacc_smooth.assign(m.nv, 0.0);
-    qacc.assign(m.nv, 0.0); qfrc_con.assign(m.nv, 0.0);
+    qacc.assign(m.nv, 0.0); qfrc_con.assign(m.nv, 0.0); qacc_int.assign(m.nv, 0.0);
     H.assign(m.nv * m.nv, 0.0);
   }
 };
@@ -1202,13 +1204,32 @@ template <class T> void forward(const Model& m, Data<T>& d, int mode) {
     else d.efc_force[r] = f > F ? T(F) : (f < -F ? T(-F) : f);
     for (int i = 0; i < m.nv; i++) d.qfrc_con[i] += d.J[r * m.nv + i] * d.efc_force[r];
   }
+  // Implicit damping: the forces linear in a dof's own velocity (joint damping b_k and
+  // the velocity gain kd of a position actuator on it) act at the end-of-step velocity
+  // qvel + h a, so the integrator's acceleration solves
+  //   (M + h diag(b + kd)) a_int = qfrc_smooth + qfrc_con,
+  // with the constraint forces of the solve above (which used M).
+  if (m.integrator == 1) {
+    std::vector<T> Mt(d.M), LD(m.nv * m.nv), rhs(m.nv);
+    for (int k = 0; k < m.nv; k++) Mt[k * m.nv + k] += m.dt * m.dof_damping[k];
+    for (int a = 0; a < m.nu; a++)
+      if (m.act_type[a] == APD) {
+        const int k = m.jnt_dofadr[m.act_jnt[a]];
+        Mt[k * m.nv + k] += m.dt * m.act_kd[a];
+      }
+    for (int k = 0; k < m.nv; k++) rhs[k] = d.qfrc_smooth[k] + d.qfrc_con[k];
+    factor_ltdl(m, Mt, LD);
+    solve_ltdl(m, LD, rhs.data(), d.qacc_int.data());
+  } else {
+    d.qacc_int = d.qacc;
+  }
 }
 
 // A11: semi-implicit Euler; free-joint orientation by the exponential map of the
 // body-frame angular velocity
 template <class T> void integrate(const Model& m, Data<T>& d) {
   const double h = m.dt;
-  for (int i = 0; i < m.nv; i++) d.qvel[i] = d.qvel[i] + h * d.qacc[i];
+  for (int i = 0; i < m.nv; i++) d.qvel[i] = d.qvel[i] + h * d.qacc_int[i];
   for (int j = 0; j < m.njnt; j++) {
     const int qa = m.jnt_qposadr[j], da = m.jnt_dofadr[j];
     if (m.jnt_type[j] == JFREE) {
@@ -1255,13 +1276,14 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   m.nq = hi[7]; m.nv = hi[8]; m.iterations = hi[9]; m.ls_iterations = hi[10];
   m.nconmax = hi[11];
   m.neq = hi[12];
+  m.integrator = hi[13];
   m.dt = hf[0];
   for (int k = 0; k < 3; k++) m.grav[k] = hf[1 + k];
   m.solref[0] = hf[4]; m.solref[1] = hf[5];
   for (int k = 0; k < 5; k++) m.solimp[k] = hf[6 + k];
   m.tolerance = hf[11];
   if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nconmax < 0 ||
-      m.neq < 0) {
+      m.neq < 0 || m.integrator < 0 || m.integrator > 1) {
     err = "negative size"; return false;
   }
   std::vector<int32_t> bi(2 * m.nbody);

@@ -11,7 +11,8 @@ with their own code.
 Blob layout (little endian, version 2), every block 8-byte aligned:
 
   header   int32[16]  : magic 0x4D484A4D ('MJHM'), version, nbody, njnt, ngeom, npair,
-                        nu, nq, nv, iterations, ls_iterations, nconmax, neq, 0, 0, 0
+                        nu, nq, nv, iterations, ls_iterations, nconmax, neq,
+                        integrator (0 semi-implicit Euler, 1 with implicit damping), 0, 0
            float64[16]: timestep, gravity[3], solref[2], solimp[5], tolerance, 0 x4
   body     int32 [nbody][2] : parent, 0
            f64   [nbody][19]: pos[3], quat[4] (w first), mass, ipos[3],
@@ -127,6 +128,7 @@ class Options:
     iterations: int = 4
     ls_iterations: int = 8
     nconmax: int = 0
+    integrator: int = 0  # 1: joint damping and PD velocity gains taken implicitly
 
 
 @dataclass
@@ -224,7 +226,7 @@ class Model:
         o = self.opt
         hdr_i = [MAGIC, VERSION, self.nbody, len(self.joints), len(self.geoms),
                  len(self.pairs), self.nu, self.nq, self.nv, o.iterations,
-                 o.ls_iterations, o.nconmax, self.neq, 0, 0, 0]
+                 o.ls_iterations, o.nconmax, self.neq, o.integrator, 0, 0]
         hdr_f = [o.timestep, *o.gravity, *o.solref, *o.solimp, o.tolerance, 0, 0, 0, 0]
         assert len(hdr_f) == 16
         parts = [struct.pack("<16i", *hdr_i), struct.pack("<16d", *hdr_f)]

@@ -230,7 +230,8 @@ QUAD_FRICTIONLOSS = 3.0
 
 
 def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
-              limits: bool = False, frictionloss: float = 0.0, tether: bool = False) -> Model:
+              limits: bool = False, frictionloss: float = 0.0, tether: bool = False,
+              implicit: bool = False) -> Model:
     """Free torso (box 0.3x0.1x0.05 m, 5 kg) + 4 legs x 3 hinges (capsules r 0.02,
     length 0.2, 0.5 kg) with massless sphere feet (r 0.025).  nq 19, nv 18, nu 12.
 
@@ -240,7 +241,8 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     the 12 are active on average, up to 7).  With ``frictionloss`` every hinge carries
     that dry friction (one friction-loss row each).  With ``tether`` the torso's centre
     is held by a connect equality on its standing position (a gantry tether: three
-    two-sided rows).
+    two-sided rows).  With ``implicit`` the PD velocity gains are integrated implicitly
+    (integrator 1).
 
     Each leg: hip link (hinge about x, capsule lateral 0.2 m), thigh (hinge about y,
     capsule down 0.2 m), shin (hinge about y, capsule down 0.2 m, foot sphere).
@@ -248,7 +250,8 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     the default pose (0, pi/4, -pi/2) per leg.  Only the feet collide (plane x 4 feet).
     """
     bld = _Builder("quadruped" + ("_limits" if limits else "") +
-                   ("_friction" if frictionloss > 0 else "") + ("_tethered" if tether else ""))
+                   ("_friction" if frictionloss > 0 else "") + ("_tethered" if tether else "") +
+                   ("_implicit" if implicit else ""))
 
     def rng(k):
         if not limits:
@@ -284,7 +287,7 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     if tether:
         bld.connect(torso, 0, (0, 0, 0), (0, 0, QUAD_STAND_Z))
     m.opt = Options(timestep=timestep, iterations=iterations, ls_iterations=8,
-                    nconmax=4)
+                    nconmax=4, integrator=1 if implicit else 0)
     q0 = np.zeros(m.nq)
     q0[0:3] = (0, 0, QUAD_STAND_Z)
     q0[3] = 1.0
@@ -465,6 +468,11 @@ def quadruped_tethered() -> Model:
     return quadruped(tether=True)
 
 
+def quadruped_implicit() -> Model:
+    """The quadruped with its PD velocity gains integrated implicitly."""
+    return quadruped(implicit=True)
+
+
 def quadruped_friction() -> Model:
     """The quadruped with dry friction QUAD_FRICTIONLOSS on every hinge."""
     return quadruped(frictionloss=QUAD_FRICTIONLOSS)
@@ -472,16 +480,17 @@ def quadruped_friction() -> Model:
 
 def slider(mass: float = 2.0, armature: float = 0.0, range=(0.0, 1.0), axis=(0, 0, 1),
            gravity=(0.0, 0.0, -9.81), timestep: float = 0.002,
-           frictionloss: float = 0.0) -> Model:
+           frictionloss: float = 0.0, damping: float = 0.0, integrator: int = 0) -> Model:
     """One sphere on a slide joint (nv 1), limited to ``range`` unless it is None: the
     one-dof limit and friction-loss problems."""
     bld = _Builder("slider")
     b = bld.body(0, name="slider")
     bld.joint(b, JNT_SLIDE, axis=axis, armature=armature, range=range,
-              frictionloss=frictionloss)
+              frictionloss=frictionloss, damping=damping)
     bld.geom(b, GEOM_SPHERE, (0.05,), mass=mass)
     m = bld.finish()
-    m.opt = Options(timestep=timestep, gravity=tuple(gravity), iterations=8, nconmax=0)
+    m.opt = Options(timestep=timestep, gravity=tuple(gravity), iterations=8, nconmax=0,
+                    integrator=integrator)
     m.qpos0 = np.zeros(1)
     return m
 
@@ -639,6 +648,7 @@ WORKLOADS = {
     "quadruped_limits": quadruped_limits,
     "quadruped_friction": quadruped_friction,
     "quadruped_tethered": quadruped_tethered,
+    "quadruped_implicit": quadruped_implicit,
     "humanoid": humanoid,
     "hand": hand,
 }

@@ -1,0 +1,91 @@
+"""Pins of the FP64 reference's implicit damping (integrator 1): the forces linear in a
+dof's own velocity (joint damping b, a position actuator's velocity gain kd) act at the
+end-of-step velocity.  No GPU.
+
+What fixes the answers here, independently of the reference's arithmetic:
+* a damped slide body without other forces: backward Euler in velocity gives
+  v_{n+1} = v_n / (1 + h b / m) exactly, against v_n (1 - h b / m) for the explicit
+  update; with h b / m > 2 the explicit update diverges and the implicit one decays;
+* a PD velocity gain acts exactly like joint damping of the same value;
+* without damping or PD gains both integrators give bit-identical trajectories;
+* with contacts the constraint forces are those of the explicit solve, and the
+  velocity update solves (M + h B) dv/h = M a*: checked by the stationarity of the
+  implicit update against the explicit one.
+"""
+import numpy as np
+import pytest
+
+from oracle import MODE_CONVERGED, MODE_FIXED, Oracle
+from paper_2502_08844_amd.synth import inputs, robots
+from paper_2502_08844_amd.synth.model import ACT_PD, Actuator
+
+
+def test_damped_slide_backward_euler_closed_form():
+    mass, b, h = 2.0, 30.0, 0.01
+    for integ, factor in ((1, 1 / (1 + h * b / mass)), (0, 1 - h * b / mass)):
+        m = robots.slider(mass=mass, range=None, damping=b, gravity=(0, 0, 0), timestep=h,
+                          integrator=integ)
+        r = Oracle(m).step(np.zeros((1, 1)), np.array([[1.5]]), nstep=20)
+        assert r["qvel"][0, 0] == pytest.approx(1.5 * factor ** 20, rel=1e-12)
+
+
+def test_stiff_damping_is_stable_only_implicitly():
+    mass, b, h = 1.0, 500.0, 0.01  # h b / m = 5
+    out = {}
+    for integ in (0, 1):
+        m = robots.slider(mass=mass, range=None, damping=b, gravity=(0, 0, 0), timestep=h,
+                          integrator=integ)
+        r = Oracle(m).step(np.zeros((1, 1)), np.array([[1.0]]), nstep=30)
+        out[integ] = r["qvel"][0, 0]
+    assert abs(out[0]) > 1e10  # explicit: |1 - 5|^30
+    assert 0 < out[1] < 1e-20  # implicit: (1 / 6)^30, monotone
+
+
+def test_pd_velocity_gain_equals_damping():
+    mass, kd, h = 1.5, 8.0, 0.005
+    m_damp = robots.slider(mass=mass, range=None, damping=kd, gravity=(0, 0, 0), timestep=h,
+                           integrator=1)
+    m_pd = robots.slider(mass=mass, range=None, gravity=(0, 0, 0), timestep=h, integrator=1)
+    m_pd.actuators.append(Actuator(type=ACT_PD, joint=0, kp=0.0, kd=kd))
+    v0 = np.array([[0.8]])
+    r1 = Oracle(m_damp).step(np.zeros((1, 1)), v0.copy(), nstep=25)
+    r2 = Oracle(m_pd).step(np.zeros((1, 1)), v0.copy(), None, np.zeros((25, 1, 1)), nstep=25)
+    assert r2["qvel"][0, 0] == pytest.approx(r1["qvel"][0, 0], rel=1e-13)
+    assert r1["qvel"][0, 0] == pytest.approx(0.8 / (1 + h * kd / mass) ** 25, rel=1e-12)
+
+
+def test_no_velocity_gains_no_difference():
+    m0 = robots.hinge_chain(n=3, slide_root=True)
+    m1 = robots.hinge_chain(n=3, slide_root=True)
+    m1.opt.integrator = 1
+    rng = np.random.default_rng(2)
+    q, v = rng.uniform(-0.5, 0.5, size=(4, m0.nq)), rng.normal(size=(4, m0.nv))
+    r0 = Oracle(m0).step(q.copy(), v.copy(), nstep=10)
+    r1 = Oracle(m1).step(q.copy(), v.copy(), nstep=10)
+    assert np.array_equal(r0["qpos"], r1["qpos"]) and np.array_equal(r0["qvel"], r1["qvel"])
+
+
+@pytest.mark.parametrize("mode", [MODE_FIXED, MODE_CONVERGED])
+def test_implicit_update_with_contacts(mode):
+    """(M + h B)(v' - v)/h = M a*: the implicit update keeps the explicit step's
+    generalized force M a* = qfrc_smooth + qfrc_con and adds the damping implicitly."""
+    m1 = robots.quadruped_implicit()
+    m0 = robots.quadruped()
+    o1, o0 = Oracle(m1), Oracle(m0)
+    qp, qv = inputs.initial_state("quadruped", m0, 6, seed=3)
+    u = inputs.controls("quadruped", m0, 6, 1, seed=3)
+    h = m1.opt.timestep
+    B = np.zeros(m1.nv)
+    for a in m1.actuators:
+        B[m1.jnt_dofadr()[a.joint]] += a.kd
+    for w in range(6):
+        f = o0.forward(qp[w], qv[w], ctrl=u[0, w], mode=mode)
+        r1 = o1.step(qp[w:w + 1].copy(), qv[w:w + 1].copy(), None, u[:, w:w + 1], nstep=1,
+                     mode=mode)
+        r0 = o0.step(qp[w:w + 1].copy(), qv[w:w + 1].copy(), None, u[:, w:w + 1], nstep=1,
+                     mode=mode)
+        dv = (r1["qvel"][0] - qv[w]) / h
+        lhs = (f["M"] + h * np.diag(B)) @ dv
+        np.testing.assert_allclose(lhs, f["M"] @ f["qacc"], rtol=1e-9, atol=1e-9)
+        # the reported acceleration (and the warm start) is the solve's a* in both
+        np.testing.assert_allclose(r1["qacc"][0], r0["qacc"][0], rtol=0, atol=0)
