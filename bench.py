@@ -69,7 +69,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--model", default="quadruped",
                     choices=["quadruped", "quadruped_limits", "quadruped_friction",
-                             "quadruped_tethered", "humanoid", "hand", "cartpole"],
+                             "quadruped_tethered", "quadruped_implicit", "humanoid", "hand",
+                             "cartpole"],
                     help="robot of the timed batch (the headline metric is the quadruped)")
     ap.add_argument("--nworld", type=int, default=8192)
     ap.add_argument("--nstep", type=int, default=1000)
@@ -84,8 +85,8 @@ def parse():
     ap.add_argument("--no-hetero", action="store_true",
                     help="skip the heterogeneous-batch comparison")
     ap.add_argument("--no-limits", action="store_true",
-                    help="skip the joint-limit, friction-loss and equality workloads "
-                         "(quadruped variants)")
+                    help="skip the joint-limit, friction-loss, equality and implicit-damping "
+                         "workloads (quadruped variants)")
     ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a reference "
@@ -401,6 +402,9 @@ def main():
         out["equality"] = constraint_compare(
             ctx, args.seed, "quadruped_tethered",
             "its torso centre held on its standing position by a connect equality")
+        out["implicit_damping"] = constraint_compare(
+            ctx, args.seed, "quadruped_implicit",
+            "its PD velocity gains integrated implicitly")
     if not args.no_cpu_baseline:
         nthreads = min(os.cpu_count() or 1, 16)
         cw = min(args.cpu_sample_worlds, nw)

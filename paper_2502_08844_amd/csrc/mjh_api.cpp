@@ -27,7 +27,7 @@ namespace {
 struct HostModel {
   // parsed blob (double precision as stored)
   int nbody = 0, njnt = 0, ngeom = 0, npair = 0, nu = 0, nq = 0, nv = 0;
-  int iterations = 0, ls_iterations = 0, nconmax = 0, neq = 0;
+  int iterations = 0, ls_iterations = 0, nconmax = 0, neq = 0, integrator = 0;
   std::vector<int> eq_body;        // [neq][2]
   std::vector<double> eq_anchor;   // [neq][6]
   double dt = 0, grav[3] = {0, 0, 0}, solref[2] = {0, 0}, solimp[5] = {0, 0, 0, 0, 0};
@@ -74,10 +74,11 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   m.nbody = hi[2]; m.njnt = hi[3]; m.ngeom = hi[4]; m.npair = hi[5]; m.nu = hi[6];
   m.nq = hi[7]; m.nv = hi[8]; m.iterations = hi[9]; m.ls_iterations = hi[10]; m.nconmax = hi[11];
   m.neq = hi[12];
+  m.integrator = hi[13];
   if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nq < 0 ||
       m.nv < 0 || m.iterations < 0 || m.nconmax < 0 || m.nbody > 4096 || m.njnt > 4096 ||
       m.ngeom > 4096 || m.npair > 65536 || m.nu > 4096 || m.nconmax > 4096 || m.neq < 0 ||
-      m.neq > 1024) {
+      m.neq > 1024 || m.integrator < 0 || m.integrator > 1) {
     err = "model blob: size field out of range";
     return MJH_EMODEL;
   }
@@ -225,6 +226,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   d.nbody = h.nbody; d.njnt = h.njnt; d.nq = h.nq; d.nv = h.nv; d.nu = h.nu;
   d.ngeom = h.ngeom; d.npair = h.npair; d.nconmax = h.nconmax;
   d.iterations = h.iterations;
+  d.implicit = h.integrator;
   if (h.nv > kMaxNv) { err = "nv > 64 is not supported"; return MJH_EUNSUPPORTED; }
   // addresses
   std::vector<int> body_jntadr(h.nbody, 0), body_jntnum(h.nbody, 0), body_dofadr(h.nbody, 0),
@@ -301,11 +303,13 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   child_start[h.nbody] = (int)child_list.size();
   // actuators: one per dof at most
   std::vector<int> dof_act(h.nv, -1), act_qadr, act_dadr;
+  std::vector<float> dof_vgain(dof_damping);
   for (int a = 0; a < h.nu; a++) {
     const int j = h.act_jnt[a];
     const int dof = jnt_dofadr[j];
     if (dof_act[dof] >= 0) { err = "two actuators on one dof are not supported"; return MJH_EUNSUPPORTED; }
     dof_act[dof] = a;
+    if (h.act_type[a] == ACT_PD) dof_vgain[dof] += (float)h.act_kd[a];
     act_qadr.push_back(jnt_qposadr[j]);
     act_dadr.push_back(dof);
   }
@@ -411,6 +415,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   pk.add(jaxis, &d.jnt_axis);
   pk.add(dof_armature, &d.dof_armature);
   pk.add(dof_damping, &d.dof_damping);
+  pk.add(dof_vgain, &d.dof_vgain);
   pk.add(gsize, &d.geom_size);
   pk.add(gpos, &d.geom_pos);
   pk.add(geom_rot, &d.geom_rot);
@@ -922,7 +927,8 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
     const DevModel& d = ctx->models[g.model]->dm;
     std::ostringstream k;
     k << d.nq << ' ' << d.nv << ' ' << d.nbody << ' ' << d.npair << ' ' << d.nconmax << ' '
-      << d.nlim << ' ' << d.nfric << ' ' << d.neq << ' ' << d.iterations << ' ' << g.nworld;
+      << d.nlim << ' ' << d.nfric << ' ' << d.neq << ' ' << d.implicit << ' ' << d.iterations
+      << ' ' << g.nworld;
     return k.str();
   };
   if (cache_path) {
@@ -1044,6 +1050,8 @@ mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every, co
   }
   if (mr.h.neq > 0)
     return fail(ctx, MJH_EUNSUPPORTED, "rollout: equality constraints are not differentiated");
+  if (mr.h.integrator != 0)
+    return fail(ctx, MJH_EUNSUPPORTED, "rollout: implicit damping is not differentiated");
   {
     std::vector<int> nj(mr.h.nbody, 0);
     for (int j = 0; j < mr.h.njnt; j++) nj[mr.h.jnt_body[j]]++;

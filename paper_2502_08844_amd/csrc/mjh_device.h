@@ -398,11 +398,17 @@ DEV void backward_and_mass(const DevModel& m, float* W, const Team& t) {
 // scaling of row k by 1/D_k waits one elimination (nothing reads it meanwhile), so each
 // elimination costs one barrier.  When `rhs` is given, the first triangular solve
 // L^T y = rhs rides along: once row k is final, y_i -= L_ki y_k for its ancestors.
-DEV void ltdl_factor(const DevModel& m, float* W, const Team& t, float* y = nullptr) {
+// With `hgain` the factor is of M + h diag(dof_vgain) (implicit damping).
+DEV void ltdl_factor(const DevModel& m, float* W, const Team& t, float* y = nullptr,
+                     bool hgain = false) {
   const float* M = W + m.o_M;
   float* H = W + m.o_H;
   for (int k = t.lane; k < m.ntri; k += t.T) H[k] = M[k];
   t.sync();
+  if (hgain) {
+    for (int i = t.lane; i < m.nv; i += t.T) H[tri(i, i)] += m.dt * m.dof_vgain[i];
+    t.sync();
+  }
   for (int k = m.nv - 1; k >= -1; k--) {
     if (k >= 0) {
       const int a0 = m.anc_start[k], na = m.anc_start[k + 1] - a0;
@@ -1480,10 +1486,12 @@ DEV void export_contacts(const DevModel& m, float* W, const Team& t, float* out,
   if (t.lane == 0 && nout) *nout = ncon;
 }
 
+// With implicit damping the velocity update takes the acceleration left in o_frc by
+// implicit_damping; otherwise the solve's qacc.
 DEV void integrate(const DevModel& m, float* W, const Team& t, int& status) {
   float* qpos = W + m.o_qpos;
   float* qvel = W + m.o_qvel;
-  const float* a = W + m.o_qacc;
+  const float* a = W + (m.implicit ? m.o_frc : m.o_qacc);
   const float h = m.dt;
   for (int i = t.lane; i < m.nv; i += t.T) qvel[i] += h * a[i];
   t.sync();
@@ -1539,6 +1547,31 @@ DEV void integrate(const DevModel& m, float* W, const Team& t, int& status) {
   } while (0)
 #endif
 
+// Implicit damping (integrator 1): the forces linear in a dof's own velocity (joint
+// damping, PD velocity gains) act at the end-of-step velocity, so the integrator's
+// acceleration solves (M + h diag(b + kd)) a_int = qfrc_smooth + J^T f, with the row
+// forces f of the solve that used M (f = -s'(e) per row piece).  a_int replaces the
+// smooth force in o_frc; qacc keeps the solve's a* (reported, and the warm start).
+DEV void implicit_damping(const DevModel& m, float* W, const Team& t) {
+  const int* scal = (const int*)(W + m.o_scal);
+  const int nv = m.nv, nrow = scal[SC_NROW];
+  const float* J = W + m.o_J;
+  const float* D = W + m.o_D;
+  const float* e = W + m.o_e;
+  const float* fl = W + m.o_fl;
+  const bool fr = has_bounds(m);
+  float* rhs = W + m.o_frc;
+  for (int i = t.lane; i < nv; i += t.T) {
+    float v = rhs[i];
+    for (int r = 0; r < nrow; r++)
+      v -= (fr ? row_slope(D[r], fl[r], e[r]) : fminf(D[r] * e[r], 0.f)) * J[r * nv + i];
+    rhs[i] = v;
+  }
+  t.sync();
+  ltdl_factor(m, W, t, rhs, true);  // also solves L^T y = rhs in place
+  ltdl_solve(m, W, t, nullptr, rhs, true);
+}
+
 DEV void world_step(const DevModel& m, float* W0, const Team& t0, const float* ctrl,
                     int& status, int iters, float gtol = 0.f, long long* ph = nullptr,
                     long long* last = nullptr) {
@@ -1584,6 +1617,10 @@ DEV void world_step(const DevModel& m, float* W0, const Team& t0, const float* c
     MJH_PHASE_CTX
     newton(m, W, t, status, iters, gtol);
     MJH_MARK(6);
+  }
+  if (m.implicit) {
+    MJH_PHASE_CTX
+    implicit_damping(m, W, t);
   }
 #undef MJH_PHASE_CTX
 }

@@ -33,6 +33,7 @@ struct DevModel {
   // ---- sizes
   int nbody, njnt, nq, nv, nu, ngeom, npair, ncand, nconmax, nlim, nfric, neq, nrowmax;
   int iterations, nlevel, nmpair, ntri;
+  int implicit;  // 1: joint damping and PD velocity gains integrated implicitly
   // ---- constants
   float dt, K, B;                       // soft-constraint stiffness/damping
   float dmin, dmax, width, mid, power;  // impedance (solimp)
@@ -82,6 +83,7 @@ struct DevModel {
   const float* jnt_axis;      // [njnt][3] unit
   const float* dof_armature;
   const float* dof_damping;
+  const float* dof_vgain;     // [nv] damping + velocity gains of PD actuators on the dof
   const float* geom_size;     // [ngeom][3]
   const float* geom_pos;      // [ngeom][3]
   const float* geom_rot;      // [ngeom][9]

@@ -1,0 +1,83 @@
+"""GPU parity of the implicit-damping integrator (joint damping and PD velocity gains
+taken at the end-of-step velocity) against the FP64 reference.
+
+The compared quantity is the integrator's acceleration a_int = (qvel' - qvel) / h of
+one step from the same float32 state (the reported qacc is the solve's a*, covered by
+the other parity tests), per world ||a_int,gpu - a_int,ref||_inf / max(||a_int,ref||_inf,
+9.81), on worlds not at a contact or activation switch (those are counted and reported).
+
+Tolerance 1e-3, ten times the qacc tolerance, with a median below 1e-5: a_int =
+(M + h B)^-1 (qfrc_smooth + J^T f) takes the row forces f of the fixed-iteration solve,
+so a difference d in a* (FP32 against FP64 iterates, up to 1e-4 of |a*|) reaches a_int
+as (M + h B)^-1 J^T D J d, and D J^T J outweighs the light leg links' inertia by about
+an order of magnitude in the violent random-target states compared here.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2502_08844_amd.synth import inputs, robots
+from tests.gpu_util import G, compare_step, gpu_ctx, run_gpu, workload
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-3
+TOL_MEDIAN = 1e-5
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return gpu_ctx()
+
+
+def _a_int_errors(ctx, mjh, m, qp, qv, ws, u1, team=None, block=None):
+    """Errors of a_int per world, and the flags of worlds at a switch (as in the other
+    parity tests: reported, not gated)."""
+    g = run_gpu(ctx, mjh, m, qp, qv, ws, u1, 1, team, block, contacts=True)
+    o = oracle.Oracle(m)
+    cmp = compare_step(m, o, (qp, qv, ws), u1, g)
+    r = o.step(qp.copy(), qv.copy(), ws.copy(), u1, nstep=1, mode=oracle.MODE_FIXED, nthreads=8)
+    h = m.opt.timestep
+    a_gpu = (g["qvel"] - qv) / h
+    a_ref = (r["qvel"] - qv) / h
+    err = np.abs(a_gpu - a_ref).max(1) / np.maximum(np.abs(a_ref).max(1), G)
+    return err, cmp["flag"], g
+
+
+@pytest.mark.parametrize("team,block", [(32, 128), (64, 64), (16, 64)])
+def test_quadruped_implicit_velocity_update(lib, team, block):
+    mjh, ctx = lib
+    m, qp, qv, u = workload("quadruped_implicit", 203, 51, seed=4)
+    # advance on the GPU to a contact-rich state, then compare one step
+    r = run_gpu(ctx, mjh, m, qp, qv, None, u[:50], 50, team, block, contacts=False)
+    err, flag, g = _a_int_errors(ctx, mjh, m, r["qpos"], r["qvel"], r["qacc"], u[50:51], team,
+                                 block)
+    print(f"[parity] quadruped_implicit-T{team}: a_int rel err max {err[~flag].max():.2e} "
+          f"median {np.median(err):.2e}; near-switch states {flag.sum()}/{len(flag)}"
+          + (f" (their err max {err[flag].max():.2e})" if flag.any() else ""), flush=True)
+    assert np.all(g["status"] & 1 == 0)
+    assert err[~flag].max() <= TOL
+    assert np.median(err) <= TOL_MEDIAN
+    assert flag.sum() <= 0.25 * len(flag)
+
+
+def test_stiff_damping_decays_on_gpu(lib):
+    """h b / m = 5: the explicit update would grow 4x per step; implicitly the velocity
+    shrinks by 1/6 per step."""
+    mjh, ctx = lib
+    m = robots.slider(mass=1.0, range=None, damping=500.0, gravity=(0, 0, 0), timestep=0.01,
+                      integrator=1)
+    qv = np.full((64, 1), 1.0)
+    r = run_gpu(ctx, mjh, m, np.zeros((64, 1)), qv, None, None, 10, contacts=False)
+    np.testing.assert_allclose(r["qvel"][:, 0], (1 / 6) ** 10, rtol=1e-5)
+
+
+def test_rollout_rejects_implicit(lib):
+    mjh, ctx = lib
+    m = robots.quadruped_implicit()
+    w = mjh.World(ctx, m, 2)
+    u = torch.zeros(4, 2, m.nu, device="cuda")
+    loss = torch.zeros(2, device="cuda")
+    with pytest.raises(mjh.MjhError):
+        w.batch.rollout_fwd(4, 2, u, 2, 0.3, 1e-3, loss)
