@@ -215,7 +215,7 @@ template <class T> inline T dot6(const T* a, const T* b) {
 
 // -------------------------------------------------------------------------- model
 enum { JFREE = 0, JSLIDE = 1, JHINGE = 2 };
-enum { GPLANE = 0, GSPHERE = 1, GCAPSULE = 2, GBOX = 3 };
+enum { GPLANE = 0, GSPHERE = 1, GCAPSULE = 2, GBOX = 3, GHFIELD = 4 };
 enum { AMOTOR = 0, APD = 1 };
 enum { ST_NONFINITE = 1, ST_OVERFLOW = 2, ST_NODESCENT = 4 };
 static const int CON_SIZE = 20;  // exported contact record (see mjo_api.h)
@@ -238,6 +238,10 @@ struct Model {
   std::vector<double> act_gear, act_kp, act_kd, act_range, act_qdef;
   int neq = 0;
   int integrator = 0;  // 0: semi-implicit Euler; 1: the same with implicit damping
+  // heightfield: nrow x ncol elevations in [0, 1] over [-sx, sx] x [-sy, sy], z = sz h
+  int hf_nrow = 0, hf_ncol = 0;
+  double hf_size[3] = {0, 0, 0};
+  std::vector<double> hf_data;
   std::vector<int> eq_type, eq_b1, eq_b2;
   std::vector<double> eq_a1, eq_a2;  // anchor in body1's / body2's frame
   std::vector<double> qpos0;
@@ -726,6 +730,121 @@ void capsule_box(const T* a, const T* u, T r, const T* c, const T* R, const doub
     if (k == sel[0] || k == sel[1]) add_cand(out, depth[k], pts[k], nrm[k], k);
 }
 
+// closest point of triangle (a, b, c) to p: the projection onto the triangle's plane
+// when it falls inside (all barycentric weights >= 0), else the nearest of the three
+// edges' closest points
+template <class T>
+void tri_closest(const T* a, const T* b, const T* c, const T* p, T* q) {
+  T ab[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+  T ac[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+  T ap[3] = {p[0] - a[0], p[1] - a[1], p[2] - a[2]};
+  T n[3];
+  cross3(ab, ac, n);
+  T nn = dot3(n, n);
+  T h = dot3(ap, n) / nn;
+  T pp[3] = {p[0] - h * n[0], p[1] - h * n[1], p[2] - h * n[2]};  // projection
+  // barycentric weights of the projection: areas of the sub-triangles against n
+  const T* v[3] = {a, b, c};
+  T w[3];
+  for (int k = 0; k < 3; k++) {
+    const T* e0 = v[(k + 1) % 3];
+    const T* e1 = v[(k + 2) % 3];
+    T d0[3] = {e0[0] - pp[0], e0[1] - pp[1], e0[2] - pp[2]};
+    T d1[3] = {e1[0] - pp[0], e1[1] - pp[1], e1[2] - pp[2]};
+    T cr[3];
+    cross3(d0, d1, cr);
+    w[k] = dot3(cr, n) / nn;
+  }
+  if (w[0] >= 0.0 && w[1] >= 0.0 && w[2] >= 0.0) {
+    for (int k = 0; k < 3; k++) q[k] = pp[k];
+    return;
+  }
+  T best = 0.0;
+  for (int e = 0; e < 3; e++) {
+    const T* s0 = v[e];
+    const T* s1 = v[(e + 1) % 3];
+    T u[3] = {s1[0] - s0[0], s1[1] - s0[1], s1[2] - s0[2]};
+    T t = seg_point_param(s0, u, p);
+    T x[3] = {s0[0] + t * u[0], s0[1] + t * u[1], s0[2] + t * u[2]};
+    T dx[3] = {p[0] - x[0], p[1] - x[1], p[2] - x[2]};
+    T dd = dot3(dx, dx);
+    if (e == 0 || dd < best) {
+      best = dd;
+      for (int k = 0; k < 3; k++) q[k] = x[k];
+    }
+  }
+}
+
+// sphere (geom 1: centre c, radius r) against the heightfield surface (geom 2, pose
+// (xg, Rg)): the nearest point q of the triangles of the grid cells that the sphere's
+// footprint overlaps (first in cell and triangle order on ties).  Signed distance
+// = +-|c - q| - r, negative when c lies below the nearest triangle's plane; the normal
+// points from the sphere into the surface; the position is midway between the surfaces.
+template <class T>
+void sphere_hfield(const Model& m, const T* xg, const T* Rg, const T* c, T r,
+                   std::vector<Cand<T>>& out) {
+  const int nr = m.hf_nrow, nc = m.hf_ncol;
+  const double sx = m.hf_size[0], sy = m.hf_size[1], sz = m.hf_size[2];
+  const double dx = 2.0 * sx / (nc - 1), dy = 2.0 * sy / (nr - 1);
+  T rel[3] = {c[0] - xg[0], c[1] - xg[1], c[2] - xg[2]};
+  T cl[3];
+  matTvec(Rg, rel, cl);  // centre in the heightfield's frame
+  auto vert = [&](int i, int j, T* v) {
+    v[0] = -sx + dx * j; v[1] = -sy + dy * i; v[2] = sz * m.hf_data[(size_t)i * nc + j];
+  };
+  const int j0 = std::max(0, (int)std::floor(val((cl[0] - r + sx) / dx)));
+  const int j1 = std::min(nc - 2, (int)std::floor(val((cl[0] + r + sx) / dx)));
+  const int i0 = std::max(0, (int)std::floor(val((cl[1] - r + sy) / dy)));
+  const int i1 = std::min(nr - 2, (int)std::floor(val((cl[1] + r + sy) / dy)));
+  bool found = false;
+  T bestd = 0.0, bq[3], bn[3];
+  for (int i = i0; i <= i1; i++)
+    for (int j = j0; j <= j1; j++) {
+      T v00[3], v01[3], v10[3], v11[3];
+      vert(i, j, v00); vert(i, j + 1, v01); vert(i + 1, j, v10); vert(i + 1, j + 1, v11);
+      const T* tris[2][3] = {{v00, v01, v11}, {v00, v11, v10}};
+      for (int k = 0; k < 2; k++) {
+        T q[3];
+        tri_closest(tris[k][0], tris[k][1], tris[k][2], cl, q);
+        T dq[3] = {cl[0] - q[0], cl[1] - q[1], cl[2] - q[2]};
+        T dd = dot3(dq, dq);
+        if (!found || dd < bestd) {
+          found = true;
+          bestd = dd;
+          for (int a = 0; a < 3; a++) bq[a] = q[a];
+          T e1[3] = {tris[k][1][0] - tris[k][0][0], tris[k][1][1] - tris[k][0][1],
+                     tris[k][1][2] - tris[k][0][2]};
+          T e2[3] = {tris[k][2][0] - tris[k][0][0], tris[k][2][1] - tris[k][0][1],
+                     tris[k][2][2] - tris[k][0][2]};
+          cross3(e1, e2, bn);
+        }
+      }
+    }
+  if (!found) return;
+  T L = sqrt(bestd);
+  T nl = norm3(bn);
+  for (int a = 0; a < 3; a++) bn[a] = bn[a] / nl;  // upward unit normal of that triangle
+  T dq[3] = {cl[0] - bq[0], cl[1] - bq[1], cl[2] - bq[2]};
+  const bool below = dot3(bn, dq) < 0.0;
+  T dist = (below ? -L : L) - r;
+  if (!(dist < 0.0)) return;
+  T nloc[3];  // from the sphere into the surface
+  if (L > 1e-12) {
+    for (int a = 0; a < 3; a++) nloc[a] = (below ? dq[a] : -dq[a]) / L;
+  } else {
+    for (int a = 0; a < 3; a++) nloc[a] = -bn[a];
+  }
+  T n[3], qw[3];
+  matvec(Rg, nloc, n);
+  matvec(Rg, bq, qw);
+  T pos[3];
+  for (int a = 0; a < 3; a++) {
+    qw[a] += xg[a];
+    pos[a] = 0.5 * (c[a] + r * n[a] + qw[a]);
+  }
+  add_cand(out, dist, pos, n, 0);
+}
+
 template <class T> void collide_pair(const Model& m, const Data<T>& d, int pi, std::vector<Cand<T>>& out) {
   const int g1 = m.pair_g1[pi], g2 = m.pair_g2[pi];
   const int t1 = m.geom_type[g1], t2 = m.geom_type[g2];
@@ -785,6 +904,8 @@ template <class T> void collide_pair(const Model& m, const Data<T>& d, int pi, s
       T t = seg_point_param(a, u, x1);
       T q[3] = {a[0] + t * u[0], a[1] + t * u[1], a[2] + t * u[2]};
       sphere_sphere(x1, T(s1[0]), q, T(s2[0]), 0, out);
+    } else if (t2 == GHFIELD) {
+      sphere_hfield(m, x2, R2, x1, T(s1[0]), out);
     } else if (t2 == GBOX) {
       T nb[3];
       T sd = box_point(x2, R2, s2, x1, nb);
@@ -1277,13 +1398,14 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   m.nconmax = hi[11];
   m.neq = hi[12];
   m.integrator = hi[13];
+  const int has_hf = hi[14];
   m.dt = hf[0];
   for (int k = 0; k < 3; k++) m.grav[k] = hf[1 + k];
   m.solref[0] = hf[4]; m.solref[1] = hf[5];
   for (int k = 0; k < 5; k++) m.solimp[k] = hf[6 + k];
   m.tolerance = hf[11];
   if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nconmax < 0 ||
-      m.neq < 0 || m.integrator < 0 || m.integrator > 1) {
+      m.neq < 0 || m.integrator < 0 || m.integrator > 1 || has_hf < 0 || has_hf > 1) {
     err = "negative size"; return false;
   }
   std::vector<int32_t> bi(2 * m.nbody);
@@ -1304,6 +1426,17 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   std::vector<int32_t> ei(4 * m.neq);
   std::vector<double> ef(6 * m.neq);
   r.read(ei.data(), ei.size()); r.read(ef.data(), ef.size());
+  if (has_hf) {
+    int32_t hd[2];
+    r.read(hd, 2);
+    r.read(m.hf_size, 3);
+    if (!r.ok || hd[0] < 2 || hd[1] < 2 || hd[0] > 4096 || hd[1] > 4096) {
+      err = "bad heightfield"; return false;
+    }
+    m.hf_nrow = hd[0]; m.hf_ncol = hd[1];
+    m.hf_data.resize((size_t)m.hf_nrow * m.hf_ncol);
+    r.read(m.hf_data.data(), m.hf_data.size());
+  }
   m.qpos0.resize(m.nq);
   r.read(m.qpos0.data(), m.nq);
   if (!r.ok || r.off != nbytes) { err = "blob size mismatch"; return false; }
@@ -1362,6 +1495,7 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
     }
     int t1 = m.geom_type[pi[2 * p]], t2 = m.geom_type[pi[2 * p + 1]];
     bool ok = t1 <= t2 && !(t1 == GPLANE && t2 == GPLANE) && !(t1 == GBOX && t2 == GBOX);
+    if (t2 == GHFIELD) ok = t1 == GSPHERE && m.hf_nrow > 0;
     if (!ok) { err = "unsupported pair"; return false; }
   }
   for (int a = 0; a < m.nu; a++) {

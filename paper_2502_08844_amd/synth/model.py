@@ -12,7 +12,8 @@ Blob layout (little endian, version 2), every block 8-byte aligned:
 
   header   int32[16]  : magic 0x4D484A4D ('MJHM'), version, nbody, njnt, ngeom, npair,
                         nu, nq, nv, iterations, ls_iterations, nconmax, neq,
-                        integrator (0 semi-implicit Euler, 1 with implicit damping), 0, 0
+                        integrator (0 semi-implicit Euler, 1 with implicit damping),
+                        hfield (1 if the model has a heightfield), 0
            float64[16]: timestep, gravity[3], solref[2], solimp[5], tolerance, 0 x4
   body     int32 [nbody][2] : parent, 0
            f64   [nbody][19]: pos[3], quat[4] (w first), mass, ipos[3],
@@ -28,6 +29,10 @@ Blob layout (little endian, version 2), every block 8-byte aligned:
            f64   [nu][7]    : gear, kp, kd, ctrlrange[2], qdefault, 0
   equality int32 [neq][4]   : type (0 connect), body1, body2, 0
            f64   [neq][6]   : anchor in body1's frame[3], the same point in body2's frame[3]
+  hfield   int32 [2]        : nrow, ncol (>= 2 each)            } only when header hfield = 1
+           f64   [3]        : half extents sx, sy; height scale sz
+           f64   [nrow][ncol] elevations in [0, 1] (row i at y = -sy + 2 sy i / (nrow - 1),
+                             column j at x = -sx + 2 sx j / (ncol - 1), z = sz h)
   qpos0    f64   [nq]
 
 A limited hinge or slide joint keeps its coordinate inside range[0] < q < range[1]
@@ -38,6 +43,10 @@ bounded by F.
 A connect equality holds a point of body1 on a point of body2 (a ball joint closing a
 loop, or pinning a body to the world when body2 = 0): three always-present two-sided
 rows.
+
+A heightfield geom (type 4) is the model's heightfield surface, placed by the geom's
+pose: each grid cell is split into the triangles (v_ij, v_i,j+1, v_i+1,j+1) and
+(v_ij, v_i+1,j+1, v_i+1,j).  Only sphere-heightfield pairs are supported.
 
 Geom sizes: sphere (r), capsule (r, half segment length; segment along local z),
 box (half extents).  Plane normal is the geom's local +z.
@@ -54,7 +63,7 @@ MAGIC = 0x4D484A4D
 VERSION = 2
 
 JNT_FREE, JNT_SLIDE, JNT_HINGE = 0, 1, 2
-GEOM_PLANE, GEOM_SPHERE, GEOM_CAPSULE, GEOM_BOX = 0, 1, 2, 3
+GEOM_PLANE, GEOM_SPHERE, GEOM_CAPSULE, GEOM_BOX, GEOM_HFIELD = 0, 1, 2, 3, 4
 ACT_MOTOR, ACT_PD = 0, 1
 EQ_CONNECT = 0
 
@@ -119,6 +128,14 @@ class Equality:
 
 
 @dataclass
+class Heightfield:
+    nrow: int
+    ncol: int
+    size: Tuple[float, float, float]  # half extents x, y and the height scale
+    data: np.ndarray = None           # [nrow, ncol] elevations in [0, 1]
+
+
+@dataclass
 class Options:
     timestep: float = 0.002
     gravity: Tuple[float, float, float] = (0.0, 0.0, -9.81)
@@ -140,6 +157,7 @@ class Model:
     pairs: List[Tuple[int, int, float]] = field(default_factory=list)
     actuators: List[Actuator] = field(default_factory=list)
     equalities: List[Equality] = field(default_factory=list)
+    hfield: Heightfield = None
     opt: Options = field(default_factory=Options)
     qpos0: np.ndarray = None
 
@@ -218,6 +236,12 @@ class Model:
             assert e.body1 != e.body2
         for g1, g2, _ in self.pairs:
             assert self.geoms[g1].type <= self.geoms[g2].type, "pair order by geom type"
+            if self.geoms[g2].type == GEOM_HFIELD:
+                assert self.geoms[g1].type == GEOM_SPHERE, "heightfields pair with spheres"
+                assert self.hfield is not None
+        if self.hfield is not None:
+            hf = self.hfield
+            assert hf.nrow >= 2 and hf.ncol >= 2 and hf.data.shape == (hf.nrow, hf.ncol)
         assert self.qpos0 is not None and len(self.qpos0) == self.nq
 
     # ---------------------------------------------------------------- to blob
@@ -226,7 +250,8 @@ class Model:
         o = self.opt
         hdr_i = [MAGIC, VERSION, self.nbody, len(self.joints), len(self.geoms),
                  len(self.pairs), self.nu, self.nq, self.nv, o.iterations,
-                 o.ls_iterations, o.nconmax, self.neq, o.integrator, 0, 0]
+                 o.ls_iterations, o.nconmax, self.neq, o.integrator,
+                 int(self.hfield is not None), 0]
         hdr_f = [o.timestep, *o.gravity, *o.solref, *o.solimp, o.tolerance, 0, 0, 0, 0]
         assert len(hdr_f) == 16
         parts = [struct.pack("<16i", *hdr_i), struct.pack("<16d", *hdr_f)]
@@ -254,5 +279,10 @@ class Model:
                             for a in self.actuators]))
         parts.append(blk_i([[e.type, e.body1, e.body2, 0] for e in self.equalities]))
         parts.append(blk_f([[*e.anchor1, *e.anchor2] for e in self.equalities]))
+        if self.hfield is not None:
+            hf = self.hfield
+            parts.append(blk_i([hf.nrow, hf.ncol]))
+            parts.append(blk_f(list(hf.size)))
+            parts.append(blk_f(np.asarray(hf.data, dtype=np.float64)))
         parts.append(blk_f(np.asarray(self.qpos0, dtype=np.float64)))
         return b"".join(parts)

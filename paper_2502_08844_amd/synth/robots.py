@@ -27,9 +27,9 @@ from typing import List, Sequence, Tuple
 
 import numpy as np
 
-from .model import (ACT_MOTOR, ACT_PD, EQ_CONNECT, GEOM_BOX, GEOM_CAPSULE, GEOM_PLANE,
-                    GEOM_SPHERE, JNT_FREE, JNT_HINGE, JNT_SLIDE, Actuator, Body, Equality,
-                    Geom, Joint, Model, Options)
+from .model import (ACT_MOTOR, ACT_PD, EQ_CONNECT, GEOM_BOX, GEOM_CAPSULE, GEOM_HFIELD,
+                    GEOM_PLANE, GEOM_SPHERE, JNT_FREE, JNT_HINGE, JNT_SLIDE, Actuator, Body,
+                    Equality, Geom, Heightfield, Joint, Model, Options)
 
 # ----------------------------------------------------------------------------------
 # closed-form mass properties (uniform density)
@@ -468,6 +468,82 @@ def quadruped_tethered() -> Model:
     return quadruped(tether=True)
 
 
+def perlin_terrain(n: int = 64, cells: int = 8, octaves: int = 3, seed: int = 0) -> np.ndarray:
+    """An n x n gradient-noise (Perlin) elevation map in [0, 1]: ``octaves`` layers of
+    random unit gradients on lattices of cells, 2 cells, ... per side, blended with the
+    quintic fade 6t^5 - 15t^4 + 10t^3, each octave at half the previous amplitude.
+    Deterministic (numpy Philox keyed by ``seed``)."""
+    rng = np.random.Generator(np.random.Philox(key=[int(seed), 17]))
+    u = np.linspace(0.0, 1.0, n)
+    out = np.zeros((n, n))
+    amp = 1.0
+    for o in range(octaves):
+        k = cells * 2 ** o
+        ang = rng.uniform(0.0, 2.0 * np.pi, size=(k + 1, k + 1))
+        gx, gy = np.cos(ang), np.sin(ang)
+        x = u * k
+        i0 = np.minimum(np.floor(x).astype(int), k - 1)
+        t = x - i0
+        fade = t ** 3 * (t * (t * 6 - 15) + 10)
+        # rows follow y, columns follow x
+        Y, X = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        iy, ix, ty, tx = i0[Y], i0[X], t[Y], t[X]
+        fy, fx = fade[Y], fade[X]
+
+        def corner(dy, dx):
+            return gx[iy + dy, ix + dx] * (tx - dx) + gy[iy + dy, ix + dx] * (ty - dy)
+        top = corner(0, 0) * (1 - fx) + corner(0, 1) * fx
+        bot = corner(1, 0) * (1 - fx) + corner(1, 1) * fx
+        out += amp * (top * (1 - fy) + bot * fy)
+        amp *= 0.5
+    out -= out.min()
+    return out / max(out.max(), 1e-12)
+
+
+# rough terrain of the quadruped_rough workload: 4 m x 4 m, 64 x 64 samples (6.3 cm
+# spacing), 6 cm from the lowest to the highest point
+ROUGH_SIZE, ROUGH_N, ROUGH_HEIGHT = 2.0, 64, 0.06
+
+
+def quadruped_rough(seed: int = 0) -> Model:
+    """The quadruped on Perlin-noise rough terrain: the feet collide with a heightfield
+    instead of the floor plane (the paper's rough-terrain locomotion setting)."""
+    m = quadruped()
+    m.name = "quadruped_rough"
+    data = perlin_terrain(ROUGH_N, seed=seed)
+    m.hfield = Heightfield(nrow=ROUGH_N, ncol=ROUGH_N,
+                           size=(ROUGH_SIZE, ROUGH_SIZE, ROUGH_HEIGHT), data=data)
+    floor = m.pairs[0][0]
+    m.geoms[floor].type = GEOM_HFIELD
+    m.pairs = [(f, floor, mu) for (_, f, mu) in m.pairs]
+    # stand on the terrain: lift the torso by the terrain height under the origin
+    h0 = ROUGH_HEIGHT * data[ROUGH_N // 2, ROUGH_N // 2]
+    m.qpos0 = m.qpos0.copy()
+    m.qpos0[2] += h0 + 0.01
+    return m
+
+
+def sphere_on_hfield(data: np.ndarray, size=(1.0, 1.0, 0.2), radius: float = 0.1,
+                     mass: float = 1.0, hpos=(0.0, 0.0, 0.0), hquat=(1.0, 0.0, 0.0, 0.0),
+                     timestep: float = 0.002, mu: float = 1.0) -> Model:
+    """A free sphere and a heightfield geom (elevations ``data``, placed at hpos/hquat)
+    with one sphere-heightfield pair (collision and resting checks)."""
+    bld = _Builder("sphere_hfield")
+    hf = bld.geom(0, GEOM_HFIELD, (0.0, 0.0, 0.0), pos=hpos, quat=hquat, friction=mu)
+    b = bld.body(0, pos=(0, 0, 1.0))
+    bld.joint(b, JNT_FREE)
+    g = bld.geom(b, GEOM_SPHERE, (radius,), mass=mass, friction=mu)
+    m = bld.finish()
+    data = np.asarray(data, dtype=np.float64)
+    m.hfield = Heightfield(nrow=data.shape[0], ncol=data.shape[1], size=tuple(size), data=data)
+    m.pairs = [(g, hf, mu)]
+    m.opt = Options(timestep=timestep, iterations=20, ls_iterations=20, nconmax=1)
+    q0 = np.zeros(7)
+    q0[2], q0[3] = 1.0, 1.0
+    m.qpos0 = q0
+    return m
+
+
 def quadruped_implicit() -> Model:
     """The quadruped with its PD velocity gains integrated implicitly."""
     return quadruped(implicit=True)
@@ -649,6 +725,7 @@ WORKLOADS = {
     "quadruped_friction": quadruped_friction,
     "quadruped_tethered": quadruped_tethered,
     "quadruped_implicit": quadruped_implicit,
+    "quadruped_rough": quadruped_rough,
     "humanoid": humanoid,
     "hand": hand,
 }
