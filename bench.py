@@ -69,8 +69,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--model", default="quadruped",
                     choices=["quadruped", "quadruped_limits", "quadruped_friction",
-                             "quadruped_tethered", "quadruped_implicit", "humanoid", "hand",
-                             "cartpole"],
+                             "quadruped_tethered", "quadruped_implicit", "quadruped_rough",
+                             "humanoid", "hand", "cartpole"],
                     help="robot of the timed batch (the headline metric is the quadruped)")
     ap.add_argument("--nworld", type=int, default=8192)
     ap.add_argument("--nstep", type=int, default=1000)
@@ -85,8 +85,8 @@ def parse():
     ap.add_argument("--no-hetero", action="store_true",
                     help="skip the heterogeneous-batch comparison")
     ap.add_argument("--no-limits", action="store_true",
-                    help="skip the joint-limit, friction-loss, equality and implicit-damping "
-                         "workloads (quadruped variants)")
+                    help="skip the joint-limit, friction-loss, equality, implicit-damping and "
+                         "rough-terrain workloads (quadruped variants)")
     ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a reference "
@@ -405,6 +405,9 @@ def main():
         out["implicit_damping"] = constraint_compare(
             ctx, args.seed, "quadruped_implicit",
             "its PD velocity gains integrated implicitly")
+        out["rough_terrain"] = constraint_compare(
+            ctx, args.seed, "quadruped_rough",
+            "its feet on 4 m x 4 m Perlin-noise terrain (64 x 64 heightfield, 6 cm relief)")
     if not args.no_cpu_baseline:
         nthreads = min(os.cpu_count() or 1, 16)
         cw = min(args.cpu_sample_worlds, nw)

@@ -28,6 +28,9 @@ struct HostModel {
   // parsed blob (double precision as stored)
   int nbody = 0, njnt = 0, ngeom = 0, npair = 0, nu = 0, nq = 0, nv = 0;
   int iterations = 0, ls_iterations = 0, nconmax = 0, neq = 0, integrator = 0;
+  int hf_nrow = 0, hf_ncol = 0;
+  double hf_size[3] = {0, 0, 0};
+  std::vector<double> hf_data;
   std::vector<int> eq_body;        // [neq][2]
   std::vector<double> eq_anchor;   // [neq][6]
   double dt = 0, grav[3] = {0, 0, 0}, solref[2] = {0, 0}, solimp[5] = {0, 0, 0, 0, 0};
@@ -75,10 +78,11 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   m.nq = hi[7]; m.nv = hi[8]; m.iterations = hi[9]; m.ls_iterations = hi[10]; m.nconmax = hi[11];
   m.neq = hi[12];
   m.integrator = hi[13];
+  const int has_hf = hi[14];
   if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nq < 0 ||
       m.nv < 0 || m.iterations < 0 || m.nconmax < 0 || m.nbody > 4096 || m.njnt > 4096 ||
       m.ngeom > 4096 || m.npair > 65536 || m.nu > 4096 || m.nconmax > 4096 || m.neq < 0 ||
-      m.neq > 1024 || m.integrator < 0 || m.integrator > 1) {
+      m.neq > 1024 || m.integrator < 0 || m.integrator > 1 || has_hf < 0 || has_hf > 1) {
     err = "model blob: size field out of range";
     return MJH_EMODEL;
   }
@@ -95,8 +99,21 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   bool ok = rd(bi, 2 * m.nbody) && rd(bf, 19 * (size_t)m.nbody) && rd(ji, 4 * m.njnt) &&
             rd(jf, 11 * (size_t)m.njnt) && rd(gi, 2 * m.ngeom) && rd(gf, 11 * (size_t)m.ngeom) &&
             rd(pi, 2 * m.npair) && rd(pf, m.npair) && rd(ai, 2 * m.nu) &&
-            rd(af, 7 * (size_t)m.nu) && rd(ei, 4 * (size_t)m.neq) && rd(ef, 6 * (size_t)m.neq) &&
-            rd(m.qpos0, m.nq);
+            rd(af, 7 * (size_t)m.nu) && rd(ei, 4 * (size_t)m.neq) && rd(ef, 6 * (size_t)m.neq);
+  if (ok && has_hf) {
+    int32_t hd[2];
+    ok = r.read(hd, 2) && r.read(m.hf_size, 3);
+    if (ok && (hd[0] < 2 || hd[1] < 2 || hd[0] > 4096 || hd[1] > 4096)) {
+      err = "model blob: heightfield needs 2..4096 rows and columns";
+      return MJH_EMODEL;
+    }
+    if (ok) {
+      m.hf_nrow = hd[0];
+      m.hf_ncol = hd[1];
+      ok = rd(m.hf_data, (size_t)m.hf_nrow * m.hf_ncol);
+    }
+  }
+  ok = ok && rd(m.qpos0, m.nq);
   if (!ok || r.off() != nbytes) { err = "model blob: size mismatch"; return MJH_EMODEL; }
   for (int b = 0; b < m.nbody; b++) {
     m.body_parent.push_back(bi[2 * b]);
@@ -142,7 +159,7 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   }
   for (int g = 0; g < m.ngeom; g++) {
     const int type = gi[2 * g], body = gi[2 * g + 1];
-    if (type < 0 || type > 3 || body < 0 || body >= m.nbody) { err = "model blob: bad geom"; return MJH_EMODEL; }
+    if (type < 0 || type > 4 || body < 0 || body >= m.nbody) { err = "model blob: bad geom"; return MJH_EMODEL; }
     m.geom_type.push_back(type);
     m.geom_body.push_back(body);
     const double* f = &gf[11 * g];
@@ -157,6 +174,10 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
     if (t1 > t2) { err = "model blob: pair geoms must be ordered by type"; return MJH_EMODEL; }
     if (t1 == GEOM_PLANE && t2 == GEOM_PLANE) { err = "model blob: plane-plane pair"; return MJH_EMODEL; }
     if (t1 == GEOM_BOX && t2 == GEOM_BOX) { err = "box-box pairs are not supported"; return MJH_EUNSUPPORTED; }
+    if (t2 == GEOM_HFIELD && (t1 != GEOM_SPHERE || m.hf_nrow == 0)) {
+      err = "heightfields pair with spheres only (and need the model's heightfield)";
+      return MJH_EUNSUPPORTED;
+    }
     m.pair_g1.push_back(g1);
     m.pair_g2.push_back(g2);
     m.pair_mu.push_back(pf[p]);
@@ -195,7 +216,9 @@ void quat_mat(const double* q, float* R) {
 
 int pair_kind_of(int t1, int t2) {
   if (t1 == GEOM_PLANE) return t2 == GEOM_SPHERE ? PK_PLANE_SPHERE : t2 == GEOM_CAPSULE ? PK_PLANE_CAPSULE : PK_PLANE_BOX;
-  if (t1 == GEOM_SPHERE) return t2 == GEOM_SPHERE ? PK_SPHERE_SPHERE : t2 == GEOM_CAPSULE ? PK_SPHERE_CAPSULE : PK_SPHERE_BOX;
+  if (t1 == GEOM_SPHERE)
+    return t2 == GEOM_SPHERE ? PK_SPHERE_SPHERE : t2 == GEOM_CAPSULE ? PK_SPHERE_CAPSULE
+           : t2 == GEOM_HFIELD ? PK_SPHERE_HFIELD : PK_SPHERE_BOX;
   return t2 == GEOM_CAPSULE ? PK_CAPSULE_CAPSULE : PK_CAPSULE_BOX;
 }
 int pair_slots(int kind) {
@@ -227,6 +250,9 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   d.ngeom = h.ngeom; d.npair = h.npair; d.nconmax = h.nconmax;
   d.iterations = h.iterations;
   d.implicit = h.integrator;
+  d.hf_nrow = h.hf_nrow;
+  d.hf_ncol = h.hf_ncol;
+  for (int k = 0; k < 3; k++) d.hf_size[k] = (float)h.hf_size[k];
   if (h.nv > kMaxNv) { err = "nv > 64 is not supported"; return MJH_EUNSUPPORTED; }
   // addresses
   std::vector<int> body_jntadr(h.nbody, 0), body_jntnum(h.nbody, 0), body_dofadr(h.nbody, 0),
@@ -427,6 +453,8 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   pk.add(ahi, &d.act_hi);
   pk.add(aqd, &d.act_qdef);
   pk.add(q0, &d.qpos0);
+  std::vector<float> hf = fv(h.hf_data);
+  pk.add(hf, &d.hf_data);
   pk.add(invw, const_cast<const float**>(&d.body_invweight));
   std::vector<float> dof_invw(h.nv, 0.f);
   pk.add(dof_invw, const_cast<const float**>(&d.dof_invweight));

@@ -632,6 +632,106 @@ DEV float sphere_sphere(const float* c1, float r1, const float* c2, float r2, fl
   return dist;
 }
 
+// Nearest point q of triangle (a, b, c) to p: p's projection onto the triangle's plane
+// when its barycentric weights are all >= 0, else the nearest edge point.  nrm receives
+// the (unnormalised) normal (b - a) x (c - a).
+DEV void tri_nearest(const float* a, const float* b, const float* c, const float* p, float* q,
+                     float* nrm) {
+  const float ab[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+  const float ac[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+  cross3(ab, ac, nrm);
+  const float nn = dot3(nrm, nrm);
+  const float ap[3] = {p[0] - a[0], p[1] - a[1], p[2] - a[2]};
+  const float hgt = dot3(ap, nrm) / nn;
+  const float pp[3] = {p[0] - hgt * nrm[0], p[1] - hgt * nrm[1], p[2] - hgt * nrm[2]};
+  const float* v[3] = {a, b, c};
+  bool inside = true;
+  for (int k = 0; k < 3; k++) {
+    const float* e0 = v[k == 2 ? 0 : k + 1];
+    const float* e1 = v[k == 0 ? 2 : k - 1];
+    const float d0[3] = {e0[0] - pp[0], e0[1] - pp[1], e0[2] - pp[2]};
+    const float d1[3] = {e1[0] - pp[0], e1[1] - pp[1], e1[2] - pp[2]};
+    float cr[3];
+    cross3(d0, d1, cr);
+    inside = inside && dot3(cr, nrm) >= 0.f;
+  }
+  if (inside) {
+    q[0] = pp[0]; q[1] = pp[1]; q[2] = pp[2];
+    return;
+  }
+  float best = INFINITY;
+  for (int e = 0; e < 3; e++) {
+    const float* s0 = v[e];
+    const float* s1 = v[e == 2 ? 0 : e + 1];
+    const float u[3] = {s1[0] - s0[0], s1[1] - s0[1], s1[2] - s0[2]};
+    const float w[3] = {p[0] - s0[0], p[1] - s0[1], p[2] - s0[2]};
+    const float tt = fminf(fmaxf(dot3(w, u) / dot3(u, u), 0.f), 1.f);
+    const float x[3] = {s0[0] + tt * u[0], s0[1] + tt * u[1], s0[2] + tt * u[2]};
+    const float dx[3] = {p[0] - x[0], p[1] - x[1], p[2] - x[2]};
+    const float dd = dot3(dx, dx);
+    if (dd < best) { best = dd; q[0] = x[0]; q[1] = x[1]; q[2] = x[2]; }
+  }
+}
+
+// Sphere (geom 1: centre c, radius r) against the heightfield (geom 2 at xg, Rg): the
+// nearest point of the triangles of the grid cells under the sphere's footprint (the
+// first in cell and triangle order on ties); signed by the side of that triangle's
+// plane.  The normal points from the sphere into the surface; pos is midway between
+// the surfaces.  +inf when the footprint misses the grid.
+DEV float sphere_hfield(const DevModel& m, const float* xg, const float* Rg, const float* c,
+                        float r, float* pos, float* n) {
+  const int nr = m.hf_nrow, nc = m.hf_ncol;
+  const float sx = m.hf_size[0], sy = m.hf_size[1], sz = m.hf_size[2];
+  const float dx = 2.f * sx / (nc - 1), dy = 2.f * sy / (nr - 1);
+  const float rel[3] = {c[0] - xg[0], c[1] - xg[1], c[2] - xg[2]};
+  const float cl[3] = {Rg[0] * rel[0] + Rg[3] * rel[1] + Rg[6] * rel[2],
+                       Rg[1] * rel[0] + Rg[4] * rel[1] + Rg[7] * rel[2],
+                       Rg[2] * rel[0] + Rg[5] * rel[1] + Rg[8] * rel[2]};
+  // cell range of the footprint, clamped before the conversion to int
+  auto cell = [](float x, int hi) { return (int)floorf(fminf(fmaxf(x, -1.f), (float)hi)); };
+  const int j0 = max(0, cell((cl[0] - r + sx) / dx, nc));
+  const int j1 = min(nc - 2, cell((cl[0] + r + sx) / dx, nc));
+  const int i0 = max(0, cell((cl[1] - r + sy) / dy, nr));
+  const int i1 = min(nr - 2, cell((cl[1] + r + sy) / dy, nr));
+  float best = INFINITY, bq[3] = {0.f, 0.f, 0.f}, bn[3] = {0.f, 0.f, 1.f};
+  for (int i = i0; i <= i1; i++)
+    for (int j = j0; j <= j1; j++) {
+      const float x0 = -sx + dx * j, x1 = x0 + dx, y0 = -sy + dy * i, y1 = y0 + dy;
+      const float* hrow = m.hf_data + (size_t)i * nc + j;
+      const float v00[3] = {x0, y0, sz * hrow[0]}, v01[3] = {x1, y0, sz * hrow[1]};
+      const float v10[3] = {x0, y1, sz * hrow[nc]}, v11[3] = {x1, y1, sz * hrow[nc + 1]};
+      for (int k = 0; k < 2; k++) {
+        float q[3], nt[3];
+        if (k == 0) tri_nearest(v00, v01, v11, cl, q, nt);
+        else tri_nearest(v00, v11, v10, cl, q, nt);
+        const float d[3] = {cl[0] - q[0], cl[1] - q[1], cl[2] - q[2]};
+        const float dd = dot3(d, d);
+        if (dd < best) {
+          best = dd;
+          bq[0] = q[0]; bq[1] = q[1]; bq[2] = q[2];
+          bn[0] = nt[0]; bn[1] = nt[1]; bn[2] = nt[2];
+        }
+      }
+    }
+  if (best == INFINITY) return INFINITY;
+  const float L = sqrtf(best);
+  const float d[3] = {cl[0] - bq[0], cl[1] - bq[1], cl[2] - bq[2]};
+  const bool below = dot3(bn, d) < 0.f;
+  float nl[3];
+  if (L > 1e-12f) {
+    const float sg = (below ? 1.f : -1.f) / L;
+    nl[0] = sg * d[0]; nl[1] = sg * d[1]; nl[2] = sg * d[2];
+  } else {
+    const float inv = -1.f / sqrtf(dot3(bn, bn));
+    nl[0] = inv * bn[0]; nl[1] = inv * bn[1]; nl[2] = inv * bn[2];
+  }
+  float qw[3];
+  mv3(Rg, nl, n);
+  mv3(Rg, bq, qw);
+  for (int k = 0; k < 3; k++) pos[k] = 0.5f * (c[k] + r * n[k] + qw[k] + xg[k]);
+  return (below ? -L : L) - r;
+}
+
 // Evaluate candidate `sub` of pair `p` (kind-specific); returns dist and fills pos and
 // normal.  For capsule-box the parameter t selects the segment point.
 DEV float pair_contact(const DevModel& m, const float* W, int p, int sub, float tpar, float* pos,
@@ -678,6 +778,8 @@ DEV float pair_contact(const DevModel& m, const float* W, int p, int sub, float 
       float q[3] = {a[0] + t * u[0], a[1] + t * u[1], a[2] + t * u[2]};
       return sphere_sphere(x1, s1[0], q, s2[0], pos, n);
     }
+    case PK_SPHERE_HFIELD:
+      return sphere_hfield(m, x2, R2, x1, s1[0], pos, n);
     case PK_SPHERE_BOX: {
       float nb[3];
       float sd = box_point(x2, R2, s2, x1, nb);

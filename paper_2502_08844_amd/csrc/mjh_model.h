@@ -10,7 +10,8 @@
 namespace mjh {
 
 enum JointType : int { JNT_FREE = 0, JNT_SLIDE = 1, JNT_HINGE = 2 };
-enum GeomType : int { GEOM_PLANE = 0, GEOM_SPHERE = 1, GEOM_CAPSULE = 2, GEOM_BOX = 3 };
+enum GeomType : int { GEOM_PLANE = 0, GEOM_SPHERE = 1, GEOM_CAPSULE = 2, GEOM_BOX = 3,
+                      GEOM_HFIELD = 4 };
 enum ActType : int { ACT_MOTOR = 0, ACT_PD = 1 };
 // pair kinds (type(geom1) <= type(geom2)) and their candidate contact slots
 enum PairKind : int {
@@ -21,7 +22,8 @@ enum PairKind : int {
   PK_SPHERE_CAPSULE = 4, // 1
   PK_SPHERE_BOX = 5,     // 1
   PK_CAPSULE_CAPSULE = 6,// 1
-  PK_CAPSULE_BOX = 7     // 4: ends + ends of the minimiser interval, at most 2 kept
+  PK_CAPSULE_BOX = 7,    // 4: ends + ends of the minimiser interval, at most 2 kept
+  PK_SPHERE_HFIELD = 8   // 1: nearest point of the heightfield's triangles
 };
 
 constexpr int kMaxNv = 64;      // ancestor masks are 64-bit
@@ -34,6 +36,8 @@ struct DevModel {
   int nbody, njnt, nq, nv, nu, ngeom, npair, ncand, nconmax, nlim, nfric, neq, nrowmax;
   int iterations, nlevel, nmpair, ntri;
   int implicit;  // 1: joint damping and PD velocity gains integrated implicitly
+  int hf_nrow, hf_ncol;  // heightfield grid (0 without one)
+  float hf_size[3];      // half extents x, y and the height scale
   // ---- constants
   float dt, K, B;                       // soft-constraint stiffness/damping
   float dmin, dmax, width, mid, power;  // impedance (solimp)
@@ -95,6 +99,7 @@ struct DevModel {
   const float* act_hi;
   const float* act_qdef;
   const float* qpos0;
+  const float* hf_data;       // [hf_nrow][hf_ncol] elevations in [0, 1]
   const float* lim_lo;        // [nlim] range of each limited joint
   const float* lim_hi;
   const float* fric_loss;     // [nfric] friction-loss bound of each such dof
