@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--no-limits", action="store_true",
                     help="skip the joint-limit, friction-loss, equality, implicit-damping and "
                          "rough-terrain workloads (quadruped variants)")
+    ap.add_argument("--no-env", action="store_true",
+                    help="skip the fused joystick env step measurement")
     ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a reference "
@@ -215,6 +217,46 @@ def constraint_compare(ctx, seed, kind, what, nw=8192, nstep=1000, reps=3):
             "nrowmax": m.nrowmax,
             "launch": list(w.batch.get_launch(0)),
             "status_nonzero_worlds": int((status != 0).sum())}
+
+
+def env_compare(ctx, seed, nw=8192, nenv=200, nsub=5, reps=3):
+    """The joystick env step fused around the physics (observation, reward, termination
+    and reset in the same kernel): 8192 quadruped worlds x 200 env steps of 5 physics
+    steps (a 0.02 s control period at dt 0.004), one launch, actions U(-0.5, 0.5) drawn
+    per env step and resident in HBM with the outputs."""
+    import torch
+    from paper_2502_08844_amd import mjh
+    from paper_2502_08844_amd.synth import inputs, robots
+    stream = torch.cuda.current_stream()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    m = robots.WORKLOADS["quadruped"]()
+    qp, qv = inputs.initial_state("quadruped", m, nw, seed=seed)
+    w = mjh.World(ctx, ctx.model_upload(m), nw, qpos=qp, qvel=qv)
+    f = dict(device="cuda", dtype=torch.float32)
+    act = (torch.rand((nenv, nw, m.nu), device="cuda", generator=gen) - 0.5).contiguous()
+    cmd = torch.stack([2 * torch.rand(nw, device="cuda", generator=gen) - 1,
+                       torch.rand(nw, device="cuda", generator=gen) - 0.5,
+                       2 * torch.rand(nw, device="cuda", generator=gen) - 1], 1).contiguous()
+    q0, v0 = w.qpos.clone(), w.qvel.clone()
+    last = torch.zeros(nw, m.nu, **f)
+    obs = torch.zeros(nenv, nw, 12 + 3 * m.nu, **f)
+    rew = torch.zeros(nenv, nw, **f)
+    done = torch.zeros(nenv, nw, dtype=torch.int32, device="cuda")
+
+    def run():
+        w.qpos.copy_(q0); w.qvel.copy_(v0); w.qacc_ws.zero_(); last.zero_()
+        w.batch.env_step(nsub, act, cmd, q0, v0, last, obs, rew, done, stream)
+    run()
+    ms = timed(run, stream, reps)
+    return {"workload": f"quadruped joystick env, {nw} worlds x {nenv} env steps of {nsub} "
+                        "physics steps, one launch",
+            "env_steps_per_s": round(nw * nenv / (ms * 1e-3), 1),
+            "world_steps_per_s": round(nw * nenv * nsub / (ms * 1e-3), 1),
+            "nobs": 12 + 3 * m.nu, "launch": list(w.batch.get_launch(0)),
+            "terminations": int(done.sum().item()),
+            "mean_reward": round(float(rew.mean().item()), 4),
+            "status_nonzero_worlds": int((w.status != 0).sum().item())}
 
 
 def hetero_compare(ctx, seed, nstep=500, reps=3):
@@ -393,6 +435,8 @@ def main():
         out["rollout"] = rollout_compare(ctx, args.seed)
     if not args.no_hetero:
         out["hetero"] = hetero_compare(ctx, args.seed)
+    if not args.no_env:
+        out["env_step"] = env_compare(ctx, args.seed)
     if not args.no_limits:
         out["limits"] = constraint_compare(ctx, args.seed, "quadruped_limits",
                                            "limited hinges (default angle +- 0.15 rad)")

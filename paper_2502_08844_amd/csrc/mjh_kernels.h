@@ -21,4 +21,22 @@ hipError_t set_step_lds_limit(size_t bytes);
 // Compute body_invweight of a freshly uploaded model (one work-group).
 hipError_t launch_invweight(const DevModel& m, hipStream_t stream);
 
+// Joystick environment steps of a single-group batch (the step kernel's tasks).
+struct EnvArgs {
+  int nenv, nsub, nobs;
+  const float* action;      // [nenv][nworld][nu]
+  const float* command;     // [nworld][3]
+  const float* reset_qpos;  // [nworld][nq]
+  const float* reset_qvel;  // [nworld][nv]
+  float* last_action;       // [nworld][nu], read and updated
+  float* obs;               // [nenv][nworld][nobs]
+  float* reward;            // [nenv][nworld]
+  int* done;                // [nenv][nworld]
+};
+// ap_words: LDS words after the pair table for the teams' previous actions
+hipError_t launch_env(const DevGroup* groups, const DevTask* tasks, int ntask, const EnvArgs& E,
+                      int block, size_t lds_bytes, int tab_words, int ap_words,
+                      hipStream_t stream);
+hipError_t set_env_lds_limit(size_t bytes);
+
 }  // namespace mjh

@@ -84,6 +84,132 @@ mjh_step_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__
   run_worlds(G, W, world, nstep, lane, T, (const unsigned char*)lds);
 }
 
+// ------------------------------------------------------------- environment step
+// The joystick locomotion task around the physics step (the paper's locomotion
+// appendix): per env step, `nsub` physics steps with the action held as the position
+// actuators' targets, then from the new state
+//   obs    = [g_b, v_b, w_b, q - q_default, qdot, a_{t-1}, cmd]  (b: root body frame;
+//            g the gravity direction, v the root's world linear velocity rotated in)
+//   reward = max(0, 1.0 exp(-|cmd_xy - v_xy|^2/0.25) + 0.5 exp(-(cmd_wz - w_z)^2/0.25)
+//            - 2 v_z^2 - 0.05 |w_xy|^2 - 5 |g_xy|^2 - 2e-4 |tau|^2 - 0.1 |q - q_default|^2
+//            - 0.01 |a_t - a_{t-1}|^2 - done)          (tau: PD torques at the new state)
+//   done   = the root's z axis points downwards (inverted).
+// A terminated world restarts from its reset state with a zero warm start and a zero
+// previous action.  The root is a free joint; actuator k drives dof 6 + k.
+constexpr float kEnvKv = 1.f, kEnvSv = 0.25f, kEnvKw = 0.5f, kEnvSw = 0.25f;
+constexpr float kEnvLinZ = -2.f, kEnvAngXY = -0.05f, kEnvOri = -5.f, kEnvTau = -2e-4f;
+constexpr float kEnvQ = -0.1f, kEnvRate = -0.01f, kEnvTerm = -1.f;
+
+__device__ void env_worlds(const DevGroup& G, const EnvArgs& E, float* W, float* aprev, int world,
+                           int lane, int T, const unsigned char* tab) {
+  const DevModel& m = G.m;
+  const Team t{lane, T, tab};
+  world_init(m, W, t);
+  const int nq = m.nq, nv = m.nv, nu = m.nu;
+  const size_t w = (size_t)world;
+  float* qpos = W + m.o_qpos;
+  float* qvel = W + m.o_qvel;
+  float* qacc = W + m.o_qacc;
+  for (int i = lane; i < nq; i += T) qpos[i] = G.qpos[w * nq + i];
+  for (int i = lane; i < nv; i += T) {
+    qvel[i] = G.qvel[w * nv + i];
+    qacc[i] = G.qacc[w * nv + i];
+  }
+  t.sync();
+  for (int k = lane; k < nu; k += T) aprev[k] = E.last_action[w * nu + k];
+  t.sync();
+  int status = 0;
+  const float* cmd = E.command + w * 3;
+  for (int e = 0; e < E.nenv; e++) {
+    const float* u = E.action + ((size_t)e * G.nworld + w) * nu;
+    for (int s = 0; s < E.nsub; s++) {
+      world_step(m, W, t, u, status, m.iterations);
+      integrate(m, W, t, status);
+    }
+    // root rotation from its quaternion (every lane)
+    float qw = qpos[3], qx = qpos[4], qy = qpos[5], qz = qpos[6];
+    const float qn = 1.f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw *= qn; qx *= qn; qy *= qn; qz *= qn;
+    const float R[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz),
+                        2.f * (qx * qz + qw * qy), 2.f * (qx * qy + qw * qz),
+                        1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
+                        2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx),
+                        1.f - 2.f * (qx * qx + qy * qy)};
+    float gb[3], vb[3];
+    for (int k = 0; k < 3; k++) {
+      gb[k] = -R[6 + k];
+      vb[k] = R[k] * qvel[0] + R[3 + k] * qvel[1] + R[6 + k] * qvel[2];
+    }
+    const bool done = R[8] < 0.f;
+    // per-actuator terms, one lane each
+    float jt = 0.f;
+    for (int k = lane; k < nu; k += T) {
+      const float lo = m.act_lo[k], hi = m.act_hi[k];
+      const float uk = fminf(fmaxf(u[k], lo), hi);
+      const float q = qpos[7 + k], qd = qvel[6 + k];
+      const float tau = m.act_kp[k] * (m.act_qdef[k] + m.act_gear[k] * uk - q) - m.act_kd[k] * qd;
+      const float dq = q - m.act_qdef[k], da = u[k] - aprev[k];
+      jt += kEnvTau * tau * tau + kEnvQ * dq * dq + kEnvRate * da * da;
+    }
+    jt = t.sum(jt);
+    float* ob = E.obs + ((size_t)e * G.nworld + w) * E.nobs;
+    for (int i = lane; i < E.nobs; i += T) {
+      float v;
+      if (i < 3) v = gb[i];
+      else if (i < 6) v = vb[i - 3];
+      else if (i < 9) v = qvel[i - 3];
+      else if (i < 9 + nu) v = qpos[7 + (i - 9)] - m.act_qdef[i - 9];
+      else if (i < 9 + 2 * nu) v = qvel[6 + (i - 9 - nu)];
+      else if (i < 9 + 3 * nu) v = aprev[i - 9 - 2 * nu];
+      else v = cmd[i - 9 - 3 * nu];
+      ob[i] = v;
+    }
+    if (lane == 0) {
+      const float ex = cmd[0] - vb[0], ey = cmd[1] - vb[1], ez = cmd[2] - qvel[5];
+      float r = kEnvKv * expf(-(ex * ex + ey * ey) / kEnvSv) + kEnvKw * expf(-ez * ez / kEnvSw) +
+                kEnvLinZ * vb[2] * vb[2] + kEnvAngXY * (qvel[3] * qvel[3] + qvel[4] * qvel[4]) +
+                kEnvOri * (gb[0] * gb[0] + gb[1] * gb[1]) + jt + (done ? kEnvTerm : 0.f);
+      E.reward[(size_t)e * G.nworld + w] = fmaxf(r, 0.f);
+      E.done[(size_t)e * G.nworld + w] = done ? 1 : 0;
+    }
+    t.sync();  // every lane has read aprev and the state
+    for (int k = lane; k < nu; k += T) aprev[k] = done ? 0.f : u[k];
+    if (done) {
+      for (int i = lane; i < nq; i += T) qpos[i] = E.reset_qpos[w * nq + i];
+      for (int i = lane; i < nv; i += T) {
+        qvel[i] = E.reset_qvel[w * nv + i];
+        qacc[i] = 0.f;
+      }
+    }
+    t.sync();
+  }
+  for (int i = lane; i < nq; i += T) G.qpos[w * nq + i] = qpos[i];
+  for (int i = lane; i < nv; i += T) {
+    G.qvel[w * nv + i] = qvel[i];
+    G.qacc[w * nv + i] = qacc[i];
+  }
+  for (int k = lane; k < nu; k += T) E.last_action[w * nu + k] = aprev[k];
+  status = t.ior(status);
+  if (lane == 0 && G.status) G.status[w] = status;
+}
+
+// LDS: the pair table, then `ap_words` holding each team's previous action (nu words a
+// team), then the worlds' working sets at the usual stride.
+__global__ void __launch_bounds__(kMaxBlock, 4)
+mjh_env_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__ tasks,
+               EnvArgs E, int tab_words, int ap_words) {
+  extern __shared__ float lds[];
+  const DevTask tk = tasks[blockIdx.x];
+  const DevGroup& G = groups[tk.group];
+  load_pair_table(G.m, (unsigned*)lds);
+  const int T = G.team;
+  const int team = threadIdx.x / T;
+  if (team >= tk.nw) return;
+  float* ap = lds + tab_words + team * G.m.nu;
+  float* W = lds + tab_words + ap_words + (size_t)team * G.m.lds_words;
+  env_worlds(G, E, W, ap, tk.w0 + team, threadIdx.x - team * T, T, (const unsigned char*)lds);
+}
+
 // Translational inverse weight of every body at qpos0:
 //   w(b) = trace(J_com(b) M^-1 J_com(b)^T) / 3,
 // and (M^-1)_kk of every dof k, one work-group of 64 lanes evaluating the model once.
@@ -153,6 +279,20 @@ hipError_t launch_step(const DevGroup* groups, const DevTask* tasks, int ntask, 
 
 hipError_t set_step_lds_limit(size_t bytes) {
   return hipFuncSetAttribute((const void*)mjh_step_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_env(const DevGroup* groups, const DevTask* tasks, int ntask, const EnvArgs& E,
+                      int block, size_t lds_bytes, int tab_words, int ap_words,
+                      hipStream_t stream) {
+  if (ntask <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mjh_env_kernel, dim3(ntask), dim3(block), lds_bytes, stream, groups, tasks,
+                     E, tab_words, ap_words);
+  return hipGetLastError();
+}
+
+hipError_t set_env_lds_limit(size_t bytes) {
+  return hipFuncSetAttribute((const void*)mjh_env_kernel,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 

@@ -1,0 +1,155 @@
+"""GPU parity of the fused joystick env step (observation, reward, termination and reset
+around the physics step) against the reference env in float64.
+
+Checks, on the quadruped from contact-rich states with a share of inverted worlds:
+* the physics inside the env step is the plain step's (same controls, nsub steps);
+* obs, reward and done from that post-physics state match the reference's formulas
+  evaluated in float64 on the same float32 state (|d| <= 5e-6 (1 + |x|));
+* done worlds restart from their reset state with a zero warm start and previous
+  action, the others keep the new state and remember the action;
+* several env steps in one launch give the outputs of as many single launches;
+* end to end against the reference env step from the same float32 state (FP32 against
+  FP64 physics over nsub steps): done identical, obs within 1e-3 (1 + |x|) for the
+  median world;
+* models without a free root and per-dof position actuators are rejected.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import env as renv
+from paper_2502_08844_amd.synth import inputs, robots
+from tests.gpu_util import gpu_ctx, run_gpu, workload
+
+pytestmark = pytest.mark.gpu
+
+OUT_TOL = 5e-6
+NSUB = 5
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return gpu_ctx()
+
+
+def _scene(ctx, mjh, nw, seed):
+    """Contact-rich quadruped states (50 random-target steps), every fifth world turned
+    upside down 0.45 m up; commands and actions drawn per world."""
+    m, qp, qv, u = workload("quadruped", nw, 50, seed=seed)
+    r = run_gpu(ctx, mjh, m, qp, qv, None, u, 50, contacts=False)
+    qp, qv, ws = r["qpos"], r["qvel"], r["qacc"]
+    inv = np.arange(nw) % 5 == 3
+    qp[inv, 2] = 0.45
+    qp[inv, 3:7] = (0.0, 1.0, 0.0, 0.0)
+    rng = np.random.default_rng(seed + 100)
+    cmd = np.stack([rng.uniform(-1, 1, nw), rng.uniform(-0.5, 0.5, nw),
+                    rng.uniform(-1, 1, nw)], 1)
+    reset_q, reset_v = inputs.initial_state("quadruped", m, nw, seed=seed + 1)
+    prev = rng.uniform(-0.5, 0.5, size=(nw, m.nu))
+    return m, inputs.f32(qp), inputs.f32(qv), inputs.f32(ws), inputs.f32(cmd), reset_q, \
+        reset_v, inputs.f32(prev), inv
+
+
+def _dev(x, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda").contiguous()
+
+
+def _env_gpu(ctx, mjh, m, qp, qv, ws, acts, cmd, reset_q, reset_v, prev, nsub=NSUB):
+    nenv, nw = acts.shape[:2]
+    w = mjh.World(ctx, m, nw, qpos=qp, qvel=qv)
+    w.qacc_ws.copy_(_dev(ws))
+    la = _dev(prev)
+    obs = torch.zeros(nenv, nw, 12 + 3 * m.nu, device="cuda")
+    rew = torch.zeros(nenv, nw, device="cuda")
+    done = torch.zeros(nenv, nw, dtype=torch.int32, device="cuda")
+    w.batch.env_step(nsub, _dev(acts), _dev(cmd), _dev(reset_q), _dev(reset_v), la, obs, rew,
+                     done)
+    torch.cuda.synchronize()
+    f = lambda t: t.cpu().double().numpy()
+    return dict(obs=f(obs), reward=f(rew), done=done.cpu().numpy().astype(bool), qpos=f(w.qpos),
+                qvel=f(w.qvel), qacc=f(w.qacc_ws), last_action=f(la), status=w.status.cpu().numpy())
+
+
+def test_env_step_outputs_and_resets(lib):
+    mjh, ctx = lib
+    nw = 240
+    print(f"[gpu] env step quadruped nw={nw} nsub={NSUB}", flush=True)
+    m, qp, qv, ws, cmd, rq, rv, prev, inv = _scene(ctx, mjh, nw, seed=3)
+    act = inputs.f32(np.random.default_rng(7).uniform(-0.6, 0.6, size=(1, nw, m.nu)))
+    g = _env_gpu(ctx, mjh, m, qp, qv, ws, act, cmd, rq, rv, prev)
+    # the plain physics step with the action held for nsub steps
+    p = run_gpu(ctx, mjh, m, qp, qv, ws, np.repeat(act, NSUB, 0), NSUB, contacts=False)
+    assert np.all(g["status"] & 1 == 0) and np.all(p["status"] & 1 == 0)
+    done_ref = np.array([renv.reward_done(m, p["qpos"][w], p["qvel"][w], act[0, w], prev[w],
+                                          cmd[w])[1] for w in range(nw)])
+    assert np.array_equal(g["done"][0], done_ref)
+    assert np.array_equal(done_ref, inv)  # exactly the inverted worlds terminate
+    keep = ~done_ref
+    dq = np.abs(g["qpos"][keep] - p["qpos"][keep]).max()
+    dv = np.abs(g["qvel"][keep] - p["qvel"][keep]).max() / max(np.abs(p["qvel"]).max(), 1.0)
+    print(f"[gpu] env physics vs plain step: |d qpos| {dq:.1e} |d qvel|/max {dv:.1e}", flush=True)
+    assert dq <= 1e-5 and dv <= 1e-5
+    # outputs from the post-physics state against the float64 formulas
+    eo, er = 0.0, 0.0
+    for w in range(nw):
+        o_ref = renv.observe(m, p["qpos"][w], p["qvel"][w], prev[w], cmd[w])
+        r_ref, _ = renv.reward_done(m, p["qpos"][w], p["qvel"][w], act[0, w], prev[w], cmd[w])
+        eo = max(eo, (np.abs(g["obs"][0, w] - o_ref) / (1 + np.abs(o_ref))).max())
+        er = max(er, abs(g["reward"][0, w] - r_ref) / (1 + abs(r_ref)))
+    print(f"[gpu] env outputs: obs err {eo:.1e} reward err {er:.1e}", flush=True)
+    assert eo <= OUT_TOL and er <= OUT_TOL
+    assert np.all(g["reward"] >= 0)
+    # resets and the remembered action
+    np.testing.assert_array_equal(g["qpos"][inv], rq[inv].astype(np.float32))
+    np.testing.assert_array_equal(g["qvel"][inv], rv[inv].astype(np.float32))
+    assert np.all(g["qacc"][inv] == 0) and np.all(g["last_action"][inv] == 0)
+    np.testing.assert_array_equal(g["last_action"][keep], act[0, keep].astype(np.float32))
+
+
+def test_multi_env_steps_one_launch(lib):
+    mjh, ctx = lib
+    nw, nenv = 96, 3
+    print(f"[gpu] env steps nenv={nenv} in one launch vs {nenv} launches", flush=True)
+    m, qp, qv, ws, cmd, rq, rv, prev, inv = _scene(ctx, mjh, nw, seed=5)
+    acts = inputs.f32(np.random.default_rng(9).uniform(-0.6, 0.6, size=(nenv, nw, m.nu)))
+    one = _env_gpu(ctx, mjh, m, qp, qv, ws, acts, cmd, rq, rv, prev)
+    s = (qp, qv, ws, prev)
+    for e in range(nenv):
+        g = _env_gpu(ctx, mjh, m, *s[:3], acts[e:e + 1], cmd, rq, rv, s[3])
+        for k in ("obs", "reward"):
+            np.testing.assert_allclose(one[k][e], g[k][0], rtol=1e-6, atol=1e-7)
+        assert np.array_equal(one["done"][e], g["done"][0])
+        s = (g["qpos"], g["qvel"], g["qacc"], g["last_action"])
+    np.testing.assert_allclose(one["qpos"], s[0], rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(one["last_action"], s[3], rtol=0, atol=0)
+    assert one["done"][0].sum() == inv.sum()
+
+
+def test_env_step_against_reference_env(lib):
+    mjh, ctx = lib
+    nw = 64
+    print(f"[gpu] env step end to end vs reference nw={nw}", flush=True)
+    m, qp, qv, ws, cmd, rq, rv, prev, inv = _scene(ctx, mjh, nw, seed=11)
+    act = inputs.f32(np.random.default_rng(13).uniform(-0.6, 0.6, size=(1, nw, m.nu)))
+    g = _env_gpu(ctx, mjh, m, qp, qv, ws, act, cmd, rq, rv, prev)
+    o = oracle.Oracle(m)
+    obs, rew, done, (q, v, w_, pa) = renv.env_step(o, m, qp, qv, ws, prev, act[0], cmd, rq, rv,
+                                                  NSUB)
+    assert np.array_equal(g["done"][0], done)
+    err = (np.abs(g["obs"][0] - obs) / (1 + np.abs(obs))).max(1)
+    print(f"[gpu] env obs vs FP64 env: median {np.median(err):.1e} max {err.max():.1e}",
+          flush=True)
+    assert np.median(err) <= 1e-3
+    np.testing.assert_array_equal(g["last_action"], pa.astype(np.float32))
+
+
+def test_env_step_rejects_other_models(lib):
+    mjh, ctx = lib
+    m = robots.hinge_chain(n=3)
+    w = mjh.World(ctx, m, 4)
+    z = lambda *s: torch.zeros(*s, device="cuda")
+    with pytest.raises(mjh.MjhError):
+        w.batch.env_step(1, z(1, 4, m.nu), z(4, 3), z(4, m.nq), z(4, m.nv), z(4, m.nu),
+                         z(1, 4, 12 + 3 * m.nu), z(1, 4),
+                         torch.zeros(1, 4, dtype=torch.int32, device="cuda"))
