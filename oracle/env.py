@@ -26,8 +26,25 @@ the robot inverts):
   zero warm start and a zero previous action; the outputs of that env step are those
   of the state it terminated in.
 * the model's root is a free joint and actuator k drives dof 6 + k.
+
+Domain randomisation (the paper's locomotion appendix: sensor noise; link centre of
+mass, reflected inertia and joint calibration offsets; ground friction and payload
+mass; the PD gains), one record of 8 + 2 n values per world:
+  [0] friction scale: every contact pair's coefficient times this;
+  [1] payload mass added to the root body at its centre of mass (its rotational
+      inertia about the centre of mass is unchanged);
+  [2:5] shift of the root body's centre of mass, in the root body's frame;
+  [5], [6] scales of the position actuators' kp and kd;  [7] unused;
+  [8:8+n] joint calibration offsets: the encoder reads q + delta, so the PD law and
+      the observation see q + delta (equivalently q_default - delta);
+  [8+n:8+2n] the reflected inertia (armature) of dof 6 + k, replacing the model's.
+The rows' regularisers keep the nominal model's inverse weights (computed once at
+qpos0), as a compiled model's constants are not recomputed when its parameters are
+varied.  Sensor noise is added to the observation as given (one value per entry).
 """
 from __future__ import annotations
+
+import copy
 
 import numpy as np
 
@@ -55,13 +72,14 @@ def pd_torques(m, qpos, qvel, action):
     return tau
 
 
-def observe(m, qpos, qvel, prev_action, cmd):
+def observe(m, qpos, qvel, prev_action, cmd, noise=None):
     R = quat_mat(qpos[3:7])
     g = R.T @ np.array([0.0, 0.0, -1.0])
     v = R.T @ qvel[0:3]  # free-joint qvel: world linear velocity of the body origin
     w = qvel[3:6]        # and the body-frame angular velocity
     qdef = np.array([a.qdefault for a in m.actuators])
-    return np.concatenate([g, v, w, qpos[7:] - qdef, qvel[6:], prev_action, cmd])
+    obs = np.concatenate([g, v, w, qpos[7:] - qdef, qvel[6:], prev_action, cmd])
+    return obs if noise is None else obs + noise
 
 
 def reward_done(m, qpos, qvel, action, prev_action, cmd):
@@ -81,15 +99,28 @@ def reward_done(m, qpos, qvel, action, prev_action, cmd):
 
 
 def env_step(o, m, qpos, qvel, qacc_ws, prev_action, action, cmd, reset_qpos, reset_qvel,
-             nsub, mode=0):
+             nsub, mode=0, dr=None, noise=None):
     """One env step of every world (arrays [nworld, ...]); returns the outputs and the
-    next (qpos, qvel, qacc_ws, prev_action) after resets."""
+    next (qpos, qvel, qacc_ws, prev_action) after resets.  dr: per-world randomisation
+    records [nworld, 8 + 2 nu] or None; noise: observation noise [nworld, nobs] or None."""
     nw = qpos.shape[0]
     u = np.repeat(np.asarray(action, dtype=np.float64)[None], nsub, axis=0)
-    r = o.step(qpos.copy(), qvel.copy(), qacc_ws.copy(), u, nstep=nsub, mode=mode, nthreads=8)
-    q, v, ws = r["qpos"], r["qvel"], r["qacc_ws"]
-    obs = np.stack([observe(m, q[w], v[w], prev_action[w], cmd[w]) for w in range(nw)])
-    rd = [reward_done(m, q[w], v[w], action[w], prev_action[w], cmd[w]) for w in range(nw)]
+    if dr is None:
+        ms = [m] * nw
+        r = o.step(qpos.copy(), qvel.copy(), qacc_ws.copy(), u, nstep=nsub, mode=mode,
+                   nthreads=8)
+        q, v, ws = r["qpos"], r["qvel"], r["qacc_ws"]
+    else:
+        ms = [randomized_model(m, dr[w]) for w in range(nw)]
+        q, v, ws = np.zeros_like(qpos), np.zeros_like(qvel), np.zeros_like(qacc_ws)
+        for w in range(nw):
+            ow = randomized_oracle(o, m, dr[w])
+            r = ow.step(qpos[w:w + 1].copy(), qvel[w:w + 1].copy(), qacc_ws[w:w + 1].copy(),
+                        u[:, w:w + 1], nstep=nsub, mode=mode)
+            q[w], v[w], ws[w] = r["qpos"][0], r["qvel"][0], r["qacc_ws"][0]
+    obs = np.stack([observe(ms[w], q[w], v[w], prev_action[w], cmd[w],
+                            None if noise is None else noise[w]) for w in range(nw)])
+    rd = [reward_done(ms[w], q[w], v[w], action[w], prev_action[w], cmd[w]) for w in range(nw)]
     rew = np.array([x[0] for x in rd])
     done = np.array([x[1] for x in rd])
     nxt_prev = np.where(done[:, None], 0.0, action)
@@ -97,3 +128,43 @@ def env_step(o, m, qpos, qvel, qacc_ws, prev_action, action, cmd, reset_qpos, re
     v = np.where(done[:, None], reset_qvel, v)
     ws = np.where(done[:, None], 0.0, ws)
     return obs, rew, done, (q, v, ws, nxt_prev)
+
+
+DR_HEAD = 8
+
+
+def dr_identity(m):
+    """The record that leaves the model as it is."""
+    rec = np.zeros(DR_HEAD + 2 * m.nu)
+    rec[0] = rec[5] = rec[6] = 1.0
+    dadr = m.jnt_dofadr()
+    for k, a in enumerate(m.actuators):
+        j = a.joint
+        rec[DR_HEAD + m.nu + k] = m.joints[j].armature
+        assert dadr[j] == 6 + k
+    return rec
+
+
+def randomized_model(m, rec):
+    """A copy of the model with one world's randomised parameters (record above)."""
+    rec = np.asarray(rec, dtype=np.float64)
+    n = m.nu
+    assert rec.shape == (DR_HEAD + 2 * n,)
+    r = copy.deepcopy(m)
+    r.pairs = [(g1, g2, mu * rec[0]) for g1, g2, mu in r.pairs]
+    root = r.bodies[r.joints[0].body]
+    root.mass = root.mass + rec[1]
+    root.ipos = tuple(np.asarray(root.ipos, dtype=np.float64) + rec[2:5])
+    for k, a in enumerate(r.actuators):
+        a.kp, a.kd = a.kp * rec[5], a.kd * rec[6]
+        a.qdefault = a.qdefault - rec[DR_HEAD + k]
+        r.joints[a.joint].armature = rec[DR_HEAD + n + k]
+    return r
+
+
+def randomized_oracle(o_nominal, m, rec):
+    """The reference for one world's randomised model, with the nominal inverse weights."""
+    from oracle import Oracle
+    o = Oracle(randomized_model(m, rec))
+    o.set_invweight(o_nominal.body_invweight(), o_nominal.dof_invweight())
+    return o

@@ -1659,6 +1659,15 @@ int mjo_dof_invweight(void* h, double* out) {
   return 0;
 }
 
+// Replace the inverse weights (the A of every row's regulariser).  A model whose
+// parameters differ per world keeps those of its nominal model, computed once at qpos0.
+int mjo_set_invweight(void* h, const double* body, const double* dof) {
+  Model& m = *static_cast<Model*>(h);
+  for (int b = 0; b < m.nbody; b++) m.body_invweight[b] = body[b];
+  for (int k = 0; k < m.nv; k++) m.dof_invweight[k] = dof[k];
+  return 0;
+}
+
 int mjo_dof_parent(void* h, int* out) {
   Model& m = *static_cast<Model*>(h);
   for (int k = 0; k < m.nv; k++) out[k] = m.dof_parent[k];

@@ -52,6 +52,7 @@ def _load():
         lib.mjo_body_invweight.argtypes = [P, D]
         lib.mjo_dof_invweight.argtypes = [P, D]
         lib.mjo_dof_parent.argtypes = [P, I]
+        lib.mjo_set_invweight.argtypes = [P, D, D]
         lib.mjo_step.argtypes = [P, C.c_int, C.c_int, D, D, D, D, C.c_int, C.c_int, D, D, I,
                                  I, D]
         lib.mjo_forward.argtypes = [P, D, D, D, D, C.c_int] + [D] * 12 + [I, D, I, D, D, D,
@@ -124,6 +125,11 @@ class Oracle:
         out = np.zeros(self.nv)
         self._lib.mjo_dof_invweight(self._h, _d(out))
         return out
+
+    def set_invweight(self, body, dof):
+        """Use these inverse weights (e.g. a nominal model's) in every row's regulariser."""
+        b, d = _arr(body, self.nbody), _arr(dof, self.nv)
+        self._lib.mjo_set_invweight(self._h, _d(b), _d(d))
 
     def dof_parent(self) -> np.ndarray:
         out = np.zeros(self.nv, dtype=np.int32)

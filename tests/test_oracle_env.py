@@ -97,3 +97,107 @@ def test_env_step_resets_inverted_worlds():
     assert rew[1] == 0.0
     np.testing.assert_array_equal(obs[:, 33:45], prev)  # the previous action in the obs
     np.testing.assert_array_equal(obs[:, 45:48], cmd)
+
+
+# ------------------------------------------------------------------ domain randomisation
+def _record(m, fric=1.0, payload=0.0, com=(0, 0, 0), kp=1.0, kd=1.0, calib=None, arm=None):
+    rec = env.dr_identity(m)
+    rec[0], rec[1], rec[2:5], rec[5], rec[6] = fric, payload, com, kp, kd
+    if calib is not None:
+        rec[8:8 + m.nu] = calib
+    if arm is not None:
+        rec[8 + m.nu:] = arm
+    return rec
+
+
+def test_identity_record_changes_nothing():
+    m = robots.quadruped()
+    assert env.randomized_model(m, env.dr_identity(m)).to_blob() == m.to_blob()
+    o = Oracle(m)
+    nw = 3
+    qp, qv = inputs.initial_state("quadruped", m, nw, seed=2)
+    a = np.random.default_rng(1).uniform(-0.5, 0.5, size=(nw, m.nu))
+    args = (qp, qv, np.zeros((nw, m.nv)), np.zeros((nw, m.nu)), a, np.zeros((nw, 3)), qp, qv, 3)
+    ref = env.env_step(o, m, *args)
+    dr = np.stack([env.dr_identity(m)] * nw)
+    noise = np.random.default_rng(2).normal(size=(nw, 48))
+    got = env.env_step(o, m, *args, dr=dr, noise=noise)
+    np.testing.assert_array_equal(got[0], ref[0] + noise)
+    np.testing.assert_array_equal(got[1], ref[1])
+    np.testing.assert_array_equal(got[3][0], ref[3][0])
+
+
+def test_payload_and_com_shift_closed_form():
+    """At qpos0 (root frame = world frame): the translational mass block gains the
+    payload, and the gravity bias on the root's rotational dofs gains the moment of the
+    root body's shifted, heavier centre of mass about the root origin."""
+    m = robots.quadruped()
+    dm, dc = 1.5, np.array([0.02, -0.01, 0.005])
+    o0 = Oracle(m)
+    ow = env.randomized_oracle(o0, m, _record(m, payload=dm, com=dc))
+    q, v = m.qpos0.copy(), np.zeros(m.nv)
+    f0, fw = o0.forward(q, v), ow.forward(q, v)
+    mtot = sum(b.mass for b in m.bodies)
+    np.testing.assert_allclose(np.diag(f0["M"])[:3], mtot, rtol=1e-14)
+    np.testing.assert_allclose(np.diag(fw["M"])[:3], mtot + dm, rtol=1e-14)
+    s = np.sign(f0["bias"][2])  # the bias holds the force against gravity, up to sign
+    assert f0["bias"][2] == pytest.approx(s * mtot * 9.81, rel=1e-12)
+    mroot = m.bodies[m.joints[0].body].mass
+    c0 = np.asarray(m.bodies[m.joints[0].body].ipos)
+    gz = np.array([0.0, 0.0, 9.81])
+    expect = s * (np.cross((mroot + dm) * (c0 + dc), gz) - np.cross(mroot * c0, gz))
+    np.testing.assert_allclose(fw["bias"][:3] - f0["bias"][:3], s * dm * gz, atol=1e-12)
+    np.testing.assert_allclose(fw["bias"][3:6] - f0["bias"][3:6], expect, atol=1e-12)
+    np.testing.assert_allclose(fw["bias"][6:], f0["bias"][6:], atol=1e-12)
+
+
+def test_armature_gains_and_calibration_closed_form():
+    m = robots.quadruped()
+    rng = np.random.default_rng(5)
+    arm = rng.uniform(0.005, 0.02, m.nu)
+    calib = rng.uniform(-0.05, 0.05, m.nu)
+    skp, skd = 0.8, 1.3
+    o0 = Oracle(m)
+    ow = env.randomized_oracle(o0, m, _record(m, kp=skp, kd=skd, calib=calib, arm=arm))
+    qp, qv = inputs.initial_state("quadruped", m, 1, seed=4)
+    qv = rng.normal(size=(1, m.nv))
+    u = rng.uniform(-0.5, 0.5, m.nu)
+    f0, fw = o0.forward(qp[0], qv[0], ctrl=u), ow.forward(qp[0], qv[0], ctrl=u)
+    np.testing.assert_allclose(fw["M"] - f0["M"], np.diag(np.r_[np.zeros(6), arm]), atol=1e-14)
+    for k, a in enumerate(m.actuators):
+        tau = skp * a.kp * (a.qdefault + u[k] - (qp[0, 7 + k] + calib[k])) \
+            - skd * a.kd * qv[0, 6 + k]
+        assert fw["act"][6 + k] == pytest.approx(tau, rel=1e-12, abs=1e-12)
+    # the observation reports the encoder reading q + delta
+    obs = env.observe(env.randomized_model(m, _record(m, calib=calib)), qp[0], qv[0],
+                      np.zeros(m.nu), np.zeros(3))
+    qdef = np.array([a.qdefault for a in m.actuators])
+    np.testing.assert_allclose(obs[9:21], qp[0, 7:] + calib - qdef, atol=1e-15)
+    # the regularisers keep the nominal inverse weights
+    np.testing.assert_array_equal(ow.body_invweight(), o0.body_invweight())
+    np.testing.assert_array_equal(ow.dof_invweight(), o0.dof_invweight())
+    assert not np.allclose(Oracle(env.randomized_model(m, _record(m, arm=arm))).dof_invweight(),
+                           o0.dof_invweight())
+
+
+def test_friction_scale_on_an_incline():
+    """Gravity tilted by atan(0.5): with mu = 1 a box sticks; with the coefficient
+    scaled to f < 0.5 it slides, and the friction it feels, (g sin - a) / (g cos), is f
+    (Coulomb along a pyramid edge) within 2 % (the soft contact's regulariser lets a
+    sliding contact transmit slightly less than mu N)."""
+    th = np.arctan(0.5)
+    grav = (9.81 * np.sin(th), 0.0, -9.81 * np.cos(th))
+    m = robots.free_body("box", mass=1.0, half=(0.1, 0.2, 0.05), plane=True, mu=1.0,
+                         gravity=grav, timestep=0.002)
+    q0 = m.qpos0.copy()
+    q0[2] = 0.05
+    for f in (1.0, 0.4, 0.3, 0.2):
+        o = env.randomized_oracle(Oracle(m), m, _record(m, fric=f))
+        r1 = o.step(q0[None].copy(), np.zeros((1, 6)), nstep=300, mode=1)
+        r2 = o.step(r1["qpos"], r1["qvel"], r1["qacc_ws"], nstep=200, mode=1)
+        acc = (r2["qvel"][0, 0] - r1["qvel"][0, 0]) / (200 * m.opt.timestep)
+        if f == 1.0:
+            assert abs(acc) < 1e-3
+        else:
+            mu_eff = (9.81 * np.sin(th) - acc) / (9.81 * np.cos(th))
+            assert mu_eff == pytest.approx(f, rel=2e-2)
