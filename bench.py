@@ -244,15 +244,27 @@ def env_compare(ctx, seed, nw=8192, nenv=200, nsub=5, reps=3):
     rew = torch.zeros(nenv, nw, **f)
     done = torch.zeros(nenv, nw, dtype=torch.int32, device="cuda")
 
-    def run():
+    # per-world randomised parameters in the ranges of the paper's randomisation, and
+    # sensor noise N(0, 0.01) on every observation entry
+    u = lambda lo, hi, *shape: lo + (hi - lo) * torch.rand(shape, device="cuda", generator=gen)
+    params = torch.cat([u(0.4, 1.25, nw, 1), u(-0.5, 2.0, nw, 1), u(-0.03, 0.03, nw, 3),
+                        u(0.8, 1.2, nw, 2), torch.zeros(nw, 1, device="cuda"),
+                        u(-0.05, 0.05, nw, m.nu), u(0.0, 0.02, nw, m.nu)], 1).contiguous()
+    noise = (0.01 * torch.randn(obs.shape, device="cuda", generator=gen)).contiguous()
+
+    def run(dr=False):
         w.qpos.copy_(q0); w.qvel.copy_(v0); w.qacc_ws.zero_(); last.zero_()
-        w.batch.env_step(nsub, act, cmd, q0, v0, last, obs, rew, done, stream)
+        w.batch.env_step(nsub, act, cmd, q0, v0, last, obs, rew, done,
+                         params if dr else None, noise if dr else None, stream)
     run()
     ms = timed(run, stream, reps)
+    run(True)
+    ms_dr = timed(lambda: run(True), stream, reps)
     return {"workload": f"quadruped joystick env, {nw} worlds x {nenv} env steps of {nsub} "
                         "physics steps, one launch",
             "env_steps_per_s": round(nw * nenv / (ms * 1e-3), 1),
             "world_steps_per_s": round(nw * nenv * nsub / (ms * 1e-3), 1),
+            "randomised_env_steps_per_s": round(nw * nenv / (ms_dr * 1e-3), 1),
             "nobs": 12 + 3 * m.nu, "launch": list(w.batch.get_launch(0)),
             "terminations": int(done.sum().item()),
             "mean_reward": round(float(rew.mean().item()), 4),

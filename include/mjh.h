@@ -140,24 +140,34 @@ mjh_status mjh_step(mjh_batch* b, int32_t nstep, void* stream);
 
 /* Joystick locomotion environment steps (the paper's locomotion appendix: observation
  * list, absolute joint-position actions through the PD mapping of eq. pd_mapping, a
- * subset of its reward table, termination when the robot inverts), fused around the
- * physics step for a single-model batch whose root is a free joint and whose position
- * actuator k drives dof 6 + k.  Each of `nenv` env steps runs `nsub` physics steps with
- * action[e] (device, [nenv][nworld][nu]) held as the actuators' controls, then writes,
- * from the new state, obs[e] ([nenv][nworld][12 + 3 nu]: gravity direction, root linear
- * and angular velocity in the root frame, joint positions minus their defaults, joint
- * velocities, previous action, command[w] ([nworld][3]: vx, vy, yaw rate)), reward[e]
- * ([nenv][nworld]: max(0, 1.0 exp(-|cmd_xy - v_xy|^2/0.25) + 0.5 exp(-(cmd_wz -
- * w_z)^2/0.25) - 2 v_z^2 - 0.05 |w_xy|^2 - 5 |g_xy|^2 - 2e-4 |tau|^2 - 0.1 |q -
- * q_default|^2 - 0.01 |a_t - a_{t-1}|^2 - done)) and done[e] ([nenv][nworld], 1 when the
- * root's z axis points downwards).  A world that is done restarts from reset_qpos /
- * reset_qvel ([nworld][nq] / [nworld][nv]) with a zero warm start and previous action.
- * last_action ([nworld][nu]) holds the previous action on entry and on return.  The
- * bound state advances in place.  Stream-ordered; MJH_EUNSUPPORTED for other models. */
+ * subset of its reward table, termination when the robot inverts, and its domain
+ * randomisation), fused around the physics step for a single-model batch whose body 1
+ * is the free root and whose position actuator k drives dof 6 + k.  Each of `nenv` env
+ * steps runs `nsub` physics steps with action[e] (device, [nenv][nworld][nu]) held as
+ * the actuators' controls, then writes, from the new state, obs[e] ([nenv][nworld]
+ * [12 + 3 nu]: gravity direction, root linear and angular velocity in the root frame,
+ * joint readings minus their defaults, joint velocities, previous action, command[w]
+ * ([nworld][3]: vx, vy, yaw rate)), reward[e] ([nenv][nworld]: max(0, 1.0 exp(-|cmd_xy -
+ * v_xy|^2/0.25) + 0.5 exp(-(cmd_wz - w_z)^2/0.25) - 2 v_z^2 - 0.05 |w_xy|^2 - 5 |g_xy|^2
+ * - 2e-4 |tau|^2 - 0.1 |q - q_default|^2 - 0.01 |a_t - a_{t-1}|^2 - done)) and done[e]
+ * ([nenv][nworld], 1 when the root's z axis points downwards).  A world that is done
+ * restarts from reset_qpos / reset_qvel ([nworld][nq] / [nworld][nv]) with a zero warm
+ * start and previous action.  last_action ([nworld][nu]) holds the previous action on
+ * entry and on return.  The bound state advances in place.
+ *
+ * params (optional, [nworld][8 + 2 nu]): each world's randomised parameters --
+ * [0] contact friction scale, [1] payload mass added to the root body at its centre of
+ * mass, [2..4] shift of the root body's centre of mass (root frame), [5] kp scale,
+ * [6] kd scale, [7] unused, [8 + k] calibration offset of joint 6 + k (the PD law, the
+ * observation and the pose term see q + offset), [8 + nu + k] armature of dof 6 + k.
+ * The rows' regularisers keep the model's nominal inverse weights.  NULL: the model as
+ * uploaded.  obs_noise (optional, [nenv][nworld][12 + 3 nu]) is added to obs.
+ * Stream-ordered; MJH_EUNSUPPORTED for other models, and for params with implicit
+ * damping. */
 mjh_status mjh_env_step(mjh_batch* b, int32_t nenv, int32_t nsub, const float* action,
                         const float* command, const float* reset_qpos, const float* reset_qvel,
-                        float* last_action, float* obs, float* reward, int32_t* done,
-                        void* stream);
+                        const float* params, const float* obs_noise, float* last_action,
+                        float* obs, float* reward, int32_t* done, void* stream);
 
 /* Capture mjh_step(b, nstep) into a HIP graph (replayed by mjh_graph_launch).  The
  * graph reads the bound pointers at replay time, so rebinding needs no recapture. */

@@ -883,8 +883,8 @@ mjh_status mjh_step(mjh_batch* b, int32_t nstep, void* stream) {
 
 mjh_status mjh_env_step(mjh_batch* b, int32_t nenv, int32_t nsub, const float* action,
                         const float* command, const float* reset_qpos, const float* reset_qvel,
-                        float* last_action, float* obs, float* reward, int32_t* done,
-                        void* stream) {
+                        const float* params, const float* obs_noise, float* last_action,
+                        float* obs, float* reward, int32_t* done, void* stream) {
   if (!b) return MJH_EINVAL;
   mjh_ctx* ctx = b->ctx;
   if (b->groups.size() != 1) return fail(ctx, MJH_EINVAL, "env_step: single-model batches only");
@@ -892,7 +892,7 @@ mjh_status mjh_env_step(mjh_batch* b, int32_t nenv, int32_t nsub, const float* a
   const GroupRec& g = b->groups[0];
   const HostModel& h = ctx->models[g.model]->h;
   // the task's layout: a free root, then one position actuator per remaining dof, in order
-  bool ok = h.njnt >= 1 && h.jnt_type[0] == JNT_FREE && h.nu == h.nv - 6;
+  bool ok = h.njnt >= 1 && h.jnt_type[0] == JNT_FREE && h.jnt_body[0] == 1 && h.nu == h.nv - 6;
   std::vector<int> dofadr(h.njnt, 0);
   for (int j = 1; j < h.njnt; j++) dofadr[j] = dofadr[j - 1] + (h.jnt_type[j - 1] == JNT_FREE ? 6 : 1);
   for (int k = 0; ok && k < h.nu; k++)
@@ -900,6 +900,9 @@ mjh_status mjh_env_step(mjh_batch* b, int32_t nenv, int32_t nsub, const float* a
   if (!ok)
     return fail(ctx, MJH_EUNSUPPORTED,
                 "env_step: needs a free root joint and position actuator k on dof 6 + k");
+  if (params && h.integrator != 0)
+    return fail(ctx, MJH_EUNSUPPORTED,
+                "env_step: per-world parameters with implicit damping are not supported");
   if (g.nworld == 0) return MJH_OK;
   if (!action || !command || !reset_qpos || !reset_qvel || !last_action || !obs || !reward ||
       !done)
@@ -909,7 +912,8 @@ mjh_status mjh_env_step(mjh_batch* b, int32_t nenv, int32_t nsub, const float* a
   st = sync_tables(b);
   if (st != MJH_OK) return st;
   const int teams = std::max(1, b->block / g.team);
-  const int ap_words = (teams * h.nu + 3) & ~3;
+  const int ndr = params ? 8 + 2 * h.nu : 0;
+  const int ap_words = (teams * (h.nu + ndr) + 3) & ~3;
   const size_t lds = b->lds_bytes + (size_t)ap_words * sizeof(float);
   if (lds > ctx->lds_limit)
     return fail(ctx, MJH_EUNSUPPORTED, "env_step: work-group exceeds the LDS limit");
@@ -917,6 +921,7 @@ mjh_status mjh_env_step(mjh_batch* b, int32_t nenv, int32_t nsub, const float* a
   E.nenv = nenv; E.nsub = nsub; E.nobs = 12 + 3 * h.nu;
   E.action = action; E.command = command; E.reset_qpos = reset_qpos; E.reset_qvel = reset_qvel;
   E.last_action = last_action; E.obs = obs; E.reward = reward; E.done = done;
+  E.ndr = ndr; E.dr = params; E.noise = obs_noise;
   MJH_HIP(launch_env(b->d_groups, b->d_tasks, b->ntask, E, b->block, lds, b->tab_words, ap_words,
                      static_cast<hipStream_t>(stream)));
   return MJH_OK;

@@ -195,11 +195,21 @@ DEV float dot6(const float* a, const float* b) {
 // fits the full-rate 24-bit multiplier)
 DEV int tri(int i, int j) { return (__mul24(i, i + 1) >> 1) + j; }  // requires i >= j
 DEV int sym(int i, int j) { return i >= j ? tri(i, j) : tri(j, i); }
+// ------------------------------------------------------------ per-world parameters
+// Optional per-world parameter record (domain randomisation, in LDS), 8 + 2 nu words:
+// [0] contact friction scale, [1] payload mass added to body 1 at its centre of mass,
+// [2..4] shift of body 1's centre of mass (body frame), [5] kp scale, [6] kd scale,
+// [7] unused, [8 + k] calibration offset of actuator k (the PD law sees q + offset),
+// [8 + nu + k] armature of dof 6 + k (replacing the model's).  The caller guarantees
+// body 1 is the free root and actuator k drives dof 6 + k.  nullptr: the model as is.
+constexpr int kDrFric = 0, kDrPayload = 1, kDrCom = 2, kDrKp = 5, kDrKd = 6, kDrHead = 8;
+
 // ------------------------------------------------------------ A0: actuation
 // per dof: motor tau = gear u; position actuator (eq. pd_mapping)
 // tau = kp (q_default + gear u - q) - kd qdot; joint damping -b qdot.  Controls are
 // clamped to their range.  Result: frc = act + passive (bias subtracted later).
-DEV void actuation(const DevModel& m, float* W, const Team& t, const float* ctrl) {
+DEV void actuation(const DevModel& m, float* W, const Team& t, const float* ctrl,
+                   const float* dr = nullptr) {
   const float* qpos = W + m.o_qpos;
   const float* qvel = W + m.o_qvel;
   float* frc = W + m.o_frc;
@@ -212,8 +222,13 @@ DEV void actuation(const DevModel& m, float* W, const Team& t, const float* ctrl
       if (m.act_type[a] == ACT_MOTOR) {
         f += m.act_gear[a] * u;
       } else {
-        f += m.act_kp[a] * (m.act_qdef[a] + m.act_gear[a] * u - qpos[m.act_qadr[a]]) -
-             m.act_kd[a] * qvel[i];
+        float kp = m.act_kp[a], kd = m.act_kd[a], q0 = m.act_qdef[a];
+        if (dr) {
+          kp *= dr[kDrKp];
+          kd *= dr[kDrKd];
+          q0 -= dr[kDrHead + a];
+        }
+        f += kp * (q0 + m.act_gear[a] * u - qpos[m.act_qadr[a]]) - kd * qvel[i];
       }
     }
     frc[i] = f;
@@ -226,7 +241,8 @@ DEV void actuation(const DevModel& m, float* W, const Team& t, const float* ctrl
 // absolute pose), record motion subspaces S (world origin) and their rates, the
 // body velocity V, bias acceleration A (qacc = 0, world at -gravity), spatial
 // inertia and the body force f = I A + V x* I V.
-DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* qacc = nullptr) {
+DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* qacc = nullptr,
+                       const float* dr = nullptr) {
   const float* qpos = W + m.o_qpos;
   const float* qvel = W + m.o_qvel;
   float* xpos = W + m.o_xpos;
@@ -319,8 +335,14 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* 
       for (int k = 0; k < 9; k++) xmat[9 * b + k] = R[k];
       for (int k = 0; k < 6; k++) { cvel[6 * b + k] = V[k]; cacc[6 * b + k] = A[k]; }
       // spatial inertia at the world origin: m, h = m c, I_O = R I R^T + m (|c|^2 1 - c c^T)
-      float c[3], Rt[9], RI[9], Iw[9];
-      mv3(R, m.body_ipos + 3 * b, c);
+      float c[3], Rt[9], RI[9], Iw[9], ip[3] = {m.body_ipos[3 * b], m.body_ipos[3 * b + 1],
+                                                m.body_ipos[3 * b + 2]};
+      float mass = m.body_mass[b];
+      if (dr && b == 1) {
+        for (int k = 0; k < 3; k++) ip[k] += dr[kDrCom + k];
+        mass += dr[kDrPayload];
+      }
+      mv3(R, ip, c);
       for (int k = 0; k < 3; k++) c[k] += pos[k];
       const float* bi = m.body_inertia + 6 * b;
       float Il[9] = {bi[0], bi[3], bi[4], bi[3], bi[1], bi[5], bi[4], bi[5], bi[2]};
@@ -328,7 +350,6 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* 
         for (int k = 0; k < 3; k++) Rt[3 * i + k] = R[3 * k + i];
       mm3(R, Il, RI);
       mm3(RI, Rt, Iw);
-      const float mass = m.body_mass[b];
       const float cc = dot3(c, c);
       float* ci = cinert + kCinert * b;
       ci[0] = mass;
@@ -350,7 +371,8 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* 
 }
 
 // ------------------------------- A3/A5 backward sweep, bias forces and CRBA (RBDA 6)
-DEV void backward_and_mass(const DevModel& m, float* W, const Team& t) {
+DEV void backward_and_mass(const DevModel& m, float* W, const Team& t,
+                           const float* dr = nullptr) {
   float* cfrc = W + m.o_cfrc;
   float* Ic = W + m.o_cinert;  // body inertias become subtree (composite) inertias
   const float* cdof = W + m.o_cdof;
@@ -386,7 +408,7 @@ DEV void backward_and_mass(const DevModel& m, float* W, const Team& t) {
     const int pr = m.mpair[k];
     const int i = pr >> 16, j = pr & 0xffff;
     float v = dot6(cdof + 6 * j, F + 6 * i);
-    if (i == j) v += m.dof_armature[i];
+    if (i == j) v += (dr && i >= 6) ? dr[kDrHead + m.nu + i - 6] : m.dof_armature[i];
     M[tri(i, j)] = v;
   }
   t.sync();
@@ -632,45 +654,42 @@ DEV float sphere_sphere(const float* c1, float r1, const float* c2, float r2, fl
   return dist;
 }
 
-// Nearest point q of triangle (a, b, c) to p: p's projection onto the triangle's plane
-// when its barycentric weights are all >= 0, else the nearest edge point.  nrm receives
-// the (unnormalised) normal (b - a) x (c - a).
-DEV void tri_nearest(const float* a, const float* b, const float* c, const float* p, float* q,
-                     float* nrm) {
-  const float ab[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
-  const float ac[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
-  cross3(ab, ac, nrm);
-  const float nn = dot3(nrm, nrm);
-  const float ap[3] = {p[0] - a[0], p[1] - a[1], p[2] - a[2]};
-  const float hgt = dot3(ap, nrm) / nn;
-  const float pp[3] = {p[0] - hgt * nrm[0], p[1] - hgt * nrm[1], p[2] - hgt * nrm[2]};
-  const float* v[3] = {a, b, c};
-  bool inside = true;
-  for (int k = 0; k < 3; k++) {
-    const float* e0 = v[k == 2 ? 0 : k + 1];
-    const float* e1 = v[k == 0 ? 2 : k - 1];
-    const float d0[3] = {e0[0] - pp[0], e0[1] - pp[1], e0[2] - pp[2]};
-    const float d1[3] = {e1[0] - pp[0], e1[1] - pp[1], e1[2] - pp[2]};
-    float cr[3];
-    cross3(d0, d1, cr);
-    inside = inside && dot3(cr, nrm) >= 0.f;
-  }
-  if (inside) {
-    q[0] = pp[0]; q[1] = pp[1]; q[2] = pp[2];
-    return;
-  }
+// Three-vectors by value: the heightfield test takes its triangle's corners as values,
+// never as pointers into local arrays (which would move those arrays to scratch memory).
+struct V3 { float x, y, z; };
+DEV V3 v3sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+DEV float v3dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+DEV V3 v3cross(V3 a, V3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+// nearest point x of segment (s0, s1) to p; keeps it in (best, q) when strictly nearer
+DEV void seg_nearest(V3 s0, V3 s1, V3 p, float& best, V3& q) {
+  const V3 u = v3sub(s1, s0), w = v3sub(p, s0);
+  const float tt = fminf(fmaxf(v3dot(w, u) / v3dot(u, u), 0.f), 1.f);
+  const V3 x = {s0.x + tt * u.x, s0.y + tt * u.y, s0.z + tt * u.z};
+  const V3 dx = v3sub(p, x);
+  const float dd = v3dot(dx, dx);
+  if (dd < best) { best = dd; q = x; }
+}
+
+// Nearest point of triangle (a, b, c) to p: p's projection onto the triangle's plane
+// when its barycentric weights are all >= 0, else the nearest edge point (edges ab, bc,
+// ca, the first on ties).  nrm receives the (unnormalised) normal (b - a) x (c - a).
+DEV V3 tri_nearest(V3 a, V3 b, V3 c, V3 p, V3& nrm) {
+  nrm = v3cross(v3sub(b, a), v3sub(c, a));
+  const float hgt = v3dot(v3sub(p, a), nrm) / v3dot(nrm, nrm);
+  const V3 pp = {p.x - hgt * nrm.x, p.y - hgt * nrm.y, p.z - hgt * nrm.z};
+  const bool in_a = v3dot(v3cross(v3sub(b, pp), v3sub(c, pp)), nrm) >= 0.f;
+  const bool in_b = v3dot(v3cross(v3sub(c, pp), v3sub(a, pp)), nrm) >= 0.f;
+  const bool in_c = v3dot(v3cross(v3sub(a, pp), v3sub(b, pp)), nrm) >= 0.f;
+  if (in_a && in_b && in_c) return pp;
   float best = INFINITY;
-  for (int e = 0; e < 3; e++) {
-    const float* s0 = v[e];
-    const float* s1 = v[e == 2 ? 0 : e + 1];
-    const float u[3] = {s1[0] - s0[0], s1[1] - s0[1], s1[2] - s0[2]};
-    const float w[3] = {p[0] - s0[0], p[1] - s0[1], p[2] - s0[2]};
-    const float tt = fminf(fmaxf(dot3(w, u) / dot3(u, u), 0.f), 1.f);
-    const float x[3] = {s0[0] + tt * u[0], s0[1] + tt * u[1], s0[2] + tt * u[2]};
-    const float dx[3] = {p[0] - x[0], p[1] - x[1], p[2] - x[2]};
-    const float dd = dot3(dx, dx);
-    if (dd < best) { best = dd; q[0] = x[0]; q[1] = x[1]; q[2] = x[2]; }
-  }
+  V3 q = a;
+  seg_nearest(a, b, p, best, q);
+  seg_nearest(b, c, p, best, q);
+  seg_nearest(c, a, p, best, q);
+  return q;
 }
 
 // Sphere (geom 1: centre c, radius r) against the heightfield (geom 2 at xg, Rg): the
@@ -683,51 +702,48 @@ DEV float sphere_hfield(const DevModel& m, const float* xg, const float* Rg, con
   const int nr = m.hf_nrow, nc = m.hf_ncol;
   const float sx = m.hf_size[0], sy = m.hf_size[1], sz = m.hf_size[2];
   const float dx = 2.f * sx / (nc - 1), dy = 2.f * sy / (nr - 1);
-  const float rel[3] = {c[0] - xg[0], c[1] - xg[1], c[2] - xg[2]};
-  const float cl[3] = {Rg[0] * rel[0] + Rg[3] * rel[1] + Rg[6] * rel[2],
-                       Rg[1] * rel[0] + Rg[4] * rel[1] + Rg[7] * rel[2],
-                       Rg[2] * rel[0] + Rg[5] * rel[1] + Rg[8] * rel[2]};
+  const float rx = c[0] - xg[0], ry = c[1] - xg[1], rz = c[2] - xg[2];
+  const V3 cl = {Rg[0] * rx + Rg[3] * ry + Rg[6] * rz, Rg[1] * rx + Rg[4] * ry + Rg[7] * rz,
+                 Rg[2] * rx + Rg[5] * ry + Rg[8] * rz};
   // cell range of the footprint, clamped before the conversion to int
   auto cell = [](float x, int hi) { return (int)floorf(fminf(fmaxf(x, -1.f), (float)hi)); };
-  const int j0 = max(0, cell((cl[0] - r + sx) / dx, nc));
-  const int j1 = min(nc - 2, cell((cl[0] + r + sx) / dx, nc));
-  const int i0 = max(0, cell((cl[1] - r + sy) / dy, nr));
-  const int i1 = min(nr - 2, cell((cl[1] + r + sy) / dy, nr));
-  float best = INFINITY, bq[3] = {0.f, 0.f, 0.f}, bn[3] = {0.f, 0.f, 1.f};
+  const int j0 = max(0, cell((cl.x - r + sx) / dx, nc));
+  const int j1 = min(nc - 2, cell((cl.x + r + sx) / dx, nc));
+  const int i0 = max(0, cell((cl.y - r + sy) / dy, nr));
+  const int i1 = min(nr - 2, cell((cl.y + r + sy) / dy, nr));
+  float best = INFINITY;
+  V3 bq = {0.f, 0.f, 0.f}, bn = {0.f, 0.f, 1.f};
   for (int i = i0; i <= i1; i++)
     for (int j = j0; j <= j1; j++) {
       const float x0 = -sx + dx * j, x1 = x0 + dx, y0 = -sy + dy * i, y1 = y0 + dy;
       const float* hrow = m.hf_data + (size_t)i * nc + j;
-      const float v00[3] = {x0, y0, sz * hrow[0]}, v01[3] = {x1, y0, sz * hrow[1]};
-      const float v10[3] = {x0, y1, sz * hrow[nc]}, v11[3] = {x1, y1, sz * hrow[nc + 1]};
+      const V3 v00 = {x0, y0, sz * hrow[0]}, v01 = {x1, y0, sz * hrow[1]};
+      const V3 v10 = {x0, y1, sz * hrow[nc]}, v11 = {x1, y1, sz * hrow[nc + 1]};
       for (int k = 0; k < 2; k++) {
-        float q[3], nt[3];
-        if (k == 0) tri_nearest(v00, v01, v11, cl, q, nt);
-        else tri_nearest(v00, v11, v10, cl, q, nt);
-        const float d[3] = {cl[0] - q[0], cl[1] - q[1], cl[2] - q[2]};
-        const float dd = dot3(d, d);
-        if (dd < best) {
-          best = dd;
-          bq[0] = q[0]; bq[1] = q[1]; bq[2] = q[2];
-          bn[0] = nt[0]; bn[1] = nt[1]; bn[2] = nt[2];
-        }
+        V3 nt;
+        const V3 q = k == 0 ? tri_nearest(v00, v01, v11, cl, nt)
+                            : tri_nearest(v00, v11, v10, cl, nt);
+        const V3 d = v3sub(cl, q);
+        const float dd = v3dot(d, d);
+        if (dd < best) { best = dd; bq = q; bn = nt; }
       }
     }
   if (best == INFINITY) return INFINITY;
   const float L = sqrtf(best);
-  const float d[3] = {cl[0] - bq[0], cl[1] - bq[1], cl[2] - bq[2]};
-  const bool below = dot3(bn, d) < 0.f;
+  const V3 d = v3sub(cl, bq);
+  const bool below = v3dot(bn, d) < 0.f;
   float nl[3];
   if (L > 1e-12f) {
     const float sg = (below ? 1.f : -1.f) / L;
-    nl[0] = sg * d[0]; nl[1] = sg * d[1]; nl[2] = sg * d[2];
+    nl[0] = sg * d.x; nl[1] = sg * d.y; nl[2] = sg * d.z;
   } else {
-    const float inv = -1.f / sqrtf(dot3(bn, bn));
-    nl[0] = inv * bn[0]; nl[1] = inv * bn[1]; nl[2] = inv * bn[2];
+    const float inv = -1.f / sqrtf(v3dot(bn, bn));
+    nl[0] = inv * bn.x; nl[1] = inv * bn.y; nl[2] = inv * bn.z;
   }
+  const float bqa[3] = {bq.x, bq.y, bq.z};
   float qw[3];
   mv3(Rg, nl, n);
-  mv3(Rg, bq, qw);
+  mv3(Rg, bqa, qw);
   for (int k = 0; k < 3; k++) pos[k] = 0.5f * (c[k] + r * n[k] + qw[k] + xg[k]);
   return (below ? -L : L) - r;
 }
@@ -884,7 +900,8 @@ DEV void contact_frame(const float* n, float* fr) {
 
 // Phase 2: select the contacts (all penetrating candidates in slot order, or on
 // overflow the nconmax deepest, ties to the lower slot) and build their records.
-DEV void select_contacts(const DevModel& m, float* W, const Team& t, int& status) {
+DEV void select_contacts(const DevModel& m, float* W, const Team& t, int& status,
+                         const float* dr = nullptr) {
   const float* cd = W + m.o_cand;
   const float* cp = cd + m.ncand;
   float* con = W + m.o_con;
@@ -921,7 +938,7 @@ DEV void select_contacts(const DevModel& m, float* W, const Team& t, int& status
       r[0] = dist;
       r[1] = pos[0]; r[2] = pos[1]; r[3] = pos[2];
       contact_frame(n, r + 4);
-      r[13] = m.pair_mu[p];
+      r[13] = dr ? m.pair_mu[p] * dr[kDrFric] : m.pair_mu[p];
       r[14] = __int_as_float(m.geom_body[m.pair_g1[p]]);
       r[15] = __int_as_float(m.geom_body[m.pair_g2[p]]);
       r[16] = __int_as_float(p);
@@ -1676,23 +1693,23 @@ DEV void implicit_damping(const DevModel& m, float* W, const Team& t) {
 
 DEV void world_step(const DevModel& m, float* W0, const Team& t0, const float* ctrl,
                     int& status, int iters, float gtol = 0.f, long long* ph = nullptr,
-                    long long* last = nullptr) {
+                    long long* last = nullptr, const float* dr = nullptr) {
 #define MJH_PHASE_CTX                                   \
   float* W = W0 + opaque_zero();                        \
   const Team t{t0.lane + opaque_zero(), t0.T, t0.tp};
   {
     MJH_PHASE_CTX
-    actuation(m, W, t, ctrl);
+    actuation(m, W, t, ctrl, dr);
     MJH_MARK(0);
   }
   {
     MJH_PHASE_CTX
-    forward_sweep(m, W, t);
+    forward_sweep(m, W, t, nullptr, dr);
     MJH_MARK(1);
   }
   {
     MJH_PHASE_CTX
-    backward_and_mass(m, W, t);
+    backward_and_mass(m, W, t, dr);
     MJH_MARK(2);
   }
   {
@@ -1707,7 +1724,7 @@ DEV void world_step(const DevModel& m, float* W0, const Team& t0, const float* c
   {
     MJH_PHASE_CTX
     collide_candidates(m, W, t);
-    select_contacts(m, W, t, status);
+    select_contacts(m, W, t, status, dr);
     MJH_MARK(4);
   }
   {

@@ -32,6 +32,9 @@ struct EnvArgs {
   float* obs;               // [nenv][nworld][nobs]
   float* reward;            // [nenv][nworld]
   int* done;                // [nenv][nworld]
+  int ndr;                  // 8 + 2 nu with per-world parameters, else 0
+  const float* dr;          // [nworld][ndr] or nullptr
+  const float* noise;       // [nenv][nworld][nobs] or nullptr
 };
 // ap_words: LDS words after the pair table for the teams' previous actions
 hipError_t launch_env(const DevGroup* groups, const DevTask* tasks, int ntask, const EnvArgs& E,

@@ -19,7 +19,7 @@ constexpr int kPhaseWorlds = 8192;
 __device__ long long g_phase_cycles[kPhaseWorlds * 8];
 #endif
 
-__device__ void run_worlds(const DevGroup& G, float* W, int world, int nstep, int lane, int T,
+__device__ __forceinline__ void run_worlds(const DevGroup& G, float* W, int world, int nstep, int lane, int T,
                            const unsigned char* tab) {
   const DevModel& m = G.m;
   const Team t{lane, T, tab};
@@ -96,12 +96,16 @@ mjh_step_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__
 //   done   = the root's z axis points downwards (inverted).
 // A terminated world restarts from its reset state with a zero warm start and a zero
 // previous action.  The root is a free joint; actuator k drives dof 6 + k.
+// Domain randomisation (optional): each world's parameter record (layout at kDrFric)
+// drives its physics, and the observation and reward see the calibrated joint reading
+// q + offset and the world's gains; sensor noise, when given, is added to every entry
+// of the observation.
 constexpr float kEnvKv = 1.f, kEnvSv = 0.25f, kEnvKw = 0.5f, kEnvSw = 0.25f;
 constexpr float kEnvLinZ = -2.f, kEnvAngXY = -0.05f, kEnvOri = -5.f, kEnvTau = -2e-4f;
 constexpr float kEnvQ = -0.1f, kEnvRate = -0.01f, kEnvTerm = -1.f;
 
-__device__ void env_worlds(const DevGroup& G, const EnvArgs& E, float* W, float* aprev, int world,
-                           int lane, int T, const unsigned char* tab) {
+__device__ __forceinline__ void env_worlds(const DevGroup& G, const EnvArgs& E, float* W, float* aprev, float* dr,
+                           int world, int lane, int T, const unsigned char* tab) {
   const DevModel& m = G.m;
   const Team t{lane, T, tab};
   world_init(m, W, t);
@@ -117,13 +121,16 @@ __device__ void env_worlds(const DevGroup& G, const EnvArgs& E, float* W, float*
   }
   t.sync();
   for (int k = lane; k < nu; k += T) aprev[k] = E.last_action[w * nu + k];
+  if (dr)
+    for (int k = lane; k < E.ndr; k += T) dr[k] = E.dr[w * E.ndr + k];
   t.sync();
+  const float skp = dr ? dr[kDrKp] : 1.f, skd = dr ? dr[kDrKd] : 1.f;
   int status = 0;
   const float* cmd = E.command + w * 3;
   for (int e = 0; e < E.nenv; e++) {
     const float* u = E.action + ((size_t)e * G.nworld + w) * nu;
     for (int s = 0; s < E.nsub; s++) {
-      world_step(m, W, t, u, status, m.iterations);
+      world_step(m, W, t, u, status, m.iterations, 0.f, nullptr, nullptr, dr);
       integrate(m, W, t, status);
     }
     // root rotation from its quaternion (every lane)
@@ -147,8 +154,9 @@ __device__ void env_worlds(const DevGroup& G, const EnvArgs& E, float* W, float*
       const float lo = m.act_lo[k], hi = m.act_hi[k];
       const float uk = fminf(fmaxf(u[k], lo), hi);
       const float q = qpos[7 + k], qd = qvel[6 + k];
-      const float tau = m.act_kp[k] * (m.act_qdef[k] + m.act_gear[k] * uk - q) - m.act_kd[k] * qd;
-      const float dq = q - m.act_qdef[k], da = u[k] - aprev[k];
+      const float q0 = dr ? m.act_qdef[k] - dr[kDrHead + k] : m.act_qdef[k];
+      const float tau = skp * m.act_kp[k] * (q0 + m.act_gear[k] * uk - q) - skd * m.act_kd[k] * qd;
+      const float dq = q - q0, da = u[k] - aprev[k];
       jt += kEnvTau * tau * tau + kEnvQ * dq * dq + kEnvRate * da * da;
     }
     jt = t.sum(jt);
@@ -158,10 +166,12 @@ __device__ void env_worlds(const DevGroup& G, const EnvArgs& E, float* W, float*
       if (i < 3) v = gb[i];
       else if (i < 6) v = vb[i - 3];
       else if (i < 9) v = qvel[i - 3];
-      else if (i < 9 + nu) v = qpos[7 + (i - 9)] - m.act_qdef[i - 9];
+      else if (i < 9 + nu) v = qpos[7 + (i - 9)] - (dr ? m.act_qdef[i - 9] - dr[kDrHead + i - 9]
+                                                         : m.act_qdef[i - 9]);
       else if (i < 9 + 2 * nu) v = qvel[6 + (i - 9 - nu)];
       else if (i < 9 + 3 * nu) v = aprev[i - 9 - 2 * nu];
       else v = cmd[i - 9 - 3 * nu];
+      if (E.noise) v += E.noise[((size_t)e * G.nworld + w) * E.nobs + i];
       ob[i] = v;
     }
     if (lane == 0) {
@@ -193,8 +203,9 @@ __device__ void env_worlds(const DevGroup& G, const EnvArgs& E, float* W, float*
   if (lane == 0 && G.status) G.status[w] = status;
 }
 
-// LDS: the pair table, then `ap_words` holding each team's previous action (nu words a
-// team), then the worlds' working sets at the usual stride.
+// LDS: the pair table, then `ap_words` holding each team's previous action and, with
+// randomisation, its parameter record (nu + ndr words a team), then the worlds' working
+// sets at the usual stride.
 __global__ void __launch_bounds__(kMaxBlock, 4)
 mjh_env_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__ tasks,
                EnvArgs E, int tab_words, int ap_words) {
@@ -205,9 +216,10 @@ mjh_env_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__ 
   const int T = G.team;
   const int team = threadIdx.x / T;
   if (team >= tk.nw) return;
-  float* ap = lds + tab_words + team * G.m.nu;
+  float* ap = lds + tab_words + team * (G.m.nu + E.ndr);
   float* W = lds + tab_words + ap_words + (size_t)team * G.m.lds_words;
-  env_worlds(G, E, W, ap, tk.w0 + team, threadIdx.x - team * T, T, (const unsigned char*)lds);
+  env_worlds(G, E, W, ap, E.dr ? ap + G.m.nu : nullptr, tk.w0 + team, threadIdx.x - team * T, T,
+             (const unsigned char*)lds);
 }
 
 // Translational inverse weight of every body at qpos0:

@@ -68,7 +68,7 @@ mjh_set_launch = _sig("mjh_set_launch", P, I32, I32, I32)
 mjh_get_launch = _sig("mjh_get_launch", P, I32, C.POINTER(I32), C.POINTER(I32))
 mjh_rollout_fwd = _sig("mjh_rollout_fwd", P, I32, I32, P, I32, F, F, P, P)
 mjh_rollout_bwd = _sig("mjh_rollout_bwd", P, P, P, P, P)
-mjh_env_step = _sig("mjh_env_step", P, I32, I32, P, P, P, P, P, P, P, P, P)
+mjh_env_step = _sig("mjh_env_step", P, I32, I32, P, P, P, P, P, P, P, P, P, P, P)
 
 
 class MjhError(RuntimeError):
@@ -242,11 +242,13 @@ class Batch:
                                        _stream(stream)))
 
     def env_step(self, nsub: int, action, command, reset_qpos, reset_qvel, last_action, obs,
-                 reward, done, stream=None):
+                 reward, done, params=None, obs_noise=None, stream=None):
         """Joystick env steps of a single-model batch: action [nenv, nworld, nu], command
         [nworld, 3], reset_qpos/reset_qvel [nworld, nq]/[nworld, nv], last_action
         [nworld, nu] (read and updated); writes obs [nenv, nworld, 12 + 3 nu], reward and
-        done [nenv, nworld].  The bound state advances nenv * nsub physics steps."""
+        done [nenv, nworld].  The bound state advances nenv * nsub physics steps.
+        params: per-world randomised parameters [nworld, 8 + 2 nu] or None; obs_noise:
+        [nenv, nworld, 12 + 3 nu] added to obs, or None."""
         if len(self.models) != 1:
             raise ValueError("env steps take a single-model batch")
         m, nw = self.models[0], self.counts[0]
@@ -254,11 +256,16 @@ class Batch:
         shapes = ((action, (nenv, nw, m.nu)), (command, (nw, 3)), (reset_qpos, (nw, m.nq)),
                   (reset_qvel, (nw, m.nv)), (last_action, (nw, m.nu)),
                   (obs, (nenv, nw, 12 + 3 * m.nu)), (reward, (nenv, nw)), (done, (nenv, nw)))
+        if params is not None:
+            shapes += ((params, (nw, 8 + 2 * m.nu)),)
+        if obs_noise is not None:
+            shapes += ((obs_noise, (nenv, nw, 12 + 3 * m.nu)),)
         for t, shp in shapes:
             if tuple(t.shape) != shp or not t.is_contiguous():
                 raise ValueError(f"env_step: expected a contiguous {shp}, got {tuple(t.shape)}")
         self.ctx.check(mjh_env_step(self._h, nenv, int(nsub), _ptr(action), _ptr(command),
-                                    _ptr(reset_qpos), _ptr(reset_qvel), _ptr(last_action),
+                                    _ptr(reset_qpos), _ptr(reset_qvel), _ptr(params),
+                                    _ptr(obs_noise), _ptr(last_action),
                                     _ptr(obs), _ptr(reward), _ptr(done, torch.int32),
                                     _stream(stream)))
 

@@ -1,0 +1,29 @@
+"""Register and scratch budget of the hot kernels, from the compiler's resource-usage
+report of the last build (no GPU).
+
+The step and env kernels run one world's whole step per team with everything inlined
+into the kernel: 128 VGPRs for four waves per SIMD, and a small private segment for
+spills.  A per-world driver left as a real call has a stack frame of several hundred
+bytes per lane (measured: 580 B and 35 % lower throughput), which these bounds catch.
+"""
+import pytest
+
+from paper_2502_08844_amd import build
+
+STEP = "_ZN3mjh15mjh_step_kernelEPKNS_8DevGroupEPKNS_7DevTaskEii"
+ENV = "_ZN3mjh14mjh_env_kernelEPKNS_8DevGroupEPKNS_7DevTaskENS_7EnvArgsEii"
+
+
+@pytest.fixture(scope="module")
+def usage():
+    u = build.resource_usage()
+    if u is None:
+        pytest.skip("no build report yet (run the build first)")
+    return u
+
+
+@pytest.mark.parametrize("kernel,scratch_max", [(STEP, 256), (ENV, 512)])
+def test_hot_kernels_fit_four_waves_with_small_scratch(usage, kernel, scratch_max):
+    k = usage[kernel]
+    assert k["VGPRs"] <= 128 and k["Occupancy"] >= 4
+    assert k["ScratchSize"] <= scratch_max, k

@@ -11,7 +11,13 @@ Checks, on the quadruped from contact-rich states with a share of inverted world
 * end to end against the reference env step from the same float32 state (FP32 against
   FP64 physics over nsub steps): done identical, obs within 1e-3 (1 + |x|) for the
   median world;
-* models without a free root and per-dof position actuators are rejected.
+* models without a free root and per-dof position actuators are rejected;
+* domain randomisation: identity records and zero noise change no bit; with random
+  records (friction, payload, centre of mass, PD gains, calibration, armature) and
+  sensor noise, one physics step's qacc matches each world's randomised reference
+  model at the parity tolerance (1e-4, worlds at a switch reported), the outputs match
+  the float64 formulas of that model, and the end-to-end env step matches the
+  reference env with the same records.
 """
 import numpy as np
 import pytest
@@ -20,7 +26,7 @@ import torch
 import oracle
 from oracle import env as renv
 from paper_2502_08844_amd.synth import inputs, robots
-from tests.gpu_util import gpu_ctx, run_gpu, workload
+from tests.gpu_util import G, compare_step, gpu_ctx, run_gpu, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -33,13 +39,13 @@ def lib():
     return gpu_ctx()
 
 
-def _scene(ctx, mjh, nw, seed):
+def _scene(ctx, mjh, nw, seed, invert=True):
     """Contact-rich quadruped states (50 random-target steps), every fifth world turned
     upside down 0.45 m up; commands and actions drawn per world."""
     m, qp, qv, u = workload("quadruped", nw, 50, seed=seed)
     r = run_gpu(ctx, mjh, m, qp, qv, None, u, 50, contacts=False)
     qp, qv, ws = r["qpos"], r["qvel"], r["qacc"]
-    inv = np.arange(nw) % 5 == 3
+    inv = (np.arange(nw) % 5 == 3) & invert
     qp[inv, 2] = 0.45
     qp[inv, 3:7] = (0.0, 1.0, 0.0, 0.0)
     rng = np.random.default_rng(seed + 100)
@@ -55,7 +61,8 @@ def _dev(x, dtype=torch.float32):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda").contiguous()
 
 
-def _env_gpu(ctx, mjh, m, qp, qv, ws, acts, cmd, reset_q, reset_v, prev, nsub=NSUB):
+def _env_gpu(ctx, mjh, m, qp, qv, ws, acts, cmd, reset_q, reset_v, prev, nsub=NSUB, dr=None,
+             noise=None):
     nenv, nw = acts.shape[:2]
     w = mjh.World(ctx, m, nw, qpos=qp, qvel=qv)
     w.qacc_ws.copy_(_dev(ws))
@@ -64,7 +71,8 @@ def _env_gpu(ctx, mjh, m, qp, qv, ws, acts, cmd, reset_q, reset_v, prev, nsub=NS
     rew = torch.zeros(nenv, nw, device="cuda")
     done = torch.zeros(nenv, nw, dtype=torch.int32, device="cuda")
     w.batch.env_step(nsub, _dev(acts), _dev(cmd), _dev(reset_q), _dev(reset_v), la, obs, rew,
-                     done)
+                     done, params=None if dr is None else _dev(dr),
+                     obs_noise=None if noise is None else _dev(noise))
     torch.cuda.synchronize()
     f = lambda t: t.cpu().double().numpy()
     return dict(obs=f(obs), reward=f(rew), done=done.cpu().numpy().astype(bool), qpos=f(w.qpos),
@@ -153,3 +161,86 @@ def test_env_step_rejects_other_models(lib):
         w.batch.env_step(1, z(1, 4, m.nu), z(4, 3), z(4, m.nq), z(4, m.nv), z(4, m.nu),
                          z(1, 4, 12 + 3 * m.nu), z(1, 4),
                          torch.zeros(1, 4, dtype=torch.int32, device="cuda"))
+
+
+def _records(m, nw, seed):
+    """Random per-world parameters in the ranges of the paper's randomisation (friction
+    0.4-1.25, payload -0.5-2 kg, centre of mass +-3 cm, gains +-20 %, calibration +-0.05
+    rad, armature 0-0.02 kg m^2)."""
+    rng = np.random.default_rng(seed)
+    rec = np.zeros((nw, 8 + 2 * m.nu))
+    rec[:, 0] = rng.uniform(0.4, 1.25, nw)
+    rec[:, 1] = rng.uniform(-0.5, 2.0, nw)
+    rec[:, 2:5] = rng.uniform(-0.03, 0.03, (nw, 3))
+    rec[:, 5:7] = rng.uniform(0.8, 1.2, (nw, 2))
+    rec[:, 8:8 + m.nu] = rng.uniform(-0.05, 0.05, (nw, m.nu))
+    rec[:, 8 + m.nu:] = rng.uniform(0.0, 0.02, (nw, m.nu))
+    return inputs.f32(rec)
+
+
+def test_identity_records_change_nothing(lib):
+    mjh, ctx = lib
+    nw = 96
+    print(f"[gpu] env step identity records nw={nw}", flush=True)
+    m, qp, qv, ws, cmd, rq, rv, prev, inv = _scene(ctx, mjh, nw, seed=21)
+    act = inputs.f32(np.random.default_rng(3).uniform(-0.6, 0.6, size=(2, nw, m.nu)))
+    ref = _env_gpu(ctx, mjh, m, qp, qv, ws, act, cmd, rq, rv, prev)
+    dr = np.stack([renv.dr_identity(m)] * nw)
+    got = _env_gpu(ctx, mjh, m, qp, qv, ws, act, cmd, rq, rv, prev, dr=dr,
+                   noise=np.zeros((2, nw, 12 + 3 * m.nu)))
+    for k in ("obs", "reward", "done", "qpos", "qvel", "qacc", "last_action"):
+        np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+
+
+def test_randomised_physics_step_parity(lib):
+    """nsub = 1 from the same float32 state: the written-back warm start is the step's
+    a*, compared per world with the reference built from that world's record."""
+    mjh, ctx = lib
+    nw = 128
+    print(f"[gpu] env step randomised physics parity nw={nw}", flush=True)
+    m, qp, qv, ws, cmd, rq, rv, prev, _ = _scene(ctx, mjh, nw, seed=23, invert=False)
+    dr = _records(m, nw, seed=5)
+    act = inputs.f32(np.random.default_rng(6).uniform(-0.6, 0.6, size=(1, nw, m.nu)))
+    noise = inputs.f32(np.random.default_rng(8).normal(scale=0.01, size=(1, nw, 48)))
+    g = _env_gpu(ctx, mjh, m, qp, qv, ws, act, cmd, rq, rv, prev, nsub=1, dr=dr, noise=noise)
+    assert not g["done"].any() and np.all(g["status"] & 1 == 0)
+    o = oracle.Oracle(m)
+    err, flag, eo, er = np.zeros(nw), np.zeros(nw, dtype=bool), 0.0, 0.0
+    for w in range(nw):
+        mw = renv.randomized_model(m, dr[w])
+        ow = renv.randomized_oracle(o, m, dr[w])
+        st = (qp[w:w + 1], qv[w:w + 1], ws[w:w + 1])
+        ref = ow.step(*(x.copy() for x in st), act[:, w:w + 1], nstep=1)
+        gpu1 = {"qacc": g["qacc"][w:w + 1], "ncon": ref["ncon"], "contacts": ref["contacts"]}
+        cmp = compare_step(mw, ow, st, act[:, w:w + 1], gpu1)
+        err[w], flag[w] = cmp["err_a"][0], cmp["flag"][0]
+        # the outputs from the GPU's own post-step state, by this world's model
+        qn, vn = g["qpos"][w], g["qvel"][w]
+        o_ref = renv.observe(mw, qn, vn, prev[w], cmd[w], noise[0, w])
+        r_ref, _ = renv.reward_done(mw, qn, vn, act[0, w], prev[w], cmd[w])
+        eo = max(eo, (np.abs(g["obs"][0, w] - o_ref) / (1 + np.abs(o_ref))).max())
+        er = max(er, abs(g["reward"][0, w] - r_ref) / (1 + abs(r_ref)))
+    print(f"[gpu] randomised qacc rel err max {err[~flag].max():.2e} median {np.median(err):.2e};"
+          f" near-switch {flag.sum()}/{nw}; obs err {eo:.1e} reward err {er:.1e}", flush=True)
+    assert err[~flag].max() <= 1e-4 and flag.sum() <= 0.25 * nw
+    assert eo <= OUT_TOL and er <= OUT_TOL
+
+
+def test_randomised_env_step_against_reference_env(lib):
+    mjh, ctx = lib
+    nw = 48
+    print(f"[gpu] randomised env step end to end nw={nw}", flush=True)
+    m, qp, qv, ws, cmd, rq, rv, prev, inv = _scene(ctx, mjh, nw, seed=27)
+    dr = _records(m, nw, seed=9)
+    act = inputs.f32(np.random.default_rng(10).uniform(-0.6, 0.6, size=(1, nw, m.nu)))
+    noise = inputs.f32(np.random.default_rng(11).normal(scale=0.01, size=(1, nw, 48)))
+    g = _env_gpu(ctx, mjh, m, qp, qv, ws, act, cmd, rq, rv, prev, dr=dr, noise=noise)
+    obs, rew, done, (q, v, w_, pa) = renv.env_step(oracle.Oracle(m), m, qp, qv, ws, prev,
+                                                  act[0], cmd, rq, rv, NSUB, dr=dr,
+                                                  noise=noise[0])
+    assert np.array_equal(g["done"][0], done) and np.array_equal(done, inv)
+    err = (np.abs(g["obs"][0] - obs) / (1 + np.abs(obs))).max(1)
+    print(f"[gpu] randomised env obs vs FP64 env: median {np.median(err):.1e} "
+          f"max {err.max():.1e}", flush=True)
+    assert np.median(err) <= 1e-3
+    np.testing.assert_array_equal(g["last_action"], pa.astype(np.float32))
