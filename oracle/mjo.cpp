@@ -237,7 +237,8 @@ struct Model {
   std::vector<int> act_type, act_jnt;
   std::vector<double> act_gear, act_kp, act_kd, act_range, act_qdef;
   int neq = 0;
-  int integrator = 0;  // 0: semi-implicit Euler; 1: the same with implicit damping
+  int integrator = 0;  // 0: semi-implicit Euler; 1: with implicit damping; 2: also implicit
+                       // PD position gains
   // heightfield: nrow x ncol elevations in [0, 1] over [-sx, sx] x [-sy, sy], z = sz h
   int hf_nrow = 0, hf_ncol = 0;
   double hf_size[3] = {0, 0, 0};
@@ -1329,16 +1330,24 @@ template <class T> void forward(const Model& m, Data<T>& d, int mode) {
   // the velocity gain kd of a position actuator on it) act at the end-of-step velocity
   // qvel + h a, so the integrator's acceleration solves
   //   (M + h diag(b + kd)) a_int = qfrc_smooth + qfrc_con,
-  // with the constraint forces of the solve above (which used M).
-  if (m.integrator == 1) {
+  // with the constraint forces of the solve above (which used M).  Integrator 2 also
+  // takes a position actuator's stiffness kp at the end-of-step position q + h qvel'
+  // (qvel' = qvel + h a): its force gains -kp h (qvel + h a), so
+  //   (M + h diag(b + kd) + h^2 diag(kp)) a_int = qfrc_smooth - h diag(kp) qvel + qfrc_con,
+  // which for a linear spring-damper is backward Euler.
+  if (m.integrator >= 1) {
     std::vector<T> Mt(d.M), LD(m.nv * m.nv), rhs(m.nv);
     for (int k = 0; k < m.nv; k++) Mt[k * m.nv + k] += m.dt * m.dof_damping[k];
+    for (int k = 0; k < m.nv; k++) rhs[k] = d.qfrc_smooth[k] + d.qfrc_con[k];
     for (int a = 0; a < m.nu; a++)
       if (m.act_type[a] == APD) {
         const int k = m.jnt_dofadr[m.act_jnt[a]];
         Mt[k * m.nv + k] += m.dt * m.act_kd[a];
+        if (m.integrator == 2) {
+          Mt[k * m.nv + k] += m.dt * m.dt * m.act_kp[a];
+          rhs[k] -= m.dt * m.act_kp[a] * d.qvel[k];
+        }
       }
-    for (int k = 0; k < m.nv; k++) rhs[k] = d.qfrc_smooth[k] + d.qfrc_con[k];
     factor_ltdl(m, Mt, LD);
     solve_ltdl(m, LD, rhs.data(), d.qacc_int.data());
   } else {
@@ -1405,7 +1414,7 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   for (int k = 0; k < 5; k++) m.solimp[k] = hf[6 + k];
   m.tolerance = hf[11];
   if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nconmax < 0 ||
-      m.neq < 0 || m.integrator < 0 || m.integrator > 1 || has_hf < 0 || has_hf > 1) {
+      m.neq < 0 || m.integrator < 0 || m.integrator > 2 || has_hf < 0 || has_hf > 1) {
     err = "negative size"; return false;
   }
   std::vector<int32_t> bi(2 * m.nbody);

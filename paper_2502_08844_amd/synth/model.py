@@ -12,7 +12,8 @@ Blob layout (little endian, version 2), every block 8-byte aligned:
 
   header   int32[16]  : magic 0x4D484A4D ('MJHM'), version, nbody, njnt, ngeom, npair,
                         nu, nq, nv, iterations, ls_iterations, nconmax, neq,
-                        integrator (0 semi-implicit Euler, 1 with implicit damping),
+                        integrator (0 semi-implicit Euler, 1 with implicit damping, 2 also with
+                        implicit PD position gains),
                         hfield (1 if the model has a heightfield), 0
            float64[16]: timestep, gravity[3], solref[2], solimp[5], tolerance, 0 x4
   body     int32 [nbody][2] : parent, 0
@@ -145,7 +146,8 @@ class Options:
     iterations: int = 4
     ls_iterations: int = 8
     nconmax: int = 0
-    integrator: int = 0  # 1: joint damping and PD velocity gains taken implicitly
+    integrator: int = 0  # 1: joint damping and PD velocity gains taken implicitly;
+                         # 2: also the PD position gains (at the end-of-step position)
 
 
 @dataclass

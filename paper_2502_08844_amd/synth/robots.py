@@ -231,7 +231,7 @@ QUAD_FRICTIONLOSS = 3.0
 
 def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
               limits: bool = False, frictionloss: float = 0.0, tether: bool = False,
-              implicit: bool = False) -> Model:
+              implicit: int = 0) -> Model:
     """Free torso (box 0.3x0.1x0.05 m, 5 kg) + 4 legs x 3 hinges (capsules r 0.02,
     length 0.2, 0.5 kg) with massless sphere feet (r 0.025).  nq 19, nv 18, nu 12.
 
@@ -241,8 +241,8 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     the 12 are active on average, up to 7).  With ``frictionloss`` every hinge carries
     that dry friction (one friction-loss row each).  With ``tether`` the torso's centre
     is held by a connect equality on its standing position (a gantry tether: three
-    two-sided rows).  With ``implicit`` the PD velocity gains are integrated implicitly
-    (integrator 1).
+    two-sided rows).  With ``implicit`` = 1 the PD velocity gains are integrated
+    implicitly (integrator 1); with 2 the PD position gains as well (integrator 2).
 
     Each leg: hip link (hinge about x, capsule lateral 0.2 m), thigh (hinge about y,
     capsule down 0.2 m), shin (hinge about y, capsule down 0.2 m, foot sphere).
@@ -251,7 +251,8 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     """
     bld = _Builder("quadruped" + ("_limits" if limits else "") +
                    ("_friction" if frictionloss > 0 else "") + ("_tethered" if tether else "") +
-                   ("_implicit" if implicit else ""))
+                   ("_implicit" if implicit == 1 else "") +
+                   ("_implicit_pd" if implicit == 2 else ""))
 
     def rng(k):
         if not limits:
@@ -287,7 +288,7 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     if tether:
         bld.connect(torso, 0, (0, 0, 0), (0, 0, QUAD_STAND_Z))
     m.opt = Options(timestep=timestep, iterations=iterations, ls_iterations=8,
-                    nconmax=4, integrator=1 if implicit else 0)
+                    nconmax=4, integrator=int(implicit))
     q0 = np.zeros(m.nq)
     q0[0:3] = (0, 0, QUAD_STAND_Z)
     q0[3] = 1.0
@@ -546,7 +547,12 @@ def sphere_on_hfield(data: np.ndarray, size=(1.0, 1.0, 0.2), radius: float = 0.1
 
 def quadruped_implicit() -> Model:
     """The quadruped with its PD velocity gains integrated implicitly."""
-    return quadruped(implicit=True)
+    return quadruped(implicit=1)
+
+
+def quadruped_implicit_pd() -> Model:
+    """The quadruped with its PD velocity and position gains integrated implicitly."""
+    return quadruped(implicit=2)
 
 
 def quadruped_friction() -> Model:
@@ -725,6 +731,7 @@ WORKLOADS = {
     "quadruped_friction": quadruped_friction,
     "quadruped_tethered": quadruped_tethered,
     "quadruped_implicit": quadruped_implicit,
+    "quadruped_implicit_pd": quadruped_implicit_pd,
     "quadruped_rough": quadruped_rough,
     "humanoid": humanoid,
     "hand": hand,

@@ -89,3 +89,67 @@ def test_implicit_update_with_contacts(mode):
         np.testing.assert_allclose(lhs, f["M"] @ f["qacc"], rtol=1e-9, atol=1e-9)
         # the reported acceleration (and the warm start) is the solve's a* in both
         np.testing.assert_allclose(r1["qacc"][0], r0["qacc"][0], rtol=0, atol=0)
+
+
+# ------------------------------------------------------------------ integrator 2
+def _pd_slider(mass, kp, kd, h, qdef=0.0, integrator=2):
+    m = robots.slider(mass=mass, range=None, gravity=(0, 0, 0), timestep=h,
+                      integrator=integrator)
+    m.actuators.append(Actuator(type=ACT_PD, joint=0, kp=kp, kd=kd, qdefault=qdef,
+                                ctrlrange=(-10.0, 10.0)))
+    return m
+
+
+def test_implicit_pd_is_backward_euler_of_the_spring_damper():
+    """With its stiffness and damping at the end of the step, a PD slider's update is
+    backward Euler of x' = A x (x = (q - q_des, qdot), A = [[0, 1], [-kp/m, -kd/m]]):
+    x_{n+1} = (I - h A)^-1 x_n, a linear solve independent of the step's arithmetic."""
+    mass, kp, kd, h, qdes = 1.5, 40.0, 0.8, 0.01, 0.3
+    m = _pd_slider(mass, kp, kd, h)
+    o = Oracle(m)
+    q, v = np.array([[-0.2]]), np.array([[0.7]])
+    A = np.array([[0.0, 1.0], [-kp / mass, -kd / mass]])
+    x = np.array([q[0, 0] - qdes, v[0, 0]])
+    u = np.full((1, 1, 1), qdes)
+    for _ in range(25):
+        r = o.step(q, v, None, u, nstep=1)
+        q, v = r["qpos"], r["qvel"]
+        x = np.linalg.solve(np.eye(2) - h * A, x)
+        assert q[0, 0] - qdes == pytest.approx(x[0], rel=1e-12, abs=1e-14)
+        assert v[0, 0] == pytest.approx(x[1], rel=1e-12, abs=1e-14)
+
+
+def test_stiff_pd_stable_only_with_implicit_stiffness():
+    """h^2 kp / m = 9 (h omega = 3 > 2): semi-implicit Euler (with or without implicit
+    damping) of the undamped spring diverges; with implicit stiffness it decays."""
+    mass, kp, h = 1.0, 90000.0, 0.01
+    amp = {}
+    for integ in (0, 1, 2):
+        m = _pd_slider(mass, kp, 0.0, h, integrator=integ)
+        r = Oracle(m).step(np.array([[0.1]]), np.zeros((1, 1)), None, np.zeros((40, 1, 1)),
+                           nstep=40)
+        amp[integ] = abs(r["qpos"][0, 0])
+    assert amp[0] > 1e3 and amp[1] > 1e3
+    assert amp[2] < 0.1 * 0.1
+
+
+def test_implicit_pd_update_with_contacts():
+    """(M + h B + h^2 K)(v' - v)/h = M a* - h K v: the update keeps the explicit solve's
+    generalized force and adds the stiffness and damping at the step's end."""
+    m2, m0 = robots.quadruped_implicit_pd(), robots.quadruped()
+    o2, o0 = Oracle(m2), Oracle(m0)
+    qp, qv = inputs.initial_state("quadruped", m0, 4, seed=5)
+    qv = inputs.f32(np.random.default_rng(1).normal(scale=0.5, size=qv.shape))
+    u = inputs.controls("quadruped", m0, 4, 1, seed=5)
+    h = m2.opt.timestep
+    B, K = np.zeros(m2.nv), np.zeros(m2.nv)
+    for a in m2.actuators:
+        B[m2.jnt_dofadr()[a.joint]] += a.kd
+        K[m2.jnt_dofadr()[a.joint]] += a.kp
+    for w in range(4):
+        f = o0.forward(qp[w], qv[w], ctrl=u[0, w])
+        r2 = o2.step(qp[w:w + 1].copy(), qv[w:w + 1].copy(), None, u[:, w:w + 1], nstep=1)
+        dv = (r2["qvel"][0] - qv[w]) / h
+        lhs = (f["M"] + h * np.diag(B) + h * h * np.diag(K)) @ dv
+        np.testing.assert_allclose(lhs, f["M"] @ f["qacc"] - h * K * qv[w], rtol=1e-9,
+                                   atol=1e-9)
