@@ -461,6 +461,9 @@ def main():
         out["implicit_damping"] = constraint_compare(
             ctx, args.seed, "quadruped_implicit",
             "its PD velocity gains integrated implicitly")
+        out["implicit_pd"] = constraint_compare(
+            ctx, args.seed, "quadruped_implicit_pd",
+            "its PD velocity and position gains integrated implicitly")
         out["rough_terrain"] = constraint_compare(
             ctx, args.seed, "quadruped_rough",
             "its feet on 4 m x 4 m Perlin-noise terrain (64 x 64 heightfield, 6 cm relief)")

@@ -82,7 +82,7 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nq < 0 ||
       m.nv < 0 || m.iterations < 0 || m.nconmax < 0 || m.nbody > 4096 || m.njnt > 4096 ||
       m.ngeom > 4096 || m.npair > 65536 || m.nu > 4096 || m.nconmax > 4096 || m.neq < 0 ||
-      m.neq > 1024 || m.integrator < 0 || m.integrator > 1 || has_hf < 0 || has_hf > 1) {
+      m.neq > 1024 || m.integrator < 0 || m.integrator > 2 || has_hf < 0 || has_hf > 1) {
     err = "model blob: size field out of range";
     return MJH_EMODEL;
   }
@@ -329,13 +329,22 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   child_start[h.nbody] = (int)child_list.size();
   // actuators: one per dof at most
   std::vector<int> dof_act(h.nv, -1), act_qadr, act_dadr;
-  std::vector<float> dof_vgain(dof_damping);
+  // implicit gains: h (b + kd) + h^2 kp on the factor's diagonal is h times dof_vgain
+  // with dof_vgain = b + kd + h kp; dof_hkp = h kp scales qvel on the right-hand side
+  // (integrator 2 only)
+  std::vector<float> dof_vgain(dof_damping), dof_hkp(h.nv, 0.f);
   for (int a = 0; a < h.nu; a++) {
     const int j = h.act_jnt[a];
     const int dof = jnt_dofadr[j];
     if (dof_act[dof] >= 0) { err = "two actuators on one dof are not supported"; return MJH_EUNSUPPORTED; }
     dof_act[dof] = a;
-    if (h.act_type[a] == ACT_PD) dof_vgain[dof] += (float)h.act_kd[a];
+    if (h.act_type[a] == ACT_PD) {
+      dof_vgain[dof] += (float)h.act_kd[a];
+      if (h.integrator == 2) {
+        dof_vgain[dof] += (float)(h.dt * h.act_kp[a]);
+        dof_hkp[dof] = (float)(h.dt * h.act_kp[a]);
+      }
+    }
     act_qadr.push_back(jnt_qposadr[j]);
     act_dadr.push_back(dof);
   }
@@ -442,6 +451,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   pk.add(dof_armature, &d.dof_armature);
   pk.add(dof_damping, &d.dof_damping);
   pk.add(dof_vgain, &d.dof_vgain);
+  pk.add(dof_hkp, &d.dof_hkp);
   pk.add(gsize, &d.geom_size);
   pk.add(gpos, &d.geom_pos);
   pk.add(geom_rot, &d.geom_rot);

@@ -1669,8 +1669,11 @@ DEV void integrate(const DevModel& m, float* W, const Team& t, int& status) {
 // Implicit damping (integrator 1): the forces linear in a dof's own velocity (joint
 // damping, PD velocity gains) act at the end-of-step velocity, so the integrator's
 // acceleration solves (M + h diag(b + kd)) a_int = qfrc_smooth + J^T f, with the row
-// forces f of the solve that used M (f = -s'(e) per row piece).  a_int replaces the
-// smooth force in o_frc; qacc keeps the solve's a* (reported, and the warm start).
+// forces f of the solve that used M (f = -s'(e) per row piece).  Integrator 2 also
+// takes the PD stiffness at the end-of-step position q + h qvel': the matrix gains
+// h^2 diag(kp) (folded into dof_vgain) and the right-hand side -h diag(kp) qvel.
+// a_int replaces the smooth force in o_frc; qacc keeps the solve's a* (reported, and
+// the warm start).
 DEV void implicit_damping(const DevModel& m, float* W, const Team& t) {
   const int* scal = (const int*)(W + m.o_scal);
   const int nv = m.nv, nrow = scal[SC_NROW];
@@ -1680,8 +1683,9 @@ DEV void implicit_damping(const DevModel& m, float* W, const Team& t) {
   const float* fl = W + m.o_fl;
   const bool fr = has_bounds(m);
   float* rhs = W + m.o_frc;
+  const float* qvel = W + m.o_qvel;
   for (int i = t.lane; i < nv; i += t.T) {
-    float v = rhs[i];
+    float v = m.implicit == 2 ? rhs[i] - m.dof_hkp[i] * qvel[i] : rhs[i];
     for (int r = 0; r < nrow; r++)
       v -= (fr ? row_slope(D[r], fl[r], e[r]) : fminf(D[r] * e[r], 0.f)) * J[r * nv + i];
     rhs[i] = v;

@@ -35,7 +35,8 @@ struct DevModel {
   // ---- sizes
   int nbody, njnt, nq, nv, nu, ngeom, npair, ncand, nconmax, nlim, nfric, neq, nrowmax;
   int iterations, nlevel, nmpair, ntri;
-  int implicit;  // 1: joint damping and PD velocity gains integrated implicitly
+  int implicit;  // 1: joint damping and PD velocity gains integrated implicitly;
+                 // 2: also the PD position gains
   int hf_nrow, hf_ncol;  // heightfield grid (0 without one)
   float hf_size[3];      // half extents x, y and the height scale
   // ---- constants
@@ -88,6 +89,9 @@ struct DevModel {
   const float* dof_armature;
   const float* dof_damping;
   const float* dof_vgain;     // [nv] damping + velocity gains of PD actuators on the dof
+                              // (+ h kp with implicit position gains)
+  const float* dof_hkp;       // [nv] h kp of a PD actuator on the dof (implicit position
+                              // gains only, else 0)
   const float* geom_size;     // [ngeom][3]
   const float* geom_pos;      // [ngeom][3]
   const float* geom_rot;      // [ngeom][9]

@@ -1,5 +1,6 @@
-"""GPU parity of the implicit-damping integrator (joint damping and PD velocity gains
-taken at the end-of-step velocity) against the FP64 reference.
+"""GPU parity of the implicit integrators against the FP64 reference: integrator 1
+(joint damping and PD velocity gains taken at the end-of-step velocity) and integrator 2
+(also the PD position gains at the end-of-step position).
 
 The compared quantity is the integrator's acceleration a_int = (qvel' - qvel) / h of
 one step from the same float32 state (the reported qacc is the solve's a*, covered by
@@ -45,15 +46,19 @@ def _a_int_errors(ctx, mjh, m, qp, qv, ws, u1, team=None, block=None):
     return err, cmp["flag"], g
 
 
-@pytest.mark.parametrize("team,block", [(32, 128), (64, 64), (16, 64)])
-def test_quadruped_implicit_velocity_update(lib, team, block):
+@pytest.mark.parametrize("kind,team,block", [("quadruped_implicit", 32, 128),
+                                             ("quadruped_implicit", 64, 64),
+                                             ("quadruped_implicit", 16, 64),
+                                             ("quadruped_implicit_pd", 32, 128),
+                                             ("quadruped_implicit_pd", 16, 64)])
+def test_quadruped_implicit_velocity_update(lib, kind, team, block):
     mjh, ctx = lib
-    m, qp, qv, u = workload("quadruped_implicit", 203, 51, seed=4)
+    m, qp, qv, u = workload(kind, 203, 51, seed=4)
     # advance on the GPU to a contact-rich state, then compare one step
     r = run_gpu(ctx, mjh, m, qp, qv, None, u[:50], 50, team, block, contacts=False)
     err, flag, g = _a_int_errors(ctx, mjh, m, r["qpos"], r["qvel"], r["qacc"], u[50:51], team,
                                  block)
-    print(f"[parity] quadruped_implicit-T{team}: a_int rel err max {err[~flag].max():.2e} "
+    print(f"[parity] {kind}-T{team}: a_int rel err max {err[~flag].max():.2e} "
           f"median {np.median(err):.2e}; near-switch states {flag.sum()}/{len(flag)}"
           + (f" (their err max {err[flag].max():.2e})" if flag.any() else ""), flush=True)
     assert np.all(g["status"] & 1 == 0)
@@ -71,6 +76,24 @@ def test_stiff_damping_decays_on_gpu(lib):
     qv = np.full((64, 1), 1.0)
     r = run_gpu(ctx, mjh, m, np.zeros((64, 1)), qv, None, None, 10, contacts=False)
     np.testing.assert_allclose(r["qvel"][:, 0], (1 / 6) ** 10, rtol=1e-5)
+
+
+def test_stiff_pd_decays_on_gpu(lib):
+    """Integrator 2 on a PD slider with h^2 kp / m = 9: backward Euler of the spring,
+    x_{n+1} = (I - h A)^-1 x_n, where semi-implicit Euler would grow sevenfold a step."""
+    mjh, ctx = lib
+    from paper_2502_08844_amd.synth.model import ACT_PD, Actuator
+    mass, kp, h = 1.0, 90000.0, 0.01
+    m = robots.slider(mass=mass, range=None, gravity=(0, 0, 0), timestep=h, integrator=2)
+    m.actuators.append(Actuator(type=ACT_PD, joint=0, kp=kp, kd=0.0, ctrlrange=(-1, 1)))
+    r = run_gpu(ctx, mjh, m, np.full((64, 1), 0.1), np.zeros((64, 1)), None,
+                np.zeros((10, 64, 1)), 10, contacts=False)
+    A = np.array([[0.0, 1.0], [-kp / mass, 0.0]])
+    x = np.array([0.1, 0.0])
+    for _ in range(10):
+        x = np.linalg.solve(np.eye(2) - h * A, x)
+    np.testing.assert_allclose(r["qpos"][:, 0], x[0], rtol=1e-4, atol=1e-9)
+    np.testing.assert_allclose(r["qvel"][:, 0], x[1], rtol=1e-4, atol=1e-7)
 
 
 def test_rollout_rejects_implicit(lib):
