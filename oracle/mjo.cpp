@@ -238,7 +238,7 @@ struct Model {
   std::vector<double> act_gear, act_kp, act_kd, act_range, act_qdef;
   int neq = 0;
   int integrator = 0;  // 0: semi-implicit Euler; 1: with implicit damping; 2: also implicit
-                       // PD position gains
+                       // PD position gains; 3: classic fourth-order Runge-Kutta
   // heightfield: nrow x ncol elevations in [0, 1] over [-sx, sx] x [-sy, sy], z = sz h
   int hf_nrow = 0, hf_ncol = 0;
   double hf_size[3] = {0, 0, 0};
@@ -1335,7 +1335,7 @@ template <class T> void forward(const Model& m, Data<T>& d, int mode) {
   // (qvel' = qvel + h a): its force gains -kp h (qvel + h a), so
   //   (M + h diag(b + kd) + h^2 diag(kp)) a_int = qfrc_smooth - h diag(kp) qvel + qfrc_con,
   // which for a linear spring-damper is backward Euler.
-  if (m.integrator >= 1) {
+  if (m.integrator == 1 || m.integrator == 2) {
     std::vector<T> Mt(d.M), LD(m.nv * m.nv), rhs(m.nv);
     for (int k = 0; k < m.nv; k++) Mt[k * m.nv + k] += m.dt * m.dof_damping[k];
     for (int k = 0; k < m.nv; k++) rhs[k] = d.qfrc_smooth[k] + d.qfrc_con[k];
@@ -1355,16 +1355,16 @@ template <class T> void forward(const Model& m, Data<T>& d, int mode) {
   }
 }
 
-// A11: semi-implicit Euler; free-joint orientation by the exponential map of the
-// body-frame angular velocity
-template <class T> void integrate(const Model& m, Data<T>& d) {
-  const double h = m.dt;
-  for (int i = 0; i < m.nv; i++) d.qvel[i] = d.qvel[i] + h * d.qacc_int[i];
+// Position update q <- q (+) h vel: hinge and slide coordinates add h vel; a free
+// joint's position adds h v and its orientation turns by the exponential map of the
+// body-frame rotation h w.
+template <class T> void integrate_pos(const Model& m, std::vector<T>& qpos, const std::vector<T>& vel,
+                                      double h) {
   for (int j = 0; j < m.njnt; j++) {
     const int qa = m.jnt_qposadr[j], da = m.jnt_dofadr[j];
     if (m.jnt_type[j] == JFREE) {
-      for (int k = 0; k < 3; k++) d.qpos[qa + k] = d.qpos[qa + k] + h * d.qvel[da + k];
-      T w[3] = {d.qvel[da + 3] * h, d.qvel[da + 4] * h, d.qvel[da + 5] * h};
+      for (int k = 0; k < 3; k++) qpos[qa + k] = qpos[qa + k] + h * vel[da + k];
+      T w[3] = {vel[da + 3] * h, vel[da + 4] * h, vel[da + 5] * h};
       T ang = norm3(w);
       T dq[4];
       if (ang > 1e-15) {
@@ -1373,14 +1373,21 @@ template <class T> void integrate(const Model& m, Data<T>& d) {
       } else {
         dq[0] = 1.0; dq[1] = 0.5 * w[0]; dq[2] = 0.5 * w[1]; dq[3] = 0.5 * w[2];
       }
-      T q[4] = {d.qpos[qa + 3], d.qpos[qa + 4], d.qpos[qa + 5], d.qpos[qa + 6]}, r[4];
+      T q[4] = {qpos[qa + 3], qpos[qa + 4], qpos[qa + 5], qpos[qa + 6]}, r[4];
       quatmul(q, dq, r);
       T L = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
-      for (int k = 0; k < 4; k++) d.qpos[qa + 3 + k] = r[k] / L;
+      for (int k = 0; k < 4; k++) qpos[qa + 3 + k] = r[k] / L;
     } else {
-      d.qpos[qa] = d.qpos[qa] + h * d.qvel[da];
+      qpos[qa] = qpos[qa] + h * vel[da];
     }
   }
+}
+
+// A11: semi-implicit Euler (velocity first, then positions with the new velocity)
+template <class T> void integrate(const Model& m, Data<T>& d) {
+  const double h = m.dt;
+  for (int i = 0; i < m.nv; i++) d.qvel[i] = d.qvel[i] + h * d.qacc_int[i];
+  integrate_pos(m, d.qpos, d.qvel, h);
   d.qacc_ws = d.qacc;
   bool fin = true;
   for (auto& x : d.qpos) fin = fin && isfinite(x);
@@ -1388,7 +1395,54 @@ template <class T> void integrate(const Model& m, Data<T>& d) {
   if (!fin) d.status |= ST_NONFINITE;
 }
 
+// Integrator 3: classic fourth-order Runge-Kutta on (q, qdot) with the whole forward
+// pass (collision, constraint rows and their solve) at every stage, as in MuJoCo's RK4.
+// Stage k's state is X_k = (q0 (+) c_k h v_{k-1}, v0 + c_k h a_{k-1}) with c = (0, 1/2,
+// 1/2, 1), v_k its velocity and a_k its acceleration; each stage's solve starts from
+// the previous stage's solution.  Then q <- q0 (+) h/6 (v1 + 2 v2 + 2 v3 + v4) and
+// qdot <- v0 + h/6 (a1 + 2 a2 + 2 a3 + a4).  The reported acceleration, the next warm
+// start and the other outputs (contacts, rows) are the first stage's.
+template <class T> void step_rk4(const Model& m, Data<T>& d, int mode) {
+  const double h = m.dt;
+  const std::vector<T> q0 = d.qpos, v0 = d.qvel;
+  forward(m, d, mode);
+  Data<T> d1 = d;  // the first stage's outputs
+  static const double c[4] = {0.0, 0.5, 0.5, 1.0}, b[4] = {1.0, 2.0, 2.0, 1.0};
+  std::vector<T> vsum(m.nv), asum(m.nv);
+  for (int i = 0; i < m.nv; i++) { vsum[i] = b[0] * v0[i]; asum[i] = b[0] * d.qacc[i]; }
+  int status = d.status;
+  for (int k = 1; k < 4; k++) {
+    std::vector<T> vprev = d.qvel, aprev = d.qacc;
+    d.qpos = q0;
+    integrate_pos(m, d.qpos, vprev, c[k] * h);
+    for (int i = 0; i < m.nv; i++) d.qvel[i] = v0[i] + c[k] * h * aprev[i];
+    d.qacc_ws = aprev;
+    forward(m, d, mode);
+    status |= d.status;
+    for (int i = 0; i < m.nv; i++) {
+      vsum[i] = vsum[i] + b[k] * d.qvel[i];
+      asum[i] = asum[i] + b[k] * d.qacc[i];
+    }
+  }
+  std::vector<T> vel(m.nv);
+  for (int i = 0; i < m.nv; i++) vel[i] = vsum[i] / 6.0;
+  d = d1;
+  d.qpos = q0;
+  integrate_pos(m, d.qpos, vel, h);
+  for (int i = 0; i < m.nv; i++) d.qvel[i] = v0[i] + h * asum[i] / 6.0;
+  d.qacc_ws = d1.qacc;
+  d.status = status;
+  bool fin = true;
+  for (auto& x : d.qpos) fin = fin && isfinite(x);
+  for (auto& x : d.qvel) fin = fin && isfinite(x);
+  if (!fin) d.status |= ST_NONFINITE;
+}
+
 template <class T> void step(const Model& m, Data<T>& d, int mode) {
+  if (m.integrator == 3) {
+    step_rk4(m, d, mode);
+    return;
+  }
   forward(m, d, mode);
   integrate(m, d);
 }
@@ -1414,7 +1468,7 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   for (int k = 0; k < 5; k++) m.solimp[k] = hf[6 + k];
   m.tolerance = hf[11];
   if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nconmax < 0 ||
-      m.neq < 0 || m.integrator < 0 || m.integrator > 2 || has_hf < 0 || has_hf > 1) {
+      m.neq < 0 || m.integrator < 0 || m.integrator > 3 || has_hf < 0 || has_hf > 1) {
     err = "negative size"; return false;
   }
   std::vector<int32_t> bi(2 * m.nbody);

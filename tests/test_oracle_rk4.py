@@ -1,0 +1,108 @@
+"""Pins of the FP64 reference's fourth-order Runge-Kutta integrator (integrator 3: the
+whole forward pass at each of four stages).  No GPU.
+
+What fixes the answers, independently of the reference's integrator code:
+* without contacts, its steps equal classic RK4 assembled here from the reference's
+  own smooth accelerations (hinge coordinates add, so the scheme is the textbook one);
+* its global error falls sixteenfold when the step halves (fourth order), against
+  twofold for semi-implicit Euler;
+* energy drift of a conservative chain is orders below semi-implicit Euler's;
+* the first stage is the Euler step's forward pass: the reported acceleration and the
+  contacts equal the Euler step's, and a body at rest on a plane stays at rest.
+"""
+import numpy as np
+import pytest
+
+from oracle import MODE_CONVERGED, Oracle
+from paper_2502_08844_amd.synth import robots
+
+G = 9.81
+
+
+def _chain(integrator, h):
+    m = robots.hinge_chain(n=4, link=0.3)
+    m.opt.integrator = integrator
+    m.opt.timestep = h
+    return m
+
+
+def _rk4_reference(o, q, v, h, nstep):
+    def acc(q, v):
+        return o.forward(q, v)["qacc_smooth"]
+    for _ in range(nstep):
+        k1q, k1v = v, acc(q, v)
+        k2q, k2v = v + 0.5 * h * k1v, acc(q + 0.5 * h * k1q, v + 0.5 * h * k1v)
+        k3q, k3v = v + 0.5 * h * k2v, acc(q + 0.5 * h * k2q, v + 0.5 * h * k2v)
+        k4q, k4v = v + h * k3v, acc(q + h * k3q, v + h * k3v)
+        q = q + h / 6 * (k1q + 2 * k2q + 2 * k3q + k4q)
+        v = v + h / 6 * (k1v + 2 * k2v + 2 * k3v + k4v)
+    return q, v
+
+
+Q0 = np.array([0.3, -0.2, 0.4, 0.1])
+V0 = np.array([0.5, -1.0, 0.7, 0.2])
+
+
+def test_rk4_equals_classic_rk4_without_contacts():
+    h = 2e-3
+    o = Oracle(_chain(3, h))
+    r = o.step(Q0[None].copy(), V0[None].copy(), nstep=50)
+    q, v = _rk4_reference(Oracle(_chain(0, h)), Q0, V0, h, 50)
+    np.testing.assert_allclose(r["qpos"][0], q, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(r["qvel"][0], v, rtol=1e-12, atol=1e-13)
+
+
+def test_rk4_is_fourth_order():
+    T = 0.2
+    ref = Oracle(_chain(3, T / 1600)).step(Q0[None].copy(), V0[None].copy(), nstep=1600)
+    err = {}
+    for integ in (0, 3):
+        for n in (50, 100):
+            r = Oracle(_chain(integ, T / n)).step(Q0[None].copy(), V0[None].copy(), nstep=n)
+            err[integ, n] = np.abs(r["qpos"][0] - ref["qpos"][0]).max()
+    assert 12 < err[3, 50] / err[3, 100] < 20
+    assert 1.5 < err[0, 50] / err[0, 100] < 2.5
+    assert err[3, 100] < 1e-4 * err[0, 100]
+
+
+def test_rk4_energy_drift_far_below_euler():
+    def energy(o, m, q, v):
+        f = o.forward(q, v)
+        return 0.5 * v @ f["M"] @ v + sum(m.bodies[b].mass * G * f["xipos"][b, 2]
+                                          for b in range(1, m.nbody))
+    drift = {}
+    for integ in (0, 3):
+        m = _chain(integ, 1e-3)
+        o = Oracle(m)
+        r = o.step(Q0[None].copy(), V0[None].copy(), nstep=1000)
+        drift[integ] = abs(energy(o, m, r["qpos"][0], r["qvel"][0]) - energy(o, m, Q0, V0))
+    assert drift[3] < 1e-7 and drift[0] > 1e3 * drift[3]
+
+
+def test_first_stage_is_the_euler_forward_pass():
+    m3 = robots.quadruped()
+    m3.opt.integrator = 3
+    m0 = robots.quadruped()
+    from paper_2502_08844_amd.synth import inputs
+    qp, qv = inputs.initial_state("quadruped", m0, 3, seed=2)
+    qv = np.random.default_rng(0).normal(scale=0.3, size=qv.shape)
+    u = inputs.controls("quadruped", m0, 3, 1, seed=2)
+    r3 = Oracle(m3).step(qp.copy(), qv.copy(), None, u, nstep=1)
+    r0 = Oracle(m0).step(qp.copy(), qv.copy(), None, u, nstep=1)
+    np.testing.assert_array_equal(r3["qacc"], r0["qacc"])
+    np.testing.assert_array_equal(r3["ncon"], r0["ncon"])
+    np.testing.assert_array_equal(r3["contacts"], r0["contacts"])
+    assert not np.allclose(r3["qvel"], r0["qvel"], rtol=1e-6)
+
+
+def test_resting_box_stays_at_rest():
+    m = robots.free_body("box", mass=1.0, half=(0.1, 0.2, 0.05), plane=True, timestep=0.002)
+    q0 = m.qpos0.copy()
+    q0[2] = 0.05
+    r = Oracle(m).step(q0[None], np.zeros((1, 6)), nstep=1500, mode=MODE_CONVERGED)
+    m.opt.integrator = 3
+    r3 = Oracle(m).step(r["qpos"].copy(), r["qvel"].copy(), r["qacc_ws"].copy(), nstep=10,
+                        mode=MODE_CONVERGED)
+    assert np.abs(r3["qpos"] - r["qpos"]).max() < 1e-9
+    assert np.abs(r3["qvel"]).max() < 1e-8
+    assert r3["contacts"][0, :4, 13].sum() == pytest.approx(G, rel=1e-6)
