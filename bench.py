@@ -464,6 +464,9 @@ def main():
         out["implicit_pd"] = constraint_compare(
             ctx, args.seed, "quadruped_implicit_pd",
             "its PD velocity and position gains integrated implicitly")
+        out["rk4"] = constraint_compare(
+            ctx, args.seed, "quadruped_rk4",
+            "fourth-order Runge-Kutta (four forward passes a step)")
         out["rough_terrain"] = constraint_compare(
             ctx, args.seed, "quadruped_rough",
             "its feet on 4 m x 4 m Perlin-noise terrain (64 x 64 heightfield, 6 cm relief)")

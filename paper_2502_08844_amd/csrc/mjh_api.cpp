@@ -82,7 +82,7 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nq < 0 ||
       m.nv < 0 || m.iterations < 0 || m.nconmax < 0 || m.nbody > 4096 || m.njnt > 4096 ||
       m.ngeom > 4096 || m.npair > 65536 || m.nu > 4096 || m.nconmax > 4096 || m.neq < 0 ||
-      m.neq > 1024 || m.integrator < 0 || m.integrator > 2 || has_hf < 0 || has_hf > 1) {
+      m.neq > 1024 || m.integrator < 0 || m.integrator > 3 || has_hf < 0 || has_hf > 1) {
     err = "model blob: size field out of range";
     return MJH_EMODEL;
   }
@@ -249,7 +249,8 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   d.nbody = h.nbody; d.njnt = h.njnt; d.nq = h.nq; d.nv = h.nv; d.nu = h.nu;
   d.ngeom = h.ngeom; d.npair = h.npair; d.nconmax = h.nconmax;
   d.iterations = h.iterations;
-  d.implicit = h.integrator;
+  d.implicit = (h.integrator == 1 || h.integrator == 2) ? h.integrator : 0;
+  d.rk4 = h.integrator == 3;
   d.hf_nrow = h.hf_nrow;
   d.hf_ncol = h.hf_ncol;
   for (int k = 0; k < 3; k++) d.hf_size[k] = (float)h.hf_size[k];
@@ -523,6 +524,10 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   // per-row force bound (0: one-sided row, F: friction loss, +inf: two-sided equality)
   d.o_fl = take(d.nfric + d.neq > 0 ? nr : 0);
   off = std::max(off, sweep_end);
+  // fourth-order Runge-Kutta: the step's start (q0, v0), the first stage's acceleration
+  // and the weighted sums of the stages' velocities and accelerations, alive across the
+  // four forward passes
+  d.o_rk = d.rk4 ? take(h.nq + 4 * nv) : 0;
   d.lds_words = off;
   // Table of the packed lower triangle at the head of a work-group's LDS: index
   // p = b (b + 1) / 2 + a -> row b, one byte (nv <= 64), four per word; a is recomputed.
@@ -602,6 +607,7 @@ struct mjh_batch {
   int block = 64;
   int tab_words = 0;
   size_t lds_bytes = 0;
+  bool rk4 = false;  // some group integrates by fourth-order Runge-Kutta
   bool dirty = true;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -683,6 +689,9 @@ static mjh_status sync_tables(mjh_batch* b) {
   b->tab_words = tab_words;
   b->block = std::max(block, 16);
   b->lds_bytes = lds;
+  b->rk4 = false;
+  for (const GroupRec& gr : b->groups)
+    if (gr.nworld > 0 && ctx->models[gr.model]->dm.rk4) b->rk4 = true;
   b->dirty = false;
   if (b->graph_exec) { (void)hipGraphExecDestroy(b->graph_exec); b->graph_exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
@@ -887,7 +896,7 @@ mjh_status mjh_step(mjh_batch* b, int32_t nstep, void* stream) {
   if (st != MJH_OK) return st;
   if (nstep == 0 || b->ntask == 0) return MJH_OK;
   MJH_HIP(launch_step(b->d_groups, b->d_tasks, b->ntask, nstep, b->block, b->lds_bytes,
-                      b->tab_words, static_cast<hipStream_t>(stream)));
+                      b->tab_words, b->rk4, static_cast<hipStream_t>(stream)));
   return MJH_OK;
 }
 
@@ -933,7 +942,7 @@ mjh_status mjh_env_step(mjh_batch* b, int32_t nenv, int32_t nsub, const float* a
   E.last_action = last_action; E.obs = obs; E.reward = reward; E.done = done;
   E.ndr = ndr; E.dr = params; E.noise = obs_noise;
   MJH_HIP(launch_env(b->d_groups, b->d_tasks, b->ntask, E, b->block, lds, b->tab_words, ap_words,
-                     static_cast<hipStream_t>(stream)));
+                     b->rk4, static_cast<hipStream_t>(stream)));
   return MJH_OK;
 }
 
@@ -950,7 +959,7 @@ mjh_status mjh_graph_capture(mjh_batch* b, int32_t nstep, void* stream) {
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   MJH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   hipError_t le = launch_step(b->d_groups, b->d_tasks, b->ntask, nstep, b->block, b->lds_bytes,
-                              b->tab_words, s);
+                              b->tab_words, b->rk4, s);
   hipGraph_t g = nullptr;
   hipError_t ce = hipStreamEndCapture(s, &g);
   if (le != hipSuccess || ce != hipSuccess) {
@@ -1012,7 +1021,7 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
     const DevModel& d = ctx->models[g.model]->dm;
     std::ostringstream k;
     k << d.nq << ' ' << d.nv << ' ' << d.nbody << ' ' << d.npair << ' ' << d.nconmax << ' '
-      << d.nlim << ' ' << d.nfric << ' ' << d.neq << ' ' << d.implicit << ' ' << d.iterations
+      << d.nlim << ' ' << d.nfric << ' ' << d.neq << ' ' << d.implicit << ' ' << d.rk4 << ' ' << d.iterations
       << ' ' << g.nworld;
     return k.str();
   };
@@ -1091,7 +1100,7 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
           if (restore() != MJH_OK) { st = MJH_EHIP; break; }
           MJH_HIP(hipEventRecord(e0, nullptr));
           MJH_HIP(launch_step(b->d_groups, b->d_tasks, b->ntask, nstep_probe, b->block, b->lds_bytes,
-                              b->tab_words, nullptr));
+                              b->tab_words, b->rk4, nullptr));
           MJH_HIP(hipEventRecord(e1, nullptr));
           MJH_HIP(hipEventSynchronize(e1));
           MJH_HIP(hipEventElapsedTime(&ms, e0, e1));

@@ -1605,21 +1605,17 @@ DEV void export_contacts(const DevModel& m, float* W, const Team& t, float* out,
   if (t.lane == 0 && nout) *nout = ncon;
 }
 
-// With implicit damping the velocity update takes the acceleration left in o_frc by
-// implicit_damping; otherwise the solve's qacc.
-DEV void integrate(const DevModel& m, float* W, const Team& t, int& status) {
-  float* qpos = W + m.o_qpos;
-  float* qvel = W + m.o_qvel;
-  const float* a = W + (m.implicit ? m.o_frc : m.o_qacc);
-  const float h = m.dt;
-  for (int i = t.lane; i < m.nv; i += t.T) qvel[i] += h * a[i];
-  t.sync();
-  bool bad = false;
+// Position update qout <- qin (+) h vel (qout may be qin): hinge and slide coordinates
+// add h vel; a free joint's position adds h v and its orientation turns by the
+// exponential map of the body-frame rotation h w (then renormalised).  `bad` flags a
+// non-finite result.
+DEV void integrate_pos(const DevModel& m, const Team& t, const float* qin, const float* vel,
+                       float h, float* qout, bool& bad) {
   for (int j = t.lane; j < m.njnt; j += t.T) {
     const int qa = m.jnt_qposadr[j], da = m.jnt_dofadr[j];
     if (m.jnt_type[j] == JNT_FREE) {
-      for (int k = 0; k < 3; k++) qpos[qa + k] += h * qvel[da + k];
-      float w[3] = {h * qvel[da + 3], h * qvel[da + 4], h * qvel[da + 5]};
+      for (int k = 0; k < 3; k++) qout[qa + k] = qin[qa + k] + h * vel[da + k];
+      float w[3] = {h * vel[da + 3], h * vel[da + 4], h * vel[da + 5]};
       float ang = sqrtf(dot3(w, w));
       float dq[4];
       if (ang > 1e-15f) {
@@ -1630,21 +1626,35 @@ DEV void integrate(const DevModel& m, float* W, const Team& t, int& status) {
       } else {
         dq[0] = 1.f; dq[1] = 0.5f * w[0]; dq[2] = 0.5f * w[1]; dq[3] = 0.5f * w[2];
       }
-      const float q0 = qpos[qa + 3], q1 = qpos[qa + 4], q2 = qpos[qa + 5], q3 = qpos[qa + 6];
+      const float q0 = qin[qa + 3], q1 = qin[qa + 4], q2 = qin[qa + 5], q3 = qin[qa + 6];
       float r0 = q0 * dq[0] - q1 * dq[1] - q2 * dq[2] - q3 * dq[3];
       float r1 = q0 * dq[1] + q1 * dq[0] + q2 * dq[3] - q3 * dq[2];
       float r2 = q0 * dq[2] - q1 * dq[3] + q2 * dq[0] + q3 * dq[1];
       float r3 = q0 * dq[3] + q1 * dq[2] - q2 * dq[1] + q3 * dq[0];
       float inv = 1.f / sqrtf(r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3);
-      qpos[qa + 3] = r0 * inv; qpos[qa + 4] = r1 * inv;
-      qpos[qa + 5] = r2 * inv; qpos[qa + 6] = r3 * inv;
-      for (int k = 0; k < 7; k++) bad |= !isfinite(qpos[qa + k]);
-      for (int k = 0; k < 6; k++) bad |= !isfinite(qvel[da + k]);
+      qout[qa + 3] = r0 * inv; qout[qa + 4] = r1 * inv;
+      qout[qa + 5] = r2 * inv; qout[qa + 6] = r3 * inv;
+      for (int k = 0; k < 7; k++) bad |= !isfinite(qout[qa + k]);
     } else {
-      qpos[qa] += h * qvel[da];
-      bad |= !isfinite(qpos[qa]) || !isfinite(qvel[da]);
+      qout[qa] = qin[qa] + h * vel[da];
+      bad |= !isfinite(qout[qa]);
     }
   }
+}
+
+// A11: semi-implicit Euler, velocity first, then the positions with the new velocity.
+// With implicit damping or gains the velocity update takes the acceleration left in
+// o_frc by implicit_damping; otherwise the solve's qacc.
+DEV void integrate(const DevModel& m, float* W, const Team& t, int& status) {
+  float* qpos = W + m.o_qpos;
+  float* qvel = W + m.o_qvel;
+  const float* a = W + (m.implicit ? m.o_frc : m.o_qacc);
+  const float h = m.dt;
+  for (int i = t.lane; i < m.nv; i += t.T) qvel[i] += h * a[i];
+  t.sync();
+  bool bad = false;
+  for (int i = t.lane; i < m.nv; i += t.T) bad |= !isfinite(qvel[i]);
+  integrate_pos(m, t, qpos, qvel, h, qpos, bad);
   if (bad) status |= 1;
   t.sync();
 }
@@ -1746,6 +1756,79 @@ DEV void world_step(const DevModel& m, float* W0, const Team& t0, const float* c
     implicit_damping(m, W, t);
   }
 #undef MJH_PHASE_CTX
+}
+
+// Fourth-order Runge-Kutta (integrator 3).  The step runs the whole forward pass at four
+// stages, one `world_step` call site in a stage loop around these helpers: stage k = 2,
+// 3, 4 starts at (q0 (+) c_k h v_{k-1}, v0 + c_k h a_{k-1}), c = (1/2, 1/2, 1), warm-
+// started from a_{k-1}; afterwards q <- q0 (+) h/6 (v1 + 2 v2 + 2 v3 + v4) and
+// qdot <- v0 + h/6 (a1 + 2 a2 + 2 a3 + a4), and qacc (reported, and the next warm
+// start) is a1.  The block at o_rk holds q0, v0, a1 and the two weighted sums.
+DEV int rk4_stages(const DevModel& m) { return m.rk4 ? 4 : 1; }
+
+// set the state of stage k >= 1 from the previous stage's velocity and acceleration
+DEV void rk4_begin(const DevModel& m, float* W, const Team& t, int k) {
+  float* qvel = W + m.o_qvel;
+  const float* q0 = W + m.o_rk;
+  const float* v0 = q0 + m.nq;
+  const float ch = (k == 3 ? 1.f : 0.5f) * m.dt;
+  bool bad = false;  // a non-finite stage shows in the final state
+  integrate_pos(m, t, q0, qvel, ch, W + m.o_qpos, bad);
+  t.sync();
+  const float* qacc = W + m.o_qacc;
+  for (int i = t.lane; i < m.nv; i += t.T) qvel[i] = v0[i] + ch * qacc[i];
+  t.sync();
+}
+
+// after stage k's forward pass: keep the step's start (k = 0) and add the stage's
+// velocity and acceleration to the weighted sums (weights 1, 2, 2, 1)
+DEV void rk4_accumulate(const DevModel& m, float* W, const Team& t, int k) {
+  const int nq = m.nq, nv = m.nv;
+  const float* qvel = W + m.o_qvel;
+  const float* qacc = W + m.o_qacc;
+  float* q0 = W + m.o_rk;
+  float* v0 = q0 + nq;
+  float* a1 = v0 + nv;
+  float* vs = a1 + nv;
+  float* as = vs + nv;
+  if (k == 0) {
+    const float* qpos = W + m.o_qpos;
+    for (int i = t.lane; i < nq; i += t.T) q0[i] = qpos[i];
+    for (int i = t.lane; i < nv; i += t.T) {
+      v0[i] = qvel[i]; a1[i] = qacc[i];
+      vs[i] = qvel[i]; as[i] = qacc[i];
+    }
+  } else {
+    const float bk = k == 3 ? 1.f : 2.f;
+    for (int i = t.lane; i < nv; i += t.T) {
+      vs[i] += bk * qvel[i];
+      as[i] += bk * qacc[i];
+    }
+  }
+  t.sync();
+}
+
+DEV void rk4_combine(const DevModel& m, float* W, const Team& t, int& status) {
+  const int nq = m.nq, nv = m.nv;
+  const float h = m.dt;
+  float* qvel = W + m.o_qvel;
+  float* qacc = W + m.o_qacc;
+  const float* q0 = W + m.o_rk;
+  const float* v0 = q0 + nq;
+  const float* a1 = v0 + nv;
+  float* vs = const_cast<float*>(a1) + nv;
+  const float* as = vs + nv;
+  for (int i = t.lane; i < nv; i += t.T) vs[i] = vs[i] / 6.f;
+  t.sync();
+  bool bad = false;
+  integrate_pos(m, t, q0, vs, h, W + m.o_qpos, bad);
+  for (int i = t.lane; i < nv; i += t.T) {
+    qvel[i] = v0[i] + h * (as[i] / 6.f);
+    qacc[i] = a1[i];
+    bad |= !isfinite(qvel[i]);
+  }
+  if (bad) status |= 1;
+  t.sync();
 }
 
 // copy a model's triangular pair table to the head of the work-group's LDS (all

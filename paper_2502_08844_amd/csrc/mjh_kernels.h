@@ -13,9 +13,11 @@ __host__ __device__ inline int table_words(const DevModel& m) {
   return ((m.ntri + 3) / 4 + 3) & ~3;
 }
 
-// Launch the step kernel: one work-group of `block` threads per task.
+// Launch the step kernel: one work-group of `block` threads per task; rk4 selects the
+// instantiation that can run fourth-order Runge-Kutta groups.
 hipError_t launch_step(const DevGroup* groups, const DevTask* tasks, int ntask, int nstep,
-                       int block, size_t lds_bytes, int tab_words, hipStream_t stream);
+                       int block, size_t lds_bytes, int tab_words, bool rk4,
+                       hipStream_t stream);
 // Allow the step kernel `bytes` of dynamic LDS per work-group.
 hipError_t set_step_lds_limit(size_t bytes);
 // Compute body_invweight of a freshly uploaded model (one work-group).
@@ -38,7 +40,7 @@ struct EnvArgs {
 };
 // ap_words: LDS words after the pair table for the teams' previous actions
 hipError_t launch_env(const DevGroup* groups, const DevTask* tasks, int ntask, const EnvArgs& E,
-                      int block, size_t lds_bytes, int tab_words, int ap_words,
+                      int block, size_t lds_bytes, int tab_words, int ap_words, bool rk4,
                       hipStream_t stream);
 hipError_t set_env_lds_limit(size_t bytes);
 

@@ -19,6 +19,9 @@ constexpr int kPhaseWorlds = 8192;
 __device__ long long g_phase_cycles[kPhaseWorlds * 8];
 #endif
 
+// RK: the instantiation that can run fourth-order Runge-Kutta groups (four forward
+// passes a step); the other compiles the one-pass step alone.
+template <bool RK>
 __device__ __forceinline__ void run_worlds(const DevGroup& G, float* W, int world, int nstep, int lane, int T,
                            const unsigned char* tab) {
   const DevModel& m = G.m;
@@ -39,15 +42,21 @@ __device__ __forceinline__ void run_worlds(const DevGroup& G, float* W, int worl
 #endif
   for (int s = 0; s < nstep; s++) {
     const float* u = G.ctrl ? G.ctrl + ((size_t)s * G.nworld + w) * nu : nullptr;
+    const bool rk = RK && m.rk4;
+    for (int k = 0; k < (rk ? 4 : 1); k++) {
+      if (k > 0) rk4_begin(m, W, t, k);
 #ifdef MJH_PHASE_TIMING
-    world_step(m, W, t, u, status, m.iterations, 0.f, ph, &last);
+      world_step(m, W, t, u, status, m.iterations, 0.f, ph, &last);
 #else
-    world_step(m, W, t, u, status, m.iterations);
+      world_step(m, W, t, u, status, m.iterations);
 #endif
-    if (s == nstep - 1 && G.con_out)
-      export_contacts(m, W, t, G.con_out + w * m.nconmax * kConOut,
-                      G.ncon_out ? G.ncon_out + w : nullptr);
-    integrate(m, W, t, status);
+      if (k == 0 && s == nstep - 1 && G.con_out)
+        export_contacts(m, W, t, G.con_out + w * m.nconmax * kConOut,
+                        G.ncon_out ? G.ncon_out + w : nullptr);
+      if (rk) rk4_accumulate(m, W, t, k);
+    }
+    if (rk) rk4_combine(m, W, t, status);
+    else integrate(m, W, t, status);
 #ifdef MJH_PHASE_TIMING
     t.sync();
     const long long now_ = (long long)__builtin_readcyclecounter();
@@ -68,6 +77,7 @@ __device__ __forceinline__ void run_worlds(const DevGroup& G, float* W, int worl
   if (lane == 0 && G.status) G.status[w] = status;
 }
 
+template <bool RK>
 __global__ void __launch_bounds__(kMaxBlock, 4)
 mjh_step_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__ tasks,
                 int nstep, int tab_words) {
@@ -81,7 +91,7 @@ mjh_step_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__
   float* W = lds + tab_words + (size_t)team * G.m.lds_words;
   const int lane = threadIdx.x - team * T;
   const int world = tk.w0 + team;
-  run_worlds(G, W, world, nstep, lane, T, (const unsigned char*)lds);
+  run_worlds<RK>(G, W, world, nstep, lane, T, (const unsigned char*)lds);
 }
 
 // ------------------------------------------------------------- environment step
@@ -104,6 +114,7 @@ constexpr float kEnvKv = 1.f, kEnvSv = 0.25f, kEnvKw = 0.5f, kEnvSw = 0.25f;
 constexpr float kEnvLinZ = -2.f, kEnvAngXY = -0.05f, kEnvOri = -5.f, kEnvTau = -2e-4f;
 constexpr float kEnvQ = -0.1f, kEnvRate = -0.01f, kEnvTerm = -1.f;
 
+template <bool RK>
 __device__ __forceinline__ void env_worlds(const DevGroup& G, const EnvArgs& E, float* W, float* aprev, float* dr,
                            int world, int lane, int T, const unsigned char* tab) {
   const DevModel& m = G.m;
@@ -130,8 +141,14 @@ __device__ __forceinline__ void env_worlds(const DevGroup& G, const EnvArgs& E, 
   for (int e = 0; e < E.nenv; e++) {
     const float* u = E.action + ((size_t)e * G.nworld + w) * nu;
     for (int s = 0; s < E.nsub; s++) {
-      world_step(m, W, t, u, status, m.iterations, 0.f, nullptr, nullptr, dr);
-      integrate(m, W, t, status);
+      const bool rk = RK && m.rk4;
+      for (int k = 0; k < (rk ? 4 : 1); k++) {
+        if (k > 0) rk4_begin(m, W, t, k);
+        world_step(m, W, t, u, status, m.iterations, 0.f, nullptr, nullptr, dr);
+        if (rk) rk4_accumulate(m, W, t, k);
+      }
+      if (rk) rk4_combine(m, W, t, status);
+      else integrate(m, W, t, status);
     }
     // root rotation from its quaternion (every lane)
     float qw = qpos[3], qx = qpos[4], qy = qpos[5], qz = qpos[6];
@@ -206,6 +223,7 @@ __device__ __forceinline__ void env_worlds(const DevGroup& G, const EnvArgs& E, 
 // LDS: the pair table, then `ap_words` holding each team's previous action and, with
 // randomisation, its parameter record (nu + ndr words a team), then the worlds' working
 // sets at the usual stride.
+template <bool RK>
 __global__ void __launch_bounds__(kMaxBlock, 4)
 mjh_env_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__ tasks,
                EnvArgs E, int tab_words, int ap_words) {
@@ -218,7 +236,7 @@ mjh_env_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__ 
   if (team >= tk.nw) return;
   float* ap = lds + tab_words + team * (G.m.nu + E.ndr);
   float* W = lds + tab_words + ap_words + (size_t)team * G.m.lds_words;
-  env_worlds(G, E, W, ap, E.dr ? ap + G.m.nu : nullptr, tk.w0 + team, threadIdx.x - team * T, T,
+  env_worlds<RK>(G, E, W, ap, E.dr ? ap + G.m.nu : nullptr, tk.w0 + team, threadIdx.x - team * T, T,
              (const unsigned char*)lds);
 }
 
@@ -282,29 +300,44 @@ __global__ void __launch_bounds__(64) mjh_invweight_kernel(DevModel m, int tab_w
 
 // ------------------------------------------------------------- host-side launchers
 hipError_t launch_step(const DevGroup* groups, const DevTask* tasks, int ntask, int nstep,
-                       int block, size_t lds_bytes, int tab_words, hipStream_t stream) {
+                       int block, size_t lds_bytes, int tab_words, bool rk4,
+                       hipStream_t stream) {
   if (ntask <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mjh_step_kernel, dim3(ntask), dim3(block), lds_bytes, stream, groups,
-                     tasks, nstep, tab_words);
+  if (rk4)
+    hipLaunchKernelGGL(mjh_step_kernel<true>, dim3(ntask), dim3(block), lds_bytes, stream,
+                       groups, tasks, nstep, tab_words);
+  else
+    hipLaunchKernelGGL(mjh_step_kernel<false>, dim3(ntask), dim3(block), lds_bytes, stream,
+                       groups, tasks, nstep, tab_words);
   return hipGetLastError();
 }
 
 hipError_t set_step_lds_limit(size_t bytes) {
-  return hipFuncSetAttribute((const void*)mjh_step_kernel,
+  hipError_t e = hipFuncSetAttribute((const void*)mjh_step_kernel<false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)mjh_step_kernel<true>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t launch_env(const DevGroup* groups, const DevTask* tasks, int ntask, const EnvArgs& E,
-                      int block, size_t lds_bytes, int tab_words, int ap_words,
+                      int block, size_t lds_bytes, int tab_words, int ap_words, bool rk4,
                       hipStream_t stream) {
   if (ntask <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mjh_env_kernel, dim3(ntask), dim3(block), lds_bytes, stream, groups, tasks,
-                     E, tab_words, ap_words);
+  if (rk4)
+    hipLaunchKernelGGL(mjh_env_kernel<true>, dim3(ntask), dim3(block), lds_bytes, stream,
+                       groups, tasks, E, tab_words, ap_words);
+  else
+    hipLaunchKernelGGL(mjh_env_kernel<false>, dim3(ntask), dim3(block), lds_bytes, stream,
+                       groups, tasks, E, tab_words, ap_words);
   return hipGetLastError();
 }
 
 hipError_t set_env_lds_limit(size_t bytes) {
-  return hipFuncSetAttribute((const void*)mjh_env_kernel,
+  hipError_t e = hipFuncSetAttribute((const void*)mjh_env_kernel<false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)mjh_env_kernel<true>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 

@@ -37,6 +37,7 @@ struct DevModel {
   int iterations, nlevel, nmpair, ntri;
   int implicit;  // 1: joint damping and PD velocity gains integrated implicitly;
                  // 2: also the PD position gains
+  int rk4;       // 1: fourth-order Runge-Kutta (forward pass at four stages)
   int hf_nrow, hf_ncol;  // heightfield grid (0 without one)
   float hf_size[3];      // half extents x, y and the height scale
   // ---- constants
@@ -117,6 +118,7 @@ struct DevModel {
   int o_M, o_H;
   int o_frc, o_a0, o_Mr, o_g, o_d, o_Md, o_tmp;
   int o_cand, o_con, o_lim, o_J, o_aref, o_D, o_e, o_s, o_fl, o_scal;
+  int o_rk;  // Runge-Kutta block (rk4 only): q0 [nq], v0, a1, vsum, asum [nv each]
   // adjoint layout only (no aliasing between the sweep and contact scratch there)
   int o_qbi, o_vbi, o_qb, o_vb, o_ub, o_mu, o_Sbar, o_xbar, o_Rbar, o_cinbar;
   int o_Vbar, o_Abar, o_Fbar, o_vup, o_aup, o_xup, o_Rup, o_rowsc, o_consc;

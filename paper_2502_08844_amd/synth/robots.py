@@ -550,6 +550,14 @@ def quadruped_implicit() -> Model:
     return quadruped(implicit=1)
 
 
+def quadruped_rk4() -> Model:
+    """The quadruped integrated by fourth-order Runge-Kutta (integrator 3)."""
+    m = quadruped()
+    m.name = "quadruped_rk4"
+    m.opt.integrator = 3
+    return m
+
+
 def quadruped_implicit_pd() -> Model:
     """The quadruped with its PD velocity and position gains integrated implicitly."""
     return quadruped(implicit=2)
@@ -732,6 +740,7 @@ WORKLOADS = {
     "quadruped_tethered": quadruped_tethered,
     "quadruped_implicit": quadruped_implicit,
     "quadruped_implicit_pd": quadruped_implicit_pd,
+    "quadruped_rk4": quadruped_rk4,
     "quadruped_rough": quadruped_rough,
     "humanoid": humanoid,
     "hand": hand,

@@ -10,8 +10,11 @@ import pytest
 
 from paper_2502_08844_amd import build
 
-STEP = "_ZN3mjh15mjh_step_kernelEPKNS_8DevGroupEPKNS_7DevTaskEii"
-ENV = "_ZN3mjh14mjh_env_kernelEPKNS_8DevGroupEPKNS_7DevTaskENS_7EnvArgsEii"
+# instantiations without / with fourth-order Runge-Kutta groups
+STEP = "_ZN3mjh15mjh_step_kernelILb0EEEvPKNS_8DevGroupEPKNS_7DevTaskEii"
+STEP_RK = "_ZN3mjh15mjh_step_kernelILb1EEEvPKNS_8DevGroupEPKNS_7DevTaskEii"
+ENV = "_ZN3mjh14mjh_env_kernelILb0EEEvPKNS_8DevGroupEPKNS_7DevTaskENS_7EnvArgsEii"
+ENV_RK = "_ZN3mjh14mjh_env_kernelILb1EEEvPKNS_8DevGroupEPKNS_7DevTaskENS_7EnvArgsEii"
 
 
 @pytest.fixture(scope="module")
@@ -22,7 +25,8 @@ def usage():
     return u
 
 
-@pytest.mark.parametrize("kernel,scratch_max", [(STEP, 256), (ENV, 512)])
+@pytest.mark.parametrize("kernel,scratch_max", [(STEP, 256), (STEP_RK, 256), (ENV, 512),
+                                                (ENV_RK, 512)])
 def test_hot_kernels_fit_four_waves_with_small_scratch(usage, kernel, scratch_max):
     k = usage[kernel]
     assert k["VGPRs"] <= 128 and k["Occupancy"] >= 4
