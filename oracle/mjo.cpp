@@ -245,6 +245,8 @@ struct Model {
   std::vector<double> hf_data;
   std::vector<int> eq_type, eq_b1, eq_b2;
   std::vector<double> eq_a1, eq_a2;  // anchor in body1's / body2's frame
+  std::vector<double> eq_relR;       // weld: body2's reference orientation in body1's frame
+  int neqrow = 0;                    // 3 rows per connect, 6 per weld
   std::vector<double> qpos0;
   // derived
   std::vector<int> jnt_qposadr, jnt_dofadr, body_jntadr, body_jntnum, body_dofadr, body_dofnum;
@@ -999,6 +1001,18 @@ template <class T> void point_jac(const Model& m, const Data<T>& d, int b, const
   }
 }
 
+// angular Jacobian (3 x nv, world frame) of body b: the rotation axes of the dofs on
+// its path to the root
+template <class T> void body_angjac(const Model& m, const Data<T>& d, int b, T* J) {
+  for (int i = 0; i < 3 * m.nv; i++) J[i] = 0.0;
+  for (; b > 0; b = m.body_parent[b]) {
+    for (int i = 0; i < m.body_dofnum[b]; i++) {
+      const int k = m.body_dofadr[b] + i;
+      for (int r = 0; r < 3; r++) J[r * m.nv + k] = d.cdof[6 * k + r];
+    }
+  }
+}
+
 // impedance d(r) from solimp = (dmin, dmax, width, mid, power)
 template <class T> T impedance(const Model& m, T r) {
   const double dmin = m.solimp[0], dmax = m.solimp[1], width = m.solimp[2];
@@ -1023,7 +1037,8 @@ template <class T> T impedance(const Model& m, T r) {
 // [-F_k, F_k] (dry joint friction, Todorov 2014's box-constrained rows).
 // Then three two-sided rows per connect equality, always present: with p1, p2 the
 // anchor's world positions through body1 and body2, row k has J = e_k^T (J_p(b1, p1) -
-// J_p(b2, p2)), r = (p1 - p2)_k, and A = w(b1) + w(b2); its force is unbounded.
+// J_p(b2, p2)), r = (p1 - p2)_k, and A = w(b1) + w(b2); its force is unbounded.  A weld
+// adds three rotational rows after its three translational ones (see below).
 template <class T> void constraint_rows(const Model& m, Data<T>& d) {
   const int nc = (int)d.con.size(), n = m.nv;
   std::vector<int> lim_dof;
@@ -1037,7 +1052,7 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
     else if (rhi < 0.0) { lim_dof.push_back(m.jnt_dofadr[j]); lim_sign.push_back(-1.0); lim_dist.push_back(rhi); }
   }
   const int nl = (int)lim_dof.size();
-  d.nrow = 4 * nc + nl + m.nfric + 3 * m.neq;
+  d.nrow = 4 * nc + nl + m.nfric + m.neqrow;
   d.J.assign(d.nrow * n, 0.0);
   d.aref.assign(d.nrow, 0.0);
   d.D.assign(d.nrow, 0.0);
@@ -1115,6 +1130,39 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
       d.aref[row] = -B * jv - K * imp * r;
       d.D[row] = 1.0 / ((1.0 - imp) / imp * A);
       d.fl[row] = INFINITY;  // two-sided: the quadratic piece everywhere
+    }
+    if (m.eq_type[q] != 1) continue;
+    // weld: body2's orientation relative to body1 held at the reference Q.  The error
+    // rotation E = R1 Q R2^T is I when held; its residual r = vee(E - E^T) / 2 = sin(theta)
+    // axis (world frame), whose rate at E = I is w1 - w2: J = J_w(b1) - J_w(b2).
+    T E[9], RQ[9];
+    const T* R1 = &d.xmat[9 * b1];
+    const T* R2 = &d.xmat[9 * b2];
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        T v = 0.0;
+        for (int k = 0; k < 3; k++) v += R1[3 * i + k] * m.eq_relR[9 * q + 3 * k + j];
+        RQ[3 * i + j] = v;
+      }
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        T v = 0.0;
+        for (int k = 0; k < 3; k++) v += RQ[3 * i + k] * R2[3 * j + k];
+        E[3 * i + j] = v;
+      }
+    const T rr[3] = {0.5 * (E[7] - E[5]), 0.5 * (E[2] - E[6]), 0.5 * (E[3] - E[1])};
+    body_angjac(m, d, b1, J1.data());
+    body_angjac(m, d, b2, J2.data());
+    for (int k = 0; k < 3; k++, row++) {
+      T jv = 0.0;
+      for (int i = 0; i < n; i++) {
+        d.J[row * n + i] = J1[k * n + i] - J2[k * n + i];
+        jv += d.J[row * n + i] * d.qvel[i];
+      }
+      const T imp = impedance(m, rr[k]);
+      d.aref[row] = -B * jv - K * imp * rr[k];
+      d.D[row] = 1.0 / ((1.0 - imp) / imp * A);
+      d.fl[row] = INFINITY;
     }
   }
 }
@@ -1455,7 +1503,7 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   r.read(hi, 16);
   r.read(hf, 16);
   if (!r.ok) { err = "blob too short"; return false; }
-  if (hi[0] != 0x4D484A4D || hi[1] != 2) { err = "bad magic/version"; return false; }
+  if (hi[0] != 0x4D484A4D || hi[1] != 3) { err = "bad magic/version"; return false; }
   m.nbody = hi[2]; m.njnt = hi[3]; m.ngeom = hi[4]; m.npair = hi[5]; m.nu = hi[6];
   m.nq = hi[7]; m.nv = hi[8]; m.iterations = hi[9]; m.ls_iterations = hi[10];
   m.nconmax = hi[11];
@@ -1487,7 +1535,7 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   std::vector<double> af(7 * m.nu);
   r.read(ai.data(), ai.size()); r.read(af.data(), af.size());
   std::vector<int32_t> ei(4 * m.neq);
-  std::vector<double> ef(6 * m.neq);
+  std::vector<double> ef(10 * m.neq);
   r.read(ei.data(), ei.size()); r.read(ef.data(), ef.size());
   if (has_hf) {
     int32_t hd[2];
@@ -1572,12 +1620,21 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   }
   for (int e = 0; e < m.neq; e++) {
     const int* q = &ei[4 * e];
-    if (q[0] != 0 || q[1] <= 0 || q[1] >= m.nbody || q[2] < 0 || q[2] >= m.nbody || q[1] == q[2]) {
+    if (q[0] < 0 || q[0] > 1 || q[1] <= 0 || q[1] >= m.nbody || q[2] < 0 || q[2] >= m.nbody ||
+        q[1] == q[2]) {
       err = "bad equality"; return false;
     }
     m.eq_type.push_back(q[0]); m.eq_b1.push_back(q[1]); m.eq_b2.push_back(q[2]);
-    m.eq_a1.insert(m.eq_a1.end(), &ef[6 * e], &ef[6 * e] + 3);
-    m.eq_a2.insert(m.eq_a2.end(), &ef[6 * e] + 3, &ef[6 * e] + 6);
+    m.eq_a1.insert(m.eq_a1.end(), &ef[10 * e], &ef[10 * e] + 3);
+    m.eq_a2.insert(m.eq_a2.end(), &ef[10 * e] + 3, &ef[10 * e] + 6);
+    const double* qr = &ef[10 * e + 6];
+    const double qn = std::sqrt(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+    if (q[0] == 1 && !(qn > 0.0)) { err = "bad weld orientation"; return false; }
+    double Rq[9];
+    const double qu[4] = {qr[0] / qn, qr[1] / qn, qr[2] / qn, qr[3] / qn};
+    quat2mat(qu, Rq);
+    m.eq_relR.insert(m.eq_relR.end(), Rq, Rq + 9);
+    m.neqrow += q[0] == 1 ? 6 : 3;
   }
   // derived addresses
   m.body_jntadr.assign(m.nbody, 0); m.body_jntnum.assign(m.nbody, 0);
@@ -1700,12 +1757,12 @@ void* mjo_load(const unsigned char* blob, long nbytes, char* err, int errlen) {
 
 void mjo_free(void* h) { delete static_cast<Model*>(h); }
 
-// out[0..12] = nq nv nu nbody njnt ngeom npair nconmax iterations ls_iterations nlimit
-// nfric neq
+// out[0..13] = nq nv nu nbody njnt ngeom npair nconmax iterations ls_iterations nlimit
+// nfric neq neqrow
 int mjo_dims(void* h, int* out) {
   Model& m = *static_cast<Model*>(h);
-  int v[13] = {m.nq, m.nv, m.nu, m.nbody, m.njnt, m.ngeom, m.npair, m.nconmax,
-               m.iterations, m.ls_iterations, m.nlimit, m.nfric, m.neq};
+  int v[14] = {m.nq, m.nv, m.nu, m.nbody, m.njnt, m.ngeom, m.npair, m.nconmax,
+               m.iterations, m.ls_iterations, m.nlimit, m.nfric, m.neq, m.neqrow};
   std::memcpy(out, v, sizeof(v));
   return 0;
 }
@@ -1797,7 +1854,7 @@ int mjo_step(void* h, int nworld, int nstep, double* qpos, double* qvel, double*
 // Output sizes: xpos [nbody*3], xmat [nbody*9], xipos [nbody*3], cdof [nv*6],
 // cvel [nbody*6], M [nv*nv], bias [nv], act [nv], pass [nv], qacc_smooth [nv],
 // qacc [nv], qfrc_con [nv], ncon, contacts [nconmax*20], nrow, J [nrowmax * nv],
-// aref, D, efc_force [nrowmax] with nrowmax = 4 nconmax + nlimit + nfric + 3 neq (contact
+// aref, D, efc_force [nrowmax] with nrowmax = 4 nconmax + nlimit + nfric + neqrow (contact
 // rows first, then the violated limits, the friction-loss rows and the equality rows).
 // NULL skips an output.
 int mjo_forward(void* h, const double* qpos, const double* qvel, const double* qacc_ws,

@@ -8,7 +8,7 @@ Playground consumes (the paper's physics knobs are MJCF options: Table
 of the step's arithmetic.  Both the FP64 reference and the GPU library parse the blob
 with their own code.
 
-Blob layout (little endian, version 2), every block 8-byte aligned:
+Blob layout (little endian, version 3), every block 8-byte aligned:
 
   header   int32[16]  : magic 0x4D484A4D ('MJHM'), version, nbody, njnt, ngeom, npair,
                         nu, nq, nv, iterations, ls_iterations, nconmax, neq,
@@ -28,8 +28,9 @@ Blob layout (little endian, version 2), every block 8-byte aligned:
            f64   [npair][1] : friction coefficient mu
   actuator int32 [nu][2]    : type (0 motor, 1 position PD), joint
            f64   [nu][7]    : gear, kp, kd, ctrlrange[2], qdefault, 0
-  equality int32 [neq][4]   : type (0 connect), body1, body2, 0
-           f64   [neq][6]   : anchor in body1's frame[3], the same point in body2's frame[3]
+  equality int32 [neq][4]   : type (0 connect, 1 weld), body1, body2, 0
+           f64   [neq][10]  : anchor in body1's frame[3], the same point in body2's frame[3],
+                              body2's orientation in body1's frame when welded (quat[4])
   hfield   int32 [2]        : nrow, ncol (>= 2 each)            } only when header hfield = 1
            f64   [3]        : half extents sx, sy; height scale sz
            f64   [nrow][ncol] elevations in [0, 1] (row i at y = -sy + 2 sy i / (nrow - 1),
@@ -43,7 +44,8 @@ bounded by F.
 
 A connect equality holds a point of body1 on a point of body2 (a ball joint closing a
 loop, or pinning a body to the world when body2 = 0): three always-present two-sided
-rows.
+rows.  A weld also holds body2's orientation relative to body1 at a reference
+(three more rows).
 
 A heightfield geom (type 4) is the model's heightfield surface, placed by the geom's
 pose: each grid cell is split into the triangles (v_ij, v_i,j+1, v_i+1,j+1) and
@@ -61,12 +63,12 @@ from typing import List, Tuple
 import numpy as np
 
 MAGIC = 0x4D484A4D
-VERSION = 2
+VERSION = 3
 
 JNT_FREE, JNT_SLIDE, JNT_HINGE = 0, 1, 2
 GEOM_PLANE, GEOM_SPHERE, GEOM_CAPSULE, GEOM_BOX, GEOM_HFIELD = 0, 1, 2, 3, 4
 ACT_MOTOR, ACT_PD = 0, 1
-EQ_CONNECT = 0
+EQ_CONNECT, EQ_WELD = 0, 1
 
 JNT_NQ = {JNT_FREE: 7, JNT_SLIDE: 1, JNT_HINGE: 1}
 JNT_NV = {JNT_FREE: 6, JNT_SLIDE: 1, JNT_HINGE: 1}
@@ -126,6 +128,7 @@ class Equality:
     body2: int
     anchor1: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     anchor2: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    relquat: Tuple[float, float, float, float] = (1.0, 0.0, 0.0, 0.0)  # weld only
 
 
 @dataclass
@@ -190,8 +193,13 @@ class Model:
         return len(self.equalities)
 
     @property
+    def neqrow(self) -> int:
+        """Equality rows: three per connect, six per weld."""
+        return sum(6 if e.type == EQ_WELD else 3 for e in self.equalities)
+
+    @property
     def nrowmax(self) -> int:
-        return 4 * self.opt.nconmax + self.nlimit + self.nfric + 3 * self.neq
+        return 4 * self.opt.nconmax + self.nlimit + self.nfric + self.neqrow
 
     @property
     def nlimit(self) -> int:
@@ -233,7 +241,7 @@ class Model:
             assert j.frictionloss >= 0 and (j.type != JNT_FREE or j.frictionloss == 0), \
                 "friction loss needs a hinge or slide joint"
         for e in self.equalities:
-            assert e.type == EQ_CONNECT, "only connect equalities"
+            assert e.type in (EQ_CONNECT, EQ_WELD), "connect and weld equalities only"
             assert 0 < e.body1 < self.nbody and 0 <= e.body2 < self.nbody
             assert e.body1 != e.body2
         for g1, g2, _ in self.pairs:
@@ -280,7 +288,7 @@ class Model:
         parts.append(blk_f([[a.gear, a.kp, a.kd, *a.ctrlrange, a.qdefault, 0]
                             for a in self.actuators]))
         parts.append(blk_i([[e.type, e.body1, e.body2, 0] for e in self.equalities]))
-        parts.append(blk_f([[*e.anchor1, *e.anchor2] for e in self.equalities]))
+        parts.append(blk_f([[*e.anchor1, *e.anchor2, *e.relquat] for e in self.equalities]))
         if self.hfield is not None:
             hf = self.hfield
             parts.append(blk_i([hf.nrow, hf.ncol]))

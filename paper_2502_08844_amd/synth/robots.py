@@ -27,7 +27,7 @@ from typing import List, Sequence, Tuple
 
 import numpy as np
 
-from .model import (ACT_MOTOR, ACT_PD, EQ_CONNECT, GEOM_BOX, GEOM_CAPSULE, GEOM_HFIELD,
+from .model import (EQ_WELD, ACT_MOTOR, ACT_PD, EQ_CONNECT, GEOM_BOX, GEOM_CAPSULE, GEOM_HFIELD,
                     GEOM_PLANE, GEOM_SPHERE, JNT_FREE, JNT_HINGE, JNT_SLIDE, Actuator, Body,
                     Equality, Geom, Heightfield, Joint, Model, Options)
 
@@ -106,6 +106,26 @@ def axis_angle_quat(axis: Sequence[float], ang: float) -> Tuple[float, float, fl
     return (math.cos(ang / 2), a[0] * s, a[1] * s, a[2] * s)
 
 
+def mat_to_quat(R) -> Tuple[float, float, float, float]:
+    """Unit quaternion (w, x, y, z), w >= 0, of a rotation matrix (largest-pivot form)."""
+    R = np.asarray(R, dtype=np.float64)
+    tr = R[0, 0] + R[1, 1] + R[2, 2]
+    if tr > 0:
+        w = math.sqrt(1.0 + tr) * 2
+        q = (0.25 * w, (R[2, 1] - R[1, 2]) / w, (R[0, 2] - R[2, 0]) / w, (R[1, 0] - R[0, 1]) / w)
+    else:
+        i = int(np.argmax(np.diag(R)))
+        j, k = (i + 1) % 3, (i + 2) % 3
+        s = math.sqrt(1.0 + R[i, i] - R[j, j] - R[k, k]) * 2
+        v = [0.0, 0.0, 0.0]
+        v[i] = 0.25 * s
+        v[j] = (R[j, i] + R[i, j]) / s
+        v[k] = (R[k, i] + R[i, k]) / s
+        q = ((R[k, j] - R[j, k]) / s, *v)
+    q = np.asarray(q) / np.linalg.norm(q)
+    return tuple(float(x) for x in (q if q[0] >= 0 else -q))
+
+
 class _Builder:
     """Accumulates bodies/geoms and derives each body's mass properties from its geoms."""
 
@@ -154,6 +174,31 @@ class _Builder:
         self.m.equalities.append(Equality(type=EQ_CONNECT, body1=body1, body2=body2,
                                           anchor1=tuple(map(float, anchor1)),
                                           anchor2=tuple(map(float, anchor2))))
+        return len(self.m.equalities) - 1
+
+    def frame(self, body: int):
+        """World pose (R, p) of a body with every joint at zero (its built pose)."""
+        R, p = np.eye(3), np.zeros(3)
+        chain = []
+        while body > 0:
+            chain.append(body)
+            body = self.m.bodies[body].parent
+        for b in reversed(chain):
+            bb = self.m.bodies[b]
+            p = p + R @ np.asarray(bb.pos, float)
+            R = R @ quat_to_mat(bb.quat)
+        return R, p
+
+    def weld(self, body1: int, body2: int, anchor=None) -> int:
+        """Hold body1's pose relative to body2 (the world if 0) at their built poses; the
+        translational rows hold the world point `anchor` (default body1's origin)."""
+        R1, p1 = self.frame(body1)
+        R2, p2 = self.frame(body2)
+        a = p1 if anchor is None else np.asarray(anchor, float)
+        self.m.equalities.append(Equality(
+            type=EQ_WELD, body1=body1, body2=body2,
+            anchor1=tuple(map(float, R1.T @ (a - p1))), anchor2=tuple(map(float, R2.T @ (a - p2))),
+            relquat=mat_to_quat(R1.T @ R2)))
         return len(self.m.equalities) - 1
 
     def capsule_fromto(self, body, p0, p1, r, mass=0.0, friction=1.0, name="") -> int:
@@ -231,7 +276,7 @@ QUAD_FRICTIONLOSS = 3.0
 
 def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
               limits: bool = False, frictionloss: float = 0.0, tether: bool = False,
-              implicit: int = 0) -> Model:
+              implicit: int = 0, weld_base: bool = False) -> Model:
     """Free torso (box 0.3x0.1x0.05 m, 5 kg) + 4 legs x 3 hinges (capsules r 0.02,
     length 0.2, 0.5 kg) with massless sphere feet (r 0.025).  nq 19, nv 18, nu 12.
 
@@ -241,7 +286,8 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     the 12 are active on average, up to 7).  With ``frictionloss`` every hinge carries
     that dry friction (one friction-loss row each).  With ``tether`` the torso's centre
     is held by a connect equality on its standing position (a gantry tether: three
-    two-sided rows).  With ``implicit`` = 1 the PD velocity gains are integrated
+    two-sided rows).  With ``weld_base`` the torso is welded to the world at its standing
+    pose (a fixed-base robot: six two-sided rows).  With ``implicit`` = 1 the PD velocity gains are integrated
     implicitly (integrator 1); with 2 the PD position gains as well (integrator 2).
 
     Each leg: hip link (hinge about x, capsule lateral 0.2 m), thigh (hinge about y,
@@ -252,7 +298,7 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     bld = _Builder("quadruped" + ("_limits" if limits else "") +
                    ("_friction" if frictionloss > 0 else "") + ("_tethered" if tether else "") +
                    ("_implicit" if implicit == 1 else "") +
-                   ("_implicit_pd" if implicit == 2 else ""))
+                   ("_implicit_pd" if implicit == 2 else "") + ("_welded" if weld_base else ""))
 
     def rng(k):
         if not limits:
@@ -287,6 +333,8 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     m.pairs = [(plane, f, mu) for f in feet]
     if tether:
         bld.connect(torso, 0, (0, 0, 0), (0, 0, QUAD_STAND_Z))
+    if weld_base:
+        bld.weld(torso, 0)
     m.opt = Options(timestep=timestep, iterations=iterations, ls_iterations=8,
                     nconmax=4, integrator=int(implicit))
     q0 = np.zeros(m.nq)
@@ -550,6 +598,11 @@ def quadruped_implicit() -> Model:
     return quadruped(implicit=1)
 
 
+def quadruped_welded() -> Model:
+    """The quadruped with its torso welded to the world at its standing pose."""
+    return quadruped(weld_base=True)
+
+
 def quadruped_rk4() -> Model:
     """The quadruped integrated by fourth-order Runge-Kutta (integrator 3)."""
     m = quadruped()
@@ -603,6 +656,44 @@ def pinned_body(shape: str = "sphere", mass: float = 1.0, anchor=(0.0, 0.0, 0.0)
     q0[2] = z0
     q0[3] = 1.0
     m.qpos0 = q0
+    return m
+
+
+def welded_box(mass: float = 1.0, half=(0.1, 0.05, 0.03), z0: float = 0.3, anchor=None,
+               gravity=(0.0, 0.0, -9.81), timestep: float = 0.002) -> Model:
+    """A free box welded to the world at its built pose (centre at (0, 0, z0)); the
+    translational rows hold the world point `anchor` (default the centre)."""
+    bld = _Builder("welded_box")
+    b = bld.body(0, pos=(0, 0, z0))
+    bld.joint(b, JNT_FREE)
+    bld.geom(b, GEOM_BOX, half, mass=mass)
+    bld.weld(b, 0, anchor)
+    m = bld.finish()
+    m.opt = Options(timestep=timestep, gravity=tuple(gravity), iterations=50,
+                    ls_iterations=50, nconmax=0)
+    m.qpos0 = np.array([0, 0, z0, 1, 0, 0, 0], dtype=np.float64)
+    return m
+
+
+def welded_pair(m1: float = 1.0, m2: float = 2.0, gravity=(0.0, 0.0, 0.0),
+                timestep: float = 0.002) -> Model:
+    """Two free boxes side by side (centres 0.25 m apart along x, the second turned 30
+    degrees about z) welded to each other at the midpoint."""
+    bld = _Builder("welded_pair")
+    b1 = bld.body(0, pos=(-0.1, 0, 0.3))
+    bld.joint(b1, JNT_FREE)
+    bld.geom(b1, GEOM_BOX, (0.1, 0.05, 0.04), mass=m1)
+    b2 = bld.body(0, pos=(0.15, 0, 0.3), quat=axis_angle_quat((0, 0, 1), math.pi / 6))
+    bld.joint(b2, JNT_FREE)
+    bld.geom(b2, GEOM_BOX, (0.08, 0.06, 0.05), mass=m2)
+    bld.weld(b1, b2, anchor=(0.0, 0.0, 0.3))
+    m = bld.finish()
+    m.opt = Options(timestep=timestep, gravity=tuple(gravity), iterations=50,
+                    ls_iterations=50, nconmax=0)
+    q = np.zeros(14)
+    q[0:3], q[3:7] = (-0.1, 0, 0.3), (1, 0, 0, 0)
+    q[7:10], q[10:14] = (0.15, 0, 0.3), axis_angle_quat((0, 0, 1), math.pi / 6)
+    m.qpos0 = q
     return m
 
 
@@ -741,6 +832,7 @@ WORKLOADS = {
     "quadruped_implicit": quadruped_implicit,
     "quadruped_implicit_pd": quadruped_implicit_pd,
     "quadruped_rk4": quadruped_rk4,
+    "quadruped_welded": quadruped_welded,
     "quadruped_rough": quadruped_rough,
     "humanoid": humanoid,
     "hand": hand,

@@ -61,7 +61,7 @@ def compare_step(m, o, state, ctrl1, gpu1, mode=oracle.MODE_FIXED, near=1e-5):
     lims = [(qadr[j], jt.range[0], jt.range[1]) for j, jt in enumerate(m.joints) if jt.limited]
 
     fric = np.array([j.frictionloss for j in m.joints if j.frictionloss > 0])
-    neqr = 3 * len(m.equalities)
+    neqr = m.neqrow
 
     def at_threshold(w):  # a row at a switch of its cost's pieces in the reference solution
         f = o.forward(qpos[w], qvel[w], ws[w], ctrl1[0, w] if ctrl1 is not None else None,
