@@ -458,6 +458,9 @@ def main():
         out["equality"] = constraint_compare(
             ctx, args.seed, "quadruped_tethered",
             "its torso centre held on its standing position by a connect equality")
+        out["weld"] = constraint_compare(
+            ctx, args.seed, "quadruped_welded",
+            "its torso welded to the world at its standing pose (a fixed base)")
         out["implicit_damping"] = constraint_compare(
             ctx, args.seed, "quadruped_implicit",
             "its PD velocity gains integrated implicitly")

@@ -33,6 +33,9 @@ struct HostModel {
   std::vector<double> hf_data;
   std::vector<int> eq_body;        // [neq][2]
   std::vector<double> eq_anchor;   // [neq][6]
+  std::vector<int> eq_type;        // [neq] 0 connect, 1 weld
+  std::vector<double> eq_relR;     // [neq][9] weld: body2's reference orientation in body1's frame
+  int neqrow = 0;                  // 3 rows per connect, 6 per weld
   double dt = 0, grav[3] = {0, 0, 0}, solref[2] = {0, 0}, solimp[5] = {0, 0, 0, 0, 0};
   std::vector<int> body_parent, jnt_type, jnt_body, jnt_limited, geom_type, geom_body,
       pair_g1, pair_g2, act_type, act_jnt;
@@ -73,7 +76,7 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   int32_t hi[16];
   double hf[16];
   if (!r.read(hi, 16) || !r.read(hf, 16)) { err = "model blob: truncated header"; return MJH_EMODEL; }
-  if (hi[0] != 0x4D484A4D || hi[1] != 2) { err = "model blob: bad magic or version"; return MJH_EMODEL; }
+  if (hi[0] != 0x4D484A4D || hi[1] != 3) { err = "model blob: bad magic or version"; return MJH_EMODEL; }
   m.nbody = hi[2]; m.njnt = hi[3]; m.ngeom = hi[4]; m.npair = hi[5]; m.nu = hi[6];
   m.nq = hi[7]; m.nv = hi[8]; m.iterations = hi[9]; m.ls_iterations = hi[10]; m.nconmax = hi[11];
   m.neq = hi[12];
@@ -99,7 +102,7 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   bool ok = rd(bi, 2 * m.nbody) && rd(bf, 19 * (size_t)m.nbody) && rd(ji, 4 * m.njnt) &&
             rd(jf, 11 * (size_t)m.njnt) && rd(gi, 2 * m.ngeom) && rd(gf, 11 * (size_t)m.ngeom) &&
             rd(pi, 2 * m.npair) && rd(pf, m.npair) && rd(ai, 2 * m.nu) &&
-            rd(af, 7 * (size_t)m.nu) && rd(ei, 4 * (size_t)m.neq) && rd(ef, 6 * (size_t)m.neq);
+            rd(af, 7 * (size_t)m.nu) && rd(ei, 4 * (size_t)m.neq) && rd(ef, 10 * (size_t)m.neq);
   if (ok && has_hf) {
     int32_t hd[2];
     ok = r.read(hd, 2) && r.read(m.hf_size, 3);
@@ -194,13 +197,25 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   }
   for (int e = 0; e < m.neq; e++) {
     const int type = ei[4 * e], b1 = ei[4 * e + 1], b2 = ei[4 * e + 2];
-    if (type != 0) { err = "only connect equalities are supported"; return MJH_EUNSUPPORTED; }
+    if (type != 0 && type != 1) { err = "only connect and weld equalities are supported"; return MJH_EUNSUPPORTED; }
     if (b1 <= 0 || b1 >= m.nbody || b2 < 0 || b2 >= m.nbody || b1 == b2) {
       err = "model blob: bad equality bodies"; return MJH_EMODEL;
     }
+    m.eq_type.push_back(type);
     m.eq_body.push_back(b1);
     m.eq_body.push_back(b2);
-    m.eq_anchor.insert(m.eq_anchor.end(), &ef[6 * e], &ef[6 * e] + 6);
+    m.eq_anchor.insert(m.eq_anchor.end(), &ef[10 * e], &ef[10 * e] + 6);
+    // the weld's reference orientation: unit quaternion (w, x, y, z) -> rotation matrix
+    const double* qr = &ef[10 * e + 6];
+    const double qn = std::sqrt(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+    if (type == 1 && !(qn > 0.0)) { err = "model blob: bad weld orientation"; return MJH_EMODEL; }
+    const double w = qn > 0 ? qr[0] / qn : 1, x = qn > 0 ? qr[1] / qn : 0;
+    const double y = qn > 0 ? qr[2] / qn : 0, z = qn > 0 ? qr[3] / qn : 0;
+    const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                         2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                         2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    m.eq_relR.insert(m.eq_relR.end(), R, R + 9);
+    m.neqrow += type == 1 ? 6 : 3;
   }
   return MJH_OK;
 }
@@ -370,7 +385,8 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
     }
   d.nfric = (int)fric_dadr.size();
   d.neq = h.neq;
-  d.nrowmax = 4 * h.nconmax + d.nlim + d.nfric + 3 * d.neq;
+  d.neqrow = h.neqrow;
+  d.nrowmax = 4 * h.nconmax + d.nlim + d.nfric + d.neqrow;
   // pairs and candidate slots
   std::vector<int> pair_kind, pair_candadr, cand_pair;
   int ncand = 0;
@@ -436,6 +452,13 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   pk.add(h.eq_body, &d.eq_body);
   std::vector<float> eq_anchor = fv(h.eq_anchor);
   pk.add(eq_anchor, &d.eq_anchor);
+  std::vector<float> eq_relR = fv(h.eq_relR);
+  pk.add(eq_relR, &d.eq_relR);
+  // each equality row: its equality | component << 16 (0-2 translational, 3-5 rotational)
+  std::vector<int> eq_row;
+  for (int q = 0; q < h.neq; q++)
+    for (int k = 0; k < (h.eq_type[q] == 1 ? 6 : 3); k++) eq_row.push_back(q | (k << 16));
+  pk.add(eq_row, &d.eq_row);
   std::vector<float> bpos = fv(h.body_pos), bmass = fv(h.body_mass), bipos = fv(h.body_ipos),
                      binert = fv(h.body_inertia), jpos = fv(h.jnt_pos), jaxis = fv(h.jnt_axis),
                      gsize = fv(h.geom_size), gpos = fv(h.geom_pos), pmu = fv(h.pair_mu),

@@ -975,6 +975,23 @@ DEV void eq_points(const DevModel& m, const float* W, int q, float* p1, float* p
   }
 }
 
+// Weld rotational residual, component k: with E = R1 Q R2^T (identity while the weld
+// holds), r = vee(E - E^T) / 2 = sin(angle) axis in the world frame, whose rate at E = I
+// is w1 - w2.
+DEV float weld_residual(const DevModel& m, const float* W, int q, int k) {
+  const float* R1 = W + m.o_xmat + 9 * m.eq_body[2 * q];
+  const float* R2 = W + m.o_xmat + 9 * m.eq_body[2 * q + 1];
+  const float* Q = m.eq_relR + 9 * q;
+  const int i = k == 0 ? 2 : (k == 1 ? 0 : 1), j = k == 0 ? 1 : (k == 1 ? 2 : 0);
+  float eij = 0.f, eji = 0.f;  // E_ij and E_ji
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) {
+      eij += R1[3 * i + a] * Q[3 * a + b] * R2[3 * j + b];
+      eji += R1[3 * j + a] * Q[3 * a + b] * R2[3 * i + b];
+    }
+  return 0.5f * (eij - eji);
+}
+
 // violated joint limit k of a world (its o_lim entry): dof, sign of its row and distance
 DEV void limit_row(const DevModel& m, const float* W, int code, int& dof, float& sg,
                    float& dist) {
@@ -995,7 +1012,9 @@ DEV void limit_row(const DevModel& m, const float* W, int code, int& dof, float&
 // the same R, and the bound stored per row (0 marks a one-sided row).  Then three
 // two-sided rows per connect equality (bound +inf): with p1, p2 the held point through
 // body1 and body2, J = J_p(b1, p1) - J_p(b2, p2) per world axis, r = p1 - p2,
-// R = (1-d)/d (w1 + w2).  Writes the row count to the SC_NROW slot.
+// R = (1-d)/d (w1 + w2); a weld adds three rotational rows, J = J_w(b1) - J_w(b2) per
+// world axis with r its rotation residual (weld_residual) and the same R.  Writes the
+// row count to the SC_NROW slot.
 DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
   int* scal = (int*)(W + m.o_scal);
   const int ncon = scal[SC_NCON];
@@ -1021,7 +1040,7 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
   }
   const int nrf = nrc + nl;  // first friction-loss row
   const int nre = nrf + m.nfric;  // first equality row
-  const int nrow = nre + 3 * m.neq;
+  const int nrow = nre + m.neqrow;
   if (t.lane == 0) scal[SC_NROW] = nrow;
   for (int idx = t.lane; idx < ncon * nv; idx += t.T) {
     const int c = idx / nv, i = idx - c * nv;
@@ -1056,24 +1075,31 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
     const int k = idx / nv, i = idx - k * nv;
     J[(nrf + k) * nv + i] = i == m.fric_dadr[k] ? 1.f : 0.f;
   }
-  for (int idx = t.lane; idx < m.neq * nv; idx += t.T) {
-    const int q = idx / nv, i = idx - q * nv;
-    float p1[3], p2[3];
-    eq_points(m, W, q, p1, p2);
+  for (int idx = t.lane; idx < m.neqrow * nv; idx += t.T) {
+    const int er = idx / nv, i = idx - er * nv;
+    const int q = m.eq_row[er] & 0xffff, k = m.eq_row[er] >> 16;
     const unsigned long long bit = 1ull << i;
-    float jd[3] = {0.f, 0.f, 0.f};
     const float* S = cdof + 6 * i;
-    if (m.body_dofmask[m.eq_body[2 * q]] & bit) {
-      float wx[3];
-      cross3(S, p1, wx);
-      for (int k = 0; k < 3; k++) jd[k] += S[3 + k] + wx[k];
+    const bool in1 = (m.body_dofmask[m.eq_body[2 * q]] & bit) != 0;
+    const bool in2 = (m.body_dofmask[m.eq_body[2 * q + 1]] & bit) != 0;
+    float jv = 0.f;
+    if (k < 3) {  // translational: J_p(b1, p1) - J_p(b2, p2), component k
+      float p1[3], p2[3];
+      eq_points(m, W, q, p1, p2);
+      if (in1) {
+        float wx[3];
+        cross3(S, p1, wx);
+        jv += S[3 + k] + wx[k];
+      }
+      if (in2) {
+        float wx[3];
+        cross3(S, p2, wx);
+        jv -= S[3 + k] + wx[k];
+      }
+    } else {  // rotational: J_w(b1) - J_w(b2), component k - 3
+      jv = (in1 ? S[k - 3] : 0.f) - (in2 ? S[k - 3] : 0.f);
     }
-    if (m.body_dofmask[m.eq_body[2 * q + 1]] & bit) {
-      float wx[3];
-      cross3(S, p2, wx);
-      for (int k = 0; k < 3; k++) jd[k] -= S[3 + k] + wx[k];
-    }
-    for (int k = 0; k < 3; k++) J[(nre + 3 * q + k) * nv + i] = jd[k];
+    J[(nre + er) * nv + i] = jv;
   }
   t.sync();
   const float* qvel = W + m.o_qvel;
@@ -1101,10 +1127,14 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
       jv = qvel[dof];
       A = m.dof_invweight[dof];
     } else {
-      const int q = (row - nre) / 3, k = row - nre - 3 * q;
-      float p1[3], p2[3];
-      eq_points(m, W, q, p1, p2);
-      dist = p1[k] - p2[k];
+      const int q = m.eq_row[row - nre] & 0xffff, k = m.eq_row[row - nre] >> 16;
+      if (k < 3) {
+        float p1[3], p2[3];
+        eq_points(m, W, q, p1, p2);
+        dist = p1[k] - p2[k];
+      } else {
+        dist = weld_residual(m, W, q, k - 3);
+      }
       for (int i = 0; i < nv; i++) jv += J[row * nv + i] * qvel[i];
       A = m.body_invweight[m.eq_body[2 * q]] + m.body_invweight[m.eq_body[2 * q + 1]];
     }
@@ -1533,7 +1563,7 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
     // two-sided row (bound +inf) has none.
     float lo = 0.f, hi = INFINITY;
     const int nbp = FR ? nrow + m.nfric : nrow;
-    const int nfr0 = nrow - m.nfric - 3 * m.neq;  // first friction-loss row
+    const int nfr0 = nrow - m.nfric - m.neqrow;  // first friction-loss row
     for (int c = t.lane; c < nbp; c += t.T) {
       const int r = c < nrow ? c : nfr0 + (c - nrow);
       const float sr = s[r];

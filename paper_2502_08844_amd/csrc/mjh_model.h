@@ -34,6 +34,7 @@ constexpr int kCinert = 10;     // spatial inertia: m, m c (3), I at origin (6)
 struct DevModel {
   // ---- sizes
   int nbody, njnt, nq, nv, nu, ngeom, npair, ncand, nconmax, nlim, nfric, neq, nrowmax;
+  int neqrow;  // equality rows: 3 per connect, 6 per weld
   int iterations, nlevel, nmpair, ntri;
   int implicit;  // 1: joint damping and PD velocity gains integrated implicitly;
                  // 2: also the PD position gains
@@ -78,7 +79,8 @@ struct DevModel {
   const int* lim_qadr;      // [nlim] qpos address of each limited joint (joint order)
   const int* lim_dadr;      // [nlim] its dof
   const int* fric_dadr;     // [nfric] dofs with friction loss (dof order)
-  const int* eq_body;       // [neq][2] connect equalities: body1, body2 (0 = world)
+  const int* eq_body;       // [neq][2] equalities: body1, body2 (0 = world)
+  const int* eq_row;        // [neqrow] equality | component << 16 (3-5: a weld's rotation)
   // ---- float tables
   const float* body_pos;      // [nbody][3] in parent frame
   const float* body_rot;      // [nbody][9] in parent frame
@@ -109,6 +111,7 @@ struct DevModel {
   const float* lim_hi;
   const float* fric_loss;     // [nfric] friction-loss bound of each such dof
   const float* eq_anchor;     // [neq][6] the held point in body1's and in body2's frame
+  const float* eq_relR;       // [neq][9] weld: body2's reference orientation in body1's frame
   float* body_invweight;      // filled on the device at upload
   float* dof_invweight;       // [nv] (M^-1)_kk at qpos0 (limit and friction rows), likewise
   // ---- per-world on-chip layout (offsets in 4-byte words)

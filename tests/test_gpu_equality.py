@@ -1,9 +1,12 @@
-"""GPU parity of connect-equality rows (three two-sided rows holding a point of one body
-on a point of another body or of the world) against the FP64 reference.
+"""GPU parity of equality rows against the FP64 reference: connect (three two-sided rows
+holding a point of one body on a point of another body or of the world) and weld (those
+three plus three rotational rows holding the relative orientation).
 
 Workloads: the parallelogram linkage (a closed loop of hinges, 16-lane teams), a capsule
 pinned at one end (a free body), two free spheres held centre to centre, and the
-quadruped with its torso tethered to its standing position beside the foot contacts.
+quadruped with its torso tethered to its standing position beside the foot contacts;
+welds: a box welded to the world off its centre (a cantilever), two free boxes welded
+to each other, and the quadruped with its torso welded to the world (a fixed base).
 Same tolerances as the other parity tests.  Rollouts of models with equalities are
 rejected (the adjoint does not cover them).
 """
@@ -35,6 +38,15 @@ def _check(kind, stats):
 
 
 def _states(m, nw, rng):
+    if m.name.startswith("welded"):  # near the welded pose: 1 mm and 0.05 rad off
+        q = np.tile(m.qpos0, (nw, 1))
+        for b in range(m.nq // 7):
+            q[:, 7 * b:7 * b + 3] += rng.normal(scale=1e-3, size=(nw, 3))
+            for w in range(nw):
+                dq = robots.axis_angle_quat(rng.normal(size=3), rng.uniform(0, 0.05))
+                R = robots.quat_to_mat(m.qpos0[7 * b + 3:7 * b + 7]) @ robots.quat_to_mat(dq)
+                q[w, 7 * b + 3:7 * b + 7] = robots.mat_to_quat(R)
+        return inputs.f32(q), inputs.f32(rng.normal(scale=0.5, size=(nw, m.nv)))
     if m.name == "four_bar":
         q = rng.uniform(-0.5, 0.5, size=(nw, 3))
         q[:, 1] = -q[:, 0] + rng.normal(scale=1e-3, size=nw)  # near the closed loop
@@ -51,7 +63,8 @@ def _states(m, nw, rng):
 
 
 @pytest.mark.parametrize("name", ["four_bar", "pinned_sphere", "pinned_capsule",
-                                  "connected_spheres", "four_bar_friction"])
+                                  "connected_spheres", "four_bar_friction", "welded_box",
+                                  "welded_pair"])
 def test_equality_parity_small_models(lib, name):
     """The pinned bodies hang 0.3 m above the origin, the quadruped torso's height.
     Spatial inertias and motion subspaces are kept at the world origin, so FP32 rounds
@@ -63,7 +76,9 @@ def test_equality_parity_small_models(lib, name):
          "pinned_sphere": lambda: robots.pinned_body("sphere", anchor=(0, 0, 0.15), z0=0.3),
          "pinned_capsule": lambda: robots.pinned_body("capsule", anchor=(0, 0, 0.2), z0=0.3),
          "connected_spheres": lambda: robots.connected_spheres(1.0, 3.0),
-         "four_bar_friction": lambda: robots.four_bar(frictionloss=0.05)}[name]()
+         "four_bar_friction": lambda: robots.four_bar(frictionloss=0.05),
+         "welded_box": lambda: robots.welded_box(anchor=(-0.08, 0.02, 0.3)),
+         "welded_pair": lambda: robots.welded_pair(gravity=(0, 0, -9.81))}[name]()
     gm = ctx.model_upload(m)
     assert gm.neq == 1 and gm.nrowmax == m.nrowmax
     nw = 96
@@ -99,6 +114,21 @@ def test_single_step_parity_quadruped_tethered(lib):
     print("[gpu] parity quadruped_tethered nw=203", flush=True)
     m, stats = teacher_forced(ctx, mjh, "quadruped_tethered", 203, [0, 5, 50, 150])
     _check("quadruped_tethered", stats)
+
+
+def test_single_step_parity_quadruped_welded(lib):
+    mjh, ctx = lib
+    print("[gpu] parity quadruped_welded nw=203", flush=True)
+    m, stats = teacher_forced(ctx, mjh, "quadruped_welded", 203, [0, 5, 50, 150])
+    _check("quadruped_welded", stats)
+
+
+@pytest.mark.parametrize("team,block", [(16, 64), (64, 64)])
+def test_welded_parity_launch_shapes(lib, team, block):
+    mjh, ctx = lib
+    m, stats = teacher_forced(ctx, mjh, "quadruped_welded", 77, [0, 3, 40], seed=2,
+                              team=team, block=block)
+    _check(f"quadruped_welded-T{team}", stats)
 
 
 @pytest.mark.parametrize("team,block", [(16, 64), (64, 64)])
