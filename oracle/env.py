@@ -151,7 +151,7 @@ def randomized_model(m, rec):
     n = m.nu
     assert rec.shape == (DR_HEAD + 2 * n,)
     r = copy.deepcopy(m)
-    r.pairs = [(g1, g2, mu * rec[0]) for g1, g2, mu in r.pairs]
+    r.pairs = [(p[0], p[1], p[2] * rec[0], *p[3:]) for p in r.pairs]
     root = r.bodies[r.joints[0].body]
     root.mass = root.mass + rec[1]
     root.ipos = tuple(np.asarray(root.ipos, dtype=np.float64) + rec[2:5])

@@ -233,6 +233,7 @@ struct Model {
   std::vector<int> geom_type, geom_body;
   std::vector<double> geom_size, geom_pos, geom_quat, geom_friction;
   std::vector<int> pair_g1, pair_g2;
+  std::vector<int> pair_condim;  // 3: friction pyramid (4 rows); 1: frictionless (1 row)
   std::vector<double> pair_mu;
   std::vector<int> act_type, act_jnt;
   std::vector<double> act_gear, act_kp, act_kd, act_range, act_qdef;
@@ -277,6 +278,7 @@ template <class T> struct Contact {
   T frame[9];  // rows: normal (geom1 -> geom2), tangent 1, tangent 2
   T mu = 0.0;
   int pair = -1, sub = -1, g1 = -1, g2 = -1;
+  int condim = 3, row = 0;  // its row count (1 or 4) and first row
 };
 
 template <class T> struct Data {
@@ -968,6 +970,7 @@ template <class T> void collision(const Model& m, Data<T>& d) {
       contact_frame(c.n, k.frame);
       k.mu = m.pair_mu[pi];
       k.pair = pi; k.sub = c.sub; k.g1 = m.pair_g1[pi]; k.g2 = m.pair_g2[pi];
+      k.condim = m.pair_condim[pi];
       all.push_back(k);
     }
   }
@@ -1052,7 +1055,12 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
     else if (rhi < 0.0) { lim_dof.push_back(m.jnt_dofadr[j]); lim_sign.push_back(-1.0); lim_dist.push_back(rhi); }
   }
   const int nl = (int)lim_dof.size();
-  d.nrow = 4 * nc + nl + m.nfric + m.neqrow;
+  int nrc = 0;  // contact rows: four pyramid edges, or one normal row without friction
+  for (int c = 0; c < nc; c++) {
+    d.con[c].row = nrc;
+    nrc += d.con[c].condim == 1 ? 1 : 4;
+  }
+  d.nrow = nrc + nl + m.nfric + m.neqrow;
   d.J.assign(d.nrow * n, 0.0);
   d.aref.assign(d.nrow, 0.0);
   d.D.assign(d.nrow, 0.0);
@@ -1074,11 +1082,24 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
         Jc[r * n + i] = s;
       }
     const T imp = impedance(m, k.dist);
+    if (k.condim == 1) {
+      // frictionless: one row along the normal, J = J_n, A = w1 + w2
+      const double A1 = std::max(m.body_invweight[b1] + m.body_invweight[b2], 1e-15);
+      const int row = k.row;
+      T jv = 0.0;
+      for (int i = 0; i < n; i++) {
+        d.J[row * n + i] = Jc[i];
+        jv += Jc[i] * d.qvel[i];
+      }
+      d.aref[row] = -B * jv - K * imp * k.dist;
+      d.D[row] = 1.0 / ((1.0 - imp) / imp * A1);
+      continue;
+    }
     const double A = std::max((1.0 + val(k.mu) * val(k.mu)) *
                                   (m.body_invweight[b1] + m.body_invweight[b2]), 1e-15);
     const T R = (1.0 - imp) / imp * A;
     for (int e = 0; e < 4; e++) {
-      const int row = 4 * c + e;
+      const int row = k.row + e;
       const int t = 1 + e / 2;
       const T sg = (e % 2 == 0) ? k.mu : -k.mu;
       T jv = 0.0;
@@ -1091,7 +1112,7 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
     }
   }
   for (int l = 0; l < nl; l++) {
-    const int row = 4 * nc + l, k = lim_dof[l];
+    const int row = nrc + l, k = lim_dof[l];
     d.J[row * n + k] = lim_sign[l];
     const T imp = impedance(m, lim_dist[l]);
     const double A = std::max(m.dof_invweight[k], 1e-15);
@@ -1099,7 +1120,7 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
     d.aref[row] = -B * (lim_sign[l] * d.qvel[k]) - K * imp * lim_dist[l];
     d.D[row] = 1.0 / R;
   }
-  int row = 4 * nc + nl;
+  int row = nrc + nl;
   for (int k = 0; k < n; k++) {
     if (!(m.dof_frictionloss[k] > 0.0)) continue;
     d.J[row * n + k] = 1.0;
@@ -1528,7 +1549,7 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   std::vector<int32_t> gi(2 * m.ngeom);
   std::vector<double> gf(11 * m.ngeom);
   r.read(gi.data(), gi.size()); r.read(gf.data(), gf.size());
-  std::vector<int32_t> pi(2 * m.npair);
+  std::vector<int32_t> pi(4 * m.npair);
   std::vector<double> pf(m.npair);
   r.read(pi.data(), pi.size()); r.read(pf.data(), pf.size());
   std::vector<int32_t> ai(2 * m.nu);
@@ -1598,13 +1619,15 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
     m.geom_friction.push_back(f[10]);
   }
   for (int p = 0; p < m.npair; p++) {
-    m.pair_g1.push_back(pi[2 * p]);
-    m.pair_g2.push_back(pi[2 * p + 1]);
+    m.pair_g1.push_back(pi[4 * p]);
+    m.pair_g2.push_back(pi[4 * p + 1]);
+    m.pair_condim.push_back(pi[4 * p + 2]);
     m.pair_mu.push_back(pf[p]);
-    if (pi[2 * p] < 0 || pi[2 * p] >= m.ngeom || pi[2 * p + 1] < 0 || pi[2 * p + 1] >= m.ngeom) {
+    if (pi[4 * p] < 0 || pi[4 * p] >= m.ngeom || pi[4 * p + 1] < 0 || pi[4 * p + 1] >= m.ngeom ||
+        (pi[4 * p + 2] != 1 && pi[4 * p + 2] != 3)) {
       err = "bad pair"; return false;
     }
-    int t1 = m.geom_type[pi[2 * p]], t2 = m.geom_type[pi[2 * p + 1]];
+    int t1 = m.geom_type[pi[4 * p]], t2 = m.geom_type[pi[4 * p + 1]];
     bool ok = t1 <= t2 && !(t1 == GPLANE && t2 == GPLANE) && !(t1 == GBOX && t2 == GBOX);
     if (t2 == GHFIELD) ok = t1 == GSPHERE && m.hf_nrow > 0;
     if (!ok) { err = "unsupported pair"; return false; }
@@ -1811,10 +1834,14 @@ static void export_contacts(const Model& m, const Data<double>& d, double* out) 
     o[0] = k.dist;
     for (int i = 0; i < 3; i++) o[1 + i] = k.pos[i];
     for (int i = 0; i < 9; i++) o[4 + i] = k.frame[i];
-    const double* f = &d.efc_force[4 * c];
-    o[13] = f[0] + f[1] + f[2] + f[3];
-    o[14] = k.mu * (f[0] - f[1]);
-    o[15] = k.mu * (f[2] - f[3]);
+    const double* f = &d.efc_force[k.row];
+    if (k.condim == 1) {
+      o[13] = f[0]; o[14] = 0.0; o[15] = 0.0;
+    } else {
+      o[13] = f[0] + f[1] + f[2] + f[3];
+      o[14] = k.mu * (f[0] - f[1]);
+      o[15] = k.mu * (f[2] - f[3]);
+    }
     o[16] = k.pair; o[17] = k.sub; o[18] = k.g1; o[19] = k.g2;
   }
 }

@@ -276,7 +276,7 @@ QUAD_FRICTIONLOSS = 3.0
 
 def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
               limits: bool = False, frictionloss: float = 0.0, tether: bool = False,
-              implicit: int = 0, weld_base: bool = False) -> Model:
+              implicit: int = 0, weld_base: bool = False, condim: int = 3) -> Model:
     """Free torso (box 0.3x0.1x0.05 m, 5 kg) + 4 legs x 3 hinges (capsules r 0.02,
     length 0.2, 0.5 kg) with massless sphere feet (r 0.025).  nq 19, nv 18, nu 12.
 
@@ -286,7 +286,8 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     the 12 are active on average, up to 7).  With ``frictionloss`` every hinge carries
     that dry friction (one friction-loss row each).  With ``tether`` the torso's centre
     is held by a connect equality on its standing position (a gantry tether: three
-    two-sided rows).  With ``weld_base`` the torso is welded to the world at its standing
+    two-sided rows).  With ``condim`` = 1 the feet's contacts are frictionless.  With
+    ``weld_base`` the torso is welded to the world at its standing
     pose (a fixed-base robot: six two-sided rows).  With ``implicit`` = 1 the PD velocity gains are integrated
     implicitly (integrator 1); with 2 the PD position gains as well (integrator 2).
 
@@ -298,7 +299,8 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     bld = _Builder("quadruped" + ("_limits" if limits else "") +
                    ("_friction" if frictionloss > 0 else "") + ("_tethered" if tether else "") +
                    ("_implicit" if implicit == 1 else "") +
-                   ("_implicit_pd" if implicit == 2 else "") + ("_welded" if weld_base else ""))
+                   ("_implicit_pd" if implicit == 2 else "") + ("_welded" if weld_base else "") +
+                   ("_frictionless" if condim == 1 else ""))
 
     def rng(k):
         if not limits:
@@ -330,7 +332,7 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     for k, j in enumerate(hinge_ids):
         m.actuators.append(Actuator(type=ACT_PD, joint=j, gear=1.0, kp=35.0, kd=0.5,
                                     ctrlrange=(-1.0, 1.0), qdefault=QUAD_Q_DEFAULT[k % 3]))
-    m.pairs = [(plane, f, mu) for f in feet]
+    m.pairs = [(plane, f, mu, condim) for f in feet]
     if tether:
         bld.connect(torso, 0, (0, 0, 0), (0, 0, QUAD_STAND_Z))
     if weld_base:
@@ -603,6 +605,11 @@ def quadruped_welded() -> Model:
     return quadruped(weld_base=True)
 
 
+def quadruped_frictionless() -> Model:
+    """The quadruped on frictionless ground (condim 1 foot contacts)."""
+    return quadruped(condim=1)
+
+
 def quadruped_rk4() -> Model:
     """The quadruped integrated by fourth-order Runge-Kutta (integrator 3)."""
     m = quadruped()
@@ -772,8 +779,10 @@ def hinge_chain(n: int = 4, link: float = 0.3, mass: float = 1.0, damping: float
 
 def free_body(shape: str = "box", mass: float = 1.0, gravity=(0.0, 0.0, -9.81),
               half=(0.1, 0.2, 0.3), z0: float = 1.0, plane: bool = False,
-              mu: float = 1.0, timestep: float = 0.002, iterations: int = 50) -> Model:
-    """One free body (box or sphere), optionally resting on a plane."""
+              mu: float = 1.0, timestep: float = 0.002, iterations: int = 50,
+              condim: int = 3) -> Model:
+    """One free body (box or sphere), optionally resting on a plane (condim 1: the
+    contacts are frictionless)."""
     bld = _Builder(f"free_{shape}")
     pl = bld.geom(0, GEOM_PLANE, (0, 0, 0), friction=mu) if plane else None
     b = bld.body(0, pos=(0, 0, z0))
@@ -791,7 +800,7 @@ def free_body(shape: str = "box", mass: float = 1.0, gravity=(0.0, 0.0, -9.81),
         raise ValueError(shape)
     m = bld.finish()
     if plane:
-        m.pairs = [(pl, g, mu)]
+        m.pairs = [(pl, g, mu, condim)]
     m.opt = Options(timestep=timestep, gravity=tuple(gravity), iterations=iterations,
                     ls_iterations=50, nconmax=nc if plane else 0)
     q0 = np.zeros(7)
@@ -833,6 +842,7 @@ WORKLOADS = {
     "quadruped_implicit_pd": quadruped_implicit_pd,
     "quadruped_rk4": quadruped_rk4,
     "quadruped_welded": quadruped_welded,
+    "quadruped_frictionless": quadruped_frictionless,
     "quadruped_rough": quadruped_rough,
     "humanoid": humanoid,
     "hand": hand,

@@ -74,7 +74,7 @@ def test_quadruped_shape():
     m = robots.quadruped()
     assert m.total_mass() == pytest.approx(11.0)
     assert len(m.pairs) == 4  # feet only
-    assert all(m.geoms[g2].type == model.GEOM_SPHERE for _, g2, _ in m.pairs)
+    assert all(m.geoms[p[1]].type == model.GEOM_SPHERE for p in m.pairs)
     # standing height: foot straight under the hip with the default pose
     assert robots.QUAD_STAND_Z == pytest.approx(0.2 * math.sqrt(2) + 0.025)
 
@@ -84,7 +84,7 @@ def test_humanoid_shape():
     assert m.total_mass() == pytest.approx(35.0)
     assert m.nbody == 14 and sum(j.type == model.JNT_HINGE for j in m.joints) == 21
     # floor pairs for every geom + self pairs of non-adjacent bodies only
-    for g1, g2, _ in m.pairs:
+    for g1, g2, *_ in m.pairs:
         b1, b2 = m.geoms[g1].body, m.geoms[g2].body
         if b1 == 0:
             continue
@@ -109,5 +109,5 @@ def test_blob_layout_size():
     blob = m.to_blob()
     nb, nj, ng, npr, nu = m.nbody, len(m.joints), len(m.geoms), len(m.pairs), m.nu
     expect = 16 * 4 + 16 * 8 + nb * (8 + 19 * 8) + nj * (16 + 88) + ng * (8 + 88) + \
-        npr * (8 + 8) + nu * (8 + 56) + m.nq * 8
+        npr * (16 + 8) + nu * (8 + 56) + m.nq * 8
     assert len(blob) == expect
