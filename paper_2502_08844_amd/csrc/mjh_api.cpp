@@ -34,6 +34,7 @@ struct HostModel {
   std::vector<int> eq_body;        // [neq][2]
   std::vector<double> eq_anchor;   // [neq][6]
   std::vector<int> eq_type;        // [neq] 0 connect, 1 weld
+  std::vector<int> pair_condim;    // [npair] 3 friction pyramid, 1 frictionless
   std::vector<double> eq_relR;     // [neq][9] weld: body2's reference orientation in body1's frame
   int neqrow = 0;                  // 3 rows per connect, 6 per weld
   double dt = 0, grav[3] = {0, 0, 0}, solref[2] = {0, 0}, solimp[5] = {0, 0, 0, 0, 0};
@@ -101,7 +102,7 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   std::vector<double> bf, jf, gf, pf, af, ef;
   bool ok = rd(bi, 2 * m.nbody) && rd(bf, 19 * (size_t)m.nbody) && rd(ji, 4 * m.njnt) &&
             rd(jf, 11 * (size_t)m.njnt) && rd(gi, 2 * m.ngeom) && rd(gf, 11 * (size_t)m.ngeom) &&
-            rd(pi, 2 * m.npair) && rd(pf, m.npair) && rd(ai, 2 * m.nu) &&
+            rd(pi, 4 * m.npair) && rd(pf, m.npair) && rd(ai, 2 * m.nu) &&
             rd(af, 7 * (size_t)m.nu) && rd(ei, 4 * (size_t)m.neq) && rd(ef, 10 * (size_t)m.neq);
   if (ok && has_hf) {
     int32_t hd[2];
@@ -171,8 +172,9 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
     m.geom_quat.insert(m.geom_quat.end(), f + 6, f + 10);
   }
   for (int p = 0; p < m.npair; p++) {
-    const int g1 = pi[2 * p], g2 = pi[2 * p + 1];
+    const int g1 = pi[4 * p], g2 = pi[4 * p + 1], condim = pi[4 * p + 2];
     if (g1 < 0 || g1 >= m.ngeom || g2 < 0 || g2 >= m.ngeom) { err = "model blob: bad pair"; return MJH_EMODEL; }
+    if (condim != 1 && condim != 3) { err = "pairs take condim 1 or 3"; return MJH_EUNSUPPORTED; }
     const int t1 = m.geom_type[g1], t2 = m.geom_type[g2];
     if (t1 > t2) { err = "model blob: pair geoms must be ordered by type"; return MJH_EMODEL; }
     if (t1 == GEOM_PLANE && t2 == GEOM_PLANE) { err = "model blob: plane-plane pair"; return MJH_EMODEL; }
@@ -183,6 +185,7 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
     }
     m.pair_g1.push_back(g1);
     m.pair_g2.push_back(g2);
+    m.pair_condim.push_back(condim);
     m.pair_mu.push_back(pf[p]);
   }
   for (int a = 0; a < m.nu; a++) {
@@ -436,6 +439,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   pk.add(h.geom_type, &d.geom_type);
   pk.add(h.geom_body, &d.geom_body);
   pk.add(h.pair_g1, &d.pair_g1);
+  pk.add(h.pair_condim, &d.pair_condim);
   pk.add(h.pair_g2, &d.pair_g2);
   pk.add(pair_kind, &d.pair_kind);
   pk.add(pair_candadr, &d.pair_candadr);
@@ -1167,6 +1171,9 @@ mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every, co
   }
   if (mr.h.neq > 0)
     return fail(ctx, MJH_EUNSUPPORTED, "rollout: equality constraints are not differentiated");
+  for (int p = 0; p < mr.h.npair; p++)
+    if (mr.h.pair_condim[p] != 3)
+      return fail(ctx, MJH_EUNSUPPORTED, "rollout: frictionless contacts are not differentiated");
   if (mr.h.integrator != 0)
     return fail(ctx, MJH_EUNSUPPORTED, "rollout: implicit damping is not differentiated");
   {

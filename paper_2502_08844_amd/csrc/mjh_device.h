@@ -938,7 +938,8 @@ DEV void select_contacts(const DevModel& m, float* W, const Team& t, int& status
       r[0] = dist;
       r[1] = pos[0]; r[2] = pos[1]; r[3] = pos[2];
       contact_frame(n, r + 4);
-      r[13] = dr ? m.pair_mu[p] * dr[kDrFric] : m.pair_mu[p];
+      // a frictionless pair keeps four rows, all along the normal (mu = 0)
+      r[13] = m.pair_condim[p] == 1 ? 0.f : (dr ? m.pair_mu[p] * dr[kDrFric] : m.pair_mu[p]);
       r[14] = __int_as_float(m.geom_body[m.pair_g1[p]]);
       r[15] = __int_as_float(m.geom_body[m.pair_g2[p]]);
       r[16] = __int_as_float(p);
@@ -1113,7 +1114,11 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
       for (int i = 0; i < nv; i++) jv += J[row * nv + i] * qvel[i];
       const int b1 = __float_as_int(r[14]), b2 = __float_as_int(r[15]);
       const float mu = r[13];
-      A = (1.f + mu * mu) * (m.body_invweight[b1] + m.body_invweight[b2]);
+      // a frictionless contact's single normal row is four identical rows with four
+      // times its R each: their costs sum to the single row's, so the solution and
+      // the total normal force are the single row's
+      const float cd = m.pair_condim[__float_as_int(r[16])] == 1 ? 4.f : 1.f;
+      A = cd * (1.f + mu * mu) * (m.body_invweight[b1] + m.body_invweight[b2]);
     } else if (row < nrf) {
       const int code = lim[row - nrc];
       int dof;

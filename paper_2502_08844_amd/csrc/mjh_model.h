@@ -99,6 +99,8 @@ struct DevModel {
   const float* geom_pos;      // [ngeom][3]
   const float* geom_rot;      // [ngeom][9]
   const float* pair_mu;
+  const int* pair_condim;     // [npair] 3: friction pyramid; 1: frictionless (four identical
+                              // normal rows, each with four times the single row's R)
   const float* act_gear;
   const float* act_kp;
   const float* act_kd;

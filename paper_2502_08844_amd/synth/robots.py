@@ -566,7 +566,7 @@ def quadruped_rough(seed: int = 0) -> Model:
                            size=(ROUGH_SIZE, ROUGH_SIZE, ROUGH_HEIGHT), data=data)
     floor = m.pairs[0][0]
     m.geoms[floor].type = GEOM_HFIELD
-    m.pairs = [(f, floor, mu) for (_, f, mu) in m.pairs]
+    m.pairs = [(p[1], floor, *p[2:]) for p in m.pairs]
     # stand on the terrain: lift the torso by the terrain height under the origin
     h0 = ROUGH_HEIGHT * data[ROUGH_N // 2, ROUGH_N // 2]
     m.qpos0 = m.qpos0.copy()

@@ -111,3 +111,13 @@ def test_blob_layout_size():
     expect = 16 * 4 + 16 * 8 + nb * (8 + 19 * 8) + nj * (16 + 88) + ng * (8 + 88) + \
         npr * (16 + 8) + nu * (8 + 56) + m.nq * 8
     assert len(blob) == expect
+
+
+def test_every_workload_builds_and_loads():
+    """Each named workload serialises and the reference parses it (sizes agree)."""
+    import oracle
+    for kind, make in robots.WORKLOADS.items():
+        m = make()
+        o = oracle.Oracle(m.to_blob())
+        assert (o.nq, o.nv, o.nu, o.npair) == (m.nq, m.nv, m.nu, len(m.pairs)), kind
+        assert o.nrowmax == m.nrowmax, kind
