@@ -69,8 +69,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--model", default="quadruped",
                     choices=["quadruped", "quadruped_limits", "quadruped_friction",
-                             "quadruped_tethered", "quadruped_implicit", "quadruped_rough",
-                             "humanoid", "hand", "cartpole"],
+                             "quadruped_tethered", "quadruped_welded", "quadruped_frictionless",
+                             "quadruped_implicit", "quadruped_implicit_pd", "quadruped_rk4",
+                             "quadruped_rough", "humanoid", "hand", "cartpole"],
                     help="robot of the timed batch (the headline metric is the quadruped)")
     ap.add_argument("--nworld", type=int, default=8192)
     ap.add_argument("--nstep", type=int, default=1000)

@@ -693,18 +693,43 @@ DEV V3 tri_nearest(V3 a, V3 b, V3 c, V3 p, V3& nrm) {
 }
 
 // Sphere (geom 1: centre c, radius r) against the heightfield (geom 2 at xg, Rg): the
-// nearest point of the triangles of the grid cells under the sphere's footprint (the
-// first in cell and triangle order on ties); signed by the side of that triangle's
-// plane.  The normal points from the sphere into the surface; pos is midway between
-// the surfaces.  +inf when the footprint misses the grid.
-DEV float sphere_hfield(const DevModel& m, const float* xg, const float* Rg, const float* c,
-                        float r, float* pos, float* n) {
-  const int nr = m.hf_nrow, nc = m.hf_ncol;
-  const float sx = m.hf_size[0], sy = m.hf_size[1], sz = m.hf_size[2];
-  const float dx = 2.f * sx / (nc - 1), dy = 2.f * sy / (nr - 1);
+// contact is the nearest point of the triangles of the grid cells under the sphere's
+// footprint (the first in cell and triangle order on ties), signed by the side of that
+// triangle's plane.  The search (hfield_nearest) runs once per candidate in the
+// candidate phase and returns the winning triangle as ((i ncol + j) << 1 | k), -1 when
+// the footprint misses the grid; sphere_hfield_tri evaluates that one triangle, so the
+// inlined contact code holds no loops.
+
+// the sphere centre in the heightfield's frame
+DEV V3 hfield_local(const float* xg, const float* Rg, const float* c) {
   const float rx = c[0] - xg[0], ry = c[1] - xg[1], rz = c[2] - xg[2];
-  const V3 cl = {Rg[0] * rx + Rg[3] * ry + Rg[6] * rz, Rg[1] * rx + Rg[4] * ry + Rg[7] * rz,
-                 Rg[2] * rx + Rg[5] * ry + Rg[8] * rz};
+  return {Rg[0] * rx + Rg[3] * ry + Rg[6] * rz, Rg[1] * rx + Rg[4] * ry + Rg[7] * rz,
+          Rg[2] * rx + Rg[5] * ry + Rg[8] * rz};
+}
+
+// triangle k (0: v00 v01 v11, 1: v00 v11 v10) of cell (i, j)
+DEV void hfield_tri(const DevModel& m, int i, int j, int k, V3& a, V3& b, V3& c) {
+  const int nc = m.hf_ncol;
+  const float sx = m.hf_size[0], sy = m.hf_size[1], sz = m.hf_size[2];
+  const float dx = 2.f * sx / (nc - 1), dy = 2.f * sy / (m.hf_nrow - 1);
+  const float x0 = -sx + dx * j, x1 = x0 + dx, y0 = -sy + dy * i, y1 = y0 + dy;
+  const float* hrow = m.hf_data + (size_t)i * nc + j;
+  a = {x0, y0, sz * hrow[0]};
+  if (k == 0) {
+    b = {x1, y0, sz * hrow[1]};
+    c = {x1, y1, sz * hrow[nc + 1]};
+  } else {
+    b = {x1, y1, sz * hrow[nc + 1]};
+    c = {x0, y1, sz * hrow[nc]};
+  }
+}
+
+DEV int hfield_nearest(const DevModel& m, const float* xg, const float* Rg, const float* c,
+                       float r) {
+  const int nr = m.hf_nrow, nc = m.hf_ncol;
+  const float sx = m.hf_size[0], sy = m.hf_size[1];
+  const float dx = 2.f * sx / (nc - 1), dy = 2.f * sy / (nr - 1);
+  const V3 cl = hfield_local(xg, Rg, c);
   // cell range of the footprint, clamped before the conversion to int
   auto cell = [](float x, int hi) { return (int)floorf(fminf(fmaxf(x, -1.f), (float)hi)); };
   const int j0 = max(0, cell((cl.x - r + sx) / dx, nc));
@@ -712,25 +737,32 @@ DEV float sphere_hfield(const DevModel& m, const float* xg, const float* Rg, con
   const int i0 = max(0, cell((cl.y - r + sy) / dy, nr));
   const int i1 = min(nr - 2, cell((cl.y + r + sy) / dy, nr));
   float best = INFINITY;
-  V3 bq = {0.f, 0.f, 0.f}, bn = {0.f, 0.f, 1.f};
+  int code = -1;
   for (int i = i0; i <= i1; i++)
-    for (int j = j0; j <= j1; j++) {
-      const float x0 = -sx + dx * j, x1 = x0 + dx, y0 = -sy + dy * i, y1 = y0 + dy;
-      const float* hrow = m.hf_data + (size_t)i * nc + j;
-      const V3 v00 = {x0, y0, sz * hrow[0]}, v01 = {x1, y0, sz * hrow[1]};
-      const V3 v10 = {x0, y1, sz * hrow[nc]}, v11 = {x1, y1, sz * hrow[nc + 1]};
+    for (int j = j0; j <= j1; j++)
       for (int k = 0; k < 2; k++) {
-        V3 nt;
-        const V3 q = k == 0 ? tri_nearest(v00, v01, v11, cl, nt)
-                            : tri_nearest(v00, v11, v10, cl, nt);
-        const V3 d = v3sub(cl, q);
+        V3 a, b, cc, nt;
+        hfield_tri(m, i, j, k, a, b, cc);
+        const V3 d = v3sub(cl, tri_nearest(a, b, cc, cl, nt));
         const float dd = v3dot(d, d);
-        if (dd < best) { best = dd; bq = q; bn = nt; }
+        if (dd < best) { best = dd; code = ((i * nc + j) << 1) | k; }
       }
-    }
-  if (best == INFINITY) return INFINITY;
-  const float L = sqrtf(best);
+  return code;
+}
+
+// The contact with triangle `code`: the normal points from the sphere into the surface
+// and pos is midway between the surfaces; +inf for code < 0.
+DEV float sphere_hfield_tri(const DevModel& m, const float* xg, const float* Rg, const float* c,
+                            float r, int code, float* pos, float* n) {
+  if (code < 0) return INFINITY;
+  const int cellid = code >> 1, k = code & 1;
+  const int i = cellid / m.hf_ncol, j = cellid - i * m.hf_ncol;
+  const V3 cl = hfield_local(xg, Rg, c);
+  V3 a, b, cc, bn;
+  hfield_tri(m, i, j, k, a, b, cc);
+  const V3 bq = tri_nearest(a, b, cc, cl, bn);
   const V3 d = v3sub(cl, bq);
+  const float L = sqrtf(v3dot(d, d));
   const bool below = v3dot(bn, d) < 0.f;
   float nl[3];
   if (L > 1e-12f) {
@@ -744,7 +776,7 @@ DEV float sphere_hfield(const DevModel& m, const float* xg, const float* Rg, con
   float qw[3];
   mv3(Rg, nl, n);
   mv3(Rg, bqa, qw);
-  for (int k = 0; k < 3; k++) pos[k] = 0.5f * (c[k] + r * n[k] + qw[k] + xg[k]);
+  for (int q = 0; q < 3; q++) pos[q] = 0.5f * (c[q] + r * n[q] + qw[q] + xg[q]);
   return (below ? -L : L) - r;
 }
 
@@ -794,8 +826,8 @@ DEV float pair_contact(const DevModel& m, const float* W, int p, int sub, float 
       float q[3] = {a[0] + t * u[0], a[1] + t * u[1], a[2] + t * u[2]};
       return sphere_sphere(x1, s1[0], q, s2[0], pos, n);
     }
-    case PK_SPHERE_HFIELD:
-      return sphere_hfield(m, x2, R2, x1, s1[0], pos, n);
+    case PK_SPHERE_HFIELD:  // tpar: the winning triangle found in the candidate phase
+      return sphere_hfield_tri(m, x2, R2, x1, s1[0], __float_as_int(tpar), pos, n);
     case PK_SPHERE_BOX: {
       float nb[3];
       float sd = box_point(x2, R2, s2, x1, nb);
@@ -869,6 +901,17 @@ DEV void collide_candidates(const DevModel& m, float* W, const Team& t) {
         used |= 1u << best;
       }
       for (int k = 0; k < 8; k++) { cd[base + k] = (used >> k & 1) ? dist[k] : INFINITY; cp[base + k] = 0.f; }
+    } else if (kind == PK_SPHERE_HFIELD) {
+      const int g1 = m.pair_g1[p], g2 = m.pair_g2[p];
+      float x1[3], R1[9], x2[3], R2[9];
+      geom_pose(m, W, g1, x1, R1);
+      geom_pose(m, W, g2, x2, R2);
+      const float r = m.geom_size[3 * g1];
+      const int code = hfield_nearest(m, x2, R2, x1, r);
+      float pos[3], n[3];
+      const float d = sphere_hfield_tri(m, x2, R2, x1, r, code, pos, n);
+      cd[base] = d < 0.f ? d : INFINITY;
+      cp[base] = __int_as_float(code);
     } else {
       const int nc = kind == PK_PLANE_CAPSULE ? 2 : 1;
       float pos[3], n[3];

@@ -5,6 +5,10 @@ The step and env kernels run one world's whole step per team with everything inl
 into the kernel: 128 VGPRs for four waves per SIMD, and a small private segment for
 spills.  A per-world driver left as a real call has a stack frame of several hundred
 bytes per lane (measured: 580 B and 35 % lower throughput), which these bounds catch.
+The step kernel's bound also keeps its spill area (bytes per lane x 64 lanes x 4096
+resident waves of the 8192-world quadruped launch) within the chip's L2: at 128 B per
+lane it outgrew it and the spills reached HBM (1.3 GB written per launch instead of
+16 MB).
 """
 import pytest
 
@@ -25,8 +29,8 @@ def usage():
     return u
 
 
-@pytest.mark.parametrize("kernel,scratch_max", [(STEP, 256), (STEP_RK, 256), (ENV, 512),
-                                                (ENV_RK, 512)])
+@pytest.mark.parametrize("kernel,scratch_max", [(STEP, 96), (STEP_RK, 128), (ENV, 256),
+                                                (ENV_RK, 256)])
 def test_hot_kernels_fit_four_waves_with_small_scratch(usage, kernel, scratch_max):
     k = usage[kernel]
     assert k["VGPRs"] <= 128 and k["Occupancy"] >= 4
