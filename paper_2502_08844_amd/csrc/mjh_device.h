@@ -1250,7 +1250,7 @@ DEV int pad_rows(const DevModel& m, float* W, const Team& t, int nrow) {
 // forward solve L y = b (b overwritten) rides along.  Returns false for a non-positive
 // pivot.  `w` (nrow words) receives the rows' curvatures: D on the quadratic piece, else 0.
 DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
-                          float* b = nullptr, float* y = nullptr) {
+                          float* b = nullptr, float* y = nullptr, bool rev = false) {
   const int nv = m.nv;
   const float* M = W + m.o_M;
   float* H = W + m.o_H;
@@ -1277,7 +1277,7 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
 #pragma unroll
     for (int v = 0; v < 16; v++) {
       const int i = 8 * (v >> 2) + 4 * kh + (v & 3);
-      C[v] = (i < nv && j <= i) ? M[tri(i, j)] : 0.f;
+      C[v] = (i < nv && j <= i) ? (rev ? M[tri(nv - 1 - j, nv - 1 - i)] : M[tri(i, j)]) : 0.f;
     }
     for (int r = 0; r < nr; r += 2) {
       const int rr = r + kh;
@@ -1297,7 +1297,7 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
     for (int k = t.lane; k < m.ntri; k += t.T) {
       int i, j;
       t.unrank(k, i, j);
-      float v = M[k];
+      float v = rev ? M[tri(nv - 1 - j, nv - 1 - i)] : M[k];
       for (int r = 0; r < nru; r++) v += w[r] * J[r * nv + i] * J[r * nv + j];
       H[k] = v;
     }
@@ -1808,9 +1808,28 @@ DEV void world_step(const DevModel& m, float* W0, const Team& t0, const float* c
     MJH_PHASE_CTX
     float* a0 = W + m.o_a0;
     const float* frc = W + m.o_frc;
-    for (int i = t.lane; i < m.nv; i += t.T) a0[i] = frc[i];
-    ltdl_factor(m, W, t, W + m.o_a0);  // also solves L^T y = frc in place
-    ltdl_solve(m, W, t, nullptr, W + m.o_a0, true);
+    if (m.nv <= t.T) {
+      // a0 = M^-1 frc by the blocked dense Cholesky of the Newton Hessian with no rows:
+      // two barriers per four columns take fewer dependent steps than the tree LTDL's
+      // one barrier per dof.  It factors M in reversed dof order (leaves first, the
+      // LTDL's elimination order): a floating base eliminated first would subtract its
+      // large coupling from the light links' inertias and lose FP32 digits there.
+      // The solve runs in a0 in reversed order (P reverses the dofs).
+      for (int i = t.lane; i < m.nv; i += t.T) a0[i] = frc[m.nv - 1 - i];
+      t.sync();
+      hessian_cholesky(m, W, t, 0, a0, a0, true);  // L y = P frc
+      cholesky_back(m, W, t, a0, a0);              // L^T x = y, a0 = P x
+      for (int i = t.lane; i < m.nv / 2; i += t.T) {
+        const float u = a0[i];
+        a0[i] = a0[m.nv - 1 - i];
+        a0[m.nv - 1 - i] = u;
+      }
+      t.sync();
+    } else {
+      for (int i = t.lane; i < m.nv; i += t.T) a0[i] = frc[i];
+      ltdl_factor(m, W, t, W + m.o_a0);  // also solves L^T y = frc in place
+      ltdl_solve(m, W, t, nullptr, W + m.o_a0, true);
+    }
     MJH_MARK(3);
   }
   {
