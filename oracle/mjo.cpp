@@ -233,8 +233,10 @@ struct Model {
   std::vector<int> geom_type, geom_body;
   std::vector<double> geom_size, geom_pos, geom_quat, geom_friction;
   std::vector<int> pair_g1, pair_g2;
-  std::vector<int> pair_condim;  // 3: friction pyramid (4 rows); 1: frictionless (1 row)
-  std::vector<double> pair_mu;
+  std::vector<int> pair_condim;  // 1 frictionless (1 row); 3 sliding (4 rows); 4 + torsion
+                                 // (6 rows); 6 + rolling (10 rows): two pyramid edges a
+                                 // friction direction
+  std::vector<double> pair_mu, pair_mu_torsion, pair_mu_rolling;
   std::vector<int> act_type, act_jnt;
   std::vector<double> act_gear, act_kp, act_kd, act_range, act_qdef;
   int neq = 0;
@@ -276,9 +278,9 @@ template <class T> struct Contact {
   T dist = 0.0;
   T pos[3];
   T frame[9];  // rows: normal (geom1 -> geom2), tangent 1, tangent 2
-  T mu = 0.0;
+  T mu = 0.0, mu_t = 0.0, mu_r = 0.0;  // sliding, torsional and rolling coefficients
   int pair = -1, sub = -1, g1 = -1, g2 = -1;
-  int condim = 3, row = 0;  // its row count (1 or 4) and first row
+  int condim = 3, row = 0;  // its contact dimension and first row
 };
 
 template <class T> struct Data {
@@ -971,6 +973,8 @@ template <class T> void collision(const Model& m, Data<T>& d) {
       k.mu = m.pair_mu[pi];
       k.pair = pi; k.sub = c.sub; k.g1 = m.pair_g1[pi]; k.g2 = m.pair_g2[pi];
       k.condim = m.pair_condim[pi];
+      k.mu_t = m.pair_mu_torsion[pi];
+      k.mu_r = m.pair_mu_rolling[pi];
       all.push_back(k);
     }
   }
@@ -1058,7 +1062,7 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
   int nrc = 0;  // contact rows: four pyramid edges, or one normal row without friction
   for (int c = 0; c < nc; c++) {
     d.con[c].row = nrc;
-    nrc += d.con[c].condim == 1 ? 1 : 4;
+    nrc += d.con[c].condim == 1 ? 1 : 2 * (d.con[c].condim - 1);
   }
   d.nrow = nrc + nl + m.nfric + m.neqrow;
   d.J.assign(d.nrow * n, 0.0);
@@ -1098,13 +1102,29 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
     const double A = std::max((1.0 + val(k.mu) * val(k.mu)) *
                                   (m.body_invweight[b1] + m.body_invweight[b2]), 1e-15);
     const T R = (1.0 - imp) / imp * A;
-    for (int e = 0; e < 4; e++) {
-      const int row = k.row + e;
-      const int t = 1 + e / 2;
-      const T sg = (e % 2 == 0) ? k.mu : -k.mu;
+    // friction directions: the two tangents (mu); with condim >= 4 the spin about the
+    // normal, n . (w2 - w1) (mu_t); with condim 6 the rolling about the tangents,
+    // t_k . (w2 - w1) (mu_r).  Each gives the edges J_n + mu J_dir and J_n - mu J_dir.
+    std::vector<T> Ja(3 * n, T(0.0));
+    if (k.condim >= 4) {
+      body_angjac(m, d, b2, J2.data());
+      body_angjac(m, d, b1, J1.data());
+      for (int r = 0; r < 3; r++)
+        for (int i = 0; i < n; i++) {
+          T s = 0.0;
+          for (int a = 0; a < 3; a++) s += k.frame[3 * r + a] * (J2[a * n + i] - J1[a * n + i]);
+          Ja[r * n + i] = s;
+        }
+    }
+    const int ndir = k.condim - 1;
+    for (int e = 0; e < 2 * ndir; e++) {
+      const int row = k.row + e, dir = e / 2;
+      const T* Jd = dir < 2 ? &Jc[(1 + dir) * n] : (dir == 2 ? &Ja[0] : &Ja[(dir - 2) * n]);
+      const T mu = dir < 2 ? k.mu : (dir == 2 ? k.mu_t : k.mu_r);
+      const T sg = (e % 2 == 0) ? mu : -mu;
       T jv = 0.0;
       for (int i = 0; i < n; i++) {
-        d.J[row * n + i] = Jc[i] + sg * Jc[t * n + i];
+        d.J[row * n + i] = Jc[i] + sg * Jd[i];
         jv += d.J[row * n + i] * d.qvel[i];
       }
       d.aref[row] = -B * jv - K * imp * k.dist;
@@ -1550,7 +1570,7 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   std::vector<double> gf(11 * m.ngeom);
   r.read(gi.data(), gi.size()); r.read(gf.data(), gf.size());
   std::vector<int32_t> pi(4 * m.npair);
-  std::vector<double> pf(m.npair);
+  std::vector<double> pf(3 * m.npair);
   r.read(pi.data(), pi.size()); r.read(pf.data(), pf.size());
   std::vector<int32_t> ai(2 * m.nu);
   std::vector<double> af(7 * m.nu);
@@ -1622,9 +1642,11 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
     m.pair_g1.push_back(pi[4 * p]);
     m.pair_g2.push_back(pi[4 * p + 1]);
     m.pair_condim.push_back(pi[4 * p + 2]);
-    m.pair_mu.push_back(pf[p]);
+    m.pair_mu.push_back(pf[3 * p]);
+    m.pair_mu_torsion.push_back(pf[3 * p + 1]);
+    m.pair_mu_rolling.push_back(pf[3 * p + 2]);
     if (pi[4 * p] < 0 || pi[4 * p] >= m.ngeom || pi[4 * p + 1] < 0 || pi[4 * p + 1] >= m.ngeom ||
-        (pi[4 * p + 2] != 1 && pi[4 * p + 2] != 3)) {
+        (pi[4 * p + 2] != 1 && pi[4 * p + 2] != 3 && pi[4 * p + 2] != 4 && pi[4 * p + 2] != 6)) {
       err = "bad pair"; return false;
     }
     int t1 = m.geom_type[pi[4 * p]], t2 = m.geom_type[pi[4 * p + 1]];
@@ -1780,12 +1802,14 @@ void* mjo_load(const unsigned char* blob, long nbytes, char* err, int errlen) {
 
 void mjo_free(void* h) { delete static_cast<Model*>(h); }
 
-// out[0..13] = nq nv nu nbody njnt ngeom npair nconmax iterations ls_iterations nlimit
-// nfric neq neqrow
+// out[0..14] = nq nv nu nbody njnt ngeom npair nconmax iterations ls_iterations nlimit
+// nfric neq neqrow conrows
 int mjo_dims(void* h, int* out) {
   Model& m = *static_cast<Model*>(h);
-  int v[14] = {m.nq, m.nv, m.nu, m.nbody, m.njnt, m.ngeom, m.npair, m.nconmax,
-               m.iterations, m.ls_iterations, m.nlimit, m.nfric, m.neq, m.neqrow};
+  int conrows = m.npair ? 1 : 4;  // rows of the widest contact
+  for (int c : m.pair_condim) conrows = std::max(conrows, c == 1 ? 1 : 2 * (c - 1));
+  int v[15] = {m.nq, m.nv, m.nu, m.nbody, m.njnt, m.ngeom, m.npair, m.nconmax,
+               m.iterations, m.ls_iterations, m.nlimit, m.nfric, m.neq, m.neqrow, conrows};
   std::memcpy(out, v, sizeof(v));
   return 0;
 }
@@ -1881,7 +1905,7 @@ int mjo_step(void* h, int nworld, int nstep, double* qpos, double* qvel, double*
 // Output sizes: xpos [nbody*3], xmat [nbody*9], xipos [nbody*3], cdof [nv*6],
 // cvel [nbody*6], M [nv*nv], bias [nv], act [nv], pass [nv], qacc_smooth [nv],
 // qacc [nv], qfrc_con [nv], ncon, contacts [nconmax*20], nrow, J [nrowmax * nv],
-// aref, D, efc_force [nrowmax] with nrowmax = 4 nconmax + nlimit + nfric + neqrow (contact
+// aref, D, efc_force [nrowmax] with nrowmax = conrows nconmax + nlimit + nfric + neqrow (contact
 // rows first, then the violated limits, the friction-loss rows and the equality rows).
 // NULL skips an output.
 int mjo_forward(void* h, const double* qpos, const double* qvel, const double* qacc_ws,

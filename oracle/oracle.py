@@ -102,12 +102,12 @@ class Oracle:
         self._h = self._lib.mjo_load(bytes(blob), len(blob), err, 256)
         if not self._h:
             raise ValueError("oracle rejected model: " + err.value.decode())
-        dims = np.zeros(14, dtype=np.int32)
+        dims = np.zeros(15, dtype=np.int32)
         self._lib.mjo_dims(self._h, _i(dims))
         (self.nq, self.nv, self.nu, self.nbody, self.njnt, self.ngeom, self.npair,
          self.nconmax, self.iterations, self.ls_iterations, self.nlimit, self.nfric,
-         self.neq, self.neqrow) = (int(x) for x in dims)
-        self.nrowmax = 4 * self.nconmax + self.nlimit + self.nfric + self.neqrow
+         self.neq, self.neqrow, self.conrows) = (int(x) for x in dims)
+        self.nrowmax = self.conrows * self.nconmax + self.nlimit + self.nfric + self.neqrow
 
     def __del__(self):
         if getattr(self, "_h", None):

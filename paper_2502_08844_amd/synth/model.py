@@ -24,8 +24,8 @@ Blob layout (little endian, version 3), every block 8-byte aligned:
            f64   [njnt][11] : pos[3], axis[3], damping, armature, range[2], frictionloss
   geom     int32 [ngeom][2] : type (0 plane, 1 sphere, 2 capsule, 3 box), body
            f64   [ngeom][11]: size[3], pos[3], quat[4], friction
-  pair     int32 [npair][4] : geom1, geom2 (type(geom1) <= type(geom2)), condim (3 or 1), 0
-           f64   [npair][1] : friction coefficient mu
+  pair     int32 [npair][4] : geom1, geom2 (type(geom1) <= type(geom2)), condim (1, 3, 4, 6), 0
+           f64   [npair][3] : friction coefficients: sliding mu, torsional, rolling
   actuator int32 [nu][2]    : type (0 motor, 1 position PD), joint
            f64   [nu][7]    : gear, kp, kd, ctrlrange[2], qdefault, 0
   equality int32 [neq][4]   : type (0 connect, 1 weld), body1, body2, 0
@@ -159,8 +159,9 @@ class Model:
     bodies: List[Body] = field(default_factory=list)
     joints: List[Joint] = field(default_factory=list)
     geoms: List[Geom] = field(default_factory=list)
-    # (geom1, geom2, mu) or (geom1, geom2, mu, condim): condim 3 (default) is the
-    # friction pyramid, condim 1 a frictionless contact (one normal row)
+    # (geom1, geom2, mu[, condim[, mu_torsion[, mu_rolling]]]): condim 3 (default) is
+    # the sliding-friction pyramid, 1 a frictionless contact (one normal row), 4 adds
+    # torsional friction about the normal and 6 rolling friction about the tangents
     pairs: List[tuple] = field(default_factory=list)
     actuators: List[Actuator] = field(default_factory=list)
     equalities: List[Equality] = field(default_factory=list)
@@ -200,8 +201,14 @@ class Model:
         return sum(6 if e.type == EQ_WELD else 3 for e in self.equalities)
 
     @property
+    def conrows(self) -> int:
+        """Rows of the model's widest contact: 1 frictionless, 2 (condim - 1) otherwise."""
+        cd = [p[3] if len(p) > 3 else 3 for p in self.pairs]
+        return max([1 if c == 1 else 2 * (c - 1) for c in cd], default=4)
+
+    @property
     def nrowmax(self) -> int:
-        return 4 * self.opt.nconmax + self.nlimit + self.nfric + self.neqrow
+        return self.conrows * self.opt.nconmax + self.nlimit + self.nfric + self.neqrow
 
     @property
     def nlimit(self) -> int:
@@ -247,7 +254,7 @@ class Model:
             assert 0 < e.body1 < self.nbody and 0 <= e.body2 < self.nbody
             assert e.body1 != e.body2
         for g1, g2, *rest in self.pairs:
-            assert len(rest) == 1 or rest[1] in (1, 3), "pair condim 1 or 3"
+            assert len(rest) == 1 or rest[1] in (1, 3, 4, 6), "pair condim 1, 3, 4 or 6"
             assert self.geoms[g1].type <= self.geoms[g2].type, "pair order by geom type"
             if self.geoms[g2].type == GEOM_HFIELD:
                 assert self.geoms[g1].type == GEOM_SPHERE, "heightfields pair with spheres"
@@ -286,7 +293,8 @@ class Model:
         parts.append(blk_i([[g.type, g.body] for g in self.geoms]))
         parts.append(blk_f([[*g.size, *g.pos, *g.quat, g.friction] for g in self.geoms]))
         parts.append(blk_i([[p[0], p[1], p[3] if len(p) > 3 else 3, 0] for p in self.pairs]))
-        parts.append(blk_f([[p[2]] for p in self.pairs]))
+        parts.append(blk_f([[p[2], p[4] if len(p) > 4 else 0.0, p[5] if len(p) > 5 else 0.0]
+                            for p in self.pairs]))
         parts.append(blk_i([[a.type, a.joint] for a in self.actuators]))
         parts.append(blk_f([[a.gear, a.kp, a.kd, *a.ctrlrange, a.qdefault, 0]
                             for a in self.actuators]))

@@ -780,9 +780,9 @@ def hinge_chain(n: int = 4, link: float = 0.3, mass: float = 1.0, damping: float
 def free_body(shape: str = "box", mass: float = 1.0, gravity=(0.0, 0.0, -9.81),
               half=(0.1, 0.2, 0.3), z0: float = 1.0, plane: bool = False,
               mu: float = 1.0, timestep: float = 0.002, iterations: int = 50,
-              condim: int = 3) -> Model:
+              condim: int = 3, mu_torsion: float = 0.0, mu_rolling: float = 0.0) -> Model:
     """One free body (box or sphere), optionally resting on a plane (condim 1: the
-    contacts are frictionless)."""
+    contacts are frictionless; 4: with torsional friction; 6: also rolling friction)."""
     bld = _Builder(f"free_{shape}")
     pl = bld.geom(0, GEOM_PLANE, (0, 0, 0), friction=mu) if plane else None
     b = bld.body(0, pos=(0, 0, z0))
@@ -800,7 +800,7 @@ def free_body(shape: str = "box", mass: float = 1.0, gravity=(0.0, 0.0, -9.81),
         raise ValueError(shape)
     m = bld.finish()
     if plane:
-        m.pairs = [(pl, g, mu, condim)]
+        m.pairs = [(pl, g, mu, condim, mu_torsion, mu_rolling)]
     m.opt = Options(timestep=timestep, gravity=tuple(gravity), iterations=iterations,
                     ls_iterations=50, nconmax=nc if plane else 0)
     q0 = np.zeros(7)

@@ -60,3 +60,82 @@ def test_frictionless_box_slides_at_g_sin_theta(theta):
         assert np.abs(res["contacts"][0, :4, 14:16]).max() == 0
     f = o.forward(q[0], v[0], ws[0], mode=MODE_CONVERGED)
     assert f["nrow"] == 4
+
+
+# ------------------------------------------------------------------ condim 4 and 6
+def _settled_sphere(condim, mu_t=0.0, mu_r=0.0, r=0.1, mass=3.0):
+    m = robots.free_body("sphere", mass=mass, half=(r, 0, 0), plane=True, condim=condim,
+                         mu_torsion=mu_t, mu_rolling=mu_r, timestep=0.002)
+    o = Oracle(m)
+    q0 = m.qpos0.copy()
+    q0[2] = r
+    res = o.step(q0[None], np.zeros((1, 6)), nstep=1500, mode=MODE_CONVERGED)
+    return m, o, res
+
+
+def _trace(o, res, v, nstep):
+    """Per step: contact count, velocity, acceleration and the rows' total force."""
+    q, vv, ws = res["qpos"], v, res["qacc_ws"]
+    out = []
+    for _ in range(nstep):
+        f = o.forward(q[0], vv[0], ws[0], mode=MODE_CONVERGED)
+        r = o.step(q, vv, ws, nstep=1, mode=MODE_CONVERGED)
+        out.append((int(r["ncon"][0]), vv[0].copy(), f["qacc"].copy(), f["efc_force"].sum(),
+                    f["nrow"]))
+        q, vv, ws = r["qpos"], r["qvel"], r["qacc_ws"]
+    return out
+
+
+@pytest.mark.parametrize("condim,mu_t", [(3, 0.0), (4, 0.01), (4, 0.02)])
+def test_torsional_friction_opposes_spin_within_its_bound(condim, mu_t):
+    """Spin about the vertical.  A point contact with sliding friction only exerts no
+    torque about the normal: the spin is kept exactly.  Torsional friction (two more
+    pyramid edges J_n -+ mu_t J_spin with forces f+, f- >= 0) exerts the torque
+    mu_t (f+ - f-), so |I_z dw/dt| <= mu_t sum(f) at every step, and the spin falls
+    monotonically.  (The soft contact makes the torque approach that bound only where
+    the edges' slip mu_t w is large against its regularisation: at these rates it is
+    velocity dependent, not Coulomb's.)  The spin stays below g / (B mu_t):
+    an edge reads it as a normal approach speed mu_t w, and its reference acceleration
+    B mu_t w would lift the ball off the plane above that."""
+    r, mass, w0 = 0.1, 3.0, 1.5
+    m, o, res = _settled_sphere(condim, mu_t, r=r, mass=mass)
+    v = res["qvel"].copy()
+    v[0, 5] = w0
+    tr = _trace(o, res, v, 25)
+    assert all(n == 1 for n, *_ in tr)
+    w = np.array([x[1][5] for x in tr])
+    if condim == 3:
+        np.testing.assert_allclose(w, w0, rtol=1e-10)
+        assert tr[-1][4] == 4
+        return
+    assert tr[-1][4] == 6
+    assert np.all(np.diff(w) < 0)
+    Iz = 0.4 * mass * r * r
+    torque = np.array([-Iz * x[2][5] for x in tr])
+    bound = np.array([mu_t * x[3] for x in tr])
+    assert np.all(torque > 0) and np.all(torque <= bound * (1 + 1e-9))
+
+
+@pytest.mark.parametrize("condim,mu_r", [(4, 0.0), (6, 0.002)])
+def test_rolling_friction_opposes_rolling_within_its_bound(condim, mu_r):
+    """A ball rolling without slipping keeps rolling under sliding and torsional
+    friction alone (to 1e-3 over 60 steps, the soft contact's own loss; rolling
+    friction takes 17 times that here).  Rolling friction (edges J_n -+ mu_r J_roll about the tangents)
+    resists it: the speed falls monotonically, and the resisting torque, (I/r + m r)
+    |dv/dt| (m a = f, I alpha = -f r - tau, a = alpha r), never exceeds mu_r sum(f)."""
+    r, mass, v0 = 0.1, 3.0, 1.0
+    m, o, res = _settled_sphere(condim, 0.01, mu_r, r=r, mass=mass)
+    v = res["qvel"].copy()
+    v[0, 0], v[0, 4] = v0, v0 / r  # x velocity with the spin about +y of rolling
+    tr = _trace(o, res, v, 60)
+    assert all(n == 1 for n, *_ in tr)
+    vx = np.array([x[1][0] for x in tr])
+    if condim == 4:
+        np.testing.assert_allclose(vx, v0, rtol=1e-3)
+        return
+    assert tr[-1][4] == 10
+    assert np.all(np.diff(vx[5:]) < 0)
+    I = 0.4 * mass * r * r
+    tau = np.array([-(I / r + mass * r) * x[2][0] for x in tr])[5:]
+    bound = np.array([mu_r * x[3] for x in tr])[5:]
+    assert np.all(tau > 0) and np.all(tau <= bound * (1 + 1e-6))

@@ -109,7 +109,7 @@ def test_blob_layout_size():
     blob = m.to_blob()
     nb, nj, ng, npr, nu = m.nbody, len(m.joints), len(m.geoms), len(m.pairs), m.nu
     expect = 16 * 4 + 16 * 8 + nb * (8 + 19 * 8) + nj * (16 + 88) + ng * (8 + 88) + \
-        npr * (16 + 8) + nu * (8 + 56) + m.nq * 8
+        npr * (16 + 24) + nu * (8 + 56) + m.nq * 8
     assert len(blob) == expect
 
 
