@@ -1859,13 +1859,13 @@ static void export_contacts(const Model& m, const Data<double>& d, double* out) 
     for (int i = 0; i < 3; i++) o[1 + i] = k.pos[i];
     for (int i = 0; i < 9; i++) o[4 + i] = k.frame[i];
     const double* f = &d.efc_force[k.row];
-    if (k.condim == 1) {
-      o[13] = f[0]; o[14] = 0.0; o[15] = 0.0;
-    } else {
-      o[13] = f[0] + f[1] + f[2] + f[3];
-      o[14] = k.mu * (f[0] - f[1]);
-      o[15] = k.mu * (f[2] - f[3]);
-    }
+    // normal force: every edge's (each has unit normal component); tangential forces
+    // from the sliding edges; torsional and rolling moments are not exported
+    const int nr = k.condim == 1 ? 1 : 2 * (k.condim - 1);
+    o[13] = 0.0;
+    for (int e = 0; e < nr; e++) o[13] += f[e];
+    o[14] = k.condim == 1 ? 0.0 : val(k.mu) * (f[0] - f[1]);
+    o[15] = k.condim == 1 ? 0.0 : val(k.mu) * (f[2] - f[3]);
     o[16] = k.pair; o[17] = k.sub; o[18] = k.g1; o[19] = k.g2;
   }
 }

@@ -34,7 +34,8 @@ struct HostModel {
   std::vector<int> eq_body;        // [neq][2]
   std::vector<double> eq_anchor;   // [neq][6]
   std::vector<int> eq_type;        // [neq] 0 connect, 1 weld
-  std::vector<int> pair_condim;    // [npair] 3 friction pyramid, 1 frictionless
+  std::vector<int> pair_condim;    // [npair] 1 frictionless, 3 sliding, 4 + torsion, 6 + rolling
+  std::vector<double> pair_mu_t, pair_mu_r;  // [npair] torsional and rolling coefficients
   std::vector<double> eq_relR;     // [neq][9] weld: body2's reference orientation in body1's frame
   int neqrow = 0;                  // 3 rows per connect, 6 per weld
   double dt = 0, grav[3] = {0, 0, 0}, solref[2] = {0, 0}, solimp[5] = {0, 0, 0, 0, 0};
@@ -102,7 +103,7 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   std::vector<double> bf, jf, gf, pf, af, ef;
   bool ok = rd(bi, 2 * m.nbody) && rd(bf, 19 * (size_t)m.nbody) && rd(ji, 4 * m.njnt) &&
             rd(jf, 11 * (size_t)m.njnt) && rd(gi, 2 * m.ngeom) && rd(gf, 11 * (size_t)m.ngeom) &&
-            rd(pi, 4 * m.npair) && rd(pf, m.npair) && rd(ai, 2 * m.nu) &&
+            rd(pi, 4 * m.npair) && rd(pf, 3 * (size_t)m.npair) && rd(ai, 2 * m.nu) &&
             rd(af, 7 * (size_t)m.nu) && rd(ei, 4 * (size_t)m.neq) && rd(ef, 10 * (size_t)m.neq);
   if (ok && has_hf) {
     int32_t hd[2];
@@ -174,7 +175,9 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   for (int p = 0; p < m.npair; p++) {
     const int g1 = pi[4 * p], g2 = pi[4 * p + 1], condim = pi[4 * p + 2];
     if (g1 < 0 || g1 >= m.ngeom || g2 < 0 || g2 >= m.ngeom) { err = "model blob: bad pair"; return MJH_EMODEL; }
-    if (condim != 1 && condim != 3) { err = "pairs take condim 1 or 3"; return MJH_EUNSUPPORTED; }
+    if (condim != 1 && condim != 3 && condim != 4 && condim != 6) {
+      err = "pairs take condim 1, 3, 4 or 6"; return MJH_EUNSUPPORTED;
+    }
     const int t1 = m.geom_type[g1], t2 = m.geom_type[g2];
     if (t1 > t2) { err = "model blob: pair geoms must be ordered by type"; return MJH_EMODEL; }
     if (t1 == GEOM_PLANE && t2 == GEOM_PLANE) { err = "model blob: plane-plane pair"; return MJH_EMODEL; }
@@ -186,7 +189,9 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
     m.pair_g1.push_back(g1);
     m.pair_g2.push_back(g2);
     m.pair_condim.push_back(condim);
-    m.pair_mu.push_back(pf[p]);
+    m.pair_mu.push_back(pf[3 * p]);
+    m.pair_mu_t.push_back(pf[3 * p + 1]);
+    m.pair_mu_r.push_back(pf[3 * p + 2]);
   }
   for (int a = 0; a < m.nu; a++) {
     const int type = ai[2 * a], jnt = ai[2 * a + 1];
@@ -389,7 +394,13 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   d.nfric = (int)fric_dadr.size();
   d.neq = h.neq;
   d.neqrow = h.neqrow;
-  d.nrowmax = 4 * h.nconmax + d.nlim + d.nfric + d.neqrow;
+  d.conrows = h.npair ? 1 : 4;
+  d.con_rows4 = 1;
+  for (int c : h.pair_condim) {
+    d.conrows = std::max(d.conrows, c == 1 ? 1 : 2 * (c - 1));
+    if (c != 3) d.con_rows4 = 0;
+  }
+  d.nrowmax = d.conrows * h.nconmax + d.nlim + d.nfric + d.neqrow;
   // pairs and candidate slots
   std::vector<int> pair_kind, pair_candadr, cand_pair;
   int ncand = 0;
@@ -440,6 +451,9 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   pk.add(h.geom_body, &d.geom_body);
   pk.add(h.pair_g1, &d.pair_g1);
   pk.add(h.pair_condim, &d.pair_condim);
+  std::vector<float> pmut = fv(h.pair_mu_t), pmur = fv(h.pair_mu_r);
+  pk.add(pmut, &d.pair_mu_t);
+  pk.add(pmur, &d.pair_mu_r);
   pk.add(h.pair_g2, &d.pair_g2);
   pk.add(pair_kind, &d.pair_kind);
   pk.add(pair_candadr, &d.pair_candadr);

@@ -1062,8 +1062,26 @@ DEV void limit_row(const DevModel& m, const float* W, int code, int& dof, float&
 DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
   int* scal = (int*)(W + m.o_scal);
   const int ncon = scal[SC_NCON];
-  const int nv = m.nv, nrc = 4 * ncon;
-  const float* con = W + m.o_con;
+  const int nv = m.nv;
+  float* con = W + m.o_con;
+  // each contact's rows (1 frictionless, else two pyramid edges per friction direction:
+  // 4, 6 or 10) and its first row, by a prefix sum in contact order
+  int nrc = 0;
+  for (int c0 = 0; c0 < ncon; c0 += t.T) {
+    const int c = c0 + t.lane;
+    int nr = 0;
+    if (c < ncon) {
+      const int cd = m.pair_condim[__float_as_int(con[kConRec * c + 16])];
+      nr = cd == 1 ? 1 : 2 * (cd - 1);
+    }
+    const int first = nrc + t.exscan(nr);
+    if (c < ncon) {
+      con[kConRec * c + 18] = __int_as_float(first);
+      con[kConRec * c + 19] = __int_as_float(nr);
+    }
+    nrc += t.isum(nr);
+  }
+  t.sync();
   const float* cdof = W + m.o_cdof;
   float* J = W + m.o_J;
   // violated limits, compacted in joint order
@@ -1091,7 +1109,7 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
     const float* r = con + kConRec * c;
     const int b1 = __float_as_int(r[14]), b2 = __float_as_int(r[15]);
     const unsigned long long bit = 1ull << i;
-    float jd[3] = {0.f, 0.f, 0.f};
+    float jd[3] = {0.f, 0.f, 0.f}, jw[3] = {0.f, 0.f, 0.f};
     const bool in2 = (m.body_dofmask[b2] & bit) != 0;
     const bool in1 = (m.body_dofmask[b1] & bit) != 0;
     if (in1 != in2) {
@@ -1099,14 +1117,37 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
       float wx[3];
       cross3(S, r + 1, wx);
       const float sg = in2 ? 1.f : -1.f;
-      for (int k = 0; k < 3; k++) jd[k] = sg * (S[3 + k] + wx[k]);
+      for (int k = 0; k < 3; k++) {
+        jd[k] = sg * (S[3 + k] + wx[k]);
+        jw[k] = sg * S[k];  // relative angular velocity (torsion and rolling rows)
+      }
     }
-    const float jn = dot3(r + 4, jd), j1 = dot3(r + 7, jd), j2 = dot3(r + 10, jd);
-    const float mu = r[13];
-    J[(4 * c + 0) * nv + i] = jn + mu * j1;
-    J[(4 * c + 1) * nv + i] = jn - mu * j1;
-    J[(4 * c + 2) * nv + i] = jn + mu * j2;
-    J[(4 * c + 3) * nv + i] = jn - mu * j2;
+    const int first = __float_as_int(r[18]), nr = __float_as_int(r[19]);
+    const float jn = dot3(r + 4, jd);
+    float* Jr = J + first * nv + i;
+    if (nr == 1) {  // frictionless
+      Jr[0] = jn;
+    } else {  // edges J_n +- mu J_dir: tangents, then spin (condim 4), then rolling (6)
+      const float j1 = dot3(r + 7, jd), j2 = dot3(r + 10, jd);
+      const float mu = r[13];
+      Jr[0] = jn + mu * j1;
+      Jr[nv] = jn - mu * j1;
+      Jr[2 * nv] = jn + mu * j2;
+      Jr[3 * nv] = jn - mu * j2;
+      if (nr > 4) {
+        const int p = __float_as_int(r[16]);
+        const float mt = m.pair_mu_t[p], js = dot3(r + 4, jw);
+        Jr[4 * nv] = jn + mt * js;
+        Jr[5 * nv] = jn - mt * js;
+        if (nr > 6) {
+          const float mr = m.pair_mu_r[p], jr1 = dot3(r + 7, jw), jr2 = dot3(r + 10, jw);
+          Jr[6 * nv] = jn + mr * jr1;
+          Jr[7 * nv] = jn - mr * jr1;
+          Jr[8 * nv] = jn + mr * jr2;
+          Jr[9 * nv] = jn - mr * jr2;
+        }
+      }
+    }
   }
   for (int idx = t.lane; idx < nl * nv; idx += t.T) {
     const int k = idx / nv, i = idx - k * nv;
@@ -1152,16 +1193,17 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
   for (int row = t.lane; row < nrow; row += t.T) {
     float dist, jv = 0.f, A;
     if (row < nrc) {
-      const float* r = con + kConRec * (row >> 2);
+      int c = row >> 2;  // four rows a contact unless some pair has another condim
+      if (!m.con_rows4) {
+        c = 0;
+        while (c + 1 < ncon && __float_as_int(con[kConRec * (c + 1) + 18]) <= row) c++;
+      }
+      const float* r = con + kConRec * c;
       dist = r[0];
       for (int i = 0; i < nv; i++) jv += J[row * nv + i] * qvel[i];
       const int b1 = __float_as_int(r[14]), b2 = __float_as_int(r[15]);
-      const float mu = r[13];
-      // a frictionless contact's single normal row is four identical rows with four
-      // times its R each: their costs sum to the single row's, so the solution and
-      // the total normal force are the single row's
-      const float cd = m.pair_condim[__float_as_int(r[16])] == 1 ? 4.f : 1.f;
-      A = cd * (1.f + mu * mu) * (m.body_invweight[b1] + m.body_invweight[b2]);
+      const float mu = r[13];  // 0 for a frictionless contact: A = w1 + w2
+      A = (1.f + mu * mu) * (m.body_invweight[b1] + m.body_invweight[b2]);
     } else if (row < nrf) {
       const int code = lim[row - nrc];
       int dof;
@@ -1670,11 +1712,16 @@ DEV void export_contacts(const DevModel& m, float* W, const Team& t, float* out,
   for (int idx = ncon * kConOut + t.lane; idx < m.nconmax * kConOut; idx += t.T) out[idx] = 0.f;
   for (int c = t.lane; c < ncon; c += t.T) {
     const float* r = con + kConRec * c;
-    float f[4];
-    for (int e = 0; e < 4; e++) f[e] = fmaxf(-D[4 * c + e] * er[4 * c + e], 0.f);
+    const int first = __float_as_int(r[18]), nr = __float_as_int(r[19]);
+    float f[4] = {0.f, 0.f, 0.f, 0.f}, fn = 0.f;
+    for (int e = 0; e < nr; e++) {
+      const float fe = fmaxf(-D[first + e] * er[first + e], 0.f);
+      fn += fe;
+      if (e < 4) f[e] = fe;
+    }
     float* o = out + kConOut * c;
     for (int k = 0; k < 13; k++) o[k] = r[k];
-    o[13] = f[0] + f[1] + f[2] + f[3];
+    o[13] = fn;  // the normal force sums every edge; torsion and rolling are not exported
     o[14] = r[13] * (f[0] - f[1]);
     o[15] = r[13] * (f[2] - f[3]);
     o[16] = (float)__float_as_int(r[16]);

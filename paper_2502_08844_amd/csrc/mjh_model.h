@@ -27,7 +27,7 @@ enum PairKind : int {
 };
 
 constexpr int kMaxNv = 64;      // ancestor masks are 64-bit
-constexpr int kConRec = 18;     // on-chip contact record (floats)
+constexpr int kConRec = 20;     // on-chip contact record (floats; [18] first row, [19] rows)
 constexpr int kConOut = 20;     // exported contact record (MJH_CON_SIZE)
 constexpr int kCinert = 10;     // spatial inertia: m, m c (3), I at origin (6)
 
@@ -35,6 +35,8 @@ struct DevModel {
   // ---- sizes
   int nbody, njnt, nq, nv, nu, ngeom, npair, ncand, nconmax, nlim, nfric, neq, nrowmax;
   int neqrow;  // equality rows: 3 per connect, 6 per weld
+  int conrows;   // rows of the widest contact (nrowmax = conrows nconmax + ...)
+  int con_rows4; // 1 when every pair has condim 3 (contact c's rows are 4c .. 4c + 3)
   int iterations, nlevel, nmpair, ntri;
   int implicit;  // 1: joint damping and PD velocity gains integrated implicitly;
                  // 2: also the PD position gains
@@ -99,8 +101,10 @@ struct DevModel {
   const float* geom_pos;      // [ngeom][3]
   const float* geom_rot;      // [ngeom][9]
   const float* pair_mu;
-  const int* pair_condim;     // [npair] 3: friction pyramid; 1: frictionless (four identical
-                              // normal rows, each with four times the single row's R)
+  const int* pair_condim;     // [npair] 1 frictionless (1 row); 3 sliding (4 rows); 4 and
+                              // torsion (6); 6 and rolling (10)
+  const float* pair_mu_t;     // [npair] torsional friction coefficient (condim >= 4)
+  const float* pair_mu_r;     // [npair] rolling friction coefficient (condim 6)
   const float* act_gear;
   const float* act_kp;
   const float* act_kd;

@@ -276,7 +276,8 @@ QUAD_FRICTIONLOSS = 3.0
 
 def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
               limits: bool = False, frictionloss: float = 0.0, tether: bool = False,
-              implicit: int = 0, weld_base: bool = False, condim: int = 3) -> Model:
+              implicit: int = 0, weld_base: bool = False, condim: int = 3,
+              mu_torsion: float = 0.0, mu_rolling: float = 0.0) -> Model:
     """Free torso (box 0.3x0.1x0.05 m, 5 kg) + 4 legs x 3 hinges (capsules r 0.02,
     length 0.2, 0.5 kg) with massless sphere feet (r 0.025).  nq 19, nv 18, nu 12.
 
@@ -286,7 +287,8 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     the 12 are active on average, up to 7).  With ``frictionloss`` every hinge carries
     that dry friction (one friction-loss row each).  With ``tether`` the torso's centre
     is held by a connect equality on its standing position (a gantry tether: three
-    two-sided rows).  With ``condim`` = 1 the feet's contacts are frictionless.  With
+    two-sided rows).  With ``condim`` = 1 the feet's contacts are frictionless; 4 adds
+    torsional friction ``mu_torsion`` and 6 also rolling friction ``mu_rolling``.  With
     ``weld_base`` the torso is welded to the world at its standing
     pose (a fixed-base robot: six two-sided rows).  With ``implicit`` = 1 the PD velocity gains are integrated
     implicitly (integrator 1); with 2 the PD position gains as well (integrator 2).
@@ -300,7 +302,8 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
                    ("_friction" if frictionloss > 0 else "") + ("_tethered" if tether else "") +
                    ("_implicit" if implicit == 1 else "") +
                    ("_implicit_pd" if implicit == 2 else "") + ("_welded" if weld_base else "") +
-                   ("_frictionless" if condim == 1 else ""))
+                   ("_frictionless" if condim == 1 else "") +
+                   (f"_condim{condim}" if condim in (4, 6) else ""))
 
     def rng(k):
         if not limits:
@@ -332,7 +335,7 @@ def quadruped(mu: float = 1.0, timestep: float = 0.004, iterations: int = 4,
     for k, j in enumerate(hinge_ids):
         m.actuators.append(Actuator(type=ACT_PD, joint=j, gear=1.0, kp=35.0, kd=0.5,
                                     ctrlrange=(-1.0, 1.0), qdefault=QUAD_Q_DEFAULT[k % 3]))
-    m.pairs = [(plane, f, mu, condim) for f in feet]
+    m.pairs = [(plane, f, mu, condim, mu_torsion, mu_rolling) for f in feet]
     if tether:
         bld.connect(torso, 0, (0, 0, 0), (0, 0, QUAD_STAND_Z))
     if weld_base:
@@ -610,6 +613,16 @@ def quadruped_frictionless() -> Model:
     return quadruped(condim=1)
 
 
+def quadruped_torsion() -> Model:
+    """The quadruped with torsional friction at the feet (condim 4, mu_t 0.02 m)."""
+    return quadruped(condim=4, mu_torsion=0.02)
+
+
+def quadruped_rolling() -> Model:
+    """The quadruped with torsional and rolling friction at the feet (condim 6)."""
+    return quadruped(condim=6, mu_torsion=0.02, mu_rolling=0.001)
+
+
 def quadruped_rk4() -> Model:
     """The quadruped integrated by fourth-order Runge-Kutta (integrator 3)."""
     m = quadruped()
@@ -843,6 +856,8 @@ WORKLOADS = {
     "quadruped_rk4": quadruped_rk4,
     "quadruped_welded": quadruped_welded,
     "quadruped_frictionless": quadruped_frictionless,
+    "quadruped_torsion": quadruped_torsion,
+    "quadruped_rolling": quadruped_rolling,
     "quadruped_rough": quadruped_rough,
     "humanoid": humanoid,
     "hand": hand,
