@@ -1065,23 +1065,28 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
   const int nv = m.nv;
   float* con = W + m.o_con;
   // each contact's rows (1 frictionless, else two pyramid edges per friction direction:
-  // 4, 6 or 10) and its first row, by a prefix sum in contact order
-  int nrc = 0;
-  for (int c0 = 0; c0 < ncon; c0 += t.T) {
-    const int c = c0 + t.lane;
-    int nr = 0;
-    if (c < ncon) {
-      const int cd = m.pair_condim[__float_as_int(con[kConRec * c + 16])];
-      nr = cd == 1 ? 1 : 2 * (cd - 1);
+  // 4, 6 or 10) and its first row.  With every pair at condim 3 they are 4 and 4c;
+  // otherwise a prefix sum in contact order packs them into the record's slot word
+  // (candidate slot | rows << 4 | first row << 8).
+  int nrc = 4 * ncon;
+  if (!m.con_rows4) {
+    nrc = 0;
+    for (int c0 = 0; c0 < ncon; c0 += t.T) {
+      const int c = c0 + t.lane;
+      int nr = 0;
+      if (c < ncon) {
+        const int cd = m.pair_condim[__float_as_int(con[kConRec * c + 16])];
+        nr = cd == 1 ? 1 : 2 * (cd - 1);
+      }
+      const int first = nrc + t.exscan(nr);
+      if (c < ncon) {
+        const int sub = __float_as_int(con[kConRec * c + 17]) & 15;
+        con[kConRec * c + 17] = __int_as_float(sub | (nr << 4) | (first << 8));
+      }
+      nrc += t.isum(nr);
     }
-    const int first = nrc + t.exscan(nr);
-    if (c < ncon) {
-      con[kConRec * c + 18] = __int_as_float(first);
-      con[kConRec * c + 19] = __int_as_float(nr);
-    }
-    nrc += t.isum(nr);
+    t.sync();
   }
-  t.sync();
   const float* cdof = W + m.o_cdof;
   float* J = W + m.o_J;
   // violated limits, compacted in joint order
@@ -1122,7 +1127,8 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
         jw[k] = sg * S[k];  // relative angular velocity (torsion and rolling rows)
       }
     }
-    const int first = __float_as_int(r[18]), nr = __float_as_int(r[19]);
+    const int slot = __float_as_int(r[17]);
+    const int first = m.con_rows4 ? 4 * c : slot >> 8, nr = m.con_rows4 ? 4 : (slot >> 4) & 15;
     const float jn = dot3(r + 4, jd);
     float* Jr = J + first * nv + i;
     if (nr == 1) {  // frictionless
@@ -1196,7 +1202,7 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
       int c = row >> 2;  // four rows a contact unless some pair has another condim
       if (!m.con_rows4) {
         c = 0;
-        while (c + 1 < ncon && __float_as_int(con[kConRec * (c + 1) + 18]) <= row) c++;
+        while (c + 1 < ncon && (__float_as_int(con[kConRec * (c + 1) + 17]) >> 8) <= row) c++;
       }
       const float* r = con + kConRec * c;
       dist = r[0];
@@ -1712,7 +1718,8 @@ DEV void export_contacts(const DevModel& m, float* W, const Team& t, float* out,
   for (int idx = ncon * kConOut + t.lane; idx < m.nconmax * kConOut; idx += t.T) out[idx] = 0.f;
   for (int c = t.lane; c < ncon; c += t.T) {
     const float* r = con + kConRec * c;
-    const int first = __float_as_int(r[18]), nr = __float_as_int(r[19]);
+    const int slot = __float_as_int(r[17]);
+    const int first = m.con_rows4 ? 4 * c : slot >> 8, nr = m.con_rows4 ? 4 : (slot >> 4) & 15;
     float f[4] = {0.f, 0.f, 0.f, 0.f}, fn = 0.f;
     for (int e = 0; e < nr; e++) {
       const float fe = fmaxf(-D[first + e] * er[first + e], 0.f);
@@ -1725,7 +1732,7 @@ DEV void export_contacts(const DevModel& m, float* W, const Team& t, float* out,
     o[14] = r[13] * (f[0] - f[1]);
     o[15] = r[13] * (f[2] - f[3]);
     o[16] = (float)__float_as_int(r[16]);
-    o[17] = (float)__float_as_int(r[17]);
+    o[17] = (float)(__float_as_int(r[17]) & 15);
   }
   if (t.lane == 0 && nout) *nout = ncon;
 }

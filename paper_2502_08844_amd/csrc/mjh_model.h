@@ -27,7 +27,7 @@ enum PairKind : int {
 };
 
 constexpr int kMaxNv = 64;      // ancestor masks are 64-bit
-constexpr int kConRec = 20;     // on-chip contact record (floats; [18] first row, [19] rows)
+constexpr int kConRec = 18;     // on-chip contact record (floats)
 constexpr int kConOut = 20;     // exported contact record (MJH_CON_SIZE)
 constexpr int kCinert = 10;     // spatial inertia: m, m c (3), I at origin (6)
 
