@@ -21,7 +21,8 @@ the robot inverts):
   joint position           -0.1 * |q - q_default|^2
   action rate              -0.01 * |a_t - a_{t-1}|^2
   termination              -1.0 * done
-* termination: the root body's z axis points downwards (the robot has inverted);
+* termination: the root body's z axis points downwards (the robot has inverted), or
+  the state is no longer finite (then the reward is 0);
 * reset: a terminated world restarts from its reset state (given by the caller) with a
   zero warm start and a zero previous action; the outputs of that env step are those
   of the state it terminated in.
@@ -83,6 +84,8 @@ def observe(m, qpos, qvel, prev_action, cmd, noise=None):
 
 
 def reward_done(m, qpos, qvel, action, prev_action, cmd):
+    if not (np.all(np.isfinite(qpos)) and np.all(np.isfinite(qvel))):
+        return 0.0, True
     R = quat_mat(qpos[3:7])
     done = R[2, 2] < 0.0
     g = R.T @ np.array([0.0, 0.0, -1.0])

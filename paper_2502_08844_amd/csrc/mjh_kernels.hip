@@ -103,7 +103,8 @@ mjh_step_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__
 //   reward = max(0, 1.0 exp(-|cmd_xy - v_xy|^2/0.25) + 0.5 exp(-(cmd_wz - w_z)^2/0.25)
 //            - 2 v_z^2 - 0.05 |w_xy|^2 - 5 |g_xy|^2 - 2e-4 |tau|^2 - 0.1 |q - q_default|^2
 //            - 0.01 |a_t - a_{t-1}|^2 - done)          (tau: PD torques at the new state)
-//   done   = the root's z axis points downwards (inverted).
+//   done   = the root's z axis points downwards (inverted), or the state is no longer
+//            finite (then the reward is 0).
 // A terminated world restarts from its reset state with a zero warm start and a zero
 // previous action.  The root is a free joint; actuator k drives dof 6 + k.
 // Domain randomisation (optional): each world's parameter record (layout at kDrFric)
@@ -164,7 +165,12 @@ __device__ __forceinline__ void env_worlds(const DevGroup& G, const EnvArgs& E, 
       gb[k] = -R[6 + k];
       vb[k] = R[k] * qvel[0] + R[3 + k] * qvel[1] + R[6 + k] * qvel[2];
     }
-    const bool done = R[8] < 0.f;
+    // a state that is no longer finite also terminates the world (reward 0)
+    int bad = 0;
+    for (int i = lane; i < nq; i += T) bad |= !isfinite(qpos[i]);
+    for (int i = lane; i < nv; i += T) bad |= !isfinite(qvel[i]);
+    bad = t.ior(bad);
+    const bool done = bad || R[8] < 0.f;
     // per-actuator terms, one lane each
     float jt = 0.f;
     for (int k = lane; k < nu; k += T) {
@@ -196,7 +202,7 @@ __device__ __forceinline__ void env_worlds(const DevGroup& G, const EnvArgs& E, 
       float r = kEnvKv * expf(-(ex * ex + ey * ey) / kEnvSv) + kEnvKw * expf(-ez * ez / kEnvSw) +
                 kEnvLinZ * vb[2] * vb[2] + kEnvAngXY * (qvel[3] * qvel[3] + qvel[4] * qvel[4]) +
                 kEnvOri * (gb[0] * gb[0] + gb[1] * gb[1]) + jt + (done ? kEnvTerm : 0.f);
-      E.reward[(size_t)e * G.nworld + w] = fmaxf(r, 0.f);
+      E.reward[(size_t)e * G.nworld + w] = bad ? 0.f : fmaxf(r, 0.f);
       E.done[(size_t)e * G.nworld + w] = done ? 1 : 0;
     }
     t.sync();  // every lane has read aprev and the state

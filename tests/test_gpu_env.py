@@ -244,3 +244,26 @@ def test_randomised_env_step_against_reference_env(lib):
           f"max {err.max():.1e}", flush=True)
     assert np.median(err) <= 1e-3
     np.testing.assert_array_equal(g["last_action"], pa.astype(np.float32))
+
+
+def test_nonfinite_worlds_terminate_and_reset(lib):
+    """Worlds whose state is no longer finite end (done, reward 0) and restart from
+    their reset state; the other worlds' outputs are those of a run without them."""
+    mjh, ctx = lib
+    nw = 64
+    print(f"[gpu] env step non-finite worlds nw={nw}", flush=True)
+    m, qp, qv, ws, cmd, rq, rv, prev, inv = _scene(ctx, mjh, nw, seed=31, invert=False)
+    act = inputs.f32(np.random.default_rng(4).uniform(-0.6, 0.6, size=(1, nw, m.nu)))
+    ref = _env_gpu(ctx, mjh, m, qp, qv, ws, act, cmd, rq, rv, prev)
+    bad = np.arange(nw) % 7 == 2
+    qv_bad = qv.copy()
+    qv_bad[bad, 7] = np.nan
+    g = _env_gpu(ctx, mjh, m, qp, qv_bad, ws, act, cmd, rq, rv, prev)
+    assert np.all(g["done"][0][bad]) and np.all(g["reward"][0][bad] == 0)
+    np.testing.assert_array_equal(g["qpos"][bad], rq[bad].astype(np.float32))
+    np.testing.assert_array_equal(g["qvel"][bad], rv[bad].astype(np.float32))
+    assert np.all(g["last_action"][bad] == 0) and np.all(np.isfinite(g["qpos"]))
+    ok = ~bad
+    for k in ("obs", "reward", "done"):
+        np.testing.assert_array_equal(g[k][0][ok], ref[k][0][ok])
+    np.testing.assert_array_equal(g["qpos"][ok], ref["qpos"][ok])

@@ -201,3 +201,12 @@ def test_friction_scale_on_an_incline():
         else:
             mu_eff = (9.81 * np.sin(th) - acc) / (9.81 * np.cos(th))
             assert mu_eff == pytest.approx(f, rel=2e-2)
+
+
+def test_nonfinite_state_terminates_with_zero_reward():
+    m = robots.quadruped()
+    q, v = _standing(m)
+    v = v.copy()
+    v[7] = np.nan
+    r, done = env.reward_done(m, q, v, np.zeros(m.nu), np.zeros(m.nu), np.zeros(3))
+    assert done and r == 0.0
