@@ -75,10 +75,11 @@ typedef struct mjh_dims {
   int32_t lds_bytes;  /* on-chip working set of one world                        */
   float timestep;
   int32_t nlimit;     /* limited hinge/slide joints (at most one row each)        */
-  int32_t nrowmax;    /* constraint rows per world: 4 nconmax + nlimit + nfric    */
-                      /*   + 3 neq                                                 */
+  int32_t nrowmax;    /* constraint rows per world: c nconmax + nlimit + nfric    */
+                      /*   + (3 per connect, 6 per weld), c the widest contact's  */
+                      /*   rows (1 frictionless, 4 / 6 / 10 for condim 3 / 4 / 6) */
   int32_t nfric;      /* dofs with friction loss (one row each, always present)   */
-  int32_t neq;        /* connect equalities (three rows each, always present)     */
+  int32_t neq;        /* equalities (connect or weld; rows always present)        */
 } mjh_dims;
 
 /* One context per device.  device: HIP device ordinal.  *out receives the handle. */
@@ -102,8 +103,17 @@ const char* mjh_last_error(const mjh_ctx* ctx);
  * A, and a force confined to [-F, F] (a Huber term in the solver's cost).  A connect
  * equality (a point fixed in body1 held on a point fixed in body2, or in the world)
  * adds three two-sided rows last, one per world axis: J = J_p(b1, p1) - J_p(b2, p2),
- * r = p1 - p2, A = w(b1) + w(b2).  mjh_rollout_fwd rejects models with equalities
- * (MJH_EUNSUPPORTED).
+ * r = p1 - p2, A = w(b1) + w(b2).  A weld equality also holds body1's orientation
+ * relative to body2 at a stored reference Q: three more rows J = J_w(b1) - J_w(b2),
+ * r = vee(E - E^T) / 2 with E = R1 Q R2^T, the same A.
+ * A pair's contact dimension sets its rows per contact: condim 1 one normal row
+ * (frictionless); 3 the sliding pyramid's four edges J_n +- mu J_t1, J_n +- mu J_t2;
+ * 4 also J_n +- mu_t J_spin (torsion about the normal); 6 also J_n +- mu_r J_roll for
+ * both tangents (rolling), all with R = (1-d)/d (1 + mu^2)(w1 + w2).
+ * Integrator 1 takes joint damping and PD velocity gains implicitly, 2 also the PD
+ * position gains, 3 is fourth-order Runge-Kutta (four forward passes a step).
+ * mjh_rollout_fwd rejects models with equalities, integrators other than 0, contact
+ * dimensions other than 3 or heightfield pairs (MJH_EUNSUPPORTED).
  * MJH_EMODEL for a malformed blob, MJH_EUNSUPPORTED for nv > 64, box-box pairs,
  * a free joint below the root or two actuators on one dof. */
 mjh_status mjh_model_upload(mjh_ctx* ctx, const void* blob, size_t nbytes,

@@ -1915,7 +1915,6 @@ DEV void world_step(const DevModel& m, float* W0, const Team& t0, const float* c
 // started from a_{k-1}; afterwards q <- q0 (+) h/6 (v1 + 2 v2 + 2 v3 + v4) and
 // qdot <- v0 + h/6 (a1 + 2 a2 + 2 a3 + a4), and qacc (reported, and the next warm
 // start) is a1.  The block at o_rk holds q0, v0, a1 and the two weighted sums.
-DEV int rk4_stages(const DevModel& m) { return m.rk4 ? 4 : 1; }
 
 // set the state of stage k >= 1 from the previous stage's velocity and acceleration
 DEV void rk4_begin(const DevModel& m, float* W, const Team& t, int k) {
