@@ -159,7 +159,8 @@ mjh_status mjh_step(mjh_batch* b, int32_t nstep, void* stream);
  * joint readings minus their defaults, joint velocities, previous action, command[w]
  * ([nworld][3]: vx, vy, yaw rate)), reward[e] ([nenv][nworld]: max(0, 1.0 exp(-|cmd_xy -
  * v_xy|^2/0.25) + 0.5 exp(-(cmd_wz - w_z)^2/0.25) - 2 v_z^2 - 0.05 |w_xy|^2 - 5 |g_xy|^2
- * - 2e-4 |tau|^2 - 0.1 |q - q_default|^2 - 0.01 |a_t - a_{t-1}|^2 - done)) and done[e]
+ * - 2e-4 |tau|^2 - 0.1 |q - q_default|^2 - 0.01 |a_t - a_{t-1}|^2 - 1e-3 sum |qdot tau|
+ * + 0.5 exp(-|q - q_default|^2) - done)) and done[e]
  * ([nenv][nworld], 1 when the root's z axis points downwards or the state is no longer
  * finite, with reward 0 then).  A world that is done
  * restarts from reset_qpos / reset_qvel ([nworld][nq] / [nworld][nv]) with a zero warm

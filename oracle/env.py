@@ -20,6 +20,8 @@ the robot inverts):
   joint torque             -2e-4 * |tau|^2          (PD torques at the new state)
   joint position           -0.1 * |q - q_default|^2
   action rate              -0.01 * |a_t - a_{t-1}|^2
+  energy                   -1e-3 * sum_k |qdot_k tau_k|
+  pose                      0.5 * exp(-|q - q_default|^2)
   termination              -1.0 * done
 * termination: the root body's z axis points downwards (the robot has inverted), or
   the state is no longer finite (then the reward is 0);
@@ -52,6 +54,7 @@ import numpy as np
 K_V, SIG_V = 1.0, 0.25
 K_W, SIG_W = 0.5, 0.25
 K_LINZ, K_ANGXY, K_ORI, K_TAU, K_Q, K_RATE, K_TERM = -2.0, -0.05, -5.0, -2e-4, -0.1, -0.01, -1.0
+K_ENERGY, K_POSE = -1e-3, 0.5
 
 
 def quat_mat(q):
@@ -97,7 +100,9 @@ def reward_done(m, qpos, qvel, action, prev_action, cmd):
          + K_W * np.exp(-(cmd[2] - w[2]) ** 2 / SIG_W)
          + K_LINZ * v[2] ** 2 + K_ANGXY * np.sum(w[:2] ** 2) + K_ORI * np.sum(g[:2] ** 2)
          + K_TAU * np.sum(tau ** 2) + K_Q * np.sum((qpos[7:] - qdef) ** 2)
-         + K_RATE * np.sum((action - prev_action) ** 2) + K_TERM * float(done))
+         + K_RATE * np.sum((action - prev_action) ** 2)
+         + K_ENERGY * np.sum(np.abs(qvel[6:] * tau))
+         + K_POSE * np.exp(-np.sum((qpos[7:] - qdef) ** 2)) + K_TERM * float(done))
     return max(r, 0.0), bool(done)
 
 

@@ -102,7 +102,8 @@ mjh_step_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__
 //            g the gravity direction, v the root's world linear velocity rotated in)
 //   reward = max(0, 1.0 exp(-|cmd_xy - v_xy|^2/0.25) + 0.5 exp(-(cmd_wz - w_z)^2/0.25)
 //            - 2 v_z^2 - 0.05 |w_xy|^2 - 5 |g_xy|^2 - 2e-4 |tau|^2 - 0.1 |q - q_default|^2
-//            - 0.01 |a_t - a_{t-1}|^2 - done)          (tau: PD torques at the new state)
+//            - 0.01 |a_t - a_{t-1}|^2 - 1e-3 sum |qdot tau| + 0.5 exp(-|q - q_default|^2)
+//            - done)                                  (tau: PD torques at the new state)
 //   done   = the root's z axis points downwards (inverted), or the state is no longer
 //            finite (then the reward is 0).
 // A terminated world restarts from its reset state with a zero warm start and a zero
@@ -114,6 +115,7 @@ mjh_step_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__
 constexpr float kEnvKv = 1.f, kEnvSv = 0.25f, kEnvKw = 0.5f, kEnvSw = 0.25f;
 constexpr float kEnvLinZ = -2.f, kEnvAngXY = -0.05f, kEnvOri = -5.f, kEnvTau = -2e-4f;
 constexpr float kEnvQ = -0.1f, kEnvRate = -0.01f, kEnvTerm = -1.f;
+constexpr float kEnvEnergy = -1e-3f, kEnvPose = 0.5f;
 
 template <bool RK>
 __device__ __forceinline__ void env_worlds(const DevGroup& G, const EnvArgs& E, float* W, float* aprev, float* dr,
@@ -172,7 +174,7 @@ __device__ __forceinline__ void env_worlds(const DevGroup& G, const EnvArgs& E, 
     bad = t.ior(bad);
     const bool done = bad || R[8] < 0.f;
     // per-actuator terms, one lane each
-    float jt = 0.f;
+    float jt = 0.f, pose = 0.f;
     for (int k = lane; k < nu; k += T) {
       const float lo = m.act_lo[k], hi = m.act_hi[k];
       const float uk = fminf(fmaxf(u[k], lo), hi);
@@ -180,9 +182,12 @@ __device__ __forceinline__ void env_worlds(const DevGroup& G, const EnvArgs& E, 
       const float q0 = dr ? m.act_qdef[k] - dr[kDrHead + k] : m.act_qdef[k];
       const float tau = skp * m.act_kp[k] * (q0 + m.act_gear[k] * uk - q) - skd * m.act_kd[k] * qd;
       const float dq = q - q0, da = u[k] - aprev[k];
-      jt += kEnvTau * tau * tau + kEnvQ * dq * dq + kEnvRate * da * da;
+      jt += kEnvTau * tau * tau + kEnvQ * dq * dq + kEnvRate * da * da +
+            kEnvEnergy * fabsf(qd * tau);
+      pose += dq * dq;
     }
     jt = t.sum(jt);
+    pose = t.sum(pose);
     float* ob = E.obs + ((size_t)e * G.nworld + w) * E.nobs;
     for (int i = lane; i < E.nobs; i += T) {
       float v;
@@ -201,7 +206,8 @@ __device__ __forceinline__ void env_worlds(const DevGroup& G, const EnvArgs& E, 
       const float ex = cmd[0] - vb[0], ey = cmd[1] - vb[1], ez = cmd[2] - qvel[5];
       float r = kEnvKv * expf(-(ex * ex + ey * ey) / kEnvSv) + kEnvKw * expf(-ez * ez / kEnvSw) +
                 kEnvLinZ * vb[2] * vb[2] + kEnvAngXY * (qvel[3] * qvel[3] + qvel[4] * qvel[4]) +
-                kEnvOri * (gb[0] * gb[0] + gb[1] * gb[1]) + jt + (done ? kEnvTerm : 0.f);
+                kEnvOri * (gb[0] * gb[0] + gb[1] * gb[1]) + jt + kEnvPose * expf(-pose) +
+                (done ? kEnvTerm : 0.f);
       E.reward[(size_t)e * G.nworld + w] = bad ? 0.f : fmaxf(r, 0.f);
       E.done[(size_t)e * G.nworld + w] = done ? 1 : 0;
     }

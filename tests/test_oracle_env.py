@@ -22,7 +22,7 @@ def test_standing_still_earns_the_tracking_maximum():
     np.testing.assert_allclose(obs[:3], [0, 0, -1], atol=1e-15)
     assert np.abs(obs[3:]).max() == 0.0
     r, done = env.reward_done(m, q, v, a, a, np.zeros(3))
-    assert r == pytest.approx(env.K_V + env.K_W, abs=1e-15) and not done
+    assert r == pytest.approx(env.K_V + env.K_W + env.K_POSE, abs=1e-15) and not done
 
 
 def test_tracking_terms_and_body_frame_velocity():
@@ -37,9 +37,12 @@ def test_tracking_terms_and_body_frame_velocity():
     np.testing.assert_allclose(obs[3:6], [0, -1, 0], atol=1e-15)
     np.testing.assert_allclose(obs[6:9], [0, 0, 0.3], atol=1e-15)
     r, _ = env.reward_done(m, q, v, a, a, np.array([0.0, -1.0, 0.3]))
-    assert r == pytest.approx(1.5, abs=1e-12)  # both commands tracked exactly
+    # both commands tracked exactly, in the default pose; the yaw rate is a body-frame
+    # angular velocity about z, which none of the penalties counts
+    assert r == pytest.approx(1.5 + env.K_POSE, abs=1e-12)
     r2, _ = env.reward_done(m, q, v, a, a, np.array([0.5, -1.0, -0.2]))
-    assert r2 == pytest.approx(np.exp(-0.25 / 0.25) + 0.5 * np.exp(-0.25 / 0.25), abs=1e-12)
+    assert r2 == pytest.approx(np.exp(-0.25 / 0.25) + 0.5 * np.exp(-0.25 / 0.25) + env.K_POSE,
+                               abs=1e-12)
 
 
 def test_orientation_termination_and_clipping():
@@ -50,7 +53,7 @@ def test_orientation_termination_and_clipping():
     obs = env.observe(m, q, v, a, np.zeros(3))
     np.testing.assert_allclose(obs[:3], [0, -1, 0], atol=1e-15)
     r, done = env.reward_done(m, q, v, a, a, np.zeros(3))
-    assert r == 0.0 and not done  # 1.5 - 5 |g_xy|^2 clipped at zero
+    assert r == 0.0 and not done  # 1.5 + 0.5 - 5 |g_xy|^2 clipped at zero
     q[3:7] = robots.axis_angle_quat((1, 0, 0), 0.55 * np.pi)  # past the side: inverted
     assert env.reward_done(m, q, v, a, a, np.zeros(3))[1]
 
@@ -59,7 +62,7 @@ def test_penalty_terms_one_at_a_time():
     m = robots.quadruped()
     q, v = _standing(m)
     a0 = np.zeros(m.nu)
-    base = env.K_V + env.K_W
+    base = env.K_V + env.K_W + env.K_POSE
     v2 = v.copy(); v2[2] = 0.2  # vertical velocity (world z = body z here)
     assert env.reward_done(m, q, v2, a0, a0, np.zeros(3))[0] == pytest.approx(
         base + env.K_LINZ * 0.04, abs=1e-12)
@@ -73,7 +76,12 @@ def test_penalty_terms_one_at_a_time():
     q4 = q.copy(); q4[7] += 0.2  # joint offset with the matching action: no torque
     a4 = np.zeros(m.nu); a4[0] = 0.2
     assert env.reward_done(m, q4, v, a4, a4, np.zeros(3))[0] == pytest.approx(
-        base + env.K_Q * 0.04, abs=1e-12)
+        base + env.K_Q * 0.04 + env.K_POSE * (np.exp(-0.04) - 1), abs=1e-12)
+    # a joint velocity: PD damping torque -kd qdot, its square and the power |qdot tau|
+    v5 = v.copy(); v5[6] = 0.5
+    kd = m.actuators[0].kd
+    assert env.reward_done(m, q, v5, a0, a0, np.zeros(3))[0] == pytest.approx(
+        base + env.K_TAU * (kd * 0.5) ** 2 + env.K_ENERGY * (kd * 0.25), abs=1e-12)
 
 
 def test_env_step_resets_inverted_worlds():
