@@ -86,8 +86,8 @@ def parse():
     ap.add_argument("--no-hetero", action="store_true",
                     help="skip the heterogeneous-batch comparison")
     ap.add_argument("--no-limits", action="store_true",
-                    help="skip the joint-limit, friction-loss, equality, implicit-damping and "
-                         "rough-terrain workloads (quadruped variants)")
+                    help="skip the quadruped variants (limits, friction loss, equalities, "
+                         "contact dimensions, integrators, rough terrain)")
     ap.add_argument("--no-env", action="store_true",
                     help="skip the fused joystick env step measurement")
     ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph")
@@ -462,6 +462,15 @@ def main():
         out["weld"] = constraint_compare(
             ctx, args.seed, "quadruped_welded",
             "its torso welded to the world at its standing pose (a fixed base)")
+        out["frictionless"] = constraint_compare(
+            ctx, args.seed, "quadruped_frictionless",
+            "frictionless feet (condim 1: one row a contact)")
+        out["torsion"] = constraint_compare(
+            ctx, args.seed, "quadruped_torsion",
+            "torsional friction at the feet (condim 4: six pyramid edges a contact)")
+        out["rolling"] = constraint_compare(
+            ctx, args.seed, "quadruped_rolling",
+            "torsional and rolling friction at the feet (condim 6: ten edges a contact)")
         out["implicit_damping"] = constraint_compare(
             ctx, args.seed, "quadruped_implicit",
             "its PD velocity gains integrated implicitly")
