@@ -9,7 +9,9 @@ forward pass at four stages) against the FP64 reference.
   world with a median below 1e-5 (as for the implicit integrators: the later stages
   carry the solve's FP32 differences through the stage states).  The first stage
   against the reference is printed; its gate is that of the Euler parity tests;
-* rollouts reject the integrator.
+* rollouts reject the integrator;
+* the Runge-Kutta instantiations of the env kernel and of a batch mixing Euler and
+  Runge-Kutta groups reproduce the separate launches.
 """
 import numpy as np
 import pytest
@@ -81,3 +83,63 @@ def test_rollout_rejects_rk4(lib):
     loss = torch.zeros(2, device="cuda")
     with pytest.raises(mjh.MjhError):
         w.batch.rollout_fwd(4, 2, u, 2, 0.3, 1e-3, loss)
+
+
+def test_env_step_with_rk4_physics(lib):
+    """The env kernel's Runge-Kutta instantiation: its physics equals the plain RK4
+    step's with the action held for the substeps."""
+    mjh, ctx = lib
+    m, qp, qv, u = workload("quadruped_rk4", 64, 21, seed=3)
+    r = run_gpu(ctx, mjh, m, qp, qv, None, u[:20], 20, contacts=False)
+    qp, qv, ws = r["qpos"], r["qvel"], r["qacc"]
+    nw, nsub = 64, 3
+    act = u[20:21]
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32,
+                                    device="cuda").contiguous()
+    w = mjh.World(ctx, m, nw, qpos=qp, qvel=qv)
+    w.qacc_ws.copy_(dev(ws))
+    obs = torch.zeros(1, nw, 12 + 3 * m.nu, device="cuda")
+    rew = torch.zeros(1, nw, device="cuda")
+    done = torch.zeros(1, nw, dtype=torch.int32, device="cuda")
+    w.batch.env_step(nsub, dev(act), torch.zeros(nw, 3, device="cuda"), dev(qp), dev(qv),
+                     torch.zeros(nw, m.nu, device="cuda"), obs, rew, done)
+    torch.cuda.synchronize()
+    p = run_gpu(ctx, mjh, m, qp, qv, ws, np.repeat(act, nsub, 0), nsub, contacts=False)
+    keep = done.cpu().numpy()[0] == 0
+    assert keep.all()
+    np.testing.assert_allclose(w.qpos.cpu().double().numpy()[keep], p["qpos"][keep],
+                               rtol=0, atol=1e-6)
+    np.testing.assert_allclose(w.qvel.cpu().double().numpy()[keep], p["qvel"][keep],
+                               rtol=1e-5, atol=1e-5)
+
+
+def test_mixed_batch_euler_and_rk4(lib):
+    """One launch over an Euler group and a Runge-Kutta group (the RK instantiation
+    serves both) equals the two groups' own launches."""
+    mjh, ctx = lib
+    kinds = ("quadruped", "quadruped_rk4")
+    ms, states, ctrls = [], [], []
+    for k, kind in enumerate(kinds):
+        m, qp, qv, u = workload(kind, 40, 10, seed=5 + k)
+        ms.append(m); states.append((qp, qv)); ctrls.append(u)
+    sep = [run_gpu(ctx, mjh, m, qp, qv, None, u, 10, contacts=False)
+           for m, (qp, qv), u in zip(ms, states, ctrls)]
+    gms = [ctx.model_upload(m) for m in ms]
+    b = ctx.world_alloc(gms, [40, 40])
+    held = []
+    for g, (m, (qp, qv), u) in enumerate(zip(ms, states, ctrls)):
+        q = torch.as_tensor(qp, dtype=torch.float32, device="cuda").contiguous()
+        v = torch.as_tensor(qv, dtype=torch.float32, device="cuda").contiguous()
+        a = torch.zeros(40, m.nv, device="cuda")
+        st = torch.zeros(40, dtype=torch.int32, device="cuda")
+        c = torch.as_tensor(u, dtype=torch.float32, device="cuda").contiguous()
+        b.bind_state(g, q, v, a, st)
+        b.bind_io(g, c)
+        held.append((q, v, a, st, c))
+    b.step(10)
+    torch.cuda.synchronize()
+    for g in range(2):
+        np.testing.assert_allclose(held[g][0].cpu().double().numpy(), sep[g]["qpos"],
+                                   rtol=0, atol=1e-6)
+        np.testing.assert_allclose(held[g][1].cpu().double().numpy(), sep[g]["qvel"],
+                                   rtol=1e-5, atol=1e-5)
