@@ -139,3 +139,13 @@ def test_rolling_friction_opposes_rolling_within_its_bound(condim, mu_r):
     tau = np.array([-(I / r + mass * r) * x[2][0] for x in tr])[5:]
     bound = np.array([mu_r * x[3] for x in tr])[5:]
     assert np.all(tau > 0) and np.all(tau <= bound * (1 + 1e-6))
+
+
+@pytest.mark.parametrize("condim", [4, 6])
+def test_resting_ball_normal_force_sums_every_edge(condim):
+    """At rest the torsional and rolling edges carry part of the load like the sliding
+    ones (every edge has unit normal component): the exported normal force, the sum
+    over all edges, is m g."""
+    mass = 3.0
+    m, o, res = _settled_sphere(condim, 0.02, 0.002, mass=mass)
+    assert res["contacts"][0, 0, 13] == pytest.approx(mass * G, rel=1e-9)

@@ -90,6 +90,7 @@ def test_first_stage_is_the_euler_forward_pass():
     r3 = Oracle(m3).step(qp.copy(), qv.copy(), None, u, nstep=1)
     r0 = Oracle(m0).step(qp.copy(), qv.copy(), None, u, nstep=1)
     np.testing.assert_array_equal(r3["qacc"], r0["qacc"])
+    np.testing.assert_array_equal(r3["qacc_ws"], r0["qacc"])  # the next warm start: a1
     np.testing.assert_array_equal(r3["ncon"], r0["ncon"])
     np.testing.assert_array_equal(r3["contacts"], r0["contacts"])
     assert not np.allclose(r3["qvel"], r0["qvel"], rtol=1e-6)
