@@ -1298,7 +1298,8 @@ DEV int pad_rows(const DevModel& m, float* W, const Team& t, int nrow) {
 // forward solve L y = b (b overwritten) rides along.  Returns false for a non-positive
 // pivot.  `w` (nrow words) receives the rows' curvatures: D on the quadratic piece, else 0.
 DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
-                          float* b = nullptr, float* y = nullptr, bool rev = false) {
+                          float* b = nullptr, float* y = nullptr, bool rev = false,
+                          bool hgain = false) {
   const int nv = m.nv;
   const float* M = W + m.o_M;
   float* H = W + m.o_H;
@@ -1326,6 +1327,7 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
     for (int v = 0; v < 16; v++) {
       const int i = 8 * (v >> 2) + 4 * kh + (v & 3);
       C[v] = (i < nv && j <= i) ? (rev ? M[tri(nv - 1 - j, nv - 1 - i)] : M[tri(i, j)]) : 0.f;
+      if (hgain && i < nv && j == i) C[v] += m.dt * m.dof_vgain[rev ? nv - 1 - i : i];
     }
     for (int r = 0; r < nr; r += 2) {
       const int rr = r + kh;
@@ -1346,6 +1348,7 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
       int i, j;
       t.unrank(k, i, j);
       float v = rev ? M[tri(nv - 1 - j, nv - 1 - i)] : M[k];
+      if (hgain && i == j) v += m.dt * m.dof_vgain[rev ? nv - 1 - i : i];
       for (int r = 0; r < nru; r++) v += w[r] * J[r * nv + i] * J[r * nv + j];
       H[k] = v;
     }
@@ -1833,8 +1836,27 @@ DEV void implicit_damping(const DevModel& m, float* W, const Team& t) {
     rhs[i] = v;
   }
   t.sync();
-  ltdl_factor(m, W, t, rhs, true);  // also solves L^T y = rhs in place
-  ltdl_solve(m, W, t, nullptr, rhs, true);
+  if (nv <= t.T) {
+    // the smooth phase's dense factor in leaves-first order, of M + h diag(dof_vgain),
+    // solved in place in rhs in reversed order
+    for (int i = t.lane; i < nv / 2; i += t.T) {
+      const float u = rhs[i];
+      rhs[i] = rhs[nv - 1 - i];
+      rhs[nv - 1 - i] = u;
+    }
+    t.sync();
+    hessian_cholesky(m, W, t, 0, rhs, rhs, true, true);
+    cholesky_back(m, W, t, rhs, rhs);
+    for (int i = t.lane; i < nv / 2; i += t.T) {
+      const float u = rhs[i];
+      rhs[i] = rhs[nv - 1 - i];
+      rhs[nv - 1 - i] = u;
+    }
+    t.sync();
+  } else {
+    ltdl_factor(m, W, t, rhs, true);  // also solves L^T y = rhs in place
+    ltdl_solve(m, W, t, nullptr, rhs, true);
+  }
 }
 
 DEV void world_step(const DevModel& m, float* W0, const Team& t0, const float* ctrl,
