@@ -334,8 +334,8 @@ def hetero_compare(ctx, seed, nstep=500, reps=3):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only; worlds are independent and "
-              "would shard across GPUs with no exchange (see DESIGN.md)", file=sys.stderr)
+        print("bench.py: measures one GPU only (--gpus 1); worlds are independent, so a "
+              "multi-GPU run would split nworld across GPUs with no exchange", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
