@@ -11,7 +11,8 @@ Checks, on the quadruped from contact-rich states with a share of inverted world
 * end to end against the reference env step from the same float32 state (FP32 against
   FP64 physics over nsub steps): done identical, obs within 1e-3 (1 + |x|) for the
   median world;
-* models without a free root and per-dof position actuators are rejected;
+* models without a free root and per-dof position actuators are rejected, and so are
+  nenv 0, nsub 0 and per-world parameters on an implicit model, leaving every buffer;
 * domain randomisation: identity records and zero noise change no bit; with random
   records (friction, payload, centre of mass, PD gains, calibration, armature) and
   sensor noise, one physics step's qacc matches each world's randomised reference
@@ -267,3 +268,35 @@ def test_nonfinite_worlds_terminate_and_reset(lib):
     for k in ("obs", "reward", "done"):
         np.testing.assert_array_equal(g[k][0][ok], ref[k][0][ok])
     np.testing.assert_array_equal(g["qpos"][ok], ref["qpos"][ok])
+
+
+def test_env_step_argument_errors_leave_state(lib):
+    """No env steps (nenv 0), no physics steps per env step (nsub 0) and per-world
+    parameters on a model with implicit damping are refused before any launch, and the
+    bound state, previous action and outputs are left as they were."""
+    mjh, ctx = lib
+    nw = 6
+    for m, params in ((robots.quadruped(), False), (robots.quadruped_implicit(), True)):
+        nobs = 12 + 3 * m.nu
+        qp, qv = inputs.initial_state("quadruped", m, nw, seed=3)
+        w = mjh.World(ctx, m, nw, qpos=qp, qvel=qv)
+        q0, v0 = w.qpos.clone(), w.qvel.clone()
+        la = torch.full((nw, m.nu), 0.25, device="cuda")
+        rq, rv = _dev(qp), _dev(qv)
+        cmd = torch.zeros(nw, 3, device="cuda")
+        dr = _dev(np.tile(renv.dr_identity(m), (nw, 1))) if params else None
+        cases = [(1, NSUB)] if params else [(0, NSUB), (1, 0)]
+        for nenv, nsub in cases:
+            obs = torch.full((nenv, nw, nobs), 7.0, device="cuda")
+            rew = torch.full((nenv, nw), 7.0, device="cuda")
+            done = torch.full((nenv, nw), 7, dtype=torch.int32, device="cuda")
+            acts = torch.zeros(nenv, nw, m.nu, device="cuda")
+            print(f"[gpu] env_step refusal: integrator {m.opt.integrator} nenv {nenv} "
+                  f"nsub {nsub} params {params}", flush=True)
+            with pytest.raises(mjh.MjhError):
+                w.batch.env_step(nsub, acts, cmd, rq, rv, la, obs, rew, done,
+                                 params=dr if params else None)
+            torch.cuda.synchronize()
+            assert torch.equal(w.qpos, q0) and torch.equal(w.qvel, v0)
+            assert torch.all(la == 0.25)
+            assert torch.all(obs == 7.0) and torch.all(rew == 7.0) and torch.all(done == 7)
