@@ -235,7 +235,7 @@ __device__ __forceinline__ void env_worlds(const DevGroup& G, const EnvArgs& E, 
 // LDS: the pair table, then `ap_words` holding each team's previous action and, with
 // randomisation, its parameter record (nu + ndr words a team), then the worlds' working
 // sets at the usual stride.
-template <bool RK>
+template <bool RK, bool DR>
 __global__ void __launch_bounds__(kMaxBlock, 4)
 mjh_env_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__ tasks,
                EnvArgs E, int tab_words, int ap_words) {
@@ -248,7 +248,7 @@ mjh_env_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__ 
   if (team >= tk.nw) return;
   float* ap = lds + tab_words + team * (G.m.nu + E.ndr);
   float* W = lds + tab_words + ap_words + (size_t)team * G.m.lds_words;
-  env_worlds<RK>(G, E, W, ap, E.dr ? ap + G.m.nu : nullptr, tk.w0 + team, threadIdx.x - team * T, T,
+  env_worlds<RK>(G, E, W, ap, DR ? ap + G.m.nu : nullptr, tk.w0 + team, threadIdx.x - team * T, T,
              (const unsigned char*)lds);
 }
 
@@ -336,20 +336,28 @@ hipError_t launch_env(const DevGroup* groups, const DevTask* tasks, int ntask, c
                       int block, size_t lds_bytes, int tab_words, int ap_words, bool rk4,
                       hipStream_t stream) {
   if (ntask <= 0) return hipSuccess;
+  // one instantiation per case, so that the plain env step carries none of the
+  // randomisation's live values; per-world records come with the Euler step only
   if (rk4)
-    hipLaunchKernelGGL(mjh_env_kernel<true>, dim3(ntask), dim3(block), lds_bytes, stream,
+    hipLaunchKernelGGL((mjh_env_kernel<true, false>), dim3(ntask), dim3(block), lds_bytes, stream,
+                       groups, tasks, E, tab_words, ap_words);
+  else if (E.dr)
+    hipLaunchKernelGGL((mjh_env_kernel<false, true>), dim3(ntask), dim3(block), lds_bytes, stream,
                        groups, tasks, E, tab_words, ap_words);
   else
-    hipLaunchKernelGGL(mjh_env_kernel<false>, dim3(ntask), dim3(block), lds_bytes, stream,
+    hipLaunchKernelGGL((mjh_env_kernel<false, false>), dim3(ntask), dim3(block), lds_bytes, stream,
                        groups, tasks, E, tab_words, ap_words);
   return hipGetLastError();
 }
 
 hipError_t set_env_lds_limit(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)mjh_env_kernel<false>,
+  hipError_t e = hipFuncSetAttribute((const void*)mjh_env_kernel<false, false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)mjh_env_kernel<false, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)mjh_env_kernel<true>,
+  return hipFuncSetAttribute((const void*)mjh_env_kernel<true, false>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
