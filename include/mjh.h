@@ -182,13 +182,20 @@ mjh_status mjh_env_step(mjh_batch* b, int32_t nenv, int32_t nsub, const float* a
                         float* obs, float* reward, int32_t* done, void* stream);
 
 /* Capture mjh_step(b, nstep) into a HIP graph (replayed by mjh_graph_launch).  The
- * graph reads the bound pointers at replay time, so rebinding needs no recapture. */
+ * graph's kernel reads the groups' bound pointers from a device table at replay time;
+ * mjh_bind_state / mjh_bind_io rewrite that table in place, so a rebound batch replays
+ * its graph with the new buffers, no recapture.  mjh_set_launch and mjh_autotune change
+ * the launch shape and drop the graph: mjh_graph_launch then fails with MJH_ESTATE until
+ * the next capture. */
 mjh_status mjh_graph_capture(mjh_batch* b, int32_t nstep, void* stream);
 mjh_status mjh_graph_launch(mjh_batch* b, void* stream);
 
 /* Time candidate launch shapes (lanes per world, worlds per work-group) for every
  * group on the bound state with nstep_probe steps, keep the fastest, and restore the
- * state afterwards.  cache_path (may be NULL) stores choices across processes. */
+ * state afterwards (also when a probe fails).  cache_path (may be NULL) names a text
+ * file of choices kept across processes, one line per group shape: the model's
+ * dimensions and the group's world count, " : ", team, block.  A group found there is
+ * not probed; the file is rewritten with every choice after a successful call. */
 mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_path);
 /* Force a launch shape for group g: team in {16, 32, 64} lanes, block in {64..1024}. */
 mjh_status mjh_set_launch(mjh_batch* b, int32_t group, int32_t team, int32_t block);
@@ -198,17 +205,22 @@ mjh_status mjh_get_launch(mjh_batch* b, int32_t group, int32_t* team, int32_t* b
  * Loss: sum_{t=1..horizon} (qpos_t[zidx] - ztarget)^2 + wctrl * sum_t |ctrl_t|^2.
  * mjh_rollout_fwd runs horizon steps from the bound state with ctrl [horizon][n][nu],
  * keeps a checkpoint every ckpt_every steps, writes loss [n] and leaves the bound
- * state at the final step.  mjh_rollout_bwd(dloss [n]) writes grad_qvel0 [n][nv] and
+ * state at the final step.  The checkpoint tapes belong to the batch and hold one
+ * rollout: *generation (may be NULL) receives that rollout's number.
+ * mjh_rollout_bwd(generation, dloss [n]) writes grad_qvel0 [n][nv] and
  * grad_ctrl [horizon][n][nu] by the adjoint of the step: implicit differentiation at
  * each Newton solution, reverse sweeps of RNE/kinematics and contact geometry,
- * segments recomputed from the checkpoints.  Inside rollouts Newton iterates until
- * max|grad| <= 1e-5 * max(1, max|smooth force|), at most 16 iterations.  Only plane-sphere and plane-capsule
+ * segments recomputed from the checkpoints.  It fails with MJH_ESTATE when
+ * `generation` is not the number of the batch's last rollout_fwd (its tapes were
+ * overwritten), and reads the ctrl buffer that rollout_fwd was given, which must be
+ * unchanged.  Inside rollouts Newton iterates until max|grad| <= 1e-5 * max(1,
+ * max|smooth force|), at most 16 iterations.  Only plane-sphere and plane-capsule
  * contacts are differentiated (MJH_EUNSUPPORTED otherwise). */
 mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every,
                            const float* ctrl, int32_t zidx, float ztarget, float wctrl,
-                           float* loss, void* stream);
-mjh_status mjh_rollout_bwd(mjh_batch* b, const float* dloss, float* grad_qvel0,
-                           float* grad_ctrl, void* stream);
+                           float* loss, int64_t* generation, void* stream);
+mjh_status mjh_rollout_bwd(mjh_batch* b, int64_t generation, const float* dloss,
+                           float* grad_qvel0, float* grad_ctrl, void* stream);
 
 #ifdef __cplusplus
 }

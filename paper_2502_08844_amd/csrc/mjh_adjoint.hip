@@ -814,6 +814,7 @@ struct AdjointState {
   int* status = nullptr;
   size_t ckpt_words = 0, seg_words = 0, status_words = 0;
   bool have_fwd = false;
+  int64_t generation = 0;  // number of forward rollouts so far; the tapes hold the last
 };
 
 static int blocks_for(int nworld, int team) {
@@ -823,8 +824,8 @@ static int blocks_for(int nworld, int team) {
 
 mjh_status adjoint_forward(AdjointState** stp, const DevModel& m, int team, int nworld, float* qpos,
                            float* qvel, float* qacc, int horizon, int ckpt, const float* ctrl,
-                           int zidx, float ztarget, float wctrl, float* loss, hipStream_t stream,
-                           std::string& err) {
+                           int zidx, float ztarget, float wctrl, float* loss, int64_t* generation,
+                           hipStream_t stream, std::string& err) {
   if (horizon <= 0 || ckpt <= 0 || !ctrl || !loss || zidx < 0 || zidx >= m.nq) {
     err = "rollout_fwd: need horizon > 0, ckpt_every > 0, ctrl, loss and 0 <= zidx < nq";
     return MJH_EINVAL;
@@ -891,6 +892,9 @@ mjh_status adjoint_forward(AdjointState** stp, const DevModel& m, int team, int 
   A.tape_ckpt = st->tape_ckpt; A.tape_seg = st->tape_seg; A.loss = loss; A.status = st->status;
   A.tape_snap = st->tape_snap; A.snap_words = m.o_qbi;
   st->have_fwd = false;
+  // the tapes are about to be overwritten: an earlier rollout can no longer be reversed
+  st->generation++;
+  if (generation) *generation = st->generation;
   if (nworld == 0) { st->have_fwd = true; return MJH_OK; }
   const size_t lds =
       ((size_t)table_words(m) + (size_t)(kAdjBlock / team) * m.lds_words) * sizeof(float);
@@ -908,9 +912,15 @@ mjh_status adjoint_forward(AdjointState** stp, const DevModel& m, int team, int 
   return MJH_OK;
 }
 
-mjh_status adjoint_backward(AdjointState* st, const float* dloss, float* grad_qvel0,
-                            float* grad_ctrl, hipStream_t stream, std::string& err) {
+mjh_status adjoint_backward(AdjointState* st, int64_t generation, const float* dloss,
+                            float* grad_qvel0, float* grad_ctrl, hipStream_t stream,
+                            std::string& err) {
   if (!st || !st->have_fwd) { err = "rollout_bwd: call rollout_fwd first"; return MJH_ESTATE; }
+  if (generation != st->generation) {
+    err = "rollout_bwd: the tapes hold rollout " + std::to_string(st->generation) +
+          ", not rollout " + std::to_string(generation) + " (a later rollout_fwd replaced it)";
+    return MJH_ESTATE;
+  }
   if (!dloss || !grad_qvel0 || !grad_ctrl) { err = "rollout_bwd: NULL argument"; return MJH_EINVAL; }
   RolloutArgs A = st->args;
   A.dloss = dloss;

@@ -649,7 +649,8 @@ struct mjh_batch {
   int tab_words = 0;
   size_t lds_bytes = 0;
   bool rk4 = false;  // some group integrates by fourth-order Runge-Kutta
-  bool dirty = true;
+  bool dirty = true;       // launch shape or world counts changed: rebuild the tables
+  bool ptrs_dirty = false; // only bound pointers changed: rewrite d_groups in place
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   int graph_nstep = 0;
@@ -681,11 +682,38 @@ static int worlds_per_block(const mjh_ctx* ctx, const ModelRec& mr, int team, in
   return wpb;
 }
 
-// rebuild the device group/task tables (synchronous)
+// the kernel's view of every group: model tables, bound pointers, counts, team
+static std::vector<DevGroup> group_table(const mjh_batch* b) {
+  const mjh_ctx* ctx = b->ctx;
+  std::vector<DevGroup> dg(b->groups.size());
+  for (size_t g = 0; g < b->groups.size(); g++) {
+    const GroupRec& gr = b->groups[g];
+    DevGroup& x = dg[g];
+    x.m = ctx->models[gr.model]->dm;
+    x.qpos = gr.qpos; x.qvel = gr.qvel; x.qacc = gr.qacc; x.status = gr.status;
+    x.ctrl = gr.ctrl; x.con_out = gr.con_out; x.ncon_out = gr.ncon_out;
+    x.nworld = gr.nworld; x.ctrl_nstep = gr.ctrl_nstep; x.team = gr.team;
+  }
+  return dg;
+}
+
+// Bring the device group/task tables up to date (synchronous).  A new launch shape or
+// world count rebuilds both tables and drops a captured graph.  New bound pointers
+// alone are written into the existing group table in place: its device address, which
+// a captured graph's kernel node holds, does not change, so the graph replays with the
+// new pointers.
 static mjh_status sync_tables(mjh_batch* b) {
   mjh_ctx* ctx = b->ctx;
-  if (!b->dirty) return MJH_OK;
-  std::vector<DevGroup> dg(b->groups.size());
+  if (!b->dirty && b->ptrs_dirty && b->d_groups) {
+    const std::vector<DevGroup> dg = group_table(b);
+    // no launch of this batch may be reading the table while it is rewritten
+    MJH_HIP(hipDeviceSynchronize());
+    MJH_HIP(hipMemcpy(b->d_groups, dg.data(), dg.size() * sizeof(DevGroup), hipMemcpyHostToDevice));
+    b->ptrs_dirty = false;
+    return MJH_OK;
+  }
+  if (!b->dirty && !b->ptrs_dirty) return MJH_OK;
+  const std::vector<DevGroup> dg = group_table(b);
   struct Tk { DevTask t; double cost; };
   std::vector<Tk> tasks;
   int block = 0;
@@ -696,11 +724,6 @@ static mjh_status sync_tables(mjh_batch* b) {
   for (size_t g = 0; g < b->groups.size(); g++) {
     const GroupRec& gr = b->groups[g];
     const ModelRec& mr = *ctx->models[gr.model];
-    DevGroup& x = dg[g];
-    x.m = mr.dm;
-    x.qpos = gr.qpos; x.qvel = gr.qvel; x.qacc = gr.qacc; x.status = gr.status;
-    x.ctrl = gr.ctrl; x.con_out = gr.con_out; x.ncon_out = gr.ncon_out;
-    x.nworld = gr.nworld; x.ctrl_nstep = gr.ctrl_nstep; x.team = gr.team;
     if (gr.nworld == 0) continue;
     const int wpb = worlds_per_block(ctx, mr, gr.team, gr.block, tab_words);
     const size_t per = (size_t)mr.dm.lds_words * sizeof(float);
@@ -734,6 +757,7 @@ static mjh_status sync_tables(mjh_batch* b) {
   for (const GroupRec& gr : b->groups)
     if (gr.nworld > 0 && ctx->models[gr.model]->dm.rk4) b->rk4 = true;
   b->dirty = false;
+  b->ptrs_dirty = false;
   if (b->graph_exec) { (void)hipGraphExecDestroy(b->graph_exec); b->graph_exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   return MJH_OK;
@@ -897,7 +921,7 @@ mjh_status mjh_bind_state(mjh_batch* b, int32_t group, float* qpos, float* qvel,
   if (g.nworld > 0 && (!qpos || !qvel || !qacc_ws))
     return fail(ctx, MJH_EINVAL, "bind_state: qpos, qvel and qacc_ws are required");
   g.qpos = qpos; g.qvel = qvel; g.qacc = qacc_ws; g.status = status;
-  b->dirty = true;
+  b->ptrs_dirty = true;
   return sync_tables(b);
 }
 
@@ -912,7 +936,7 @@ mjh_status mjh_bind_io(mjh_batch* b, int32_t group, const float* ctrl, int32_t c
   GroupRec& g = b->groups[group];
   g.ctrl = ctrl; g.ctrl_nstep = ctrl ? ctrl_nstep : 0;
   g.con_out = contact_out; g.ncon_out = ncon_out;
-  b->dirty = true;
+  b->ptrs_dirty = true;
   return sync_tables(b);
 }
 
@@ -1048,37 +1072,42 @@ mjh_status mjh_get_launch(mjh_batch* b, int32_t group, int32_t* team, int32_t* b
   return MJH_OK;
 }
 
+// Autotune cache key of a group: the model dimensions that set its cost, and its
+// world count.  One line of the cache file is "<key> : <team> <block>".
+static std::string tune_key(const DevModel& d, int nworld) {
+  std::ostringstream k;
+  k << d.nq << ' ' << d.nv << ' ' << d.nbody << ' ' << d.npair << ' ' << d.ncand << ' '
+    << d.nconmax << ' ' << d.nlim << ' ' << d.nfric << ' ' << d.neq << ' ' << d.conrows << ' '
+    << d.implicit << ' ' << d.rk4 << ' ' << d.iterations << ' ' << nworld;
+  return k.str();
+}
+
+static bool valid_shape(int team, int block) {
+  return (team == 16 || team == 32 || team == 64) && block >= team && block <= kMaxBlock &&
+         block % team == 0;
+}
+
 // Time every candidate shape per group (other groups keep their shape), keep the
-// fastest.  The bound state is saved before and restored after the probes.
+// fastest.  The bound state is saved before and restored after the probes, also when a
+// probe fails; groups found in the cache are not probed.
 mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_path) {
   if (!b) return MJH_EINVAL;
   mjh_ctx* ctx = b->ctx;
   if (nstep_probe <= 0) return fail(ctx, MJH_EINVAL, "autotune: nstep_probe must be > 0");
   mjh_status st = check_ready(b, nstep_probe);
   if (st != MJH_OK) return st;
-  // cache: lines "nq nv nbody npair nconmax nworld team block"
   std::map<std::string, std::pair<int, int>> cache;
-  auto key_of = [&](const GroupRec& g) {
-    const DevModel& d = ctx->models[g.model]->dm;
-    std::ostringstream k;
-    k << d.nq << ' ' << d.nv << ' ' << d.nbody << ' ' << d.npair << ' ' << d.nconmax << ' '
-      << d.nlim << ' ' << d.nfric << ' ' << d.neq << ' ' << d.implicit << ' ' << d.rk4 << ' ' << d.iterations
-      << ' ' << g.nworld;
-    return k.str();
-  };
   if (cache_path) {
     std::ifstream f(cache_path);
     std::string line;
     while (std::getline(f, line)) {
-      std::istringstream is(line);
-      int v[7], t, bl;
-      bool ok = true;
-      for (int& x : v) ok = ok && (bool)(is >> x);
-      if (ok && (is >> t >> bl)) {
-        std::ostringstream k;
-        k << v[0] << ' ' << v[1] << ' ' << v[2] << ' ' << v[3] << ' ' << v[4] << ' ' << v[5] << ' ' << v[6];
-        cache[k.str()] = {t, bl};
-      }
+      const size_t c = line.find(':');
+      if (c == std::string::npos) continue;
+      std::string key = line.substr(0, c);
+      while (!key.empty() && key.back() == ' ') key.pop_back();
+      std::istringstream is(line.substr(c + 1));
+      int t = 0, bl = 0;
+      if ((is >> t >> bl) && valid_shape(t, bl)) cache[key] = {t, bl};
     }
   }
   // save state
@@ -1095,25 +1124,36 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
     MJH_HIP(hipMemcpy(saved[g].v.data(), gr.qvel, saved[g].v.size() * 4, hipMemcpyDeviceToHost));
     MJH_HIP(hipMemcpy(saved[g].a.data(), gr.qacc, saved[g].a.size() * 4, hipMemcpyDeviceToHost));
   }
-  auto restore = [&]() -> mjh_status {
+  std::string herr;  // first failing HIP call of the probes
+  auto hip_ok = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && herr.empty()) herr = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipSuccess;
+  };
+  auto restore = [&]() {
+    bool ok = true;
     for (size_t g = 0; g < b->groups.size(); g++) {
       GroupRec& gr = b->groups[g];
       if (gr.nworld == 0) continue;
-      MJH_HIP(hipMemcpy(gr.qpos, saved[g].q.data(), saved[g].q.size() * 4, hipMemcpyHostToDevice));
-      MJH_HIP(hipMemcpy(gr.qvel, saved[g].v.data(), saved[g].v.size() * 4, hipMemcpyHostToDevice));
-      MJH_HIP(hipMemcpy(gr.qacc, saved[g].a.data(), saved[g].a.size() * 4, hipMemcpyHostToDevice));
+      ok = ok && hip_ok(hipMemcpy(gr.qpos, saved[g].q.data(), saved[g].q.size() * 4,
+                                  hipMemcpyHostToDevice), "autotune: restore qpos");
+      ok = ok && hip_ok(hipMemcpy(gr.qvel, saved[g].v.data(), saved[g].v.size() * 4,
+                                  hipMemcpyHostToDevice), "autotune: restore qvel");
+      ok = ok && hip_ok(hipMemcpy(gr.qacc, saved[g].a.data(), saved[g].a.size() * 4,
+                                  hipMemcpyHostToDevice), "autotune: restore qacc_ws");
     }
-    return MJH_OK;
+    return ok;
   };
-  hipEvent_t e0, e1;
-  MJH_HIP(hipEventCreate(&e0));
-  MJH_HIP(hipEventCreate(&e1));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool ok = hip_ok(hipEventCreate(&e0), "autotune: event") &&
+            hip_ok(hipEventCreate(&e1), "autotune: event");
   const int teams[3] = {16, 32, 64};
   const int blocks[3] = {64, 128, 256};
-  for (size_t g = 0; g < b->groups.size(); g++) {
+  std::vector<int> counts;
+  for (auto& o : b->groups) counts.push_back(o.nworld);
+  for (size_t g = 0; ok && g < b->groups.size(); g++) {
     GroupRec& gr = b->groups[g];
     if (gr.nworld == 0) continue;
-    const std::string key = key_of(gr);
+    const std::string key = tune_key(ctx->models[gr.model]->dm, gr.nworld);
     auto it = cache.find(key);
     if (it != cache.end()) {
       gr.team = it->second.first;
@@ -1122,54 +1162,55 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
       continue;
     }
     // time this group alone: other groups are switched off during its probes
-    std::vector<int> counts;
-    for (auto& o : b->groups) counts.push_back(o.nworld);
     for (size_t o = 0; o < b->groups.size(); o++)
       if (o != g) b->groups[o].nworld = 0;
     float best = INFINITY;
     int bt = gr.team, bb = gr.block;
     for (int t : teams)
       for (int bl : blocks) {
-        if (bl < t) continue;
+        if (!ok || bl < t) continue;
         gr.team = t;
         gr.block = bl;
         b->dirty = true;
         st = sync_tables(b);
-        if (st != MJH_OK) break;
+        if (st != MJH_OK) { ok = false; break; }
         float ms = 0.f;
-        for (int rep = 0; rep < 2; rep++) {  // first run warms caches
-          if (restore() != MJH_OK) { st = MJH_EHIP; break; }
-          MJH_HIP(hipEventRecord(e0, nullptr));
-          MJH_HIP(launch_step(b->d_groups, b->d_tasks, b->ntask, nstep_probe, b->block, b->lds_bytes,
-                              b->tab_words, b->rk4, nullptr));
-          MJH_HIP(hipEventRecord(e1, nullptr));
-          MJH_HIP(hipEventSynchronize(e1));
-          MJH_HIP(hipEventElapsedTime(&ms, e0, e1));
+        for (int rep = 0; ok && rep < 2; rep++) {  // the first run warms caches
+          ok = restore() && hip_ok(hipEventRecord(e0, nullptr), "autotune: event") &&
+               hip_ok(launch_step(b->d_groups, b->d_tasks, b->ntask, nstep_probe, b->block,
+                                  b->lds_bytes, b->tab_words, b->rk4, nullptr),
+                      "autotune: probe launch") &&
+               hip_ok(hipEventRecord(e1, nullptr), "autotune: event") &&
+               hip_ok(hipEventSynchronize(e1), "autotune: probe") &&
+               hip_ok(hipEventElapsedTime(&ms, e0, e1), "autotune: event");
         }
-        if (st != MJH_OK) break;
-        if (ms < best) { best = ms; bt = t; bb = bl; }
+        if (ok && ms < best) { best = ms; bt = t; bb = bl; }
       }
     for (size_t o = 0; o < b->groups.size(); o++) b->groups[o].nworld = counts[o];
     gr.team = bt;
     gr.block = bb;
     b->dirty = true;
-    if (st != MJH_OK) break;
-    cache[key] = {bt, bb};
+    if (ok) cache[key] = {bt, bb};
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  mjh_status rs = restore();
-  if (st == MJH_OK) st = rs;
-  if (st == MJH_OK) st = sync_tables(b);
+  for (size_t o = 0; o < b->groups.size(); o++) b->groups[o].nworld = counts[o];
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  const bool restored = restore();
+  if (st == MJH_OK && !(ok && restored)) st = MJH_EHIP;
+  const mjh_status ts = sync_tables(b);
+  if (st == MJH_EHIP && !herr.empty()) ctx->err = herr;
+  if (st == MJH_OK) st = ts;
   if (st == MJH_OK && cache_path) {
     std::ofstream f(cache_path);
-    for (auto& kv : cache) f << kv.first << ' ' << kv.second.first << ' ' << kv.second.second << '\n';
+    for (auto& kv : cache) f << kv.first << " : " << kv.second.first << ' ' << kv.second.second << '\n';
+    if (!f) return fail(ctx, MJH_EINVAL, std::string("autotune: cannot write ") + cache_path);
   }
   return st;
 }
 
 mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every, const float* ctrl,
-                           int32_t zidx, float ztarget, float wctrl, float* loss, void* stream) {
+                           int32_t zidx, float ztarget, float wctrl, float* loss,
+                           int64_t* generation, void* stream) {
   if (!b) return MJH_EINVAL;
   mjh_ctx* ctx = b->ctx;
   if (b->groups.size() != 1) return fail(ctx, MJH_EINVAL, "rollout: single-model batches only");
@@ -1198,18 +1239,18 @@ mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every, co
   }
   std::string err;
   mjh_status st = adjoint_forward(&b->adj, mr.dm_adj, g.team, g.nworld, g.qpos, g.qvel, g.qacc, horizon,
-                                  ckpt_every, ctrl, zidx, ztarget, wctrl, loss,
+                                  ckpt_every, ctrl, zidx, ztarget, wctrl, loss, generation,
                                   static_cast<hipStream_t>(stream), err);
   if (st != MJH_OK) return fail(ctx, st, err);
   return MJH_OK;
 }
 
-mjh_status mjh_rollout_bwd(mjh_batch* b, const float* dloss, float* grad_qvel0, float* grad_ctrl,
-                           void* stream) {
+mjh_status mjh_rollout_bwd(mjh_batch* b, int64_t generation, const float* dloss,
+                           float* grad_qvel0, float* grad_ctrl, void* stream) {
   if (!b) return MJH_EINVAL;
   mjh_ctx* ctx = b->ctx;
   std::string err;
-  mjh_status st = adjoint_backward(b->adj, dloss, grad_qvel0, grad_ctrl,
+  mjh_status st = adjoint_backward(b->adj, generation, dloss, grad_qvel0, grad_ctrl,
                                    static_cast<hipStream_t>(stream), err);
   if (st != MJH_OK) return fail(ctx, st, err);
   return MJH_OK;

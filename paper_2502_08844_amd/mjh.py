@@ -66,8 +66,9 @@ mjh_graph_launch = _sig("mjh_graph_launch", P, P)
 mjh_autotune = _sig("mjh_autotune", P, I32, C.c_char_p)
 mjh_set_launch = _sig("mjh_set_launch", P, I32, I32, I32)
 mjh_get_launch = _sig("mjh_get_launch", P, I32, C.POINTER(I32), C.POINTER(I32))
-mjh_rollout_fwd = _sig("mjh_rollout_fwd", P, I32, I32, P, I32, F, F, P, P)
-mjh_rollout_bwd = _sig("mjh_rollout_bwd", P, P, P, P, P)
+I64 = C.c_int64
+mjh_rollout_fwd = _sig("mjh_rollout_fwd", P, I32, I32, P, I32, F, F, P, C.POINTER(I64), P)
+mjh_rollout_bwd = _sig("mjh_rollout_bwd", P, I64, P, P, P, P)
 mjh_env_step = _sig("mjh_env_step", P, I32, I32, P, P, P, P, P, P, P, P, P, P, P)
 
 
@@ -230,16 +231,19 @@ class Batch:
         return t.value, b.value
 
     def rollout_fwd(self, horizon: int, ckpt_every: int, ctrl, zidx: int, ztarget: float,
-                    wctrl: float, loss, stream=None):
+                    wctrl: float, loss, stream=None) -> int:
+        """Forward rollout; returns its generation number (rollout_bwd's key)."""
         if len(self.models) != 1:
             raise ValueError("rollouts take a single-model batch")
         nw, nu = self.counts[0], self.models[0].nu
         if ctrl is None or ctrl.numel() != horizon * nw * nu or loss.numel() != nw:
             raise ValueError(f"ctrl must be [{horizon}, {nw}, {nu}] and loss [{nw}]")
-        self._rollout = (int(horizon), nw, self.models[0].nv, nu)
+        gen = I64(0)
         self.ctx.check(mjh_rollout_fwd(self._h, int(horizon), int(ckpt_every), _ptr(ctrl),
                                        int(zidx), float(ztarget), float(wctrl), _ptr(loss),
-                                       _stream(stream)))
+                                       C.byref(gen), _stream(stream)))
+        self._rollout = (int(horizon), nw, self.models[0].nv, nu, gen.value)
+        return gen.value
 
     def env_step(self, nsub: int, action, command, reset_qpos, reset_qvel, last_action, obs,
                  reward, done, params=None, obs_noise=None, stream=None):
@@ -269,16 +273,19 @@ class Batch:
                                     _ptr(obs), _ptr(reward), _ptr(done, torch.int32),
                                     _stream(stream)))
 
-    def rollout_bwd(self, dloss, grad_qvel0, grad_ctrl, stream=None):
+    def rollout_bwd(self, dloss, grad_qvel0, grad_ctrl, stream=None, generation=None):
+        """Adjoint of the rollout `generation` (default: the last rollout_fwd).  The
+        library refuses any rollout but the last one (its tapes were overwritten)."""
         shp = getattr(self, "_rollout", None)
         if shp is None:
             raise ValueError("rollout_bwd needs a preceding rollout_fwd")
-        horizon, nw, nv, nu = shp
+        horizon, nw, nv, nu, last = shp
         if (dloss.numel() != nw or grad_qvel0.numel() != nw * nv
                 or grad_ctrl.numel() != horizon * nw * nu):
             raise ValueError(f"dloss [{nw}], grad_qvel0 [{nw}, {nv}], "
                              f"grad_ctrl [{horizon}, {nw}, {nu}] expected")
-        self.ctx.check(mjh_rollout_bwd(self._h, _ptr(dloss), _ptr(grad_qvel0),
+        gen = last if generation is None else int(generation)
+        self.ctx.check(mjh_rollout_bwd(self._h, gen, _ptr(dloss), _ptr(grad_qvel0),
                                        _ptr(grad_ctrl), _stream(stream)))
 
 
@@ -337,7 +344,8 @@ class Rollout(torch.autograd.Function):
         world.qvel.copy_(qvel0)
         ctrl = ctrl.contiguous()
         loss = torch.empty(world.nworld, dtype=torch.float32, device=qvel0.device)
-        world.batch.rollout_fwd(horizon, ckpt_every, ctrl, zidx, ztarget, wctrl, loss)
+        ctx.generation = world.batch.rollout_fwd(horizon, ckpt_every, ctrl, zidx, ztarget,
+                                                 wctrl, loss)
         ctx.world = world
         ctx.save_for_backward(ctrl)
         return loss
@@ -348,7 +356,9 @@ class Rollout(torch.autograd.Function):
         w = ctx.world
         gq = torch.empty(w.nworld, w.model.nv, dtype=torch.float32, device=dloss.device)
         gu = torch.empty_like(ctrl)
-        w.batch.rollout_bwd(dloss.contiguous().float(), gq, gu)
+        # a later forward rollout of the same world overwrote the tapes: the library
+        # refuses this backward (MJH_ESTATE) rather than return another rollout's gradient
+        w.batch.rollout_bwd(dloss.contiguous().float(), gq, gu, generation=ctx.generation)
         return gq, gu, None, None, None, None, None, None
 
 

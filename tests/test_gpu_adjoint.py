@@ -117,3 +117,30 @@ def test_rollout_rejects_unsupported_contacts():
     loss = torch.zeros(2, device="cuda")
     with pytest.raises(mjh.MjhError):
         w.batch.rollout_fwd(4, 2, u, 2, 0.3, 1e-3, loss)
+
+
+def test_backward_of_a_replaced_rollout_is_refused():
+    """Two forward rollouts of one world share its tapes: the first one's backward is
+    refused (MJH_ESTATE), the second one's gradient equals a fresh single rollout's."""
+    from paper_2502_08844_amd import mjh
+    nw = 32
+    m, qp, qv, u = _setup(nw, seed=2)
+    ctx = mjh.Context(0)
+    w = mjh.World(ctx, m, nw, qpos=qp)
+    qv0 = torch.tensor(qv, dtype=torch.float32, device="cuda", requires_grad=True)
+    ut = torch.tensor(u, dtype=torch.float32, device="cuda", requires_grad=True)
+    loss1 = mjh.Rollout.apply(qv0, ut, w, H, K)
+    w.qpos.copy_(torch.tensor(qp, dtype=torch.float32, device="cuda"))
+    w.qacc_ws.zero_()
+    loss2 = mjh.Rollout.apply(qv0, ut, w, H, K)
+    with pytest.raises(mjh.MjhError) as e:
+        loss1.sum().backward(retain_graph=True)
+    assert e.value.code == mjh.ESTATE
+    qv0.grad = None
+    ut.grad = None
+    loss2.sum().backward()
+    torch.cuda.synchronize()
+    L, gq, gu = _gpu_grads(m, qp, qv, u)
+    assert np.array_equal(loss2.detach().cpu().double().numpy(), L)
+    assert np.array_equal(qv0.grad.cpu().double().numpy(), gq)
+    assert np.array_equal(ut.grad.cpu().double().numpy(), gu)
