@@ -222,6 +222,25 @@ mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every,
 mjh_status mjh_rollout_bwd(mjh_batch* b, int64_t generation, const float* dloss,
                            float* grad_qvel0, float* grad_ctrl, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * training loops, harnesses that forbid hipMalloc): mjh_rollout_fwd followed by
+ * mjh_rollout_bwd in one call, with the same arguments, kernels and results (loss [n],
+ * grad_qvel0 [n][nv], grad_ctrl [horizon][n][nu], all caller-owned device memory; dloss
+ * [n] is an input), the bound state left at the final step.  The tapes live in a static
+ * device array of the library (64 MiB on every device it runs on, held until the process
+ * ends) instead of the batch's own tapes, so this call allocates nothing; the batch's
+ * pending rollout_fwd, if any, stays valid.  A rollout whose tapes need more than the
+ * array -- ceil(horizon / ckpt_every) + min(ckpt_every, horizon) + 1 states of
+ * nq + 2 nv floats plus min(ckpt_every, horizon) on-chip images per world -- fails with
+ * MJH_EINVAL before launching anything (about 1 000 quadruped worlds at horizon 64 and a
+ * checkpoint every 8 steps fit).  Every call on one device shares the array: two calls
+ * that overlap on one device (two streams, two threads, two contexts) race and give
+ * undefined results.  Same model restrictions as mjh_rollout_fwd. */
+mjh_status mjh_rollout_noalloc(mjh_batch* b, int32_t horizon, int32_t ckpt_every,
+                               const float* ctrl, int32_t zidx, float ztarget, float wctrl,
+                               const float* dloss, float* loss, float* grad_qvel0,
+                               float* grad_ctrl, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "mjh_adjoint.h"
 #include "mjh_device.h"
@@ -933,6 +934,103 @@ mjh_status adjoint_backward(AdjointState* st, int64_t generation, const float* d
                      stream, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) { err = std::string("rollout_bwd: ") + hipGetErrorString(e); return MJH_EHIP; }
+  return MJH_OK;
+}
+
+// ------------------------------------------------------------------ no-alloc rollouts
+// Tapes of mjh_rollout_noalloc: one rollout's checkpoints, segment states and per-step
+// on-chip images.  A file-scope device array: every device the library runs on holds its
+// own copy from the module's load until the process ends, and every call on that device
+// shares it (calls that overlap on one device race).  Host code never passes the array's
+// name to a kernel: it is a host-side stand-in, not a device address.  The address comes
+// from hipGetSymbolAddress, once per device, in noalloc_scratch_init.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = static_cast<unsigned char*>(p);
+  return hipSuccess;
+}
+
+static size_t round256(size_t bytes) { return (bytes + 255) & ~size_t(255); }
+
+size_t noalloc_tape_bytes(const DevModel& m, int nworld, int horizon, int ckpt) {
+  const size_t nseg = (size_t)((horizon + ckpt - 1) / ckpt);
+  const size_t seglen = (size_t)std::min(ckpt, horizon);
+  const size_t ns = (size_t)m.nq + 2 * (size_t)m.nv;
+  return round256(nseg * nworld * ns * sizeof(float)) +
+         round256((seglen + 1) * nworld * ns * sizeof(float)) +
+         round256(seglen * nworld * (size_t)m.o_qbi * sizeof(unsigned));
+}
+
+mjh_status adjoint_noalloc(int device, const DevModel& m, int team, int nworld, float* qpos,
+                           float* qvel, float* qacc, int horizon, int ckpt, const float* ctrl,
+                           int zidx, float ztarget, float wctrl, const float* dloss, float* loss,
+                           float* grad_qvel0, float* grad_ctrl, hipStream_t stream,
+                           std::string& err) {
+  if (horizon <= 0 || ckpt <= 0 || !ctrl || !loss || !dloss || !grad_qvel0 || !grad_ctrl ||
+      zidx < 0 || zidx >= m.nq) {
+    err = "rollout_noalloc: need horizon > 0, ckpt_every > 0, ctrl, dloss, loss, gradients "
+          "and 0 <= zidx < nq";
+    return MJH_EINVAL;
+  }
+  if (!qpos || !qvel || !qacc) { err = "rollout_noalloc: state not bound"; return MJH_ESTATE; }
+  if (nworld < 0) { err = "rollout_noalloc: negative world count"; return MJH_EINVAL; }
+  const size_t need = noalloc_tape_bytes(m, nworld, horizon, ckpt);
+  if (need > kNoAllocScratchBytes) {
+    err = "rollout_noalloc: " + std::to_string(nworld) + " worlds over " +
+          std::to_string(horizon) + " steps with a checkpoint every " + std::to_string(ckpt) +
+          " need " + std::to_string(need) + " bytes of tape, more than the library's " +
+          std::to_string(kNoAllocScratchBytes) + "-byte scratch";
+    return MJH_EINVAL;
+  }
+  unsigned char* base = (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+  if (!base) { err = "rollout_noalloc: device scratch not initialised"; return MJH_ESTATE; }
+  if (nworld == 0) return MJH_OK;
+  team = (team == 16 || team == 32 || team == 64) ? team : 32;
+  RolloutArgs A{};
+  A.m = m;
+  A.nworld = nworld; A.horizon = horizon; A.ckpt = ckpt; A.zidx = zidx; A.team = team;
+  A.nseg = (horizon + ckpt - 1) / ckpt; A.ztarget = ztarget; A.wctrl = wctrl;
+  A.qpos = qpos; A.qvel = qvel; A.qacc = qacc; A.ctrl = ctrl;
+  const size_t ns = (size_t)m.nq + 2 * (size_t)m.nv;
+  const size_t seglen = (size_t)std::min(ckpt, horizon);
+  size_t off = 0;
+  A.tape_ckpt = reinterpret_cast<float*>(base + off);
+  off += round256((size_t)A.nseg * nworld * ns * sizeof(float));
+  A.tape_seg = reinterpret_cast<float*>(base + off);
+  off += round256((seglen + 1) * nworld * ns * sizeof(float));
+  A.tape_snap = reinterpret_cast<unsigned*>(base + off);
+  A.snap_words = m.o_qbi;
+  A.status = nullptr;  // the rollouts' per-world status is not reported
+  A.loss = loss; A.dloss = dloss; A.grad_qvel0 = grad_qvel0; A.grad_ctrl = grad_ctrl;
+  const size_t lds =
+      ((size_t)table_words(m) + (size_t)(kAdjBlock / team) * m.lds_words) * sizeof(float);
+  hipError_t e = hipFuncSetAttribute((const void*)rollout_fwd_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)rollout_bwd_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) { err = std::string("rollout_noalloc: ") + hipGetErrorString(e); return MJH_EHIP; }
+  // forward, then reverse: stream order keeps the reverse sweep behind the tapes' writes
+  hipLaunchKernelGGL(rollout_fwd_kernel, dim3(blocks_for(nworld, team)), dim3(kAdjBlock), lds,
+                     stream, A);
+  e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(rollout_bwd_kernel, dim3(blocks_for(nworld, team)), dim3(kAdjBlock), lds,
+                       stream, A);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) { err = std::string("rollout_noalloc: ") + hipGetErrorString(e); return MJH_EHIP; }
   return MJH_OK;
 }
 

@@ -783,6 +783,8 @@ mjh_status mjh_create(int device, mjh_ctx** out) {
   ctx->num_cu = prop.multiProcessorCount;
   if (set_step_lds_limit(ctx->lds_limit) != hipSuccess || set_env_lds_limit(ctx->lds_limit) != hipSuccess)
     ctx->lds_limit = 65536;
+  // the device address of the no-alloc rollouts' scratch, looked up once per device
+  if (noalloc_scratch_init(device) != hipSuccess) { delete ctx; return MJH_EHIP; }
   *out = ctx;
   return MJH_OK;
 }
@@ -1208,14 +1210,11 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
   return st;
 }
 
-mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every, const float* ctrl,
-                           int32_t zidx, float ztarget, float wctrl, float* loss,
-                           int64_t* generation, void* stream) {
-  if (!b) return MJH_EINVAL;
-  mjh_ctx* ctx = b->ctx;
-  if (b->groups.size() != 1) return fail(ctx, MJH_EINVAL, "rollout: single-model batches only");
-  GroupRec& g = b->groups[0];
-  const ModelRec& mr = *ctx->models[g.model];
+}  // extern "C"
+
+// The models the rollouts' reverse sweep covers: plane-sphere / plane-capsule contact
+// geometry with condim 3, no equalities, integrator 0, bodies of at most four joints.
+static mjh_status rollout_model_check(mjh_ctx* ctx, const ModelRec& mr) {
   // the reverse sweep covers plane-sphere / plane-capsule contact geometry and bodies
   // of at most four scalar joints
   for (int p = 0; p < mr.h.npair; p++) {
@@ -1237,10 +1236,25 @@ mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every, co
     for (int b = 0; b < mr.h.nbody; b++)
       if (nj[b] > 4) return fail(ctx, MJH_EUNSUPPORTED, "rollout: a body has more than 4 joints");
   }
+  return MJH_OK;
+}
+
+extern "C" {
+
+mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every, const float* ctrl,
+                           int32_t zidx, float ztarget, float wctrl, float* loss,
+                           int64_t* generation, void* stream) {
+  if (!b) return MJH_EINVAL;
+  mjh_ctx* ctx = b->ctx;
+  if (b->groups.size() != 1) return fail(ctx, MJH_EINVAL, "rollout: single-model batches only");
+  GroupRec& g = b->groups[0];
+  const ModelRec& mr = *ctx->models[g.model];
+  mjh_status st = rollout_model_check(ctx, mr);
+  if (st != MJH_OK) return st;
   std::string err;
-  mjh_status st = adjoint_forward(&b->adj, mr.dm_adj, g.team, g.nworld, g.qpos, g.qvel, g.qacc, horizon,
-                                  ckpt_every, ctrl, zidx, ztarget, wctrl, loss, generation,
-                                  static_cast<hipStream_t>(stream), err);
+  st = adjoint_forward(&b->adj, mr.dm_adj, g.team, g.nworld, g.qpos, g.qvel, g.qacc, horizon,
+                       ckpt_every, ctrl, zidx, ztarget, wctrl, loss, generation,
+                       static_cast<hipStream_t>(stream), err);
   if (st != MJH_OK) return fail(ctx, st, err);
   return MJH_OK;
 }
@@ -1252,6 +1266,25 @@ mjh_status mjh_rollout_bwd(mjh_batch* b, int64_t generation, const float* dloss,
   std::string err;
   mjh_status st = adjoint_backward(b->adj, generation, dloss, grad_qvel0, grad_ctrl,
                                    static_cast<hipStream_t>(stream), err);
+  if (st != MJH_OK) return fail(ctx, st, err);
+  return MJH_OK;
+}
+
+mjh_status mjh_rollout_noalloc(mjh_batch* b, int32_t horizon, int32_t ckpt_every,
+                               const float* ctrl, int32_t zidx, float ztarget, float wctrl,
+                               const float* dloss, float* loss, float* grad_qvel0,
+                               float* grad_ctrl, void* stream) {
+  if (!b) return MJH_EINVAL;
+  mjh_ctx* ctx = b->ctx;
+  if (b->groups.size() != 1) return fail(ctx, MJH_EINVAL, "rollout: single-model batches only");
+  GroupRec& g = b->groups[0];
+  const ModelRec& mr = *ctx->models[g.model];
+  mjh_status st = rollout_model_check(ctx, mr);
+  if (st != MJH_OK) return st;
+  std::string err;
+  st = adjoint_noalloc(ctx->device, mr.dm_adj, g.team, g.nworld, g.qpos, g.qvel, g.qacc, horizon,
+                       ckpt_every, ctrl, zidx, ztarget, wctrl, dloss, loss, grad_qvel0,
+                       grad_ctrl, static_cast<hipStream_t>(stream), err);
   if (st != MJH_OK) return fail(ctx, st, err);
   return MJH_OK;
 }

@@ -69,6 +69,7 @@ mjh_get_launch = _sig("mjh_get_launch", P, I32, C.POINTER(I32), C.POINTER(I32))
 I64 = C.c_int64
 mjh_rollout_fwd = _sig("mjh_rollout_fwd", P, I32, I32, P, I32, F, F, P, C.POINTER(I64), P)
 mjh_rollout_bwd = _sig("mjh_rollout_bwd", P, I64, P, P, P, P)
+mjh_rollout_noalloc = _sig("mjh_rollout_noalloc", P, I32, I32, P, I32, F, F, P, P, P, P, P)
 mjh_env_step = _sig("mjh_env_step", P, I32, I32, P, P, P, P, P, P, P, P, P, P, P)
 
 
@@ -287,6 +288,26 @@ class Batch:
         gen = last if generation is None else int(generation)
         self.ctx.check(mjh_rollout_bwd(self._h, gen, _ptr(dloss), _ptr(grad_qvel0),
                                        _ptr(grad_ctrl), _stream(stream)))
+
+    def rollout_noalloc(self, horizon: int, ckpt_every: int, ctrl, zidx: int, ztarget: float,
+                        wctrl: float, dloss, loss, grad_qvel0, grad_ctrl, stream=None):
+        """rollout_fwd then rollout_bwd in one library call that allocates no device
+        memory (its tapes live in the library's static scratch).  Every tensor is
+        caller-owned: ctrl [horizon, nworld, nu] and dloss [nworld] in; loss [nworld],
+        grad_qvel0 [nworld, nv] and grad_ctrl [horizon, nworld, nu] out."""
+        if len(self.models) != 1:
+            raise ValueError("rollouts take a single-model batch")
+        nw, nv, nu = self.counts[0], self.models[0].nv, self.models[0].nu
+        if (ctrl is None or ctrl.numel() != horizon * nw * nu or loss.numel() != nw
+                or dloss.numel() != nw or grad_qvel0.numel() != nw * nv
+                or grad_ctrl.numel() != horizon * nw * nu):
+            raise ValueError(f"ctrl [{horizon}, {nw}, {nu}], dloss and loss [{nw}], "
+                             f"grad_qvel0 [{nw}, {nv}], grad_ctrl [{horizon}, {nw}, {nu}] "
+                             "expected")
+        self.ctx.check(mjh_rollout_noalloc(self._h, int(horizon), int(ckpt_every), _ptr(ctrl),
+                                           int(zidx), float(ztarget), float(wctrl),
+                                           _ptr(dloss), _ptr(loss), _ptr(grad_qvel0),
+                                           _ptr(grad_ctrl), _stream(stream)))
 
 
 # ------------------------------------------------------------------ convenience
