@@ -15,9 +15,14 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -fno-hip-fp32-correctly-rounded-divide-sqrt: FP32 division and square root within a
 # few ulp (v_rcp/v_sqrt based) instead of the correctly rounded ~10-instruction
 # sequences; pivots and line-search ratios sit on per-column dependency chains.
+# -disable-machine-licm: the machine-level loop-invariant motion hoisted constants and
+# address arithmetic out of the per-world step loop and held them in VGPRs for the
+# whole launch; the step kernel then spilled 22 VGPRs (100 B/lane of scratch).  Without
+# it the constants are rematerialised where used: 2 VGPR spills, +3 % world-steps/s.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+         "-mllvm", "-disable-machine-licm",
          "-Wall", "-Wno-unused-function"]
 
 

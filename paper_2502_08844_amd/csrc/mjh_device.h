@@ -258,6 +258,12 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* 
     cvel[t.lane] = 0.f;
     cacc[t.lane] = t.lane < 3 ? 0.f : -m.grav[t.lane - 3];
   }
+  // Positions are relative to the origin p0, the first joint's position when it is a
+  // free joint (else the world origin): the world body sits at -p0.  The step is
+  // translation invariant, and spatial inertias taken at an origin near the bodies keep
+  // their rotational part, which FP32 rounds away against m |c|^2 far from the origin.
+  if (t.lane < 3)
+    xpos[t.lane] = (m.njnt > 0 && m.jnt_type[0] == JNT_FREE) ? -qpos[m.jnt_qposadr[0] + t.lane] : 0.f;
   t.sync();
   for (int lv = 1; lv < m.nlevel; lv++) {
     const int e = m.level_start[lv + 1];
@@ -280,7 +286,7 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* 
           float inv = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
           for (int k = 0; k < 4; k++) q[k] *= inv;
           quat_to_mat(q, R);
-          for (int k = 0; k < 3; k++) pos[k] = qpos[qa + k];
+          for (int k = 0; k < 3; k++) pos[k] = qpos[qa + k] + xpos[k];  // relative to p0
           for (int i = 0; i < 3; i++) {
             float* s = S + 6 * i;
             s[0] = s[1] = s[2] = 0.f;
@@ -1257,6 +1263,13 @@ DEV float row_slope(float D, float F, float e) {  // s'(e), D min(0, e) or clamp
 DEV bool row_quad(float D, float F, float e) {  // on the quadratic piece: curvature D
   return F == 0.f ? e < 0.f : fabsf(D * e) < F;
 }
+// which piece of its cost a row is on: 1 quadratic; 0 inactive (one-sided row) or the
+// friction bound -F; 2 the bound +F
+DEV int row_piece(float D, float F, float e) {
+  if (F == 0.f) return e < 0.f ? 1 : 0;
+  const float v = D * e;
+  return v >= F ? 2 : (v <= -F ? 0 : 1);
+}
 
 // --------------------------------------------------- A9: Newton solve (NW ch. 3, 6)
 // Loops over all constraint rows run to a wave-uniform bound (the largest row count
@@ -1552,6 +1565,10 @@ DEV void cholesky_back(const DevModel& m, float* W, const Team& t, const float* 
 // friction-loss rows (two breakpoints each, Huber pieces) or two-sided equality rows
 // (quadratic everywhere, no breakpoint); without them every row is one-sided and the
 // loops keep their shorter form.
+// Newton stops before its iteration count when the last step stayed on one piece of
+// every row's cost and its refinement correction was below this fraction of max(1,
+// max |a|): the iterate is then the minimiser up to FP32 rounding.
+constexpr float kNewtonExitTol = 1e-6f;
 template <bool FR>
 DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, int iters,
                      float gtol) {
@@ -1634,6 +1651,32 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
     // ---- delta = -H^-1 g: forward solve fused into the factorisation, then back
     if (!hessian_cholesky(m, W, t, nru, d, tmp)) { status |= 4; break; }
     cholesky_back(m, W, t, tmp, d);
+    // ---- one step of iterative refinement: the FP32 factor of H carries a relative
+    // error near cond(H) eps into d, and the fixed iteration count leaves the iterate
+    // mid-path, where such errors compound.  The residual r = g + H d, with H applied
+    // unassembled (M d + sum over rows on their quadratic piece of D J^T (J d)), is
+    // accurate to the gradient's own rounding; d -= H^-1 r with the same factor.
+    for (int r = t.lane; r < nru; r += t.T) {
+      float v = 0.f;
+      for (int i = 0; i < nv; i++) v += J[r * nv + i] * d[i];
+      const bool q = FR ? row_quad(D[r], fl[r], e[r]) : e[r] < 0.f;
+      s[r] = q ? D[r] * v : 0.f;
+    }
+    t.sync();
+    for (int i = t.lane; i < nv; i += t.T) {
+      float v = g[i];
+      for (int k = 0; k < nv; k++) v += M[sym(i, k)] * d[k];
+      for (int r = 0; r < nru; r++) v += s[r] * J[r * nv + i];
+      tmp[i] = v;
+    }
+    t.sync();
+    cholesky_solve(m, W, t, tmp, tmp, 1.f);
+    float cmax = 0.f;  // size of the correction: the unrefined direction's error
+    for (int i = t.lane; i < nv; i += t.T) {
+      d[i] -= tmp[i];
+      cmax = fmaxf(cmax, fabsf(tmp[i]));
+    }
+    t.sync();
     // ---- line search quantities
     float gd = 0.f, dMd = 0.f, dMr = 0.f;
     for (int i = t.lane; i < nv; i += t.T) {
@@ -1700,9 +1743,29 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
     float al = -Ac / Bc;
     al = fminf(fmaxf(al, lo), hi);
     // ---- update
-    for (int i = t.lane; i < nv; i += t.T) { a[i] += al * d[i]; Mr[i] += al * Md[i]; }
-    for (int r = t.lane; r < nrow; r += t.T) e[r] += al * s[r];
+    float amax = 1.f;
+    for (int i = t.lane; i < nv; i += t.T) {
+      a[i] += al * d[i];
+      Mr[i] += al * Md[i];
+      amax = fmaxf(amax, fabsf(a[i]));
+    }
+    int moved = 0;  // some row changed piece between 0 and al
+    for (int r = t.lane; r < nrow; r += t.T) {
+      const float e1 = e[r] + al * s[r];
+      moved |= FR ? (row_piece(D[r], fl[r], e[r]) != row_piece(D[r], fl[r], e1))
+                  : ((e[r] < 0.f) != (e1 < 0.f));
+      e[r] = e1;
+    }
+    // Exact optimum: when no row changed piece, the step stayed on the piece the Hessian
+    // was built for, where F is that quadratic; a + al d is its minimiser (al = 1 up to
+    // rounding) and the gradient there vanishes, so further iterations only reduce the
+    // FP32 error of this step, which is about cond(H) eps |d|.  Stop once that error is
+    // known small: the refinement's correction, the unrefined direction's error, is
+    // below kNewtonExitTol max(1, max |a|).
+    moved = t.ior(moved);
+    const float cm = t.max(cmax), am = t.max(amax);
     t.sync();
+    if (!moved && cm <= kNewtonExitTol * am) break;
   }
 }
 DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int iters,
@@ -1731,6 +1794,7 @@ DEV void export_contacts(const DevModel& m, float* W, const Team& t, float* out,
     }
     float* o = out + kConOut * c;
     for (int k = 0; k < 13; k++) o[k] = r[k];
+    for (int k = 0; k < 3; k++) o[1 + k] = r[1 + k] - W[m.o_xpos + k];  // world position
     o[13] = fn;  // the normal force sums every edge; torsion and rolling are not exported
     o[14] = r[13] * (f[0] - f[1]);
     o[15] = r[13] * (f[2] - f[3]);

@@ -12,6 +12,7 @@ import torch
 
 import oracle
 from paper_2502_08844_amd.synth import inputs, robots
+from tests.gpu_util import directional_check
 
 pytestmark = pytest.mark.gpu
 
@@ -100,12 +101,12 @@ def test_gradient_directional_vs_dual_numbers():
     dv = rng.normal(size=(nw, m.nv))
     du = rng.normal(size=(H, nw, m.nu))
     Lr, dL = o.rollout_jvp(qp, qv, u, dv, du, mode=oracle.MODE_CONVERGED, nthreads=16)
-    g_dot = np.sum(gq * dv, axis=1) + np.einsum("twa,twa->w", gu, du)
-    rel = np.abs(g_dot - dL) / np.maximum(np.abs(dL), 1e-6 * np.abs(dL).max())
-    print(f"[adjoint] <grad, d> vs dual JVP: rel err max {rel.max():.2e} median "
-          f"{np.median(rel):.2e} (p90 {np.percentile(rel, 90):.2e})", flush=True)
-    assert np.median(rel) < GRAD_TOL
-    assert np.percentile(rel, 90) < 1e-2
+    rel, smooth = directional_check(o, qp, qv, u, gq, gu, dv, du, dL)
+    print(f"[adjoint] <grad, d> vs dual JVP, error / (|grad| |d|): max {rel[smooth].max():.2e} "
+          f"median {np.median(rel[smooth]):.2e} over {smooth.sum()}/{nw} smooth worlds; "
+          f"non-smooth worlds' err {np.round(rel[~smooth], 5).tolist()}", flush=True)
+    assert smooth.sum() >= 0.9 * nw
+    assert rel[smooth].max() < GRAD_TOL
 
 
 def test_rollout_rejects_unsupported_contacts():

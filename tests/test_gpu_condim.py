@@ -6,12 +6,9 @@ rolling friction (condim 6, ten edges).
   other parity tests);
 * a box on a plane tilted by 0.4 rad accelerates down the slope at g sin(theta), with
   no tangential contact force;
-* the quadruped with torsional / rolling friction at the feet (condim 4 / 6): the 99th
-  percentile of qacc errors within the usual 1e-4, and outliers bounded (qacc 5e-4,
-  contact force 2e-3, relative to m g).  The spin and rolling edges put mu omega of the
-  light legs' rotation into stiff normal rows, and in rare states the four fixed FP32
-  Newton iterations carry that rounding further than elsewhere; the isolated rows
-  (spinning spheres) meet the usual tolerances;
+* the quadruped with torsional / rolling friction at the feet (condim 4 / 6) at the
+  usual tolerances (qacc 1e-4, contact force 1e-3 relative to m g) in every world not
+  at a switch;
 * spinning spheres on a plane with torsional friction (one step from many states);
 * rollouts reject frictionless pairs.
 """
@@ -40,7 +37,7 @@ def test_frictionless_quadruped_parity(lib, team, block):
                               [0, 5, 50], seed=3, team=team, block=block)
     ea, ef, nflag, ntot = summarize(f"quadruped_frictionless-T{team}", stats)
     assert ea.max() <= 1e-4 and ef.size > 0 and ef.max() <= 1e-3
-    assert nflag <= 0.25 * ntot
+    assert nflag <= max(1, 0.02 * ntot)
     for s in stats:
         gc = s["gpu_contacts"]
         assert np.abs(gc[:, :, 14:16]).max() == 0
@@ -56,9 +53,9 @@ def test_torsion_rolling_quadruped_parity(lib, kind, team, block):
     m, stats = teacher_forced(ctx, mjh, kind, 203 if team is None else 77, [0, 5, 50],
                               seed=4, team=team, block=block)
     ea, ef, nflag, ntot = summarize(f"{kind}-T{team}", stats)
-    assert np.percentile(ea, 99) <= 1e-4 and ea.max() <= 5e-4
-    assert ef.size > 0 and np.percentile(ef, 99) <= 1e-3 and ef.max() <= 2e-3
-    assert nflag <= 0.25 * ntot
+    assert ea.max() <= 1e-4
+    assert ef.size > 0 and ef.max() <= 1e-3
+    assert nflag <= max(1, 0.02 * ntot)
 
 
 def test_spinning_spheres_torsion(lib):
@@ -84,7 +81,7 @@ def test_spinning_spheres_torsion(lib):
           f"force max {cmp['err_f'][ok].max():.2e}, flagged {int(cmp['flag'].sum())}",
           flush=True)
     assert cmp["err_a"][ok].max() <= 1e-4 and cmp["err_f"][ok].max() <= 1e-3
-    assert cmp["flag"].sum() <= 0.25 * nw
+    assert cmp["flag"].sum() <= 0.02 * nw
 
 
 def test_frictionless_box_on_incline(lib):

@@ -9,8 +9,8 @@ Checks, on the quadruped from contact-rich states with a share of inverted world
   action, the others keep the new state and remember the action;
 * several env steps in one launch give the outputs of as many single launches;
 * end to end against the reference env step from the same float32 state (FP32 against
-  FP64 physics over nsub steps): done identical, obs within 1e-3 (1 + |x|) for the
-  median world;
+  FP64 physics over nsub steps): done identical, obs within 1e-4 (1 + |x|) in every
+  world;
 * models without a free root and per-dof position actuators are rejected, and so are
   nenv 0, nsub 0 and per-world parameters on an implicit model, leaving every buffer;
 * domain randomisation: identity records and zero noise change no bit; with random
@@ -149,7 +149,7 @@ def test_env_step_against_reference_env(lib):
     err = (np.abs(g["obs"][0] - obs) / (1 + np.abs(obs))).max(1)
     print(f"[gpu] env obs vs FP64 env: median {np.median(err):.1e} max {err.max():.1e}",
           flush=True)
-    assert np.median(err) <= 1e-3
+    assert err.max() <= 1e-4
     np.testing.assert_array_equal(g["last_action"], pa.astype(np.float32))
 
 
@@ -223,7 +223,7 @@ def test_randomised_physics_step_parity(lib):
         er = max(er, abs(g["reward"][0, w] - r_ref) / (1 + abs(r_ref)))
     print(f"[gpu] randomised qacc rel err max {err[~flag].max():.2e} median {np.median(err):.2e};"
           f" near-switch {flag.sum()}/{nw}; obs err {eo:.1e} reward err {er:.1e}", flush=True)
-    assert err[~flag].max() <= 1e-4 and flag.sum() <= 0.25 * nw
+    assert err[~flag].max() <= 1e-4 and flag.sum() <= max(1, 0.02 * nw)
     assert eo <= OUT_TOL and er <= OUT_TOL
 
 
@@ -243,7 +243,7 @@ def test_randomised_env_step_against_reference_env(lib):
     err = (np.abs(g["obs"][0] - obs) / (1 + np.abs(obs))).max(1)
     print(f"[gpu] randomised env obs vs FP64 env: median {np.median(err):.1e} "
           f"max {err.max():.1e}", flush=True)
-    assert np.median(err) <= 1e-3
+    assert err.max() <= 1e-4
     np.testing.assert_array_equal(g["last_action"], pa.astype(np.float32))
 
 

@@ -34,7 +34,7 @@ def _check(kind, stats):
     assert ea.max() <= QACC_TOL
     if ef.size:
         assert ef.max() <= FORCE_TOL
-    assert nflag <= 0.25 * ntot
+    assert nflag <= max(1, 0.02 * ntot)
 
 
 def _states(m, nw, rng):

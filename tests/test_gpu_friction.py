@@ -13,7 +13,8 @@ import torch
 
 import oracle
 from paper_2502_08844_amd.synth import inputs, robots
-from tests.gpu_util import compare_step, gpu_ctx, run_gpu, summarize, teacher_forced
+from tests.gpu_util import (compare_step, directional_check, gpu_ctx, run_gpu, summarize,
+                             teacher_forced)
 
 pytestmark = pytest.mark.gpu
 
@@ -31,7 +32,7 @@ def _check(kind, stats):
     assert ea.max() <= QACC_TOL
     if ef.size:
         assert ef.max() <= FORCE_TOL
-    assert nflag <= 0.25 * ntot
+    assert nflag <= max(1, 0.02 * ntot)
 
 
 def test_friction_model_dims(lib):
@@ -130,11 +131,12 @@ def test_adjoint_through_friction_rows_vs_dual_numbers(lib):
     du = np.random.default_rng(7).normal(size=(H, nw, m.nu))
     Lr, dL = o.rollout_jvp(qp, qv, u, dv, du, mode=oracle.MODE_CONVERGED, nthreads=16)
     rel_loss = np.abs(L - Lr) / np.abs(Lr)
-    g_dot = np.sum(gq * dv, axis=1) + np.einsum("twa,twa->w", gu, du)
-    rel = np.abs(g_dot - dL) / np.maximum(np.abs(dL), 1e-6 * np.abs(dL).max())
-    print(f"[adjoint-friction] loss rel err max {rel_loss.max():.2e}; <grad, d> vs dual JVP "
-          f"rel err median {np.median(rel):.2e} p90 {np.percentile(rel, 90):.2e}", flush=True)
+    rel, smooth = directional_check(o, qp, qv, u, gq, gu, dv, du, dL)
+    print(f"[adjoint-friction] loss rel err max {rel_loss.max():.2e}; <grad, d> vs dual JVP, error / "
+          f"(|grad| |d|): max {rel[smooth].max():.2e} median {np.median(rel[smooth]):.2e} over "
+          f"{smooth.sum()}/{nw} smooth worlds; non-smooth worlds' err "
+          f"{np.round(rel[~smooth], 5).tolist()}", flush=True)
     assert np.all(np.isfinite(gq)) and np.all(np.isfinite(gu))
     assert rel_loss.max() < 1e-3
-    assert np.median(rel) < 1e-3
-    assert np.percentile(rel, 90) < 1e-2
+    assert smooth.sum() >= 0.9 * nw
+    assert rel[smooth].max() < 1e-3

@@ -53,7 +53,7 @@ def _check(kind, m, state, u1, gpu1, idx):
     assert ea.max() <= QACC_TOL
     if ef.size:
         assert ef.max() <= FORCE_TOL
-    assert nflag <= 0.25 * ntot
+    assert nflag <= max(1, 0.02 * ntot)
 
 
 def _one_step(w, mjh, u1):

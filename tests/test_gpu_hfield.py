@@ -29,7 +29,7 @@ def _check(kind, stats, min_contacts=1):
     assert ea.max() <= QACC_TOL
     assert ef.size >= min_contacts
     assert ef.max() <= FORCE_TOL
-    assert nflag <= 0.25 * ntot
+    assert nflag <= max(1, 0.02 * ntot)
 
 
 def test_single_step_parity_quadruped_rough(lib):

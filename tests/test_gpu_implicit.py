@@ -7,11 +7,9 @@ one step from the same float32 state (the reported qacc is the solve's a*, cover
 the other parity tests), per world ||a_int,gpu - a_int,ref||_inf / max(||a_int,ref||_inf,
 9.81), on worlds not at a contact or activation switch (those are counted and reported).
 
-Tolerance 1e-3, ten times the qacc tolerance, with a median below 1e-5: a_int =
-(M + h B)^-1 (qfrc_smooth + J^T f) takes the row forces f of the fixed-iteration solve,
-so a difference d in a* (FP32 against FP64 iterates, up to 1e-4 of |a*|) reaches a_int
-as (M + h B)^-1 J^T D J d, and D J^T J outweighs the light leg links' inertia by about
-an order of magnitude in the violent random-target states compared here.
+Tolerance 1e-4, the qacc tolerance, in every world not at a switch, with a median
+below 1e-5: a_int = (M + h B)^-1 (qfrc_smooth + J^T f) takes the row forces f of the
+fixed-iteration solve.
 """
 import numpy as np
 import pytest
@@ -23,7 +21,7 @@ from tests.gpu_util import G, compare_step, gpu_ctx, run_gpu, workload
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-3
+TOL = 1e-4
 TOL_MEDIAN = 1e-5
 
 
@@ -64,7 +62,7 @@ def test_quadruped_implicit_velocity_update(lib, kind, team, block):
     assert np.all(g["status"] & 1 == 0)
     assert err[~flag].max() <= TOL
     assert np.median(err) <= TOL_MEDIAN
-    assert flag.sum() <= 0.25 * len(flag)
+    assert flag.sum() <= max(1, 0.02 * len(flag))
 
 
 def test_stiff_damping_decays_on_gpu(lib):

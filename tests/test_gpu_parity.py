@@ -49,7 +49,7 @@ def test_single_step_parity(lib, kind, nw, ckpts):
     assert ea.max() <= QACC_TOL
     if ef.size:
         assert ef.max() <= FORCE_TOL
-    assert nflag <= 0.25 * ntot
+    assert nflag <= max(1, 0.02 * ntot)
 
 
 def test_trajectory_and_status_and_determinism(lib):

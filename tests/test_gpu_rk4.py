@@ -5,10 +5,8 @@ forward pass at four stages) against the FP64 reference.
   GPU's state against the reference's at FP32 accuracy;
 * the quadruped from contact-rich states at 32- and 16-lane teams: the reported qacc
   (the first stage's) is the Euler step's from the same state bit for bit, and the
-  step's average acceleration (qdot' - qdot) / h is within 1e-3 of max(|a|, g) per
-  world with a median below 1e-5 (as for the implicit integrators: the later stages
-  carry the solve's FP32 differences through the stage states).  The first stage
-  against the reference is printed; its gate is that of the Euler parity tests;
+  step's average acceleration (qdot' - qdot) / h is within 1e-4 of max(|a|, g) per
+  world with a median below 1e-5, and the first stage's qacc within 1e-4;
 * rollouts reject the integrator;
 * the Runge-Kutta instantiations of the env kernel and of a batch mixing Euler and
   Runge-Kutta groups reproduce the separate launches.
@@ -71,8 +69,9 @@ def test_rk4_quadruped_parity(lib, team, block):
           f"step acceleration max {err[~flag].max():.2e} median {np.median(err):.2e}; "
           f"near-switch {flag.sum()}/{len(flag)}", flush=True)
     assert np.all(g["status"] & 1 == 0)
-    assert err[~flag].max() <= 1e-3 and np.median(err) <= 1e-5
-    assert flag.sum() <= 0.25 * len(flag)
+    assert ea[~flag].max() <= 1e-4
+    assert err[~flag].max() <= 1e-4 and np.median(err) <= 1e-5
+    assert flag.sum() <= max(1, 0.02 * len(flag))
 
 
 def test_rollout_rejects_rk4(lib):
