@@ -18,11 +18,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP32 vector ceiling of this code: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
-# The published 157.3 TFLOP/s counts packed FP32 (two FMAs per lane), which this build
-# disables.
-FP32_VECTOR_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6
+# MI355X's published FP32 vector peak (it counts packed FP32, two FMAs per lane and
+# cycle) is the roofline's peak.  This build disables packed FP32, so its own ceiling is
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s, reported beside.
 FP32_PUBLISHED_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6
+QACC_TOL, FORCE_TOL, GRAD_TOL = 1e-4, 1e-3, 1e-3
 HBM_PEAK_GBS = 8000.0             # MI355X published HBM3E bandwidth
 PROFILE = os.path.join(ROOT, "profiles", "mjh_step_kernel_quadruped_8192x1000.txt")
 PROFILED = (8192, 1000)           # nworld, nstep of the committed counter profile
@@ -76,7 +77,8 @@ def parse():
     ap.add_argument("--nworld", type=int, default=8192)
     ap.add_argument("--nstep", type=int, default=1000)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the host leg (FP64 reference: parity, FLOP count, CPU rate)")
     ap.add_argument("--cpu-sample-worlds", type=int, default=8192)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="run the reference on the host in chunks of 40 steps until this "
@@ -97,33 +99,151 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_flops_per_world_step(model, qpos, qvel, ctrl):
-    """Floating-point operations of the reference algorithm per world-step, counted by
-    running the FP64 reference with an operation-counting scalar on sampled states."""
-    import oracle
-    o = oracle.Oracle(model)
-    return o.count_flops(qpos, qvel, None, ctrl)
+def host_cpu():
+    """(CPU model, CPUs the host reports, threads the reference may use).  The threads
+    are the CPUs this process may run on, capped by OMP_NUM_THREADS when it is set (a
+    GPU machine's share of its host's cores)."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0))
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return name, os.cpu_count(), min(avail, share) if share > 0 else avail
 
 
-def cpu_baseline(kind, model, qpos, qvel, nthreads, seconds, seed, chunk=40, max_chunks=200):
-    """The FP64 reference stepping the same kind of worlds on the host: chunks of `chunk`
-    steps with fresh controls, state carried over, until `seconds` have been spent."""
+def gpu_states(ctx, kind, nw, warm, seed):
+    """nw worlds of `kind` advanced `warm` steps on the GPU from the seeded initial state
+    with random controls; returns the model, the float32 state (as float64) and the
+    control of the next step."""
+    import torch
+    from paper_2502_08844_amd import mjh
+    from paper_2502_08844_amd.synth import inputs, robots
+    m = robots.WORKLOADS[kind]()
+    qp, qv = inputs.initial_state(kind, m, nw, seed=seed)
+    u = inputs.controls(kind, m, nw, warm + 1, seed=seed)
+    w = mjh.World(ctx, m, nw, qpos=qp, qvel=qv)
+    w.step(torch.tensor(u[:warm], dtype=torch.float32, device="cuda"), nstep=warm)
+    torch.cuda.synchronize()
+    st = [x.cpu().double().numpy() for x in (w.qpos, w.qvel, w.qacc_ws)]
+    return m, w, st, u[warm:warm + 1]
+
+
+def step_parity(ctx, o, kind, nw=64, warm=50, seed=0):
+    """One GPU step against one reference step (fixed iteration count) from the same
+    float32 states after `warm` GPU steps: per world ||qacc_gpu - qacc_ref||_inf /
+    max(||qacc_ref||_inf, 9.81), and each contact's frame force error / (total mass *
+    9.81).  Worlds whose contact sets differ, or with a contact within 1e-5 of its
+    emission distance, sit at a switch: they are counted, not included."""
+    import numpy as np
+    import torch
+    m, w, (q, v, a), u1 = gpu_states(ctx, kind, nw, warm, seed)
+    con, ncon = w.step(torch.tensor(u1, dtype=torch.float32, device="cuda"), nstep=1,
+                       contacts=True)
+    torch.cuda.synchronize()
+    ga, gc, gn = (w.qacc_ws.cpu().double().numpy(), con.cpu().double().numpy(),
+                  ncon.cpu().numpy())
+    ref = o.step(q, v, a, u1, nstep=1, nthreads=8)
+    mass = sum(b.mass for b in m.bodies)
+    ea, ef, nsw = [], [], 0
+    for k in range(nw):
+        nr = int(ref["ncon"][k])
+        cr, cg = ref["contacts"][k, :nr], gc[k, :int(gn[k])]
+        if int(gn[k]) != nr or not np.array_equal(cr[:, 16:18], cg[:, 16:18]) or \
+                (nr and np.abs(cr[:, 0]).min() < 1e-5):
+            nsw += 1
+            continue
+        ea.append(np.abs(ga[k] - ref["qacc"][k]).max() / max(np.abs(ref["qacc"][k]).max(), 9.81))
+        if nr:
+            ef.append(np.abs(cg[:, 13:16] - cr[:, 13:16]).max() / (mass * 9.81))
+    return ({"qacc_max": float(f"{max(ea):.3g}"), "force_max": float(f"{max(ef):.3g}") if ef else 0.0,
+             "worlds": nw, "at_switch": nsw, "step": warm + 1},
+            (q, v, a, u1[0]))
+
+
+def adjoint_parity(ctx, o, nw=16, horizon=64, ckpt=8, seed=0):
+    """The GPU rollout gradient (wrt qvel0 and the 64 x 12 controls) along one random
+    direction per world against the reference's exact directional derivative (dual
+    numbers, solver converged): |<g, d> - dL| / (|g| |d|)."""
+    import numpy as np
+    import torch
+    from paper_2502_08844_amd import mjh
+    from paper_2502_08844_amd.synth import inputs, robots
+    m = robots.quadruped()
+    qp, qv = inputs.initial_state("quadruped", m, nw, seed=seed)
+    rng = inputs.rng(seed, 7)
+    qv = inputs.f32(qv + rng.normal(scale=0.1, size=qv.shape))
+    u = inputs.f32(rng.uniform(-0.5, 0.5, size=(horizon, nw, m.nu)))
+    w = mjh.World(ctx, m, nw, qpos=qp)
+    qv0 = torch.tensor(qv, dtype=torch.float32, device="cuda", requires_grad=True)
+    ut = torch.tensor(u, dtype=torch.float32, device="cuda", requires_grad=True)
+    mjh.Rollout.apply(qv0, ut, w, horizon, ckpt).sum().backward()
+    torch.cuda.synchronize()
+    gq, gu = qv0.grad.cpu().double().numpy(), ut.grad.cpu().double().numpy()
+    dv = rng.normal(size=(nw, m.nv))
+    du = rng.normal(size=(horizon, nw, m.nu))
     import oracle
-    from paper_2502_08844_amd.synth import inputs
-    o = oracle.Oracle(model)
-    nw = qpos.shape[0]
-    q, v, ws = qpos.copy(), qvel.copy(), None
-    spent, steps = 0.0, 0
-    for c in range(max_chunks):
-        u = inputs.controls(kind, model, nw, chunk, seed=seed + 1000 + c)
-        t0 = time.perf_counter()
-        out = o.step(q, v, ws, u, nstep=chunk, nthreads=nthreads)
-        spent += time.perf_counter() - t0
-        steps += chunk
-        q, v, ws = out["qpos"], out["qvel"], out["qacc_ws"]
-        if spent >= seconds:
-            break
-    return nw * steps / spent, spent, steps
+    _, dL = o.rollout_jvp(qp, qv, u, dv, du, mode=oracle.MODE_CONVERGED, nthreads=8)
+    g_dot = np.sum(gq * dv, axis=1) + np.einsum("twa,twa->w", gu, du)
+    gn = np.sqrt(np.sum(gq * gq, 1) + np.einsum("twa,twa->w", gu, gu))
+    dn = np.sqrt(np.sum(dv * dv, 1) + np.einsum("twa,twa->w", du, du))
+    rel = np.abs(g_dot - dL) / (gn * dn)
+    return {"directional_max": float(f"{rel.max():.3g}"), "worlds": nw, "horizon": horizon,
+            "ckpt_every": ckpt}
+
+
+def host_leg(ctx, kind, m, qp, qv, seconds, seed, single_seconds=4.0, chunk=40,
+             max_chunks=200):
+    """Everything that runs the FP64 reference (the oracle), on the host, outside the
+    timed GPU region:
+    * parity: one GPU step against one reference step for every workload's model
+      (cartpole, quadruped, humanoid, hand: the heterogeneous batch runs the same
+      per-world kernels) and the adjoint rollout's gradient against dual numbers;
+    * the algorithmic FLOP count per world-step on the quadruped's sampled states;
+    * the reference's own rate on a bounded sample of the benched workload: chunks of
+      `chunk` steps with fresh controls until `seconds` are spent, at the threads the
+      host grants, and on one thread for `single_seconds`."""
+    import oracle
+    from paper_2502_08844_amd.synth import inputs, robots
+    parity = {"tolerance": {"qacc": QACC_TOL, "force": FORCE_TOL, "gradient": GRAD_TOL}}
+    flops = None
+    for k in ("cartpole", "quadruped", "humanoid", "hand"):
+        o = oracle.Oracle(robots.WORKLOADS[k]())
+        parity[k], (q, v, a, u1) = step_parity(ctx, o, k, seed=seed)
+        if k == kind or (flops is None and k == "quadruped"):
+            flops = {"nonzero": o.count_flops(q, v, a, u1, nonzero=True),
+                     "dense": o.count_flops(q, v, a, u1)}
+    parity["adjoint"] = adjoint_parity(ctx, oracle.Oracle(robots.quadruped()), seed=seed)
+    name, ncpu, nthreads = host_cpu()
+    o = oracle.Oracle(m)
+    rates = {}
+    for threads, budget, nw in ((nthreads, seconds, qp.shape[0]),
+                                (1, single_seconds, min(qp.shape[0], 1024))):
+        q, v, ws = qp[:nw].copy(), qv[:nw].copy(), None
+        spent, steps = 0.0, 0
+        for c in range(max_chunks):
+            u = inputs.controls(kind, m, nw, chunk, seed=seed + 1000 + c)
+            t0 = time.perf_counter()
+            out = o.step(q, v, ws, u, nstep=chunk, nthreads=threads)
+            spent += time.perf_counter() - t0
+            steps += chunk
+            q, v, ws = out["qpos"], out["qvel"], out["qacc_ws"]
+            if spent >= budget:
+                break
+        rates[threads] = (nw * steps / spent, spent, steps, nw)
+    r, r1 = rates[nthreads], rates[1]
+    cpu = {"value": round(r[0], 1), "unit": "world-steps/s", "cores": nthreads, "kind": "oracle",
+           "sample": f"{r[3]} {kind} worlds x {r[2]} steps (chunks of {chunk}, fresh random "
+                     f"controls), FP64, {r[1]:.1f} s on {nthreads} threads",
+           "single_thread_value": round(r1[0], 1),
+           "single_thread_sample": f"{r1[3]} worlds x {r1[2]} steps, {r1[1]:.1f} s",
+           "cpu_model": name, "host_cpus": ncpu}
+    return cpu, parity, flops
 
 
 def timed(fn, stream, reps):
@@ -414,19 +534,14 @@ def main():
     ms_per_step = 1000.0 * wall / args.steps
     kavg = float(np.mean(kern_ms))
 
-    # roofline of the step kernel: plain FP32 ALU work (no MFMA, not HBM bound)
-    sample = min(nw, 64)
-    flops_ws = algorithmic_flops_per_world_step(m, qp[:sample], qv[:sample],
-                                                inputs.controls(kind, m, sample, 1, seed=1))
-    achieved_tf = flops_ws * nw * ns / (kavg * 1e-3) / 1e12
+    # roofline of the step kernel: plain FP32 ALU work (no MFMA, not HBM bound); the
+    # algorithmic FLOP count comes from the host leg below
     bytes_ws = algo_bytes(m.nu, m.nq, m.nv, ns)
-    roof = {"bound": "alu", "achieved": round(achieved_tf, 4),
-            "peak": round(FP32_VECTOR_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-            "frac": round(achieved_tf / FP32_VECTOR_PEAK_TFLOPS, 6),
-            "traffic": profiled_traffic(kind, nw, ns),
-            "published_fp32_peak_packed": FP32_PUBLISHED_PEAK_TFLOPS,
+    roof = {"bound": "alu", "achieved": None, "peak": FP32_PUBLISHED_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": None, "traffic": profiled_traffic(kind, nw, ns),
+            "peak_nonpacked": round(FP32_NONPACKED_PEAK_TFLOPS, 1), "frac_nonpacked": None,
             "kernel": "mjh_step_kernel", "kernel_ms": round(kavg, 3),
-            "flops_per_world_step": round(flops_ws, 1),
+            "flops_per_world_step": None, "flops_per_world_step_dense": None,
             "hbm_bytes_per_world_step": round(bytes_ws, 2),
             "hbm_frac": round(bytes_ws * nw * ns / (kavg * 1e-3) / 1e9 / HBM_PEAK_GBS, 8)}
     metric = ("world-steps/sec at 8192 quadruped worlds; fwd+bwd rollout steps/sec vs plain"
@@ -482,16 +597,19 @@ def main():
             "fourth-order Runge-Kutta (four forward passes a step)")
         out["rough_terrain"] = constraint_compare(
             ctx, args.seed, "quadruped_rough",
-            "its feet on 4 m x 4 m Perlin-noise terrain (64 x 64 heightfield, 6 cm relief)")
+            "its feet on 8 m x 8 m Perlin-noise terrain (128 x 128 heightfield, 6 cm relief)")
     if not args.no_cpu_baseline:
-        nthreads = min(os.cpu_count() or 1, 16)
-        cw = min(args.cpu_sample_worlds, nw)
-        rate, secs, cs = cpu_baseline(kind, m, qp[:cw], qv[:cw], nthreads, args.cpu_seconds,
+        cpu, parity, flops = host_leg(ctx, kind, m, qp[:min(args.cpu_sample_worlds, nw)],
+                                      qv[:min(args.cpu_sample_worlds, nw)], args.cpu_seconds,
                                       args.seed)
-        out["cpu_baseline"] = {"value": round(rate, 1), "unit": "world-steps/s",
-                               "cores": nthreads, "kind": "oracle",
-                               "sample": f"{cw} {kind} worlds x {cs} steps (chunks of 40, "
-                                         f"fresh random controls), FP64, {secs:.1f} s"}
+        achieved = flops["nonzero"] * nw * ns / (kavg * 1e-3) / 1e12
+        roof.update({"achieved": round(achieved, 4),
+                     "frac": round(achieved / FP32_PUBLISHED_PEAK_TFLOPS, 6),
+                     "frac_nonpacked": round(achieved / FP32_NONPACKED_PEAK_TFLOPS, 6),
+                     "flops_per_world_step": round(flops["nonzero"], 1),
+                     "flops_per_world_step_dense": round(flops["dense"], 1)})
+        out["parity"] = parity
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -78,18 +78,27 @@ inline double val(Dual x) { return x.v; }
 
 // ------------------------------------------------------- operation-counting scalar
 // Counts floating-point operations (+ - * / and elementary functions, one each) of the
-// reference algorithm; used to report the algorithmic work of one step.
+// reference algorithm; used to report the algorithmic work of one step.  g_flops counts
+// every operation of these plain dense loops; g_flops_nz only those whose operands are
+// all nonzero: a product with an exact zero (a structural zero of the dense Jacobian or
+// mass matrix, an inactive row's force) and a sum with an exact zero are free to an
+// implementation that skips them, so g_flops_nz is the algorithmic count.
 thread_local long long g_flops = 0;
+thread_local long long g_flops_nz = 0;
 struct Cnt {
   double v = 0.0;
   Cnt() = default;
   Cnt(double x) : v(x) {}  // NOLINT: implicit on purpose
 };
-inline Cnt operator+(Cnt a, Cnt b) { g_flops++; return Cnt(a.v + b.v); }
-inline Cnt operator-(Cnt a, Cnt b) { g_flops++; return Cnt(a.v - b.v); }
+inline void count_op(double a, double b) {
+  g_flops++;
+  if (a != 0.0 && b != 0.0) g_flops_nz++;
+}
+inline Cnt operator+(Cnt a, Cnt b) { count_op(a.v, b.v); return Cnt(a.v + b.v); }
+inline Cnt operator-(Cnt a, Cnt b) { count_op(a.v, b.v); return Cnt(a.v - b.v); }
 inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
-inline Cnt operator*(Cnt a, Cnt b) { g_flops++; return Cnt(a.v * b.v); }
-inline Cnt operator/(Cnt a, Cnt b) { g_flops++; return Cnt(a.v / b.v); }
+inline Cnt operator*(Cnt a, Cnt b) { count_op(a.v, b.v); return Cnt(a.v * b.v); }
+inline Cnt operator/(Cnt a, Cnt b) { count_op(a.v, 1.0); return Cnt(a.v / b.v); }
 inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
 inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
 inline Cnt& operator*=(Cnt& a, Cnt b) { a = a * b; return a; }
@@ -100,11 +109,11 @@ inline bool operator<=(Cnt a, Cnt b) { return a.v <= b.v; }
 inline bool operator>=(Cnt a, Cnt b) { return a.v >= b.v; }
 inline bool operator==(Cnt a, Cnt b) { return a.v == b.v; }
 inline bool operator!=(Cnt a, Cnt b) { return a.v != b.v; }
-inline Cnt sqrt(Cnt a) { g_flops++; return Cnt(std::sqrt(a.v)); }
-inline Cnt sin(Cnt a) { g_flops++; return Cnt(std::sin(a.v)); }
-inline Cnt cos(Cnt a) { g_flops++; return Cnt(std::cos(a.v)); }
+inline Cnt sqrt(Cnt a) { count_op(a.v, 1.0); return Cnt(std::sqrt(a.v)); }
+inline Cnt sin(Cnt a) { count_op(1.0, 1.0); return Cnt(std::sin(a.v)); }
+inline Cnt cos(Cnt a) { count_op(1.0, 1.0); return Cnt(std::cos(a.v)); }
 inline Cnt fabs(Cnt a) { return Cnt(std::fabs(a.v)); }
-inline Cnt pow(Cnt a, double p) { g_flops++; return Cnt(std::pow(a.v, p)); }
+inline Cnt pow(Cnt a, double p) { count_op(1.0, 1.0); return Cnt(std::pow(a.v, p)); }
 inline bool isfinite(Cnt a) { return std::isfinite(a.v); }
 inline double val(Cnt x) { return x.v; }
 
@@ -2066,11 +2075,12 @@ int mjo_trajectory(void* h, int nstep, const double* qpos, const double* qvel,
 
 extern "C" {
 // Average floating-point operation count of one step (fixed mode) from each of nworld
-// states, counted by the operation-counting scalar.
-double mjo_count_flops(void* h, int nworld, const double* qpos, const double* qvel,
-                       const double* qacc_ws, const double* ctrl) {
+// states, counted by the operation-counting scalar: every operation of the dense loops,
+// and, when nonzero_out is given, those whose operands are all nonzero (*nonzero_out).
+double mjo_count_flops2(void* h, int nworld, const double* qpos, const double* qvel,
+                        const double* qacc_ws, const double* ctrl, double* nonzero_out) {
   Model& m = *static_cast<Model*>(h);
-  long long total = 0;
+  long long total = 0, total_nz = 0;
   for (int w = 0; w < nworld; w++) {
     Data<Cnt> d;
     d.alloc(m);
@@ -2079,9 +2089,16 @@ double mjo_count_flops(void* h, int nworld, const double* qpos, const double* qv
     if (qacc_ws) for (int i = 0; i < m.nv; i++) d.qacc_ws[i] = qacc_ws[(size_t)w * m.nv + i];
     if (ctrl) for (int a = 0; a < m.nu; a++) d.ctrl[a] = ctrl[(size_t)w * m.nu + a];
     g_flops = 0;
+    g_flops_nz = 0;
     step(m, d, 0);
     total += g_flops;
+    total_nz += g_flops_nz;
   }
+  if (nonzero_out) *nonzero_out = nworld > 0 ? (double)total_nz / nworld : 0.0;
   return nworld > 0 ? (double)total / nworld : 0.0;
+}
+double mjo_count_flops(void* h, int nworld, const double* qpos, const double* qvel,
+                       const double* qacc_ws, const double* ctrl) {
+  return mjo_count_flops2(h, nworld, qpos, qvel, qacc_ws, ctrl, nullptr);
 }
 }  // extern "C"

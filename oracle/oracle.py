@@ -70,6 +70,8 @@ def _load():
         lib.mjo_trajectory.argtypes = [P, C.c_int, D, D, D, D, C.c_int, D, D, I]
         lib.mjo_count_flops.argtypes = [P, C.c_int, D, D, D, D]
         lib.mjo_count_flops.restype = C.c_double
+        lib.mjo_count_flops2.argtypes = [P, C.c_int, D, D, D, D, D]
+        lib.mjo_count_flops2.restype = C.c_double
         _lib = lib
     return _lib
 
@@ -262,14 +264,18 @@ class Oracle:
                                  mode, _d(tq), _d(tv), _i(st))
         return tq, tv, int(st[0])
 
-    def count_flops(self, qpos, qvel, qacc_ws=None, ctrl=None) -> float:
-        """Average floating-point operations of one reference step from each state.
-
-        ctrl is [nworld, nu] or [1, nworld, nu]."""
+    def count_flops(self, qpos, qvel, qacc_ws=None, ctrl=None, nonzero=False) -> float:
+        """Average floating-point operations of one reference step from each state: every
+        operation of the dense loops, or with nonzero=True those whose operands are all
+        nonzero (products and sums with an exact zero are free to a sparse
+        implementation).  ctrl is [nworld, nu] or [1, nworld, nu]."""
         qpos = np.array(qpos, dtype=np.float64, order="C", ndmin=2)
         qvel = np.array(qvel, dtype=np.float64, order="C", ndmin=2)
         nw = qpos.shape[0]
         ws = None if qacc_ws is None else np.ascontiguousarray(qacc_ws, dtype=np.float64)
         u = None if ctrl is None else np.ascontiguousarray(ctrl, dtype=np.float64).reshape(
             nw, self.nu)
-        return float(self._lib.mjo_count_flops(self._h, nw, _d(qpos), _d(qvel), _d(ws), _d(u)))
+        nz = np.zeros(1)
+        dense = float(self._lib.mjo_count_flops2(self._h, nw, _d(qpos), _d(qvel), _d(ws), _d(u),
+                                                 _d(nz)))
+        return float(nz[0]) if nonzero else dense

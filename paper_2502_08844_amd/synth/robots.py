@@ -554,9 +554,11 @@ def perlin_terrain(n: int = 64, cells: int = 8, octaves: int = 3, seed: int = 0)
     return out / max(out.max(), 1e-12)
 
 
-# rough terrain of the quadruped_rough workload: 4 m x 4 m, 64 x 64 samples (6.3 cm
-# spacing), 6 cm from the lowest to the highest point
-ROUGH_SIZE, ROUGH_N, ROUGH_HEIGHT = 2.0, 64, 0.06
+# rough terrain of the quadruped_rough workload: 8 m x 8 m, 128 x 128 samples (6.3 cm
+# spacing), 16 noise cells a side (50 cm features), 6 cm from the lowest to the highest
+# point.  Under random PD targets a quadruped wanders up to 2.8 m from the origin in
+# 1000 steps (4 s), so every world stays on the terrain.
+ROUGH_SIZE, ROUGH_N, ROUGH_CELLS, ROUGH_HEIGHT = 4.0, 128, 16, 0.06
 
 
 def quadruped_rough(seed: int = 0) -> Model:
@@ -564,7 +566,7 @@ def quadruped_rough(seed: int = 0) -> Model:
     instead of the floor plane (the paper's rough-terrain locomotion setting)."""
     m = quadruped()
     m.name = "quadruped_rough"
-    data = perlin_terrain(ROUGH_N, seed=seed)
+    data = perlin_terrain(ROUGH_N, cells=ROUGH_CELLS, seed=seed)
     m.hfield = Heightfield(nrow=ROUGH_N, ncol=ROUGH_N,
                            size=(ROUGH_SIZE, ROUGH_SIZE, ROUGH_HEIGHT), data=data)
     floor = m.pairs[0][0]

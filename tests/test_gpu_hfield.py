@@ -1,6 +1,6 @@
 """GPU parity of sphere-heightfield contacts against the FP64 reference.
 
-Workloads: the quadruped on Perlin-noise rough terrain (feet against a 64 x 64
+Workloads: the quadruped on Perlin-noise rough terrain (feet against a 128 x 128
 heightfield) at 16/32/64-lane teams and at full size, and free spheres dropped on a
 rotated, shifted Perlin heightfield.  Same tolerances as the other parity tests:
 qacc <= 1e-4 and contact forces <= 1e-3 per world, states at a switch reported.
