@@ -670,62 +670,83 @@ T box_point(const T* c, const T* R, const double* h, const T* p, T* nworld) {
   return s;
 }
 
-// capsule segment a + t u against a box.  The box SDF f(t) along the segment is convex,
-// so its derivative f'(t) = grad sdf(p(t)) . u is nondecreasing.  The minimiser set is
-// bracketed by t_lo = sup{t : f'(t) < -tau} and t_hi = inf{t : f'(t) > tau}
-// (tau = 1e-5 |u|), found by bisection on the sign of f' (well conditioned where the
-// values of f are not).  A bracket longer than 1e-3 is a flat stretch: both ends are
-// candidates; otherwise its midpoint is.  With the two segment ends this gives up to
-// four candidates (t = 0, t = 1, then the interior ones), de-duplicated within 1e-6;
-// the two deepest penetrating ones are kept.  Normal from capsule to box.
+// capsule segment a + t u (t in [0, 1]) against a box.  In box coordinates the segment is
+// P(t) = p0 + t v, and the box's signed distance f(t) along it is convex and piecewise
+// smooth: its pieces change where a coordinate crosses -h_k, 0 or h_k and, inside the
+// box, where the largest face distance changes hands (|P_i| - h_i = |P_j| - h_j).  On a
+// piece outside the box f^2 is the sum, over the coordinates beyond their slab, of
+// (|P_k| - h_k)^2: a quadratic in t with a closed-form minimiser.  Inside, f is linear.
+// So the minimiser set of f over [0, 1] is found exactly among the breakpoints and the
+// pieces' stationary points: the points whose f equals the minimum (to g_cb_eq of the
+// segment's scale, a rounding allowance) span it.  Candidates: the segment's ends and
+// the minimiser set's ends (both when it is a stretch, as for a capsule lying on a face;
+// one point otherwise), de-duplicated within g_cb_dup in t; the two deepest penetrating
+// ones are kept.  Normal from capsule to box.
+// mjo_set_capsule_box_tolerances changes g_cb_eq and g_cb_dup (tests only: the contacts
+// must not depend on them).
+static double g_cb_eq = 1e-12, g_cb_dup = 1e-6;
 template <class T>
 void capsule_box(const T* a, const T* u, T r, const T* c, const T* R, const double* h,
                  std::vector<Cand<T>>& out) {
-  // f'(t) from the box-frame SDF gradient at p(t)
-  auto fprime = [&](T t) {
-    T p[3] = {a[0] + t * u[0], a[1] + t * u[1], a[2] + t * u[2]};
-    T nw[3];
-    box_point(c, R, h, p, nw);
-    return dot3(nw, u);
+  T rel[3] = {a[0] - c[0], a[1] - c[1], a[2] - c[2]}, p0[3], v[3];
+  matTvec(R, rel, p0);
+  matTvec(R, u, v);
+  auto f = [&](T t) {
+    T p[3] = {p0[0] + t * v[0], p0[1] + t * v[1], p0[2] + t * v[2]};
+    return box_sdf(p, h, (T*)nullptr);
   };
-  const T tau = 1e-5 * norm3(u);
-  T tlo, thi;
-  if (!(fprime(T(0.0)) < -tau)) tlo = 0.0;
-  else if (fprime(T(1.0)) < -tau) tlo = 1.0;
-  else {
-    T l = 0.0, g = 1.0;  // fprime(l) < -tau <= fprime(g)
-    for (int it = 0; it < 60; it++) {
-      T mid = 0.5 * (l + g);
-      if (fprime(mid) < -tau) l = mid; else g = mid;
+  std::vector<T> ts = {T(0.0), T(1.0)};
+  auto add = [&](T t) {
+    if (t > 0.0 && t < 1.0) ts.push_back(t);
+  };
+  for (int k = 0; k < 3; k++)
+    if (v[k] != 0.0)
+      for (double q : {-h[k], 0.0, h[k]}) add((T(q) - p0[k]) / v[k]);
+  for (int i = 0; i < 3; i++)
+    for (int j = i + 1; j < 3; j++)
+      for (double si : {-1.0, 1.0})
+        for (double sj : {-1.0, 1.0}) {  // si P_i - h_i = sj P_j - h_j
+          const T den = si * v[i] - sj * v[j];
+          if (den != 0.0) add((T(h[i] - h[j]) - si * p0[i] + sj * p0[j]) / den);
+        }
+  std::sort(ts.begin(), ts.end(), [](const T& x, const T& y) { return x < y; });
+  const size_t nb = ts.size();
+  for (size_t k = 0; k + 1 < nb; k++) {  // stationary point of each outside piece
+    const T mid = 0.5 * (ts[k] + ts[k + 1]);
+    T num = 0.0, den = 0.0;
+    for (int i = 0; i < 3; i++) {
+      const T pi = p0[i] + mid * v[i];
+      if (!(fabs(pi) > h[i])) continue;
+      const T s = pi < 0.0 ? T(-1.0) : T(1.0);
+      num += (s * p0[i] - h[i]) * s * v[i];
+      den += v[i] * v[i];
     }
-    tlo = 0.5 * (l + g);
-  }
-  if (!(fprime(T(1.0)) > tau)) thi = 1.0;
-  else if (fprime(T(0.0)) > tau) thi = 0.0;
-  else {
-    T l = 0.0, g = 1.0;  // fprime(l) <= tau < fprime(g)
-    for (int it = 0; it < 60; it++) {
-      T mid = 0.5 * (l + g);
-      if (fprime(mid) > tau) g = mid; else l = mid;
+    if (den > 0.0) {
+      const T t = -num / den;
+      if (t > ts[k] && t < ts[k + 1]) ts.push_back(t);
     }
-    thi = 0.5 * (l + g);
   }
-  T ts[4] = {T(0.0), T(1.0), tlo, thi};
+  T fmin = f(ts[0]);
+  for (const T& t : ts) fmin = tmin(fmin, f(t));
+  const double eq = g_cb_eq * (val(norm3(v)) + h[0] + h[1] + h[2]);
+  T tlo = 1.0, thi = 0.0;
+  for (const T& t : ts)
+    if (f(t) <= fmin + eq) {
+      tlo = tmin(tlo, t);
+      thi = tmax(thi, t);
+    }
+  T ts4[4] = {T(0.0), T(1.0), tlo, thi};
   bool keep[4] = {true, true, true, true};
-  if (thi - tlo < 1e-3) {  // not a flat stretch: one interior candidate at the middle
-    ts[2] = 0.5 * (tlo + thi);
-    keep[3] = false;
-  }
-  const double tdup = 1e-6;
+  const double tdup = g_cb_dup;
   for (int k = 2; k < 4; k++)
-    if (fabs(ts[k] - 0.0) < tdup || fabs(ts[k] - 1.0) < tdup) keep[k] = false;
-  if (keep[2] && keep[3] && fabs(ts[3] - ts[2]) < tdup) keep[3] = false;
+    if (fabs(ts4[k] - 0.0) < tdup || fabs(ts4[k] - 1.0) < tdup) keep[k] = false;
+  if (keep[2] && keep[3] && fabs(ts4[3] - ts4[2]) < tdup) keep[3] = false;
   T depth[4];
   T nrm[4][3];
   T pts[4][3];
   for (int k = 0; k < 4; k++) {
     if (!keep[k]) continue;
-    T p[3] = {a[0] + ts[k] * u[0], a[1] + ts[k] * u[1], a[2] + ts[k] * u[2]};
+    T p[3] = {a[0] + ts4[k] * u[0], a[1] + ts4[k] * u[1], a[2] + ts4[k] * u[2]};
     T nb[3];
     T sd = box_point(c, R, h, p, nb);
     depth[k] = sd - r;
@@ -2074,6 +2095,13 @@ int mjo_trajectory(void* h, int nstep, const double* qpos, const double* qvel,
 }  // extern "C"
 
 extern "C" {
+// Set the capsule-box tolerances (the equal-value allowance relative to the segment's
+// scale, and the de-duplication distance in t); returns the previous pair in prev[2].
+void mjo_set_capsule_box_tolerances(double eq, double dup, double* prev) {
+  if (prev) { prev[0] = g_cb_eq; prev[1] = g_cb_dup; }
+  g_cb_eq = eq;
+  g_cb_dup = dup;
+}
 // Average floating-point operation count of one step (fixed mode) from each of nworld
 // states, counted by the operation-counting scalar: every operation of the dense loops,
 // and, when nonzero_out is given, those whose operands are all nonzero (*nonzero_out).

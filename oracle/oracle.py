@@ -70,6 +70,8 @@ def _load():
         lib.mjo_trajectory.argtypes = [P, C.c_int, D, D, D, D, C.c_int, D, D, I]
         lib.mjo_count_flops.argtypes = [P, C.c_int, D, D, D, D]
         lib.mjo_count_flops.restype = C.c_double
+        lib.mjo_set_capsule_box_tolerances.argtypes = [C.c_double, C.c_double, D]
+        lib.mjo_set_capsule_box_tolerances.restype = None
         lib.mjo_count_flops2.argtypes = [P, C.c_int, D, D, D, D, D]
         lib.mjo_count_flops2.restype = C.c_double
         _lib = lib
@@ -91,6 +93,14 @@ def _arr(x, n=None):
     if n is not None:
         assert a.size == n, (a.shape, n)
     return a
+
+
+def set_capsule_box_tolerances(tau: float, flat: float):
+    """Set the capsule-box bracket tolerances (defaults 1e-5 and 1e-3); returns the
+    previous pair.  For tests of the contacts' independence from them."""
+    prev = np.zeros(2)
+    _load().mjo_set_capsule_box_tolerances(float(tau), float(flat), _d(prev))
+    return float(prev[0]), float(prev[1])
 
 
 class Oracle:
