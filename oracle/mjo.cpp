@@ -249,6 +249,7 @@ struct Model {
   std::vector<int> act_type, act_jnt;
   std::vector<double> act_gear, act_kp, act_kd, act_range, act_qdef;
   int neq = 0;
+  int cone = 0;  // friction cone: 0 pyramidal (edges), 1 elliptic (the contact frame's rows)
   int integrator = 0;  // 0: semi-implicit Euler; 1: with implicit damping; 2: also implicit
                        // PD position gains; 3: classic fourth-order Runge-Kutta
   // heightfield: nrow x ncol elevations in [0, 1] over [-sx, sx] x [-sy, sy], z = sz h
@@ -305,6 +306,12 @@ template <class T> struct Data {
   std::vector<T> qacc;
   std::vector<T> qacc_int;  // acceleration the integrator applies (differs with implicit damping)
   std::vector<T> H;  // dense Cholesky factor of the last Newton Hessian
+  // elliptic cone blocks: a contact's first row, its rows (condim) and sliding mu; per row,
+  // the ratio mu_j / mu of its friction coefficient to the sliding one (1 on the normal)
+  // and whether it belongs to such a block
+  std::vector<int> cone_row0, cone_nd;
+  std::vector<T> cone_mu, row_ratio;
+  std::vector<char> in_cone;
   int status = 0;
   int newton_iters = 0;
   void alloc(const Model& m) {
@@ -1089,16 +1096,24 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
     else if (rhi < 0.0) { lim_dof.push_back(m.jnt_dofadr[j]); lim_sign.push_back(-1.0); lim_dist.push_back(rhi); }
   }
   const int nl = (int)lim_dof.size();
-  int nrc = 0;  // contact rows: four pyramid edges, or one normal row without friction
+  // contact rows: a pyramid's edges, an elliptic cone's frame rows (condim of them), or
+  // one normal row without friction
+  int nrc = 0;
   for (int c = 0; c < nc; c++) {
     d.con[c].row = nrc;
-    nrc += d.con[c].condim == 1 ? 1 : 2 * (d.con[c].condim - 1);
+    const int cd = d.con[c].condim;
+    nrc += (cd == 1 || m.cone == 1) ? cd : 2 * (cd - 1);
   }
   d.nrow = nrc + nl + m.nfric + m.neqrow;
   d.J.assign(d.nrow * n, 0.0);
   d.aref.assign(d.nrow, 0.0);
   d.D.assign(d.nrow, 0.0);
   d.fl.assign(d.nrow, 0.0);
+  d.cone_row0.clear();
+  d.cone_nd.clear();
+  d.cone_mu.clear();
+  d.row_ratio.assign(d.nrow, T(1.0));
+  d.in_cone.assign(d.nrow, 0);
   const double tc = std::max(m.solref[0], 2.0 * m.dt), zeta = m.solref[1];
   const double dmax = m.solimp[1];
   const double K = 1.0 / (dmax * dmax * tc * tc * zeta * zeta);
@@ -1129,12 +1144,9 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
       d.D[row] = 1.0 / ((1.0 - imp) / imp * A1);
       continue;
     }
-    const double A = std::max((1.0 + val(k.mu) * val(k.mu)) *
-                                  (m.body_invweight[b1] + m.body_invweight[b2]), 1e-15);
-    const T R = (1.0 - imp) / imp * A;
     // friction directions: the two tangents (mu); with condim >= 4 the spin about the
     // normal, n . (w2 - w1) (mu_t); with condim 6 the rolling about the tangents,
-    // t_k . (w2 - w1) (mu_r).  Each gives the edges J_n + mu J_dir and J_n - mu J_dir.
+    // t_k . (w2 - w1) (mu_r).
     std::vector<T> Ja(3 * n, T(0.0));
     if (k.condim >= 4) {
       body_angjac(m, d, b2, J2.data());
@@ -1147,6 +1159,38 @@ template <class T> void constraint_rows(const Model& m, Data<T>& d) {
         }
     }
     const int ndir = k.condim - 1;
+    if (m.cone == 1) {
+      // Elliptic cone: the contact frame's rows (normal, then one per friction direction)
+      // with the normal's impedance.  The normal row has aref = -b (J_n qvel) - k d(r) r
+      // and R_n = (1-d)/d (w1 + w2); a friction row, with no distance, aref = -b (J qvel)
+      // and R = R_n (mu / mu_j)^2, mu the sliding coefficient: in the coordinates
+      // e_j mu_j / mu the rows share D_n and the cone is round (see cone_eval).
+      const double A1 = std::max(m.body_invweight[b1] + m.body_invweight[b2], 1e-15);
+      const T Dn = 1.0 / ((1.0 - imp) / imp * A1);
+      d.cone_row0.push_back(k.row);
+      d.cone_nd.push_back(k.condim);
+      d.cone_mu.push_back(k.mu);
+      for (int e = 0; e < k.condim; e++) {
+        const int row = k.row + e;
+        const T* Jr = e == 0 ? &Jc[0] : (e < 3 ? &Jc[e * n] : (e == 3 ? &Ja[0] : &Ja[(e - 3) * n]));
+        const T mu_e = e < 3 ? k.mu : (e == 3 ? k.mu_t : k.mu_r);
+        const T ratio = e == 0 ? T(1.0) : mu_e / k.mu;
+        T jv = 0.0;
+        for (int i = 0; i < n; i++) {
+          d.J[row * n + i] = Jr[i];
+          jv += Jr[i] * d.qvel[i];
+        }
+        d.aref[row] = e == 0 ? -B * jv - K * imp * k.dist : -B * jv;
+        d.D[row] = Dn * ratio * ratio;
+        d.row_ratio[row] = ratio;
+        d.in_cone[row] = 1;
+      }
+      continue;
+    }
+    // Pyramid: each friction direction gives the edges J_n + mu J_dir and J_n - mu J_dir.
+    const double A = std::max((1.0 + val(k.mu) * val(k.mu)) *
+                                  (m.body_invweight[b1] + m.body_invweight[b2]), 1e-15);
+    const T R = (1.0 - imp) / imp * A;
     for (int e = 0; e < 2 * ndir; e++) {
       const int row = k.row + e, dir = e / 2;
       const T* Jd = dir < 2 ? &Jc[(1 + dir) * n] : (dir == 2 ? &Ja[0] : &Ja[(dir - 2) * n]);
@@ -1274,6 +1318,74 @@ template <class T> struct Solver {
     const double F = d.fl[i];
     return F == 0.0 ? e < 0.0 : (std::isinf(F) || fabs(d.D[i] * e) < F);
   }
+  // Elliptic cone block b at e (its rows' J a - aref): cost s, row forces f (so that
+  // ds/de = -f) and, when Hb is given, the Hessian d2s/de2 (nd x nd, row-major).
+  // The block's rows share D = D_n in the coordinates x = (e_n, e_j mu_j / mu), where the
+  // friction cone is round: K = {g : |g_t| <= mu g_n}.  The soft-constraint cost is
+  //   s(e) = max over g in K of  -g.x - |g|^2 / (2 D)  =  |P_K(-D x)|^2 / (2 D),
+  // whose maximiser g = P_K(-D x) is the Euclidean projection onto K, in three zones
+  // with T = |x_t|:
+  //   separated  e_n >= mu T:   g = 0;
+  //   sticking   mu e_n + T <= 0: g = -D x (every row on its quadratic);
+  //   sliding    otherwise:      g on the cone's surface, g_n = c psi with
+  //              psi = mu T - e_n > 0, c = D / (1 + mu^2), g_t = -mu g_n x_t / T, and
+  //              s = c psi^2 / 2 (its Hessian: c (a a^T + psi mu/T (I - t t^T) on the
+  //              friction coordinates), a = (-1, mu t), t = x_t / T).
+  // Physical forces f_j = g_j mu_j / mu; the Hessian maps back by the same scaling.
+  void cone_eval(int b, const T* e, T& cost_out, T* f, T* Hb) const {
+    const int r0 = d.cone_row0[b], nd = d.cone_nd[b];
+    const T mu = d.cone_mu[b], D = d.D[r0];
+    T x[6];
+    T T2 = 0.0;
+    x[0] = e[0];
+    for (int j = 1; j < nd; j++) {
+      x[j] = e[j] * d.row_ratio[r0 + j];
+      T2 += x[j] * x[j];
+    }
+    const T Tn = sqrt(T2);
+    T g[6];
+    T Hs[36];
+    for (int j = 0; j < nd * nd; j++) Hs[j] = 0.0;
+    if (!(x[0] < mu * Tn)) {  // separated
+      cost_out = 0.0;
+      for (int j = 0; j < nd; j++) g[j] = 0.0;
+    } else if (mu * x[0] + Tn <= 0.0) {  // sticking
+      cost_out = 0.5 * D * (x[0] * x[0] + T2);
+      for (int j = 0; j < nd; j++) {
+        g[j] = -D * x[j];
+        Hs[j * nd + j] = D;
+      }
+    } else {  // sliding on the cone's surface
+      const T psi = mu * Tn - x[0], c = D / (1.0 + mu * mu);
+      cost_out = 0.5 * c * psi * psi;
+      g[0] = c * psi;
+      T a[6];
+      a[0] = -1.0;
+      for (int j = 1; j < nd; j++) {
+        g[j] = -mu * g[0] * x[j] / Tn;
+        a[j] = mu * x[j] / Tn;
+      }
+      const T w2 = c * psi * mu / Tn;
+      for (int i = 0; i < nd; i++)
+        for (int j = 0; j < nd; j++) {
+          T v = c * a[i] * a[j];
+          if (i > 0 && j > 0) v += w2 * ((i == j ? 1.0 : 0.0) - x[i] * x[j] / T2);
+          Hs[i * nd + j] = v;
+        }
+    }
+    for (int j = 0; j < nd; j++) f[j] = g[j] * d.row_ratio[r0 + j];
+    if (Hb)
+      for (int i = 0; i < nd; i++)
+        for (int j = 0; j < nd; j++)
+          Hb[i * nd + j] = Hs[i * nd + j] * d.row_ratio[r0 + i] * d.row_ratio[r0 + j];
+  }
+  T cone_cost(int b, const T* a) const {
+    const int r0 = d.cone_row0[b], nd = d.cone_nd[b];
+    T e[6], f[6], c;
+    for (int j = 0; j < nd; j++) e[j] = jrow(r0 + j, a) - d.aref[r0 + j];
+    cone_eval(b, e, c, f, nullptr);
+    return c;
+  }
   T cost(const T* a) const {
     std::vector<T> da(n), Mda(n);
     for (int k = 0; k < n; k++) da[k] = a[k] - d.qacc_smooth[k];
@@ -1283,7 +1395,9 @@ template <class T> struct Solver {
       for (int k = 0; k < n; k++) s += d.M[i * n + k] * da[k];
       c += 0.5 * da[i] * s;
     }
-    for (int i = 0; i < nr; i++) c += srow(i, jrow(i, a) - d.aref[i]);
+    for (int i = 0; i < nr; i++)
+      if (!d.in_cone[i]) c += srow(i, jrow(i, a) - d.aref[i]);
+    for (size_t b = 0; b < d.cone_row0.size(); b++) c += cone_cost((int)b, a);
     return c;
   }
   // gradient and Hessian with the active set at a
@@ -1295,6 +1409,7 @@ template <class T> struct Solver {
       for (int k = 0; k < n; k++) H[i * n + k] = d.M[i * n + k];
     }
     for (int r = 0; r < nr; r++) {
+      if (d.in_cone[r]) continue;
       T e = jrow(r, a) - d.aref[r];
       const T* Jr = &d.J[r * n];
       const T ds = dsrow(r, e);
@@ -1303,6 +1418,75 @@ template <class T> struct Solver {
       for (int i = 0; i < n; i++)
         for (int k = 0; k < n; k++) H[i * n + k] += d.D[r] * Jr[i] * Jr[k];
     }
+    // elliptic cone blocks: g += J_c^T (-f), H += J_c^T Hb J_c
+    for (size_t b = 0; b < d.cone_row0.size(); b++) {
+      const int r0 = d.cone_row0[b], nd = d.cone_nd[b];
+      T e[6], f[6], Hb[36], c;
+      for (int j = 0; j < nd; j++) e[j] = jrow(r0 + j, a) - d.aref[r0 + j];
+      cone_eval((int)b, e, c, f, Hb);
+      for (int j = 0; j < nd; j++)
+        for (int i = 0; i < n; i++) g[i] -= f[j] * d.J[(r0 + j) * n + i];
+      for (int p = 0; p < nd; p++)
+        for (int q = 0; q < nd; q++) {
+          if (Hb[p * nd + q] == 0.0) continue;
+          for (int i = 0; i < n; i++)
+            for (int k = 0; k < n; k++)
+              H[i * n + k] += Hb[p * nd + q] * d.J[(r0 + p) * n + i] * d.J[(r0 + q) * n + k];
+        }
+    }
+  }
+  // exact minimiser of phi(alpha) = F(a + alpha delta) over alpha >= 0 when the model
+  // has elliptic cone blocks: phi is convex and C^1 but no longer piecewise quadratic.
+  // phi' (nondecreasing, negative at 0) is bracketed by doubling from alpha = 1, then
+  // its root is found by Newton steps on phi' (phi'' from the pieces' curvatures), each
+  // replaced by the bracket's midpoint when it leaves the bracket, until the bracket or
+  // phi' vanishes to the working precision.
+  T line_search_cone(const T* a, const T* delta) const {
+    std::vector<T> e(nr), s(nr);
+    for (int i = 0; i < nr; i++) { e[i] = jrow(i, a) - d.aref[i]; s[i] = jrow(i, delta); }
+    T dMd = 0.0, dMa = 0.0;
+    for (int i = 0; i < n; i++) {
+      T t = 0.0;
+      for (int k = 0; k < n; k++) t += d.M[i * n + k] * delta[k];
+      dMd += delta[i] * t;
+      dMa += t * (a[i] - d.qacc_smooth[i]);
+    }
+    auto dphi = [&](T al, T& d2) {
+      T v = dMa + al * dMd;
+      d2 = dMd;
+      for (int i = 0; i < nr; i++) {
+        if (d.in_cone[i]) continue;
+        const T ep = e[i] + al * s[i];
+        v += s[i] * dsrow(i, ep);
+        if (quad(i, ep)) d2 += d.D[i] * s[i] * s[i];
+      }
+      for (size_t b = 0; b < d.cone_row0.size(); b++) {
+        const int r0 = d.cone_row0[b], nd = d.cone_nd[b];
+        T eb[6], f[6], Hb[36], c;
+        for (int j = 0; j < nd; j++) eb[j] = e[r0 + j] + al * s[r0 + j];
+        cone_eval((int)b, eb, c, f, Hb);
+        for (int p = 0; p < nd; p++) {
+          v -= s[r0 + p] * f[p];
+          for (int q = 0; q < nd; q++) d2 += s[r0 + p] * Hb[p * nd + q] * s[r0 + q];
+        }
+      }
+      return v;
+    };
+    T d2;
+    T lo = 0.0, hi = 1.0;
+    for (int k = 0; k < 200 && dphi(hi, d2) < 0.0; k++) { lo = hi; hi = 2.0 * hi; }
+    T al = lo < 1.0 ? T(1.0) : hi;  // the Newton step length, or the bracket's end
+    for (int it = 0; it < 200; it++) {
+      const T v = dphi(al, d2);
+      if (v == 0.0) return al;
+      if (v < 0.0) lo = al; else hi = al;
+      T next = al - v / d2;
+      if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+      // converged: the Newton correction (or the bracket) is below the working precision
+      if (!(fabs(next - al) > 1e-15 * al) || !(hi - lo > 1e-15 * hi)) return next;
+      al = next;
+    }
+    return al;
   }
   // exact minimiser of phi(alpha) = F(a + alpha delta) over alpha >= 0: phi' is piecewise
   // linear and nondecreasing; walk its breakpoints in increasing order
@@ -1403,7 +1587,8 @@ template <class T> struct Solver {
       T slope = 0.0;
       for (int i = 0; i < n; i++) slope += g[i] * delta[i];
       if (!(slope < 0.0)) break;  // zero gradient: already optimal
-      T al = line_search(a.data(), delta.data());
+      T al = d.cone_row0.empty() ? line_search(a.data(), delta.data())
+                                 : line_search_cone(a.data(), delta.data());
       for (int i = 0; i < n; i++) a[i] += al * delta[i];
       d.newton_iters++;
     }
@@ -1437,14 +1622,25 @@ template <class T> void forward(const Model& m, Data<T>& d, int mode) {
   d.efc_force.assign(d.nrow, 0.0);
   std::fill(d.qfrc_con.begin(), d.qfrc_con.end(), T(0.0));
   for (int r = 0; r < d.nrow; r++) {
+    if (d.in_cone[r]) continue;
     T jar = 0.0;
     for (int i = 0; i < m.nv; i++) jar += d.J[r * m.nv + i] * d.qacc[i];
     T f = d.D[r] * (d.aref[r] - jar);
     const double F = d.fl[r];
     if (F == 0.0) d.efc_force[r] = f > 0.0 ? f : T(0.0);
     else d.efc_force[r] = f > F ? T(F) : (f < -F ? T(-F) : f);
-    for (int i = 0; i < m.nv; i++) d.qfrc_con[i] += d.J[r * m.nv + i] * d.efc_force[r];
   }
+  if (!d.cone_row0.empty()) {  // elliptic cone blocks: the projected force of cone_eval
+    Solver<T> s(m, d);
+    for (size_t b = 0; b < d.cone_row0.size(); b++) {
+      const int r0 = d.cone_row0[b], nd = d.cone_nd[b];
+      T e[6], c;
+      for (int j = 0; j < nd; j++) e[j] = s.jrow(r0 + j, d.qacc.data()) - d.aref[r0 + j];
+      s.cone_eval((int)b, e, c, &d.efc_force[r0], nullptr);
+    }
+  }
+  for (int r = 0; r < d.nrow; r++)
+    for (int i = 0; i < m.nv; i++) d.qfrc_con[i] += d.J[r * m.nv + i] * d.efc_force[r];
   // Implicit damping: the forces linear in a dof's own velocity (joint damping b_k and
   // the velocity gain kd of a position actuator on it) act at the end-of-step velocity
   // qvel + h a, so the integrator's acceleration solves
@@ -1580,6 +1776,7 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   m.nconmax = hi[11];
   m.neq = hi[12];
   m.integrator = hi[13];
+  m.cone = hi[15];
   const int has_hf = hi[14];
   m.dt = hf[0];
   for (int k = 0; k < 3; k++) m.grav[k] = hf[1 + k];
@@ -1587,7 +1784,8 @@ static bool load_model(const uint8_t* blob, size_t nbytes, Model& m, std::string
   for (int k = 0; k < 5; k++) m.solimp[k] = hf[6 + k];
   m.tolerance = hf[11];
   if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nconmax < 0 ||
-      m.neq < 0 || m.integrator < 0 || m.integrator > 3 || has_hf < 0 || has_hf > 1) {
+      m.neq < 0 || m.integrator < 0 || m.integrator > 3 || has_hf < 0 || has_hf > 1 ||
+      m.cone < 0 || m.cone > 1) {
     err = "negative size"; return false;
   }
   std::vector<int32_t> bi(2 * m.nbody);
@@ -1889,13 +2087,21 @@ static void export_contacts(const Model& m, const Data<double>& d, double* out) 
     for (int i = 0; i < 3; i++) o[1 + i] = k.pos[i];
     for (int i = 0; i < 9; i++) o[4 + i] = k.frame[i];
     const double* f = &d.efc_force[k.row];
-    // normal force: every edge's (each has unit normal component); tangential forces
-    // from the sliding edges; torsional and rolling moments are not exported
-    const int nr = k.condim == 1 ? 1 : 2 * (k.condim - 1);
-    o[13] = 0.0;
-    for (int e = 0; e < nr; e++) o[13] += f[e];
-    o[14] = k.condim == 1 ? 0.0 : val(k.mu) * (f[0] - f[1]);
-    o[15] = k.condim == 1 ? 0.0 : val(k.mu) * (f[2] - f[3]);
+    if (m.cone == 1) {
+      // elliptic: the frame rows' forces (normal, tangent 1, tangent 2)
+      o[13] = f[0];
+      o[14] = k.condim == 1 ? 0.0 : f[1];
+      o[15] = k.condim == 1 ? 0.0 : f[2];
+    } else {
+      // pyramid: the normal force is every edge's (each has unit normal component);
+      // tangential forces from the sliding edges
+      const int nr = k.condim == 1 ? 1 : 2 * (k.condim - 1);
+      o[13] = 0.0;
+      for (int e = 0; e < nr; e++) o[13] += f[e];
+      o[14] = k.condim == 1 ? 0.0 : val(k.mu) * (f[0] - f[1]);
+      o[15] = k.condim == 1 ? 0.0 : val(k.mu) * (f[2] - f[3]);
+    }
+    // torsional and rolling moments are not exported
     o[16] = k.pair; o[17] = k.sub; o[18] = k.g1; o[19] = k.g2;
   }
 }

@@ -14,7 +14,8 @@ Blob layout (little endian, version 3), every block 8-byte aligned:
                         nu, nq, nv, iterations, ls_iterations, nconmax, neq,
                         integrator (0 semi-implicit Euler, 1 with implicit damping, 2 also with
                         implicit PD position gains),
-                        hfield (1 if the model has a heightfield), 0
+                        hfield (1 if the model has a heightfield),
+                        cone (0 pyramidal, 1 elliptic friction cone)
            float64[16]: timestep, gravity[3], solref[2], solimp[5], tolerance, 0 x4
   body     int32 [nbody][2] : parent, 0
            f64   [nbody][19]: pos[3], quat[4] (w first), mass, ipos[3],
@@ -151,6 +152,8 @@ class Options:
     nconmax: int = 0
     integrator: int = 0  # 1: joint damping and PD velocity gains taken implicitly;
                          # 2: also the PD position gains (at the end-of-step position)
+    cone: int = 0        # friction cone: 0 pyramidal (2 (condim - 1) edge rows a contact),
+                         # 1 elliptic (the contact frame's condim rows)
 
 
 @dataclass
@@ -202,8 +205,11 @@ class Model:
 
     @property
     def conrows(self) -> int:
-        """Rows of the model's widest contact: 1 frictionless, 2 (condim - 1) otherwise."""
+        """Rows of the model's widest contact: 1 frictionless; 2 (condim - 1) pyramid
+        edges, or condim frame rows with the elliptic cone."""
         cd = [p[3] if len(p) > 3 else 3 for p in self.pairs]
+        if self.opt.cone == 1:
+            return max(cd, default=3)
         return max([1 if c == 1 else 2 * (c - 1) for c in cd], default=4)
 
     @property
@@ -253,8 +259,13 @@ class Model:
             assert e.type in (EQ_CONNECT, EQ_WELD), "connect and weld equalities only"
             assert 0 < e.body1 < self.nbody and 0 <= e.body2 < self.nbody
             assert e.body1 != e.body2
+        assert self.opt.cone in (0, 1), "cone 0 (pyramidal) or 1 (elliptic)"
         for g1, g2, *rest in self.pairs:
             assert len(rest) == 1 or rest[1] in (1, 3, 4, 6), "pair condim 1, 3, 4 or 6"
+            cd = rest[1] if len(rest) > 1 else 3
+            if self.opt.cone == 1 and cd >= 3:
+                assert rest[0] > 0 and all(mu > 0 for mu in rest[2:cd - 1]), \
+                    "elliptic cones need positive friction coefficients"
             assert self.geoms[g1].type <= self.geoms[g2].type, "pair order by geom type"
             if self.geoms[g2].type == GEOM_HFIELD:
                 assert self.geoms[g1].type == GEOM_SPHERE, "heightfields pair with spheres"
@@ -271,7 +282,7 @@ class Model:
         hdr_i = [MAGIC, VERSION, self.nbody, len(self.joints), len(self.geoms),
                  len(self.pairs), self.nu, self.nq, self.nv, o.iterations,
                  o.ls_iterations, o.nconmax, self.neq, o.integrator,
-                 int(self.hfield is not None), 0]
+                 int(self.hfield is not None), o.cone]
         hdr_f = [o.timestep, *o.gravity, *o.solref, *o.solimp, o.tolerance, 0, 0, 0, 0]
         assert len(hdr_f) == 16
         parts = [struct.pack("<16i", *hdr_i), struct.pack("<16d", *hdr_f)]
