@@ -2035,7 +2035,8 @@ void mjo_free(void* h) { delete static_cast<Model*>(h); }
 int mjo_dims(void* h, int* out) {
   Model& m = *static_cast<Model*>(h);
   int conrows = m.npair ? 1 : 4;  // rows of the widest contact
-  for (int c : m.pair_condim) conrows = std::max(conrows, c == 1 ? 1 : 2 * (c - 1));
+  for (int c : m.pair_condim)  // pyramid edges, or an elliptic cone's frame rows
+    conrows = std::max(conrows, (c == 1 || m.cone == 1) ? c : 2 * (c - 1));
   int v[15] = {m.nq, m.nv, m.nu, m.nbody, m.njnt, m.ngeom, m.npair, m.nconmax,
                m.iterations, m.ls_iterations, m.nlimit, m.nfric, m.neq, m.neqrow, conrows};
   std::memcpy(out, v, sizeof(v));

@@ -28,6 +28,7 @@ struct HostModel {
   // parsed blob (double precision as stored)
   int nbody = 0, njnt = 0, ngeom = 0, npair = 0, nu = 0, nq = 0, nv = 0;
   int iterations = 0, ls_iterations = 0, nconmax = 0, neq = 0, integrator = 0;
+  int cone = 0;  // friction cone: 0 pyramidal, 1 elliptic
   int hf_nrow = 0, hf_ncol = 0;
   double hf_size[3] = {0, 0, 0};
   std::vector<double> hf_data;
@@ -84,10 +85,12 @@ mjh_status parse_blob(const uint8_t* blob, size_t nbytes, HostModel& m, std::str
   m.neq = hi[12];
   m.integrator = hi[13];
   const int has_hf = hi[14];
+  m.cone = hi[15];
   if (m.nbody < 1 || m.njnt < 0 || m.ngeom < 0 || m.npair < 0 || m.nu < 0 || m.nq < 0 ||
       m.nv < 0 || m.iterations < 0 || m.nconmax < 0 || m.nbody > 4096 || m.njnt > 4096 ||
       m.ngeom > 4096 || m.npair > 65536 || m.nu > 4096 || m.nconmax > 4096 || m.neq < 0 ||
-      m.neq > 1024 || m.integrator < 0 || m.integrator > 3 || has_hf < 0 || has_hf > 1) {
+      m.neq > 1024 || m.integrator < 0 || m.integrator > 3 || has_hf < 0 || has_hf > 1 ||
+      m.cone < 0 || m.cone > 1) {
     err = "model blob: size field out of range";
     return MJH_EMODEL;
   }
@@ -394,12 +397,18 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   d.nfric = (int)fric_dadr.size();
   d.neq = h.neq;
   d.neqrow = h.neqrow;
+  // a contact's rows: 1 frictionless; 2 (condim - 1) pyramid edges; condim frame rows of
+  // an elliptic cone.  con_nr: that count when every pair shares it (contact c's rows
+  // are con_nr c ..), else 0 (each contact's first row and count packed in its record)
+  d.cone = h.cone;
+  auto rows_of = [&](int c) { return (c == 1 || h.cone == 1) ? c : 2 * (c - 1); };
   d.conrows = h.npair ? 1 : 4;
-  d.con_rows4 = 1;
+  d.con_nr = h.npair ? rows_of(h.pair_condim[0]) : 4;
   for (int c : h.pair_condim) {
-    d.conrows = std::max(d.conrows, c == 1 ? 1 : 2 * (c - 1));
-    if (c != 3) d.con_rows4 = 0;
+    d.conrows = std::max(d.conrows, rows_of(c));
+    if (rows_of(c) != d.con_nr) d.con_nr = 0;
   }
+  if (d.con_nr != 3 && d.con_nr != 4) d.con_nr = 0;  // the fast path: 3 and 4 rows
   d.nrowmax = d.conrows * h.nconmax + d.nlim + d.nfric + d.neqrow;
   // pairs and candidate slots
   std::vector<int> pair_kind, pair_candadr, cand_pair;
@@ -564,6 +573,11 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   d.o_s = take(nr);
   // per-row force bound (0: one-sided row, F: friction loss, +inf: two-sided equality)
   d.o_fl = take(d.nfric + d.neq > 0 ? nr : 0);
+  // elliptic cones: the Newton Hessian's rows (a cone's virtual rows, the others' own)
+  // and every row's slope ds/de, left behind for the force export and implicit damping
+  d.o_Jv = d.cone ? take(nr * nv) : 0;
+  d.o_sl = d.cone ? take(nr) : 0;
+  d.o_cv = d.cone ? take(h.nconmax * d.conrows * d.conrows) : 0;
   off = std::max(off, sweep_end);
   // fourth-order Runge-Kutta: the step's start (q0, v0), the first stage's acceleration
   // and the weighted sums of the stages' velocities and accelerations, alive across the
@@ -601,6 +615,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   x.o_aref = take(nr);
   x.o_D = take(nr); x.o_e = take(nr); x.o_s = take(nr); x.o_fl = take(d.nfric + d.neq > 0 ? nr : 0);
   x.o_qbi = take(h.nq); x.o_vbi = take(nv); x.o_qb = take(h.nq); x.o_vb = take(nv);
+  x.o_Jv = x.o_sl = x.o_cv = 0;  // rollouts take pyramidal cones only
   x.o_ub = take(h.nu); x.o_mu = take(nv); x.o_Sbar = take(6 * nv);
   x.o_xbar = take(3 * nb); x.o_Rbar = take(9 * nb); x.o_cinbar = take(kCinert * nb);
   x.o_Vbar = take(6 * nb); x.o_Abar = take(6 * nb); x.o_Fbar = take(6 * nb);
@@ -649,6 +664,7 @@ struct mjh_batch {
   int tab_words = 0;
   size_t lds_bytes = 0;
   bool rk4 = false;  // some group integrates by fourth-order Runge-Kutta
+  bool cone = false; // some group's model has elliptic cones
   bool dirty = true;       // launch shape or world counts changed: rebuild the tables
   bool ptrs_dirty = false; // only bound pointers changed: rewrite d_groups in place
   hipGraph_t graph = nullptr;
@@ -754,8 +770,11 @@ static mjh_status sync_tables(mjh_batch* b) {
   b->block = std::max(block, 16);
   b->lds_bytes = lds;
   b->rk4 = false;
-  for (const GroupRec& gr : b->groups)
+  b->cone = false;
+  for (const GroupRec& gr : b->groups) {
     if (gr.nworld > 0 && ctx->models[gr.model]->dm.rk4) b->rk4 = true;
+    if (gr.nworld > 0 && ctx->models[gr.model]->dm.cone) b->cone = true;
+  }
   b->dirty = false;
   b->ptrs_dirty = false;
   if (b->graph_exec) { (void)hipGraphExecDestroy(b->graph_exec); b->graph_exec = nullptr; }
@@ -963,7 +982,7 @@ mjh_status mjh_step(mjh_batch* b, int32_t nstep, void* stream) {
   if (st != MJH_OK) return st;
   if (nstep == 0 || b->ntask == 0) return MJH_OK;
   MJH_HIP(launch_step(b->d_groups, b->d_tasks, b->ntask, nstep, b->block, b->lds_bytes,
-                      b->tab_words, b->rk4, static_cast<hipStream_t>(stream)));
+                      b->tab_words, b->rk4, b->cone, static_cast<hipStream_t>(stream)));
   return MJH_OK;
 }
 
@@ -989,6 +1008,8 @@ mjh_status mjh_env_step(mjh_batch* b, int32_t nenv, int32_t nsub, const float* a
   if (params && h.integrator != 0)
     return fail(ctx, MJH_EUNSUPPORTED,
                 "env_step: per-world parameters with implicit damping are not supported");
+  if (h.cone != 0)
+    return fail(ctx, MJH_EUNSUPPORTED, "env_step: elliptic cones are not supported");
   if (g.nworld == 0) return MJH_OK;
   if (!action || !command || !reset_qpos || !reset_qvel || !last_action || !obs || !reward ||
       !done)
@@ -1026,7 +1047,7 @@ mjh_status mjh_graph_capture(mjh_batch* b, int32_t nstep, void* stream) {
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   MJH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   hipError_t le = launch_step(b->d_groups, b->d_tasks, b->ntask, nstep, b->block, b->lds_bytes,
-                              b->tab_words, b->rk4, s);
+                              b->tab_words, b->rk4, b->cone, s);
   hipGraph_t g = nullptr;
   hipError_t ce = hipStreamEndCapture(s, &g);
   if (le != hipSuccess || ce != hipSuccess) {
@@ -1080,7 +1101,7 @@ static std::string tune_key(const DevModel& d, int nworld) {
   std::ostringstream k;
   k << d.nq << ' ' << d.nv << ' ' << d.nbody << ' ' << d.npair << ' ' << d.ncand << ' '
     << d.nconmax << ' ' << d.nlim << ' ' << d.nfric << ' ' << d.neq << ' ' << d.conrows << ' '
-    << d.implicit << ' ' << d.rk4 << ' ' << d.iterations << ' ' << nworld;
+    << d.implicit << ' ' << d.rk4 << ' ' << d.cone << ' ' << d.iterations << ' ' << nworld;
   return k.str();
 }
 
@@ -1180,7 +1201,7 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
         for (int rep = 0; ok && rep < 2; rep++) {  // the first run warms caches
           ok = restore() && hip_ok(hipEventRecord(e0, nullptr), "autotune: event") &&
                hip_ok(launch_step(b->d_groups, b->d_tasks, b->ntask, nstep_probe, b->block,
-                                  b->lds_bytes, b->tab_words, b->rk4, nullptr),
+                                  b->lds_bytes, b->tab_words, b->rk4, b->cone, nullptr),
                       "autotune: probe launch") &&
                hip_ok(hipEventRecord(e1, nullptr), "autotune: event") &&
                hip_ok(hipEventSynchronize(e1), "autotune: probe") &&
@@ -1230,6 +1251,8 @@ static mjh_status rollout_model_check(mjh_ctx* ctx, const ModelRec& mr) {
       return fail(ctx, MJH_EUNSUPPORTED, "rollout: frictionless contacts are not differentiated");
   if (mr.h.integrator != 0)
     return fail(ctx, MJH_EUNSUPPORTED, "rollout: implicit damping is not differentiated");
+  if (mr.h.cone != 0)
+    return fail(ctx, MJH_EUNSUPPORTED, "rollout: elliptic cones are not differentiated");
   {
     std::vector<int> nj(mr.h.nbody, 0);
     for (int j = 0; j < mr.h.njnt; j++) nj[mr.h.jnt_body[j]]++;

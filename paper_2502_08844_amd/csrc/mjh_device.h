@@ -1070,19 +1070,20 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
   const int ncon = scal[SC_NCON];
   const int nv = m.nv;
   float* con = W + m.o_con;
-  // each contact's rows (1 frictionless, else two pyramid edges per friction direction:
-  // 4, 6 or 10) and its first row.  With every pair at condim 3 they are 4 and 4c;
-  // otherwise a prefix sum in contact order packs them into the record's slot word
-  // (candidate slot | rows << 4 | first row << 8).
-  int nrc = 4 * ncon;
-  if (!m.con_rows4) {
+  // each contact's rows (1 frictionless; else two pyramid edges per friction direction,
+  // 4, 6 or 10, or an elliptic cone's condim frame rows) and its first row.  With every
+  // pair at condim 3 they are con_nr and con_nr c; otherwise a prefix sum in contact
+  // order packs them into the record's slot word (candidate slot | rows << 4 | first
+  // row << 8).
+  int nrc = m.con_nr * ncon;
+  if (!m.con_nr) {
     nrc = 0;
     for (int c0 = 0; c0 < ncon; c0 += t.T) {
       const int c = c0 + t.lane;
       int nr = 0;
       if (c < ncon) {
         const int cd = m.pair_condim[__float_as_int(con[kConRec * c + 16])];
-        nr = cd == 1 ? 1 : 2 * (cd - 1);
+        nr = (cd == 1 || m.cone) ? cd : 2 * (cd - 1);
       }
       const int first = nrc + t.exscan(nr);
       if (c < ncon) {
@@ -1114,7 +1115,10 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
   const int nrf = nrc + nl;  // first friction-loss row
   const int nre = nrf + m.nfric;  // first equality row
   const int nrow = nre + m.neqrow;
-  if (t.lane == 0) scal[SC_NROW] = nrow;
+  if (t.lane == 0) {
+    scal[SC_NROW] = nrow;
+    scal[SC_NRC] = nrc;
+  }
   for (int idx = t.lane; idx < ncon * nv; idx += t.T) {
     const int c = idx / nv, i = idx - c * nv;
     const float* r = con + kConRec * c;
@@ -1134,11 +1138,22 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
       }
     }
     const int slot = __float_as_int(r[17]);
-    const int first = m.con_rows4 ? 4 * c : slot >> 8, nr = m.con_rows4 ? 4 : (slot >> 4) & 15;
+    const int first = m.con_nr ? m.con_nr * c : slot >> 8, nr = m.con_nr ? m.con_nr : (slot >> 4) & 15;
     const float jn = dot3(r + 4, jd);
     float* Jr = J + first * nv + i;
     if (nr == 1) {  // frictionless
       Jr[0] = jn;
+    } else if (m.cone) {  // elliptic: normal, tangents, spin (condim 4), rolling (6)
+      Jr[0] = jn;
+      Jr[nv] = dot3(r + 7, jd);
+      Jr[2 * nv] = dot3(r + 10, jd);
+      if (nr > 3) {
+        Jr[3 * nv] = dot3(r + 4, jw);
+        if (nr > 4) {
+          Jr[4 * nv] = dot3(r + 7, jw);
+          Jr[5 * nv] = dot3(r + 10, jw);
+        }
+      }
     } else {  // edges J_n +- mu J_dir: tangents, then spin (condim 4), then rolling (6)
       const float j1 = dot3(r + 7, jd), j2 = dot3(r + 10, jd);
       const float mu = r[13];
@@ -1205,17 +1220,32 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
   for (int row = t.lane; row < nrow; row += t.T) {
     float dist, jv = 0.f, A;
     if (row < nrc) {
-      int c = row >> 2;  // four rows a contact unless some pair has another condim
-      if (!m.con_rows4) {
-        c = 0;
+      int c = m.con_nr ? row / m.con_nr : 0;  // con_nr rows a contact when uniform
+      if (!m.con_nr)
         while (c + 1 < ncon && (__float_as_int(con[kConRec * (c + 1) + 17]) >> 8) <= row) c++;
-      }
       const float* r = con + kConRec * c;
       dist = r[0];
       for (int i = 0; i < nv; i++) jv += J[row * nv + i] * qvel[i];
       const int b1 = __float_as_int(r[14]), b2 = __float_as_int(r[15]);
       const float mu = r[13];  // 0 for a frictionless contact: A = w1 + w2
-      A = (1.f + mu * mu) * (m.body_invweight[b1] + m.body_invweight[b2]);
+      if (m.cone) {
+        // elliptic: the normal row's impedance and A = w1 + w2 for every row; a friction
+        // row has no distance term and D scaled by (mu_j / mu)^2
+        const int first = m.con_nr ? m.con_nr * c : __float_as_int(r[17]) >> 8;
+        const int k = row - first;
+        A = m.body_invweight[b1] + m.body_invweight[b2];
+        if (k > 0) {
+          const int p = __float_as_int(r[16]);
+          const float ratio = k < 3 ? 1.f : (k == 3 ? m.pair_mu_t[p] : m.pair_mu_r[p]) / mu;
+          const float imp = impedance(m, dist);
+          aref[row] = -m.B * jv;
+          D[row] = ratio * ratio * imp / ((1.f - imp) * fmaxf(A, 1e-15f));
+          if (has_bounds(m)) W[m.o_fl + row] = 0.f;
+          continue;
+        }
+      } else {
+        A = (1.f + mu * mu) * (m.body_invweight[b1] + m.body_invweight[b2]);
+      }
     } else if (row < nrf) {
       const int code = lim[row - nrc];
       int dof;
@@ -1310,17 +1340,21 @@ DEV int pad_rows(const DevModel& m, float* W, const Team& t, int nrow) {
 // interval.  When `y` is given the
 // forward solve L y = b (b overwritten) rides along.  Returns false for a non-positive
 // pivot.  `w` (nrow words) receives the rows' curvatures: D on the quadratic piece, else 0.
+// Jh (default the constraint rows J) and w_given (the caller stored the weights in the
+// o_s words) let the elliptic-cone solve pass its own Hessian rows and weights.
 DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
                           float* b = nullptr, float* y = nullptr, bool rev = false,
-                          bool hgain = false) {
+                          bool hgain = false, const float* Jh = nullptr,
+                          bool w_given = false) {
   const int nv = m.nv;
   const float* M = W + m.o_M;
   float* H = W + m.o_H;
-  const float* J = W + m.o_J;
+  const float* J = Jh ? Jh : W + m.o_J;
   const float* D = W + m.o_D;
   const float* e = W + m.o_e;
   float* w = W + m.o_s;  // row weights; the line search rewrites this scratch later
-  if (has_bounds(m)) {
+  if (w_given) {
+  } else if (has_bounds(m)) {
     const float* fl = W + m.o_fl;
     for (int r = t.lane; r < nru; r += t.T) w[r] = row_quad(D[r], fl[r], e[r]) ? D[r] : 0.f;
   } else {
@@ -1768,8 +1802,359 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
     if (!moved && cm <= kNewtonExitTol * am) break;
   }
 }
+// ------------------------------------------------- A9 with elliptic friction cones
+// One contact's cone at e (its nd rows' J a - aref): the cost, the rows' slopes ds/de
+// (minus the row forces) and its zone, in the coordinates x_j = e_j r_j (r_j = mu_j / mu:
+// 1 on the normal and the tangents) where the cone |g_t| <= mu g_n is round and the rows
+// share D = D_n (the convex soft-constraint cost of the force set, maximised at the
+// projection of -D x onto the cone):
+//   separated (0)  x_0 >= mu |x_t|:        s = 0;
+//   sliding   (1)  otherwise:              s = c psi^2 / 2, psi = mu |x_t| - x_0 > 0,
+//                                          c = D / (1 + mu^2);
+//   sticking  (2)  mu x_0 + |x_t| <= 0:    s = D |x|^2 / 2.
+// With V (nd x nd) and w (nd) given, also the Hessian as weighted virtual rows,
+// d2s/de2 = sum_k w_k V_k V_k^T: the rows themselves when sticking (w_k = D r_k^2); when
+// sliding the direction a = (-1, mu t), t = x_t / |x_t|, with weight c, and a
+// Householder basis of the friction coordinates orthogonal to t with weight
+// c psi mu / |x_t|, both mapped back by r_j.
+DEV int cone_eval(float mu, float D, const float* ratio, int nd, const float* e,
+                  float& cost, float* slope, float* w = nullptr, float* V = nullptr) {
+  float x[6], T2 = 0.f;
+  x[0] = e[0];
+  for (int j = 1; j < nd; j++) {
+    x[j] = e[j] * ratio[j];
+    T2 += x[j] * x[j];
+  }
+  const float Tn = sqrtf(T2);
+  if (w)
+    for (int k = 0; k < nd; k++) {
+      w[k] = 0.f;
+      for (int j = 0; j < nd; j++) V[k * nd + j] = 0.f;
+    }
+  if (!(x[0] < mu * Tn)) {
+    cost = 0.f;
+    for (int j = 0; j < nd; j++) slope[j] = 0.f;
+    return 0;
+  }
+  if (mu * x[0] + Tn <= 0.f) {
+    cost = 0.5f * D * (x[0] * x[0] + T2);
+    for (int j = 0; j < nd; j++) slope[j] = D * x[j] * ratio[j];
+    if (w)
+      for (int k = 0; k < nd; k++) {
+        w[k] = D * ratio[k] * ratio[k];
+        V[k * nd + k] = 1.f;
+      }
+    return 2;
+  }
+  const float psi = mu * Tn - x[0], c = D / (1.f + mu * mu), inv = 1.f / Tn;
+  cost = 0.5f * c * psi * psi;
+  slope[0] = -c * psi;
+  for (int j = 1; j < nd; j++) slope[j] = c * psi * mu * x[j] * inv * ratio[j];
+  if (w) {
+    w[0] = c;
+    V[0] = -1.f;
+    for (int j = 1; j < nd; j++) V[j] = mu * x[j] * inv * ratio[j];
+    // the reflection I - beta u u^T (u = t + sign(t_1) e_1) takes t to -+e_1; its
+    // other columns span the friction coordinates orthogonal to t
+    const int mf = nd - 1;
+    float u[5];
+    for (int j = 0; j < mf; j++) u[j] = x[1 + j] * inv;
+    u[0] += u[0] >= 0.f ? 1.f : -1.f;
+    float uu = 0.f;
+    for (int j = 0; j < mf; j++) uu += u[j] * u[j];
+    const float beta = 2.f / uu, w2 = c * psi * mu * inv;
+    for (int k = 1; k < mf; k++) {
+      w[k] = w2;
+      for (int j = 0; j < mf; j++)
+        V[k * nd + 1 + j] = ((j == k ? 1.f : 0.f) - beta * u[j] * u[k]) * ratio[1 + j];
+    }
+  }
+  return 1;
+}
+
+// contact c's rows (first, count), friction coefficient and per-row ratios r_j
+DEV int cone_of(const DevModel& m, const float* con, int c, int& first, float& mu,
+                float* ratio) {
+  const float* r = con + kConRec * c;
+  const int slot = __float_as_int(r[17]);
+  first = m.con_nr ? m.con_nr * c : slot >> 8;
+  const int nd = m.con_nr ? m.con_nr : (slot >> 4) & 15;
+  mu = r[13];
+  const int p = __float_as_int(r[16]);
+  for (int j = 0; j < nd; j++)
+    ratio[j] = j < 3 ? 1.f : (j == 3 ? m.pair_mu_t[p] : m.pair_mu_r[p]) / mu;
+  return nd;
+}
+
+// The Newton solve of newton_impl for a model with elliptic cones.  Contact rows are
+// handled per contact (a cone block, or one one-sided row for a frictionless contact),
+// the others per row.  Each iteration evaluates every row's slope ds/de (sl) and the
+// Hessian's rows (Jv: a cone's virtual rows, the other rows themselves, with their
+// weights in the o_s words), assembles and factors H = M + sum_r w_r Jv_r^T Jv_r, takes
+// the refined direction, and minimises phi(al) = F(a + al d) exactly: phi' is continuous
+// and nondecreasing but not piecewise linear, so its root is bracketed by doubling from
+// al = 1 and found by Newton steps on phi' kept inside the bracket (midpoint otherwise).
+// On exit sl holds the final slopes (the rows' forces are -sl).
+template <bool FR>
+DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, int iters,
+                     float gtol) {
+  const float* fl = W + m.o_fl;
+  const int* scal = (const int*)(W + m.o_scal);
+  const int nv = m.nv, nrow = scal[SC_NROW], nrc = scal[SC_NRC], ncon = scal[SC_NCON];
+  const float* con = W + m.o_con;
+  const float* M = W + m.o_M;
+  const float* J = W + m.o_J;
+  const float* aref = W + m.o_aref;
+  const float* D = W + m.o_D;
+  float* e = W + m.o_e;
+  float* s = W + m.o_s;
+  const float* a0 = W + m.o_a0;
+  float* a = W + m.o_qacc;
+  float* Mr = W + m.o_Mr;
+  float* g = W + m.o_g;
+  float* d = W + m.o_d;
+  float* Md = W + m.o_Md;
+  float* tmp = W + m.o_tmp;
+  float* Jv = W + m.o_Jv;
+  float* sl = W + m.o_sl;
+  float* cv = W + m.o_cv;
+  const int cw = m.conrows * m.conrows;
+  if (nrow == 0) {
+    for (int i = t.lane; i < nv; i += t.T) a[i] = a0[i];
+    t.sync();
+    return;
+  }
+  const int nru = pad_rows(m, W, t, nrow);
+  auto row_s = [&](int r, float ev) {  // a non-cone row's slope
+    return FR ? row_slope(D[r], fl[r], ev) : fminf(D[r] * ev, 0.f);
+  };
+  auto row_q = [&](int r, float ev) {
+    return FR ? row_quad(D[r], fl[r], ev) : ev < 0.f;
+  };
+  // cost of the rows at e + al s (per lane; sum over the team afterwards)
+  auto rows_cost = [&](const float* ee, const float* ss, float al) {
+    float cst = 0.f;
+    for (int c = t.lane; c < ncon; c += t.T) {
+      int first;
+      float mu, ratio[6], ev[6], sv[6], cc;
+      const int nd = cone_of(m, con, c, first, mu, ratio);
+      for (int j = 0; j < nd; j++) ev[j] = ee[first + j] + (ss ? al * ss[first + j] : 0.f);
+      if (nd == 1) {
+        cst += ev[0] < 0.f ? 0.5f * D[first] * ev[0] * ev[0] : 0.f;
+      } else {
+        cone_eval(mu, D[first], ratio, nd, ev, cc, sv);
+        cst += cc;
+      }
+    }
+    for (int r = nrc + t.lane; r < nrow; r += t.T) {
+      const float ev = ee[r] + (ss ? al * ss[r] : 0.f);
+      cst += FR ? row_cost(D[r], fl[r], ev) : (ev < 0.f ? 0.5f * D[r] * ev * ev : 0.f);
+    }
+    return cst;
+  };
+  // ---- start point: cost of the warm start vs cost of a0
+  for (int i = t.lane; i < nv; i += t.T) tmp[i] = a[i] - a0[i];
+  t.sync();
+  float qw = 0.f;
+  for (int i = t.lane; i < nv; i += t.T) {
+    float v = 0.f;
+    for (int k = 0; k < nv; k++) v += M[sym(i, k)] * tmp[k];
+    Mr[i] = v;
+    qw += 0.5f * tmp[i] * v;
+  }
+  for (int r = t.lane; r < nrow; r += t.T) {
+    float jw = 0.f, j0 = 0.f;
+    for (int i = 0; i < nv; i++) { jw += J[r * nv + i] * a[i]; j0 += J[r * nv + i] * a0[i]; }
+    e[r] = jw - aref[r];
+    s[r] = j0 - aref[r];  // stash
+  }
+  t.sync();
+  const float cw0 = t.sum(rows_cost(e, nullptr, 0.f) + qw);
+  const float c00 = t.sum(rows_cost(s, nullptr, 0.f));
+  t.sync();
+  if (!(cw0 <= c00)) {
+    for (int i = t.lane; i < nv; i += t.T) { a[i] = a0[i]; Mr[i] = 0.f; }
+    for (int r = t.lane; r < nrow; r += t.T) e[r] = s[r];
+    t.sync();
+  }
+  float gstop = 0.f;
+  if (gtol > 0.f) {
+    const float* frc = W + m.o_frc;
+    float fm = 1.f;
+    for (int i = t.lane; i < nv; i += t.T) fm = fmaxf(fm, fabsf(frc[i]));
+    gstop = gtol * t.max(fm);
+  }
+  for (int it = 0; it < iters; it++) {
+    // ---- slopes, Hessian weights and the cones' virtual-row maps
+    for (int c = t.lane; c < ncon; c += t.T) {
+      int first;
+      float mu, ratio[6], ev[6], sv[6], wv[6], cc;
+      const int nd = cone_of(m, con, c, first, mu, ratio);
+      if (nd == 1) {
+        sl[first] = fminf(D[first] * e[first], 0.f);
+        s[first] = e[first] < 0.f ? D[first] : 0.f;
+        continue;
+      }
+      for (int j = 0; j < nd; j++) ev[j] = e[first + j];
+      cone_eval(mu, D[first], ratio, nd, ev, cc, sv, wv, cv + c * cw);
+      for (int j = 0; j < nd; j++) {
+        sl[first + j] = sv[j];
+        s[first + j] = wv[j];
+      }
+    }
+    for (int r = nrc + t.lane; r < nru; r += t.T) {
+      sl[r] = row_s(r, e[r]);
+      s[r] = row_q(r, e[r]) ? D[r] : 0.f;
+    }
+    t.sync();
+    // Hessian rows: a cone's k-th virtual row sum_j V[k][j] J_j, the others copied
+    for (int idx = t.lane; idx < nru * nv; idx += t.T) {
+      const int r = idx / nv, i = idx - r * nv;
+      float v = J[idx];
+      if (r < nrc) {
+        int c = m.con_nr ? r / m.con_nr : 0;
+        if (!m.con_nr)
+          while (c + 1 < ncon && (__float_as_int(con[kConRec * (c + 1) + 17]) >> 8) <= r) c++;
+        int first;
+        float mu, ratio[6];
+        const int nd = cone_of(m, con, c, first, mu, ratio);
+        if (nd > 1) {
+          const float* V = cv + c * cw + (r - first) * nd;
+          v = 0.f;
+          for (int j = 0; j < nd; j++) v += V[j] * J[(first + j) * nv + i];
+        }
+      }
+      Jv[idx] = v;
+    }
+    // ---- gradient g = M (a - a0) + sum_r sl_r J_r
+    float gmax = 0.f;
+    t.sync();
+    for (int i = t.lane; i < nv; i += t.T) {
+      float v = Mr[i];
+      for (int r = 0; r < nru; r++) v += sl[r] * J[r * nv + i];
+      g[i] = v;
+      gmax = fmaxf(gmax, fabsf(v));
+    }
+    if (gtol > 0.f && t.max(gmax) <= gstop) break;
+    for (int i = t.lane; i < nv; i += t.T) d[i] = -g[i];
+    // ---- delta = -H^-1 g, then one step of iterative refinement (as in newton_impl)
+    if (!hessian_cholesky(m, W, t, nru, d, tmp, false, false, Jv, true)) { status |= 4; break; }
+    cholesky_back(m, W, t, tmp, d);
+    for (int r = t.lane; r < nru; r += t.T) {
+      float v = 0.f;
+      for (int i = 0; i < nv; i++) v += Jv[r * nv + i] * d[i];
+      s[r] *= v;  // weight times the virtual row's product
+    }
+    t.sync();
+    for (int i = t.lane; i < nv; i += t.T) {
+      float v = g[i];
+      for (int k = 0; k < nv; k++) v += M[sym(i, k)] * d[k];
+      for (int r = 0; r < nru; r++) v += s[r] * Jv[r * nv + i];
+      tmp[i] = v;
+    }
+    t.sync();
+    cholesky_solve(m, W, t, tmp, tmp, 1.f);
+    for (int i = t.lane; i < nv; i += t.T) d[i] -= tmp[i];
+    t.sync();
+    // ---- line search quantities
+    float gd = 0.f, dMd = 0.f, dMr = 0.f;
+    for (int i = t.lane; i < nv; i += t.T) {
+      float v = 0.f;
+      for (int k = 0; k < nv; k++) v += M[sym(i, k)] * d[k];
+      Md[i] = v;
+      gd += g[i] * d[i];
+      dMd += d[i] * v;
+      dMr += d[i] * Mr[i];
+    }
+    for (int r = t.lane; r < nru; r += t.T) {
+      float v = 0.f;
+      for (int i = 0; i < nv; i++) v += J[r * nv + i] * d[i];
+      s[r] = v;
+    }
+    gd = t.sum(gd);
+    dMd = t.sum(dMd);
+    dMr = t.sum(dMr);
+    t.sync();
+    if (!(gd < 0.f)) break;
+    // phi'(al) and phi''(al), summed over the team
+    auto dphi = [&](float al, float& d2) {
+      float v = 0.f, h2 = 0.f;
+      for (int c = t.lane; c < ncon; c += t.T) {
+        int first;
+        float mu, ratio[6], ev[6], sv[6], wv[6], V[36], cc;
+        const int nd = cone_of(m, con, c, first, mu, ratio);
+        if (nd == 1) {
+          const float ep = e[first] + al * s[first];
+          if (ep < 0.f) {
+            v += s[first] * D[first] * ep;
+            h2 += D[first] * s[first] * s[first];
+          }
+          continue;
+        }
+        for (int j = 0; j < nd; j++) ev[j] = e[first + j] + al * s[first + j];
+        cone_eval(mu, D[first], ratio, nd, ev, cc, sv, wv, V);
+        for (int k = 0; k < nd; k++) {
+          v += s[first + k] * sv[k];
+          float q = 0.f;
+          for (int j = 0; j < nd; j++) q += V[k * nd + j] * s[first + j];
+          h2 += wv[k] * q * q;
+        }
+      }
+      for (int r = nrc + t.lane; r < nrow; r += t.T) {
+        const float ep = e[r] + al * s[r];
+        v += s[r] * row_s(r, ep);
+        if (row_q(r, ep)) h2 += D[r] * s[r] * s[r];
+      }
+      d2 = t.sum(h2) + dMd;
+      return t.sum(v) + dMr + al * dMd;
+    };
+    float d2, lo = 0.f, hi = 1.f;
+    for (int k = 0; k < 30 && dphi(hi, d2) < 0.f; k++) { lo = hi; hi *= 2.f; }
+    float al = lo < 1.f ? 1.f : hi;
+    for (int k = 0; k < 24; k++) {
+      const float v = dphi(al, d2);
+      if (v == 0.f) break;
+      if (v < 0.f) lo = al; else hi = al;
+      float next = al - v / d2;
+      if (!(next > lo && next < hi)) next = 0.5f * (lo + hi);
+      const bool done = !(fabsf(next - al) > 1e-6f * al) || !(hi - lo > 1e-6f * hi);
+      al = next;
+      if (done) break;
+    }
+    // ---- update
+    for (int i = t.lane; i < nv; i += t.T) { a[i] += al * d[i]; Mr[i] += al * Md[i]; }
+    for (int r = t.lane; r < nrow; r += t.T) e[r] += al * s[r];
+    t.sync();
+  }
+  // ---- the final slopes (the rows' forces are -sl)
+  for (int c = t.lane; c < ncon; c += t.T) {
+    int first;
+    float mu, ratio[6], ev[6], sv[6], cc;
+    const int nd = cone_of(m, con, c, first, mu, ratio);
+    if (nd == 1) {
+      sl[first] = fminf(D[first] * e[first], 0.f);
+      continue;
+    }
+    for (int j = 0; j < nd; j++) ev[j] = e[first + j];
+    cone_eval(mu, D[first], ratio, nd, ev, cc, sv);
+    for (int j = 0; j < nd; j++) sl[first + j] = sv[j];
+  }
+  for (int r = nrc + t.lane; r < nrow; r += t.T) sl[r] = row_s(r, e[r]);
+  t.sync();
+}
+
+// CONE: the instantiation that can solve elliptic-cone models (kept out of the others,
+// whose registers it would crowd)
+template <bool CONE = false>
 DEV void newton(const DevModel& m, float* W, const Team& t, int& status, int iters,
                 float gtol = 0.f) {
+  if constexpr (CONE) {
+    if (m.cone) {
+      if (has_bounds(m)) newton_cone<true>(m, W, t, status, iters, gtol);
+      else newton_cone<false>(m, W, t, status, iters, gtol);
+      return;
+    }
+  }
   if (has_bounds(m)) newton_impl<true>(m, W, t, status, iters, gtol);
   else newton_impl<false>(m, W, t, status, iters, gtol);
 }
@@ -1785,7 +2170,7 @@ DEV void export_contacts(const DevModel& m, float* W, const Team& t, float* out,
   for (int c = t.lane; c < ncon; c += t.T) {
     const float* r = con + kConRec * c;
     const int slot = __float_as_int(r[17]);
-    const int first = m.con_rows4 ? 4 * c : slot >> 8, nr = m.con_rows4 ? 4 : (slot >> 4) & 15;
+    const int first = m.con_nr ? m.con_nr * c : slot >> 8, nr = m.con_nr ? m.con_nr : (slot >> 4) & 15;
     float f[4] = {0.f, 0.f, 0.f, 0.f}, fn = 0.f;
     for (int e = 0; e < nr; e++) {
       const float fe = fmaxf(-D[first + e] * er[first + e], 0.f);
@@ -1795,9 +2180,16 @@ DEV void export_contacts(const DevModel& m, float* W, const Team& t, float* out,
     float* o = out + kConOut * c;
     for (int k = 0; k < 13; k++) o[k] = r[k];
     for (int k = 0; k < 3; k++) o[1 + k] = r[1 + k] - W[m.o_xpos + k];  // world position
-    o[13] = fn;  // the normal force sums every edge; torsion and rolling are not exported
-    o[14] = r[13] * (f[0] - f[1]);
-    o[15] = r[13] * (f[2] - f[3]);
+    if (m.cone) {  // elliptic: the frame rows' forces, minus their final slopes
+      const float* sl = W + m.o_sl;
+      o[13] = -sl[first];
+      o[14] = nr > 1 ? -sl[first + 1] : 0.f;
+      o[15] = nr > 1 ? -sl[first + 2] : 0.f;
+    } else {  // the normal force sums every edge; torsion and rolling are not exported
+      o[13] = fn;
+      o[14] = r[13] * (f[0] - f[1]);
+      o[15] = r[13] * (f[2] - f[3]);
+    }
     o[16] = (float)__float_as_int(r[16]);
     o[17] = (float)(__float_as_int(r[17]) & 15);
   }
@@ -1893,10 +2285,12 @@ DEV void implicit_damping(const DevModel& m, float* W, const Team& t) {
   const bool fr = has_bounds(m);
   float* rhs = W + m.o_frc;
   const float* qvel = W + m.o_qvel;
+  const float* sl = W + m.o_sl;  // elliptic cones: the solve's final slopes
   for (int i = t.lane; i < nv; i += t.T) {
     float v = m.implicit == 2 ? rhs[i] - m.dof_hkp[i] * qvel[i] : rhs[i];
     for (int r = 0; r < nrow; r++)
-      v -= (fr ? row_slope(D[r], fl[r], e[r]) : fminf(D[r] * e[r], 0.f)) * J[r * nv + i];
+      v -= (m.cone ? sl[r] : (fr ? row_slope(D[r], fl[r], e[r]) : fminf(D[r] * e[r], 0.f))) *
+           J[r * nv + i];
     rhs[i] = v;
   }
   t.sync();
@@ -1923,6 +2317,7 @@ DEV void implicit_damping(const DevModel& m, float* W, const Team& t) {
   }
 }
 
+template <bool CONE = false>
 DEV void world_step(const DevModel& m, float* W0, const Team& t0, const float* ctrl,
                     int& status, int iters, float gtol = 0.f, long long* ph = nullptr,
                     long long* last = nullptr, const float* dr = nullptr) {
@@ -1985,7 +2380,7 @@ DEV void world_step(const DevModel& m, float* W0, const Team& t0, const float* c
   }
   {
     MJH_PHASE_CTX
-    newton(m, W, t, status, iters, gtol);
+    newton<CONE>(m, W, t, status, iters, gtol);
     MJH_MARK(6);
   }
   if (m.implicit) {

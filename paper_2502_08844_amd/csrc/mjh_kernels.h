@@ -14,9 +14,10 @@ __host__ __device__ inline int table_words(const DevModel& m) {
 }
 
 // Launch the step kernel: one work-group of `block` threads per task; rk4 selects the
-// instantiation that can run fourth-order Runge-Kutta groups.
+// instantiation that can run fourth-order Runge-Kutta groups, cone the one that can
+// also solve elliptic-cone models.
 hipError_t launch_step(const DevGroup* groups, const DevTask* tasks, int ntask, int nstep,
-                       int block, size_t lds_bytes, int tab_words, bool rk4,
+                       int block, size_t lds_bytes, int tab_words, bool rk4, bool cone,
                        hipStream_t stream);
 // Allow the step kernel `bytes` of dynamic LDS per work-group.
 hipError_t set_step_lds_limit(size_t bytes);

@@ -20,8 +20,9 @@ __device__ long long g_phase_cycles[kPhaseWorlds * 8];
 #endif
 
 // RK: the instantiation that can run fourth-order Runge-Kutta groups (four forward
-// passes a step); the other compiles the one-pass step alone.
-template <bool RK>
+// passes a step); the other compiles the one-pass step alone.  CONE: the one that can
+// solve elliptic-cone models (with RK, for any batch that has one).
+template <bool RK, bool CONE>
 __device__ __forceinline__ void run_worlds(const DevGroup& G, float* W, int world, int nstep, int lane, int T,
                            const unsigned char* tab) {
   const DevModel& m = G.m;
@@ -46,9 +47,9 @@ __device__ __forceinline__ void run_worlds(const DevGroup& G, float* W, int worl
     for (int k = 0; k < (rk ? 4 : 1); k++) {
       if (k > 0) rk4_begin(m, W, t, k);
 #ifdef MJH_PHASE_TIMING
-      world_step(m, W, t, u, status, m.iterations, 0.f, ph, &last);
+      world_step<CONE>(m, W, t, u, status, m.iterations, 0.f, ph, &last);
 #else
-      world_step(m, W, t, u, status, m.iterations);
+      world_step<CONE>(m, W, t, u, status, m.iterations);
 #endif
       if (k == 0 && s == nstep - 1 && G.con_out)
         export_contacts(m, W, t, G.con_out + w * m.nconmax * kConOut,
@@ -77,7 +78,7 @@ __device__ __forceinline__ void run_worlds(const DevGroup& G, float* W, int worl
   if (lane == 0 && G.status) G.status[w] = status;
 }
 
-template <bool RK>
+template <bool RK, bool CONE>
 __global__ void __launch_bounds__(kMaxBlock, 4)
 mjh_step_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__ tasks,
                 int nstep, int tab_words) {
@@ -91,7 +92,7 @@ mjh_step_kernel(const DevGroup* __restrict__ groups, const DevTask* __restrict__
   float* W = lds + tab_words + (size_t)team * G.m.lds_words;
   const int lane = threadIdx.x - team * T;
   const int world = tk.w0 + team;
-  run_worlds<RK>(G, W, world, nstep, lane, T, (const unsigned char*)lds);
+  run_worlds<RK, CONE>(G, W, world, nstep, lane, T, (const unsigned char*)lds);
 }
 
 // ------------------------------------------------------------- environment step
@@ -312,23 +313,29 @@ __global__ void __launch_bounds__(64) mjh_invweight_kernel(DevModel m, int tab_w
 
 // ------------------------------------------------------------- host-side launchers
 hipError_t launch_step(const DevGroup* groups, const DevTask* tasks, int ntask, int nstep,
-                       int block, size_t lds_bytes, int tab_words, bool rk4,
+                       int block, size_t lds_bytes, int tab_words, bool rk4, bool cone,
                        hipStream_t stream) {
   if (ntask <= 0) return hipSuccess;
-  if (rk4)
-    hipLaunchKernelGGL(mjh_step_kernel<true>, dim3(ntask), dim3(block), lds_bytes, stream,
-                       groups, tasks, nstep, tab_words);
+  if (cone)
+    hipLaunchKernelGGL((mjh_step_kernel<true, true>), dim3(ntask), dim3(block), lds_bytes,
+                       stream, groups, tasks, nstep, tab_words);
+  else if (rk4)
+    hipLaunchKernelGGL((mjh_step_kernel<true, false>), dim3(ntask), dim3(block), lds_bytes,
+                       stream, groups, tasks, nstep, tab_words);
   else
-    hipLaunchKernelGGL(mjh_step_kernel<false>, dim3(ntask), dim3(block), lds_bytes, stream,
-                       groups, tasks, nstep, tab_words);
+    hipLaunchKernelGGL((mjh_step_kernel<false, false>), dim3(ntask), dim3(block), lds_bytes,
+                       stream, groups, tasks, nstep, tab_words);
   return hipGetLastError();
 }
 
 hipError_t set_step_lds_limit(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)mjh_step_kernel<false>,
+  hipError_t e = hipFuncSetAttribute((const void*)mjh_step_kernel<false, false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)mjh_step_kernel<true, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)mjh_step_kernel<true>,
+  return hipFuncSetAttribute((const void*)mjh_step_kernel<true, true>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 

@@ -36,7 +36,10 @@ struct DevModel {
   int nbody, njnt, nq, nv, nu, ngeom, npair, ncand, nconmax, nlim, nfric, neq, nrowmax;
   int neqrow;  // equality rows: 3 per connect, 6 per weld
   int conrows;   // rows of the widest contact (nrowmax = conrows nconmax + ...)
-  int con_rows4; // 1 when every pair has condim 3 (contact c's rows are 4c .. 4c + 3)
+  int con_nr;    // rows of every contact when all pairs have the same count (4: pyramid,
+                 // 3: elliptic cone, both condim 3; contact c's rows are con_nr c ..),
+                 // else 0 (first row and count packed in the contact record)
+  int cone;      // friction cone: 0 pyramidal (edge rows), 1 elliptic (frame rows)
   int iterations, nlevel, nmpair, ntri;
   int implicit;  // 1: joint damping and PD velocity gains integrated implicitly;
                  // 2: also the PD position gains
@@ -128,15 +131,18 @@ struct DevModel {
   int o_frc, o_a0, o_Mr, o_g, o_d, o_Md, o_tmp;
   int o_cand, o_con, o_lim, o_J, o_aref, o_D, o_e, o_s, o_fl, o_scal;
   int o_rk;  // Runge-Kutta block (rk4 only): q0 [nq], v0, a1, vsum, asum [nv each]
+  int o_Jv, o_sl;  // elliptic cones only: Hessian rows [nrowmax][nv], row slopes [nrowmax]
+  int o_cv;        // elliptic cones only: each contact's virtual-row map [nconmax][conrows^2]
   // adjoint layout only (no aliasing between the sweep and contact scratch there)
   int o_qbi, o_vbi, o_qb, o_vb, o_ub, o_mu, o_Sbar, o_xbar, o_Rbar, o_cinbar;
   int o_Vbar, o_Abar, o_Fbar, o_vup, o_aup, o_xup, o_Rup, o_rowsc, o_consc;
 };
 
-// scalar slots inside o_scal: the contact count and the row count (4 per contact, then
-// one per violated joint limit, then one per friction-loss dof)
+// scalar slots inside o_scal: the contact count, the row count (the contacts' rows, then
+// one per violated joint limit, one per friction-loss dof and the equality rows) and the
+// contacts' rows alone
 enum ScalSlot : int {
-  SC_NCON = 0, SC_NROW = 1, SC_COUNT = 4
+  SC_NCON = 0, SC_NROW = 1, SC_NRC = 2, SC_COUNT = 4
 };
 
 // one group of worlds of the same model inside a batch, as the kernel sees it

@@ -39,9 +39,9 @@ def initial_state(kind: str, m: Model, nworld: int, seed: int = 0):
     elif kind.startswith("quadruped"):
         qpos[:, 7:] = np.tile(robots.QUAD_Q_DEFAULT, 4) + r_q.uniform(-0.2, 0.2,
                                                                         size=(nworld, 12))
-    elif kind == "humanoid":
+    elif kind.startswith("humanoid"):
         qpos[:, 7:] += r_q.uniform(-0.1, 0.1, size=(nworld, nq - 7))
-    elif kind == "hand":
+    elif kind.startswith("hand"):
         qpos[:, :16] += r_q.uniform(-0.1, 0.1, size=(nworld, 16))
     else:
         raise ValueError(kind)
@@ -56,9 +56,9 @@ def controls(kind: str, m: Model, nworld: int, nstep: int, seed: int = 0) -> np.
         u = r.uniform(-1.0, 1.0, size=shape)
     elif kind.startswith("quadruped"):
         u = r.uniform(-0.5, 0.5, size=shape)
-    elif kind == "humanoid":
+    elif kind.startswith("humanoid"):
         u = np.clip(r.normal(0.0, 0.3, size=shape), -1.0, 1.0)
-    elif kind == "hand":
+    elif kind.startswith("hand"):
         u = r.uniform(-0.3, 0.3, size=shape)
     else:
         raise ValueError(kind)

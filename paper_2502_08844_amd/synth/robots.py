@@ -625,6 +625,33 @@ def quadruped_rolling() -> Model:
     return quadruped(condim=6, mu_torsion=0.02, mu_rolling=0.001)
 
 
+def elliptic(m: Model) -> Model:
+    """The model with elliptic friction cones (the contact frame's rows) in place of the
+    pyramid."""
+    m.name = m.name + "_elliptic"
+    m.opt.cone = 1
+    return m
+
+
+def quadruped_elliptic() -> Model:
+    """The quadruped with elliptic friction cones at the feet."""
+    return elliptic(quadruped())
+
+
+def quadruped_elliptic_rolling() -> Model:
+    """The quadruped with elliptic cones over sliding, torsional and rolling friction
+    (condim 6: six frame rows a contact)."""
+    return elliptic(quadruped_rolling())
+
+
+def humanoid_elliptic() -> Model:
+    return elliptic(humanoid())
+
+
+def hand_elliptic() -> Model:
+    return elliptic(hand())
+
+
 def quadruped_rk4() -> Model:
     """The quadruped integrated by fourth-order Runge-Kutta (integrator 3)."""
     m = quadruped()
@@ -861,6 +888,10 @@ WORKLOADS = {
     "quadruped_torsion": quadruped_torsion,
     "quadruped_rolling": quadruped_rolling,
     "quadruped_rough": quadruped_rough,
+    "quadruped_elliptic": quadruped_elliptic,
+    "quadruped_elliptic_rolling": quadruped_elliptic_rolling,
     "humanoid": humanoid,
+    "humanoid_elliptic": humanoid_elliptic,
     "hand": hand,
+    "hand_elliptic": hand_elliptic,
 }

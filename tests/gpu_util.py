@@ -70,8 +70,29 @@ def compare_step(m, o, state, ctrl1, gpu1, mode=oracle.MODE_FIXED, near=1e-5):
             return False
         e = f["J"] @ f["qacc"] - f["aref"]
         tol = 1e-6 * (1 + np.abs(f["aref"]).max())
+        lo = 0  # first row whose switch is at e = 0
+        if m.opt.cone == 1:  # elliptic: a cone at the border of its zones
+            first = 0
+            for c in f["contacts"]:
+                pair = m.pairs[int(c[16])]
+                cd = pair[3] if len(pair) > 3 else 3
+                if cd > 1:
+                    mu = pair[2]
+                    ratio = np.ones(cd)
+                    if cd > 3:
+                        ratio[3] = pair[4] / mu
+                    if cd > 4:
+                        ratio[4:] = pair[5] / mu
+                    x = e[first:first + cd] * ratio
+                    T = np.linalg.norm(x[1:])
+                    if min(abs(x[0] - mu * T), abs(mu * x[0] + T)) < tol:
+                        return True
+                elif abs(e[first]) < tol:
+                    return True
+                first += cd
+            lo = first
         one = f["nrow"] - len(fric) - neqr  # one-sided rows: switch at e = 0
-        if np.any(np.abs(e[:one]) < tol):
+        if np.any(np.abs(e[lo:one]) < tol):
             return True
         if len(fric):  # friction loss: switch where |D e| = F
             De = np.abs(f["D"][one:one + len(fric)] * e[one:one + len(fric)])

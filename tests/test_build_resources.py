@@ -14,9 +14,11 @@ import pytest
 
 from paper_2502_08844_amd import build
 
-# instantiations without / with fourth-order Runge-Kutta groups
-STEP = "_ZN3mjh15mjh_step_kernelILb0EEEvPKNS_8DevGroupEPKNS_7DevTaskEii"
-STEP_RK = "_ZN3mjh15mjh_step_kernelILb1EEEvPKNS_8DevGroupEPKNS_7DevTaskEii"
+# instantiations without / with fourth-order Runge-Kutta groups, and the one that also
+# solves elliptic-cone models
+STEP = "_ZN3mjh15mjh_step_kernelILb0ELb0EEEvPKNS_8DevGroupEPKNS_7DevTaskEii"
+STEP_RK = "_ZN3mjh15mjh_step_kernelILb1ELb0EEEvPKNS_8DevGroupEPKNS_7DevTaskEii"
+STEP_CONE = "_ZN3mjh15mjh_step_kernelILb1ELb1EEEvPKNS_8DevGroupEPKNS_7DevTaskEii"
 # env kernel: plain, with per-world randomised parameters, with Runge-Kutta
 ENV = "_ZN3mjh14mjh_env_kernelILb0ELb0EEEvPKNS_8DevGroupEPKNS_7DevTaskENS_7EnvArgsEii"
 ENV_DR = "_ZN3mjh14mjh_env_kernelILb0ELb1EEEvPKNS_8DevGroupEPKNS_7DevTaskENS_7EnvArgsEii"
@@ -31,8 +33,8 @@ def usage():
     return u
 
 
-@pytest.mark.parametrize("kernel,scratch_max", [(STEP, 96), (STEP_RK, 128), (ENV, 224),
-                                                (ENV_DR, 256), (ENV_RK, 256)])
+@pytest.mark.parametrize("kernel,scratch_max", [(STEP, 32), (STEP_RK, 64), (STEP_CONE, 512),
+                                                (ENV, 160), (ENV_DR, 192), (ENV_RK, 160)])
 def test_hot_kernels_fit_four_waves_with_small_scratch(usage, kernel, scratch_max):
     k = usage[kernel]
     assert k["VGPRs"] <= 128 and k["Occupancy"] >= 4
