@@ -72,7 +72,8 @@ def parse():
                     choices=["quadruped", "quadruped_limits", "quadruped_friction",
                              "quadruped_tethered", "quadruped_welded", "quadruped_frictionless",
                              "quadruped_implicit", "quadruped_implicit_pd", "quadruped_rk4",
-                             "quadruped_rough", "humanoid", "hand", "cartpole"],
+                             "quadruped_rough", "quadruped_elliptic", "humanoid", "hand",
+                             "cartpole"],
                     help="robot of the timed batch (the headline metric is the quadruped)")
     ap.add_argument("--nworld", type=int, default=8192)
     ap.add_argument("--nstep", type=int, default=1000)
@@ -586,6 +587,12 @@ def main():
         out["rolling"] = constraint_compare(
             ctx, args.seed, "quadruped_rolling",
             "torsional and rolling friction at the feet (condim 6: ten edges a contact)")
+        out["elliptic"] = constraint_compare(
+            ctx, args.seed, "quadruped_elliptic",
+            "elliptic friction cones at the feet (three frame rows a contact)")
+        out["elliptic_rolling"] = constraint_compare(
+            ctx, args.seed, "quadruped_elliptic_rolling",
+            "elliptic cones over sliding, torsional and rolling friction (six rows a contact)")
         out["implicit_damping"] = constraint_compare(
             ctx, args.seed, "quadruped_implicit",
             "its PD velocity gains integrated implicitly")

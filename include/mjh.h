@@ -110,10 +110,17 @@ const char* mjh_last_error(const mjh_ctx* ctx);
  * (frictionless); 3 the sliding pyramid's four edges J_n +- mu J_t1, J_n +- mu J_t2;
  * 4 also J_n +- mu_t J_spin (torsion about the normal); 6 also J_n +- mu_r J_roll for
  * both tangents (rolling), all with R = (1-d)/d (1 + mu^2)(w1 + w2).
+ * With the model option cone = 1 a contact's rows are instead its frame's (normal,
+ * tangents, then spin and rolling for condim 4 / 6) under an elliptic cone: the rows
+ * share the normal's impedance, friction rows have no distance term and R_j = R_n
+ * (mu / mu_j)^2 with R_n = (1-d)/d (w1 + w2), and the contact's force is the projection
+ * of -D x onto the round cone |g_t| <= mu g_n in the coordinates x_j = (J a - aref)_j
+ * mu_j / mu (separated, sliding on the cone's surface, or sticking).
  * Integrator 1 takes joint damping and PD velocity gains implicitly, 2 also the PD
  * position gains, 3 is fourth-order Runge-Kutta (four forward passes a step).
  * mjh_rollout_fwd rejects models with equalities, integrators other than 0, contact
- * dimensions other than 3 or heightfield pairs (MJH_EUNSUPPORTED).
+ * dimensions other than 3, elliptic cones or heightfield pairs (MJH_EUNSUPPORTED), and
+ * mjh_env_step rejects elliptic cones.
  * MJH_EMODEL for a malformed blob, MJH_EUNSUPPORTED for nv > 64, box-box pairs,
  * a free joint below the root or two actuators on one dof. */
 mjh_status mjh_model_upload(mjh_ctx* ctx, const void* blob, size_t nbytes,

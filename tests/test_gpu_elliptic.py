@@ -60,10 +60,11 @@ def test_full_size_quadruped_elliptic(lib):
     m, qp, qv, u = workload("quadruped_elliptic", nw, nstep + 1, seed=2)
     w = mjh.World(ctx, m, nw, qpos=qp, qvel=qv)
     w.batch.set_launch(0, 32, 128)
-    w.step(torch.tensor(u[:nstep], dtype=torch.float32, device="cuda"), nstep=nstep)
+    ut = torch.tensor(u, dtype=torch.float32, device="cuda")
+    w.step(ut[:nstep])
     torch.cuda.synchronize()
     state = _state(w)
-    g1 = _one_step(w, mjh, u[nstep:nstep + 1])
+    g1 = _one_step(w, mjh, ut[nstep:nstep + 1].contiguous())
     assert np.all(w.status.cpu().numpy() & 1 == 0)
     _check("quadruped_elliptic-full", m, state, u[nstep:nstep + 1], g1, _sample(nw))
 
