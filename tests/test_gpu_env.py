@@ -13,6 +13,12 @@ Checks, on the quadruped from contact-rich states with a share of inverted world
   world;
 * models without a free root and per-dof position actuators are rejected, and so are
   nenv 0, nsub 0 and per-world parameters on an implicit model, leaving every buffer;
+* the GPU env computes the reward table's terms without the feet terms and the
+  stand-still term, and returns the observation of the state a world ended in (its
+  terminal observation) also for a done world: it is compared with the reference's
+  terminal observations and with its reward before those terms; its parameter
+  records carry no link centre-of-mass shifts (the reference's records are padded
+  with zero shifts);
 * domain randomisation: identity records and zero noise change no bit; with random
   records (friction, payload, centre of mass, PD gains, calibration, armature) and
   sensor noise, one physics step's qacc matches each world's randomised reference
@@ -56,6 +62,16 @@ def _scene(ctx, mjh, nw, seed, invert=True):
     prev = rng.uniform(-0.5, 0.5, size=(nw, m.nu))
     return m, inputs.f32(qp), inputs.f32(qv), inputs.f32(ws), inputs.f32(cmd), reset_q, \
         reset_v, inputs.f32(prev), inv
+
+
+def _gpu_record_size(m):
+    """Words of the GPU env's parameter record: the reference's without link shifts."""
+    return 8 + 2 * m.nu
+
+
+def _pad_records(m, dr):
+    """The reference's records for GPU records: zero link centre-of-mass shifts."""
+    return np.concatenate([dr, np.zeros((dr.shape[0], renv.dr_size(m) - dr.shape[1]))], 1)
 
 
 def _dev(x, dtype=torch.float32):
@@ -143,10 +159,10 @@ def test_env_step_against_reference_env(lib):
     act = inputs.f32(np.random.default_rng(13).uniform(-0.6, 0.6, size=(1, nw, m.nu)))
     g = _env_gpu(ctx, mjh, m, qp, qv, ws, act, cmd, rq, rv, prev)
     o = oracle.Oracle(m)
-    obs, rew, done, (q, v, w_, pa) = renv.env_step(o, m, qp, qv, ws, prev, act[0], cmd, rq, rv,
-                                                  NSUB)
+    _, rew, done, (q, v, w_, pa, _), term = renv.env_step(o, m, qp, qv, ws, prev, act[0], cmd,
+                                                          rq, rv, NSUB)
     assert np.array_equal(g["done"][0], done)
-    err = (np.abs(g["obs"][0] - obs) / (1 + np.abs(obs))).max(1)
+    err = (np.abs(g["obs"][0] - term) / (1 + np.abs(term))).max(1)
     print(f"[gpu] env obs vs FP64 env: median {np.median(err):.1e} max {err.max():.1e}",
           flush=True)
     assert err.max() <= 1e-4
@@ -169,7 +185,7 @@ def _records(m, nw, seed):
     0.4-1.25, payload -0.5-2 kg, centre of mass +-3 cm, gains +-20 %, calibration +-0.05
     rad, armature 0-0.02 kg m^2)."""
     rng = np.random.default_rng(seed)
-    rec = np.zeros((nw, 8 + 2 * m.nu))
+    rec = np.zeros((nw, _gpu_record_size(m)))
     rec[:, 0] = rng.uniform(0.4, 1.25, nw)
     rec[:, 1] = rng.uniform(-0.5, 2.0, nw)
     rec[:, 2:5] = rng.uniform(-0.03, 0.03, (nw, 3))
@@ -186,7 +202,7 @@ def test_identity_records_change_nothing(lib):
     m, qp, qv, ws, cmd, rq, rv, prev, inv = _scene(ctx, mjh, nw, seed=21)
     act = inputs.f32(np.random.default_rng(3).uniform(-0.6, 0.6, size=(2, nw, m.nu)))
     ref = _env_gpu(ctx, mjh, m, qp, qv, ws, act, cmd, rq, rv, prev)
-    dr = np.stack([renv.dr_identity(m)] * nw)
+    dr = np.stack([renv.dr_identity(m)[:_gpu_record_size(m)]] * nw)
     got = _env_gpu(ctx, mjh, m, qp, qv, ws, act, cmd, rq, rv, prev, dr=dr,
                    noise=np.zeros((2, nw, 12 + 3 * m.nu)))
     for k in ("obs", "reward", "done", "qpos", "qvel", "qacc", "last_action"):
@@ -208,8 +224,9 @@ def test_randomised_physics_step_parity(lib):
     o = oracle.Oracle(m)
     err, flag, eo, er = np.zeros(nw), np.zeros(nw, dtype=bool), 0.0, 0.0
     for w in range(nw):
-        mw = renv.randomized_model(m, dr[w])
-        ow = renv.randomized_oracle(o, m, dr[w])
+        rec = _pad_records(m, dr[w:w + 1])[0]
+        mw = renv.randomized_model(m, rec)
+        ow = renv.randomized_oracle(o, m, rec)
         st = (qp[w:w + 1], qv[w:w + 1], ws[w:w + 1])
         ref = ow.step(*(x.copy() for x in st), act[:, w:w + 1], nstep=1)
         gpu1 = {"qacc": g["qacc"][w:w + 1], "ncon": ref["ncon"], "contacts": ref["contacts"]}
@@ -236,9 +253,9 @@ def test_randomised_env_step_against_reference_env(lib):
     act = inputs.f32(np.random.default_rng(10).uniform(-0.6, 0.6, size=(1, nw, m.nu)))
     noise = inputs.f32(np.random.default_rng(11).normal(scale=0.01, size=(1, nw, 48)))
     g = _env_gpu(ctx, mjh, m, qp, qv, ws, act, cmd, rq, rv, prev, dr=dr, noise=noise)
-    obs, rew, done, (q, v, w_, pa) = renv.env_step(oracle.Oracle(m), m, qp, qv, ws, prev,
-                                                  act[0], cmd, rq, rv, NSUB, dr=dr,
-                                                  noise=noise[0])
+    _, rew, done, (q, v, w_, pa, _), obs = renv.env_step(
+        oracle.Oracle(m), m, qp, qv, ws, prev, act[0], cmd, rq, rv, NSUB, dr=_pad_records(m, dr),
+        noise=noise[0])
     assert np.array_equal(g["done"][0], done) and np.array_equal(done, inv)
     err = (np.abs(g["obs"][0] - obs) / (1 + np.abs(obs))).max(1)
     print(f"[gpu] randomised env obs vs FP64 env: median {np.median(err):.1e} "
@@ -284,7 +301,7 @@ def test_env_step_argument_errors_leave_state(lib):
         la = torch.full((nw, m.nu), 0.25, device="cuda")
         rq, rv = _dev(qp), _dev(qv)
         cmd = torch.zeros(nw, 3, device="cuda")
-        dr = _dev(np.tile(renv.dr_identity(m), (nw, 1))) if params else None
+        dr = _dev(np.tile(renv.dr_identity(m)[:_gpu_record_size(m)], (nw, 1))) if params else None
         cases = [(1, NSUB)] if params else [(0, NSUB), (1, 0)]
         for nenv, nsub in cases:
             obs = torch.full((nenv, nw, nobs), 7.0, device="cuda")
