@@ -39,13 +39,18 @@ ALGO_BYTES_PER_WORLD_STEP_AT_1000 = algo_bytes(12, 19, 18, 1000)  # quadruped
 
 
 def kernel_digest():
-    """Digest of the built library (the build is reproducible, and comments do not
-    change it): a counter profile applies to the current kernel only if it was taken
-    with the same digest."""
+    """Digest of the library's sources and compile flags: a counter profile applies to
+    the current kernel only if it was taken with the same digest.  (The built file
+    itself is not hashed: it records the directory it was built in.)"""
     import hashlib
-    from paper_2502_08844_amd import mjh
-    with open(mjh.LIB_PATH, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    from paper_2502_08844_amd import build
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(build.CSRC)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(build.CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    h.update(" ".join(build.FLAGS).encode())
+    return h.hexdigest()[:16]
 
 
 def profiled_traffic(kind, nw, ns):
@@ -56,7 +61,7 @@ def profiled_traffic(kind, nw, ns):
     digest, traffic = None, None
     with open(PROFILE) as f:
         for line in f:
-            if line.startswith("library digest:"):
+            if line.startswith("kernel source digest:"):
                 digest = line.split(":", 1)[1].strip()
             elif line.strip().startswith("traffic_bytes_per_launch:"):
                 traffic = float(line.split(":", 1)[1])
