@@ -205,17 +205,15 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
   for (int i = t.lane; i < nv; i += t.T) abar[i] = h * vb[i];
   // ---- implicit differentiation: lambda = H(a*)^-1 a_bar, mu = -lambda
   {
-    const float* J = W + m.o_J;
     const float* aref = W + m.o_aref;
     float* e = W + m.o_e;
-    const int nru = pad_rows(m, W, t, nrow);
-    for (int r = t.lane; r < nrow; r += t.T) {
-      float v = 0.f;
-      for (int i = 0; i < nv; i++) v += J[r * nv + i] * a[i];
-      e[r] = v - aref[r];
-    }
+    const RowBounds rb = pad_rows(m, W, t, nrow);
+    rows_times(m, W, t, nrow, rb, a, e);
+    for (int r = t.lane; r < nrow; r += t.T) e[r] -= aref[r];
     t.sync();
-    if (!hessian_cholesky(m, W, t, nru)) status |= 4;
+    if (!hessian_cholesky(m, W, t, rb.nru, nullptr, nullptr, false, false, nullptr, false,
+                          rb.nou))
+      status |= 4;
     cholesky_solve(m, W, t, abar, mu, -1.f);
   }
   // ---- actuation and passive forces, reversed (lane per dof)
@@ -355,7 +353,6 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
   }
   // ---- contact rows, reversed
   if (nrow > 0) {
-    const float* J = W + m.o_J;
     const float* D = W + m.o_D;
     const float* e = W + m.o_e;
     const float* con = W + m.o_con;
@@ -364,7 +361,7 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
     for (int r = t.lane; r < nrow; r += t.T) {
       float sv = 0.f, xv = 0.f, yv = 0.f;
       for (int i = 0; i < nv; i++) {
-        const float jr = J[r * nv + i];
+        const float jr = row_entry(m, W, r, i, ncon);
         sv += jr * mu[i]; xv += jr * qvel[i]; yv += jr * a[i];
       }
       float al = 0.f, be = 0.f, ga = 0.f, rho = 0.f;
@@ -402,7 +399,7 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
       for (int r = 0; r < nrow; r++) {
         const float* o = rs + 7 * r;
         if (!row_quad(D[r], r < nrf ? 0.f : fl[r], e[r])) continue;
-        vadd += o[4] * J[r * nv + k];
+        vadd += o[4] * row_entry(m, W, r, k, ncon);
         if (r >= nrc) continue;  // limit and friction rows: constant Jacobians
         const float* rec = con + kConRec * (r >> 2);
         const int b1 = __float_as_int(rec[14]), b2 = __float_as_int(rec[15]);

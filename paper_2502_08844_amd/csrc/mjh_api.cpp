@@ -410,6 +410,10 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   }
   if (d.con_nr != 3 && d.con_nr != 4) d.con_nr = 0;  // the fast path: 3 and 4 rows
   d.nrowmax = d.conrows * h.nconmax + d.nlim + d.nfric + d.neqrow;
+  d.jframe = (!h.cone && d.con_nr == 4) ? 1 : 0;
+  // J rows: a frame-row contact keeps 3 of its 4 edge rows' worth
+  const int njrow = d.jframe ? 3 * h.nconmax + d.nlim + d.nfric + d.neqrow : d.nrowmax;
+  const int nfw = d.jframe ? 5 * h.nconmax + d.nlim + d.nfric + d.neqrow : 0;
   // pairs and candidate slots
   std::vector<int> pair_kind, pair_candadr, cand_pair;
   int ncand = 0;
@@ -564,7 +568,8 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   else d.o_cand = take(2 * ncand);
   d.o_con = take(kConRec * h.nconmax);
   d.o_lim = take(d.nlim);  // violated limits: joint-limit index | 0x10000 for the upper end
-  d.o_J = take(nr * nv);
+  d.o_J = take(njrow * nv);
+  d.o_fw = take(nfw);
   // the reference accelerations are read once, when Newton forms its residuals, before
   // the first Hessian is built: they too share H's words
   d.o_aref = nr <= d.ntri ? d.o_H : take(nr);
@@ -611,7 +616,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   x.o_cinert = take(kCinert * nb); x.o_F = take(6 * nv);
   x.o_H = take(d.ntri); x.o_Mr = take(nv); x.o_g = take(nv); x.o_d = take(nv);
   x.o_Md = take(nv); x.o_tmp = take(nv); x.o_cand = take(2 * ncand);
-  x.o_con = take(kConRec * h.nconmax); x.o_lim = take(d.nlim); x.o_J = take(nr * nv);
+  x.o_con = take(kConRec * h.nconmax); x.o_lim = take(d.nlim); x.o_J = take(njrow * nv);
   x.o_aref = take(nr);
   x.o_D = take(nr); x.o_e = take(nr); x.o_s = take(nr); x.o_fl = take(d.nfric + d.neq > 0 ? nr : 0);
   x.o_qbi = take(h.nq); x.o_vbi = take(nv); x.o_qb = take(h.nq); x.o_vb = take(nv);
@@ -621,6 +626,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   x.o_Vbar = take(6 * nb); x.o_Abar = take(6 * nb); x.o_Fbar = take(6 * nb);
   x.o_vup = take(6 * nb); x.o_aup = take(6 * nb); x.o_xup = take(3 * nb);
   x.o_Rup = take(9 * nb); x.o_rowsc = take(7 * nr); x.o_consc = take(10 * h.nconmax);
+  x.o_fw = take(nfw);
   x.lds_words = off;
   off = d.lds_words;
   d.lds_words = off;
@@ -1173,6 +1179,21 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
   const int blocks[3] = {64, 128, 256};
   std::vector<int> counts;
   for (auto& o : b->groups) counts.push_back(o.nworld);
+  // each probed group's three fastest shapes alone, for the combined pass below
+  std::vector<std::vector<std::pair<float, std::pair<int, int>>>> solo(b->groups.size());
+  auto probe = [&](float& ms) {
+    bool good = true;
+    for (int rep = 0; good && rep < 2; rep++) {  // the first run warms caches
+      good = restore() && hip_ok(hipEventRecord(e0, nullptr), "autotune: event") &&
+             hip_ok(launch_step(b->d_groups, b->d_tasks, b->ntask, nstep_probe, b->block,
+                                b->lds_bytes, b->tab_words, b->rk4, b->cone, nullptr),
+                    "autotune: probe launch") &&
+             hip_ok(hipEventRecord(e1, nullptr), "autotune: event") &&
+             hip_ok(hipEventSynchronize(e1), "autotune: probe") &&
+             hip_ok(hipEventElapsedTime(&ms, e0, e1), "autotune: event");
+    }
+    return good;
+  };
   for (size_t g = 0; ok && g < b->groups.size(); g++) {
     GroupRec& gr = b->groups[g];
     if (gr.nworld == 0) continue;
@@ -1198,24 +1219,54 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
         st = sync_tables(b);
         if (st != MJH_OK) { ok = false; break; }
         float ms = 0.f;
-        for (int rep = 0; ok && rep < 2; rep++) {  // the first run warms caches
-          ok = restore() && hip_ok(hipEventRecord(e0, nullptr), "autotune: event") &&
-               hip_ok(launch_step(b->d_groups, b->d_tasks, b->ntask, nstep_probe, b->block,
-                                  b->lds_bytes, b->tab_words, b->rk4, b->cone, nullptr),
-                      "autotune: probe launch") &&
-               hip_ok(hipEventRecord(e1, nullptr), "autotune: event") &&
-               hip_ok(hipEventSynchronize(e1), "autotune: probe") &&
-               hip_ok(hipEventElapsedTime(&ms, e0, e1), "autotune: event");
-        }
+        ok = probe(ms);
+        if (ok) solo[g].push_back({ms, {t, bl}});
         if (ok && ms < best) { best = ms; bt = t; bb = bl; }
       }
     for (size_t o = 0; o < b->groups.size(); o++) b->groups[o].nworld = counts[o];
     gr.team = bt;
     gr.block = bb;
     b->dirty = true;
-    if (ok) cache[key] = {bt, bb};
   }
   for (size_t o = 0; o < b->groups.size(); o++) b->groups[o].nworld = counts[o];
+  // A batch of several groups runs as one launch whose block and LDS size are the
+  // largest any group needs, so the groups' solo choices can starve each other: one pass
+  // over the groups tries each one's three fastest solo shapes in the combined launch.
+  int nactive = 0;
+  for (auto& o : b->groups) nactive += o.nworld > 0;
+  if (ok && nactive >= 2) {
+    float cur = INFINITY;
+    b->dirty = true;
+    st = sync_tables(b);
+    ok = st == MJH_OK && probe(cur);
+    for (size_t g = 0; ok && g < b->groups.size(); g++) {
+      std::sort(solo[g].begin(), solo[g].end());
+      GroupRec& gr = b->groups[g];
+      for (size_t k = 0; ok && k < solo[g].size() && k < 3; k++) {
+        const int t = solo[g][k].second.first, bl = solo[g][k].second.second;
+        if (t == gr.team && bl == gr.block) continue;
+        const int t0 = gr.team, b0 = gr.block;
+        gr.team = t;
+        gr.block = bl;
+        b->dirty = true;
+        st = sync_tables(b);
+        if (st != MJH_OK) { ok = false; break; }
+        float ms = 0.f;
+        ok = probe(ms);
+        if (ok && ms < cur) {
+          cur = ms;
+        } else {
+          gr.team = t0;
+          gr.block = b0;
+          b->dirty = true;
+        }
+      }
+    }
+  }
+  for (size_t g = 0; ok && g < b->groups.size(); g++)
+    if (b->groups[g].nworld > 0)
+      cache[tune_key(ctx->models[b->groups[g].model]->dm, b->groups[g].nworld)] =
+          {b->groups[g].team, b->groups[g].block};
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   const bool restored = restore();

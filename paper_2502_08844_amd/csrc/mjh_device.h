@@ -1140,9 +1140,13 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
     const int slot = __float_as_int(r[17]);
     const int first = m.con_nr ? m.con_nr * c : slot >> 8, nr = m.con_nr ? m.con_nr : (slot >> 4) & 15;
     const float jn = dot3(r + 4, jd);
-    float* Jr = J + first * nv + i;
+    float* Jr = J + (m.jframe ? 3 * c : first) * nv + i;
     if (nr == 1) {  // frictionless
       Jr[0] = jn;
+    } else if (m.jframe) {  // the pyramid's frame: normal, tangents
+      Jr[0] = jn;
+      Jr[nv] = dot3(r + 7, jd);
+      Jr[2 * nv] = dot3(r + 10, jd);
     } else if (m.cone) {  // elliptic: normal, tangents, spin (condim 4), rolling (6)
       Jr[0] = jn;
       Jr[nv] = dot3(r + 7, jd);
@@ -1176,16 +1180,18 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
       }
     }
   }
+  // J row of row nrc (the first non-contact row): frame-row contacts keep 3 of their 4
+  float* Jo = J + (m.jframe ? 3 * ncon : nrc) * nv;
   for (int idx = t.lane; idx < nl * nv; idx += t.T) {
     const int k = idx / nv, i = idx - k * nv;
     int dof;
     float sg, dist;
     limit_row(m, W, lim[k], dof, sg, dist);
-    J[(nrc + k) * nv + i] = i == dof ? sg : 0.f;
+    Jo[k * nv + i] = i == dof ? sg : 0.f;
   }
   for (int idx = t.lane; idx < m.nfric * nv; idx += t.T) {
     const int k = idx / nv, i = idx - k * nv;
-    J[(nrf + k) * nv + i] = i == m.fric_dadr[k] ? 1.f : 0.f;
+    Jo[(nl + k) * nv + i] = i == m.fric_dadr[k] ? 1.f : 0.f;
   }
   for (int idx = t.lane; idx < m.neqrow * nv; idx += t.T) {
     const int er = idx / nv, i = idx - er * nv;
@@ -1211,12 +1217,22 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
     } else {  // rotational: J_w(b1) - J_w(b2), component k - 3
       jv = (in1 ? S[k - 3] : 0.f) - (in2 ? S[k - 3] : 0.f);
     }
-    J[(nre + er) * nv + i] = jv;
+    Jo[(nl + m.nfric + er) * nv + i] = jv;
   }
   t.sync();
   const float* qvel = W + m.o_qvel;
   float* aref = W + m.o_aref;
   float* D = W + m.o_D;
+  // frame-row contacts: the rows' J qvel from their frames' products, staged in o_fw
+  float* pf = W + m.o_fw;
+  if (m.jframe) {
+    for (int f = t.lane; f < nrow - ncon; f += t.T) {
+      float v = 0.f;
+      for (int i = 0; i < nv; i++) v += J[f * nv + i] * qvel[i];
+      pf[f] = v;
+    }
+    t.sync();
+  }
   for (int row = t.lane; row < nrow; row += t.T) {
     float dist, jv = 0.f, A;
     if (row < nrc) {
@@ -1225,7 +1241,12 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
         while (c + 1 < ncon && (__float_as_int(con[kConRec * (c + 1) + 17]) >> 8) <= row) c++;
       const float* r = con + kConRec * c;
       dist = r[0];
-      for (int i = 0; i < nv; i++) jv += J[row * nv + i] * qvel[i];
+      if (m.jframe) {
+        const int k = row & 3;
+        jv = pf[3 * c] + ((k & 1) ? -r[13] : r[13]) * pf[3 * c + 1 + (k >> 1)];
+      } else {
+        for (int i = 0; i < nv; i++) jv += J[row * nv + i] * qvel[i];
+      }
       const int b1 = __float_as_int(r[14]), b2 = __float_as_int(r[15]);
       const float mu = r[13];  // 0 for a frictionless contact: A = w1 + w2
       if (m.cone) {
@@ -1267,7 +1288,11 @@ DEV void constraint_rows(const DevModel& m, float* W, const Team& t) {
       } else {
         dist = weld_residual(m, W, q, k - 3);
       }
-      for (int i = 0; i < nv; i++) jv += J[row * nv + i] * qvel[i];
+      if (m.jframe) {
+        jv = pf[row - ncon];
+      } else {
+        for (int i = 0; i < nv; i++) jv += J[row * nv + i] * qvel[i];
+      }
       A = m.body_invweight[m.eq_body[2 * q]] + m.body_invweight[m.eq_body[2 * q + 1]];
     }
     const float imp = impedance(m, dist);
@@ -1309,28 +1334,145 @@ DEV int row_piece(float D, float F, float e) {
 // that left the kernel never wrote theirs, and cross-lane operations are not used here
 // because teams may be inactive.  A world's rows from its own count up to the bound are
 // zeroed (J, D, e, s), so they add nothing to gradients, Hessian or line search.
-// Returns the bound.
-DEV int pad_rows(const DevModel& m, float* W, const Team& t, int nrow) {
+// With frame-row contacts (jframe) the non-contact rows follow a world's 4 ncon edge
+// rows and 3 ncon frame rows; their loops run to nou, the largest non-contact row count
+// in the wavefront, and the padding reaches edge row 4 ncon + nou and J row 3 ncon + nou.
+struct RowBounds {
+  int nru;  // rows
+  int nou;  // non-contact rows (jframe only, else 0)
+};
+DEV RowBounds pad_rows(const DevModel& m, float* W, const Team& t, int nrow) {
   const int tw = 64 / t.T;                              // teams per wavefront
   const int my = (int)((threadIdx.x & 63) / t.T);      // this team's place in it
-  int mx = 0;
+  // a team that left holds stale counts: clamping them to the model's maxima keeps every
+  // padded index inside its region (non-contact rows: at most nrowmax - 4 nconmax)
+  const int nomax = m.nrowmax - 4 * m.nconmax;
+  int mx = 0, mo = 0;
   for (int k = 0; k < tw; k++) {
     const int* sk = (const int*)(W + (k - my) * m.lds_words + m.o_scal);
-    const int nr = sk[SC_NROW];
-    mx = max(mx, min(max(nr, 0), m.nrowmax));
+    const int nr = min(max(sk[SC_NROW], 0), m.nrowmax);
+    mx = max(mx, nr);
+    if (m.jframe)
+      mo = max(mo, min(max(nr - 4 * min(max(sk[SC_NCON], 0), m.nconmax), 0), nomax));
   }
-  // every active lane computed the same mx, and this team's own count is among them
-  const int nru = __builtin_amdgcn_readfirstlane(mx);
+  // every active lane computed the same bounds, and this team's own counts are among them
+  RowBounds rb;
+  rb.nru = __builtin_amdgcn_readfirstlane(mx);
+  rb.nou = __builtin_amdgcn_readfirstlane(mo);
+  const int nv = m.nv;
+  int rend = rb.nru, jfirst = nrow, jend = rb.nru;  // zeroed: rows [nrow, rend), J rows [jfirst, jend)
+  if (m.jframe) {
+    const int ncon = ((const int*)(W + m.o_scal))[SC_NCON];
+    rend = max(rb.nru, 4 * ncon + rb.nou);
+    jfirst = nrow - ncon;
+    jend = 3 * ncon + rb.nou;
+  }
   float* J = W + m.o_J;
-  for (int k = nrow * m.nv + t.lane; k < nru * m.nv; k += t.T) J[k] = 0.f;
+  for (int k = jfirst * nv + t.lane; k < jend * nv; k += t.T) J[k] = 0.f;
   float* D = W + m.o_D;
   float* e = W + m.o_e;
   float* s = W + m.o_s;
-  for (int r = nrow + t.lane; r < nru; r += t.T) { D[r] = 0.f; e[r] = 0.f; s[r] = 0.f; }
+  for (int r = nrow + t.lane; r < rend; r += t.T) { D[r] = 0.f; e[r] = 0.f; s[r] = 0.f; }
   if (has_bounds(m))
-    for (int r = nrow + t.lane; r < nru; r += t.T) W[m.o_fl + r] = 0.f;
+    for (int r = nrow + t.lane; r < rend; r += t.T) W[m.o_fl + r] = 0.f;
   t.sync();
-  return nru;
+  return rb;
+}
+
+// Entry i of row r's Jacobian (nrc = 4 ncon contact rows; frame-row contacts form the
+// edge J_n +- mu J_tk from their frames).  For the few per-row reads of the adjoint.
+DEV float row_entry(const DevModel& m, const float* W, int r, int i, int ncon) {
+  const float* J = W + m.o_J;
+  const int nv = m.nv;
+  if (!m.jframe) return J[r * nv + i];
+  if (r >= 4 * ncon) return J[(r - ncon) * nv + i];
+  const int c = r >> 2, k = r & 3;
+  const float mu = W[m.o_con + kConRec * c + 13];
+  return J[3 * c * nv + i] + ((k & 1) ? -mu : mu) * J[(3 * c + 1 + (k >> 1)) * nv + i];
+}
+
+// Products with the constraint rows.  rows_times: out[r] = J_r x for r < max(nru, 4 ncon
+// + nou) (0 past the world's rows).  rows_t_times: out_i = init_i + sum_r y(r) J_ri over
+// the same rows, y a row functor (0 past the world's rows).  With frame-row contacts the
+// frames' products (or weights) are staged in o_fw: a contact's edges J_n +- mu J_tk take
+// J_n x +- mu J_tk x, and its frames' weights are sum_e y_e on J_n and mu (y_+ - y_-) on
+// J_tk.  Both end with a barrier; out may alias init.
+DEV void rows_times(const DevModel& m, float* W0, const Team& t0, int nrow, const RowBounds& rb,
+                    const float* x, float* out) {
+  float* W = W0 + opaque_zero();
+  const Team t{t0.lane + opaque_zero(), t0.T, t0.tp};
+  const int nv = m.nv;
+  const float* J = W + m.o_J;
+  if (!m.jframe) {
+    for (int r = t.lane; r < rb.nru; r += t.T) {
+      float v = 0.f;
+      for (int i = 0; i < nv; i++) v += J[r * nv + i] * x[i];
+      out[r] = v;
+    }
+    t.sync();
+    return;
+  }
+  const int ncon = ((const int*)(W + m.o_scal))[SC_NCON];
+  const float* con = W + m.o_con;
+  float* pf = W + m.o_fw;
+  const int nf = 3 * ncon + rb.nou;
+  for (int f = t.lane; f < nf; f += t.T) {
+    float v = 0.f;
+    for (int i = 0; i < nv; i++) v += J[f * nv + i] * x[i];
+    pf[f] = v;
+  }
+  t.sync();
+  for (int c = t.lane; c < ncon; c += t.T) {
+    const float mu = con[kConRec * c + 13];
+    const float pn = pf[3 * c], p1 = mu * pf[3 * c + 1], p2 = mu * pf[3 * c + 2];
+    out[4 * c] = pn + p1;
+    out[4 * c + 1] = pn - p1;
+    out[4 * c + 2] = pn + p2;
+    out[4 * c + 3] = pn - p2;
+  }
+  const int r0 = 4 * ncon, rend = max(rb.nru, r0 + rb.nou);
+  for (int r = r0 + t.lane; r < rend; r += t.T) {
+    const int k = r - r0;
+    out[r] = (k < rb.nou && r < nrow) ? pf[3 * ncon + k] : 0.f;
+  }
+  t.sync();
+}
+
+template <class Y>
+DEV void rows_t_times(const DevModel& m, float* W0, const Team& t0, const RowBounds& rb, Y y,
+                      const float* init, float* out) {
+  float* W = W0 + opaque_zero();
+  const Team t{t0.lane + opaque_zero(), t0.T, t0.tp};
+  const int nv = m.nv;
+  const float* J = W + m.o_J;
+  if (!m.jframe) {
+    for (int i = t.lane; i < nv; i += t.T) {
+      float v = init ? init[i] : 0.f;
+      for (int r = 0; r < rb.nru; r++) v += y(r) * J[r * nv + i];
+      out[i] = v;
+    }
+    t.sync();
+    return;
+  }
+  const int ncon = ((const int*)(W + m.o_scal))[SC_NCON];
+  const float* con = W + m.o_con;
+  float* fy = W + m.o_fw;
+  for (int c = t.lane; c < ncon; c += t.T) {
+    const float mu = con[kConRec * c + 13];
+    const float y0 = y(4 * c), y1 = y(4 * c + 1), y2 = y(4 * c + 2), y3 = y(4 * c + 3);
+    fy[3 * c] = (y0 + y1) + (y2 + y3);
+    fy[3 * c + 1] = mu * (y0 - y1);
+    fy[3 * c + 2] = mu * (y2 - y3);
+  }
+  for (int k = t.lane; k < rb.nou; k += t.T) fy[3 * ncon + k] = y(4 * ncon + k);
+  t.sync();
+  const int nf = 3 * ncon + rb.nou;
+  for (int i = t.lane; i < nv; i += t.T) {
+    float v = init ? init[i] : 0.f;
+    for (int f = 0; f < nf; f++) v += fy[f] * J[f * nv + i];
+    out[i] = v;
+  }
+  t.sync();
 }
 
 // H = M + sum_{rows with e < 0} D J^T J (packed lower), factorised in place as L L^T.
@@ -1342,10 +1484,12 @@ DEV int pad_rows(const DevModel& m, float* W, const Team& t, int nrow) {
 // pivot.  `w` (nrow words) receives the rows' curvatures: D on the quadratic piece, else 0.
 // Jh (default the constraint rows J) and w_given (the caller stored the weights in the
 // o_s words) let the elliptic-cone solve pass its own Hessian rows and weights.
-DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
+DEV bool hessian_cholesky(const DevModel& m, float* W0, const Team& t0, int nru,
                           float* b = nullptr, float* y = nullptr, bool rev = false,
                           bool hgain = false, const float* Jh = nullptr,
-                          bool w_given = false) {
+                          bool w_given = false, int nou = 0) {
+  float* W = W0 + opaque_zero();
+  const Team t{t0.lane + opaque_zero(), t0.T, t0.tp};
   const int nv = m.nv;
   const float* M = W + m.o_M;
   float* H = W + m.o_H;
@@ -1353,12 +1497,33 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
   const float* D = W + m.o_D;
   const float* e = W + m.o_e;
   float* w = W + m.o_s;  // row weights; the line search rewrites this scratch later
+  // frame-row contacts: the rows run to 4 ncon + nou (pad_rows), and each contact's four
+  // edges J_n +- mu J_tk with weights w0..w3 add J3^T C J3 to H over its frames J3 =
+  // (J_n, J_t1, J_t2), C = [[w0+w1+w2+w3, mu (w0-w1), mu (w2-w3)], [., mu^2 (w0+w1), 0],
+  // [., 0, mu^2 (w2+w3)]]; o_fw holds C's five entries per contact
+  const bool fr = m.jframe && !Jh && nru > 0;
+  const int ncon = fr ? ((const int*)(W + m.o_scal))[SC_NCON] : 0;
+  const int rend = fr ? max(nru, 4 * ncon + nou) : nru;
   if (w_given) {
   } else if (has_bounds(m)) {
     const float* fl = W + m.o_fl;
-    for (int r = t.lane; r < nru; r += t.T) w[r] = row_quad(D[r], fl[r], e[r]) ? D[r] : 0.f;
+    for (int r = t.lane; r < rend; r += t.T) w[r] = row_quad(D[r], fl[r], e[r]) ? D[r] : 0.f;
   } else {
-    for (int r = t.lane; r < nru; r += t.T) w[r] = e[r] < 0.f ? D[r] : 0.f;
+    for (int r = t.lane; r < rend; r += t.T) w[r] = e[r] < 0.f ? D[r] : 0.f;
+  }
+  const float* con = W + m.o_con;
+  float* cf = W + m.o_fw;
+  if (fr) {
+    t.sync();
+    for (int c = t.lane; c < ncon; c += t.T) {
+      const float mu = con[kConRec * c + 13];
+      const float w0 = w[4 * c], w1 = w[4 * c + 1], w2 = w[4 * c + 2], w3 = w[4 * c + 3];
+      cf[5 * c] = (w0 + w1) + (w2 + w3);
+      cf[5 * c + 1] = mu * (w0 - w1);
+      cf[5 * c + 2] = mu * mu * (w0 + w1);
+      cf[5 * c + 3] = mu * (w2 - w3);
+      cf[5 * c + 4] = mu * mu * (w2 + w3);
+    }
   }
   t.sync();
   if (t.T == 64 && nv <= 32) {
@@ -1376,11 +1541,20 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
       C[v] = (i < nv && j <= i) ? (rev ? M[tri(nv - 1 - j, nv - 1 - i)] : M[tri(i, j)]) : 0.f;
       if (hgain && i < nv && j == i) C[v] += m.dt * m.dof_vgain[rev ? nv - 1 - i : i];
     }
-    for (int r = 0; r < nr; r += 2) {
+    const int nrf = fr ? rend : nr;
+    for (int r = 0; r < nrf; r += 2) {
       const int rr = r + kh;
       float a = 0.f, b = 0.f;
-      if (rr < nr && j < nv) {
-        b = J[rr * nv + j];
+      if (rr < nrf && j < nv) {
+        if (!fr) {
+          b = J[rr * nv + j];
+        } else if (rr < 4 * ncon) {  // edge rr & 3 of contact rr / 4 from its frames
+          const int c = rr >> 2, k = rr & 3;
+          const float mu = con[kConRec * c + 13];
+          b = J[3 * c * nv + j] + ((k & 1) ? -mu : mu) * J[(3 * c + 1 + (k >> 1)) * nv + j];
+        } else {
+          b = J[(rr - ncon) * nv + j];
+        }
         a = w[rr] * b;
       }
       C = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, C, 0, 0, 0);
@@ -1396,7 +1570,21 @@ DEV bool hessian_cholesky(const DevModel& m, float* W, const Team& t, int nru,
       t.unrank(k, i, j);
       float v = rev ? M[tri(nv - 1 - j, nv - 1 - i)] : M[k];
       if (hgain && i == j) v += m.dt * m.dof_vgain[rev ? nv - 1 - i : i];
-      for (int r = 0; r < nru; r++) v += w[r] * J[r * nv + i] * J[r * nv + j];
+      if (!fr) {
+        for (int r = 0; r < nru; r++) v += w[r] * J[r * nv + i] * J[r * nv + j];
+      } else {
+        for (int c = 0; c < ncon; c++) {
+          const float* q = cf + 5 * c;
+          const float* Jn = J + 3 * c * nv;
+          const float ni = Jn[i], nj = Jn[j], ai = Jn[nv + i], aj = Jn[nv + j];
+          const float bi = Jn[2 * nv + i], bj = Jn[2 * nv + j];
+          v += q[0] * ni * nj + q[2] * ai * aj + q[4] * bi * bj + q[1] * (ni * aj + ai * nj) +
+               q[3] * (ni * bj + bi * nj);
+        }
+        const float* Jo = J + 3 * ncon * nv;
+        const float* wo = w + 4 * ncon;
+        for (int k2 = 0; k2 < nou; k2++) v += wo[k2] * Jo[k2 * nv + i] * Jo[k2 * nv + j];
+      }
       H[k] = v;
     }
   }
@@ -1610,7 +1798,6 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
   const int* scal = (const int*)(W + m.o_scal);
   const int nv = m.nv, nrow = scal[SC_NROW];
   const float* M = W + m.o_M;
-  const float* J = W + m.o_J;
   const float* aref = W + m.o_aref;
   const float* D = W + m.o_D;
   float* e = W + m.o_e;     // J a - aref
@@ -1627,7 +1814,10 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
     t.sync();
     return;
   }
-  const int nru = pad_rows(m, W, t, nrow);
+  const RowBounds rb = pad_rows(m, W, t, nrow);
+  const int nru = rb.nru;
+  // rows the row products define (frame-row contacts: to 4 ncon + nou, see pad_rows)
+  const int rend = m.jframe ? max(nru, 4 * scal[SC_NCON] + rb.nou) : nru;
   // ---- start point: cost of the warm start vs cost of a0
   for (int i = t.lane; i < nv; i += t.T) tmp[i] = a[i] - a0[i];
   t.sync();
@@ -1638,11 +1828,11 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
     Mr[i] = v;
     qw += 0.5f * tmp[i] * v;
   }
+  rows_times(m, W, t, nrow, rb, a, e);
+  rows_times(m, W, t, nrow, rb, a0, s);
   float cw = 0.f, c0 = 0.f;
   for (int r = t.lane; r < nrow; r += t.T) {
-    float jw = 0.f, j0 = 0.f;
-    for (int i = 0; i < nv; i++) { jw += J[r * nv + i] * a[i]; j0 += J[r * nv + i] * a0[i]; }
-    const float ew = jw - aref[r], e0 = j0 - aref[r];
+    const float ew = e[r] - aref[r], e0 = s[r] - aref[r];
     if (FR) {
       cw += row_cost(D[r], fl[r], ew);
       c0 += row_cost(D[r], fl[r], e0);
@@ -1670,40 +1860,37 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
   }
   for (int it = 0; it < iters; it++) {
     // ---- gradient g = M (a - a0) + sum_active D e J
+    rows_t_times(m, W, t, rb, [&](int r) {
+      const float er = e[r];
+      return FR ? row_slope(D[r], fl[r], er) : (er < 0.f ? D[r] * er : 0.f);
+    }, Mr, g);
     float gmax = 0.f;
-    for (int i = t.lane; i < nv; i += t.T) {
-      float v = Mr[i];
-      for (int r = 0; r < nru; r++) {
-        const float er = e[r];
-        v += (FR ? row_slope(D[r], fl[r], er) : (er < 0.f ? D[r] * er : 0.f)) * J[r * nv + i];
-      }
-      g[i] = v;
-      gmax = fmaxf(gmax, fabsf(v));
-    }
+    for (int i = t.lane; i < nv; i += t.T) gmax = fmaxf(gmax, fabsf(g[i]));
     if (gtol > 0.f && t.max(gmax) <= gstop) break;  // converged to FP32 precision
     for (int i = t.lane; i < nv; i += t.T) d[i] = -g[i];
     // ---- delta = -H^-1 g: forward solve fused into the factorisation, then back
-    if (!hessian_cholesky(m, W, t, nru, d, tmp)) { status |= 4; break; }
+    if (!hessian_cholesky(m, W, t, nru, d, tmp, false, false, nullptr, false, rb.nou)) {
+      status |= 4;
+      break;
+    }
     cholesky_back(m, W, t, tmp, d);
     // ---- one step of iterative refinement: the FP32 factor of H carries a relative
     // error near cond(H) eps into d, and the fixed iteration count leaves the iterate
     // mid-path, where such errors compound.  The residual r = g + H d, with H applied
     // unassembled (M d + sum over rows on their quadratic piece of D J^T (J d)), is
     // accurate to the gradient's own rounding; d -= H^-1 r with the same factor.
-    for (int r = t.lane; r < nru; r += t.T) {
-      float v = 0.f;
-      for (int i = 0; i < nv; i++) v += J[r * nv + i] * d[i];
+    rows_times(m, W, t, nrow, rb, d, s);
+    for (int r = t.lane; r < rend; r += t.T) {
       const bool q = FR ? row_quad(D[r], fl[r], e[r]) : e[r] < 0.f;
-      s[r] = q ? D[r] * v : 0.f;
+      s[r] = q ? D[r] * s[r] : 0.f;
     }
-    t.sync();
     for (int i = t.lane; i < nv; i += t.T) {
       float v = g[i];
       for (int k = 0; k < nv; k++) v += M[sym(i, k)] * d[k];
-      for (int r = 0; r < nru; r++) v += s[r] * J[r * nv + i];
       tmp[i] = v;
     }
     t.sync();
+    rows_t_times(m, W, t, rb, [&](int r) { return s[r]; }, tmp, tmp);
     cholesky_solve(m, W, t, tmp, tmp, 1.f);
     float cmax = 0.f;  // size of the correction: the unrefined direction's error
     for (int i = t.lane; i < nv; i += t.T) {
@@ -1721,11 +1908,7 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
       dMd += d[i] * v;
       dMr += d[i] * Mr[i];
     }
-    for (int r = t.lane; r < nrow; r += t.T) {
-      float v = 0.f;
-      for (int i = 0; i < nv; i++) v += J[r * nv + i] * d[i];
-      s[r] = v;
-    }
+    rows_times(m, W, t, nrow, rb, d, s);
     gd = t.sum(gd);
     dMd = t.sum(dMd);
     dMr = t.sum(dMr);
@@ -1924,7 +2107,7 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
     t.sync();
     return;
   }
-  const int nru = pad_rows(m, W, t, nrow);
+  const int nru = pad_rows(m, W, t, nrow).nru;
   auto row_s = [&](int r, float ev) {  // a non-cone row's slope
     return FR ? row_slope(D[r], fl[r], ev) : fminf(D[r] * ev, 0.f);
   };
@@ -2278,7 +2461,6 @@ DEV void integrate(const DevModel& m, float* W, const Team& t, int& status) {
 DEV void implicit_damping(const DevModel& m, float* W, const Team& t) {
   const int* scal = (const int*)(W + m.o_scal);
   const int nv = m.nv, nrow = scal[SC_NROW];
-  const float* J = W + m.o_J;
   const float* D = W + m.o_D;
   const float* e = W + m.o_e;
   const float* fl = W + m.o_fl;
@@ -2286,14 +2468,13 @@ DEV void implicit_damping(const DevModel& m, float* W, const Team& t) {
   float* rhs = W + m.o_frc;
   const float* qvel = W + m.o_qvel;
   const float* sl = W + m.o_sl;  // elliptic cones: the solve's final slopes
-  for (int i = t.lane; i < nv; i += t.T) {
-    float v = m.implicit == 2 ? rhs[i] - m.dof_hkp[i] * qvel[i] : rhs[i];
-    for (int r = 0; r < nrow; r++)
-      v -= (m.cone ? sl[r] : (fr ? row_slope(D[r], fl[r], e[r]) : fminf(D[r] * e[r], 0.f))) *
-           J[r * nv + i];
-    rhs[i] = v;
-  }
-  t.sync();
+  if (m.implicit == 2)
+    for (int i = t.lane; i < nv; i += t.T) rhs[i] -= m.dof_hkp[i] * qvel[i];
+  const RowBounds rb = pad_rows(m, W, t, nrow);  // the solve's padding, rebuilt
+  rows_t_times(m, W, t, rb, [&](int r) {
+    if (r >= nrow) return 0.f;
+    return -(m.cone ? sl[r] : (fr ? row_slope(D[r], fl[r], e[r]) : fminf(D[r] * e[r], 0.f)));
+  }, rhs, rhs);
   if (nv <= t.T) {
     // the smooth phase's dense factor in leaves-first order, of M + h diag(dof_vgain),
     // solved in place in rhs in reversed order

@@ -40,6 +40,11 @@ struct DevModel {
                  // 3: elliptic cone, both condim 3; contact c's rows are con_nr c ..),
                  // else 0 (first row and count packed in the contact record)
   int cone;      // friction cone: 0 pyramidal (edge rows), 1 elliptic (frame rows)
+  int jframe;    // 1: every contact is a condim-3 pyramid whose Jacobian is stored as its
+                 // three frame rows (normal, t1, t2); its four edge rows J_n +- mu J_tk
+                 // are formed where they are used.  Contact c's frames are J rows 3c ..
+                 // 3c + 2, its edges rows 4c .. 4c + 3 of the per-row arrays, and a
+                 // non-contact row r >= 4 ncon is J row r - ncon.
   int iterations, nlevel, nmpair, ntri;
   int implicit;  // 1: joint damping and PD velocity gains integrated implicitly;
                  // 2: also the PD position gains
@@ -130,6 +135,8 @@ struct DevModel {
   int o_M, o_H;
   int o_frc, o_a0, o_Mr, o_g, o_d, o_Md, o_tmp;
   int o_cand, o_con, o_lim, o_J, o_aref, o_D, o_e, o_s, o_fl, o_scal;
+  int o_fw;  // jframe only: per-frame staging of products and weights, and each
+             // contact's five Hessian coefficients (5 nconmax + non-contact rows words)
   int o_rk;  // Runge-Kutta block (rk4 only): q0 [nq], v0, a1, vsum, asum [nv each]
   int o_Jv, o_sl;  // elliptic cones only: Hessian rows [nrowmax][nv], row slopes [nrowmax]
   int o_cv;        // elliptic cones only: each contact's virtual-row map [nconmax][conrows^2]

@@ -41,6 +41,12 @@ def run_gpu(ctx, mjh, m, qpos, qvel, qacc_ws, ctrl, nstep, team=None, block=None
     return res
 
 
+# A world whose qacc error exceeds this is tested for a switch inside the solve's
+# iteration path (see compare_step).
+PATH_TOL = 1e-4
+PATH_REL, PATH_DRAWS = 1e-7, 24
+
+
 def compare_step(m, o, state, ctrl1, gpu1, mode=oracle.MODE_FIXED, near=1e-5):
     """Compare one GPU step (gpu1) with the reference step from the same float32 state.
 
@@ -48,7 +54,17 @@ def compare_step(m, o, state, ctrl1, gpu1, mode=oracle.MODE_FIXED, near=1e-5):
     states near a switch (contact emission |dist| < near, a limited joint within near
     of its range end, a candidate set change, a one-sided row at its activation
     threshold, or a friction-loss row where |D e| meets its bound), which are
-    reported, not gated."""
+    reported, not gated.
+
+    A fixed-iteration solve can also meet a switch on its way: an intermediate iterate
+    that lands on a row's breakpoint makes the next Hessian, and everything after it, a
+    discrete choice that rounding decides.  Such a world's reference answer jumps when
+    its inputs move by FP32 rounding.  A world whose qacc error exceeds PATH_TOL is
+    stepped by the reference again from PATH_DRAWS inputs with qvel and the warm start
+    scaled by 1 + PATH_REL N(0, 1) (about FP32's rounding); if one of those answers
+    differs from the unperturbed one by more than PATH_TOL and the GPU's is within
+    PATH_TOL of it, the world is flagged (the GPU took the other branch) and the
+    distance to that branch is kept in err_branch."""
     qpos, qvel, ws = state
     nw = qpos.shape[0]
     ref = o.step(qpos.copy(), qvel.copy(), ws.copy(), ctrl1, nstep=1, mode=mode, nthreads=8)
@@ -124,8 +140,23 @@ def compare_step(m, o, state, ctrl1, gpu1, mode=oracle.MODE_FIXED, near=1e-5):
         err_f[w] = np.abs(cg[:, 13:16] - cr[:, 13:16]).max() / (mass * G)
         err_geo[w] = (np.abs(cg[:, 0] - cr[:, 0]).max(), np.abs(cg[:, 1:4] - cr[:, 1:4]).max(),
                       np.abs(cg[:, 4:7] - cr[:, 4:7]).max())
+    err_branch = np.full(nw, np.nan)
+    rng = np.random.default_rng(12345)
+    for w in np.flatnonzero((err_a > PATH_TOL) & ~flag):
+        a_r, a_g = ref["qacc"][w], gpu1["qacc"][w]
+        sc = max(np.abs(a_r).max(), G)
+        u1 = ctrl1[0, w] if ctrl1 is not None else None
+        for _ in range(PATH_DRAWS):
+            qv = qvel[w] * (1 + PATH_REL * rng.standard_normal(qvel.shape[1]))
+            wp = ws[w] * (1 + PATH_REL * rng.standard_normal(ws.shape[1]))
+            a_p = o.forward(qpos[w], qv, wp, u1, mode=mode)["qacc"]
+            if np.abs(a_p - a_r).max() / sc > PATH_TOL and np.abs(a_g - a_p).max() / sc <= PATH_TOL:
+                flag[w] = True
+                err_branch[w] = np.abs(a_g - a_p).max() / sc
+                break
     return dict(err_a=err_a, err_f=err_f, err_geo=err_geo, flag=flag, ref=ref,
-                state=state, ctrl=ctrl1, gpu_qacc=gpu1["qacc"], gpu_contacts=gpu1.get("contacts"))
+                state=state, ctrl=ctrl1, gpu_qacc=gpu1["qacc"], gpu_contacts=gpu1.get("contacts"),
+                err_branch=err_branch)
 
 
 def workload(kind, nw, nstep, seed=0):
@@ -164,10 +195,14 @@ def summarize(kind, stats):
     nflag = int(sum(s["flag"].sum() for s in stats))
     ntot = int(sum(len(s["flag"]) for s in stats))
     fa = np.concatenate([s["err_a"][s["flag"]] for s in stats])
+    eb = np.concatenate([s["err_branch"][np.isfinite(s["err_branch"])] for s in stats
+                         if "err_branch" in s])
     line = (f"[parity] {kind}: qacc rel err max {ea.max():.2e} p99 "
             f"{np.percentile(ea, 99):.2e}; contact force rel err max "
             f"{(ef.max() if ef.size else 0):.2e}; near-switch states {nflag}/{ntot}"
-            + (f" (their qacc err max {fa.max():.2e})" if fa.size else ""))
+            + (f" (their qacc err max {fa.max():.2e})" if fa.size else "")
+            + (f"; {eb.size} at a switch on the iteration path, within {eb.max():.2e} of the "
+               f"reference's other branch" if eb.size else ""))
     print(line, flush=True)
     # the worst unflagged world: its contacts, and optionally its state for offline study
     best = None

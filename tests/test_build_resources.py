@@ -33,9 +33,17 @@ def usage():
     return u
 
 
-@pytest.mark.parametrize("kernel,scratch_max", [(STEP, 32), (STEP_RK, 64), (STEP_CONE, 512),
-                                                (ENV, 160), (ENV_DR, 192), (ENV_RK, 160)])
+@pytest.mark.parametrize("kernel,scratch_max", [(STEP, 16), (STEP_RK, 16), (STEP_CONE, 416),
+                                                (ENV, 96), (ENV_DR, 112), (ENV_RK, 112)])
 def test_hot_kernels_fit_four_waves_with_small_scratch(usage, kernel, scratch_max):
     k = usage[kernel]
     assert k["VGPRs"] <= 128 and k["Occupancy"] >= 4
     assert k["ScratchSize"] <= scratch_max, k
+
+
+@pytest.mark.parametrize("kernel", [STEP, STEP_RK])
+def test_pyramid_step_kernels_spill_no_vgpr(usage, kernel):
+    """The Newton loop's helpers re-derive their LDS base and lane from an opaque zero;
+    without it the compiler hoisted their address arithmetic out of the iteration loop
+    and spilled 31 VGPRs of the plain step kernel."""
+    assert usage[kernel]["VGPRsSpill"] == 0, usage[kernel]
