@@ -2169,7 +2169,37 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
   }
   for (int it = 0; it < iters; it++) {
     // ---- slopes, Hessian weights and the cones' virtual-row maps
-    for (int c = t.lane; c < ncon; c += t.T) {
+    for (int c = t.lane; c < ncon && m.con_nr == 3; c += t.T) {
+      // condim-3 cones in registers (cone_eval's rows for nd = 3): sticking, the rows
+      // themselves with weight D; sliding, (-1, mu t) with D / (1 + mu^2) and the unit
+      // tangent across t with c psi mu / T; separated, nothing
+      const int f = 3 * c;
+      const float mu = con[kConRec * c + 13], Dn = D[f];
+      const float e0 = e[f], e1 = e[f + 1], e2 = e[f + 2];
+      const float Tn = sqrtf(e1 * e1 + e2 * e2);
+      float* V = cv + c * cw;
+      float sv0 = 0.f, sv1 = 0.f, sv2 = 0.f, w0 = 0.f, w1 = 0.f, w2 = 0.f;
+      for (int k = 0; k < 9; k++) V[k] = 0.f;
+      if (e0 < mu * Tn) {
+        if (mu * e0 + Tn <= 0.f) {
+          sv0 = Dn * e0; sv1 = Dn * e1; sv2 = Dn * e2;
+          w0 = w1 = w2 = Dn;
+          V[0] = V[4] = V[8] = 1.f;
+        } else {
+          const float inv = 1.f / Tn, psi = mu * Tn - e0, cc = Dn / (1.f + mu * mu);
+          sv0 = -cc * psi;
+          sv1 = cc * psi * mu * e1 * inv;
+          sv2 = cc * psi * mu * e2 * inv;
+          w0 = cc;
+          w1 = cc * psi * mu * inv;
+          V[0] = -1.f; V[1] = mu * e1 * inv; V[2] = mu * e2 * inv;
+          V[4] = -e2 * inv; V[5] = e1 * inv;
+        }
+      }
+      sl[f] = sv0; sl[f + 1] = sv1; sl[f + 2] = sv2;
+      s[f] = w0; s[f + 1] = w1; s[f + 2] = w2;
+    }
+    for (int c = t.lane; c < ncon && m.con_nr != 3; c += t.T) {
       int first;
       float mu, ratio[6], ev[6], sv[6], wv[6], cc;
       const int nd = cone_of(m, con, c, first, mu, ratio);
@@ -2194,7 +2224,11 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
     for (int idx = t.lane; idx < nru * nv; idx += t.T) {
       const int r = idx / nv, i = idx - r * nv;
       float v = J[idx];
-      if (r < nrc) {
+      if (r < nrc && m.con_nr == 3) {  // condim-3 cones: no per-row coefficients
+        const int c = r / 3, f = 3 * c;
+        const float* V = cv + c * cw + (r - f) * 3;
+        v = V[0] * J[f * nv + i] + V[1] * J[(f + 1) * nv + i] + V[2] * J[(f + 2) * nv + i];
+      } else if (r < nrc) {
         int c = m.con_nr ? r / m.con_nr : 0;
         if (!m.con_nr)
           while (c + 1 < ncon && (__float_as_int(con[kConRec * (c + 1) + 17]) >> 8) <= r) c++;
@@ -2262,6 +2296,36 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
     // phi'(al) and phi''(al), summed over the team
     auto dphi = [&](float al, float& d2) {
       float v = 0.f, h2 = 0.f;
+      if (m.con_nr == 3) {
+        // every contact a condim-3 cone: its rows' slope and curvature along s in
+        // registers (cone_eval's zones for nd = 3: sticking, D I; sliding, curvature
+        // c = D / (1 + mu^2) along (-1, mu t) and c psi mu / T across t)
+        for (int c = t.lane; c < ncon; c += t.T) {
+          const int f = 3 * c;
+          const float mu = con[kConRec * c + 13], Dn = D[f];
+          const float s0 = s[f], s1 = s[f + 1], s2 = s[f + 2];
+          const float e0 = e[f] + al * s0, e1 = e[f + 1] + al * s1, e2 = e[f + 2] + al * s2;
+          const float Tn = sqrtf(e1 * e1 + e2 * e2);
+          if (!(e0 < mu * Tn)) continue;  // separated
+          if (mu * e0 + Tn <= 0.f) {       // sticking
+            v += Dn * (s0 * e0 + s1 * e1 + s2 * e2);
+            h2 += Dn * (s0 * s0 + s1 * s1 + s2 * s2);
+          } else {                         // sliding on the cone's surface
+            const float inv = 1.f / Tn, psi = mu * Tn - e0, cc = Dn / (1.f + mu * mu);
+            const float q0 = mu * (e1 * s1 + e2 * s2) * inv - s0;
+            const float q1 = (e1 * s2 - e2 * s1) * inv;
+            v += cc * psi * q0;
+            h2 += cc * q0 * q0 + cc * psi * mu * inv * q1 * q1;
+          }
+        }
+        for (int r = nrc + t.lane; r < nrow; r += t.T) {
+          const float ep = e[r] + al * s[r];
+          v += s[r] * row_s(r, ep);
+          if (row_q(r, ep)) h2 += D[r] * s[r] * s[r];
+        }
+        d2 = t.sum(h2) + dMd;
+        return t.sum(v) + dMr + al * dMd;
+      }
       for (int c = t.lane; c < ncon; c += t.T) {
         int first;
         float mu, ratio[6], ev[6], sv[6], wv[6], V[36], cc;
