@@ -2168,51 +2168,71 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
     gstop = gtol * t.max(fm);
   }
   for (int it = 0; it < iters; it++) {
-    // ---- slopes, Hessian weights and the cones' virtual-row maps
-    for (int c = t.lane; c < ncon && m.con_nr == 3; c += t.T) {
-      // condim-3 cones in registers (cone_eval's rows for nd = 3): sticking, the rows
-      // themselves with weight D; sliding, (-1, mu t) with D / (1 + mu^2) and the unit
-      // tangent across t with c psi mu / T; separated, nothing
-      const int f = 3 * c;
-      const float mu = con[kConRec * c + 13], Dn = D[f];
-      const float e0 = e[f], e1 = e[f + 1], e2 = e[f + 2];
-      const float Tn = sqrtf(e1 * e1 + e2 * e2);
-      float* V = cv + c * cw;
-      float sv0 = 0.f, sv1 = 0.f, sv2 = 0.f, w0 = 0.f, w1 = 0.f, w2 = 0.f;
-      for (int k = 0; k < 9; k++) V[k] = 0.f;
-      if (e0 < mu * Tn) {
-        if (mu * e0 + Tn <= 0.f) {
-          sv0 = Dn * e0; sv1 = Dn * e1; sv2 = Dn * e2;
-          w0 = w1 = w2 = Dn;
-          V[0] = V[4] = V[8] = 1.f;
-        } else {
-          const float inv = 1.f / Tn, psi = mu * Tn - e0, cc = Dn / (1.f + mu * mu);
-          sv0 = -cc * psi;
-          sv1 = cc * psi * mu * e1 * inv;
-          sv2 = cc * psi * mu * e2 * inv;
-          w0 = cc;
-          w1 = cc * psi * mu * inv;
-          V[0] = -1.f; V[1] = mu * e1 * inv; V[2] = mu * e2 * inv;
-          V[4] = -e2 * inv; V[5] = e1 * inv;
-        }
-      }
-      sl[f] = sv0; sl[f + 1] = sv1; sl[f + 2] = sv2;
-      s[f] = w0; s[f + 1] = w1; s[f + 2] = w2;
-    }
-    for (int c = t.lane; c < ncon && m.con_nr != 3; c += t.T) {
-      int first;
-      float mu, ratio[6], ev[6], sv[6], wv[6], cc;
-      const int nd = cone_of(m, con, c, first, mu, ratio);
+    // ---- slopes, Hessian weights and the cones' virtual-row maps (cone_eval's, in
+    // registers and the map's LDS words): sticking, the rows themselves with weights
+    // D r_j^2; sliding, (-1, mu t) with D / (1 + mu^2) and the columns of the reflection
+    // I - beta u u^T (u = t + sign(t_1) e_1) orthogonal to t with c psi mu / T;
+    // separated, nothing
+    for (int c = t.lane; c < ncon; c += t.T) {
+      const float* rc = con + kConRec * c;
+      const int slot = __float_as_int(rc[17]);
+      const int first = m.con_nr ? m.con_nr * c : slot >> 8;
+      const int nd = m.con_nr ? m.con_nr : (slot >> 4) & 15;
+      const float Dn = D[first], x0 = e[first];
       if (nd == 1) {
-        sl[first] = fminf(D[first] * e[first], 0.f);
-        s[first] = e[first] < 0.f ? D[first] : 0.f;
+        sl[first] = fminf(Dn * x0, 0.f);
+        s[first] = x0 < 0.f ? Dn : 0.f;
         continue;
       }
-      for (int j = 0; j < nd; j++) ev[j] = e[first + j];
-      cone_eval(mu, D[first], ratio, nd, ev, cc, sv, wv, cv + c * cw);
-      for (int j = 0; j < nd; j++) {
-        sl[first + j] = sv[j];
-        s[first + j] = wv[j];
+      const float mu = rc[13];
+      float rt = 1.f, rr = 1.f;
+      if (nd > 3) {
+        const int p = __float_as_int(rc[16]);
+        rt = m.pair_mu_t[p] / mu;
+        rr = m.pair_mu_r[p] / mu;
+      }
+      auto ratio = [&](int q) { return q < 3 ? 1.f : (q == 3 ? rt : rr); };
+      float* V = cv + c * cw;
+      for (int k = 0; k < nd * nd; k++) V[k] = 0.f;
+      float xx = 0.f;
+      for (int q = 1; q < nd; q++) {
+        const float xq = e[first + q] * ratio(q);
+        xx += xq * xq;
+      }
+      const float Tn = sqrtf(xx);
+      for (int q = 0; q < nd; q++) { sl[first + q] = 0.f; s[first + q] = 0.f; }
+      if (!(x0 < mu * Tn)) continue;  // separated
+      if (mu * x0 + Tn <= 0.f) {       // sticking
+        for (int q = 0; q < nd; q++) {
+          const float rq = ratio(q);
+          sl[first + q] = Dn * e[first + q] * rq * rq;
+          s[first + q] = Dn * rq * rq;
+          V[q * nd + q] = 1.f;
+        }
+        continue;
+      }
+      const float inv = 1.f / Tn, psi = mu * Tn - x0, cc = Dn / (1.f + mu * mu);
+      sl[first] = -cc * psi;
+      s[first] = cc;
+      V[0] = -1.f;
+      const float u0 = e[first + 1] * inv, sg = u0 >= 0.f ? 1.f : -1.f;
+      float uu = 0.f;
+      for (int q = 1; q < nd; q++) {
+        const float rq = ratio(q), xq = e[first + q] * rq;
+        sl[first + q] = cc * psi * mu * xq * inv * rq;
+        V[q] = mu * xq * inv * rq;
+        const float uq = xq * inv + (q == 1 ? sg : 0.f);
+        uu += uq * uq;
+      }
+      const float beta = 2.f / uu, w2 = cc * psi * mu * inv;
+      const int mf = nd - 1;
+      for (int k = 1; k < mf; k++) {
+        s[first + k] = w2;
+        const float uk = e[first + 1 + k] * ratio(1 + k) * inv;
+        for (int q = 0; q < mf; q++) {
+          const float uq = e[first + 1 + q] * ratio(1 + q) * inv + (q == 0 ? sg : 0.f);
+          V[k * nd + 1 + q] = ((q == k ? 1.f : 0.f) - beta * uq * uk) * ratio(1 + q);
+        }
       }
     }
     for (int r = nrc + t.lane; r < nru; r += t.T) {
@@ -2224,17 +2244,13 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
     for (int idx = t.lane; idx < nru * nv; idx += t.T) {
       const int r = idx / nv, i = idx - r * nv;
       float v = J[idx];
-      if (r < nrc && m.con_nr == 3) {  // condim-3 cones: no per-row coefficients
-        const int c = r / 3, f = 3 * c;
-        const float* V = cv + c * cw + (r - f) * 3;
-        v = V[0] * J[f * nv + i] + V[1] * J[(f + 1) * nv + i] + V[2] * J[(f + 2) * nv + i];
-      } else if (r < nrc) {
+      if (r < nrc) {
         int c = m.con_nr ? r / m.con_nr : 0;
         if (!m.con_nr)
           while (c + 1 < ncon && (__float_as_int(con[kConRec * (c + 1) + 17]) >> 8) <= r) c++;
-        int first;
-        float mu, ratio[6];
-        const int nd = cone_of(m, con, c, first, mu, ratio);
+        const int slot = __float_as_int(con[kConRec * c + 17]);
+        const int first = m.con_nr ? m.con_nr * c : slot >> 8;
+        const int nd = m.con_nr ? m.con_nr : (slot >> 4) & 15;
         if (nd > 1) {
           const float* V = cv + c * cw + (r - first) * nd;
           v = 0.f;
@@ -2271,7 +2287,11 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
     }
     t.sync();
     cholesky_solve(m, W, t, tmp, tmp, 1.f);
-    for (int i = t.lane; i < nv; i += t.T) d[i] -= tmp[i];
+    float cmax = 0.f;  // size of the correction: the unrefined direction's error
+    for (int i = t.lane; i < nv; i += t.T) {
+      d[i] -= tmp[i];
+      cmax = fmaxf(cmax, fabsf(tmp[i]));
+    }
     t.sync();
     // ---- line search quantities
     float gd = 0.f, dMd = 0.f, dMr = 0.f;
@@ -2296,55 +2316,49 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
     // phi'(al) and phi''(al), summed over the team
     auto dphi = [&](float al, float& d2) {
       float v = 0.f, h2 = 0.f;
-      if (m.con_nr == 3) {
-        // every contact a condim-3 cone: its rows' slope and curvature along s in
-        // registers (cone_eval's zones for nd = 3: sticking, D I; sliding, curvature
-        // c = D / (1 + mu^2) along (-1, mu t) and c psi mu / T across t)
-        for (int c = t.lane; c < ncon; c += t.T) {
-          const int f = 3 * c;
-          const float mu = con[kConRec * c + 13], Dn = D[f];
-          const float s0 = s[f], s1 = s[f + 1], s2 = s[f + 2];
-          const float e0 = e[f] + al * s0, e1 = e[f + 1] + al * s1, e2 = e[f + 2] + al * s2;
-          const float Tn = sqrtf(e1 * e1 + e2 * e2);
-          if (!(e0 < mu * Tn)) continue;  // separated
-          if (mu * e0 + Tn <= 0.f) {       // sticking
-            v += Dn * (s0 * e0 + s1 * e1 + s2 * e2);
-            h2 += Dn * (s0 * s0 + s1 * s1 + s2 * s2);
-          } else {                         // sliding on the cone's surface
-            const float inv = 1.f / Tn, psi = mu * Tn - e0, cc = Dn / (1.f + mu * mu);
-            const float q0 = mu * (e1 * s1 + e2 * s2) * inv - s0;
-            const float q1 = (e1 * s2 - e2 * s1) * inv;
-            v += cc * psi * q0;
-            h2 += cc * q0 * q0 + cc * psi * mu * inv * q1 * q1;
-          }
-        }
-        for (int r = nrc + t.lane; r < nrow; r += t.T) {
-          const float ep = e[r] + al * s[r];
-          v += s[r] * row_s(r, ep);
-          if (row_q(r, ep)) h2 += D[r] * s[r] * s[r];
-        }
-        d2 = t.sum(h2) + dMd;
-        return t.sum(v) + dMr + al * dMd;
-      }
+      // each contact's rows in registers, any condim (cone_eval's zones): with x_j = e_j
+      // r_j and y_j = s_j r_j over the friction rows (r_j = mu_j / mu), sticking adds
+      // D (x0 s0 + x.y) and D (s0^2 + |y|^2); sliding, with psi = mu T - x0 and
+      // c = D / (1 + mu^2), adds c psi q0 and c q0^2 + (c psi mu / T)(|y|^2 - (x.y / T)^2),
+      // q0 = mu x.y / T - s0: the curvature along (-1, mu t) and across t
       for (int c = t.lane; c < ncon; c += t.T) {
-        int first;
-        float mu, ratio[6], ev[6], sv[6], wv[6], V[36], cc;
-        const int nd = cone_of(m, con, c, first, mu, ratio);
+        const float* rc = con + kConRec * c;
+        const int slot = __float_as_int(rc[17]);
+        const int first = m.con_nr ? m.con_nr * c : slot >> 8;
+        const int nd = m.con_nr ? m.con_nr : (slot >> 4) & 15;
+        const float Dn = D[first], s0 = s[first], x0 = e[first] + al * s0;
         if (nd == 1) {
-          const float ep = e[first] + al * s[first];
-          if (ep < 0.f) {
-            v += s[first] * D[first] * ep;
-            h2 += D[first] * s[first] * s[first];
+          if (x0 < 0.f) {
+            v += s0 * Dn * x0;
+            h2 += Dn * s0 * s0;
           }
           continue;
         }
-        for (int j = 0; j < nd; j++) ev[j] = e[first + j] + al * s[first + j];
-        cone_eval(mu, D[first], ratio, nd, ev, cc, sv, wv, V);
-        for (int k = 0; k < nd; k++) {
-          v += s[first + k] * sv[k];
-          float q = 0.f;
-          for (int j = 0; j < nd; j++) q += V[k * nd + j] * s[first + j];
-          h2 += wv[k] * q * q;
+        const float mu = rc[13];
+        float rt = 1.f, rr = 1.f;
+        if (nd > 3) {
+          const int p = __float_as_int(rc[16]);
+          rt = m.pair_mu_t[p] / mu;
+          rr = m.pair_mu_r[p] / mu;
+        }
+        float xx = 0.f, xy = 0.f, yy = 0.f;
+        for (int q = 1; q < nd; q++) {
+          const float rq = q < 3 ? 1.f : (q == 3 ? rt : rr);
+          const float yq = s[first + q] * rq, xq = (e[first + q] + al * s[first + q]) * rq;
+          xx += xq * xq;
+          xy += xq * yq;
+          yy += yq * yq;
+        }
+        const float Tn = sqrtf(xx);
+        if (!(x0 < mu * Tn)) continue;  // separated
+        if (mu * x0 + Tn <= 0.f) {       // sticking
+          v += Dn * (x0 * s0 + xy);
+          h2 += Dn * (s0 * s0 + yy);
+        } else {                         // sliding on the cone's surface
+          const float inv = 1.f / Tn, psi = mu * Tn - x0, cc = Dn / (1.f + mu * mu);
+          const float q0 = mu * xy * inv - s0, xt = xy * inv;
+          v += cc * psi * q0;
+          h2 += cc * q0 * q0 + cc * psi * mu * inv * fmaxf(yy - xt * xt, 0.f);
         }
       }
       for (int r = nrc + t.lane; r < nrow; r += t.T) {
@@ -2368,10 +2382,63 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
       al = next;
       if (done) break;
     }
-    // ---- update
-    for (int i = t.lane; i < nv; i += t.T) { a[i] += al * d[i]; Mr[i] += al * Md[i]; }
-    for (int r = t.lane; r < nrow; r += t.T) e[r] += al * s[r];
+    // ---- update, and whether a row or cone changed zone along the step
+    float amax = 1.f, dmax = 0.f;
+    for (int i = t.lane; i < nv; i += t.T) {
+      a[i] += al * d[i];
+      Mr[i] += al * Md[i];
+      amax = fmaxf(amax, fabsf(a[i]));
+      dmax = fmaxf(dmax, fabsf(al * d[i]));
+    }
+    int moved = 0, sliding = 0;
+    for (int c = t.lane; c < ncon; c += t.T) {
+      const float* rc = con + kConRec * c;
+      const int slot = __float_as_int(rc[17]);
+      const int first = m.con_nr ? m.con_nr * c : slot >> 8;
+      const int nd = m.con_nr ? m.con_nr : (slot >> 4) & 15;
+      if (nd == 1) {
+        moved |= (e[first] < 0.f) != (e[first] + al * s[first] < 0.f);
+        continue;
+      }
+      const float mu = rc[13];
+      float rt = 1.f, rr = 1.f;
+      if (nd > 3) {
+        const int p = __float_as_int(rc[16]);
+        rt = m.pair_mu_t[p] / mu;
+        rr = m.pair_mu_r[p] / mu;
+      }
+      // zone of x = e r at the old and new iterate: 0 separated, 2 sticking, 1 sliding
+      float T0 = 0.f, T1 = 0.f, x0 = e[first], x1 = e[first] + al * s[first];
+      for (int j2 = 1; j2 < nd; j2++) {
+        const float rj = j2 < 3 ? 1.f : (j2 == 3 ? rt : rr);
+        const float u0 = e[first + j2] * rj, u1 = (e[first + j2] + al * s[first + j2]) * rj;
+        T0 += u0 * u0;
+        T1 += u1 * u1;
+      }
+      T0 = sqrtf(T0);
+      T1 = sqrtf(T1);
+      const int z0 = !(x0 < mu * T0) ? 0 : (mu * x0 + T0 <= 0.f ? 2 : 1);
+      const int z1 = !(x1 < mu * T1) ? 0 : (mu * x1 + T1 <= 0.f ? 2 : 1);
+      moved |= z0 != z1;
+      sliding |= z1 == 1;
+    }
+    for (int r = nrc + t.lane; r < nrow; r += t.T) {
+      const float e1 = e[r] + al * s[r];
+      moved |= FR ? (row_piece(D[r], fl[r], e[r]) != row_piece(D[r], fl[r], e1))
+                  : ((e[r] < 0.f) != (e1 < 0.f));
+    }
     t.sync();
+    for (int r = t.lane; r < nrow; r += t.T) e[r] += al * s[r];
+    // Exit as newton_impl does once the last step stayed on one piece of every row and
+    // cone and its refinement correction was small: with no cone sliding the cost is
+    // quadratic there and the iterate is its minimiser; a sliding cone's cost is smooth
+    // but not quadratic, and there the step itself must also be below the tolerance
+    // (Newton's quadratic convergence leaves the next one far smaller).
+    moved = t.ior(moved);
+    sliding = t.ior(sliding);
+    const float cm = t.max(cmax), am = t.max(amax), dm = t.max(dmax);
+    t.sync();
+    if (!moved && cm <= kNewtonExitTol * am && (!sliding || dm <= kNewtonExitTol * am)) break;
   }
   // ---- the final slopes (the rows' forces are -sl)
   for (int c = t.lane; c < ncon; c += t.T) {

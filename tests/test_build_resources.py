@@ -33,7 +33,7 @@ def usage():
     return u
 
 
-@pytest.mark.parametrize("kernel,scratch_max", [(STEP, 16), (STEP_RK, 16), (STEP_CONE, 416),
+@pytest.mark.parametrize("kernel,scratch_max", [(STEP, 16), (STEP_RK, 16), (STEP_CONE, 48),
                                                 (ENV, 96), (ENV_DR, 112), (ENV_RK, 112)])
 def test_hot_kernels_fit_four_waves_with_small_scratch(usage, kernel, scratch_max):
     k = usage[kernel]
