@@ -1179,7 +1179,7 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
   const int blocks[3] = {64, 128, 256};
   std::vector<int> counts;
   for (auto& o : b->groups) counts.push_back(o.nworld);
-  // each probed group's three fastest shapes alone, for the combined pass below
+  // each probed group's shapes timed alone, for the combined pass below
   std::vector<std::vector<std::pair<float, std::pair<int, int>>>> solo(b->groups.size());
   auto probe = [&](float& ms) {
     bool good = true;
@@ -1230,8 +1230,13 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
   }
   for (size_t o = 0; o < b->groups.size(); o++) b->groups[o].nworld = counts[o];
   // A batch of several groups runs as one launch whose block and LDS size are the
-  // largest any group needs, so the groups' solo choices can starve each other: one pass
-  // over the groups tries each one's three fastest solo shapes in the combined launch.
+  // largest any group needs, so the groups' solo choices can starve each other (a group
+  // of small worlds then holds the LDS of the largest group's work-group).  First, for
+  // each work-group LDS size L that some group's shape needs, every group takes its
+  // fastest solo shape within L (else its smallest): the fastest of these combinations
+  // is kept.  Then one pass over the groups tries each of a group's shapes in the
+  // combined launch (a group's solo ranking can mislead: alone, a small group may fill
+  // the device only with shapes that spread its worlds thinly).
   int nactive = 0;
   for (auto& o : b->groups) nactive += o.nworld > 0;
   if (ok && nactive >= 2) {
@@ -1239,10 +1244,59 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
     b->dirty = true;
     st = sync_tables(b);
     ok = st == MJH_OK && probe(cur);
+    int tab_words = 0;
+    for (auto& o : b->groups)
+      if (o.nworld > 0) tab_words = std::max(tab_words, table_words(ctx->models[o.model]->dm));
+    auto wg_lds = [&](size_t g, int t, int bl) {
+      const ModelRec& mr = *ctx->models[b->groups[g].model];
+      return (size_t)tab_words * sizeof(float) +
+             (size_t)worlds_per_block(ctx, mr, t, bl, tab_words) * mr.dm.lds_words * sizeof(float);
+    };
+    std::vector<size_t> caps;
+    for (size_t g = 0; g < b->groups.size(); g++)
+      for (auto& s : solo[g]) caps.push_back(wg_lds(g, s.second.first, s.second.second));
+    std::sort(caps.begin(), caps.end());
+    caps.erase(std::unique(caps.begin(), caps.end()), caps.end());
+    std::vector<std::pair<int, int>> best_shape(b->groups.size());
+    for (size_t g = 0; g < b->groups.size(); g++) best_shape[g] = {b->groups[g].team, b->groups[g].block};
+    for (size_t ci = 0; ok && ci < caps.size(); ci++) {
+      bool same = true;
+      for (size_t g = 0; g < b->groups.size(); g++) {
+        if (solo[g].empty()) continue;  // not probed (a cached shape): kept as it is
+        int pick = -1, small = 0;
+        for (size_t k = 0; k < solo[g].size(); k++) {
+          const int t = solo[g][k].second.first, bl = solo[g][k].second.second;
+          const size_t l = wg_lds(g, t, bl);
+          if (l <= caps[ci] && (pick < 0 || solo[g][k].first < solo[g][pick].first)) pick = (int)k;
+          const size_t ls = wg_lds(g, solo[g][small].second.first, solo[g][small].second.second);
+          if (l < ls || (l == ls && solo[g][k].first < solo[g][small].first)) small = (int)k;
+        }
+        if (pick < 0) pick = small;
+        GroupRec& gr = b->groups[g];
+        same = same && gr.team == solo[g][pick].second.first && gr.block == solo[g][pick].second.second;
+        gr.team = solo[g][pick].second.first;
+        gr.block = solo[g][pick].second.second;
+      }
+      if (same) continue;
+      b->dirty = true;
+      st = sync_tables(b);
+      if (st != MJH_OK) { ok = false; break; }
+      float ms = 0.f;
+      ok = probe(ms);
+      if (ok && ms < cur) {
+        cur = ms;
+        for (size_t g = 0; g < b->groups.size(); g++) best_shape[g] = {b->groups[g].team, b->groups[g].block};
+      }
+    }
+    for (size_t g = 0; g < b->groups.size(); g++) {
+      b->groups[g].team = best_shape[g].first;
+      b->groups[g].block = best_shape[g].second;
+    }
+    b->dirty = true;
     for (size_t g = 0; ok && g < b->groups.size(); g++) {
       std::sort(solo[g].begin(), solo[g].end());
       GroupRec& gr = b->groups[g];
-      for (size_t k = 0; ok && k < solo[g].size() && k < 3; k++) {
+      for (size_t k = 0; ok && k < solo[g].size(); k++) {
         const int t = solo[g][k].second.first, bl = solo[g][k].second.second;
         if (t == gr.team && bl == gr.block) continue;
         const int t0 = gr.team, b0 = gr.block;

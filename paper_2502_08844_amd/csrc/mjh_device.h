@@ -1858,6 +1858,7 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
     for (int i = t.lane; i < nv; i += t.T) fm = fmaxf(fm, fabsf(frc[i]));
     gstop = gtol * t.max(fm);
   }
+  bool kept = false;  // o_H holds the factor of the Hessian at the current pieces
   for (int it = 0; it < iters; it++) {
     // ---- gradient g = M (a - a0) + sum_active D e J
     rows_t_times(m, W, t, rb, [&](int r) {
@@ -1867,13 +1868,20 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
     float gmax = 0.f;
     for (int i = t.lane; i < nv; i += t.T) gmax = fmaxf(gmax, fabsf(g[i]));
     if (gtol > 0.f && t.max(gmax) <= gstop) break;  // converged to FP32 precision
-    for (int i = t.lane; i < nv; i += t.T) d[i] = -g[i];
-    // ---- delta = -H^-1 g: forward solve fused into the factorisation, then back
-    if (!hessian_cholesky(m, W, t, nru, d, tmp, false, false, nullptr, false, rb.nou)) {
-      status |= 4;
-      break;
+    // ---- delta = -H^-1 g.  H depends on the iterate only through the rows' pieces, so
+    // after a step on which no row changed piece the factor left in o_H is this
+    // iteration's: solve with it.  Otherwise assemble and factor, the forward solve
+    // fused into the factorisation, then the back substitution.
+    if (kept) {
+      cholesky_solve(m, W, t, g, d, -1.f);
+    } else {
+      for (int i = t.lane; i < nv; i += t.T) d[i] = -g[i];
+      if (!hessian_cholesky(m, W, t, nru, d, tmp, false, false, nullptr, false, rb.nou)) {
+        status |= 4;
+        break;
+      }
+      cholesky_back(m, W, t, tmp, d);
     }
-    cholesky_back(m, W, t, tmp, d);
     // ---- one step of iterative refinement: the FP32 factor of H carries a relative
     // error near cond(H) eps into d, and the fixed iteration count leaves the iterate
     // mid-path, where such errors compound.  The residual r = g + H d, with H applied
@@ -1983,6 +1991,7 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
     const float cm = t.max(cmax), am = t.max(amax);
     t.sync();
     if (!moved && cm <= kNewtonExitTol * am) break;
+    kept = !moved;
   }
 }
 // ------------------------------------------------- A9 with elliptic friction cones
@@ -2167,6 +2176,7 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
     for (int i = t.lane; i < nv; i += t.T) fm = fmaxf(fm, fabsf(frc[i]));
     gstop = gtol * t.max(fm);
   }
+  bool kept = false;  // o_H holds the factor of the Hessian at the current zones
   for (int it = 0; it < iters; it++) {
     // ---- slopes, Hessian weights and the cones' virtual-row maps (cone_eval's, in
     // registers and the map's LDS words): sticking, the rows themselves with weights
@@ -2269,10 +2279,16 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
       gmax = fmaxf(gmax, fabsf(v));
     }
     if (gtol > 0.f && t.max(gmax) <= gstop) break;
-    for (int i = t.lane; i < nv; i += t.T) d[i] = -g[i];
-    // ---- delta = -H^-1 g, then one step of iterative refinement (as in newton_impl)
-    if (!hessian_cholesky(m, W, t, nru, d, tmp, false, false, Jv, true)) { status |= 4; break; }
-    cholesky_back(m, W, t, tmp, d);
+    // ---- delta = -H^-1 g, then one step of iterative refinement (as in newton_impl).
+    // With every zone unchanged by the last step and no cone sliding (whose curvature
+    // moves with x), the Hessian is the last one and its factor is still in o_H.
+    if (kept) {
+      cholesky_solve(m, W, t, g, d, -1.f);
+    } else {
+      for (int i = t.lane; i < nv; i += t.T) d[i] = -g[i];
+      if (!hessian_cholesky(m, W, t, nru, d, tmp, false, false, Jv, true)) { status |= 4; break; }
+      cholesky_back(m, W, t, tmp, d);
+    }
     for (int r = t.lane; r < nru; r += t.T) {
       float v = 0.f;
       for (int i = 0; i < nv; i++) v += Jv[r * nv + i] * d[i];
@@ -2439,6 +2455,7 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
     const float cm = t.max(cmax), am = t.max(amax), dm = t.max(dmax);
     t.sync();
     if (!moved && cm <= kNewtonExitTol * am && (!sliding || dm <= kNewtonExitTol * am)) break;
+    kept = !moved && !sliding;
   }
   // ---- the final slopes (the rows' forces are -sl)
   for (int c = t.lane; c < ncon; c += t.T) {
