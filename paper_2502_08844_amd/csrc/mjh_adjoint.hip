@@ -108,6 +108,121 @@ DEV void body_base(const DevModel& m, const float* W, int b, float* pos, float* 
   mm3(Rp, m.body_rot + 9 * b, R);
 }
 
+// ------------------------------------------------- contact geometry, reversed
+// Each takes the cotangents of a forward function's outputs and adds those of its
+// inputs, recomputing what it needs (the same branches as the forward code).
+
+// contact_frame: t1 = v / |v|, v = e_ax - n_ax n (ax: the smallest |n_k|), t2 = n x t1.
+// Cotangents t1b, t2b are added into nb.
+DEV void frame_rev(const float* n, const float* t1, const float* t1b, const float* t2b,
+                   float* nb) {
+  float a[3], b[3];
+  cross3(t1, t2b, a);  // d/dn of (n x t1).g is t1 x g; d/dt1 is g x n
+  cross3(t2b, n, b);
+  const float tb[3] = {t1b[0] + b[0], t1b[1] + b[1], t1b[2] + b[2]};
+  int ax = 0;
+  if (fabsf(n[1]) < fabsf(n[ax])) ax = 1;
+  if (fabsf(n[2]) < fabsf(n[ax])) ax = 2;
+  const float en = n[ax];
+  float v[3] = {-en * n[0], -en * n[1], -en * n[2]};
+  v[ax] += 1.f;
+  const float inv = 1.f / sqrtf(dot3(v, v));
+  const float tt = dot3(t1, tb);
+  float vb[3];
+  for (int k = 0; k < 3; k++) vb[k] = (tb[k] - t1[k] * tt) * inv;
+  const float enb = -dot3(n, vb);
+  for (int k = 0; k < 3; k++) nb[k] += a[k] - en * vb[k];
+  nb[ax] += enb;
+}
+
+// sphere_sphere: with d = c2 - c1, L = |d|, n = d / L, dist = L - r1 - r2 and
+// pos = c1 + d / 2 + (r1 - r2) n / 2.  Cotangents of pos (xb), n (nb), dist (db).
+DEV void sphere_sphere_rev(const float* c1, float r1, const float* c2, float r2,
+                           const float* xb, const float* nb, float db, float* c1b,
+                           float* c2b) {
+  const float d[3] = {c2[0] - c1[0], c2[1] - c1[1], c2[2] - c1[2]};
+  const float L = sqrtf(dot3(d, d));
+  const bool ok = L > 1e-12f;  // otherwise the forward code fixed n = e_z
+  const float n[3] = {ok ? d[0] / L : 0.f, ok ? d[1] / L : 0.f, ok ? d[2] / L : 1.f};
+  const float rho = 0.5f * (r1 - r2);
+  const float g[3] = {rho * xb[0] + nb[0], rho * xb[1] + nb[1], rho * xb[2] + nb[2]};
+  const float gn = dot3(n, g);
+  for (int k = 0; k < 3; k++) {
+    const float dbar = 0.5f * xb[k] + (ok ? db * n[k] + (g[k] - n[k] * gn) / L : 0.f);
+    c1b[k] += xb[k] - dbar;
+    c2b[k] += dbar;
+  }
+}
+
+// nearest point q = a + t u of a segment to x, t = clamp((x - a).u / u.u, 0, 1)
+DEV void seg_point_rev(const float* x, const float* a, const float* u, const float* qb,
+                       float* xb, float* ab, float* ub) {
+  const float uu = dot3(u, u);
+  const float ap[3] = {x[0] - a[0], x[1] - a[1], x[2] - a[2]};
+  const float t0 = uu < 1e-30f ? 0.f : dot3(ap, u) / uu;
+  const float t = fminf(fmaxf(t0, 0.f), 1.f);
+  for (int k = 0; k < 3; k++) { ab[k] += qb[k]; ub[k] += t * qb[k]; }
+  if (uu >= 1e-30f && t0 > 0.f && t0 < 1.f) {
+    const float tb = dot3(qb, u);
+    for (int k = 0; k < 3; k++) {
+      const float apb = tb * u[k] / uu;
+      xb[k] += apb;
+      ab[k] -= apb;
+      ub[k] += tb * (ap[k] - 2.f * t * u[k]) / uu;
+    }
+  }
+}
+
+// seg_seg: parameters s, t of the closest points p0 + s d1, q0 + t d2; cotangents sb, tb
+DEV void seg_seg_rev(const float* p0, const float* d1, const float* q0, const float* d2,
+                     float sb, float tb, float* p0b, float* d1b, float* q0b, float* d2b) {
+  const float r[3] = {p0[0] - q0[0], p0[1] - q0[1], p0[2] - q0[2]};
+  const float a = dot3(d1, d1), e = dot3(d2, d2), f = dot3(d2, r), c = dot3(d1, r),
+              b = dot3(d1, d2);
+  const float den = a * e - b * b;
+  auto inner = [](float x) { return x > 0.f && x < 1.f; };
+  float ab_ = 0.f, eb = 0.f, fb = 0.f, cb = 0.f, bb = 0.f;
+  if (den > 1e-6f * a * e) {
+    const float s1 = (b * f - c * e) / den;
+    const float s = fminf(fmaxf(s1, 0.f), 1.f);
+    const float t1 = (b * s + f) / e;
+    if (t1 < 0.f) {  // t = 0, s = clamp(-c / a)
+      if (inner(-c / a)) { cb -= sb / a; ab_ += sb * c / (a * a); }
+    } else if (t1 > 1.f) {  // t = 1, s = clamp((b - c) / a)
+      const float s2 = (b - c) / a;
+      if (inner(s2)) { bb += sb / a; cb -= sb / a; ab_ -= sb * s2 / a; }
+    } else {  // t = (b s + f) / e, s = clamp(s1)
+      bb += tb * s / e;
+      fb += tb / e;
+      eb -= tb * t1 / e;
+      if (inner(s1)) {
+        const float s1b = sb + tb * b / e;
+        const float numb = s1b / den, denb = -s1b * s1 / den;
+        bb += numb * f - 2.f * denb * b;
+        fb += numb * b;
+        cb -= numb * e;
+        eb += denb * a - numb * c;
+        ab_ += denb * e;
+      }
+    }
+  } else {  // near-parallel: s the mean of the two end projections
+    const float s0r = -c / a, s1r = (b - c) / a;
+    const float s = 0.5f * (fminf(fmaxf(s0r, 0.f), 1.f) + fminf(fmaxf(s1r, 0.f), 1.f));
+    const float tr = (b * s + f) / e;
+    float sbt = sb;
+    if (inner(tr)) { bb += tb * s / e; fb += tb / e; eb -= tb * tr / e; sbt += tb * b / e; }
+    if (inner(s0r)) { cb -= 0.5f * sbt / a; ab_ += 0.5f * sbt * c / (a * a); }
+    if (inner(s1r)) { bb += 0.5f * sbt / a; cb -= 0.5f * sbt / a; ab_ -= 0.5f * sbt * s1r / a; }
+  }
+  for (int k = 0; k < 3; k++) {
+    const float rb = fb * d2[k] + cb * d1[k];
+    d1b[k] += 2.f * ab_ * d1[k] + cb * r[k] + bb * d2[k];
+    d2b[k] += 2.f * eb * d2[k] + fb * r[k] + bb * d1[k];
+    p0b[k] += rb;
+    q0b[k] -= rb;
+  }
+}
+
 // ------------------------------------------------------------------ adjoint step
 // Inputs in LDS: qpos/qvel (state before the step), qacc (= a*), qbi/vbi (cotangents of
 // the state after the step).  Outputs: qb (nq), vb (nv), ub (nu).  Returns false for an
@@ -357,7 +472,7 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
     const float* e = W + m.o_e;
     const float* con = W + m.o_con;
     float* rs = W + m.o_rowsc;   // per row: s, x, y, alpha, beta, gamma, rho
-    float* cs = W + m.o_consc;   // per contact: csbar[3], gp[3], body, ok
+    float* cs = W + m.o_consc;   // per contact: kConSc words (below)
     for (int r = t.lane; r < nrow; r += t.T) {
       float sv = 0.f, xv = 0.f, yv = 0.f;
       for (int i = 0; i < nv; i++) {
@@ -418,12 +533,17 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
       vb[k] += vadd;
       for (int c = 0; c < 6; c++) Sbar[6 * k + c] += sb[c];
     }
-    // contacts: point and distance cotangents -> sphere-centre cotangent
+    // contacts: cotangents of each contact's point, normal and distance, reversed through
+    // its geometry to points fixed on its bodies (record: four points, each a world-frame
+    // cotangent and its body-frame position; points 0-1 on body 1, 2-3 on body 2)
     for (int c = t.lane; c < ncon; c += t.T) {
       const float* rec = con + kConRec * c;
       const int b1 = __float_as_int(rec[14]), b2 = __float_as_int(rec[15]);
       const int p = __float_as_int(rec[16]), sub = __float_as_int(rec[17]);
+      const int kind = m.pair_kind[p];
+      const bool plane = kind == PK_PLANE_SPHERE || kind == PK_PLANE_CAPSULE;
       float xb[3] = {0.f, 0.f, 0.f}, rb = 0.f;
+      float fb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // of n, t1, t2
       for (int ed = 0; ed < 4; ed++) {
         const int r = 4 * c + ed;
         if (!(e[r] < 0.f)) continue;
@@ -432,34 +552,104 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
         const float sgm = (ed & 1) ? -rec[13] : rec[13];
         const float* tk = rec + 4 + 3 * (1 + (ed >> 1));
         const float ev[3] = {rec[4] + sgm * tk[0], rec[5] + sgm * tk[1], rec[6] + sgm * tk[2]};
-        float om[3] = {0.f, 0.f, 0.f};
+        float om[3] = {0.f, 0.f, 0.f}, ln[3] = {0.f, 0.f, 0.f};
         for (int k = 0; k < nv; k++) {
           const unsigned long long bit = 1ull << k;
           const bool in2 = (m.body_dofmask[b2] & bit) != 0, in1 = (m.body_dofmask[b1] & bit) != 0;
           if (in1 == in2) continue;
           const float w = (in2 ? 1.f : -1.f) * (o[3] * mu[k] + o[4] * qvel[k] + o[5] * a[k]);
-          for (int q = 0; q < 3; q++) om[q] += cdof[6 * k + q] * w;
+          for (int q = 0; q < 3; q++) {
+            om[q] += cdof[6 * k + q] * w;
+            ln[q] += cdof[6 * k + 3 + q] * w;
+          }
         }
         float x3[3];
         cross3(ev, om, x3);
         for (int q = 0; q < 3; q++) xb[q] += x3[q];
+        if (!plane) {  // the row direction n +- mu t_k moves: its cotangent ln + om x pos
+          float op[3];
+          cross3(om, rec + 1, op);
+          for (int q = 0; q < 3; q++) {
+            const float g = ln[q] + op[q];
+            fb[q] += g;
+            fb[3 + 3 * (ed >> 1) + q] += sgm * g;
+          }
+        }
       }
-      // plane contacts: pos = c_s - n (R + r/2), r = n . (c_s - p0) - R
-      const int kind = m.pair_kind[p];
-      float* o = cs + 10 * c;
-      const float* n = rec + 4;
-      const float nx = dot3(n, xb);
-      for (int q = 0; q < 3; q++) o[q] = xb[q] - 0.5f * n[q] * nx + rb * n[q];
-      const int g2 = m.pair_g2[p];
-      float gp[3] = {m.geom_pos[3 * g2], m.geom_pos[3 * g2 + 1], m.geom_pos[3 * g2 + 2]};
-      if (kind == PK_PLANE_CAPSULE) {
-        const float* Rg = m.geom_rot + 9 * g2;
-        const float sg = sub == 0 ? -m.geom_size[3 * g2 + 1] : m.geom_size[3 * g2 + 1];
-        gp[0] += sg * Rg[2]; gp[1] += sg * Rg[5]; gp[2] += sg * Rg[8];
+      float* o = cs + kConSc * c;
+      for (int q = 0; q < 24; q++) o[q] = 0.f;
+      o[24] = __int_as_float(b1);
+      o[25] = __int_as_float(b2);
+      o[26] = 1.f;
+      const int g1 = m.pair_g1[p], g2 = m.pair_g2[p];
+      // body-frame point of geom g on its axis at offset sh (0: the centre)
+      auto local = [&](int k, int g, float sh) {
+        const float* L = m.geom_rot + 9 * g;
+        for (int q = 0; q < 3; q++) o[6 * k + 3 + q] = m.geom_pos[3 * g + q] + sh * L[3 * q + 2];
+      };
+      if (plane) {
+        // pos = c - n (R + r/2), r = n . (c - p0) - R, c the sphere centre or capsule end
+        const float* n = rec + 4;
+        const float nx = dot3(n, xb);
+        for (int q = 0; q < 3; q++) o[12 + q] = xb[q] - 0.5f * n[q] * nx + rb * n[q];
+        local(2, g2, kind == PK_PLANE_CAPSULE ? (sub == 0 ? -1.f : 1.f) * m.geom_size[3 * g2 + 1]
+                                              : 0.f);
+      } else if (kind == PK_SPHERE_SPHERE || kind == PK_SPHERE_CAPSULE ||
+                 kind == PK_CAPSULE_CAPSULE) {
+        float nb[3] = {fb[0], fb[1], fb[2]};
+        frame_rev(rec + 4, rec + 7, fb + 3, fb + 6, nb);
+        float x1[3], R1[9], x2[3], R2[9];
+        geom_pose(m, W, g1, x1, R1);
+        geom_pose(m, W, g2, x2, R2);
+        const float r1 = m.geom_size[3 * g1], r2 = m.geom_size[3 * g2];
+        const float h1 = m.geom_size[3 * g1 + 1], h2 = m.geom_size[3 * g2 + 1];
+        // the capsules' segments: start a, direction u (end a + u)
+        float a1[3], u1[3], a2[3], u2[3];
+        for (int q = 0; q < 3; q++) {
+          a1[q] = x1[q] - h1 * R1[3 * q + 2]; u1[q] = 2.f * h1 * R1[3 * q + 2];
+          a2[q] = x2[q] - h2 * R2[3 * q + 2]; u2[q] = 2.f * h2 * R2[3 * q + 2];
+        }
+        if (kind == PK_SPHERE_SPHERE) {
+          sphere_sphere_rev(x1, r1, x2, r2, xb, nb, rb, o, o + 12);
+          local(0, g1, 0.f);
+          local(2, g2, 0.f);
+        } else if (kind == PK_SPHERE_CAPSULE) {
+          const float uu = dot3(u2, u2);
+          const float ap[3] = {x1[0] - a2[0], x1[1] - a2[1], x1[2] - a2[2]};
+          const float tq = uu < 1e-30f ? 0.f : fminf(fmaxf(dot3(ap, u2) / uu, 0.f), 1.f);
+          const float qq[3] = {a2[0] + tq * u2[0], a2[1] + tq * u2[1], a2[2] + tq * u2[2]};
+          float qb[3] = {0.f, 0.f, 0.f}, ab[3] = {0.f, 0.f, 0.f}, ub[3] = {0.f, 0.f, 0.f};
+          sphere_sphere_rev(x1, r1, qq, r2, xb, nb, rb, o, qb);
+          seg_point_rev(x1, a2, u2, qb, o, ab, ub);
+          for (int q = 0; q < 3; q++) { o[12 + q] = ab[q] - ub[q]; o[18 + q] = ub[q]; }
+          local(0, g1, 0.f);
+          local(2, g2, -h2);
+          local(3, g2, h2);
+        } else {
+          float sp, tp;
+          seg_seg(a1, u1, a2, u2, sp, tp);
+          const float pp[3] = {a1[0] + sp * u1[0], a1[1] + sp * u1[1], a1[2] + sp * u1[2]};
+          const float qq[3] = {a2[0] + tp * u2[0], a2[1] + tp * u2[1], a2[2] + tp * u2[2]};
+          float ppb[3] = {0.f, 0.f, 0.f}, qqb[3] = {0.f, 0.f, 0.f};
+          sphere_sphere_rev(pp, r1, qq, r2, xb, nb, rb, ppb, qqb);
+          float ab[3], ub[3], bb[3], wb[3];
+          for (int q = 0; q < 3; q++) {
+            ab[q] = ppb[q]; ub[q] = sp * ppb[q];
+            bb[q] = qqb[q]; wb[q] = tp * qqb[q];
+          }
+          seg_seg_rev(a1, u1, a2, u2, dot3(ppb, u1), dot3(qqb, u2), ab, ub, bb, wb);
+          for (int q = 0; q < 3; q++) {
+            o[q] = ab[q] - ub[q]; o[6 + q] = ub[q];
+            o[12 + q] = bb[q] - wb[q]; o[18 + q] = wb[q];
+          }
+          local(0, g1, -h1);
+          local(1, g1, h1);
+          local(2, g2, -h2);
+          local(3, g2, h2);
+        }
+      } else {
+        o[26] = 0.f;  // geometry not differentiated (the rollout refuses such models)
       }
-      o[3] = gp[0]; o[4] = gp[1]; o[5] = gp[2];
-      o[6] = __int_as_float(b2);
-      o[7] = (kind == PK_PLANE_SPHERE || kind == PK_PLANE_CAPSULE) ? 1.f : 0.f;
     }
     // joint limits: the distance cotangent goes to the joint coordinate, r = +-(q - end)
     for (int k = t.lane; k < nl; k += t.T) {
@@ -471,16 +661,19 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
     t.sync();
     for (int b = 1 + t.lane; b < nb; b += t.T) {
       for (int c = 0; c < ncon; c++) {
-        const float* o = cs + 10 * c;
-        if (__float_as_int(o[6]) != b) continue;
-        for (int q = 0; q < 3; q++) {
-          xbar[3 * b + q] += o[q];
-          for (int k = 0; k < 3; k++) Rbar[9 * b + 3 * q + k] += o[q] * o[3 + k];
+        const float* o = cs + kConSc * c;
+        for (int k = 0; k < 4; k++) {
+          if (__float_as_int(o[k < 2 ? 24 : 25]) != b) continue;
+          const float* pt = o + 6 * k;  // point = x_b + R_b l: x_b gets pt, R_b gets pt l^T
+          for (int q = 0; q < 3; q++) {
+            xbar[3 * b + q] += pt[q];
+            for (int k2 = 0; k2 < 3; k2++) Rbar[9 * b + 3 * q + k2] += pt[q] * pt[3 + k2];
+          }
         }
       }
     }
     int bad = 0;
-    for (int c = t.lane; c < ncon; c += t.T) bad |= (cs[10 * c + 7] == 0.f);
+    for (int c = t.lane; c < ncon; c += t.T) bad |= (cs[kConSc * c + 26] == 0.f);
     if (t.isum(bad)) status |= 8;
   }
   t.sync();

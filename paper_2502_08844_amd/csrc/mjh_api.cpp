@@ -625,7 +625,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   x.o_xbar = take(3 * nb); x.o_Rbar = take(9 * nb); x.o_cinbar = take(kCinert * nb);
   x.o_Vbar = take(6 * nb); x.o_Abar = take(6 * nb); x.o_Fbar = take(6 * nb);
   x.o_vup = take(6 * nb); x.o_aup = take(6 * nb); x.o_xup = take(3 * nb);
-  x.o_Rup = take(9 * nb); x.o_rowsc = take(7 * nr); x.o_consc = take(10 * h.nconmax);
+  x.o_Rup = take(9 * nb); x.o_rowsc = take(7 * nr); x.o_consc = take(kConSc * h.nconmax);
   x.o_fw = take(nfw);
   x.lds_words = off;
   off = d.lds_words;
@@ -1341,13 +1341,15 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
 // The models the rollouts' reverse sweep covers: plane-sphere / plane-capsule contact
 // geometry with condim 3, no equalities, integrator 0, bodies of at most four joints.
 static mjh_status rollout_model_check(mjh_ctx* ctx, const ModelRec& mr) {
-  // the reverse sweep covers plane-sphere / plane-capsule contact geometry and bodies
-  // of at most four scalar joints
+  // the reverse sweep covers the contact geometry of planes, spheres and capsules against
+  // spheres and capsules, and bodies of at most four scalar joints
   for (int p = 0; p < mr.h.npair; p++) {
     const int t1 = mr.h.geom_type[mr.h.pair_g1[p]], t2 = mr.h.geom_type[mr.h.pair_g2[p]];
-    if (!(t1 == GEOM_PLANE && (t2 == GEOM_SPHERE || t2 == GEOM_CAPSULE)))
+    const bool round2 = t2 == GEOM_SPHERE || t2 == GEOM_CAPSULE;
+    if (!(round2 && (t1 == GEOM_PLANE || t1 == GEOM_SPHERE || t1 == GEOM_CAPSULE)))
       return fail(ctx, MJH_EUNSUPPORTED,
-                  "rollout: only plane-sphere and plane-capsule contacts are differentiated");
+                  "rollout: only contacts of planes, spheres and capsules with spheres and "
+                  "capsules are differentiated");
   }
   if (mr.h.neq > 0)
     return fail(ctx, MJH_EUNSUPPORTED, "rollout: equality constraints are not differentiated");

@@ -139,9 +139,7 @@ __device__ __forceinline__ void env_worlds(const DevGroup& G, const EnvArgs& E, 
   if (dr)
     for (int k = lane; k < E.ndr; k += T) dr[k] = E.dr[w * E.ndr + k];
   t.sync();
-  const float skp = dr ? dr[kDrKp] : 1.f, skd = dr ? dr[kDrKd] : 1.f;
   int status = 0;
-  const float* cmd = E.command + w * 3;
   for (int e = 0; e < E.nenv; e++) {
     const float* u = E.action + ((size_t)e * G.nworld + w) * nu;
     for (int s = 0; s < E.nsub; s++) {
@@ -154,6 +152,9 @@ __device__ __forceinline__ void env_worlds(const DevGroup& G, const EnvArgs& E, 
       if (rk) rk4_combine(m, W, t, status);
       else integrate(m, W, t, status);
     }
+    // (read here, after the physics steps, rather than held across them)
+    const float skp = dr ? dr[kDrKp] : 1.f, skd = dr ? dr[kDrKd] : 1.f;
+    const float* cmd = E.command + w * 3;
     // root rotation from its quaternion (every lane)
     float qw = qpos[3], qx = qpos[4], qy = qpos[5], qz = qpos[6];
     const float qn = 1.f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);

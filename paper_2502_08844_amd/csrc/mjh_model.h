@@ -30,6 +30,8 @@ constexpr int kMaxNv = 64;      // ancestor masks are 64-bit
 constexpr int kConRec = 18;     // on-chip contact record (floats)
 constexpr int kConOut = 20;     // exported contact record (MJH_CON_SIZE)
 constexpr int kCinert = 10;     // spatial inertia: m, m c (3), I at origin (6)
+constexpr int kConSc = 28;      // adjoint scratch per contact: four (cotangent, body point)
+                                // pairs, the two bodies, a flag
 
 struct DevModel {
   // ---- sizes

@@ -34,7 +34,7 @@ def usage():
 
 
 @pytest.mark.parametrize("kernel,scratch_max", [(STEP, 16), (STEP_RK, 16), (STEP_CONE, 48),
-                                                (ENV, 96), (ENV_DR, 112), (ENV_RK, 112)])
+                                                (ENV, 96), (ENV_DR, 104), (ENV_RK, 104)])
 def test_hot_kernels_fit_four_waves_with_small_scratch(usage, kernel, scratch_max):
     k = usage[kernel]
     assert k["VGPRs"] <= 128 and k["Occupancy"] >= 4
