@@ -173,6 +173,74 @@ DEV void seg_point_rev(const float* x, const float* a, const float* u, const flo
   }
 }
 
+// sphere_hfield_tri against a heightfield fixed in the world: the cotangents of pos
+// (xb), n (nb) and dist (db) -> of the sphere centre c.  In the field's frame, with
+// cl = Rg^T (c - xg), bq the triangle's nearest point and d = cl - bq: pos = (c + r n +
+// xg + Rg bq) / 2, n = Rg sg d / |d| and dist = -sg |d| - r (sg = +1 below the
+// triangle's plane, -1 above).  bq moves with cl by the projection onto the triangle's
+// plane (face), onto the edge's line (edge) or not at all (vertex).
+DEV void sphere_hfield_rev(const DevModel& m, const float* xg, const float* Rg, const float* c,
+                           float r, int code, const float* xb, const float* nb, float db,
+                           float* cb) {
+  if (code < 0) return;
+  const int cellid = code >> 1, k = code & 1;
+  const int i = cellid / m.hf_ncol, j = cellid - i * m.hf_ncol;
+  const V3 cl = hfield_local(xg, Rg, c);
+  V3 a, b, cc, bn;
+  hfield_tri(m, i, j, k, a, b, cc);
+  const V3 bq = tri_nearest(a, b, cc, cl, bn);
+  const V3 d = v3sub(cl, bq);
+  const float L = sqrtf(v3dot(d, d));
+  const float nt[3] = {nb[0] + 0.5f * r * xb[0], nb[1] + 0.5f * r * xb[1],
+                       nb[2] + 0.5f * r * xb[2]};  // the normal's whole cotangent
+  float xl[3], nl[3];
+  mtv3(Rg, xb, xl);
+  mtv3(Rg, nt, nl);
+  for (int q = 0; q < 3; q++) cb[q] += 0.5f * xb[q];
+  float dbar[3] = {0.f, 0.f, 0.f};
+  if (L > 1e-12f) {  // otherwise the forward code took the triangle's normal: constant
+    const float sg = v3dot(bn, d) < 0.f ? 1.f : -1.f;
+    const float dh[3] = {d.x / L, d.y / L, d.z / L};
+    const float dn = dh[0] * nl[0] + dh[1] * nl[1] + dh[2] * nl[2];
+    for (int q = 0; q < 3; q++) dbar[q] = sg * (nl[q] - dh[q] * dn) / L - sg * db * dh[q];
+  }
+  // d = cl - bq; bq's cotangent is that of pos's Rg bq / 2 minus d's
+  float bqb[3], clb[3];
+  for (int q = 0; q < 3; q++) { bqb[q] = 0.5f * xl[q] - dbar[q]; clb[q] = dbar[q]; }
+  // the region tri_nearest took
+  const float hgt = v3dot(v3sub(cl, a), bn) / v3dot(bn, bn);
+  const V3 pp = {cl.x - hgt * bn.x, cl.y - hgt * bn.y, cl.z - hgt * bn.z};
+  const bool in_a = v3dot(v3cross(v3sub(b, pp), v3sub(cc, pp)), bn) >= 0.f;
+  const bool in_b = v3dot(v3cross(v3sub(cc, pp), v3sub(a, pp)), bn) >= 0.f;
+  const bool in_c = v3dot(v3cross(v3sub(a, pp), v3sub(b, pp)), bn) >= 0.f;
+  if (in_a && in_b && in_c) {
+    const float nn = v3dot(bn, bn);
+    const float pn = (bqb[0] * bn.x + bqb[1] * bn.y + bqb[2] * bn.z) / nn;
+    clb[0] += bqb[0] - pn * bn.x; clb[1] += bqb[1] - pn * bn.y; clb[2] += bqb[2] - pn * bn.z;
+  } else {
+    // the edge seg_nearest kept: the first strictly nearest of ab, bc, ca
+    const V3 s0s[3] = {a, b, cc}, s1s[3] = {b, cc, a};
+    float best = INFINITY, tbest = 0.f;
+    V3 ubest = {0.f, 0.f, 0.f};
+    for (int e = 0; e < 3; e++) {
+      const V3 u = v3sub(s1s[e], s0s[e]), w = v3sub(cl, s0s[e]);
+      const float tt = fminf(fmaxf(v3dot(w, u) / v3dot(u, u), 0.f), 1.f);
+      const V3 x = {s0s[e].x + tt * u.x, s0s[e].y + tt * u.y, s0s[e].z + tt * u.z};
+      const V3 dx = v3sub(cl, x);
+      const float dd = v3dot(dx, dx);
+      if (dd < best) { best = dd; tbest = tt; ubest = u; }
+    }
+    if (tbest > 0.f && tbest < 1.f) {
+      const float uu = v3dot(ubest, ubest);
+      const float pu = (bqb[0] * ubest.x + bqb[1] * ubest.y + bqb[2] * ubest.z) / uu;
+      clb[0] += pu * ubest.x; clb[1] += pu * ubest.y; clb[2] += pu * ubest.z;
+    }
+  }
+  float cw[3];
+  mv3(Rg, clb, cw);  // cl = Rg^T (c - xg)
+  for (int q = 0; q < 3; q++) cb[q] += cw[q];
+}
+
 // seg_seg: parameters s, t of the closest points p0 + s d1, q0 + t d2; cotangents sb, tb
 DEV void seg_seg_rev(const float* p0, const float* d1, const float* q0, const float* d2,
                      float sb, float tb, float* p0b, float* d1b, float* q0b, float* d2b) {
@@ -647,6 +715,16 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
           local(2, g2, -h2);
           local(3, g2, h2);
         }
+      } else if (kind == PK_SPHERE_HFIELD) {
+        float nb[3] = {fb[0], fb[1], fb[2]};
+        frame_rev(rec + 4, rec + 7, fb + 3, fb + 6, nb);
+        float x1[3], R1[9], x2[3], R2[9];
+        geom_pose(m, W, g1, x1, R1);
+        geom_pose(m, W, g2, x2, R2);
+        const float* cpar = W + m.o_cand + m.ncand;  // the winning triangle per candidate
+        const int code = __float_as_int(cpar[m.pair_candadr[p] + (sub & 15)]);
+        sphere_hfield_rev(m, x2, R2, x1, m.geom_size[3 * g1], code, xb, nb, rb, o);
+        local(0, g1, 0.f);
       } else {
         o[26] = 0.f;  // geometry not differentiated (the rollout refuses such models)
       }

@@ -1,8 +1,9 @@
-"""GPU adjoint of the checkpointed rollout for a model with self-contacts.
+"""GPU adjoint of the checkpointed rollout for contact geometry beyond plane contacts.
 
-Workload: the humanoid (capsule-capsule and sphere-capsule pairs between its own limbs,
-plus capsule and sphere feet on the floor), horizon 64, checkpoints every 8 steps, the
-loss of the quadruped test (root z against 0.3, plus 1e-3 |u|^2).  Reference: the FP64
+Workloads: the humanoid (capsule-capsule and sphere-capsule pairs between its own
+limbs, plus capsule and sphere feet on the floor) and the quadruped on rough terrain
+(sphere feet against a heightfield); horizon 64, checkpoints every 8 steps, the loss of
+the quadruped test (root z against 0.3, plus 1e-3 |u|^2).  Reference: the FP64
 rollout's exact directional derivatives (forward-mode dual numbers, solver iterated to
 convergence) along random directions of the initial qvel and the controls.
 """
@@ -20,34 +21,32 @@ H, K = 64, 8
 GRAD_TOL = 1e-3
 
 
-def _setup(nw, seed):
-    m = robots.humanoid()
-    qp, qv = inputs.initial_state("humanoid", m, nw, seed=seed)
+def _setup(kind, nw, seed):
+    m = robots.WORKLOADS[kind]()
+    qp, qv = inputs.initial_state(kind, m, nw, seed=seed)
     rng = inputs.rng(seed, 7)
     qv = inputs.f32(qv + rng.normal(scale=0.1, size=qv.shape))
     u = inputs.f32(rng.uniform(-0.5, 0.5, size=(H, nw, m.nu)))
     return m, qp, qv, u
 
 
-def _self_contacts(o, m, qp, qv, u):
-    """Self-contacts per world over the rollout (FP64 reference, converged solver)."""
-    selfp = np.array([0 not in (m.geoms[p[0]].body, m.geoms[p[1]].body) for p in m.pairs])
+def _contacts_of(o, m, qp, qv, u, pairs):
+    """Contacts of the given pairs per world over the rollout (FP64 reference)."""
     q, v, ws = qp.astype(float), qv.astype(float), np.zeros((qp.shape[0], m.nv))
     n = np.zeros(qp.shape[0], dtype=int)
     for s in range(u.shape[0]):
         out = o.step(q, v, ws, u[s][None], nstep=1, mode=oracle.MODE_CONVERGED, nthreads=16)
         for w in range(qp.shape[0]):
             k = out["ncon"][w]
-            n[w] += selfp[out["contacts"][w, :k, 16].astype(int)].sum()
+            n[w] += pairs[out["contacts"][w, :k, 16].astype(int)].sum()
         q, v, ws = out["qpos"], out["qvel"], out["qacc"]
     return n
 
 
-def test_humanoid_gradient_directional_vs_dual_numbers():
+def _check(kind, pairs, what, seed=0, nw=64):
     from paper_2502_08844_amd import mjh
-    nw = 64
-    m, qp, qv, u = _setup(nw, seed=0)
-    print(f"[gpu] adjoint rollout humanoid nw={nw} horizon={H} ckpt={K}", flush=True)
+    m, qp, qv, u = _setup(kind, nw, seed)
+    print(f"[gpu] adjoint rollout {kind} nw={nw} horizon={H} ckpt={K}", flush=True)
     ctx = mjh.Context(0)
     w = mjh.World(ctx, m, nw, qpos=qp)
     qv0 = torch.tensor(qv, dtype=torch.float32, device="cuda", requires_grad=True)
@@ -65,15 +64,31 @@ def test_humanoid_gradient_directional_vs_dual_numbers():
     Lr, dL = o.rollout_jvp(qp, qv, u, dv, du, mode=oracle.MODE_CONVERGED, nthreads=16)
     rel_loss = np.abs(L - Lr) / np.abs(Lr)
     rel, smooth = directional_check(o, qp, qv, u, gq, gu, dv, du, dL)
-    nself = _self_contacts(o, m, qp, qv, u)
-    hit = nself > 0
-    print(f"[adjoint-self] loss rel err max {rel_loss.max():.2e}; worlds with self-contacts "
+    hit = _contacts_of(o, m, qp, qv, u, pairs(m)) > 0
+    without = rel[~hit & smooth]
+    print(f"[adjoint-{kind}] loss rel err max {rel_loss.max():.2e}; worlds with {what} "
           f"{hit.sum()}/{nw} (smooth {(hit & smooth).sum()})", flush=True)
-    print(f"[adjoint-self] <grad, d> vs dual JVP, error / (|grad| |d|): smooth worlds with "
-          f"self-contacts max {rel[hit & smooth].max():.2e} median "
-          f"{np.median(rel[hit & smooth]):.2e}; without max {rel[~hit & smooth].max():.2e}; "
-          f"non-smooth worlds' err {np.round(rel[~smooth], 5).tolist()}", flush=True)
+    print(f"[adjoint-{kind}] <grad, d> vs dual JVP, error / (|grad| |d|): smooth worlds with "
+          f"{what} max {rel[hit & smooth].max():.2e} median {np.median(rel[hit & smooth]):.2e}; "
+          f"without max {without.max() if without.size else 0.0:.2e}; non-smooth worlds' err "
+          f"{np.round(rel[~smooth], 5).tolist()}", flush=True)
     assert rel_loss.max() < 1e-3
-    assert (hit & smooth).sum() >= 8  # the self-contact geometry is exercised
+    assert (hit & smooth).sum() >= 8  # the geometry under test is exercised
     assert smooth.sum() >= 0.75 * nw
     assert rel[smooth].max() < GRAD_TOL
+
+
+def _self_pairs(m):
+    return np.array([0 not in (m.geoms[p[0]].body, m.geoms[p[1]].body) for p in m.pairs])
+
+
+def _field_pairs(m):
+    return np.array([m.geoms[p[1]].type == 4 for p in m.pairs])
+
+
+def test_humanoid_gradient_directional_vs_dual_numbers():
+    _check("humanoid", _self_pairs, "self-contacts")
+
+
+def test_rough_terrain_gradient_directional_vs_dual_numbers():
+    _check("quadruped_rough", _field_pairs, "heightfield contacts")
