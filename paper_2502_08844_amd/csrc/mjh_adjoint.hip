@@ -291,6 +291,18 @@ DEV void seg_seg_rev(const float* p0, const float* d1, const float* q0, const fl
   }
 }
 
+// contact rows: contact c's first row (con_nr c when every contact has con_nr rows,
+// else packed in its record), and the contact a row belongs to
+DEV int first_row(const DevModel& m, const float* rec, int c) {
+  return m.con_nr ? m.con_nr * c : __float_as_int(rec[17]) >> 8;
+}
+DEV int contact_of_row(const DevModel& m, const float* con, int ncon, int r) {
+  if (m.con_nr) return r / m.con_nr;
+  int c = 0;
+  while (c + 1 < ncon && (__float_as_int(con[kConRec * (c + 1) + 17]) >> 8) <= r) c++;
+  return c;
+}
+
 // ------------------------------------------------------------------ adjoint step
 // Inputs in LDS: qpos/qvel (state before the step), qacc (= a*), qbi/vbi (cotangents of
 // the state after the step).  Outputs: qb (nq), vb (nv), ub (nu).  Returns false for an
@@ -300,7 +312,9 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
   const float h = m.dt;
   const int ncon = ((const int*)(W + m.o_scal))[SC_NCON];
   const int nrow = ((const int*)(W + m.o_scal))[SC_NROW];
-  const int nrc = 4 * ncon;  // contact rows; joint-limit rows follow, then friction loss
+  // contact rows (4 a condim-3 pyramid, 1 a frictionless contact); joint-limit rows
+  // follow, then friction loss
+  const int nrc = ((const int*)(W + m.o_scal))[SC_NRC];
   const int nrf = nrow - m.nfric;
   const int nl = nrf - nrc;
   const int* lim = (const int*)(W + m.o_lim);
@@ -553,7 +567,7 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
       if (row_quad(D[r], r < nrf ? 0.f : fl[r], e[r])) {
         float dist = 0.f;  // friction loss: r = 0, not a function of the state
         if (r < nrc) {
-          dist = con[kConRec * (r >> 2)];
+          dist = con[kConRec * contact_of_row(m, con, ncon, r)];
         } else if (r < nrf) {
           int dof;
           float sg;
@@ -584,12 +598,13 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
         if (!row_quad(D[r], r < nrf ? 0.f : fl[r], e[r])) continue;
         vadd += o[4] * row_entry(m, W, r, k, ncon);
         if (r >= nrc) continue;  // limit and friction rows: constant Jacobians
-        const float* rec = con + kConRec * (r >> 2);
+        const int cr = contact_of_row(m, con, ncon, r);
+        const float* rec = con + kConRec * cr;
         const int b1 = __float_as_int(rec[14]), b2 = __float_as_int(rec[15]);
         const bool in2 = (m.body_dofmask[b2] & bit) != 0, in1 = (m.body_dofmask[b1] & bit) != 0;
         if (in1 == in2) continue;
         const float sg = in2 ? 1.f : -1.f;
-        const int ed = r & 3;
+        const int ed = r - first_row(m, rec, cr);  // edge n +- mu t_k (mu = 0: one row, n)
         const float sgm = (ed & 1) ? -rec[13] : rec[13];
         const float* tk = rec + 4 + 3 * (1 + (ed >> 1));
         const float ev[3] = {rec[4] + sgm * tk[0], rec[5] + sgm * tk[1], rec[6] + sgm * tk[2]};
@@ -607,13 +622,15 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
     for (int c = t.lane; c < ncon; c += t.T) {
       const float* rec = con + kConRec * c;
       const int b1 = __float_as_int(rec[14]), b2 = __float_as_int(rec[15]);
-      const int p = __float_as_int(rec[16]), sub = __float_as_int(rec[17]);
+      const int p = __float_as_int(rec[16]), sub = __float_as_int(rec[17]) & 15;
       const int kind = m.pair_kind[p];
       const bool plane = kind == PK_PLANE_SPHERE || kind == PK_PLANE_CAPSULE;
       float xb[3] = {0.f, 0.f, 0.f}, rb = 0.f;
       float fb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // of n, t1, t2
-      for (int ed = 0; ed < 4; ed++) {
-        const int r = 4 * c + ed;
+      const int first = first_row(m, rec, c);
+      const int nr = m.con_nr ? m.con_nr : (__float_as_int(rec[17]) >> 4) & 15;
+      for (int ed = 0; ed < nr; ed++) {
+        const int r = first + ed;
         if (!(e[r] < 0.f)) continue;
         const float* o = rs + 7 * r;
         rb += o[6];

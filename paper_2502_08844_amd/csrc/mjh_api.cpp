@@ -1357,8 +1357,10 @@ static mjh_status rollout_model_check(mjh_ctx* ctx, const ModelRec& mr) {
   if (mr.h.neq > 0)
     return fail(ctx, MJH_EUNSUPPORTED, "rollout: equality constraints are not differentiated");
   for (int p = 0; p < mr.h.npair; p++)
-    if (mr.h.pair_condim[p] != 3)
-      return fail(ctx, MJH_EUNSUPPORTED, "rollout: frictionless contacts are not differentiated");
+    if (mr.h.pair_condim[p] != 3 && mr.h.pair_condim[p] != 1)
+      return fail(ctx, MJH_EUNSUPPORTED,
+                  "rollout: only frictionless (condim 1) and condim-3 contacts are "
+                  "differentiated");
   if (mr.h.integrator != 0)
     return fail(ctx, MJH_EUNSUPPORTED, "rollout: implicit damping is not differentiated");
   if (mr.h.cone != 0)

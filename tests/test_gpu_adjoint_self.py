@@ -1,8 +1,9 @@
-"""GPU adjoint of the checkpointed rollout for contact geometry beyond plane contacts.
+"""GPU adjoint of the checkpointed rollout for contacts beyond condim-3 plane contacts.
 
 Workloads: the humanoid (capsule-capsule and sphere-capsule pairs between its own
-limbs, plus capsule and sphere feet on the floor) and the quadruped on rough terrain
-(sphere feet against a heightfield); horizon 64, checkpoints every 8 steps, the loss of
+limbs, plus capsule and sphere feet on the floor), the quadruped on rough terrain
+(sphere feet against a heightfield) and on frictionless ground (one row per contact);
+horizon 64, checkpoints every 8 steps, the loss of
 the quadruped test (root z against 0.3, plus 1e-3 |u|^2).  Reference: the FP64
 rollout's exact directional derivatives (forward-mode dual numbers, solver iterated to
 convergence) along random directions of the initial qvel and the controls.
@@ -92,3 +93,11 @@ def test_humanoid_gradient_directional_vs_dual_numbers():
 
 def test_rough_terrain_gradient_directional_vs_dual_numbers():
     _check("quadruped_rough", _field_pairs, "heightfield contacts")
+
+
+def _all_pairs(m):
+    return np.ones(len(m.pairs), dtype=bool)
+
+
+def test_frictionless_gradient_directional_vs_dual_numbers():
+    _check("quadruped_frictionless", _all_pairs, "contacts")
