@@ -303,139 +303,48 @@ DEV int contact_of_row(const DevModel& m, const float* con, int ncon, int r) {
   return c;
 }
 
-// ------------------------------------------------------------------ adjoint step
-// Inputs in LDS: qpos/qvel (state before the step), qacc (= a*), qbi/vbi (cotangents of
-// the state after the step).  Outputs: qb (nq), vb (nv), ub (nu).  Returns false for an
-// unsupported contact pair.
-DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u, int& status) {
+// x <- (M + h diag(dof_vgain))^-1 x in place, the implicit integrators' matrix (nv <= T),
+// with the dense factor in leaves-first (reversed) order as implicit_damping builds it;
+// refactor = false solves with the factor already in o_H.
+DEV void mhb_solve(const DevModel& m, float* W, const Team& t, float* x, bool refactor) {
+  const int nv = m.nv;
+  auto flip = [&]() {
+    for (int i = t.lane; i < nv / 2; i += t.T) {
+      const float v = x[i];
+      x[i] = x[nv - 1 - i];
+      x[nv - 1 - i] = v;
+    }
+    t.sync();
+  };
+  flip();
+  if (refactor) {
+    hessian_cholesky(m, W, t, 0, x, x, true, true);
+    cholesky_back(m, W, t, x, x);
+  } else {
+    cholesky_solve(m, W, t, x, x, 1.f);
+  }
+  flip();
+}
+
+// Reverse sweep of the recursive Newton-Euler inverse dynamics: adds to Sbar, cinbar
+// (and, unless still, vb) the cotangents of cot^T ID(q, qdot, acc).  still: zero
+// velocity and no gravity, so that ID = M(q) acc and the sweep gives the cotangent of
+// cot^T M(q) acc.
+DEV void rne_reverse(const DevModel& m, float* W, const Team& t, const float* cot,
+                     const float* acc, bool still) {
   const int nv = m.nv, nb = m.nbody;
-  const float h = m.dt;
-  const int ncon = ((const int*)(W + m.o_scal))[SC_NCON];
-  const int nrow = ((const int*)(W + m.o_scal))[SC_NROW];
-  // contact rows (4 a condim-3 pyramid, 1 a frictionless contact); joint-limit rows
-  // follow, then friction loss
-  const int nrc = ((const int*)(W + m.o_scal))[SC_NRC];
-  const int nrf = nrow - m.nfric;
-  const int nl = nrf - nrc;
-  const int* lim = (const int*)(W + m.o_lim);
-  const float* fl = W + m.o_fl;
-  const float* qpos = W + m.o_qpos;
-  const float* qvel = W + m.o_qvel;
-  const float* a = W + m.o_qacc;
-  const float* qbi = W + m.o_qbi;
-  const float* vbi = W + m.o_vbi;
-  float* qb = W + m.o_qb;
+  const float* qv0 = W + m.o_qvel;
+  auto qv = [&](int i) { return still ? 0.f : qv0[i]; };
   float* vb = W + m.o_vb;
-  float* ub = W + m.o_ub;
-  float* mu = W + m.o_mu;
-  float* abar = W + m.o_g;  // scratch of the forward solve, free now
   const float* cdof = W + m.o_cdof;
   float* Sbar = W + m.o_Sbar;
-  float* xbar = W + m.o_xbar;
-  float* Rbar = W + m.o_Rbar;
   float* cinbar = W + m.o_cinbar;
   float* Vbar = W + m.o_Vbar;
   float* Abar = W + m.o_Abar;
   float* Fbar = W + m.o_Fbar;
   float* vup = W + m.o_vup;
   float* aup = W + m.o_aup;
-  float* xup = W + m.o_xup;
-  float* Rup = W + m.o_Rup;
-
-  // ---- clear body accumulators
-  for (int k = t.lane; k < 3 * nb; k += t.T) xbar[k] = 0.f;
-  for (int k = t.lane; k < 9 * nb; k += t.T) Rbar[k] = 0.f;
-  for (int k = t.lane; k < kCinert * nb; k += t.T) cinbar[k] = 0.f;
-  for (int k = t.lane; k < m.nu; k += t.T) ub[k] = 0.f;
-  // ---- semi-implicit Euler, reversed (lane per joint)
-  for (int j = t.lane; j < m.njnt; j += t.T) {
-    const int qa = m.jnt_qposadr[j], da = m.jnt_dofadr[j];
-    if (m.jnt_type[j] == JNT_FREE) {
-      for (int k = 0; k < 3; k++) {
-        qb[qa + k] = qbi[qa + k];
-        vb[da + k] = vbi[da + k] + h * qbi[qa + k];
-      }
-      // q' = normalize(q (x) exp(h w')), w' = qvel'[3:6]
-      float wv[3];
-      for (int k = 0; k < 3; k++) wv[k] = h * (qvel[da + 3 + k] + h * a[da + 3 + k]);
-      const float th = sqrtf(dot3(wv, wv));
-      float sn, cs;
-      sincosf(0.5f * th, &sn, &cs);
-      // f(th) = sin(th/2)/th and f'(th)/th; series below 0.1 (the closed form cancels)
-      float fth, fpt;
-      if (th > 0.1f) {
-        fth = sn / th;
-        fpt = (0.5f * th * cs - sn) / (th * th * th);
-      } else {
-        const float t2 = th * th;
-        fth = 0.5f - t2 / 48.f + t2 * t2 / 3840.f;
-        fpt = -1.f / 24.f + t2 / 960.f;
-      }
-      const float ds0 = -0.5f * fth;
-      const float dq[4] = {cs, fth * wv[0], fth * wv[1], fth * wv[2]};
-      const float quat[4] = {qpos[qa + 3], qpos[qa + 4], qpos[qa + 5], qpos[qa + 6]};
-      float r[4];
-      quat_mul4(quat, dq, r);
-      const float rn = sqrtf(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
-      const float qo[4] = {r[0] / rn, r[1] / rn, r[2] / rn, r[3] / rn};
-      const float* gq = qbi + qa + 3;
-      const float dotq = qo[0] * gq[0] + qo[1] * gq[1] + qo[2] * gq[2] + qo[3] * gq[3];
-      float rbar[4];
-      for (int k = 0; k < 4; k++) rbar[k] = (gq[k] - qo[k] * dotq) / rn;
-      const float dqc[4] = {dq[0], -dq[1], -dq[2], -dq[3]};
-      const float qc[4] = {quat[0], -quat[1], -quat[2], -quat[3]};
-      float qq[4], dqbar[4];
-      quat_mul4(rbar, dqc, qq);
-      quat_mul4(qc, rbar, dqbar);
-      for (int k = 0; k < 4; k++) qb[qa + 3 + k] = qq[k];
-      const float wd = wv[0] * dqbar[1] + wv[1] * dqbar[2] + wv[2] * dqbar[3];
-      for (int k = 0; k < 3; k++) {
-        const float wbar = dqbar[0] * ds0 * wv[k] + fth * dqbar[1 + k] + fpt * wd * wv[k];
-        vb[da + 3 + k] = vbi[da + 3 + k] + h * wbar;
-      }
-    } else {
-      qb[qa] = qbi[qa];
-      vb[da] = vbi[da] + h * qbi[qa];
-    }
-  }
-  t.sync();
-  for (int i = t.lane; i < nv; i += t.T) abar[i] = h * vb[i];
-  // ---- implicit differentiation: lambda = H(a*)^-1 a_bar, mu = -lambda
-  {
-    const float* aref = W + m.o_aref;
-    float* e = W + m.o_e;
-    const RowBounds rb = pad_rows(m, W, t, nrow);
-    rows_times(m, W, t, nrow, rb, a, e);
-    for (int r = t.lane; r < nrow; r += t.T) e[r] -= aref[r];
-    t.sync();
-    if (!hessian_cholesky(m, W, t, rb.nru, nullptr, nullptr, false, false, nullptr, false,
-                          rb.nou))
-      status |= 4;
-    cholesky_solve(m, W, t, abar, mu, -1.f);
-  }
-  // ---- actuation and passive forces, reversed (lane per dof)
-  for (int i = t.lane; i < nv; i += t.T) {
-    const float mi = mu[i];
-    vb[i] += m.dof_damping[i] * mi;
-    const int ac = m.dof_act[i];
-    if (ac >= 0) {
-      const float c = u ? u[ac] : 0.f;
-      const bool inr = c >= m.act_lo[ac] && c <= m.act_hi[ac];
-      if (m.act_type[ac] == ACT_MOTOR) {
-        ub[ac] = inr ? -m.act_gear[ac] * mi : 0.f;
-      } else {
-        ub[ac] = inr ? -m.act_kp[ac] * m.act_gear[ac] * mi : 0.f;
-        vb[i] += m.act_kd[ac] * mi;
-      }
-    }
-  }
-  t.sync();
-  for (int i = t.lane; i < nv; i += t.T) {  // PD stiffness acts on qpos (separate pass:
-    const int ac = m.dof_act[i];             // qb of a hinge is one word per lane)
-    if (ac >= 0 && m.act_type[ac] == ACT_PD) qb[m.act_qadr[ac]] += m.act_kp[ac] * mu[i];
-  }
-  // ---- inverse dynamics with a*: V, A, body inertias, subtree forces
-  forward_sweep(m, W, t, a);
+  forward_sweep(m, W, t, acc, nullptr, still);
   accumulate_forces(m, W, t);
   const float* cvel = W + m.o_cvel;
   const float* cacc = W + m.o_cacc;
@@ -444,12 +353,12 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
   // S_bar = mu_k F_body(k); F_bar(b) = sum_k in b mu_k S_k
   for (int k = t.lane; k < nv; k += t.T) {
     const int b = m.dof_body[k];
-    for (int c = 0; c < 6; c++) Sbar[6 * k + c] = mu[k] * cfrc[6 * b + c];
+    for (int c = 0; c < 6; c++) Sbar[6 * k + c] += cot[k] * cfrc[6 * b + c];
   }
   for (int b = t.lane; b < nb; b += t.T) {
     float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int k = m.body_dofadr[b]; k < m.body_dofadr[b] + m.body_dofnum[b]; k++)
-      for (int c = 0; c < 6; c++) f[c] += mu[k] * cdof[6 * k + c];
+      for (int c = 0; c < 6; c++) f[c] += cot[k] * cdof[6 * k + c];
     for (int c = 0; c < 6; c++) Fbar[6 * b + c] = f[c];
   }
   t.sync();
@@ -501,7 +410,7 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
       if (!free) {
         for (int jj = 0; jj < nj && jj < 4; jj++) {
           const int da = m.jnt_dofadr[j0 + jj];
-          for (int c = 0; c < 6; c++) { V[c] += cdof[6 * da + c] * qvel[da]; Vs[jj][c] = V[c]; }
+          for (int c = 0; c < 6; c++) { V[c] += cdof[6 * da + c] * qv(da); Vs[jj][c] = V[c]; }
         }
         for (int jj = nj - 1; jj >= 0; jj--) {
           const int da = m.jnt_dofadr[j0 + jj];
@@ -510,28 +419,28 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
           float Sdbar[6], Sd[6], tmp[6];
           crossm(Vs[jj < 4 ? jj : 3], S, Sd);
           for (int c = 0; c < 6; c++) {
-            Sdbar[c] = qvel[da] * Ab_[c];
-            Sbar[6 * da + c] += a[da] * Ab_[c];
+            Sdbar[c] = qv(da) * Ab_[c];
+            Sbar[6 * da + c] += acc[da] * Ab_[c];
           }
-          vb[da] += dot6(Sd, Ab_);
+          if (!still) vb[da] += dot6(Sd, Ab_);
           crossf(S, Sdbar, tmp);
           for (int c = 0; c < 6; c++) Vb_[c] += tmp[c];
           crossf(Vs[jj < 4 ? jj : 3], Sdbar, tmp);
-          for (int c = 0; c < 6; c++) Sbar[6 * da + c] += -tmp[c] + qvel[da] * Vb_[c];
-          vb[da] += dot6(S, Vb_);
+          for (int c = 0; c < 6; c++) Sbar[6 * da + c] += -tmp[c] + qv(da) * Vb_[c];
+          if (!still) vb[da] += dot6(S, Vb_);
         }
       } else {
         const int da = m.jnt_dofadr[j0];
         for (int i = 0; i < 6; i++)
-          for (int c = 0; c < 6; c++) V[c] += cdof[6 * (da + i) + c] * qvel[da + i];
+          for (int c = 0; c < 6; c++) V[c] += cdof[6 * (da + i) + c] * qv(da + i);
         for (int i = 0; i < 6; i++) {
           const float* S = cdof + 6 * (da + i);
-          for (int c = 0; c < 6; c++) Sbar[6 * (da + i) + c] += a[da + i] * Ab_[c];
+          for (int c = 0; c < 6; c++) Sbar[6 * (da + i) + c] += acc[da + i] * Ab_[c];
           if (i >= 3) {
             float Sd[6], Sdbar[6], tmp[6];
             crossm(V, S, Sd);
-            for (int c = 0; c < 6; c++) Sdbar[c] = qvel[da + i] * Ab_[c];
-            vb[da + i] += dot6(Sd, Ab_);
+            for (int c = 0; c < 6; c++) Sdbar[c] = qv(da + i) * Ab_[c];
+            if (!still) vb[da + i] += dot6(Sd, Ab_);
             crossf(S, Sdbar, tmp);
             for (int c = 0; c < 6; c++) Vb_[c] += tmp[c];
             crossf(V, Sdbar, tmp);
@@ -540,14 +449,184 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
         }
         for (int i = 0; i < 6; i++) {
           const float* S = cdof + 6 * (da + i);
-          for (int c = 0; c < 6; c++) Sbar[6 * (da + i) + c] += qvel[da + i] * Vb_[c];
-          vb[da + i] += dot6(S, Vb_);
+          for (int c = 0; c < 6; c++) Sbar[6 * (da + i) + c] += qv(da + i) * Vb_[c];
+          if (!still) vb[da + i] += dot6(S, Vb_);
         }
       }
       for (int c = 0; c < 6; c++) { vup[6 * b + c] = Vb_[c]; aup[6 * b + c] = Ab_[c]; }
     }
     t.sync();
   }
+}
+
+// ------------------------------------------------------------------ adjoint step
+// Inputs in LDS: qpos/qvel (state before the step), qacc (= a*), qbi/vbi (cotangents of
+// the state after the step).  Outputs: qb (nq), vb (nv), ub (nu).  Returns false for an
+// unsupported contact pair.
+DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u, int& status) {
+  const int nv = m.nv, nb = m.nbody;
+  const float h = m.dt;
+  const int ncon = ((const int*)(W + m.o_scal))[SC_NCON];
+  const int nrow = ((const int*)(W + m.o_scal))[SC_NROW];
+  // contact rows (4 a condim-3 pyramid, 1 a frictionless contact); joint-limit rows
+  // follow, then friction loss
+  const int nrc = ((const int*)(W + m.o_scal))[SC_NRC];
+  const int nrf = nrow - m.nfric;
+  const int nl = nrf - nrc;
+  const int* lim = (const int*)(W + m.o_lim);
+  const float* fl = W + m.o_fl;
+  const float* qpos = W + m.o_qpos;
+  const float* qvel = W + m.o_qvel;
+  const float* a = W + m.o_qacc;
+  const float* qbi = W + m.o_qbi;
+  const float* vbi = W + m.o_vbi;
+  float* qb = W + m.o_qb;
+  float* vb = W + m.o_vb;
+  float* ub = W + m.o_ub;
+  float* mu = W + m.o_mu;
+  float* abar = W + m.o_g;  // scratch of the forward solve, free now
+  const float* cdof = W + m.o_cdof;
+  float* Sbar = W + m.o_Sbar;
+  float* xbar = W + m.o_xbar;
+  float* Rbar = W + m.o_Rbar;
+  float* cinbar = W + m.o_cinbar;
+  float* Vbar = W + m.o_Vbar;
+  float* Abar = W + m.o_Abar;
+  float* Fbar = W + m.o_Fbar;
+  float* vup = W + m.o_vup;
+  float* aup = W + m.o_aup;
+  float* xup = W + m.o_xup;
+  float* Rup = W + m.o_Rup;
+
+  // ---- clear body accumulators
+  for (int k = t.lane; k < 3 * nb; k += t.T) xbar[k] = 0.f;
+  for (int k = t.lane; k < 9 * nb; k += t.T) Rbar[k] = 0.f;
+  for (int k = t.lane; k < kCinert * nb; k += t.T) cinbar[k] = 0.f;
+  for (int k = t.lane; k < 6 * nv; k += t.T) Sbar[k] = 0.f;
+  for (int k = t.lane; k < m.nu; k += t.T) ub[k] = 0.f;
+  // ---- implicit integrators: qvel' = qvel + h a_int, (M + h B) a_int = M a* - c qdot
+  // (the converged solve's smooth and row forces sum to M a*; B = diag(dof_vgain), c =
+  // dof_hkp for integrator 2, else 0)
+  const bool imp = m.implicit != 0;
+  const float* M = W + m.o_M;
+  float* ai = W + m.o_d;  // a_int, later a* - a_int
+  float* y = W + m.o_Md;  // (M + h B)^-1 a_int_bar
+  if (imp) {
+    for (int i = t.lane; i < nv; i += t.T) {
+      float v = m.implicit == 2 ? -m.dof_hkp[i] * qvel[i] : 0.f;
+      for (int k = 0; k < nv; k++) v += M[sym(i, k)] * a[k];
+      ai[i] = v;
+    }
+    t.sync();
+    mhb_solve(m, W, t, ai, true);
+  }
+  const float* av = imp ? ai : a;  // the acceleration of the velocity update
+  // ---- semi-implicit Euler, reversed (lane per joint)
+  for (int j = t.lane; j < m.njnt; j += t.T) {
+    const int qa = m.jnt_qposadr[j], da = m.jnt_dofadr[j];
+    if (m.jnt_type[j] == JNT_FREE) {
+      for (int k = 0; k < 3; k++) {
+        qb[qa + k] = qbi[qa + k];
+        vb[da + k] = vbi[da + k] + h * qbi[qa + k];
+      }
+      // q' = normalize(q (x) exp(h w')), w' = qvel'[3:6]
+      float wv[3];
+      for (int k = 0; k < 3; k++) wv[k] = h * (qvel[da + 3 + k] + h * av[da + 3 + k]);
+      const float th = sqrtf(dot3(wv, wv));
+      float sn, cs;
+      sincosf(0.5f * th, &sn, &cs);
+      // f(th) = sin(th/2)/th and f'(th)/th; series below 0.1 (the closed form cancels)
+      float fth, fpt;
+      if (th > 0.1f) {
+        fth = sn / th;
+        fpt = (0.5f * th * cs - sn) / (th * th * th);
+      } else {
+        const float t2 = th * th;
+        fth = 0.5f - t2 / 48.f + t2 * t2 / 3840.f;
+        fpt = -1.f / 24.f + t2 / 960.f;
+      }
+      const float ds0 = -0.5f * fth;
+      const float dq[4] = {cs, fth * wv[0], fth * wv[1], fth * wv[2]};
+      const float quat[4] = {qpos[qa + 3], qpos[qa + 4], qpos[qa + 5], qpos[qa + 6]};
+      float r[4];
+      quat_mul4(quat, dq, r);
+      const float rn = sqrtf(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+      const float qo[4] = {r[0] / rn, r[1] / rn, r[2] / rn, r[3] / rn};
+      const float* gq = qbi + qa + 3;
+      const float dotq = qo[0] * gq[0] + qo[1] * gq[1] + qo[2] * gq[2] + qo[3] * gq[3];
+      float rbar[4];
+      for (int k = 0; k < 4; k++) rbar[k] = (gq[k] - qo[k] * dotq) / rn;
+      const float dqc[4] = {dq[0], -dq[1], -dq[2], -dq[3]};
+      const float qc[4] = {quat[0], -quat[1], -quat[2], -quat[3]};
+      float qq[4], dqbar[4];
+      quat_mul4(rbar, dqc, qq);
+      quat_mul4(qc, rbar, dqbar);
+      for (int k = 0; k < 4; k++) qb[qa + 3 + k] = qq[k];
+      const float wd = wv[0] * dqbar[1] + wv[1] * dqbar[2] + wv[2] * dqbar[3];
+      for (int k = 0; k < 3; k++) {
+        const float wbar = dqbar[0] * ds0 * wv[k] + fth * dqbar[1 + k] + fpt * wd * wv[k];
+        vb[da + 3 + k] = vbi[da + 3 + k] + h * wbar;
+      }
+    } else {
+      qb[qa] = qbi[qa];
+      vb[da] = vbi[da] + h * qbi[qa];
+    }
+  }
+  t.sync();
+  for (int i = t.lane; i < nv; i += t.T) abar[i] = h * vb[i];
+  if (imp) {
+    // a_int's cotangent: y = (M + h B)^-1 a_int_bar; then a* gets M y, qdot gets -c y,
+    // and M(q) the outer product y (a* - a_int)^T (its sweep below)
+    t.sync();
+    for (int i = t.lane; i < nv; i += t.T) y[i] = abar[i];
+    t.sync();
+    mhb_solve(m, W, t, y, false);
+    for (int i = t.lane; i < nv; i += t.T) {
+      if (m.implicit == 2) vb[i] -= m.dof_hkp[i] * y[i];
+      float v = 0.f;
+      for (int k = 0; k < nv; k++) v += M[sym(i, k)] * y[k];
+      abar[i] = v;
+      ai[i] = a[i] - ai[i];
+    }
+    t.sync();
+  }
+  // ---- implicit differentiation: lambda = H(a*)^-1 a_bar, mu = -lambda
+  {
+    const float* aref = W + m.o_aref;
+    float* e = W + m.o_e;
+    const RowBounds rb = pad_rows(m, W, t, nrow);
+    rows_times(m, W, t, nrow, rb, a, e);
+    for (int r = t.lane; r < nrow; r += t.T) e[r] -= aref[r];
+    t.sync();
+    if (!hessian_cholesky(m, W, t, rb.nru, nullptr, nullptr, false, false, nullptr, false,
+                          rb.nou))
+      status |= 4;
+    cholesky_solve(m, W, t, abar, mu, -1.f);
+  }
+  // ---- actuation and passive forces, reversed (lane per dof)
+  for (int i = t.lane; i < nv; i += t.T) {
+    const float mi = mu[i];
+    vb[i] += m.dof_damping[i] * mi;
+    const int ac = m.dof_act[i];
+    if (ac >= 0) {
+      const float c = u ? u[ac] : 0.f;
+      const bool inr = c >= m.act_lo[ac] && c <= m.act_hi[ac];
+      if (m.act_type[ac] == ACT_MOTOR) {
+        ub[ac] = inr ? -m.act_gear[ac] * mi : 0.f;
+      } else {
+        ub[ac] = inr ? -m.act_kp[ac] * m.act_gear[ac] * mi : 0.f;
+        vb[i] += m.act_kd[ac] * mi;
+      }
+    }
+  }
+  t.sync();
+  for (int i = t.lane; i < nv; i += t.T) {  // PD stiffness acts on qpos (separate pass:
+    const int ac = m.dof_act[i];             // qb of a hinge is one word per lane)
+    if (ac >= 0 && m.act_type[ac] == ACT_PD) qb[m.act_qadr[ac]] += m.act_kp[ac] * mu[i];
+  }
+  // ---- inverse dynamics with a*, reversed (implicit integrators: first y^T M(q) (a* - a_int))
+  if (imp) rne_reverse(m, W, t, y, ai, true);
+  rne_reverse(m, W, t, mu, a, false);
   // ---- contact rows, reversed
   if (nrow > 0) {
     const float* D = W + m.o_D;

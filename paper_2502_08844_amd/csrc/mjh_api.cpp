@@ -1338,8 +1338,9 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
 
 }  // extern "C"
 
-// The models the rollouts' reverse sweep covers: plane-sphere / plane-capsule contact
-// geometry with condim 3, no equalities, integrator 0, bodies of at most four joints.
+// The models the rollouts' reverse sweep covers: the contact geometry below with condim 1
+// or 3, no equalities, no elliptic cones, semi-implicit Euler or the implicit
+// integrators (not RK4), bodies of at most four joints.
 static mjh_status rollout_model_check(mjh_ctx* ctx, const ModelRec& mr) {
   // the reverse sweep covers the contact geometry of planes, spheres and capsules against
   // spheres and capsules, and of spheres against a heightfield fixed in the world; and
@@ -1361,8 +1362,8 @@ static mjh_status rollout_model_check(mjh_ctx* ctx, const ModelRec& mr) {
       return fail(ctx, MJH_EUNSUPPORTED,
                   "rollout: only frictionless (condim 1) and condim-3 contacts are "
                   "differentiated");
-  if (mr.h.integrator != 0)
-    return fail(ctx, MJH_EUNSUPPORTED, "rollout: implicit damping is not differentiated");
+  if (mr.h.integrator == 3)
+    return fail(ctx, MJH_EUNSUPPORTED, "rollout: Runge-Kutta steps are not differentiated");
   if (mr.h.cone != 0)
     return fail(ctx, MJH_EUNSUPPORTED, "rollout: elliptic cones are not differentiated");
   {
@@ -1386,6 +1387,10 @@ mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every, co
   const ModelRec& mr = *ctx->models[g.model];
   mjh_status st = rollout_model_check(ctx, mr);
   if (st != MJH_OK) return st;
+  if (mr.h.integrator != 0 && mr.dm.nv > g.team)
+    return fail(ctx, MJH_EUNSUPPORTED,
+                "rollout: implicit integrators are differentiated for worlds of at most one "
+                "dof per lane of their team");
   std::string err;
   st = adjoint_forward(&b->adj, mr.dm_adj, g.team, g.nworld, g.qpos, g.qvel, g.qacc, horizon,
                        ckpt_every, ctrl, zidx, ztarget, wctrl, loss, generation,

@@ -241,10 +241,12 @@ DEV void actuation(const DevModel& m, float* W, const Team& t, const float* ctrl
 // absolute pose), record motion subspaces S (world origin) and their rates, the
 // body velocity V, bias acceleration A (qacc = 0, world at -gravity), spatial
 // inertia and the body force f = I A + V x* I V.
+// still: velocities taken as zero and no gravity (then cfrc = the forces of M qacc alone)
 DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* qacc = nullptr,
-                       const float* dr = nullptr) {
+                       const float* dr = nullptr, bool still = false) {
   const float* qpos = W + m.o_qpos;
-  const float* qvel = W + m.o_qvel;
+  const float* qv0 = W + m.o_qvel;
+  auto qvel = [&](int i) { return still ? 0.f : qv0[i]; };
   float* xpos = W + m.o_xpos;
   float* xmat = W + m.o_xmat;
   float* cvel = W + m.o_cvel;
@@ -256,7 +258,7 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* 
   // contact phases, so it is set again every step)
   if (t.lane < 6) {
     cvel[t.lane] = 0.f;
-    cacc[t.lane] = t.lane < 3 ? 0.f : -m.grav[t.lane - 3];
+    cacc[t.lane] = (still || t.lane < 3) ? 0.f : -m.grav[t.lane - 3];
   }
   // Positions are relative to the origin p0, the first joint's position when it is a
   // free joint (else the world origin): the world body sits at -p0.  The step is
@@ -297,12 +299,12 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* 
             cross3(pos, col, r + 3);
           }
           for (int i = 0; i < 6; i++)
-            for (int k = 0; k < 6; k++) V[k] += S[6 * i + k] * qvel[da + i];
+            for (int k = 0; k < 6; k++) V[k] += S[6 * i + k] * qvel(da + i);
           // translation subspaces are fixed in the world (zero rate), rotation ones turn
           // with the body: rate V_body x S
           for (int i = 3; i < 6; i++) {
             crossm(V, S + 6 * i, Sd);
-            for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel[da + i];
+            for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel(da + i);
           }
           if (qacc)
             for (int i = 0; i < 6; i++)
@@ -314,9 +316,9 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* 
           for (int k = 0; k < 3; k++) pos[k] += ax[k] * q;
           S[0] = S[1] = S[2] = 0.f;
           S[3] = ax[0]; S[4] = ax[1]; S[5] = ax[2];
-          for (int k = 0; k < 6; k++) V[k] += S[k] * qvel[da];
+          for (int k = 0; k < 6; k++) V[k] += S[k] * qvel(da);
           crossm(V, S, Sd);
-          for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel[da] + (qacc ? S[k] * qacc[da] : 0.f);
+          for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel(da) + (qacc ? S[k] * qacc[da] : 0.f);
         } else {  // hinge
           // Rotation about the world axis R a equals R Rot(a, q) with the body-frame
           // axis a.  The second form builds the joint rotation from exact model data,
@@ -332,9 +334,9 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* 
           for (int k = 0; k < 3; k++) pos[k] = anc[k] - off[k];
           S[0] = ax[0]; S[1] = ax[1]; S[2] = ax[2];
           cross3(anc, ax, S + 3);
-          for (int k = 0; k < 6; k++) V[k] += S[k] * qvel[da];
+          for (int k = 0; k < 6; k++) V[k] += S[k] * qvel(da);
           crossm(V, S, Sd);
-          for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel[da] + (qacc ? S[k] * qacc[da] : 0.f);
+          for (int k = 0; k < 6; k++) A[k] += Sd[k] * qvel(da) + (qacc ? S[k] * qacc[da] : 0.f);
         }
       }
       for (int k = 0; k < 3; k++) xpos[3 * b + k] = pos[k];

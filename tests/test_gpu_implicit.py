@@ -94,10 +94,12 @@ def test_stiff_pd_decays_on_gpu(lib):
     np.testing.assert_allclose(r["qvel"][:, 0], x[1], rtol=1e-4, atol=1e-7)
 
 
-def test_rollout_rejects_implicit(lib):
+def test_rollout_rejects_implicit_beyond_one_dof_per_lane(lib):
+    """The implicit integrators' reverse sweep takes the dense factor (nv <= team)."""
     mjh, ctx = lib
-    m = robots.quadruped_implicit()
+    m = robots.quadruped_implicit()  # nv 18
     w = mjh.World(ctx, m, 2)
+    w.batch.set_launch(0, 16, 64)
     u = torch.zeros(4, 2, m.nu, device="cuda")
     loss = torch.zeros(2, device="cuda")
     with pytest.raises(mjh.MjhError):
