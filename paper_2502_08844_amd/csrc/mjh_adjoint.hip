@@ -459,6 +459,29 @@ DEV void rne_reverse(const DevModel& m, float* W, const Team& t, const float* co
   }
 }
 
+// Directions of edge ed of a pyramid contact (record rec): the row is lin . v + ang . w
+// for the relative point velocity v and angular velocity w.  Edges 0-3: n +- mu t_k;
+// 4, 5 (condim 4): n and +- mu_t n (spin); 6-9 (condim 6): n and +- mu_r t_k (rolling).
+// Returns the frame vector the angular part scales (0: n, 1: t1, 2: t2; -1: none) and
+// its factor in sa.
+DEV int edge_dirs(const DevModel& m, const float* rec, int ed, float* lin, float* ang,
+                  float& sa) {
+  const float* n = rec + 4;
+  sa = 0.f;
+  if (ed < 4) {
+    const float sgm = (ed & 1) ? -rec[13] : rec[13];
+    const float* tk = rec + 4 + 3 * (1 + (ed >> 1));
+    for (int q = 0; q < 3; q++) { lin[q] = n[q] + sgm * tk[q]; ang[q] = 0.f; }
+    return -1;
+  }
+  const int p = __float_as_int(rec[16]);
+  const int f = ed < 6 ? 0 : 1 + ((ed - 6) >> 1);
+  const float c = ed < 6 ? m.pair_mu_t[p] : m.pair_mu_r[p];
+  sa = (ed & 1) ? -c : c;
+  for (int q = 0; q < 3; q++) { lin[q] = n[q]; ang[q] = sa * rec[4 + 3 * f + q]; }
+  return f;
+}
+
 // ------------------------------------------------------------------ adjoint step
 // Inputs in LDS: qpos/qvel (state before the step), qacc (= a*), qbi/vbi (cotangents of
 // the state after the step).  Outputs: qb (nq), vb (nv), ub (nu).  Returns false for an
@@ -683,14 +706,13 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
         const bool in2 = (m.body_dofmask[b2] & bit) != 0, in1 = (m.body_dofmask[b1] & bit) != 0;
         if (in1 == in2) continue;
         const float sg = in2 ? 1.f : -1.f;
-        const int ed = r - first_row(m, rec, cr);  // edge n +- mu t_k (mu = 0: one row, n)
-        const float sgm = (ed & 1) ? -rec[13] : rec[13];
-        const float* tk = rec + 4 + 3 * (1 + (ed >> 1));
-        const float ev[3] = {rec[4] + sgm * tk[0], rec[5] + sgm * tk[1], rec[6] + sgm * tk[2]};
+        const int ed = r - first_row(m, rec, cr);  // (mu = 0: one row, along n)
+        float ev[3], ew[3], sa;
+        edge_dirs(m, rec, ed, ev, ew, sa);
         const float w = sg * (o[3] * mu[k] + o[4] * qvel[k] + o[5] * a[k]);
         float pe[3];
         cross3(rec + 1, ev, pe);
-        for (int c = 0; c < 3; c++) { sb[c] += w * pe[c]; sb[3 + c] += w * ev[c]; }
+        for (int c = 0; c < 3; c++) { sb[c] += w * (pe[c] + ew[c]); sb[3 + c] += w * ev[c]; }
       }
       vb[k] += vadd;
       for (int c = 0; c < 6; c++) Sbar[6 * k + c] += sb[c];
@@ -713,9 +735,8 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
         if (!(e[r] < 0.f)) continue;
         const float* o = rs + 7 * r;
         rb += o[6];
-        const float sgm = (ed & 1) ? -rec[13] : rec[13];
-        const float* tk = rec + 4 + 3 * (1 + (ed >> 1));
-        const float ev[3] = {rec[4] + sgm * tk[0], rec[5] + sgm * tk[1], rec[6] + sgm * tk[2]};
+        float ev[3], ew[3], sa;
+        const int fa = edge_dirs(m, rec, ed, ev, ew, sa);
         float om[3] = {0.f, 0.f, 0.f}, ln[3] = {0.f, 0.f, 0.f};
         for (int k = 0; k < nv; k++) {
           const unsigned long long bit = 1ull << k;
@@ -730,13 +751,16 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
         float x3[3];
         cross3(ev, om, x3);
         for (int q = 0; q < 3; q++) xb[q] += x3[q];
-        if (!plane) {  // the row direction n +- mu t_k moves: its cotangent ln + om x pos
+        if (!plane) {  // the frame moves: the linear direction's cotangent ln + om x pos,
+                       // the angular direction's om
           float op[3];
           cross3(om, rec + 1, op);
+          const float sgm = (ed & 1) ? -rec[13] : rec[13];
           for (int q = 0; q < 3; q++) {
             const float g = ln[q] + op[q];
             fb[q] += g;
-            fb[3 + 3 * (ed >> 1) + q] += sgm * g;
+            if (ed < 4) fb[3 + 3 * (ed >> 1) + q] += sgm * g;
+            if (fa >= 0) fb[3 * fa + q] += sa * om[q];
           }
         }
       }

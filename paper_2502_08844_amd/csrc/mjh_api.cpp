@@ -1338,8 +1338,8 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
 
 }  // extern "C"
 
-// The models the rollouts' reverse sweep covers: the contact geometry below with condim 1
-// or 3, no equalities, no elliptic cones, semi-implicit Euler or the implicit
+// The models the rollouts' reverse sweep covers: the contact geometry below with pyramid
+// contacts of any dimension, no equalities, no elliptic cones, semi-implicit Euler or the implicit
 // integrators (not RK4), bodies of at most four joints.
 static mjh_status rollout_model_check(mjh_ctx* ctx, const ModelRec& mr) {
   // the reverse sweep covers the contact geometry of planes, spheres and capsules against
@@ -1358,10 +1358,9 @@ static mjh_status rollout_model_check(mjh_ctx* ctx, const ModelRec& mr) {
   if (mr.h.neq > 0)
     return fail(ctx, MJH_EUNSUPPORTED, "rollout: equality constraints are not differentiated");
   for (int p = 0; p < mr.h.npair; p++)
-    if (mr.h.pair_condim[p] != 3 && mr.h.pair_condim[p] != 1)
-      return fail(ctx, MJH_EUNSUPPORTED,
-                  "rollout: only frictionless (condim 1) and condim-3 contacts are "
-                  "differentiated");
+    if (mr.h.pair_condim[p] != 1 && mr.h.pair_condim[p] != 3 && mr.h.pair_condim[p] != 4 &&
+        mr.h.pair_condim[p] != 6)
+      return fail(ctx, MJH_EUNSUPPORTED, "rollout: contact dimension not differentiated");
   if (mr.h.integrator == 3)
     return fail(ctx, MJH_EUNSUPPORTED, "rollout: Runge-Kutta steps are not differentiated");
   if (mr.h.cone != 0)

@@ -2,8 +2,8 @@
 
 Workloads: the humanoid (capsule-capsule and sphere-capsule pairs between its own
 limbs, plus capsule and sphere feet on the floor), the quadruped on rough terrain
-(sphere feet against a heightfield), on frictionless ground (one row per contact) and
-with the implicit integrators (joint damping and PD gains at the end-of-step state);
+(sphere feet against a heightfield), on frictionless ground (one row per contact), with
+torsional and rolling friction (condim 4 / 6 pyramids) and with the implicit integrators (joint damping and PD gains at the end-of-step state);
 horizon 64, checkpoints every 8 steps, the loss of
 the quadruped test (root z against 0.3, plus 1e-3 |u|^2).  Reference: the FP64
 rollout's exact directional derivatives (forward-mode dual numbers, solver iterated to
@@ -100,8 +100,10 @@ def _all_pairs(m):
     return np.ones(len(m.pairs), dtype=bool)
 
 
-def test_frictionless_gradient_directional_vs_dual_numbers():
-    _check("quadruped_frictionless", _all_pairs, "contacts")
+@pytest.mark.parametrize("kind", ["quadruped_frictionless", "quadruped_torsion",
+                                  "quadruped_rolling"])
+def test_contact_dimension_gradient_directional_vs_dual_numbers(kind):
+    _check(kind, _all_pairs, "contacts")
 
 
 @pytest.mark.parametrize("kind", ["quadruped_implicit", "quadruped_implicit_pd"])

@@ -10,8 +10,8 @@ rolling friction (condim 6, ten edges).
   usual tolerances (qacc 1e-4, contact force 1e-3 relative to m g) in every world not
   at a switch;
 * spinning spheres on a plane with torsional friction (one step from many states);
-* rollouts reject condim-4 pairs (frictionless ones are differentiated:
-  `tests/test_gpu_adjoint_self.py`).
+* the rollouts' gradients for every contact dimension are in
+  `tests/test_gpu_adjoint_self.py`.
 """
 import math
 
@@ -99,12 +99,3 @@ def test_frictionless_box_on_incline(lib):
     assert np.abs(r["contacts"][:, :4, 14:16]).max() == 0
     np.testing.assert_allclose(r["contacts"][:, :4, 13].sum(1), 9.81 * math.cos(th), rtol=1e-3)
 
-
-def test_rollout_rejects_torsion(lib):
-    mjh, ctx = lib
-    m = robots.quadruped_torsion()
-    w = mjh.World(ctx, m, 2)
-    u = torch.zeros(4, 2, m.nu, device="cuda")
-    loss = torch.zeros(2, device="cuda")
-    with pytest.raises(mjh.MjhError):
-        w.batch.rollout_fwd(4, 2, u, 2, 0.3, 1e-3, loss)
