@@ -537,7 +537,7 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
   if (imp) {
     for (int i = t.lane; i < nv; i += t.T) {
       float v = m.implicit == 2 ? -m.dof_hkp[i] * qvel[i] : 0.f;
-      for (int k = 0; k < nv; k++) v += M[sym(i, k)] * a[k];
+      v += sym_row_dot(M, i, a, nv);
       ai[i] = v;
     }
     t.sync();
@@ -606,8 +606,7 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
     mhb_solve(m, W, t, y, false);
     for (int i = t.lane; i < nv; i += t.T) {
       if (m.implicit == 2) vb[i] -= m.dof_hkp[i] * y[i];
-      float v = 0.f;
-      for (int k = 0; k < nv; k++) v += M[sym(i, k)] * y[k];
+      const float v = sym_row_dot(M, i, y, nv);
       abar[i] = v;
       ai[i] = a[i] - ai[i];
     }

@@ -195,6 +195,18 @@ DEV float dot6(const float* a, const float* b) {
 // fits the full-rate 24-bit multiplier)
 DEV int tri(int i, int j) { return (__mul24(i, i + 1) >> 1) + j; }  // requires i >= j
 DEV int sym(int i, int j) { return i >= j ? tri(i, j) : tri(j, i); }
+// v0 plus row i of a packed symmetric matrix times x, summed in k order from v0: M_ik
+// sits at tri(i, k) = tri(i, 0) + k for k <= i, then at tri(k, i), which grows by k + 1
+// from one k to the next
+DEV float sym_row_dot(const float* M, int i, const float* x, int n, float v0 = 0.f) {
+  float v = v0;
+  int at = tri(i, 0);
+  for (int k = 0; k < n; k++) {
+    v += M[at] * x[k];
+    at += k < i ? 1 : k + 1;
+  }
+  return v;
+}
 // ------------------------------------------------------------ per-world parameters
 // Optional per-world parameter record (domain randomisation, in LDS), 8 + 2 nu words:
 // [0] contact friction scale, [1] payload mass added to body 1 at its centre of mass,
@@ -1825,8 +1837,7 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
   t.sync();
   float qw = 0.f;
   for (int i = t.lane; i < nv; i += t.T) {
-    float v = 0.f;
-    for (int k = 0; k < nv; k++) v += M[sym(i, k)] * tmp[k];
+    float v = sym_row_dot(M, i, tmp, nv);
     Mr[i] = v;
     qw += 0.5f * tmp[i] * v;
   }
@@ -1895,8 +1906,7 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
       s[r] = q ? D[r] * s[r] : 0.f;
     }
     for (int i = t.lane; i < nv; i += t.T) {
-      float v = g[i];
-      for (int k = 0; k < nv; k++) v += M[sym(i, k)] * d[k];
+      float v = sym_row_dot(M, i, d, nv, g[i]);
       tmp[i] = v;
     }
     t.sync();
@@ -1911,8 +1921,7 @@ DEV void newton_impl(const DevModel& m, float* W, const Team& t, int& status, in
     // ---- line search quantities
     float gd = 0.f, dMd = 0.f, dMr = 0.f;
     for (int i = t.lane; i < nv; i += t.T) {
-      float v = 0.f;
-      for (int k = 0; k < nv; k++) v += M[sym(i, k)] * d[k];
+      float v = sym_row_dot(M, i, d, nv);
       Md[i] = v;
       gd += g[i] * d[i];
       dMd += d[i] * v;
@@ -2151,8 +2160,7 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
   t.sync();
   float qw = 0.f;
   for (int i = t.lane; i < nv; i += t.T) {
-    float v = 0.f;
-    for (int k = 0; k < nv; k++) v += M[sym(i, k)] * tmp[k];
+    float v = sym_row_dot(M, i, tmp, nv);
     Mr[i] = v;
     qw += 0.5f * tmp[i] * v;
   }
@@ -2298,8 +2306,7 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
     }
     t.sync();
     for (int i = t.lane; i < nv; i += t.T) {
-      float v = g[i];
-      for (int k = 0; k < nv; k++) v += M[sym(i, k)] * d[k];
+      float v = sym_row_dot(M, i, d, nv, g[i]);
       for (int r = 0; r < nru; r++) v += s[r] * Jv[r * nv + i];
       tmp[i] = v;
     }
@@ -2314,8 +2321,7 @@ DEV void newton_cone(const DevModel& m, float* W, const Team& t, int& status, in
     // ---- line search quantities
     float gd = 0.f, dMd = 0.f, dMr = 0.f;
     for (int i = t.lane; i < nv; i += t.T) {
-      float v = 0.f;
-      for (int k = 0; k < nv; k++) v += M[sym(i, k)] * d[k];
+      float v = sym_row_dot(M, i, d, nv);
       Md[i] = v;
       gd += g[i] * d[i];
       dMd += d[i] * v;
