@@ -1742,9 +1742,11 @@ DEV void cholesky_solve(const DevModel& m, float* W, const Team& t, const float*
       if (i > j && i < nv) acc -= H[tri(i, j)] * yj;
     }
     acc *= rinv;
+    int at = tri(nv - 1, i);  // tri(j, i), one column down per step
     for (int j = nv - 1; j > 0; j--) {  // L^T x = y
       const float xj = t.bcast(acc * rinv, j);
-      if (i < j) acc -= H[tri(j, i)] * xj;
+      if (i < j) acc -= H[at] * xj;
+      at -= j;
     }
     if (i < nv) x[i] = acc * rinv;
     t.sync();
@@ -1773,9 +1775,11 @@ DEV void cholesky_back(const DevModel& m, float* W, const Team& t, const float* 
     const int i = t.lane;
     float acc = i < nv ? y[i] : 0.f;
     const float rinv = i < nv ? 1.f / H[tri(i, i)] : 0.f;
+    int at = tri(nv - 1, i);  // tri(j, i), one column down per step
     for (int j = nv - 1; j > 0; j--) {
       const float xj = t.bcast(acc * rinv, j);
-      if (i < j) acc -= H[tri(j, i)] * xj;
+      if (i < j) acc -= H[at] * xj;
+      at -= j;
     }
     if (i < nv) x[i] = acc * rinv;
     t.sync();
