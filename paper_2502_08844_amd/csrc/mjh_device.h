@@ -1737,9 +1737,11 @@ DEV void cholesky_solve(const DevModel& m, float* W, const Team& t, const float*
     const int i = t.lane;
     const float rinv = i < nv ? 1.f / H[tri(i, i)] : 0.f;
     float acc = i < nv ? sgn * rhs[i] : 0.f;
+    const float* Hi = H + tri(i, 0);  // row i of the factor
+    const int last = i < nv ? i : 0;  // the row takes columns j < last
     for (int j = 0; j < nv - 1; j++) {  // L y = sgn rhs
       const float yj = t.bcast(acc * rinv, j);
-      if (i > j && i < nv) acc -= H[tri(i, j)] * yj;
+      if (j < last) acc -= Hi[j] * yj;
     }
     acc *= rinv;
     int at = tri(nv - 1, i);  // tri(j, i), one column down per step
