@@ -1727,29 +1727,62 @@ DEV bool hessian_cholesky(const DevModel& m, float* W0, const Team& t0, int nru,
   }
   return ok;
 }
+// Triangular solves with the factor L in H (packed lower), lane i holding entry i of a
+// team of TT lanes (nv <= TT); each finished entry is broadcast from its lane.  The team
+// size is a template argument so that the loops carry no test of it.
+template <int TT>
+DEV float team_bcast(float v, int j, int base) {  // v of the team's lane j (j uniform)
+  const int iv = __float_as_int(v);
+  int r = __builtin_amdgcn_readlane(iv, j);
+  if constexpr (TT == 32) {
+    const int r1 = __builtin_amdgcn_readlane(iv, j + 32);
+    r = base ? r1 : r;
+  } else if constexpr (TT == 16) {
+    const int r1 = __builtin_amdgcn_readlane(iv, j + 16);
+    const int r2 = __builtin_amdgcn_readlane(iv, j + 32);
+    const int r3 = __builtin_amdgcn_readlane(iv, j + 48);
+    r = base == 0 ? r : base == 16 ? r1 : base == 32 ? r2 : r3;
+  }
+  return __int_as_float(r);
+}
+// acc: this lane's right-hand side entry; fwd: L y = acc first; then L^T x = y.  Returns
+// x_i scaled by the pivot (the caller multiplies by rinv)
+template <int TT>
+DEV float tri_solves(const float* H0, int nv, int i0, float acc, float rinv, bool fwd) {
+  const float* H = H0 + opaque_zero();  // (a context of its own: see opaque_zero)
+  const int i = i0 + opaque_zero();
+  const int base = (int)(threadIdx.x & 63) - i;  // the team's first lane in the wave
+  if (fwd) {
+    const float* Hi = H + tri(i, 0);  // row i of the factor
+    const int last = i < nv ? i : 0;  // the row takes columns j < last
+    for (int j = 0; j < nv - 1; j++) {
+      const float yj = team_bcast<TT>(acc * rinv, j, base);
+      if (j < last) acc -= Hi[j] * yj;
+    }
+    acc *= rinv;
+  }
+  int at = tri(nv - 1, i);  // tri(j, i), one column down per step
+  for (int j = nv - 1; j > 0; j--) {
+    const float xj = team_bcast<TT>(acc * rinv, j, base);
+    if (i < j) acc -= H[at] * xj;
+    at -= j;
+  }
+  return acc;
+}
+DEV float tri_solves(const Team& t, const float* H, int nv, float acc, float rinv, bool fwd) {
+  if (t.T == 32) return tri_solves<32>(H, nv, t.lane, acc, rinv, fwd);
+  if (t.T == 64) return tri_solves<64>(H, nv, t.lane, acc, rinv, fwd);
+  return tri_solves<16>(H, nv, t.lane, acc, rinv, fwd);
+}
 // x = sgn * (L L^T)^{-1} rhs with the factor in H (rhs and x may alias)
 DEV void cholesky_solve(const DevModel& m, float* W, const Team& t, const float* rhs, float* x,
                         float sgn) {
   const float* H = W + m.o_H;
   const int nv = m.nv;
   if (nv <= t.T) {
-    // lane i holds entry i; each finished entry is broadcast from its lane
     const int i = t.lane;
     const float rinv = i < nv ? 1.f / H[tri(i, i)] : 0.f;
-    float acc = i < nv ? sgn * rhs[i] : 0.f;
-    const float* Hi = H + tri(i, 0);  // row i of the factor
-    const int last = i < nv ? i : 0;  // the row takes columns j < last
-    for (int j = 0; j < nv - 1; j++) {  // L y = sgn rhs
-      const float yj = t.bcast(acc * rinv, j);
-      if (j < last) acc -= Hi[j] * yj;
-    }
-    acc *= rinv;
-    int at = tri(nv - 1, i);  // tri(j, i), one column down per step
-    for (int j = nv - 1; j > 0; j--) {  // L^T x = y
-      const float xj = t.bcast(acc * rinv, j);
-      if (i < j) acc -= H[at] * xj;
-      at -= j;
-    }
+    const float acc = tri_solves(t, H, nv, i < nv ? sgn * rhs[i] : 0.f, rinv, true);
     if (i < nv) x[i] = acc * rinv;
     t.sync();
     return;
@@ -1773,16 +1806,9 @@ DEV void cholesky_back(const DevModel& m, float* W, const Team& t, const float* 
   const float* H = W + m.o_H;
   const int nv = m.nv;
   if (nv <= t.T) {
-    // lane i holds entry i; x_j is broadcast from lane j once its column is finished
     const int i = t.lane;
-    float acc = i < nv ? y[i] : 0.f;
     const float rinv = i < nv ? 1.f / H[tri(i, i)] : 0.f;
-    int at = tri(nv - 1, i);  // tri(j, i), one column down per step
-    for (int j = nv - 1; j > 0; j--) {
-      const float xj = t.bcast(acc * rinv, j);
-      if (i < j) acc -= H[at] * xj;
-      at -= j;
-    }
+    const float acc = tri_solves(t, H, nv, i < nv ? y[i] : 0.f, rinv, false);
     if (i < nv) x[i] = acc * rinv;
     t.sync();
     return;
