@@ -224,7 +224,8 @@ mjh_status mjh_get_launch(mjh_batch* b, int32_t group, int32_t* team, int32_t* b
  * max|smooth force|), at most 16 iterations.  The contacts differentiated are those of
  * planes, spheres and capsules against spheres and capsules, self-contacts included,
  * and of spheres against a heightfield fixed in the world, as pyramids of any contact
- * dimension (MJH_EUNSUPPORTED for other pairs and for elliptic cones); semi-implicit Euler, and the implicit integrators
+ * dimension (MJH_EUNSUPPORTED for other pairs and for elliptic cones); connect and weld
+ * equalities; semi-implicit Euler, and the implicit integrators
  * when nv is at most the group's team size (MJH_EUNSUPPORTED otherwise, and for RK4). */
 mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every,
                            const float* ctrl, int32_t zidx, float ztarget, float wctrl,

@@ -494,7 +494,8 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
   // contact rows (4 a condim-3 pyramid, 1 a frictionless contact); joint-limit rows
   // follow, then friction loss
   const int nrc = ((const int*)(W + m.o_scal))[SC_NRC];
-  const int nrf = nrow - m.nfric;
+  const int nrf = nrow - m.nfric - m.neqrow;  // first friction-loss row
+  const int nre = nrow - m.neqrow;            // first equality row
   const int nl = nrf - nrc;
   const int* lim = (const int*)(W + m.o_lim);
   const float* fl = W + m.o_fl;
@@ -673,6 +674,15 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
           int dof;
           float sg;
           limit_row(m, W, lim[r - nrc], dof, sg, dist);
+        } else if (r >= nre) {  // equality: the residual's component
+          const int q = m.eq_row[r - nre] & 0xffff, k = m.eq_row[r - nre] >> 16;
+          if (k < 3) {
+            float p1[3], p2[3];
+            eq_points(m, W, q, p1, p2);
+            dist = p1[k] - p2[k];
+          } else {
+            dist = weld_residual(m, W, q, k - 3);
+          }
         }
         float d, dd;
         impedance_d(m, dist, d, dd);
@@ -683,7 +693,7 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
         al = Dv * core;
         be = m.B * Dv * sv;
         ga = Dv * sv;
-        rho = r < nrf ? sv * (Dp * core + Dv * m.K * (dd * dist + d)) : 0.f;
+        rho = (r < nrf || r >= nre) ? sv * (Dp * core + Dv * m.K * (dd * dist + d)) : 0.f;
       }
       float* o = rs + 7 * r;
       o[0] = sv; o[1] = xv; o[2] = yv; o[3] = al; o[4] = be; o[5] = ga; o[6] = rho;
@@ -698,6 +708,29 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
         const float* o = rs + 7 * r;
         if (!row_quad(D[r], r < nrf ? 0.f : fl[r], e[r])) continue;
         vadd += o[4] * row_entry(m, W, r, k, ncon);
+        if (r >= nre) {  // equality: J_p(b1, p1) - J_p(b2, p2), or J_w(b1) - J_w(b2)
+          const int q = m.eq_row[r - nre] & 0xffff, kk = m.eq_row[r - nre] >> 16;
+          const bool in1 = (m.body_dofmask[m.eq_body[2 * q]] & bit) != 0;
+          const bool in2 = (m.body_dofmask[m.eq_body[2 * q + 1]] & bit) != 0;
+          const float w = o[3] * mu[k] + o[4] * qvel[k] + o[5] * a[k];
+          if (kk < 3) {
+            float p1[3], p2[3];
+            eq_points(m, W, q, p1, p2);
+            // e_kk . (S_lin + S_ang x p) = S_lin[kk] + S_ang . (p x e_kk)
+            const float pe1[3] = {kk == 2 ? p1[1] : (kk == 1 ? -p1[2] : 0.f),
+                                  kk == 0 ? p1[2] : (kk == 2 ? -p1[0] : 0.f),
+                                  kk == 1 ? p1[0] : (kk == 0 ? -p1[1] : 0.f)};
+            const float pe2[3] = {kk == 2 ? p2[1] : (kk == 1 ? -p2[2] : 0.f),
+                                  kk == 0 ? p2[2] : (kk == 2 ? -p2[0] : 0.f),
+                                  kk == 1 ? p2[0] : (kk == 0 ? -p2[1] : 0.f)};
+            const float s1 = in1 ? w : 0.f, s2 = in2 ? w : 0.f;
+            for (int c = 0; c < 3; c++) sb[c] += s1 * pe1[c] - s2 * pe2[c];
+            sb[3 + kk] += s1 - s2;
+          } else {
+            sb[kk - 3] += (in1 ? w : 0.f) - (in2 ? w : 0.f);
+          }
+          continue;
+        }
         if (r >= nrc) continue;  // limit and friction rows: constant Jacobians
         const int cr = contact_of_row(m, con, ncon, r);
         const float* rec = con + kConRec * cr;
@@ -848,6 +881,63 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
         o[26] = 0.f;  // geometry not differentiated (the rollout refuses such models)
       }
     }
+    // equalities (lane per constraint): the anchors' cotangents, from the residual (its
+    // distance cotangent) and the translational Jacobians (their dependence on the
+    // anchors: p_bar = e_k x sum_dofs w S_ang), and the weld rotation residual's
+    // cotangents of the two bodies' rotations: r = (E_ij - E_ji) / 2, E = R1 Q R2^T
+    float* eqs = W + m.o_eqsc;
+    for (int q = t.lane; q < m.neq; q += t.T) {
+      float* o = eqs + kEqSc * q;  // p1_bar [3], p2_bar [3], R1_bar [9], R2_bar [9]
+      for (int c = 0; c < kEqSc; c++) o[c] = 0.f;
+      const int b1 = m.eq_body[2 * q], b2 = m.eq_body[2 * q + 1];
+      const float* R1 = W + m.o_xmat + 9 * b1;
+      const float* R2 = W + m.o_xmat + 9 * b2;
+      const float* Q = m.eq_relR + 9 * q;
+      for (int er = 0; er < m.neqrow; er++) {
+        if ((m.eq_row[er] & 0xffff) != q) continue;
+        const int kk = m.eq_row[er] >> 16, r = nre + er;
+        const float* ro = rs + 7 * r;
+        if (kk < 3) {
+          float om1[3] = {0.f, 0.f, 0.f}, om2[3] = {0.f, 0.f, 0.f};
+          for (int k = 0; k < nv; k++) {
+            const unsigned long long bit = 1ull << k;
+            const float w = ro[3] * mu[k] + ro[4] * qvel[k] + ro[5] * a[k];
+            const bool in1 = (m.body_dofmask[b1] & bit) != 0, in2 = (m.body_dofmask[b2] & bit) != 0;
+            for (int c = 0; c < 3; c++) {
+              if (in1) om1[c] += w * cdof[6 * k + c];
+              if (in2) om2[c] += w * cdof[6 * k + c];
+            }
+          }
+          // d/dp of e . (S_ang x p) = e x S_ang; the residual p1 - p2 adds +-rho e
+          const float ek[3] = {kk == 0 ? 1.f : 0.f, kk == 1 ? 1.f : 0.f, kk == 2 ? 1.f : 0.f};
+          float x1[3], x2[3];
+          cross3(ek, om1, x1);
+          cross3(ek, om2, x2);
+          for (int c = 0; c < 3; c++) {
+            o[c] += x1[c] + ro[6] * ek[c];
+            o[3 + c] += -x2[c] - ro[6] * ek[c];
+          }
+        } else {
+          const int k3 = kk - 3;
+          const int i = k3 == 0 ? 2 : (k3 == 1 ? 0 : 1), j = k3 == 0 ? 1 : (k3 == 1 ? 2 : 0);
+          const float hr = 0.5f * ro[6];
+          // dE_ij/dR1[i][a] = (Q R2^T)[a][j], dE_ij/dR2[j][b] = (R1 Q)[i][b]
+          for (int aa = 0; aa < 3; aa++) {
+            float qj = 0.f, qi = 0.f, ri = 0.f, rj = 0.f;
+            for (int bb = 0; bb < 3; bb++) {
+              qj += Q[3 * aa + bb] * R2[3 * j + bb];
+              qi += Q[3 * aa + bb] * R2[3 * i + bb];
+              ri += R1[3 * i + bb] * Q[3 * bb + aa];
+              rj += R1[3 * j + bb] * Q[3 * bb + aa];
+            }
+            o[6 + 3 * i + aa] += hr * qj;
+            o[6 + 3 * j + aa] -= hr * qi;
+            o[15 + 3 * j + aa] += hr * ri;
+            o[15 + 3 * i + aa] -= hr * rj;
+          }
+        }
+      }
+    }
     // joint limits: the distance cotangent goes to the joint coordinate, r = +-(q - end)
     for (int k = t.lane; k < nl; k += t.T) {
       int dof;
@@ -857,6 +947,19 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
     }
     t.sync();
     for (int b = 1 + t.lane; b < nb; b += t.T) {
+      for (int q = 0; q < m.neq; q++) {  // anchors p = x_b + R_b l and the weld rotations
+        const float* o = eqs + kEqSc * q;
+        for (int s2 = 0; s2 < 2; s2++) {
+          if (m.eq_body[2 * q + s2] != b) continue;
+          const float* pb = o + 3 * s2;
+          const float* l = m.eq_anchor + 6 * q + 3 * s2;
+          for (int c = 0; c < 3; c++) {
+            xbar[3 * b + c] += pb[c];
+            for (int k2 = 0; k2 < 3; k2++) Rbar[9 * b + 3 * c + k2] += pb[c] * l[k2];
+          }
+          for (int c = 0; c < 9; c++) Rbar[9 * b + c] += o[6 + 9 * s2 + c];
+        }
+      }
       for (int c = 0; c < ncon; c++) {
         const float* o = cs + kConSc * c;
         for (int k = 0; k < 4; k++) {

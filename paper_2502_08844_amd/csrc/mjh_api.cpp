@@ -626,6 +626,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   x.o_Vbar = take(6 * nb); x.o_Abar = take(6 * nb); x.o_Fbar = take(6 * nb);
   x.o_vup = take(6 * nb); x.o_aup = take(6 * nb); x.o_xup = take(3 * nb);
   x.o_Rup = take(9 * nb); x.o_rowsc = take(7 * nr); x.o_consc = take(kConSc * h.nconmax);
+  x.o_eqsc = take(kEqSc * h.neq);
   x.o_fw = take(nfw);
   x.lds_words = off;
   off = d.lds_words;
@@ -1339,7 +1340,7 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
 }  // extern "C"
 
 // The models the rollouts' reverse sweep covers: the contact geometry below with pyramid
-// contacts of any dimension, no equalities, no elliptic cones, semi-implicit Euler or the implicit
+// contacts of any dimension, connect and weld equalities, no elliptic cones, semi-implicit Euler or the implicit
 // integrators (not RK4), bodies of at most four joints.
 static mjh_status rollout_model_check(mjh_ctx* ctx, const ModelRec& mr) {
   // the reverse sweep covers the contact geometry of planes, spheres and capsules against
@@ -1355,8 +1356,6 @@ static mjh_status rollout_model_check(mjh_ctx* ctx, const ModelRec& mr) {
                   "rollout: only contacts of planes, spheres and capsules with spheres and "
                   "capsules, and of spheres with a fixed heightfield, are differentiated");
   }
-  if (mr.h.neq > 0)
-    return fail(ctx, MJH_EUNSUPPORTED, "rollout: equality constraints are not differentiated");
   for (int p = 0; p < mr.h.npair; p++)
     if (mr.h.pair_condim[p] != 1 && mr.h.pair_condim[p] != 3 && mr.h.pair_condim[p] != 4 &&
         mr.h.pair_condim[p] != 6)

@@ -30,6 +30,8 @@ constexpr int kMaxNv = 64;      // ancestor masks are 64-bit
 constexpr int kConRec = 18;     // on-chip contact record (floats)
 constexpr int kConOut = 20;     // exported contact record (MJH_CON_SIZE)
 constexpr int kCinert = 10;     // spatial inertia: m, m c (3), I at origin (6)
+constexpr int kEqSc = 24;       // adjoint scratch per equality: two anchors' and two
+                                // rotations' cotangents
 constexpr int kConSc = 28;      // adjoint scratch per contact: four (cotangent, body point)
                                 // pairs, the two bodies, a flag
 
@@ -144,7 +146,7 @@ struct DevModel {
   int o_cv;        // elliptic cones only: each contact's virtual-row map [nconmax][conrows^2]
   // adjoint layout only (no aliasing between the sweep and contact scratch there)
   int o_qbi, o_vbi, o_qb, o_vb, o_ub, o_mu, o_Sbar, o_xbar, o_Rbar, o_cinbar;
-  int o_Vbar, o_Abar, o_Fbar, o_vup, o_aup, o_xup, o_Rup, o_rowsc, o_consc;
+  int o_Vbar, o_Abar, o_Fbar, o_vup, o_aup, o_xup, o_Rup, o_rowsc, o_consc, o_eqsc;
 };
 
 // scalar slots inside o_scal: the contact count, the row count (the contacts' rows, then

@@ -231,7 +231,7 @@ def summarize(kind, stats):
     return ea, ef, nflag, ntot
 
 
-def directional_check(o, qp, qv, u, gq, gu, dv, du, dL, h=1e-6, nthreads=16):
+def directional_check(o, qp, qv, u, gq, gu, dv, du, dL, h=1e-6, nthreads=16, **loss):
     """The GPU rollout gradient (gq wrt qvel0, gu wrt the controls) along random
     directions (dv, du) against the reference's exact directional derivative dL of the
     same rollout (forward-mode dual numbers, solver iterated to convergence).
@@ -243,12 +243,13 @@ def directional_check(o, qp, qv, u, gq, gu, dv, du, dL, h=1e-6, nthreads=16):
     * smooth: the reference's central difference along d (step h) agrees with dL within
       1e-5 max(1, |dL|).  Where it does not, a contact switch lies within reach of the
       trajectory and the derivative of the FP32 rollout may legitimately differ; such
-      worlds are reported, not gated."""
+      worlds are reported, not gated.
+    loss: the rollout loss's zidx, ztarget, wctrl when not the defaults."""
     nw = qp.shape[0]
     QP = np.concatenate([qp, qp])
     QV = np.concatenate([qv + h * dv, qv - h * dv])
     U = np.concatenate([u + h * du, u - h * du], axis=1)
-    Lpm = o.rollout_loss(QP, QV, U, mode=oracle.MODE_CONVERGED, nthreads=nthreads)
+    Lpm = o.rollout_loss(QP, QV, U, mode=oracle.MODE_CONVERGED, nthreads=nthreads, **loss)
     fd = (Lpm[:nw] - Lpm[nw:]) / (2 * h)
     smooth = np.abs(fd - dL) <= 1e-5 * np.maximum(1.0, np.abs(dL))
     g_dot = np.sum(gq * dv, axis=1) + np.einsum("twa,twa->w", gu, du)

@@ -3,7 +3,8 @@
 Workloads: the humanoid (capsule-capsule and sphere-capsule pairs between its own
 limbs, plus capsule and sphere feet on the floor), the quadruped on rough terrain
 (sphere feet against a heightfield), on frictionless ground (one row per contact), with
-torsional and rolling friction (condim 4 / 6 pyramids) and with the implicit integrators (joint damping and PD gains at the end-of-step state);
+torsional and rolling friction (condim 4 / 6 pyramids), tethered or welded to the world
+(connect and weld equality rows) and with the implicit integrators (joint damping and PD gains at the end-of-step state);
 horizon 64, checkpoints every 8 steps, the loss of
 the quadruped test (root z against 0.3, plus 1e-3 |u|^2).  Reference: the FP64
 rollout's exact directional derivatives (forward-mode dual numbers, solver iterated to
@@ -45,7 +46,7 @@ def _contacts_of(o, m, qp, qv, u, pairs):
     return n
 
 
-def _check(kind, pairs, what, seed=0, nw=64):
+def _check(kind, pairs, what, seed=0, nw=64, **loss):
     from paper_2502_08844_amd import mjh
     m, qp, qv, u = _setup(kind, nw, seed)
     print(f"[gpu] adjoint rollout {kind} nw={nw} horizon={H} ckpt={K}", flush=True)
@@ -53,19 +54,20 @@ def _check(kind, pairs, what, seed=0, nw=64):
     w = mjh.World(ctx, m, nw, qpos=qp)
     qv0 = torch.tensor(qv, dtype=torch.float32, device="cuda", requires_grad=True)
     ut = torch.tensor(u, dtype=torch.float32, device="cuda", requires_grad=True)
-    loss = mjh.Rollout.apply(qv0, ut, w, H, K)
-    loss.sum().backward()
+    lt = mjh.Rollout.apply(qv0, ut, w, H, K, *((loss["zidx"], loss["ztarget"], loss["wctrl"])
+                                              if loss else ()))
+    lt.sum().backward()
     torch.cuda.synchronize()
-    L = loss.detach().cpu().double().numpy()
+    L = lt.detach().cpu().double().numpy()
     gq, gu = qv0.grad.cpu().double().numpy(), ut.grad.cpu().double().numpy()
     assert np.all(np.isfinite(gq)) and np.all(np.isfinite(gu))
     o = oracle.Oracle(m)
     rng = np.random.default_rng(11)
     dv = rng.normal(size=(nw, m.nv))
     du = rng.normal(size=(H, nw, m.nu))
-    Lr, dL = o.rollout_jvp(qp, qv, u, dv, du, mode=oracle.MODE_CONVERGED, nthreads=16)
+    Lr, dL = o.rollout_jvp(qp, qv, u, dv, du, mode=oracle.MODE_CONVERGED, nthreads=16, **loss)
     rel_loss = np.abs(L - Lr) / np.abs(Lr)
-    rel, smooth = directional_check(o, qp, qv, u, gq, gu, dv, du, dL)
+    rel, smooth = directional_check(o, qp, qv, u, gq, gu, dv, du, dL, **loss)
     hit = _contacts_of(o, m, qp, qv, u, pairs(m)) > 0
     without = rel[~hit & smooth]
     print(f"[adjoint-{kind}] loss rel err max {rel_loss.max():.2e}; worlds with {what} "
@@ -109,3 +111,10 @@ def test_contact_dimension_gradient_directional_vs_dual_numbers(kind):
 @pytest.mark.parametrize("kind", ["quadruped_implicit", "quadruped_implicit_pd"])
 def test_implicit_integrator_gradient_directional_vs_dual_numbers(kind):
     _check(kind, _all_pairs, "contacts")
+
+
+@pytest.mark.parametrize("kind", ["quadruped_tethered", "quadruped_welded"])
+def test_equality_gradient_directional_vs_dual_numbers(kind):
+    # no control cost: the torso's height under the tether or the soft weld is all the
+    # loss, so the gradient runs through the equality rows
+    _check(kind, _all_pairs, "contacts", zidx=2, ztarget=0.3, wctrl=0.0)

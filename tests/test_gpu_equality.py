@@ -7,12 +7,11 @@ pinned at one end (a free body), two free spheres held centre to centre, and the
 quadruped with its torso tethered to its standing position beside the foot contacts;
 welds: a box welded to the world off its centre (a cantilever), two free boxes welded
 to each other, and the quadruped with its torso welded to the world (a fixed base).
-Same tolerances as the other parity tests.  Rollouts of models with equalities are
-rejected (the adjoint does not cover them).
+Same tolerances as the other parity tests.  The rollouts' gradients with equalities are
+in `tests/test_gpu_adjoint_self.py`.
 """
 import numpy as np
 import pytest
-import torch
 
 import oracle
 from paper_2502_08844_amd.synth import inputs, robots
@@ -138,12 +137,3 @@ def test_tethered_parity_launch_shapes(lib, team, block):
                               team=team, block=block)
     _check(f"quadruped_tethered-T{team}", stats)
 
-
-def test_rollout_rejects_equalities(lib):
-    mjh, ctx = lib
-    m = robots.quadruped_tethered()
-    w = mjh.World(ctx, m, 2)
-    u = torch.zeros(4, 2, m.nu, device="cuda")
-    loss = torch.zeros(2, device="cuda")
-    with pytest.raises(mjh.MjhError):
-        w.batch.rollout_fwd(4, 2, u, 2, 0.3, 1e-3, loss)
