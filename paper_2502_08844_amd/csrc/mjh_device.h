@@ -1623,7 +1623,7 @@ DEV bool hessian_cholesky(const DevModel& m, float* W0, const Team& t0, int nru,
       for (int c = 0; c < 4; c++) {
         const float pc = c < bw ? P[c][c] : 1.f;
         ok = ok && (pc > 0.f);
-        in[c] = 1.f / sqrtf(fmaxf(pc, 1e-30f));
+        in[c] = __builtin_amdgcn_rsqf(fmaxf(pc, 1e-30f));  // v_rsq: one instruction
         const float rc = in[c] * in[c];
 #pragma unroll
         for (int a = c + 1; a < 4; a++)
