@@ -588,6 +588,9 @@ DEV float box_sdf_only(const float* c, const float* R, const float* h, const flo
 constexpr float kCapBoxTau = 1e-5f;
 constexpr float kCapBoxFlat = 1e-3f;
 constexpr float kCapBoxDup = 1e-6f;
+// bisection steps: the bracket of [0, 1] halves to 2^-24, the FP32 spacing near t = 1
+// and well inside kCapBoxDup (more steps move the point by less than 3e-9 |u|)
+constexpr int kCapBoxBisect = 24;
 DEV void capsule_box_cands(const float* a, const float* u, float r, const float* c,
                            const float* R, const float* h, float* dist, float* tpar) {
   auto fprime = [&](float t) {
@@ -601,7 +604,7 @@ DEV void capsule_box_cands(const float* a, const float* u, float r, const float*
   else if (fprime(1.f) < -tau) tlo = 1.f;
   else {
     float l = 0.f, g = 1.f;
-    for (int it = 0; it < 32; it++) {
+    for (int it = 0; it < kCapBoxBisect; it++) {
       const float md = 0.5f * (l + g);
       if (fprime(md) < -tau) l = md; else g = md;
     }
@@ -611,7 +614,7 @@ DEV void capsule_box_cands(const float* a, const float* u, float r, const float*
   else if (fprime(0.f) > tau) thi = 0.f;
   else {
     float l = 0.f, g = 1.f;
-    for (int it = 0; it < 32; it++) {
+    for (int it = 0; it < kCapBoxBisect; it++) {
       const float md = 0.5f * (l + g);
       if (fprime(md) > tau) g = md; else l = md;
     }
