@@ -1755,19 +1755,21 @@ DEV float tri_solves(const float* H0, int nv, int i0, float acc, float rinv, boo
   const float* H = H0 + opaque_zero();  // (a context of its own: see opaque_zero)
   const int i = i0 + opaque_zero();
   const int base = (int)(threadIdx.x & 63) - i;  // the team's first lane in the wave
+  // (the row tests select the factor entry or 0 from an address valid in every lane,
+  // rather than branching around the update)
   if (fwd) {
-    const float* Hi = H + tri(i, 0);  // row i of the factor
     const int last = i < nv ? i : 0;  // the row takes columns j < last
+    const float* Hi = H + tri(last, 0);  // row i of the factor (row 0 past nv)
     for (int j = 0; j < nv - 1; j++) {
       const float yj = team_bcast<TT>(acc * rinv, j, base);
-      if (j < last) acc -= Hi[j] * yj;
+      acc -= (j < last ? Hi[j] : 0.f) * yj;
     }
     acc *= rinv;
   }
   int at = tri(nv - 1, i);  // tri(j, i), one column down per step
   for (int j = nv - 1; j > 0; j--) {
     const float xj = team_bcast<TT>(acc * rinv, j, base);
-    if (i < j) acc -= H[at] * xj;
+    acc -= (i < j ? H[i < j ? at : 0] : 0.f) * xj;
     at -= j;
   }
   return acc;
