@@ -354,9 +354,21 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* 
       for (int k = 0; k < 3; k++) xpos[3 * b + k] = pos[k];
       for (int k = 0; k < 9; k++) xmat[9 * b + k] = R[k];
       for (int k = 0; k < 6; k++) { cvel[6 * b + k] = V[k]; cacc[6 * b + k] = A[k]; }
+    }
+    t.sync();
+  }
+  // Spatial inertias and bias forces need only each body's own pose, velocity and
+  // acceleration: one pass over all bodies, not one per level.
+  const int z = opaque_zero();  // (a context of its own: see opaque_zero)
+  for (int b = 1 + t.lane + z; b < m.nbody; b += t.T) {
+    {
+      const float* pos = W + z + m.o_xpos + 3 * b;
+      const float* R = W + z + m.o_xmat + 9 * b;
+      const float* V = W + z + m.o_cvel + 6 * b;
+      const float* A = W + z + m.o_cacc + 6 * b;
       // spatial inertia at the world origin: m, h = m c, I_O = R I R^T + m (|c|^2 1 - c c^T)
-      float c[3], Rt[9], RI[9], Iw[9], ip[3] = {m.body_ipos[3 * b], m.body_ipos[3 * b + 1],
-                                                m.body_ipos[3 * b + 2]};
+      float c[3], RI[9], ip[3] = {m.body_ipos[3 * b], m.body_ipos[3 * b + 1],
+                                  m.body_ipos[3 * b + 2]};
       float mass = m.body_mass[b];
       if (dr && b == 1) {
         for (int k = 0; k < 3; k++) ip[k] += dr[kDrCom + k];
@@ -366,12 +378,15 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* 
       for (int k = 0; k < 3; k++) c[k] += pos[k];
       const float* bi = m.body_inertia + 6 * b;
       float Il[9] = {bi[0], bi[3], bi[4], bi[3], bi[1], bi[5], bi[4], bi[5], bi[2]};
-      for (int i = 0; i < 3; i++)
-        for (int k = 0; k < 3; k++) Rt[3 * i + k] = R[3 * k + i];
       mm3(R, Il, RI);
-      mm3(RI, Rt, Iw);
+      // the six entries of R I R^T the inertia keeps: (R I R^T)_ij = (R I)_i . R_j
+      auto iw = [&](int i, int j) {
+        return RI[3 * i] * R[3 * j] + RI[3 * i + 1] * R[3 * j + 1] + RI[3 * i + 2] * R[3 * j + 2];
+      };
+      const float Iw[9] = {iw(0, 0), iw(0, 1), iw(0, 2), 0.f, iw(1, 1), iw(1, 2), 0.f, 0.f,
+                           iw(2, 2)};
       const float cc = dot3(c, c);
-      float* ci = cinert + kCinert * b;
+      float* ci = W + z + m.o_cinert + kCinert * b;
       ci[0] = mass;
       ci[1] = mass * c[0]; ci[2] = mass * c[1]; ci[3] = mass * c[2];
       ci[4] = Iw[0] + mass * (cc - c[0] * c[0]);
@@ -384,10 +399,10 @@ DEV void forward_sweep(const DevModel& m, float* W, const Team& t, const float* 
       inertia_mul(ci, A, IA);
       inertia_mul(ci, V, IV);
       crossf(V, IV, VIV);
-      for (int k = 0; k < 6; k++) cfrc[6 * b + k] = IA[k] + VIV[k];
+      for (int k = 0; k < 6; k++) W[z + m.o_cfrc + 6 * b + k] = IA[k] + VIV[k];
     }
-    t.sync();
   }
+  t.sync();
 }
 
 // ------------------------------- A3/A5 backward sweep, bias forces and CRBA (RBDA 6)
