@@ -118,9 +118,9 @@ const char* mjh_last_error(const mjh_ctx* ctx);
  * mu_j / mu (separated, sliding on the cone's surface, or sticking).
  * Integrator 1 takes joint damping and PD velocity gains implicitly, 2 also the PD
  * position gains, 3 is fourth-order Runge-Kutta (four forward passes a step).
- * mjh_rollout_fwd rejects models with equalities, integrators other than 0, contact
- * dimensions other than 3, elliptic cones or heightfield pairs (MJH_EUNSUPPORTED), and
- * mjh_env_step rejects elliptic cones.
+ * mjh_rollout_fwd rejects the pairs its reverse pass does not differentiate and
+ * elliptic cones (MJH_EUNSUPPORTED; the list is at mjh_rollout_fwd), and mjh_env_step
+ * rejects elliptic cones.
  * MJH_EMODEL for a malformed blob, MJH_EUNSUPPORTED for nv > 64, box-box pairs,
  * a free joint below the root or two actuators on one dof. */
 mjh_status mjh_model_upload(mjh_ctx* ctx, const void* blob, size_t nbytes,
@@ -225,8 +225,10 @@ mjh_status mjh_get_launch(mjh_batch* b, int32_t group, int32_t* team, int32_t* b
  * planes, spheres and capsules against spheres and capsules, self-contacts included,
  * and of spheres against a heightfield fixed in the world, as pyramids of any contact
  * dimension (MJH_EUNSUPPORTED for other pairs and for elliptic cones); connect and weld
- * equalities; semi-implicit Euler, and the implicit integrators
- * when nv is at most the group's team size (MJH_EUNSUPPORTED otherwise, and for RK4). */
+ * equalities; semi-implicit Euler, fourth-order Runge-Kutta (each step's four stages
+ * reversed from an on-chip image per stage, four times the tape of an Euler step), and
+ * the implicit integrators when nv is at most the group's team size (MJH_EUNSUPPORTED
+ * otherwise). */
 mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every,
                            const float* ctrl, int32_t zidx, float ztarget, float wctrl,
                            float* loss, int64_t* generation, void* stream);

@@ -482,11 +482,72 @@ DEV int edge_dirs(const DevModel& m, const float* rec, int ed, float* lin, float
   return f;
 }
 
+// Reverse of qpos' = q0 (+) ch v (lane per joint), the position update of
+// integrate_pos: gq is the cotangent of qpos'; q0b gets q0's (assigned, or added with
+// `add`) and vb accumulates v's.  A free joint's rotation is q' = normalize(q0 (x)
+// exp(ch w)), w its angular velocity; v is read through vel(dof).
+template <class V>
+DEV void integrate_pos_rev(const DevModel& m, const Team& t, const float* q0, V vel, float ch,
+                           const float* gq, float* q0b, float* vb, bool add) {
+  auto put = [&](int i, float x) { q0b[i] = add ? q0b[i] + x : x; };
+  for (int j = t.lane; j < m.njnt; j += t.T) {
+    const int qa = m.jnt_qposadr[j], da = m.jnt_dofadr[j];
+    if (m.jnt_type[j] == JNT_FREE) {
+      for (int k = 0; k < 3; k++) {
+        put(qa + k, gq[qa + k]);
+        vb[da + k] += ch * gq[qa + k];
+      }
+      float wv[3];
+      for (int k = 0; k < 3; k++) wv[k] = ch * vel(da + 3 + k);
+      const float th = sqrtf(dot3(wv, wv));
+      float sn, cs;
+      sincosf(0.5f * th, &sn, &cs);
+      // f(th) = sin(th/2)/th and f'(th)/th; series below 0.1 (the closed form cancels)
+      float fth, fpt;
+      if (th > 0.1f) {
+        fth = sn / th;
+        fpt = (0.5f * th * cs - sn) / (th * th * th);
+      } else {
+        const float t2 = th * th;
+        fth = 0.5f - t2 / 48.f + t2 * t2 / 3840.f;
+        fpt = -1.f / 24.f + t2 / 960.f;
+      }
+      const float ds0 = -0.5f * fth;
+      const float dq[4] = {cs, fth * wv[0], fth * wv[1], fth * wv[2]};
+      const float quat[4] = {q0[qa + 3], q0[qa + 4], q0[qa + 5], q0[qa + 6]};
+      float r[4];
+      quat_mul4(quat, dq, r);
+      const float rn = sqrtf(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+      const float qo[4] = {r[0] / rn, r[1] / rn, r[2] / rn, r[3] / rn};
+      const float* g4 = gq + qa + 3;
+      const float dotq = qo[0] * g4[0] + qo[1] * g4[1] + qo[2] * g4[2] + qo[3] * g4[3];
+      float rbar[4];
+      for (int k = 0; k < 4; k++) rbar[k] = (g4[k] - qo[k] * dotq) / rn;
+      const float dqc[4] = {dq[0], -dq[1], -dq[2], -dq[3]};
+      const float qc[4] = {quat[0], -quat[1], -quat[2], -quat[3]};
+      float qq[4], dqbar[4];
+      quat_mul4(rbar, dqc, qq);
+      quat_mul4(qc, rbar, dqbar);
+      for (int k = 0; k < 4; k++) put(qa + 3 + k, qq[k]);
+      const float wd = wv[0] * dqbar[1] + wv[1] * dqbar[2] + wv[2] * dqbar[3];
+      for (int k = 0; k < 3; k++) {
+        const float wbar = dqbar[0] * ds0 * wv[k] + fth * dqbar[1 + k] + fpt * wd * wv[k];
+        vb[da + 3 + k] += ch * wbar;
+      }
+    } else {
+      put(qa, gq[qa]);
+      vb[da] += ch * gq[qa];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ adjoint step
 // Inputs in LDS: qpos/qvel (state before the step), qacc (= a*), qbi/vbi (cotangents of
-// the state after the step).  Outputs: qb (nq), vb (nv), ub (nu).  Returns false for an
-// unsupported contact pair.
-DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u, int& status) {
+// the state after the step).  Outputs: qb (nq), vb (nv), ub (nu).  With abar_in (one
+// stage of a Runge-Kutta step): a*'s cotangent is abar_in, and qb and vb receive the
+// solve's cotangents only.  Status bit 4: the Hessian's factor failed.
+DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u, int& status,
+                      const float* abar_in = nullptr) {
   const int nv = m.nv, nb = m.nbody;
   const float h = m.dt;
   const int ncon = ((const int*)(W + m.o_scal))[SC_NCON];
@@ -545,59 +606,24 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
     mhb_solve(m, W, t, ai, true);
   }
   const float* av = imp ? ai : a;  // the acceleration of the velocity update
-  // ---- semi-implicit Euler, reversed (lane per joint)
-  for (int j = t.lane; j < m.njnt; j += t.T) {
-    const int qa = m.jnt_qposadr[j], da = m.jnt_dofadr[j];
-    if (m.jnt_type[j] == JNT_FREE) {
-      for (int k = 0; k < 3; k++) {
-        qb[qa + k] = qbi[qa + k];
-        vb[da + k] = vbi[da + k] + h * qbi[qa + k];
-      }
-      // q' = normalize(q (x) exp(h w')), w' = qvel'[3:6]
-      float wv[3];
-      for (int k = 0; k < 3; k++) wv[k] = h * (qvel[da + 3 + k] + h * av[da + 3 + k]);
-      const float th = sqrtf(dot3(wv, wv));
-      float sn, cs;
-      sincosf(0.5f * th, &sn, &cs);
-      // f(th) = sin(th/2)/th and f'(th)/th; series below 0.1 (the closed form cancels)
-      float fth, fpt;
-      if (th > 0.1f) {
-        fth = sn / th;
-        fpt = (0.5f * th * cs - sn) / (th * th * th);
-      } else {
-        const float t2 = th * th;
-        fth = 0.5f - t2 / 48.f + t2 * t2 / 3840.f;
-        fpt = -1.f / 24.f + t2 / 960.f;
-      }
-      const float ds0 = -0.5f * fth;
-      const float dq[4] = {cs, fth * wv[0], fth * wv[1], fth * wv[2]};
-      const float quat[4] = {qpos[qa + 3], qpos[qa + 4], qpos[qa + 5], qpos[qa + 6]};
-      float r[4];
-      quat_mul4(quat, dq, r);
-      const float rn = sqrtf(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
-      const float qo[4] = {r[0] / rn, r[1] / rn, r[2] / rn, r[3] / rn};
-      const float* gq = qbi + qa + 3;
-      const float dotq = qo[0] * gq[0] + qo[1] * gq[1] + qo[2] * gq[2] + qo[3] * gq[3];
-      float rbar[4];
-      for (int k = 0; k < 4; k++) rbar[k] = (gq[k] - qo[k] * dotq) / rn;
-      const float dqc[4] = {dq[0], -dq[1], -dq[2], -dq[3]};
-      const float qc[4] = {quat[0], -quat[1], -quat[2], -quat[3]};
-      float qq[4], dqbar[4];
-      quat_mul4(rbar, dqc, qq);
-      quat_mul4(qc, rbar, dqbar);
-      for (int k = 0; k < 4; k++) qb[qa + 3 + k] = qq[k];
-      const float wd = wv[0] * dqbar[1] + wv[1] * dqbar[2] + wv[2] * dqbar[3];
-      for (int k = 0; k < 3; k++) {
-        const float wbar = dqbar[0] * ds0 * wv[k] + fth * dqbar[1 + k] + fpt * wd * wv[k];
-        vb[da + 3 + k] = vbi[da + 3 + k] + h * wbar;
-      }
-    } else {
-      qb[qa] = qbi[qa];
-      vb[da] = vbi[da] + h * qbi[qa];
+  if (abar_in) {
+    // one stage of a Runge-Kutta step: the solve's cotangents alone (the stage loop
+    // around this call reverses the stage states and the final combination)
+    for (int i = t.lane; i < m.nq; i += t.T) qb[i] = 0.f;
+    for (int i = t.lane; i < nv; i += t.T) {
+      vb[i] = 0.f;
+      abar[i] = abar_in[i];
     }
+    t.sync();
+  } else {
+    // ---- semi-implicit Euler, reversed: qvel' = qvel + h a, qpos' = qpos (+) h qvel'
+    for (int i = t.lane; i < nv; i += t.T) vb[i] = vbi[i];
+    t.sync();
+    integrate_pos_rev(m, t, qpos, [&](int i) { return qvel[i] + h * av[i]; }, h, qbi, qb, vb,
+                      false);
+    t.sync();
+    for (int i = t.lane; i < nv; i += t.T) abar[i] = h * vb[i];
   }
-  t.sync();
-  for (int i = t.lane; i < nv; i += t.T) abar[i] = h * vb[i];
   if (imp) {
     // a_int's cotangent: y = (M + h B)^-1 a_int_bar; then a* gets M y, qdot gets -c y,
     // and M(q) the outer product y (a* - a_int)^T (its sweep below)
@@ -1148,6 +1174,82 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
   }
 }
 
+// Reverse of one fourth-order Runge-Kutta step (rk4_begin / rk4_accumulate / rk4_combine
+// around four solves).  snap: the on-chip image after stage 0's solve, the later stages'
+// at multiples of `stride` words after it ([0, words) each); qbi/vbi: the cotangents of
+// the step's end state.  Outputs as adjoint_step: qb, vb, ub.  Stage k (0-based) runs at
+// q_k = q0 (+) c_k v_{k-1}, v_k = v0 + c_k a_{k-1} (c = h/2, h/2, h for k = 1, 2, 3; q_0 =
+// q0, v_0 = v0); the step ends at q0 (+) h (v_0 + 2 v_1 + 2 v_2 + v_3) / 6 and
+// v0 + h (a_0 + 2 a_1 + 2 a_2 + a_3) / 6.
+DEV void adjoint_step_rk4(const DevModel& m, float* W, const Team& t, const float* u,
+                          int& status, const unsigned* snap, size_t stride, int words) {
+  const int nq = m.nq, nv = m.nv, nu = m.nu;
+  const float h = m.dt;
+  float* Qb = W + m.o_rkb;  // q0's cotangent
+  float* V0b = Qb + nq;     // v0's
+  float* Ab = V0b + nv;     // the current stage's acceleration's
+  float* Vc = Ab + nv;      // the current stage's velocity's, through the next stage's position
+  float* Wb = Vc + nv;      // the combined velocity's
+  float* Ub = Wb + nv;      // the controls'
+  const float* qbi = W + m.o_qbi;
+  const float* vbi = W + m.o_vbi;
+  float* qb = W + m.o_qb;
+  float* vb = W + m.o_vb;
+  float* ub = W + m.o_ub;
+  const float* rk = W + m.o_rk;  // q0, v0, a_0, partial sums (stages 1-3's images)
+  auto restore = [&](int k) {
+    const unsigned* src = snap + k * stride;
+    unsigned* Wu = (unsigned*)W;
+    for (int i = t.lane; i < words; i += t.T) Wu[i] = src[i];
+    t.sync();
+  };
+  // the final combination; stage 3's image holds v_0 + 2 v_1 + 2 v_2 and v_3
+  restore(3);
+  {
+    const float* vs = rk + nq + 2 * nv;
+    const float* qvel = W + m.o_qvel;
+    float* vcomb = W + m.o_tmp;
+    for (int i = t.lane; i < nv; i += t.T) {
+      vcomb[i] = (vs[i] + qvel[i]) / 6.f;
+      V0b[i] = vbi[i];
+      Ab[i] = Vc[i] = Wb[i] = 0.f;
+    }
+    for (int i = t.lane; i < nu; i += t.T) Ub[i] = 0.f;
+    t.sync();
+    integrate_pos_rev(m, t, rk, [&](int i) { return vcomb[i]; }, h, qbi, Qb, Wb, false);
+    t.sync();
+  }
+  for (int k = 3; k >= 0; k--) {
+    if (k < 3) restore(k);
+    const float bk = (k == 0 || k == 3) ? 1.f : 2.f;
+    for (int i = t.lane; i < nv; i += t.T) Ab[i] += bk * (h / 6.f) * vbi[i];
+    t.sync();
+    adjoint_step(m, W, t, u, status, Ab);
+    t.sync();
+    const float ch = (k == 3 ? 1.f : 0.5f) * h;
+    for (int i = t.lane; i < nu; i += t.T) Ub[i] += ub[i];
+    for (int i = t.lane; i < nv; i += t.T) {
+      const float v = vb[i] + Vc[i] + bk / 6.f * Wb[i];  // v_k's whole cotangent
+      V0b[i] += v;
+      Ab[i] = ch * v;  // a_{k-1}'s, through v_k = v0 + c_k a_{k-1}
+      Vc[i] = 0.f;
+    }
+    t.sync();
+    if (k > 0) {  // q_k = q0 (+) c_k v_{k-1}; v_{k-1} is in stage k-1's image
+      const unsigned* vprev = snap + (k - 1) * stride + m.o_qvel;
+      integrate_pos_rev(m, t, rk, [&](int i) { return __uint_as_float(vprev[i]); }, ch, qb, Qb,
+                        Vc, true);
+    } else {
+      for (int i = t.lane; i < nq; i += t.T) Qb[i] += qb[i];
+    }
+    t.sync();
+  }
+  for (int i = t.lane; i < nq; i += t.T) qb[i] = Qb[i];
+  for (int i = t.lane; i < nv; i += t.T) vb[i] = V0b[i];
+  for (int i = t.lane; i < nu; i += t.T) ub[i] = Ub[i];
+  t.sync();
+}
+
 // ------------------------------------------------------------------ kernels
 struct RolloutArgs {
   DevModel m;
@@ -1159,7 +1261,7 @@ struct RolloutArgs {
   const float* ctrl;  // [horizon][nworld][nu]
   float* tape_ckpt;   // [nseg][nworld][nq + 2 nv]
   float* tape_seg;    // [ckpt + 1][nworld][nq + 2 nv]
-  unsigned* tape_snap;  // [ckpt][nworld][snap_words]: on-chip image after each step's solve
+  unsigned* tape_snap;  // [ckpt][stages][nworld][snap_words]: on-chip image after each solve
   int snap_words;       // the forward regions of the adjoint layout, [0, o_qbi)
   float* loss;
   const float* dloss;
@@ -1210,8 +1312,13 @@ __global__ void __launch_bounds__(kAdjBlock) rollout_fwd_kernel(RolloutArgs A) {
     if (s % A.ckpt == 0)
       store_state(m, W, t, A.tape_ckpt + ((size_t)(s / A.ckpt) * A.nworld + w) * ns);
     const float* u = A.ctrl + ((size_t)s * A.nworld + w) * m.nu;
-    world_step(m, W, t, u, status, kAdjIters, kAdjGtol);
-    integrate(m, W, t, status);
+    for (int k = 0; k < (m.rk4 ? 4 : 1); k++) {
+      if (k > 0) rk4_begin(m, W, t, k);
+      world_step(m, W, t, u, status, kAdjIters, kAdjGtol);
+      if (m.rk4) rk4_accumulate(m, W, t, k);
+    }
+    if (m.rk4) rk4_combine(m, W, t, status);
+    else integrate(m, W, t, status);
     if (t.lane == 0) {
       const float dz = W[m.o_qpos + A.zidx] - A.ztarget;
       float uu = 0.f;
@@ -1242,6 +1349,7 @@ __global__ void __launch_bounds__(kAdjBlock) rollout_bwd_kernel(RolloutArgs A) {
   const Team t{(int)threadIdx.x - team * T, T, (const unsigned char*)lds};
   float* W = lds + table_words(m) + (size_t)team * m.lds_words;
   const int ns = m.nq + 2 * m.nv;
+  const int nst = m.rk4 ? 4 : 1;  // solves per step
   world_init(m, W, t);
   const float dl = A.dloss[w];
   float* qbi = W + m.o_qbi;
@@ -1261,11 +1369,17 @@ __global__ void __launch_bounds__(kAdjBlock) rollout_bwd_kernel(RolloutArgs A) {
     store_state(m, W, t, seg_slot(0));
     for (int k = 0; k < len; k++) {
       const float* u = A.ctrl + ((size_t)(s0 + k) * A.nworld + w) * m.nu;
-      world_step(m, W, t, u, status, kAdjIters, kAdjGtol);
-      unsigned* snap = A.tape_snap + ((size_t)k * A.nworld + w) * A.snap_words;
-      const unsigned* Wu = (const unsigned*)W;
-      for (int i = t.lane; i < A.snap_words; i += T) snap[i] = Wu[i];
-      integrate(m, W, t, status);
+      for (int st = 0; st < nst; st++) {  // (Runge-Kutta: an image per stage)
+        if (st > 0) rk4_begin(m, W, t, st);
+        world_step(m, W, t, u, status, kAdjIters, kAdjGtol);
+        unsigned* snap = A.tape_snap + (((size_t)k * nst + st) * A.nworld + w) * A.snap_words;
+        const unsigned* Wu = (const unsigned*)W;
+        for (int i = t.lane; i < A.snap_words; i += T) snap[i] = Wu[i];
+        t.sync();
+        if (nst > 1) rk4_accumulate(m, W, t, st);
+      }
+      if (nst > 1) rk4_combine(m, W, t, status);
+      else integrate(m, W, t, status);
       store_state(m, W, t, seg_slot(k + 1));
     }
     t.sync();
@@ -1275,13 +1389,16 @@ __global__ void __launch_bounds__(kAdjBlock) rollout_bwd_kernel(RolloutArgs A) {
       // loss term of the state after step s
       const float znext = seg_slot(k + 1)[A.zidx];
       if (t.lane == 0) qbi[A.zidx] += 2.f * (znext - A.ztarget) * dl;
-      {
-        const unsigned* snap = A.tape_snap + ((size_t)k * A.nworld + w) * A.snap_words;
+      const unsigned* snap = A.tape_snap + ((size_t)k * nst * A.nworld + w) * A.snap_words;
+      if (nst > 1) {
+        adjoint_step_rk4(m, W, t, u, status, snap, (size_t)A.nworld * A.snap_words,
+                         A.snap_words);
+      } else {
         unsigned* Wu = (unsigned*)W;
         for (int i = t.lane; i < A.snap_words; i += T) Wu[i] = snap[i];
+        t.sync();
+        adjoint_step(m, W, t, u, status);
       }
-      t.sync();
-      adjoint_step(m, W, t, u, status);
       float* gu = A.grad_ctrl + ((size_t)s * A.nworld + w) * m.nu;
       const float* ub = W + m.o_ub;
       for (int i = t.lane; i < m.nu; i += T) gu[i] = ub[i] + 2.f * A.wctrl * u[i] * dl;
@@ -1354,7 +1471,8 @@ mjh_status adjoint_forward(AdjointState** stp, const DevModel& m, int team, int 
     }
     st->seg_words = need_seg;
   }
-  const size_t need_snap = (size_t)std::min(ckpt, horizon) * nworld * (size_t)m.o_qbi;
+  const size_t need_snap =
+      (size_t)std::min(ckpt, horizon) * (m.rk4 ? 4 : 1) * nworld * (size_t)m.o_qbi;
   if (need_snap > st->snap_alloc) {
     if (st->tape_snap) (void)hipFree(st->tape_snap);
     st->tape_snap = nullptr;
@@ -1459,7 +1577,7 @@ size_t noalloc_tape_bytes(const DevModel& m, int nworld, int horizon, int ckpt) 
   const size_t ns = (size_t)m.nq + 2 * (size_t)m.nv;
   return round256(nseg * nworld * ns * sizeof(float)) +
          round256((seglen + 1) * nworld * ns * sizeof(float)) +
-         round256(seglen * nworld * (size_t)m.o_qbi * sizeof(unsigned));
+         round256(seglen * (m.rk4 ? 4 : 1) * nworld * (size_t)m.o_qbi * sizeof(unsigned));
 }
 
 mjh_status adjoint_noalloc(int device, const DevModel& m, int team, int nworld, float* qpos,

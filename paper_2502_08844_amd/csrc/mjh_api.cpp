@@ -619,6 +619,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   x.o_con = take(kConRec * h.nconmax); x.o_lim = take(d.nlim); x.o_J = take(njrow * nv);
   x.o_aref = take(nr);
   x.o_D = take(nr); x.o_e = take(nr); x.o_s = take(nr); x.o_fl = take(d.nfric + d.neq > 0 ? nr : 0);
+  x.o_rk = d.rk4 ? take(h.nq + 4 * nv) : 0;  // inside the images a reverse step restores
   x.o_qbi = take(h.nq); x.o_vbi = take(nv); x.o_qb = take(h.nq); x.o_vb = take(nv);
   x.o_Jv = x.o_sl = x.o_cv = 0;  // rollouts take pyramidal cones only
   x.o_ub = take(h.nu); x.o_mu = take(nv); x.o_Sbar = take(6 * nv);
@@ -627,6 +628,7 @@ mjh_status compile_model(const HostModel& h, ModelRec& rec, Packer& pk, std::str
   x.o_vup = take(6 * nb); x.o_aup = take(6 * nb); x.o_xup = take(3 * nb);
   x.o_Rup = take(9 * nb); x.o_rowsc = take(7 * nr); x.o_consc = take(kConSc * h.nconmax);
   x.o_eqsc = take(kEqSc * h.neq);
+  x.o_rkb = d.rk4 ? take(h.nq + 4 * nv + h.nu) : 0;
   x.o_fw = take(nfw);
   x.lds_words = off;
   off = d.lds_words;
@@ -1360,8 +1362,6 @@ static mjh_status rollout_model_check(mjh_ctx* ctx, const ModelRec& mr) {
     if (mr.h.pair_condim[p] != 1 && mr.h.pair_condim[p] != 3 && mr.h.pair_condim[p] != 4 &&
         mr.h.pair_condim[p] != 6)
       return fail(ctx, MJH_EUNSUPPORTED, "rollout: contact dimension not differentiated");
-  if (mr.h.integrator == 3)
-    return fail(ctx, MJH_EUNSUPPORTED, "rollout: Runge-Kutta steps are not differentiated");
   if (mr.h.cone != 0)
     return fail(ctx, MJH_EUNSUPPORTED, "rollout: elliptic cones are not differentiated");
   {
@@ -1385,7 +1385,7 @@ mjh_status mjh_rollout_fwd(mjh_batch* b, int32_t horizon, int32_t ckpt_every, co
   const ModelRec& mr = *ctx->models[g.model];
   mjh_status st = rollout_model_check(ctx, mr);
   if (st != MJH_OK) return st;
-  if (mr.h.integrator != 0 && mr.dm.nv > g.team)
+  if ((mr.h.integrator == 1 || mr.h.integrator == 2) && mr.dm.nv > g.team)
     return fail(ctx, MJH_EUNSUPPORTED,
                 "rollout: implicit integrators are differentiated for worlds of at most one "
                 "dof per lane of their team");

@@ -147,6 +147,7 @@ struct DevModel {
   // adjoint layout only (no aliasing between the sweep and contact scratch there)
   int o_qbi, o_vbi, o_qb, o_vb, o_ub, o_mu, o_Sbar, o_xbar, o_Rbar, o_cinbar;
   int o_Vbar, o_Abar, o_Fbar, o_vup, o_aup, o_xup, o_Rup, o_rowsc, o_consc, o_eqsc;
+  int o_rkb;  // rk4 only: a step's cotangent sums [nq + 4 nv + nu] across its stages
 };
 
 // scalar slots inside o_scal: the contact count, the row count (the contacts' rows, then

@@ -7,7 +7,7 @@ forward pass at four stages) against the FP64 reference.
   (the first stage's) is the Euler step's from the same state bit for bit, and the
   step's average acceleration (qdot' - qdot) / h is within 1e-4 of max(|a|, g) per
   world with a median below 1e-5, and the first stage's qacc within 1e-4;
-* rollouts reject the integrator;
+* (its rollouts' gradients: tests/test_gpu_adjoint_self.py);
 * the Runge-Kutta instantiations of the env kernel and of a batch mixing Euler and
   Runge-Kutta groups reproduce the separate launches.
 """
@@ -72,16 +72,6 @@ def test_rk4_quadruped_parity(lib, team, block):
     assert ea[~flag].max() <= 1e-4
     assert err[~flag].max() <= 1e-4 and np.median(err) <= 1e-5
     assert flag.sum() <= max(1, 0.02 * len(flag))
-
-
-def test_rollout_rejects_rk4(lib):
-    mjh, ctx = lib
-    m = robots.quadruped_rk4()
-    w = mjh.World(ctx, m, 2)
-    u = torch.zeros(4, 2, m.nu, device="cuda")
-    loss = torch.zeros(2, device="cuda")
-    with pytest.raises(mjh.MjhError):
-        w.batch.rollout_fwd(4, 2, u, 2, 0.3, 1e-3, loss)
 
 
 def test_env_step_with_rk4_physics(lib):
