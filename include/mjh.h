@@ -210,6 +210,7 @@ mjh_status mjh_get_launch(mjh_batch* b, int32_t group, int32_t* team, int32_t* b
 
 /* Differentiable rollout of group 0 (single-model batch).
  * Loss: sum_{t=1..horizon} (qpos_t[zidx] - ztarget)^2 + wctrl * sum_t |ctrl_t|^2.
+ * For a model without actuators (nu = 0) ctrl and grad_ctrl may be NULL.
  * mjh_rollout_fwd runs horizon steps from the bound state with ctrl [horizon][n][nu],
  * keeps a checkpoint every ckpt_every steps, writes loss [n] and leaves the bound
  * state at the final step.  The checkpoint tapes belong to the batch and hold one
@@ -223,6 +224,7 @@ mjh_status mjh_get_launch(mjh_batch* b, int32_t group, int32_t* team, int32_t* b
  * unchanged.  Inside rollouts Newton iterates until max|grad| <= 1e-5 * max(1,
  * max|smooth force|), at most 16 iterations.  The contacts differentiated are those of
  * planes, spheres and capsules against spheres and capsules, self-contacts included,
+ * of planes against box corners,
  * and of spheres against a heightfield fixed in the world, as pyramids of any contact
  * dimension (MJH_EUNSUPPORTED for other pairs and for elliptic cones); connect and weld
  * equalities; semi-implicit Euler, fourth-order Runge-Kutta (each step's four stages

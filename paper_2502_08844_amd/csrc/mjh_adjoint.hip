@@ -783,7 +783,7 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
       const int b1 = __float_as_int(rec[14]), b2 = __float_as_int(rec[15]);
       const int p = __float_as_int(rec[16]), sub = __float_as_int(rec[17]) & 15;
       const int kind = m.pair_kind[p];
-      const bool plane = kind == PK_PLANE_SPHERE || kind == PK_PLANE_CAPSULE;
+      const bool plane = kind == PK_PLANE_SPHERE || kind == PK_PLANE_CAPSULE || kind == PK_PLANE_BOX;
       float xb[3] = {0.f, 0.f, 0.f}, rb = 0.f;
       float fb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // of n, t1, t2
       const int first = first_row(m, rec, c);
@@ -834,12 +834,23 @@ DEV void adjoint_step(const DevModel& m, float* W, const Team& t, const float* u
         for (int q = 0; q < 3; q++) o[6 * k + 3 + q] = m.geom_pos[3 * g + q] + sh * L[3 * q + 2];
       };
       if (plane) {
-        // pos = c - n (R + r/2), r = n . (c - p0) - R, c the sphere centre or capsule end
+        // pos = c - n (R + r/2), r = n . (c - p0) - R, c the sphere centre, capsule end
+        // or box corner (R = 0)
         const float* n = rec + 4;
         const float nx = dot3(n, xb);
         for (int q = 0; q < 3; q++) o[12 + q] = xb[q] - 0.5f * n[q] * nx + rb * n[q];
-        local(2, g2, kind == PK_PLANE_CAPSULE ? (sub == 0 ? -1.f : 1.f) * m.geom_size[3 * g2 + 1]
-                                              : 0.f);
+        if (kind == PK_PLANE_BOX) {  // corner `sub`: bit k takes +half-size k, else -
+          const float* L = m.geom_rot + 9 * g2;
+          const float* hs = m.geom_size + 3 * g2;
+          const float loc[3] = {(sub & 1) ? hs[0] : -hs[0], (sub & 2) ? hs[1] : -hs[1],
+                                (sub & 4) ? hs[2] : -hs[2]};
+          for (int q = 0; q < 3; q++)
+            o[15 + q] = m.geom_pos[3 * g2 + q] + L[3 * q] * loc[0] + L[3 * q + 1] * loc[1] +
+                        L[3 * q + 2] * loc[2];
+        } else {
+          local(2, g2, kind == PK_PLANE_CAPSULE ? (sub == 0 ? -1.f : 1.f) * m.geom_size[3 * g2 + 1]
+                                                : 0.f);
+        }
       } else if (kind == PK_SPHERE_SPHERE || kind == PK_SPHERE_CAPSULE ||
                  kind == PK_CAPSULE_CAPSULE) {
         float nb[3] = {fb[0], fb[1], fb[2]};
@@ -1434,7 +1445,7 @@ mjh_status adjoint_forward(AdjointState** stp, const DevModel& m, int team, int 
                            float* qvel, float* qacc, int horizon, int ckpt, const float* ctrl,
                            int zidx, float ztarget, float wctrl, float* loss, int64_t* generation,
                            hipStream_t stream, std::string& err) {
-  if (horizon <= 0 || ckpt <= 0 || !ctrl || !loss || zidx < 0 || zidx >= m.nq) {
+  if (horizon <= 0 || ckpt <= 0 || (!ctrl && m.nu > 0) || !loss || zidx < 0 || zidx >= m.nq) {
     err = "rollout_fwd: need horizon > 0, ckpt_every > 0, ctrl, loss and 0 <= zidx < nq";
     return MJH_EINVAL;
   }
@@ -1530,7 +1541,10 @@ mjh_status adjoint_backward(AdjointState* st, int64_t generation, const float* d
           ", not rollout " + std::to_string(generation) + " (a later rollout_fwd replaced it)";
     return MJH_ESTATE;
   }
-  if (!dloss || !grad_qvel0 || !grad_ctrl) { err = "rollout_bwd: NULL argument"; return MJH_EINVAL; }
+  if (!dloss || !grad_qvel0 || (!grad_ctrl && st->args.m.nu > 0)) {
+    err = "rollout_bwd: NULL argument";
+    return MJH_EINVAL;
+  }
   RolloutArgs A = st->args;
   A.dloss = dloss;
   A.grad_qvel0 = grad_qvel0;
@@ -1585,7 +1599,8 @@ mjh_status adjoint_noalloc(int device, const DevModel& m, int team, int nworld, 
                            int zidx, float ztarget, float wctrl, const float* dloss, float* loss,
                            float* grad_qvel0, float* grad_ctrl, hipStream_t stream,
                            std::string& err) {
-  if (horizon <= 0 || ckpt <= 0 || !ctrl || !loss || !dloss || !grad_qvel0 || !grad_ctrl ||
+  if (horizon <= 0 || ckpt <= 0 || (!ctrl && m.nu > 0) || !loss || !dloss || !grad_qvel0 ||
+      (!grad_ctrl && m.nu > 0) ||
       zidx < 0 || zidx >= m.nq) {
     err = "rollout_noalloc: need horizon > 0, ckpt_every > 0, ctrl, dloss, loss, gradients "
           "and 0 <= zidx < nq";

@@ -1346,17 +1346,21 @@ mjh_status mjh_autotune(mjh_batch* b, int32_t nstep_probe, const char* cache_pat
 // integrators (not RK4), bodies of at most four joints.
 static mjh_status rollout_model_check(mjh_ctx* ctx, const ModelRec& mr) {
   // the reverse sweep covers the contact geometry of planes, spheres and capsules against
-  // spheres and capsules, and of spheres against a heightfield fixed in the world; and
+  // spheres and capsules, of planes against boxes, and of spheres against a heightfield
+  // fixed in the world; and
   // bodies of at most four scalar joints
   for (int p = 0; p < mr.h.npair; p++) {
     const int g1 = mr.h.pair_g1[p], g2 = mr.h.pair_g2[p];
     const int t1 = mr.h.geom_type[g1], t2 = mr.h.geom_type[g2];
     const bool round2 = t2 == GEOM_SPHERE || t2 == GEOM_CAPSULE;
     const bool field = t1 == GEOM_SPHERE && t2 == GEOM_HFIELD && mr.h.geom_body[g2] == 0;
-    if (!field && !(round2 && (t1 == GEOM_PLANE || t1 == GEOM_SPHERE || t1 == GEOM_CAPSULE)))
+    const bool plane_box = t1 == GEOM_PLANE && t2 == GEOM_BOX;
+    if (!field && !plane_box &&
+        !(round2 && (t1 == GEOM_PLANE || t1 == GEOM_SPHERE || t1 == GEOM_CAPSULE)))
       return fail(ctx, MJH_EUNSUPPORTED,
                   "rollout: only contacts of planes, spheres and capsules with spheres and "
-                  "capsules, and of spheres with a fixed heightfield, are differentiated");
+                  "capsules, of planes with boxes and of spheres with a fixed heightfield are "
+                  "differentiated");
   }
   for (int p = 0; p < mr.h.npair; p++)
     if (mr.h.pair_condim[p] != 1 && mr.h.pair_condim[p] != 3 && mr.h.pair_condim[p] != 4 &&

@@ -48,8 +48,11 @@ def _contacts_of(o, m, qp, qv, u, pairs):
 
 
 def _check(kind, pairs, what, seed=0, nw=64, **loss):
+    _run(kind, *_setup(kind, nw, seed), pairs, what, nw, **loss)
+
+
+def _run(kind, m, qp, qv, u, pairs, what, nw, **loss):
     from paper_2502_08844_amd import mjh
-    m, qp, qv, u = _setup(kind, nw, seed)
     print(f"[gpu] adjoint rollout {kind} nw={nw} horizon={H} ckpt={K}", flush=True)
     ctx = mjh.Context(0)
     w = mjh.World(ctx, m, nw, qpos=qp)
@@ -128,3 +131,30 @@ def test_equality_gradient_directional_vs_dual_numbers(kind):
 
 def test_runge_kutta_gradient_directional_vs_dual_numbers():
     _check("quadruped_rk4", _all_pairs, "contacts")
+
+
+def test_box_on_plane_gradient_directional_vs_dual_numbers():
+    """A free box tumbling on the floor (corner contacts, no actuators): worlds start
+    tilted, their lowest corners 0-5 mm into the plane, with random velocities."""
+    nw = 64
+    m = robots.free_body("box", half=(0.1, 0.15, 0.05), plane=True, timestep=0.002)
+    rng = np.random.default_rng(5)
+    qp = np.zeros((nw, m.nq))
+    for w in range(nw):
+        ax = rng.normal(size=3)
+        ax /= np.linalg.norm(ax)
+        ang = rng.uniform(0.0, 0.3)
+        q = np.r_[np.cos(ang / 2), np.sin(ang / 2) * ax]
+        qp[w, 3:7] = q
+        # the corners' lowest z at the origin, then lowered by 0-5 mm
+        R = np.array([[1 - 2 * (q[2]**2 + q[3]**2), 2 * (q[1]*q[2] - q[0]*q[3]), 2 * (q[1]*q[3] + q[0]*q[2])],
+                      [2 * (q[1]*q[2] + q[0]*q[3]), 1 - 2 * (q[1]**2 + q[3]**2), 2 * (q[2]*q[3] - q[0]*q[1])],
+                      [2 * (q[1]*q[3] - q[0]*q[2]), 2 * (q[2]*q[3] + q[0]*q[1]), 1 - 2 * (q[1]**2 + q[2]**2)]])
+        half = np.array([0.1, 0.15, 0.05])
+        corners = np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)]) * half
+        qp[w, 2] = -(corners @ R.T)[:, 2].min() - rng.uniform(0.0, 0.005)
+    qp = inputs.f32(qp)
+    qv = inputs.f32(rng.normal(scale=0.5, size=(nw, m.nv)))
+    u = np.zeros((H, nw, 0), dtype=np.float32)
+    _run("box_on_plane", m, qp, qv, u, _all_pairs, "corner contacts", nw,
+         zidx=2, ztarget=0.1, wctrl=0.0)
