@@ -5,7 +5,8 @@ limbs, plus capsule and sphere feet on the floor), the quadruped on rough terrai
 (sphere feet against a heightfield), on frictionless ground (one row per contact), with
 torsional and rolling friction (condim 4 / 6 pyramids), tethered or welded to the world
 (connect and weld equality rows), with the implicit integrators (joint damping and PD gains at the end-of-step state)
-and with fourth-order Runge-Kutta steps (four solves a step, each reversed);
+and with fourth-order Runge-Kutta steps (four solves a step, each reversed), and a free box
+tumbling on the floor (corner contacts, no actuators);
 horizon 64, checkpoints every 8 steps, the loss of
 the quadruped test (root z against 0.3, plus 1e-3 |u|^2).  Reference: the FP64
 rollout's exact directional derivatives (forward-mode dual numbers, solver iterated to
