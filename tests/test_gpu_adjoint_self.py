@@ -86,6 +86,11 @@ def _run(kind, m, qp, qv, u, pairs, what, nw, **loss):
     # a world whose central differences disagree with the dual numbers passes a switch
     # (contact or friction piece) within the difference step: there the FP32 and FP64
     # trajectories may take the switch at different steps, so its loss is only reported
+    ws = int(np.flatnonzero(smooth)[rel[smooth].argmax()])
+    n_all = _contacts_of(o, m, qp, qv, u, np.ones(len(m.pairs), dtype=bool))
+    print(f"[adjoint-{kind}] worst smooth world {ws}: err {rel[ws]:.2e}, contacts over the "
+          f"rollout {n_all[ws]} ({what}: {bool(hit[ws])}), dual JVP {dL[ws]:.3e}, "
+          f"|grad| {np.sqrt((gq[ws] ** 2).sum() + (gu[:, ws] ** 2).sum()):.3e}", flush=True)
     assert rel_loss[smooth].max() < 1e-3
     assert (hit & smooth).sum() >= 8  # the geometry under test is exercised
     assert smooth.sum() >= 0.75 * nw
